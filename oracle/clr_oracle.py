@@ -39,7 +39,8 @@ path and listed in the design notes):
   matrices are always dense.  A block's accumulation is done densely iff it is
   such a diagonal block, or any contribution is dense, or the concatenated
   rank R satisfies 2 R >= min(m, n).
-* After accumulation a block whose exact norm is below tau is dropped.
+* After accumulation a block whose exact norm is below tau is dropped; a
+  block whose accumulated value is exactly zero is a zero block.
 * Factor convention: X (here U) carries the orthonormal basis, W (here V)
   carries the singular values, as X = Q_r in the paper.
 * Ties in the low-rank x low-rank absorb rule go to the W side (V_B Z^T).
@@ -64,6 +65,7 @@ __all__ = [
     "combine",
     "block_product",
     "gemm",
+    "gemm_block",
     "ns_T",
     "identity",
     "scale",
@@ -219,7 +221,7 @@ def combine(m: int, n: int, contribs: List[tuple], tol: float, tau: float,
             else:
                 D += c[1] @ c[2].T
         normc = frob(D)
-        if normc < tau:
+        if normc < tau or normc == 0.0:
             return None
         if force_dense or tol == 0.0:
             return Block("D", D=D, norm=normc)
@@ -235,14 +237,14 @@ def combine(m: int, n: int, contribs: List[tuple], tol: float, tau: float,
     Vcat = np.concatenate([c[2] for c in contribs], axis=1)
     if tol == 0.0:
         normc = frob(Ucat @ Vcat.T)
-        if normc < tau:
+        if normc < tau or normc == 0.0:
             return None
         return Block("L", U=Ucat, V=Vcat, norm=normc)
     QU, RU = np.linalg.qr(Ucat)
     QV, RV = np.linalg.qr(Vcat)
     M = RU @ RV.T
     normc = frob(M)
-    if normc < tau:
+    if normc < tau or normc == 0.0:
         return None
     Um, s, Vmt = np.linalg.svd(M)
     r = truncation_rank(s, tol, normc)
@@ -302,50 +304,57 @@ def block_tau(eps_sp: float, m: int, n: int, screen: str) -> float:
     return eps_sp * m * n if screen == "area" else eps_sp
 
 
+def gemm_block(A: OMatrix, B: OMatrix, i: int, j: int, tol: float, eps_sp: float,
+               screen: str = "abs", alpha: float = 1.0,
+               stats: Optional[GemmStats] = None) -> Optional[Block]:
+    """Result block (i, j) of alpha * A @ B: screening, products, accumulation, recompression."""
+    m, n = A.row_sizes[i], B.col_sizes[j]
+    square = list(A.row_sizes) == list(B.col_sizes)
+    klist = [k for k in range(A.ncb) if (i, k) in A.blocks and (k, j) in B.blocks]
+    if not klist:
+        return None
+    est = 0.0
+    for k in klist:
+        est += A.blocks[(i, k)].norm * B.blocks[(k, j)].norm
+    est *= abs(alpha)
+    tau = block_tau(eps_sp, m, n, screen)
+    if est < tau:
+        if stats is not None:
+            stats.screened += 1
+        return None
+    contribs = []
+    for k in klist:
+        a, b = A.blocks[(i, k)], B.blocks[(k, j)]
+        contribs.append(block_product(a, b, alpha))
+        if stats is not None:
+            kk = A.col_sizes[k]
+            stats.triples += 1
+            if a.kind == "D" and b.kind == "D":
+                stats.flops_dd += 2.0 * m * kk * n
+            elif a.kind == "L" and b.kind == "D":
+                stats.flops_ld += 2.0 * a.rank * kk * n
+            elif a.kind == "D" and b.kind == "L":
+                stats.flops_dl += 2.0 * m * kk * b.rank
+            else:
+                side = m if b.rank < a.rank else n
+                stats.flops_ll += 2.0 * kk * a.rank * b.rank + 2.0 * side * a.rank * b.rank
+    blk = combine(m, n, contribs, tol, tau, square and i == j)
+    if stats is not None:
+        stats.computed += 1
+        if blk is None:
+            stats.dropped += 1
+    return blk
+
+
 def gemm(A: OMatrix, B: OMatrix, tol: float, eps_sp: float, screen: str = "abs",
          alpha: float = 1.0, stats: Optional[GemmStats] = None) -> OMatrix:
     """C = alpha * A @ B in CLR arithmetic: screening, block products, accumulation, recompression."""
     if list(A.col_sizes) != list(B.row_sizes):
         raise ValueError("inner blockings differ")
-    square = list(A.row_sizes) == list(B.col_sizes)
     blocks = {}
     for i in range(A.nrb):
-        m = A.row_sizes[i]
         for j in range(B.ncb):
-            n = B.col_sizes[j]
-            klist = [k for k in range(A.ncb) if (i, k) in A.blocks and (k, j) in B.blocks]
-            if not klist:
-                continue
-            est = 0.0
-            for k in klist:
-                est += A.blocks[(i, k)].norm * B.blocks[(k, j)].norm
-            est *= abs(alpha)
-            tau = block_tau(eps_sp, m, n, screen)
-            if est < tau:
-                if stats is not None:
-                    stats.screened += 1
-                continue
-            contribs = []
-            for k in klist:
-                a, b = A.blocks[(i, k)], B.blocks[(k, j)]
-                contribs.append(block_product(a, b, alpha))
-                if stats is not None:
-                    kk = A.col_sizes[k]
-                    stats.triples += 1
-                    if a.kind == "D" and b.kind == "D":
-                        stats.flops_dd += 2.0 * m * kk * n
-                    elif a.kind == "L" and b.kind == "D":
-                        stats.flops_ld += 2.0 * a.rank * kk * n
-                    elif a.kind == "D" and b.kind == "L":
-                        stats.flops_dl += 2.0 * m * kk * b.rank
-                    else:
-                        side = m if b.rank < a.rank else n
-                        stats.flops_ll += 2.0 * kk * a.rank * b.rank + 2.0 * side * a.rank * b.rank
-            blk = combine(m, n, contribs, tol, tau, square and i == j)
-            if stats is not None:
-                stats.computed += 1
-                if blk is None:
-                    stats.dropped += 1
+            blk = gemm_block(A, B, i, j, tol, eps_sp, screen, alpha, stats)
             if blk is not None:
                 blocks[(i, j)] = blk
     return OMatrix(list(A.row_sizes), list(B.col_sizes), blocks)
