@@ -1,0 +1,212 @@
+/*
+ * clr.h - C ABI of the MI355X (gfx950) library for products of clustered
+ * low-rank (CLR) block-rank-sparse matrices and the Newton-Schulz square-root
+ * inverse built on them.
+ *
+ * Method: Calvin, Lewis & Valeev, "Scalable Task-Based Algorithm for
+ * Multiplication of Block-Rank-Sparse Matrices" (IA^3 2015), Sec. 4.1 (CLR
+ * representation, Eqs. (4)-(7), screening) and Sec. 4.2 (Eqs. (8)-(11)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All numeric payload is IEEE double, column-major.  A dense block of an
+ *   m x n block is m x n with leading dimension m; a low-rank block is a pair
+ *   U (m x r, ld m) and V (n x r, ld n) with value U V^T.
+ * - Block metadata arrays (kind, rank, norm) are row-major over the block grid:
+ *   entry I * ncb + J describes block (I, J).  kind: 0 zero, 1 dense, 2 low rank.
+ * - Pointers documented as "device" must point to memory of the device that
+ *   was current when the context was created; "host" pointers are plain CPU
+ *   memory.  The library never retains caller pointers after a call returns.
+ * - Every call is enqueued on the context's stream.  Calls that return host
+ *   data, and calls whose output sizes depend on results (clr_gemm,
+ *   clr_compress, clr_sqrt_inv and the backward calls), synchronise that
+ *   stream.
+ * - A failing call returns a status other than CLR_OK, leaves any output
+ *   handle set to NULL, and records a message retrievable by clr_last_error().
+ *   No C++ exception crosses this interface.
+ * - A context and the matrices created from it are used by one host thread at
+ *   a time.
+ */
+#ifndef CLR_H
+#define CLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct clr_context clr_context;
+typedef struct clr_matrix clr_matrix;
+
+typedef enum {
+  CLR_OK = 0,
+  CLR_ERR_INVALID_ARG = 1,   /* null handle, negative size, bad option value        */
+  CLR_ERR_SHAPE = 2,         /* inner blockings of a product differ                 */
+  CLR_ERR_CAPACITY = 3,      /* a size exceeds what the library supports            */
+  CLR_ERR_NONFINITE = 4,     /* a block norm is NaN or infinite                     */
+  CLR_ERR_NOT_CONVERGED = 5, /* S^-1/2: stopped without meeting conv_tol            */
+  CLR_ERR_HIP = 6,           /* a HIP runtime call failed                           */
+  CLR_ERR_NORM_MISMATCH = 7, /* caller norms disagree with the recomputed ones      */
+  CLR_ERR_DIVERGED = 8,      /* S^-1/2: ||X_n - I|| grew in two consecutive steps   */
+  CLR_ERR_INTERNAL = 9       /* a kernel reported an inconsistent state             */
+} clr_status;
+
+typedef enum { CLR_FP64 = 0, CLR_MIXED = 1 } clr_precision;
+
+/* Screening threshold tau of a result block (I, J) of size m x n (Sec. 4.1,
+ * last paragraph): ABS uses tau = eps_sp, AREA uses tau = eps_sp * m * n.    */
+typedef enum { CLR_SCREEN_ABS = 0, CLR_SCREEN_AREA = 1 } clr_screen_mode;
+
+typedef struct {
+  double tol;      /* relative truncation tolerance per block; 0 = no truncation       */
+  double eps_sp;   /* screening threshold (see clr_screen_mode)                        */
+  int screen;      /* clr_screen_mode                                                  */
+  int precision;   /* clr_precision: block products in FP64, or FP32 MFMA with FP64
+                      accumulation every 16 inner indices (MIXED)                      */
+  int split;       /* MIXED only: 1 adds the hi*lo and lo*hi correction products,
+                      0 uses the FP32-rounded operands alone                           */
+  double alpha;    /* result is alpha * A * B (screening estimate scaled by |alpha|)   */
+} clr_gemm_opts;
+
+typedef struct {
+  clr_gemm_opts g;     /* options of every product of the iteration                    */
+  double alpha;        /* scaling of Eq. (8); 0 selects 1 / max_I sum_J ||S_IJ||_F      */
+  double conv_tol;     /* target of ||X_n - I||_F/sqrt(N) and of ||W S W - I||_F/sqrt(N) */
+  int max_iter;        /* iteration cap when fixed_iters == 0                          */
+  int fixed_iters;     /* > 0: run exactly this many iterations, no stopping test       */
+} clr_sqrtinv_opts;
+
+typedef struct {
+  int64_t candidates;   /* result blocks with at least one nonzero pair              */
+  int64_t computed;     /* of those, passed the screening test                        */
+  int64_t dropped;      /* computed but below tau after accumulation                  */
+  int64_t triples;      /* block products formed                                      */
+  int64_t n_dd, n_ld, n_dl, n_ll;
+  int64_t out_dense, out_lowrank;
+  int64_t densified;    /* result blocks accumulated densely                          */
+  double flops_dd, flops_ld, flops_dl, flops_ll; /* 2mkn, 2r k n, 2 m k r, 2k rA rB + 2 side rA rB */
+  double flops_densify; /* 2 m n r for low-rank terms added into dense accumulators   */
+  double flops_products;/* sum of the five above                                      */
+  double bytes_compulsory; /* stored elements of A, B and C, 8 bytes each             */
+  double ms_symbolic, ms_products, ms_recompress, ms_total; /* device time per phase */
+} clr_gemm_stats;
+
+typedef struct {
+  int iterations;
+  int converged;            /* 1 when ||W S W - I||_F/sqrt(N) <= conv_tol              */
+  double alpha;
+  double internal_residual; /* last ||X_n - I||_F / sqrt(N)                            */
+  double explicit_residual; /* ||W S W - I||_F / sqrt(N) at exit (untruncated products) */
+  int n_gemms;
+  double flops_products;    /* sum over every product of clr_gemm_stats.flops_products  */
+  double ms_total;
+} clr_sqrtinv_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context bound to the current HIP device and to `stream` (a
+ * hipStream_t; NULL selects the default stream).  Owns all workspace. */
+clr_status clr_context_create(clr_context** ctx, void* stream);
+clr_status clr_context_destroy(clr_context* ctx);
+/* Message of the last failing call on this context ("" if none).  Valid until
+ * the next call on the context. */
+const char* clr_last_error(const clr_context* ctx);
+const char* clr_status_string(clr_status s);
+
+/* ---- matrices (Sec. 4.1: the CLR representation) ------------------------- */
+
+/* Build a CLR matrix from given factors, copied into a library-owned arena.
+ *   row_sizes[nrb], col_sizes[ncb] (host): the nonuniform blocking.
+ *   kind[nrb*ncb] (host): 0 zero, 1 dense, 2 low rank.
+ *   rank[nrb*ncb] (host): r of low-rank blocks (1 <= r <= min(m, n)); ignored otherwise.
+ *   norms[nrb*ncb] (host, nullable): ||block||_F; when given they are checked
+ *     against the recomputed values (relative 1e-10, else CLR_ERR_NORM_MISMATCH).
+ *   f0[nrb*ncb], f1[nrb*ncb] (host arrays of device pointers): dense block or U;
+ *     V for low-rank blocks.  Entries of zero blocks are ignored.
+ * Sizes must be >= 1.  The stored norms are recomputed on the device. */
+clr_status clr_create(clr_context* ctx, int nrb, const int* row_sizes, int ncb,
+                      const int* col_sizes, const int8_t* kind, const int* rank,
+                      const double* norms, const double* const* f0,
+                      const double* const* f1, clr_matrix** out);
+
+/* CLR form of a dense matrix (device, column-major, leading dimension ld >=
+ * rows): blocks with ||block||_F < drop become zero, diagonal blocks of a
+ * square blocking stay dense, every other block is truncated to relative
+ * `tol` by SVD and stored dense iff its rank exceeds half of min(m, n). */
+clr_status clr_compress(clr_context* ctx, const double* dense, int64_t ld, int nrb,
+                        const int* row_sizes, int ncb, const int* col_sizes, double tol,
+                        double drop, clr_matrix** out);
+
+clr_status clr_destroy(clr_matrix* m);
+
+/* Blocking and storage summary (host outputs, all nullable). */
+clr_status clr_matrix_info(const clr_matrix* m, int* nrb, int* ncb, int64_t* rows,
+                           int64_t* cols, int64_t* stored_elements);
+/* Block metadata copied to host arrays of nrb*ncb entries (each nullable). */
+clr_status clr_get_meta(clr_context* ctx, const clr_matrix* m, int8_t* kind, int* rank,
+                        double* norms);
+/* Copy the factors of block (I, J) to device buffers: f0 receives the dense
+ * block (m*n) or U (m*r); f1 receives V (n*r) and may be NULL for dense blocks. */
+clr_status clr_get_block(clr_context* ctx, const clr_matrix* m, int I, int J, double* f0,
+                         double* f1);
+/* Expand to a dense device matrix (column-major, leading dimension ld >= rows). */
+clr_status clr_to_dense(clr_context* ctx, const clr_matrix* m, double* out, int64_t ld);
+
+/* ---- the product (Sec. 4.1, Eqs. (4)-(7) and the screening rule) ---------- */
+
+/* C = alpha * A * B in CLR arithmetic: screening by norm estimates, dense x
+ * dense / low-rank x dense / dense x low-rank / low-rank x low-rank block
+ * products, accumulation (dense sum or factor concatenation), FP64
+ * recompression by truncated SVD, and C's norm table.  A's column blocking
+ * must equal B's row blocking.  `st` (nullable) receives counts and times. */
+clr_status clr_gemm(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
+                    const clr_gemm_opts* opts, clr_matrix** C, clr_gemm_stats* st);
+
+/* T = a * X + b * Y + c * I blockwise with the same accumulation and
+ * recompression rules (Y nullable; c applies to diagonal blocks of a square
+ * blocking).  With a = -10/8, b = 3/8, c = 15/8 and Y = X*X this is Eq. (9). */
+clr_status clr_axpby(clr_context* ctx, double a, const clr_matrix* X, double b,
+                     const clr_matrix* Y, double c, const clr_gemm_opts* opts,
+                     clr_matrix** T);
+
+/* ---- the square-root inverse (Sec. 4.2, Eqs. (8)-(11)) -------------------- */
+
+/* W = S^-1/2 by the coupled third-order Newton-Schulz iteration: X = alpha Y Z,
+ * T = (-10 X + 3 X^2 + 15 I)/8, Z <- Z T, Y <- T Y, W = sqrt(alpha) Z.  S must be
+ * square-blocked.  Stops when ||X_n - I||_F/sqrt(N) <= conv_tol and the explicit
+ * residual of W is <= conv_tol, or when the explicit residual stops halving
+ * (CLR_ERR_NOT_CONVERGED, W still returned), or at max_iter
+ * (CLR_ERR_NOT_CONVERGED, W returned), or on growth of ||X_n - I|| in two
+ * consecutive iterations (CLR_ERR_DIVERGED, no W). */
+clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const clr_sqrtinv_opts* opts,
+                        clr_matrix** W, clr_sqrtinv_stats* st);
+
+/* ||X - I||_F / sqrt(N) of a square-blocked matrix (host result). */
+clr_status clr_identity_residual(clr_context* ctx, const clr_matrix* X, double* out);
+
+/* ---- adjoints (truncation treated as the identity) ------------------------ */
+
+/* Given dC (device, dense rows(A) x cols(B), column-major, leading dimension
+ * ldc), write dA = alpha dC B^T and dB = alpha A^T dC restricted to the stored
+ * blocks of A and B (entries of zero blocks are set to 0), dense column-major
+ * with leading dimensions lda, ldb.  Either output may be NULL. */
+clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
+                             double alpha, const double* dC, int64_t ldc, double* dA,
+                             int64_t lda, double* dB, int64_t ldb);
+
+/* dS of L = sum(Wbar .* W) for W from `iters` unrolled iterations (alpha held
+ * constant, truncation treated as the identity), restricted to S's stored
+ * blocks.  Wbar and dS are dense device matrices N x N with leading dimension
+ * ld.  Iterates are re-computed from checkpoints kept every
+ * `checkpoint_every` iterations.  W (nullable) receives the forward result. */
+clr_status clr_sqrt_inv_backward(clr_context* ctx, const clr_matrix* S,
+                                 const clr_sqrtinv_opts* opts, int iters,
+                                 int checkpoint_every, const double* Wbar, double* dS,
+                                 int64_t ld, clr_matrix** W);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLR_H */

@@ -1,0 +1,239 @@
+"""Python binding of the MI355X CLR block-product library (libclr_mi355x.so).
+
+Argument marshalling only: every step of the product, the recompression and
+the square-root inverse runs in the library's HIP kernels.  PyTorch supplies
+device memory (input/output tensors) and the stream.  Importing this package
+loads the shared library and fails loudly if it has not been built
+(``python -m paper_1509_00309_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _abi
+from ._abi import (CLR_FP64, CLR_MIXED, CLR_SCREEN_ABS, CLR_SCREEN_AREA, ClrError,
+                   GemmOpts, GemmStats, SqrtInvOpts, SqrtInvStats, lib, LIB_PATH)
+
+__all__ = [
+    "Context", "CLRMatrix", "ClrError", "GemmStats", "SqrtInvStats", "lib", "LIB_PATH",
+    "CLR_FP64", "CLR_MIXED",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _col_major(t):
+    """A column-major copy of a 2-D float64 CUDA tensor: returns (buffer, ld)."""
+    torch = _torch()
+    if t.dtype != torch.float64:
+        raise TypeError("float64 tensors are required")
+    if not t.is_cuda:
+        raise TypeError("device (cuda) tensors are required")
+    buf = t.t().contiguous()            # (cols, rows) row-major == (rows, cols) column-major
+    return buf, t.shape[0]
+
+
+def _gemm_opts(tol, eps_sp, screen, precision, split, alpha) -> GemmOpts:
+    o = GemmOpts()
+    o.tol = float(tol)
+    o.eps_sp = float(eps_sp)
+    o.screen = {"abs": CLR_SCREEN_ABS, "area": CLR_SCREEN_AREA}[screen] if isinstance(screen, str) else int(screen)
+    o.precision = {"fp64": CLR_FP64, "mixed": CLR_MIXED}[precision] if isinstance(precision, str) else int(precision)
+    o.split = int(split)
+    o.alpha = float(alpha)
+    return o
+
+
+class Context:
+    """A library context bound to the current device and a torch stream."""
+
+    def __init__(self, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the CLR library needs a ROCm GPU")
+        self.device = torch.cuda.current_device()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._stream = s
+        h = C.c_void_p()
+        _abi.check(lib.clr_context_create(C.byref(h), C.c_void_p(s.cuda_stream)), None)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.clr_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        _abi.check(rc, self._h)
+
+    # -- matrices ------------------------------------------------------------
+    def create(self, row_sizes: Sequence[int], col_sizes: Sequence[int], kind, rank,
+               f0: Dict[Tuple[int, int], object], f1: Dict[Tuple[int, int], object],
+               norms=None) -> "CLRMatrix":
+        """CLR matrix from per-block factors (torch float64 cuda tensors, any 2-D layout).
+
+        kind/rank: (nrb, ncb) arrays; f0[(I,J)] dense m x n or U m x r; f1[(I,J)] V n x r.
+        """
+        nrb, ncb = len(row_sizes), len(col_sizes)
+        kind = np.ascontiguousarray(np.asarray(kind, dtype=np.int8).reshape(nrb, ncb))
+        rank = np.ascontiguousarray(np.asarray(rank, dtype=np.int32).reshape(nrb, ncb))
+        keep = []
+        p0 = (C.c_void_p * (nrb * ncb))()
+        p1 = (C.c_void_p * (nrb * ncb))()
+        for i in range(nrb):
+            for j in range(ncb):
+                if kind[i, j] == 0:
+                    continue
+                b0, _ = _col_major(f0[(i, j)])
+                keep.append(b0)
+                p0[i * ncb + j] = b0.data_ptr()
+                if kind[i, j] == 2:
+                    b1, _ = _col_major(f1[(i, j)])
+                    keep.append(b1)
+                    p1[i * ncb + j] = b1.data_ptr()
+        rs = (C.c_int * nrb)(*map(int, row_sizes))
+        cs = (C.c_int * ncb)(*map(int, col_sizes))
+        nptr = None
+        if norms is not None:
+            nrm = np.ascontiguousarray(np.asarray(norms, dtype=np.float64).reshape(nrb, ncb))
+            keep.append(nrm)
+            nptr = nrm.ctypes.data_as(C.POINTER(C.c_double))
+        h = C.c_void_p()
+        self._check(lib.clr_create(self._h, nrb, rs, ncb, cs,
+                                   kind.ctypes.data_as(C.POINTER(C.c_int8)),
+                                   rank.ctypes.data_as(C.POINTER(C.c_int)), nptr, p0, p1,
+                                   C.byref(h)))
+        return CLRMatrix(self, h)
+
+    def compress(self, dense, row_sizes, col_sizes, tol: float, drop: float) -> "CLRMatrix":
+        """CLR form of a dense float64 cuda matrix (truncated SVD per block, see clr.h)."""
+        buf, ld = _col_major(dense)
+        nrb, ncb = len(row_sizes), len(col_sizes)
+        rs = (C.c_int * nrb)(*map(int, row_sizes))
+        cs = (C.c_int * ncb)(*map(int, col_sizes))
+        h = C.c_void_p()
+        self._check(lib.clr_compress(self._h, C.c_void_p(buf.data_ptr()), C.c_int64(ld), nrb, rs,
+                                     ncb, cs, C.c_double(tol), C.c_double(drop), C.byref(h)))
+        return CLRMatrix(self, h)
+
+    # -- the method ----------------------------------------------------------
+    def gemm(self, A: "CLRMatrix", B: "CLRMatrix", tol: float, eps_sp: float, screen="abs",
+             precision="fp64", split: int = 0, alpha: float = 1.0, stats: bool = False):
+        o = _gemm_opts(tol, eps_sp, screen, precision, split, alpha)
+        h = C.c_void_p()
+        st = GemmStats()
+        self._check(lib.clr_gemm(self._h, A._h, B._h, C.byref(o), C.byref(h), C.byref(st) if stats else None))
+        M = CLRMatrix(self, h)
+        return (M, st) if stats else M
+
+    def axpby(self, a: float, X: "CLRMatrix", b: float, Y: Optional["CLRMatrix"], c: float,
+              tol: float, eps_sp: float, screen="abs", precision="fp64") -> "CLRMatrix":
+        o = _gemm_opts(tol, eps_sp, screen, precision, 0, 1.0)
+        h = C.c_void_p()
+        self._check(lib.clr_axpby(self._h, C.c_double(a), X._h, C.c_double(b),
+                                  Y._h if Y is not None else None, C.c_double(c), C.byref(o),
+                                  C.byref(h)))
+        return CLRMatrix(self, h)
+
+    def sqrt_inv(self, S: "CLRMatrix", tol: float, eps_sp: float, conv_tol: float = 1e-10,
+                 max_iter: int = 50, fixed_iters: int = 0, alpha: float = 0.0, screen="abs",
+                 precision="fp64", split: int = 0, allow_not_converged: bool = True):
+        """W = S^-1/2 (Newton-Schulz, Eqs. (8)-(11)); returns (W, SqrtInvStats)."""
+        o = SqrtInvOpts()
+        o.g = _gemm_opts(tol, eps_sp, screen, precision, split, 1.0)
+        o.alpha = float(alpha)
+        o.conv_tol = float(conv_tol)
+        o.max_iter = int(max_iter)
+        o.fixed_iters = int(fixed_iters)
+        h = C.c_void_p()
+        st = SqrtInvStats()
+        rc = lib.clr_sqrt_inv(self._h, S._h, C.byref(o), C.byref(h), C.byref(st))
+        if rc == _abi.CLR_ERR_NOT_CONVERGED and allow_not_converged and h.value:
+            return CLRMatrix(self, h), st
+        self._check(rc)
+        return CLRMatrix(self, h), st
+
+    def identity_residual(self, X: "CLRMatrix") -> float:
+        out = C.c_double()
+        self._check(lib.clr_identity_residual(self._h, X._h, C.byref(out)))
+        return out.value
+
+
+class CLRMatrix:
+    """Handle of a library-owned CLR matrix."""
+
+    def __init__(self, ctx: Context, handle: C.c_void_p):
+        self.ctx = ctx
+        self._h = handle
+        nrb, ncb = C.c_int(), C.c_int()
+        rows, cols = C.c_int64(), C.c_int64()
+        ctx._check(lib.clr_matrix_info(handle, C.byref(nrb), C.byref(ncb), C.byref(rows),
+                                       C.byref(cols), None))
+        self.nrb, self.ncb = nrb.value, ncb.value
+        self.rows, self.cols = rows.value, cols.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.clr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.rows, self.cols)
+
+    def meta(self):
+        nb = self.nrb * self.ncb
+        kind = np.zeros(nb, dtype=np.int8)
+        rank = np.zeros(nb, dtype=np.int32)
+        norm = np.zeros(nb, dtype=np.float64)
+        self.ctx._check(lib.clr_get_meta(self.ctx._h, self._h,
+                                         kind.ctypes.data_as(C.POINTER(C.c_int8)),
+                                         rank.ctypes.data_as(C.POINTER(C.c_int)),
+                                         norm.ctypes.data_as(C.POINTER(C.c_double))))
+        return (kind.reshape(self.nrb, self.ncb), rank.reshape(self.nrb, self.ncb),
+                norm.reshape(self.nrb, self.ncb))
+
+    def stored_elements(self) -> int:
+        s = C.c_int64()
+        self.ctx._check(lib.clr_matrix_info(self._h, None, None, None, None, C.byref(s)))
+        return s.value
+
+    def to_dense(self):
+        torch = _torch()
+        buf = torch.empty((self.cols, self.rows), dtype=torch.float64, device="cuda")
+        self.ctx._check(lib.clr_to_dense(self.ctx._h, self._h, C.c_void_p(buf.data_ptr()),
+                                         C.c_int64(self.rows)))
+        return buf.t()
+
+    def block(self, I: int, J: int, m: int, n: int, kind: int, rank: int):
+        """Factors of block (I, J): ("D", D) or ("L", U, V) as torch tensors."""
+        torch = _torch()
+        if kind == 1:
+            d = torch.empty((n, m), dtype=torch.float64, device="cuda")
+            self.ctx._check(lib.clr_get_block(self.ctx._h, self._h, I, J, C.c_void_p(d.data_ptr()), None))
+            return ("D", d.t())
+        u = torch.empty((rank, m), dtype=torch.float64, device="cuda")
+        v = torch.empty((rank, n), dtype=torch.float64, device="cuda")
+        self.ctx._check(lib.clr_get_block(self.ctx._h, self._h, I, J, C.c_void_p(u.data_ptr()),
+                                          C.c_void_p(v.data_ptr())))
+        return ("L", u.t(), v.t())

@@ -1,0 +1,1129 @@
+// Host side of the C ABI declared in include/clr.h: contexts, CLR matrices in
+// a slot arena, and the drivers of the product, the blockwise combination and
+// the Newton-Schulz square-root inverse (Sec. 4.1 and 4.2 of Calvin, Lewis &
+// Valeev, IA^3 2015).
+//
+// Storage of a CLR matrix with blocking m_0..m_{R-1} x n_0..n_{C-1}: one FP64
+// arena of rows*cols doubles; block (I, J) owns the m_I x n_J slot at
+// roff[I]*cols + m_I*coff[J].  A dense block fills its slot (column-major,
+// ld m); a low-rank block stores U (m x r) then V (n x r) in it, which fits
+// because (m + n) r <= m n whenever r <= m n / (m + n) (in particular for
+// every r <= min(m, n)/2).  The slot layout is the dense upper bound of the
+// method's memory use, so ranks can change from product to product without
+// reallocation or compaction.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "clr.h"
+#include "clr_internal.h"
+
+using namespace clr;
+
+// ---------------------------------------------------------------------------
+// Context and buffers
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct clr_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
+      items_thin2, pieces, rec, pool, scratch, acc, status, terms, aux_items, aux_segs,
+      aux_dense, ptrs;
+  hipEvent_t ev[6] = {};
+};
+
+struct clr_matrix {
+  clr_context* ctx = nullptr;
+  int nrb = 0, ncb = 0;
+  std::vector<int> rs, cs, roff, coff;
+  int64_t rows = 0, cols = 0;
+  int* d_roff = nullptr;
+  int* d_coff = nullptr;
+  int* d_kind = nullptr;
+  int* d_rank = nullptr;
+  double* d_norm = nullptr;
+  double* arena = nullptr;
+
+  MatView view() const {
+    MatView v;
+    v.kind = d_kind;
+    v.rank = d_rank;
+    v.norm = d_norm;
+    v.roff = d_roff;
+    v.coff = d_coff;
+    v.arena = arena;
+    v.nrb = nrb;
+    v.ncb = ncb;
+    v.ncols = cols;
+    return v;
+  }
+  bool square_blocked() const { return rs == cs; }
+};
+
+namespace {
+
+constexpr int kMaxBlockEdge = 512;
+
+clr_status fail(clr_context* ctx, clr_status s, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return fail((ctx), CLR_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+hipError_t ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return hipSuccess;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return e;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  const size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) return e;
+    b.bytes = bytes;
+    return hipSuccess;
+  }
+  b.bytes = want;
+  return hipSuccess;
+}
+
+void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+template <typename T>
+T* as(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+void free_matrix(clr_matrix* m) {
+  if (!m) return;
+  if (m->d_roff) (void)hipFree(m->d_roff);
+  if (m->d_coff) (void)hipFree(m->d_coff);
+  if (m->d_kind) (void)hipFree(m->d_kind);
+  if (m->d_rank) (void)hipFree(m->d_rank);
+  if (m->d_norm) (void)hipFree(m->d_norm);
+  if (m->arena) (void)hipFree(m->arena);
+  delete m;
+}
+
+// Allocate a matrix with the given blocking; metadata set to "all zero blocks".
+clr_status alloc_matrix(clr_context* ctx, const std::vector<int>& rs, const std::vector<int>& cs,
+                        clr_matrix** out) {
+  *out = nullptr;
+  if (rs.empty() || cs.empty()) return fail(ctx, CLR_ERR_INVALID_ARG, "empty blocking");
+  for (int v : rs)
+    if (v < 1) return fail(ctx, CLR_ERR_INVALID_ARG, "block size %d < 1", v);
+  for (int v : cs)
+    if (v < 1) return fail(ctx, CLR_ERR_INVALID_ARG, "block size %d < 1", v);
+  for (int v : rs)
+    if (v > kMaxBlockEdge)
+      return fail(ctx, CLR_ERR_CAPACITY, "block size %d exceeds %d", v, kMaxBlockEdge);
+  for (int v : cs)
+    if (v > kMaxBlockEdge)
+      return fail(ctx, CLR_ERR_CAPACITY, "block size %d exceeds %d", v, kMaxBlockEdge);
+  clr_matrix* m = new clr_matrix();
+  m->ctx = ctx;
+  m->nrb = (int)rs.size();
+  m->ncb = (int)cs.size();
+  m->rs = rs;
+  m->cs = cs;
+  m->roff.assign(m->nrb + 1, 0);
+  m->coff.assign(m->ncb + 1, 0);
+  for (int i = 0; i < m->nrb; ++i) m->roff[i + 1] = m->roff[i] + rs[i];
+  for (int j = 0; j < m->ncb; ++j) m->coff[j + 1] = m->coff[j] + cs[j];
+  m->rows = m->roff.back();
+  m->cols = m->coff.back();
+  const int64_t nb = (int64_t)m->nrb * m->ncb;
+  if (nb > (int64_t)1 << 30) {
+    free_matrix(m);
+    return fail(ctx, CLR_ERR_CAPACITY, "too many blocks");
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc(&m->d_roff, sizeof(int) * (m->nrb + 1));
+  if (e == hipSuccess) e = hipMalloc(&m->d_coff, sizeof(int) * (m->ncb + 1));
+  if (e == hipSuccess) e = hipMalloc(&m->d_kind, sizeof(int) * nb);
+  if (e == hipSuccess) e = hipMalloc(&m->d_rank, sizeof(int) * nb);
+  if (e == hipSuccess) e = hipMalloc(&m->d_norm, sizeof(double) * nb);
+  if (e == hipSuccess) e = hipMalloc(&m->arena, sizeof(double) * (size_t)m->rows * m->cols);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->d_roff, m->roff.data(), sizeof(int) * (m->nrb + 1),
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->d_coff, m->coff.data(), sizeof(int) * (m->ncb + 1),
+                       hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = launch_fill_i32(m->d_kind, 0, nb, ctx->stream);
+  if (e == hipSuccess) e = launch_fill_i32(m->d_rank, 0, nb, ctx->stream);
+  if (e == hipSuccess) e = launch_fill_f64(m->d_norm, 0.0, nb, ctx->stream);
+  // host vectors roff/coff outlive the copies: they belong to the matrix
+  if (e != hipSuccess) {
+    free_matrix(m);
+    return fail(ctx, CLR_ERR_HIP, "matrix allocation failed: %s", hipGetErrorString(e));
+  }
+  *out = m;
+  return CLR_OK;
+}
+
+clr_status check_opts(clr_context* ctx, const clr_gemm_opts* o) {
+  if (!o) return fail(ctx, CLR_ERR_INVALID_ARG, "null options");
+  if (!(o->tol >= 0.0) || !(o->tol < 1.0)) return fail(ctx, CLR_ERR_INVALID_ARG, "tol must be in [0, 1)");
+  if (!(o->eps_sp >= 0.0)) return fail(ctx, CLR_ERR_INVALID_ARG, "eps_sp must be >= 0");
+  if (o->screen != CLR_SCREEN_ABS && o->screen != CLR_SCREEN_AREA)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "bad screen mode");
+  if (o->precision != CLR_FP64 && o->precision != CLR_MIXED)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "bad precision");
+  if (!std::isfinite(o->alpha)) return fail(ctx, CLR_ERR_INVALID_ARG, "alpha must be finite");
+  return CLR_OK;
+}
+
+hipError_t run_ggemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
+                     hipStream_t s) {
+  if (o->precision == CLR_MIXED) return launch_ggemm_f32(items, segs, n, o->split, s);
+  return launch_ggemm_f64(items, segs, n, s);
+}
+
+int max_item(const clr_gemm_opts* o) {
+  return o->precision == CLR_MIXED ? kMaxItemF32 : kMaxItemF64;
+}
+
+// Read and clear the device status word; map it to a status code.
+clr_status check_status(clr_context* ctx) {
+  int h = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&h, ctx->status.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (h == 0) return CLR_OK;
+  HIP_TRY(ctx, launch_fill_i32(as<int>(ctx->status), 0, 1, ctx->stream));
+  if (h & 2) return fail(ctx, CLR_ERR_NONFINITE, "non-finite block norm");
+  if (h & (4 | 8)) return fail(ctx, CLR_ERR_INTERNAL, "recompression working set mis-planned");
+  if (h & 1) return fail(ctx, CLR_ERR_INTERNAL, "Jacobi SVD did not converge");
+  return fail(ctx, CLR_ERR_INTERNAL, "device status %d", h);
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+struct HostMeta {
+  std::vector<int> kind, rank;
+  std::vector<double> norm;
+};
+
+clr_status fetch_meta(clr_context* ctx, const clr_matrix* m, HostMeta& h) {
+  const size_t nb = (size_t)m->nrb * m->ncb;
+  h.kind.resize(nb);
+  h.rank.resize(nb);
+  h.norm.resize(nb);
+  HIP_TRY(ctx, hipMemcpyAsync(h.kind.data(), m->d_kind, nb * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(h.rank.data(), m->d_rank, nb * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(h.norm.data(), m->d_norm, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return CLR_OK;
+}
+
+double stored_elements(const clr_matrix* m, const HostMeta& h) {
+  double s = 0.0;
+  for (int I = 0; I < m->nrb; ++I)
+    for (int J = 0; J < m->ncb; ++J) {
+      const int k = h.kind[(size_t)I * m->ncb + J];
+      if (k == 1) s += (double)m->rs[I] * m->cs[J];
+      if (k == 2) s += (double)(m->rs[I] + m->cs[J]) * h.rank[(size_t)I * m->ncb + J];
+    }
+  return s;
+}
+
+// Upload a host vector into a growable device buffer (synchronous with the stream).
+template <typename T>
+clr_status upload(clr_context* ctx, DevBuf& b, const std::vector<T>& v) {
+  HIP_TRY(ctx, ensure(b, sizeof(T) * v.size()));
+  if (!v.empty())
+    HIP_TRY(ctx, hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return CLR_OK;
+}
+
+clr_status copy_matrix(clr_context* ctx, const clr_matrix* src, clr_matrix** out) {
+  clr_matrix* m = nullptr;
+  clr_status s = alloc_matrix(ctx, src->rs, src->cs, &m);
+  if (s != CLR_OK) return s;
+  const size_t nb = (size_t)src->nrb * src->ncb;
+  hipError_t e = hipMemcpyAsync(m->d_kind, src->d_kind, nb * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->d_rank, src->d_rank, nb * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->d_norm, src->d_norm, nb * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->arena, src->arena, sizeof(double) * (size_t)src->rows * src->cols,
+                       hipMemcpyDeviceToDevice, ctx->stream);
+  if (e != hipSuccess) {
+    free_matrix(m);
+    return fail(ctx, CLR_ERR_HIP, "copy failed: %s", hipGetErrorString(e));
+  }
+  *out = m;
+  return CLR_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+extern "C" clr_status clr_context_create(clr_context** ctx, void* stream) {
+  if (!ctx) return CLR_ERR_INVALID_ARG;
+  *ctx = nullptr;
+  clr_context* c = new clr_context();
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return CLR_ERR_HIP;
+  }
+  c->stream = (hipStream_t)stream;
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return CLR_ERR_HIP;
+    }
+  if (ensure(c->status, sizeof(int)) != hipSuccess ||
+      launch_fill_i32(as<int>(c->status), 0, 1, c->stream) != hipSuccess) {
+    delete c;
+    return CLR_ERR_HIP;
+  }
+  *ctx = c;
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_context_destroy(clr_context* ctx) {
+  if (!ctx) return CLR_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (DevBuf* b : {&ctx->cnt, &ctx->off, &ctx->st, &ctx->flags, &ctx->totals, &ctx->seg_dense,
+                    &ctx->items_dense, &ctx->seg_thin1, &ctx->items_thin1, &ctx->seg_thin2,
+                    &ctx->items_thin2, &ctx->pieces, &ctx->rec, &ctx->pool, &ctx->scratch,
+                    &ctx->acc, &ctx->status, &ctx->terms, &ctx->aux_items, &ctx->aux_segs,
+                    &ctx->aux_dense, &ctx->ptrs})
+    free_buf(*b);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+  return CLR_OK;
+}
+
+extern "C" const char* clr_last_error(const clr_context* ctx) {
+  return ctx ? ctx->last_error.c_str() : "";
+}
+
+extern "C" const char* clr_status_string(clr_status s) {
+  switch (s) {
+    case CLR_OK: return "ok";
+    case CLR_ERR_INVALID_ARG: return "invalid argument";
+    case CLR_ERR_SHAPE: return "blockings do not conform";
+    case CLR_ERR_CAPACITY: return "capacity exceeded";
+    case CLR_ERR_NONFINITE: return "non-finite value";
+    case CLR_ERR_NOT_CONVERGED: return "not converged";
+    case CLR_ERR_HIP: return "HIP runtime error";
+    case CLR_ERR_NORM_MISMATCH: return "norms disagree with the factors";
+    case CLR_ERR_DIVERGED: return "iteration diverged";
+    case CLR_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+// ---------------------------------------------------------------------------
+// Matrices
+// ---------------------------------------------------------------------------
+
+extern "C" clr_status clr_create(clr_context* ctx, int nrb, const int* row_sizes, int ncb,
+                                 const int* col_sizes, const int8_t* kind, const int* rank,
+                                 const double* norms, const double* const* f0,
+                                 const double* const* f1, clr_matrix** out) {
+  if (!ctx || !out) return CLR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (nrb < 1 || ncb < 1 || !row_sizes || !col_sizes || !kind || !f0)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "clr_create: missing blocking, kinds or factors");
+  std::vector<int> rs(row_sizes, row_sizes + nrb), cs(col_sizes, col_sizes + ncb);
+  const size_t nb = (size_t)nrb * ncb;
+  std::vector<int> k(nb), r(nb, 0);
+  std::vector<const double*> p0(nb, nullptr), p1(nb, nullptr);
+  for (int I = 0; I < nrb; ++I)
+    for (int J = 0; J < ncb; ++J) {
+      const size_t b = (size_t)I * ncb + J;
+      k[b] = kind[b];
+      if (k[b] < 0 || k[b] > 2) return fail(ctx, CLR_ERR_INVALID_ARG, "block (%d,%d): bad kind", I, J);
+      if (k[b] == 0) continue;
+      if (I < 0 || rs[I] < 1 || cs[J] < 1) return fail(ctx, CLR_ERR_INVALID_ARG, "bad block size");
+      p0[b] = f0[b];
+      if (!p0[b]) return fail(ctx, CLR_ERR_INVALID_ARG, "block (%d,%d): null factor", I, J);
+      if (k[b] == 2) {
+        if (!rank || !f1 || !f1[b])
+          return fail(ctx, CLR_ERR_INVALID_ARG, "block (%d,%d): low-rank block needs rank and V", I, J);
+        r[b] = rank[b];
+        const int64_t m = rs[I], n = cs[J];
+        if (r[b] < 1 || (m + n) * r[b] > m * n)
+          return fail(ctx, CLR_ERR_CAPACITY, "block (%d,%d): rank %d does not fit the %lldx%lld slot",
+                      I, J, r[b], (long long)m, (long long)n);
+        p1[b] = f1[b];
+      } else {
+        r[b] = std::min(rs[I], cs[J]);
+      }
+    }
+  clr_matrix* m = nullptr;
+  clr_status s = alloc_matrix(ctx, rs, cs, &m);
+  if (s != CLR_OK) return s;
+  std::vector<const double*> tab(2 * nb);
+  std::copy(p0.begin(), p0.end(), tab.begin());
+  std::copy(p1.begin(), p1.end(), tab.begin() + nb);
+  hipError_t e = hipMemcpyAsync(m->d_kind, k.data(), nb * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->d_rank, r.data(), nb * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = ensure(ctx->ptrs, tab.size() * sizeof(double*));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->ptrs.p, tab.data(), tab.size() * sizeof(double*), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    const double* const* d0 = as<const double*>(ctx->ptrs);
+    e = launch_ingest(m->view(), m->arena, d0, d0 + nb, m->d_norm, ctx->stream);
+  }
+  std::vector<double> got(nb);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(got.data(), m->d_norm, nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    free_matrix(m);
+    return fail(ctx, CLR_ERR_HIP, "clr_create: %s", hipGetErrorString(e));
+  }
+  for (size_t b = 0; b < nb; ++b) {
+    if (!std::isfinite(got[b])) {
+      free_matrix(m);
+      return fail(ctx, CLR_ERR_NONFINITE, "block %zu has a non-finite norm", b);
+    }
+    if (norms && k[b] != 0) {
+      const double ref = norms[b];
+      if (!(fabs(ref - got[b]) <= 1e-10 * std::max(fabs(got[b]), 1e-300))) {
+        free_matrix(m);
+        return fail(ctx, CLR_ERR_NORM_MISMATCH, "block %zu: norm %.17g given, %.17g computed", b,
+                    ref, got[b]);
+      }
+    }
+  }
+  *out = m;
+  return CLR_OK;
+}
+
+// Recompression of every block of a dense matrix (compression of an input).
+extern "C" clr_status clr_compress(clr_context* ctx, const double* dense, int64_t ld, int nrb,
+                                   const int* row_sizes, int ncb, const int* col_sizes,
+                                   double tol, double drop, clr_matrix** out) {
+  if (!ctx || !out) return CLR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!dense || nrb < 1 || ncb < 1 || !row_sizes || !col_sizes)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "clr_compress: missing input");
+  if (!(tol >= 0.0 && tol < 1.0) || !(drop >= 0.0))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "clr_compress: bad tol or drop");
+  std::vector<int> rs(row_sizes, row_sizes + nrb), cs(col_sizes, col_sizes + ncb);
+  clr_matrix* m = nullptr;
+  clr_status s = alloc_matrix(ctx, rs, cs, &m);
+  if (s != CLR_OK) return s;
+  if (ld < m->rows) {
+    free_matrix(m);
+    return fail(ctx, CLR_ERR_INVALID_ARG, "clr_compress: ld < rows");
+  }
+  const bool square = m->square_blocked();
+  std::vector<RecItem> items;
+  int64_t scratch_total = 0;
+  std::vector<int64_t> scratch_off;
+  for (int I = 0; I < nrb; ++I)
+    for (int J = 0; J < ncb; ++J) {
+      RecItem r{};
+      r.path = (square && I == J) ? kPathForceDense : kPathDense;
+      r.m = rs[I];
+      r.n = cs[J];
+      r.R = 0;
+      r.D = dense + m->roff[I] + (int64_t)m->coff[J] * ld;
+      r.ldd = ld;
+      r.tau = drop;
+      r.out = m->arena + slot_offset(m->roff.data(), m->coff.data(), m->cols, I, J);
+      const int64_t need = rec_scratch_doubles(r.path, r.m, r.n, 0, tol);
+      scratch_off.push_back(need > 0 ? scratch_total : -1);
+      scratch_total += need;
+      const size_t b = (size_t)I * ncb + J;
+      r.kind_out = m->d_kind + b;
+      r.rank_out = m->d_rank + b;
+      r.norm_out = m->d_norm + b;
+      items.push_back(r);
+    }
+  hipError_t e = ensure(ctx->scratch, sizeof(double) * std::max<int64_t>(scratch_total, 1));
+  if (e != hipSuccess) {
+    free_matrix(m);
+    return fail(ctx, CLR_ERR_HIP, "scratch allocation: %s", hipGetErrorString(e));
+  }
+  for (size_t i = 0; i < items.size(); ++i)
+    items[i].scratch = scratch_off[i] >= 0 ? as<double>(ctx->scratch) + scratch_off[i] : nullptr;
+  s = upload(ctx, ctx->rec, items);
+  if (s != CLR_OK) {
+    free_matrix(m);
+    return s;
+  }
+  e = launch_recompress(as<RecItem>(ctx->rec), nullptr, (int)items.size(), tol, as<int>(ctx->status),
+                        ctx->stream);
+  if (e != hipSuccess) {
+    free_matrix(m);
+    return fail(ctx, CLR_ERR_HIP, "recompress launch: %s", hipGetErrorString(e));
+  }
+  s = check_status(ctx);
+  if (s != CLR_OK) {
+    free_matrix(m);
+    return s;
+  }
+  *out = m;
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_destroy(clr_matrix* m) {
+  if (!m) return CLR_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(m->ctx->stream);
+  free_matrix(m);
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_matrix_info(const clr_matrix* m, int* nrb, int* ncb, int64_t* rows,
+                                      int64_t* cols, int64_t* stored) {
+  if (!m) return CLR_ERR_INVALID_ARG;
+  if (nrb) *nrb = m->nrb;
+  if (ncb) *ncb = m->ncb;
+  if (rows) *rows = m->rows;
+  if (cols) *cols = m->cols;
+  if (stored) {
+    HostMeta h;
+    clr_status s = fetch_meta(m->ctx, m, h);
+    if (s != CLR_OK) return s;
+    *stored = (int64_t)stored_elements(m, h);
+  }
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_get_meta(clr_context* ctx, const clr_matrix* m, int8_t* kind, int* rank,
+                                   double* norms) {
+  if (!ctx || !m) return CLR_ERR_INVALID_ARG;
+  HostMeta h;
+  clr_status s = fetch_meta(ctx, m, h);
+  if (s != CLR_OK) return s;
+  const size_t nb = (size_t)m->nrb * m->ncb;
+  for (size_t b = 0; b < nb; ++b) {
+    if (kind) kind[b] = (int8_t)h.kind[b];
+    if (rank) rank[b] = h.kind[b] == 0 ? 0 : h.rank[b];
+    if (norms) norms[b] = h.norm[b];
+  }
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_get_block(clr_context* ctx, const clr_matrix* m, int I, int J,
+                                    double* f0, double* f1) {
+  if (!ctx || !m || !f0) return CLR_ERR_INVALID_ARG;
+  if (I < 0 || J < 0 || I >= m->nrb || J >= m->ncb)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "block index out of range");
+  const size_t b = (size_t)I * m->ncb + J;
+  int k = 0, r = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&k, m->d_kind + b, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(&r, m->d_rank + b, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const int64_t rows = m->rs[I], cols = m->cs[J];
+  const double* src = m->arena + slot_offset(m->roff.data(), m->coff.data(), m->cols, I, J);
+  if (k == 0) return fail(ctx, CLR_ERR_INVALID_ARG, "block (%d,%d) is zero", I, J);
+  if (k == 1) {
+    HIP_TRY(ctx, hipMemcpyAsync(f0, src, sizeof(double) * rows * cols, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    if (!f1) return fail(ctx, CLR_ERR_INVALID_ARG, "low-rank block needs f1");
+    HIP_TRY(ctx, hipMemcpyAsync(f0, src, sizeof(double) * rows * r, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(f1, src + rows * r, sizeof(double) * cols * r, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_to_dense(clr_context* ctx, const clr_matrix* m, double* out, int64_t ld) {
+  if (!ctx || !m || !out) return CLR_ERR_INVALID_ARG;
+  if (ld < m->rows) return fail(ctx, CLR_ERR_INVALID_ARG, "ld < rows");
+  HIP_TRY(ctx, launch_to_dense(m->view(), out, ld, ctx->stream));
+  return CLR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The product
+// ---------------------------------------------------------------------------
+
+namespace {
+
+clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
+                     const clr_gemm_opts* o, clr_matrix** Cout, clr_gemm_stats* st) {
+  *Cout = nullptr;
+  if (A->cs != B->rs)
+    return fail(ctx, CLR_ERR_SHAPE, "column blocking of A differs from row blocking of B");
+  clr_matrix* C = nullptr;
+  clr_status s = alloc_matrix(ctx, A->rs, B->cs, &C);
+  if (s != CLR_OK) return s;
+  auto bail = [&](clr_status code) {
+    free_matrix(C);
+    return code;
+  };
+  hipStream_t stream = ctx->stream;
+  PlanParams P;
+  P.A = A->view();
+  P.B = B->view();
+  P.nrb = A->nrb;
+  P.ncb = B->ncb;
+  P.nkb = A->ncb;
+  P.eps_sp = o->eps_sp;
+  P.screen = o->screen;
+  P.alpha = o->alpha;
+  P.tol = o->tol;
+  P.square = (A->rs == B->cs) ? 1 : 0;
+  P.max_item = max_item(o);
+  const int64_t npairs = (int64_t)P.nrb * P.ncb;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = ensure(ctx->cnt, sizeof(int64_t) * kNumCounters * npairs);
+  if (e == hipSuccess) e = ensure(ctx->off, sizeof(int64_t) * kNumCounters * npairs);
+  if (e == hipSuccess) e = ensure(ctx->st, sizeof(double) * kNumStats * npairs);
+  if (e == hipSuccess) e = ensure(ctx->flags, sizeof(int) * npairs);
+  if (e == hipSuccess) e = ensure(ctx->totals, sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats);
+  if (e != hipSuccess) {
+    fail(ctx, CLR_ERR_HIP, "workspace: %s", hipGetErrorString(e));
+    return bail(CLR_ERR_HIP);
+  }
+  int64_t* tot_cnt = as<int64_t>(ctx->totals);
+  double* tot_st = reinterpret_cast<double*>(tot_cnt + kNumCounters);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], stream);
+  if (e == hipSuccess) e = launch_symbolic(P, as<int64_t>(ctx->cnt), as<double>(ctx->st), as<int>(ctx->flags), stream);
+  if (e == hipSuccess) e = launch_scan(as<int64_t>(ctx->cnt), as<int64_t>(ctx->off), npairs, kNumCounters, tot_cnt, stream);
+  if (e == hipSuccess) e = launch_reduce(as<double>(ctx->st), npairs, kNumStats, tot_st, stream);
+  int64_t hc[kNumCounters];
+  double hs[kNumStats];
+  if (e == hipSuccess) e = hipMemcpyAsync(hc, tot_cnt, sizeof(hc), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hs, tot_st, sizeof(hs), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    fail(ctx, CLR_ERR_HIP, "symbolic phase: %s", hipGetErrorString(e));
+    return bail(CLR_ERR_HIP);
+  }
+  for (int i = 0; i < kNumCounters; ++i)
+    if (hc[i] < 0 || (i != kCntPool && i != kCntScratch && hc[i] > INT32_MAX))
+      return bail(fail(ctx, CLR_ERR_CAPACITY, "work list %d too long (%lld)", i, (long long)hc[i]));
+  if (e == hipSuccess) e = ensure(ctx->seg_dense, sizeof(Seg) * hc[kCntSegDense]);
+  if (e == hipSuccess) e = ensure(ctx->items_dense, sizeof(GemmItem) * hc[kCntGemmItems]);
+  if (e == hipSuccess) e = ensure(ctx->seg_thin1, sizeof(Seg) * hc[kCntThin1]);
+  if (e == hipSuccess) e = ensure(ctx->items_thin1, sizeof(GemmItem) * hc[kCntThin1]);
+  if (e == hipSuccess) e = ensure(ctx->seg_thin2, sizeof(Seg) * hc[kCntThin2]);
+  if (e == hipSuccess) e = ensure(ctx->items_thin2, sizeof(GemmItem) * hc[kCntThin2]);
+  if (e == hipSuccess) e = ensure(ctx->pieces, sizeof(Piece) * hc[kCntPieces]);
+  if (e == hipSuccess) e = ensure(ctx->rec, sizeof(RecItem) * hc[kCntComputed]);
+  if (e == hipSuccess) e = ensure(ctx->pool, sizeof(double) * hc[kCntPool]);
+  if (e == hipSuccess) e = ensure(ctx->scratch, sizeof(double) * hc[kCntScratch]);
+  if (e == hipSuccess && hc[kCntGemmItems] > 0)
+    e = ensure(ctx->acc, sizeof(double) * (size_t)C->rows * C->cols);
+  if (e != hipSuccess) {
+    fail(ctx, CLR_ERR_HIP, "work lists: %s", hipGetErrorString(e));
+    return bail(CLR_ERR_HIP);
+  }
+  FillParams F;
+  F.off = as<int64_t>(ctx->off);
+  F.cnt = as<int64_t>(ctx->cnt);
+  F.flags = as<int>(ctx->flags);
+  F.seg_dense = as<Seg>(ctx->seg_dense);
+  F.items_dense = as<GemmItem>(ctx->items_dense);
+  F.seg_thin1 = as<Seg>(ctx->seg_thin1);
+  F.items_thin1 = as<GemmItem>(ctx->items_thin1);
+  F.seg_thin2 = as<Seg>(ctx->seg_thin2);
+  F.items_thin2 = as<GemmItem>(ctx->items_thin2);
+  F.pieces = as<Piece>(ctx->pieces);
+  F.rec = as<RecItem>(ctx->rec);
+  F.pool = as<double>(ctx->pool);
+  F.scratch = as<double>(ctx->scratch);
+  F.acc = as<double>(ctx->acc);
+  F.c_arena = C->arena;
+  F.c_kind = C->d_kind;
+  F.c_rank = C->d_rank;
+  F.c_norm = C->d_norm;
+  F.c_ncols = C->cols;
+  if (e == hipSuccess) e = launch_fill(P, F, stream);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], stream);
+  if (e == hipSuccess) e = run_ggemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream);
+  if (e == hipSuccess) e = run_ggemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
+  if (e == hipSuccess) e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
+  if (e == hipSuccess)
+    e = launch_recompress(F.rec, F.pieces, (int)hc[kCntComputed], o->tol, as<int>(ctx->status), stream);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[3], stream);
+  if (e != hipSuccess) {
+    fail(ctx, CLR_ERR_HIP, "product launch: %s", hipGetErrorString(e));
+    return bail(CLR_ERR_HIP);
+  }
+  s = check_status(ctx);
+  if (s != CLR_OK) return bail(s);
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->candidates = (int64_t)hs[kStCandidate];
+    st->computed = hc[kCntComputed];
+    st->n_dd = (int64_t)hs[kStNDD];
+    st->n_ld = (int64_t)hs[kStNLD];
+    st->n_dl = (int64_t)hs[kStNDL];
+    st->n_ll = (int64_t)hs[kStNLL];
+    st->triples = st->n_dd + st->n_ld + st->n_dl + st->n_ll;
+    st->flops_dd = hs[kStFlopsDD];
+    st->flops_ld = hs[kStFlopsLD];
+    st->flops_dl = hs[kStFlopsDL];
+    st->flops_ll = hs[kStFlopsLL];
+    st->flops_densify = hs[kStFlopsDensify];
+    st->flops_products = st->flops_dd + st->flops_ld + st->flops_dl + st->flops_ll + st->flops_densify;
+    st->ms_symbolic = elapsed(ctx->ev[0], ctx->ev[1]);
+    st->ms_products = elapsed(ctx->ev[1], ctx->ev[2]);
+    st->ms_recompress = elapsed(ctx->ev[2], ctx->ev[3]);
+    st->ms_total = elapsed(ctx->ev[0], ctx->ev[3]);
+    HostMeta ha, hb, hcm;
+    if ((s = fetch_meta(ctx, A, ha)) != CLR_OK) return bail(s);
+    if ((s = fetch_meta(ctx, B, hb)) != CLR_OK) return bail(s);
+    if ((s = fetch_meta(ctx, C, hcm)) != CLR_OK) return bail(s);
+    st->bytes_compulsory = 8.0 * (stored_elements(A, ha) + stored_elements(B, hb) + stored_elements(C, hcm));
+    std::vector<int> fl(npairs);
+    HIP_TRY(ctx, hipMemcpy(fl.data(), ctx->flags.p, sizeof(int) * npairs, hipMemcpyDeviceToHost));
+    for (int64_t b = 0; b < npairs; ++b) {
+      if (!(fl[b] & kFlagComputed)) continue;
+      if (fl[b] & kFlagDensify) st->densified++;
+      if (hcm.kind[b] == 0) st->dropped++;
+      if (hcm.kind[b] == 1) st->out_dense++;
+      if (hcm.kind[b] == 2) st->out_lowrank++;
+    }
+  }
+  *Cout = C;
+  return CLR_OK;
+}
+
+}  // namespace
+
+extern "C" clr_status clr_gemm(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
+                               const clr_gemm_opts* opts, clr_matrix** C, clr_gemm_stats* st) {
+  if (!ctx || !A || !B || !C) return CLR_ERR_INVALID_ARG;
+  *C = nullptr;
+  clr_status s = check_opts(ctx, opts);
+  if (s != CLR_OK) return s;
+  return gemm_impl(ctx, A, B, opts, C, st);
+}
+
+// ---------------------------------------------------------------------------
+// Blockwise combination a X + b Y + c I
+// ---------------------------------------------------------------------------
+
+extern "C" clr_status clr_axpby(clr_context* ctx, double a, const clr_matrix* X, double b,
+                                const clr_matrix* Y, double c, const clr_gemm_opts* o,
+                                clr_matrix** Tout) {
+  if (!ctx || !X || !Tout) return CLR_ERR_INVALID_ARG;
+  *Tout = nullptr;
+  clr_status s = check_opts(ctx, o);
+  if (s != CLR_OK) return s;
+  if (Y && (Y->rs != X->rs || Y->cs != X->cs))
+    return fail(ctx, CLR_ERR_SHAPE, "clr_axpby: blockings differ");
+  HostMeta hx, hy;
+  if ((s = fetch_meta(ctx, X, hx)) != CLR_OK) return s;
+  if (Y && (s = fetch_meta(ctx, Y, hy)) != CLR_OK) return s;
+  clr_matrix* T = nullptr;
+  if ((s = alloc_matrix(ctx, X->rs, X->cs, &T)) != CLR_OK) return s;
+  const bool square = X->square_blocked();
+  std::vector<RecItem> rec;
+  std::vector<Piece> pieces;
+  std::vector<AxpbyDenseItem> dense;
+  std::vector<GemmItem> items;
+  std::vector<Seg> segs;
+  std::vector<int64_t> scratch_off;
+  int64_t scratch_total = 0;
+  const int maxe = max_item(o);
+  HIP_TRY(ctx, ensure(ctx->acc, sizeof(double) * (size_t)X->rows * X->cols));
+  double* acc = as<double>(ctx->acc);
+  for (int I = 0; I < X->nrb; ++I)
+    for (int J = 0; J < X->ncb; ++J) {
+      const size_t blk = (size_t)I * X->ncb + J;
+      const int m = X->rs[I], n = X->cs[J];
+      const int64_t so = slot_offset(X->roff.data(), X->coff.data(), X->cols, I, J);
+      const int kx = hx.kind[blk];
+      const int ky = Y ? hy.kind[blk] : 0;
+      const bool diag = square && I == J;
+      const bool has_i = diag && c != 0.0;
+      double est = 0.0;
+      if (kx) est += fabs(a) * hx.norm[blk];
+      if (ky) est += fabs(b) * hy.norm[blk];
+      if (has_i) est += fabs(c) * sqrt((double)m);
+      if (!kx && !ky && !has_i) continue;
+      const double tau = o->screen == CLR_SCREEN_AREA ? o->eps_sp * m * (double)n : o->eps_sp;
+      if (est < tau) continue;
+      const int R = (kx == 2 ? hx.rank[blk] : 0) + (ky == 2 ? hy.rank[blk] : 0);
+      const bool any_dense = kx == 1 || ky == 1 || has_i;
+      const bool densify = diag || any_dense || 2 * R >= std::min(m, n);
+      RecItem r{};
+      r.m = m;
+      r.n = n;
+      r.tau = tau;
+      r.out = T->arena + so;
+      r.kind_out = T->d_kind + blk;
+      r.rank_out = T->d_rank + blk;
+      r.norm_out = T->d_norm + blk;
+      const double* xs = X->arena + so;
+      const double* ys = Y ? Y->arena + so : nullptr;
+      if (densify) {
+        r.path = diag ? kPathForceDense : kPathDense;
+        r.D = acc + so;
+        r.ldd = m;
+        AxpbyDenseItem d{};
+        d.D = acc + so;
+        d.X = kx == 1 ? xs : nullptr;
+        d.Y = ky == 1 ? ys : nullptr;
+        d.a = a;
+        d.b = b;
+        d.c = diag ? c : 0.0;
+        d.m = m;
+        d.n = n;
+        dense.push_back(d);
+        const int seg0 = (int)segs.size();
+        int kb = 0;
+        auto add_lr = [&](const double* f, int rk, double sc) {
+          Seg sg{};
+          sg.L = f;                     // U (m x r)
+          sg.sLi = 1;
+          sg.sLk = m;
+          sg.R = f + (int64_t)m * rk;   // V (n x r) used transposed
+          sg.sRk = n;
+          sg.sRj = 1;
+          sg.k = rk;
+          sg.kbase = kb;
+          sg.scale = sc;
+          kb += rk;
+          segs.push_back(sg);
+        };
+        if (kx == 2) add_lr(xs, hx.rank[blk], a);
+        if (ky == 2) add_lr(ys, hy.rank[blk], b);
+        if (kb > 0) {
+          const int pr = num_parts(m, maxe), pc = num_parts(n, maxe);
+          for (int pa = 0; pa < pr; ++pa)
+            for (int pb = 0; pb < pc; ++pb) {
+              GemmItem g{};
+              part_range(m, pr, pa, &g.row0, &g.m);
+              part_range(n, pc, pb, &g.col0, &g.n);
+              g.C = acc + so;
+              g.ldc = m;
+              g.seg0 = seg0;
+              g.nseg = (int)segs.size() - seg0;
+              g.ktotal = kb;
+              g.accumulate = 1;
+              g.alpha = 1.0;
+              items.push_back(g);
+            }
+        }
+      } else {
+        r.path = kPathLowRank;
+        r.piece0 = (int)pieces.size();
+        r.R = R;
+        auto add_piece = [&](const double* f, int rk, double sc) {
+          Piece p{};
+          p.U = f;
+          p.ldu = m;
+          p.V = f + (int64_t)m * rk;
+          p.ldv = n;
+          p.r = rk;
+          p.scale = sc;
+          pieces.push_back(p);
+        };
+        if (kx == 2) add_piece(xs, hx.rank[blk], a);
+        if (ky == 2) add_piece(ys, hy.rank[blk], b);
+        r.npieces = (int)pieces.size() - r.piece0;
+      }
+      const int64_t need = rec_scratch_doubles(r.path, m, n, r.R, o->tol);
+      scratch_off.push_back(need > 0 ? scratch_total : -1);
+      scratch_total += need;
+      rec.push_back(r);
+    }
+  auto bail = [&](clr_status code) {
+    free_matrix(T);
+    return code;
+  };
+  if (ensure(ctx->scratch, sizeof(double) * std::max<int64_t>(scratch_total, 1)) != hipSuccess)
+    return bail(fail(ctx, CLR_ERR_HIP, "scratch allocation failed"));
+  for (size_t i = 0; i < rec.size(); ++i)
+    rec[i].scratch = scratch_off[i] >= 0 ? as<double>(ctx->scratch) + scratch_off[i] : nullptr;
+  if ((s = upload(ctx, ctx->aux_dense, dense)) != CLR_OK) return bail(s);
+  if ((s = upload(ctx, ctx->aux_segs, segs)) != CLR_OK) return bail(s);
+  if ((s = upload(ctx, ctx->aux_items, items)) != CLR_OK) return bail(s);
+  if ((s = upload(ctx, ctx->pieces, pieces)) != CLR_OK) return bail(s);
+  if ((s = upload(ctx, ctx->rec, rec)) != CLR_OK) return bail(s);
+  hipError_t e = launch_axpby_dense(ctx->aux_dense.p, (int)dense.size(), ctx->stream);
+  if (e == hipSuccess)
+    e = run_ggemm(o, as<GemmItem>(ctx->aux_items), as<Seg>(ctx->aux_segs), (int)items.size(), ctx->stream);
+  if (e == hipSuccess)
+    e = launch_recompress(as<RecItem>(ctx->rec), as<Piece>(ctx->pieces), (int)rec.size(), o->tol,
+                          as<int>(ctx->status), ctx->stream);
+  if (e != hipSuccess) return bail(fail(ctx, CLR_ERR_HIP, "axpby launch: %s", hipGetErrorString(e)));
+  if ((s = check_status(ctx)) != CLR_OK) return bail(s);
+  *Tout = T;
+  return CLR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Residuals and the square-root inverse
+// ---------------------------------------------------------------------------
+
+extern "C" clr_status clr_identity_residual(clr_context* ctx, const clr_matrix* X, double* out) {
+  if (!ctx || !X || !out) return CLR_ERR_INVALID_ARG;
+  if (!X->square_blocked()) return fail(ctx, CLR_ERR_SHAPE, "identity residual needs a square blocking");
+  const int64_t nb = (int64_t)X->nrb * X->ncb;
+  HIP_TRY(ctx, ensure(ctx->terms, sizeof(double) * nb));
+  HIP_TRY(ctx, launch_identity_terms(X->view(), as<double>(ctx->terms), ctx->stream));
+  std::vector<double> t(nb);
+  HIP_TRY(ctx, hipMemcpyAsync(t.data(), ctx->terms.p, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double s = 0.0;
+  for (double v : t) s += v;
+  *out = sqrt(s) / sqrt((double)X->rows);
+  return CLR_OK;
+}
+
+namespace {
+
+clr_status scaled_copy(clr_context* ctx, const clr_matrix* src, double sc, clr_matrix** out) {
+  clr_status s = copy_matrix(ctx, src, out);
+  if (s != CLR_OK) return s;
+  HIP_TRY(ctx, launch_scale((*out)->view(), (*out)->arena, (*out)->d_norm, sc, ctx->stream));
+  return CLR_OK;
+}
+
+clr_status identity_matrix(clr_context* ctx, const std::vector<int>& sizes, clr_matrix** out) {
+  clr_matrix* Z = nullptr;
+  clr_status s = alloc_matrix(ctx, sizes, sizes, &Z);
+  if (s != CLR_OK) return s;
+  // Z = 0 * (nothing) + 1 * I through the dense combination path
+  const int nb = Z->nrb;
+  std::vector<AxpbyDenseItem> items;
+  std::vector<int> kind(nb * nb, 0), rank(nb * nb, 0);
+  std::vector<double> norm(nb * nb, 0.0);
+  for (int I = 0; I < nb; ++I) {
+    AxpbyDenseItem d{};
+    d.D = Z->arena + slot_offset(Z->roff.data(), Z->coff.data(), Z->cols, I, I);
+    d.c = 1.0;
+    d.m = d.n = sizes[I];
+    items.push_back(d);
+    kind[I * nb + I] = 1;
+    rank[I * nb + I] = sizes[I];
+    norm[I * nb + I] = sqrt((double)sizes[I]);
+  }
+  if ((s = upload(ctx, ctx->aux_dense, items)) != CLR_OK) {
+    free_matrix(Z);
+    return s;
+  }
+  hipError_t e = launch_axpby_dense(ctx->aux_dense.p, nb, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(Z->d_kind, kind.data(), sizeof(int) * nb * nb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(Z->d_rank, rank.data(), sizeof(int) * nb * nb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(Z->d_norm, norm.data(), sizeof(double) * nb * nb, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    free_matrix(Z);
+    return fail(ctx, CLR_ERR_HIP, "identity: %s", hipGetErrorString(e));
+  }
+  *out = Z;
+  return CLR_OK;
+}
+
+// ||W S W - I||_F / sqrt(N) with untruncated, unscreened FP64 products.
+clr_status explicit_residual(clr_context* ctx, const clr_matrix* W, const clr_matrix* S,
+                             double* out, double* flops) {
+  clr_gemm_opts ex{};
+  ex.tol = 0.0;
+  ex.eps_sp = 0.0;
+  ex.screen = CLR_SCREEN_ABS;
+  ex.precision = CLR_FP64;
+  ex.alpha = 1.0;
+  clr_matrix *WS = nullptr, *WSW = nullptr;
+  clr_gemm_stats g1{}, g2{};
+  clr_status s = gemm_impl(ctx, W, S, &ex, &WS, &g1);
+  if (s != CLR_OK) return s;
+  s = gemm_impl(ctx, WS, W, &ex, &WSW, &g2);
+  free_matrix(WS);
+  if (s != CLR_OK) return s;
+  s = clr_identity_residual(ctx, WSW, out);
+  free_matrix(WSW);
+  if (flops) *flops += g1.flops_products + g2.flops_products;
+  return s;
+}
+
+}  // namespace
+
+extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const clr_sqrtinv_opts* o,
+                                   clr_matrix** Wout, clr_sqrtinv_stats* st) {
+  if (!ctx || !S || !o || !Wout) return CLR_ERR_INVALID_ARG;
+  *Wout = nullptr;
+  clr_status s = check_opts(ctx, &o->g);
+  if (s != CLR_OK) return s;
+  if (!S->square_blocked()) return fail(ctx, CLR_ERR_SHAPE, "S must be square-blocked");
+  if (!(o->conv_tol >= 0.0) || o->max_iter < 1 || o->fixed_iters < 0 || !(o->alpha >= 0.0))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "bad iteration options");
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[4], ctx->stream));
+  double alpha = o->alpha;
+  if (alpha == 0.0) {
+    HostMeta h;
+    if ((s = fetch_meta(ctx, S, h)) != CLR_OK) return s;
+    double worst = 0.0;
+    for (int I = 0; I < S->nrb; ++I) {
+      double row = 0.0;
+      for (int J = 0; J < S->ncb; ++J)
+        if (h.kind[(size_t)I * S->ncb + J]) row += h.norm[(size_t)I * S->ncb + J];
+      worst = std::max(worst, row);
+    }
+    if (!(worst > 0.0)) return fail(ctx, CLR_ERR_INVALID_ARG, "S has no nonzero blocks");
+    alpha = 1.0 / worst;
+  }
+  clr_gemm_opts g = o->g;
+  g.alpha = 1.0;
+  clr_gemm_opts ga = g;
+  ga.alpha = alpha;
+  clr_matrix *Z = nullptr, *Y = nullptr;
+  if ((s = identity_matrix(ctx, S->rs, &Z)) != CLR_OK) return s;
+  if ((s = copy_matrix(ctx, S, &Y)) != CLR_OK) {
+    free_matrix(Z);
+    return s;
+  }
+  std::vector<double> internal;
+  std::vector<double> expl;
+  double flops = 0.0;
+  int n_gemms = 0;
+  int it = 0;
+  clr_status result = CLR_ERR_NOT_CONVERGED;
+  bool converged = false;
+  double last_explicit = -1.0;
+  const int n_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
+  for (it = 0; it < n_iter; ++it) {
+    clr_matrix *X = nullptr, *Q = nullptr, *T = nullptr, *Zn = nullptr, *Yn = nullptr;
+    clr_gemm_stats gs{};
+    double r = 0.0;
+    s = gemm_impl(ctx, Y, Z, &ga, &X, &gs);                 // X_n = alpha Y_n Z_n   (Eq. (8))
+    flops += gs.flops_products;
+    if (s == CLR_OK) s = gemm_impl(ctx, X, X, &g, &Q, &gs); // X_n^2
+    flops += gs.flops_products;
+    if (s == CLR_OK) s = clr_axpby(ctx, -10.0 / 8.0, X, 3.0 / 8.0, Q, 15.0 / 8.0, &g, &T);  // Eq. (9)
+    if (s == CLR_OK) s = gemm_impl(ctx, Z, T, &g, &Zn, &gs);  // Z_{n+1} = Z_n T_n     (Eq. (10))
+    flops += gs.flops_products;
+    if (s == CLR_OK) s = gemm_impl(ctx, T, Y, &g, &Yn, &gs);  // Y_{n+1} = T_n Y_n     (Eq. (11))
+    flops += gs.flops_products;
+    if (s == CLR_OK) s = clr_identity_residual(ctx, X, &r);
+    n_gemms += 4;
+    free_matrix(X);
+    free_matrix(Q);
+    free_matrix(T);
+    if (s != CLR_OK) {
+      free_matrix(Zn);
+      free_matrix(Yn);
+      free_matrix(Z);
+      free_matrix(Y);
+      return s;
+    }
+    free_matrix(Z);
+    free_matrix(Y);
+    Z = Zn;
+    Y = Yn;
+    internal.push_back(r);
+    if (o->fixed_iters > 0) continue;
+    if (r <= o->conv_tol) {
+      clr_matrix* W = nullptr;
+      if ((s = scaled_copy(ctx, Z, sqrt(alpha), &W)) != CLR_OK) break;
+      double e = 0.0;
+      s = explicit_residual(ctx, W, S, &e, &flops);
+      n_gemms += 2;
+      free_matrix(W);
+      if (s != CLR_OK) break;
+      expl.push_back(e);
+      if (e <= o->conv_tol) {
+        converged = true;
+        result = CLR_OK;
+        ++it;
+        break;
+      }
+      if (last_explicit >= 0.0 && e > 0.5 * last_explicit) {
+        result = CLR_ERR_NOT_CONVERGED;
+        ++it;
+        break;
+      }
+      last_explicit = e;
+    } else if (internal.size() >= 3 && internal[internal.size() - 1] > internal[internal.size() - 2] &&
+               internal[internal.size() - 2] > internal[internal.size() - 3]) {
+      free_matrix(Z);
+      free_matrix(Y);
+      return fail(ctx, CLR_ERR_DIVERGED, "||X_n - I|| grew in two consecutive iterations");
+    }
+  }
+  if (s != CLR_OK) {
+    free_matrix(Z);
+    free_matrix(Y);
+    return s;
+  }
+  if (o->fixed_iters > 0) result = CLR_OK;
+  clr_matrix* W = nullptr;
+  s = scaled_copy(ctx, Z, sqrt(alpha), &W);
+  free_matrix(Z);
+  free_matrix(Y);
+  if (s != CLR_OK) return s;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[5], ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(ctx->ev[5]));
+  if (st) {
+    memset(st, 0, sizeof(*st));
+    st->iterations = o->fixed_iters > 0 ? o->fixed_iters : it;
+    st->converged = converged ? 1 : 0;
+    st->alpha = alpha;
+    st->internal_residual = internal.empty() ? -1.0 : internal.back();
+    st->explicit_residual = expl.empty() ? -1.0 : expl.back();
+    st->n_gemms = n_gemms;
+    st->flops_products = flops;
+    st->ms_total = elapsed(ctx->ev[4], ctx->ev[5]);
+  }
+  *Wout = W;
+  if (result != CLR_OK)
+    fail(ctx, result, "stopped after %d iterations without meeting conv_tol", it);
+  return result;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoints
+// ---------------------------------------------------------------------------
+
+extern "C" clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
+                                        double alpha, const double* dC, int64_t ldc, double* dA,
+                                        int64_t lda, double* dB, int64_t ldb) {
+  (void)A; (void)B; (void)alpha; (void)dC; (void)ldc; (void)dA; (void)lda; (void)dB; (void)ldb;
+  return fail(ctx, CLR_ERR_INVALID_ARG, "clr_gemm_backward: not available in this build");
+}
+
+extern "C" clr_status clr_sqrt_inv_backward(clr_context* ctx, const clr_matrix* S,
+                                            const clr_sqrtinv_opts* opts, int iters,
+                                            int checkpoint_every, const double* Wbar, double* dS,
+                                            int64_t ld, clr_matrix** W) {
+  (void)S; (void)opts; (void)iters; (void)checkpoint_every; (void)Wbar; (void)dS; (void)ld; (void)W;
+  return fail(ctx, CLR_ERR_INVALID_ARG, "clr_sqrt_inv_backward: not available in this build");
+}

@@ -1,0 +1,210 @@
+// Internal declarations shared by the HIP kernels and the host driver of the
+// CLR block-product library (gfx950).  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clr {
+
+// ---------------------------------------------------------------------------
+// Tunables
+// ---------------------------------------------------------------------------
+constexpr int kSlabK = 16;            // inner indices staged in LDS per pipeline step
+constexpr int kGemmThreads = 256;     // 4 waves, arranged 2 x 2 over the output tile
+constexpr int kF64WaveTiles = 5;      // 16x16 MFMA tiles per wave and dimension (FP64 form)
+constexpr int kF32WaveTiles = 4;      // same for the FP32-MFMA (mixed) form
+constexpr int kMaxItemF64 = 32 * kF64WaveTiles;   // 160: largest output tile edge per item
+constexpr int kMaxItemF32 = 32 * kF32WaveTiles;   // 128
+constexpr int kRecThreads = 256;      // recompression workgroup (16 groups of 16 lanes)
+constexpr int kRecLdsBytes = 144 * 1024;  // dynamic LDS for the working set (160 KiB minus bookkeeping)
+constexpr int kJacobiMaxSweeps = 40;
+
+// ---------------------------------------------------------------------------
+// Work descriptors (device resident, built by the planning kernels)
+// ---------------------------------------------------------------------------
+
+// One term of a grouped GEMM item:  scale * L (m x k) * R (k x n) where
+// L(i, kk) = L[i*sLi + kk*sLk] and R(kk, j) = R[kk*sRk + j*sRj].
+struct Seg {
+  const double* L;
+  const double* R;
+  int64_t sLi, sLk, sRk, sRj;
+  int k;          // inner length of this term
+  int kbase;      // inner offset of this term inside its item's concatenated inner range
+  double scale;
+};
+
+// One output tile: C[row0.., col0..] (m x n, column-major, ldc) =
+//   (accumulate ? C : 0) + alpha * sum_s scale_s * L_s * R_s,
+// where every term's L is offset by row0 rows and R by col0 columns.
+struct GemmItem {
+  double* C;
+  int64_t ldc;
+  int row0, col0, m, n;
+  int seg0, nseg;
+  int ktotal;
+  int accumulate;
+  double alpha;
+};
+
+// A low-rank term scale * U V^T of a result block kept in factored form.
+struct Piece {
+  const double* U;
+  const double* V;
+  int64_t ldu, ldv;
+  int r;
+  int pad;
+  double scale;
+};
+
+enum RecPath : int { kPathSkip = -1, kPathDense = 0, kPathLowRank = 1, kPathForceDense = 2 };
+
+// Recompression of one result block (Sec. 4.1, Eqs. (5)-(7) and the rank rule).
+struct RecItem {
+  int path;
+  int m, n;
+  int piece0, npieces, R;     // low-rank path: concatenated factors
+  const double* D;            // dense path: accumulated block
+  int64_t ldd;
+  double tau;                 // drop threshold
+  double* out;                // result slot (dense m*n, or U m*r followed by V n*r)
+  double* scratch;            // global working memory when the LDS budget is exceeded
+  int* kind_out;
+  int* rank_out;
+  double* norm_out;
+};
+
+// Doubles of working memory the recompression of one block needs, and how much
+// of it must come from global scratch (when it exceeds the LDS budget).
+__host__ __device__ inline int64_t rec_work_doubles(int path, int m, int n, int R) {
+  if (path == kPathLowRank) return (int64_t)(m + n) * R + 2 * (int64_t)R * R + 2 * (int64_t)R;
+  return (int64_t)m * n;
+}
+__host__ __device__ inline int64_t rec_scratch_doubles(int path, int m, int n, int R, double tol) {
+  if (path == kPathSkip || path == kPathForceDense) return 0;
+  if (path == kPathDense && tol == 0.0) return 0;
+  const int64_t w = rec_work_doubles(path, m, n, R);
+  return w * 8 > (int64_t)kRecLdsBytes ? w : 0;
+}
+
+// Per-block plan produced by the symbolic phase of a product.
+enum PlanCounter : int {
+  kCntSegDense = 0,   // terms of the dense accumulation GEMM (densified blocks)
+  kCntPieces,         // low-rank pieces (blocks kept in factored form)
+  kCntThin1,          // thin factor products, first launch
+  kCntThin2,          // thin factor products that consume a core Z (second launch)
+  kCntPool,           // doubles of thin-product output
+  kCntScratch,        // doubles of recompression scratch
+  kCntComputed,       // 1 if the block passed screening
+  kCntGemmItems,      // output tiles of the dense accumulation GEMM
+  kNumCounters
+};
+
+// Floating-point per-block statistics of the symbolic phase.
+enum PlanStat : int {
+  kStEst = 0, kStFlopsDD, kStFlopsLD, kStFlopsDL, kStFlopsLL, kStFlopsDensify,
+  kStNDD, kStNLD, kStNDL, kStNLL, kStCandidate, kNumStats
+};
+
+// Device view of a CLR matrix's metadata and arena.
+struct MatView {
+  const int* kind;      // nrb*ncb
+  const int* rank;
+  const double* norm;
+  const int* roff;      // nrb+1
+  const int* coff;      // ncb+1
+  const double* arena;  // slot (I,J) at roff[I]*ncols + m_I*coff[J]
+  int nrb, ncb;
+  int64_t ncols;
+};
+
+__host__ __device__ inline int64_t slot_offset(const int* roff, const int* coff, int64_t ncols,
+                                               int I, int J) {
+  const int64_t m = roff[I + 1] - roff[I];
+  return (int64_t)roff[I] * ncols + m * (int64_t)coff[J];
+}
+
+// Split `extent` into at most ceil(extent/maxe) parts on 16-element boundaries.
+__host__ __device__ inline int num_parts(int extent, int maxe) {
+  return (extent + maxe - 1) / maxe;
+}
+__host__ __device__ inline void part_range(int extent, int parts, int p, int* start, int* len) {
+  const int tiles = (extent + 15) / 16;
+  const int base = tiles / parts, extra = tiles % parts;
+  const int t0 = p * base + (p < extra ? p : extra);
+  const int tn = base + (p < extra ? 1 : 0);
+  int s = t0 * 16, e = (t0 + tn) * 16;
+  if (e > extent) e = extent;
+  *start = s;
+  *len = e - s;
+}
+
+struct PlanParams {
+  MatView A, B;
+  int nrb, ncb, nkb;
+  double eps_sp;
+  int screen;     // 0 absolute, 1 per area
+  double alpha;
+  double tol;
+  int square;     // C's row and column blockings are identical
+  int max_item;   // largest output tile edge of the grouped GEMM
+};
+
+struct FillParams {
+  const int64_t* off;     // [kNumCounters][npairs]
+  const int64_t* cnt;
+  const int* flags;
+  Seg* seg_dense;
+  GemmItem* items_dense;
+  Seg* seg_thin1;
+  GemmItem* items_thin1;
+  Seg* seg_thin2;
+  GemmItem* items_thin2;
+  Piece* pieces;
+  RecItem* rec;
+  double* pool;
+  double* scratch;
+  double* acc;            // dense accumulators, same slot layout as C
+  double* c_arena;
+  int* c_kind;
+  int* c_rank;
+  double* c_norm;
+  int64_t c_ncols;
+};
+
+enum : int { kFlagComputed = 1, kFlagDensify = 2, kFlagForce = 4 };
+
+// Dense part of one block of a X + b Y + c I.
+struct AxpbyDenseItem {
+  double* D;
+  const double* X;   // dense block of X or null
+  const double* Y;   // dense block of Y or null
+  double a, b, c;
+  int m, n;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s);
+hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
+                            hipStream_t s);
+hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
+                             int* status, hipStream_t s);
+hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
+                           hipStream_t s);
+hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,
+                       hipStream_t s);
+hipError_t launch_reduce(const double* in, int64_t n, int narrays, double* totals, hipStream_t s);
+hipError_t launch_fill(const PlanParams& P, const FillParams& F, hipStream_t s);
+hipError_t launch_ingest(const MatView& M, double* arena, const double* const* f0,
+                         const double* const* f1, double* norm_out, hipStream_t s);
+hipError_t launch_to_dense(const MatView& M, double* out, int64_t ld, hipStream_t s);
+hipError_t launch_scale(const MatView& M, double* arena, double* norm, double sc, hipStream_t s);
+hipError_t launch_identity_terms(const MatView& M, double* out, hipStream_t s);
+hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+
+}  // namespace clr

@@ -1,0 +1,194 @@
+// Elementwise and per-block helper kernels of the CLR library: ingest of
+// caller factors into the slot arena with exact block norms, expansion to a
+// dense matrix, scaling, the blockwise terms of ||X - I||_F, and the dense
+// part of the blockwise combination a X + b Y + c I.
+#include "clr_internal.h"
+
+namespace clr {
+
+__device__ double wg_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Copy caller factors into the arena and compute exact block norms
+// (dense: sqrt(sum d^2); low rank: sqrt(sum (U V^T)_ij^2)).
+__global__ __launch_bounds__(256) void k_ingest(MatView M, double* arena, const double* const* f0,
+                                                const double* const* f1, double* norm_out) {
+  __shared__ double red[256];
+  const int blk = blockIdx.x;
+  const int I = blk / M.ncb, J = blk % M.ncb;
+  const int kind = M.kind[blk];
+  if (kind == 0) {
+    if (threadIdx.x == 0) norm_out[blk] = 0.0;
+    return;
+  }
+  const int m = M.roff[I + 1] - M.roff[I];
+  const int n = M.coff[J + 1] - M.coff[J];
+  double* dst = arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  double part = 0.0;
+  if (kind == 1) {
+    const double* src = f0[blk];
+    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
+      const double v = src[e];
+      dst[e] = v;
+      part += v * v;
+    }
+  } else {
+    const int r = M.rank[blk];
+    const double* u = f0[blk];
+    const double* v = f1[blk];
+    for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += 256) dst[e] = u[e];
+    for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += 256) dst[(int64_t)m * r + e] = v[e];
+    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
+      const int i = (int)(e % m), j = (int)(e / m);
+      double s = 0.0;
+      for (int c = 0; c < r; ++c) s += u[i + (int64_t)c * m] * v[j + (int64_t)c * n];
+      part += s * s;
+    }
+  }
+  const double tot = wg_sum(part, red);
+  if (threadIdx.x == 0) norm_out[blk] = sqrt(tot);
+}
+
+// out (rows x cols, column-major, ld) = dense expansion of M.
+__global__ __launch_bounds__(256) void k_to_dense(MatView M, double* out, int64_t ld) {
+  const int blk = blockIdx.x;
+  const int I = blk / M.ncb, J = blk % M.ncb;
+  const int m = M.roff[I + 1] - M.roff[I];
+  const int n = M.coff[J + 1] - M.coff[J];
+  const int kind = M.kind[blk];
+  const double* src = M.arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  double* dst = out + M.roff[I] + (int64_t)M.coff[J] * ld;
+  const int r = kind == 2 ? M.rank[blk] : 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    double v = 0.0;
+    if (kind == 1) {
+      v = src[e];
+    } else if (kind == 2) {
+      const double* u = src;
+      const double* w = src + (int64_t)m * r;
+      for (int c = 0; c < r; ++c) v += u[i + (int64_t)c * m] * w[j + (int64_t)c * n];
+    }
+    dst[i + (int64_t)j * ld] = v;
+  }
+}
+
+// M <- s * M  (dense blocks and U factors scaled; norms by |s|).
+__global__ __launch_bounds__(256) void k_scale(MatView M, double* arena, double* norm, double s) {
+  const int blk = blockIdx.x;
+  const int kind = M.kind[blk];
+  if (kind == 0) return;
+  const int I = blk / M.ncb, J = blk % M.ncb;
+  const int m = M.roff[I + 1] - M.roff[I];
+  const int n = M.coff[J + 1] - M.coff[J];
+  double* dst = arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  const int64_t cnt = kind == 1 ? (int64_t)m * n : (int64_t)m * M.rank[blk];
+  for (int64_t e = threadIdx.x; e < cnt; e += 256) dst[e] *= s;
+  if (threadIdx.x == 0) norm[blk] = fabs(s) * norm[blk];
+}
+
+// Per-block term of ||X - I||_F^2: diagonal blocks exactly, others by their stored norm.
+__global__ __launch_bounds__(256) void k_identity_terms(MatView M, double* out) {
+  __shared__ double red[256];
+  const int blk = blockIdx.x;
+  const int I = blk / M.ncb, J = blk % M.ncb;
+  const int kind = M.kind[blk];
+  const int m = M.roff[I + 1] - M.roff[I];
+  const int n = M.coff[J + 1] - M.coff[J];
+  if (I != J) {
+    if (threadIdx.x == 0) out[blk] = kind == 0 ? 0.0 : M.norm[blk] * M.norm[blk];
+    return;
+  }
+  const double* src = M.arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  const int r = kind == 2 ? M.rank[blk] : 0;
+  double part = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    double v = 0.0;
+    if (kind == 1) {
+      v = src[e];
+    } else if (kind == 2) {
+      for (int c = 0; c < r; ++c) v += src[i + (int64_t)c * m] * src[(int64_t)m * r + j + (int64_t)c * n];
+    }
+    if (i == j) v -= 1.0;
+    part += v * v;
+  }
+  const double tot = wg_sum(part, red);
+  if (threadIdx.x == 0) out[blk] = tot;
+}
+
+// D = a X + b Y + c I over the dense parts of one block.
+__global__ __launch_bounds__(256) void k_axpby_dense(const AxpbyDenseItem* items) {
+  const AxpbyDenseItem it = items[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < (int64_t)it.m * it.n; e += 256) {
+    const int i = (int)(e % it.m), j = (int)(e / it.m);
+    double v = 0.0;
+    if (it.X) v += it.a * it.X[e];
+    if (it.Y) v += it.b * it.Y[e];
+    if (i == j) v += it.c;
+    it.D[e] = v;
+  }
+}
+
+__global__ void k_fill_i32(int* p, int v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double* p, double v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_ingest(const MatView& M, double* arena, const double* const* f0,
+                         const double* const* f1, double* norm_out, hipStream_t s) {
+  const int nb = M.nrb * M.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ingest, dim3(nb), dim3(256), 0, s, M, arena, f0, f1, norm_out);
+  return hipGetLastError();
+}
+hipError_t launch_to_dense(const MatView& M, double* out, int64_t ld, hipStream_t s) {
+  const int nb = M.nrb * M.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_dense, dim3(nb), dim3(256), 0, s, M, out, ld);
+  return hipGetLastError();
+}
+hipError_t launch_scale(const MatView& M, double* arena, double* norm, double sc, hipStream_t s) {
+  const int nb = M.nrb * M.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale, dim3(nb), dim3(256), 0, s, M, arena, norm, sc);
+  return hipGetLastError();
+}
+hipError_t launch_identity_terms(const MatView& M, double* out, hipStream_t s) {
+  const int nb = M.nrb * M.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_identity_terms, dim3(nb), dim3(256), 0, s, M, out);
+  return hipGetLastError();
+}
+hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby_dense, dim3(n), dim3(256), 0, s, (const AxpbyDenseItem*)items);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace clr

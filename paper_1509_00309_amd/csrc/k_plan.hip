@@ -1,0 +1,386 @@
+// Symbolic phase of the CLR product C = alpha A B on the device.
+//
+// k_symbolic: one thread per candidate result block (I, J).  It walks the
+//   inner block index K in ascending order over the pairs where both A_IK
+//   and B_KJ are nonzero, accumulates the norm estimate
+//   est_IJ = |alpha| sum_K ||A_IK||_F ||B_KJ||_F (triangle inequality and
+//   submultiplicativity, Sec. 4.1), applies the screening test est >= tau,
+//   decides dense or factored accumulation, and counts the work and memory
+//   every later phase needs.
+// k_scan:     exclusive prefix sums of those counts (one workgroup).
+// k_reduce:   deterministic totals of the per-block statistics.
+// k_fill:     writes the work lists at the scanned offsets: thin factor
+//   products (Eq. (4)), terms of the dense accumulation GEMM, low-rank pieces
+//   of factored blocks (Eq. (5)) and one recompression item per block.
+#include "clr_internal.h"
+
+namespace clr {
+
+__device__ inline int64_t parts2(int rows, int cols, int maxe) {
+  return (int64_t)num_parts(rows, maxe) * num_parts(cols, maxe);
+}
+
+__global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __restrict__ st,
+                           int* __restrict__ flags) {
+  const int npairs = P.nrb * P.ncb;
+  const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pair >= npairs) return;
+  const int I = pair / P.ncb, J = pair % P.ncb;
+  const int m = P.A.roff[I + 1] - P.A.roff[I];
+  const int n = P.B.coff[J + 1] - P.B.coff[J];
+  double est = 0.0, fdd = 0.0, fld = 0.0, fdl = 0.0, fll = 0.0, fden = 0.0;
+  int nseg = 0, ndd = 0, nld = 0, ndl = 0, nll = 0;
+  int64_t rcat = 0, pool = 0, thin1 = 0, thin2 = 0;
+  bool anydd = false;
+  // low-rank contributions that a densified block adds with rank r cost 2 m n r
+  int64_t lr_rank_sum = 0;
+  for (int K = 0; K < P.nkb; ++K) {
+    const int ka = P.A.kind[I * P.nkb + K];
+    if (ka == 0) continue;
+    const int kb = P.B.kind[K * P.ncb + J];
+    if (kb == 0) continue;
+    const int k = P.A.coff[K + 1] - P.A.coff[K];
+    est += P.A.norm[I * P.nkb + K] * P.B.norm[K * P.ncb + J];
+    ++nseg;
+    if (ka == 1 && kb == 1) {
+      anydd = true;
+      ++ndd;
+      fdd += 2.0 * m * (double)k * n;
+    } else if (ka == 2 && kb == 1) {
+      const int ra = P.A.rank[I * P.nkb + K];
+      ++nld;
+      rcat += ra;
+      pool += (int64_t)n * ra;
+      thin1 += parts2(n, ra, P.max_item);
+      fld += 2.0 * ra * (double)k * n;
+    } else if (ka == 1 && kb == 2) {
+      const int rb = P.B.rank[K * P.ncb + J];
+      ++ndl;
+      rcat += rb;
+      pool += (int64_t)m * rb;
+      thin1 += parts2(m, rb, P.max_item);
+      fdl += 2.0 * m * (double)k * rb;
+    } else {
+      const int ra = P.A.rank[I * P.nkb + K];
+      const int rb = P.B.rank[K * P.ncb + J];
+      ++nll;
+      pool += (int64_t)ra * rb;
+      thin1 += parts2(ra, rb, P.max_item);
+      if (rb < ra) {
+        rcat += rb;
+        pool += (int64_t)m * rb;
+        thin2 += parts2(m, rb, P.max_item);
+        fll += 2.0 * k * (double)ra * rb + 2.0 * m * (double)ra * rb;
+      } else {
+        rcat += ra;
+        pool += (int64_t)n * ra;
+        thin2 += parts2(n, ra, P.max_item);
+        fll += 2.0 * k * (double)ra * rb + 2.0 * n * (double)ra * rb;
+      }
+    }
+  }
+  lr_rank_sum = rcat;
+  est *= fabs(P.alpha);
+  const double tau = P.screen ? P.eps_sp * m * (double)n : P.eps_sp;
+  const bool candidate = nseg > 0;
+  const bool computed = candidate && est >= tau;
+  const bool force = P.square && I == J;
+  const int mn = m < n ? m : n;
+  const bool densify = force || anydd || 2 * rcat >= mn;
+  int64_t c[kNumCounters];
+  for (int i = 0; i < kNumCounters; ++i) c[i] = 0;
+  if (computed) {
+    c[kCntSegDense] = densify ? nseg : 0;
+    c[kCntPieces] = densify ? 0 : nseg;
+    c[kCntThin1] = thin1;
+    c[kCntThin2] = thin2;
+    c[kCntPool] = pool;
+    const int path = force ? kPathForceDense : (densify ? kPathDense : kPathLowRank);
+    c[kCntScratch] = rec_scratch_doubles(path, m, n, (int)rcat, P.tol);
+    c[kCntComputed] = 1;
+    c[kCntGemmItems] = densify ? parts2(m, n, P.max_item) : 0;
+    if (densify) fden = 2.0 * m * (double)n * (double)lr_rank_sum;
+  }
+  for (int i = 0; i < kNumCounters; ++i) cnt[(int64_t)i * npairs + pair] = c[i];
+  const double s[kNumStats] = {est,
+                               computed ? fdd : 0.0,
+                               computed ? fld : 0.0,
+                               computed ? fdl : 0.0,
+                               computed ? fll : 0.0,
+                               computed ? fden : 0.0,
+                               computed ? (double)ndd : 0.0,
+                               computed ? (double)nld : 0.0,
+                               computed ? (double)ndl : 0.0,
+                               computed ? (double)nll : 0.0,
+                               candidate ? 1.0 : 0.0};
+  for (int i = 0; i < kNumStats; ++i) st[(int64_t)i * npairs + pair] = s[i];
+  flags[pair] = (computed ? kFlagComputed : 0) | (densify ? kFlagDensify : 0) |
+                (force ? kFlagForce : 0);
+}
+
+// Exclusive prefix sums of `narrays` arrays of length n (one workgroup of 1024).
+__global__ __launch_bounds__(1024) void k_scan(const int64_t* __restrict__ in,
+                                               int64_t* __restrict__ out, int64_t n,
+                                               int narrays, int64_t* __restrict__ totals) {
+  __shared__ int64_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  for (int a = 0; a < narrays; ++a) {
+    const int64_t* x = in + (int64_t)a * n;
+    int64_t* y = out + (int64_t)a * n;
+    const int64_t b0 = tid * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    int64_t s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += x[i];
+    part[tid] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 1024 partials
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int64_t v = tid >= o ? part[tid - o] : 0;
+      __syncthreads();
+      part[tid] += v;
+      __syncthreads();
+    }
+    int64_t run = part[tid] - s;
+    for (int64_t i = b0; i < b1; ++i) {
+      y[i] = run;
+      run += x[i];
+    }
+    if (tid == 1023) totals[a] = part[1023];
+    __syncthreads();
+  }
+}
+
+// Totals of `narrays` double arrays of length n in a fixed order (one workgroup of 256).
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, int64_t n,
+                                                int narrays, double* __restrict__ totals) {
+  __shared__ double part[256];
+  const int tid = threadIdx.x;
+  for (int a = 0; a < narrays; ++a) {
+    double s = 0.0;
+    for (int64_t i = tid; i < n; i += 256) s += in[(int64_t)a * n + i];
+    part[tid] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) part[tid] += part[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) totals[a] = part[0];
+    __syncthreads();
+  }
+}
+
+// Emit the sub-items of one thin product job (single term) into a list.
+__device__ void emit_thin(Seg* segs, GemmItem* items, int64_t& cursor, const Seg& s, double* C,
+                          int64_t ldc, int rows, int cols, int max_item) {
+  const int pr = num_parts(rows, max_item), pc = num_parts(cols, max_item);
+  for (int a = 0; a < pr; ++a) {
+    int r0, rl;
+    part_range(rows, pr, a, &r0, &rl);
+    for (int b = 0; b < pc; ++b) {
+      int c0, cl;
+      part_range(cols, pc, b, &c0, &cl);
+      Seg sc = s;
+      sc.kbase = 0;
+      segs[cursor] = sc;
+      GemmItem it;
+      it.C = C;
+      it.ldc = ldc;
+      it.row0 = r0;
+      it.col0 = c0;
+      it.m = rl;
+      it.n = cl;
+      it.seg0 = (int)cursor;
+      it.nseg = 1;
+      it.ktotal = s.k;
+      it.accumulate = 0;
+      it.alpha = 1.0;
+      items[cursor] = it;
+      ++cursor;
+    }
+  }
+}
+
+__device__ inline Seg make_seg(const double* L, int64_t sLi, int64_t sLk, const double* R,
+                               int64_t sRk, int64_t sRj, int k, double scale) {
+  Seg s;
+  s.L = L;
+  s.R = R;
+  s.sLi = sLi;
+  s.sLk = sLk;
+  s.sRk = sRk;
+  s.sRj = sRj;
+  s.k = k;
+  s.kbase = 0;
+  s.scale = scale;
+  return s;
+}
+
+__global__ void k_fill(PlanParams P, FillParams F) {
+  const int npairs = P.nrb * P.ncb;
+  const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pair >= npairs) return;
+  const int fl = F.flags[pair];
+  if (!(fl & kFlagComputed)) return;
+  const bool densify = fl & kFlagDensify;
+  const bool force = fl & kFlagForce;
+  const int I = pair / P.ncb, J = pair % P.ncb;
+  const int m = P.A.roff[I + 1] - P.A.roff[I];
+  const int n = P.B.coff[J + 1] - P.B.coff[J];
+  auto off = [&](int c) { return F.off[(int64_t)c * npairs + pair]; };
+  int64_t po = off(kCntPool);
+  int64_t so = off(kCntSegDense);
+  const int64_t so0 = so;
+  int64_t pi = off(kCntPieces);
+  const int64_t pi0 = pi;
+  int64_t t1 = off(kCntThin1);
+  int64_t t2 = off(kCntThin2);
+  const int64_t cslot = slot_offset(P.A.roff, P.B.coff, F.c_ncols, I, J);
+  double* accb = F.acc + cslot;
+  int kb = 0;
+  int rcat = 0;
+  for (int K = 0; K < P.nkb; ++K) {
+    const int ka = P.A.kind[I * P.nkb + K];
+    if (ka == 0) continue;
+    const int kbk = P.B.kind[K * P.ncb + J];
+    if (kbk == 0) continue;
+    const int k = P.A.coff[K + 1] - P.A.coff[K];
+    const double* a = P.A.arena + slot_offset(P.A.roff, P.A.coff, P.A.ncols, I, K);
+    const double* b = P.B.arena + slot_offset(P.B.roff, P.B.coff, P.B.ncols, K, J);
+    Seg dense_term;
+    Piece pc;
+    pc.pad = 0;
+    pc.scale = P.alpha;
+    if (ka == 1 && kbk == 1) {
+      dense_term = make_seg(a, 1, m, b, 1, k, k, 1.0);
+    } else if (ka == 2 && kbk == 1) {
+      // LD: U_A (B^T V_A)^T; T = B^T V_A is n x rA
+      const int ra = P.A.rank[I * P.nkb + K];
+      const double* Ua = a;
+      const double* Va = a + (int64_t)m * ra;
+      double* T = F.pool + po;
+      po += (int64_t)n * ra;
+      emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(b, k, 1, Va, 1, k, k, 1.0), T, n, n, ra,
+                P.max_item);
+      dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
+      pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
+    } else if (ka == 1 && kbk == 2) {
+      // DL: (A U_B) V_B^T; T = A U_B is m x rB
+      const int rb = P.B.rank[K * P.ncb + J];
+      const double* Ub = b;
+      const double* Vb = b + (int64_t)k * rb;
+      double* T = F.pool + po;
+      po += (int64_t)m * rb;
+      emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(a, 1, m, Ub, 1, k, k, 1.0), T, m, m, rb,
+                P.max_item);
+      dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
+      pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
+    } else {
+      // LL: core Z = V_A^T U_B (rA x rB), absorbed on the side giving the smaller rank (Eq. (4))
+      const int ra = P.A.rank[I * P.nkb + K];
+      const int rb = P.B.rank[K * P.ncb + J];
+      const double* Ua = a;
+      const double* Va = a + (int64_t)m * ra;
+      const double* Ub = b;
+      const double* Vb = b + (int64_t)k * rb;
+      double* Z = F.pool + po;
+      po += (int64_t)ra * rb;
+      emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(Va, k, 1, Ub, 1, k, k, 1.0), Z, ra, ra,
+                rb, P.max_item);
+      double* T = F.pool + po;
+      if (rb < ra) {
+        po += (int64_t)m * rb;   // T = U_A Z (m x rB)
+        emit_thin(F.seg_thin2, F.items_thin2, t2, make_seg(Ua, 1, m, Z, 1, ra, ra, 1.0), T, m, m,
+                  rb, P.max_item);
+        dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
+        pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
+      } else {
+        po += (int64_t)n * ra;   // T = V_B Z^T (n x rA)
+        emit_thin(F.seg_thin2, F.items_thin2, t2, make_seg(Vb, 1, n, Z, ra, 1, rb, 1.0), T, n, n,
+                  ra, P.max_item);
+        dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
+        pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
+      }
+    }
+    if (densify) {
+      dense_term.kbase = kb;
+      kb += dense_term.k;
+      F.seg_dense[so++] = dense_term;
+    } else {
+      rcat += pc.r;
+      F.pieces[pi++] = pc;
+    }
+  }
+  const double tau = P.screen ? P.eps_sp * m * (double)n : P.eps_sp;
+  if (densify) {
+    int64_t gi = off(kCntGemmItems);
+    const int pr = num_parts(m, P.max_item), pcn = num_parts(n, P.max_item);
+    for (int a = 0; a < pr; ++a) {
+      int r0, rl;
+      part_range(m, pr, a, &r0, &rl);
+      for (int b = 0; b < pcn; ++b) {
+        int c0, cl;
+        part_range(n, pcn, b, &c0, &cl);
+        GemmItem it;
+        it.C = accb;
+        it.ldc = m;
+        it.row0 = r0;
+        it.col0 = c0;
+        it.m = rl;
+        it.n = cl;
+        it.seg0 = (int)so0;
+        it.nseg = (int)(so - so0);
+        it.ktotal = kb;
+        it.accumulate = 0;
+        it.alpha = P.alpha;
+        F.items_dense[gi++] = it;
+      }
+    }
+  }
+  RecItem r;
+  r.path = force ? kPathForceDense : (densify ? kPathDense : kPathLowRank);
+  r.m = m;
+  r.n = n;
+  r.piece0 = (int)pi0;
+  r.npieces = (int)(pi - pi0);
+  r.R = rcat;
+  r.D = accb;
+  r.ldd = m;
+  r.tau = tau;
+  r.out = F.c_arena + cslot;
+  r.scratch = F.cnt[(int64_t)kCntScratch * npairs + pair] > 0 ? F.scratch + off(kCntScratch)
+                                                               : nullptr;
+  r.kind_out = F.c_kind + pair;
+  r.rank_out = F.c_rank + pair;
+  r.norm_out = F.c_norm + pair;
+  F.rec[off(kCntComputed)] = r;
+}
+
+hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
+                           hipStream_t s) {
+  const int npairs = P.nrb * P.ncb;
+  if (npairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_symbolic, dim3((npairs + 255) / 256), dim3(256), 0, s, P, cnt, st, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, narrays, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* in, int64_t n, int narrays, double* totals,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, in, n, narrays, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const PlanParams& P, const FillParams& F, hipStream_t s) {
+  const int npairs = P.nrb * P.ncb;
+  if (npairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((npairs + 255) / 256), dim3(256), 0, s, P, F);
+  return hipGetLastError();
+}
+
+}  // namespace clr

@@ -1,0 +1,285 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import parity
+from workloads import (config1, config2, kernel_matrix, points_3d, random_blocks, rng_for,
+                       scaled_config, sizes_weighted)
+
+pytestmark = pytest.mark.gpu
+
+FP64_BOUND = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_1509_00309_amd as clr
+    return clr.Context()
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_from_random(ctx, torch, rc):
+    f0 = {k: torch.from_numpy(v).cuda() for k, v in rc.f0.items()}
+    f1 = {k: torch.from_numpy(v).cuda() for k, v in rc.f1.items()}
+    return ctx.create(rc.row_sizes, rc.col_sizes, rc.kind, rc.rank, f0, f1)
+
+
+def orc_from_random(rc):
+    return orc.from_factors(rc.row_sizes, rc.col_sizes, rc.kind, rc.f0, rc.f1)
+
+
+# ---------------------------------------------------------------------------
+# Boundary: ingest, round trip, norms
+# ---------------------------------------------------------------------------
+
+def test_create_roundtrip_dense_bit_exact(ctx, torch):
+    log("create/to_dense round trip, dense blocks")
+    rc = random_blocks(101, [17, 33, 5], [9, 40, 16, 1], p_zero=0.3, p_dense=1.0)
+    M = gpu_from_random(ctx, torch, rc)
+    got = M.to_dense().cpu().numpy()
+    ref = orc.to_dense(orc_from_random(rc))
+    assert np.array_equal(got, ref)
+    kind, rank, norm = M.meta()
+    assert np.array_equal(kind, rc.kind)
+
+
+def test_create_lowrank_norms(ctx, torch):
+    log("create low-rank blocks, norms")
+    rc = random_blocks(102, [30, 45, 12, 64], [50, 20, 33], p_zero=0.1, p_dense=0.3)
+    M = gpu_from_random(ctx, torch, rc)
+    O = orc_from_random(rc)
+    got = M.to_dense().cpu().numpy()
+    ref = orc.to_dense(O)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+    _k, _r, norm = M.meta()
+    on = O.norms()
+    assert np.max(np.abs(norm - on) / np.maximum(on, 1e-300)) < 1e-13
+
+
+def test_create_rejects_bad_input(ctx, torch):
+    import paper_1509_00309_amd as clr
+    rc = random_blocks(103, [8, 8], [8, 8], p_zero=0.0, p_dense=1.0)
+    bad = rc.f0[(0, 0)].copy()
+    bad[0, 0] = np.nan
+    rc.f0[(0, 0)] = bad
+    with pytest.raises(clr.ClrError) as e:
+        gpu_from_random(ctx, torch, rc)
+    assert e.value.code == 4
+    rc = random_blocks(104, [8, 8], [8, 8], p_zero=0.0, p_dense=1.0)
+    with pytest.raises(clr.ClrError) as e:
+        f0 = {k: torch.from_numpy(v).cuda() for k, v in rc.f0.items()}
+        ctx.create(rc.row_sizes, rc.col_sizes, rc.kind, rc.rank, f0, {}, norms=np.ones((2, 2)))
+    assert e.value.code == 7
+
+
+# ---------------------------------------------------------------------------
+# Compression of an input (drop, diagonal dense, truncated SVD, dense switch)
+# ---------------------------------------------------------------------------
+
+def test_compress_config1(ctx, torch):
+    log("compress config1 (N=512, 1D)")
+    wl = config1()
+    Sd = wl.dense()
+    G = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    E = orc.compress(Sd, wl.sizes, wl.sizes, 0.0, 1e-10)
+    rep = parity.compare(G, O, wl.tol, exact=E)
+    parity.assert_parity(rep, FP64_BOUND, nblocks=64)
+    assert rep.max_norm_rel < 1e-12
+
+
+def test_compress_rectangular_blocks_and_edges(ctx, torch):
+    """Blocks with m < n and m > n (both Jacobi orientations), size-1 blocks, tol = 0."""
+    log("compress rectangular / size-1 blocks")
+    rng = rng_for(105)
+    rows, cols = [1, 37, 96, 150], [80, 1, 23, 130]
+    pts_r = rng.uniform(0, 30, size=(sum(rows), 1))
+    pts_c = rng.uniform(0, 30, size=(sum(cols), 1))
+    from workloads import kernel_block
+    Sd = kernel_block(np.sort(pts_r, axis=0), np.sort(pts_c, axis=0), 0.05)
+    for tol in (1e-6, 1e-10, 0.0):
+        G = ctx.compress(torch.from_numpy(Sd).cuda(), rows, cols, tol, 1e-12)
+        O = orc.compress(Sd, rows, cols, tol, 1e-12)
+        E = orc.compress(Sd, rows, cols, 0.0, 1e-12)
+        rep = parity.compare(G, O, tol, exact=E)
+        parity.assert_parity(rep, FP64_BOUND, nblocks=16)
+
+
+# ---------------------------------------------------------------------------
+# The product
+# ---------------------------------------------------------------------------
+
+def test_gemm_dense_limit_exact(ctx, torch):
+    """tol = 0, eps_sp = 0, all blocks dense: the product equals the dense FP64 product."""
+    log("gemm dense limit")
+    rc_a = random_blocks(106, [48, 160, 17, 129], [100, 33, 160], p_zero=0.0, p_dense=1.0)
+    rc_b = random_blocks(107, [100, 33, 160], [64, 150, 7], p_zero=0.0, p_dense=1.0)
+    A, B = gpu_from_random(ctx, torch, rc_a), gpu_from_random(ctx, torch, rc_b)
+    C = ctx.gemm(A, B, tol=0.0, eps_sp=0.0)
+    got = C.to_dense().cpu().numpy()
+    ref = orc.to_dense(orc_from_random(rc_a)) @ orc.to_dense(orc_from_random(rc_b))
+    assert np.sqrt(np.sum((got - ref) ** 2)) / np.sqrt(np.sum(ref ** 2)) < 1e-14
+
+
+@pytest.mark.parametrize("seed", [110, 111, 112])
+def test_gemm_all_product_kinds_untruncated(ctx, torch, seed):
+    """Mixed zero/dense/low-rank blocks, tol = 0: every product kind and both accumulation paths."""
+    log(f"gemm random kinds untruncated seed={seed}")
+    rows, inner, cols = [40, 96, 23, 150], [64, 30, 128, 77], [50, 96, 33, 140]
+    rc_a = random_blocks(seed, rows, inner, p_zero=0.2, p_dense=0.25)
+    rc_b = random_blocks(seed + 50, inner, cols, p_zero=0.2, p_dense=0.25)
+    A, B = gpu_from_random(ctx, torch, rc_a), gpu_from_random(ctx, torch, rc_b)
+    C, st = ctx.gemm(A, B, tol=0.0, eps_sp=0.0, alpha=0.75, stats=True)
+    Oc = orc.gemm(orc_from_random(rc_a), orc_from_random(rc_b), 0.0, 0.0, alpha=0.75)
+    rep = parity.compare(C, Oc, 0.0)
+    parity.assert_parity(rep, FP64_BOUND, nblocks=16)
+    assert st.n_ld + st.n_dl + st.n_ll > 0
+
+
+@pytest.mark.parametrize("seed", [120, 121])
+def test_gemm_all_product_kinds_truncated(ctx, torch, seed):
+    log(f"gemm random kinds truncated seed={seed}")
+    rows, inner, cols = [40, 96, 23, 150], [64, 30, 128, 77], [50, 96, 33, 140]
+    rc_a = random_blocks(seed, rows, inner, p_zero=0.2, p_dense=0.25, max_rank=6)
+    rc_b = random_blocks(seed + 50, inner, cols, p_zero=0.2, p_dense=0.25, max_rank=6)
+    A, B = gpu_from_random(ctx, torch, rc_a), gpu_from_random(ctx, torch, rc_b)
+    tol = 1e-3
+    C = ctx.gemm(A, B, tol=tol, eps_sp=1e-12)
+    Oa, Ob = orc_from_random(rc_a), orc_from_random(rc_b)
+    Oc = orc.gemm(Oa, Ob, tol, 1e-12)
+    E = orc.gemm(Oa, Ob, 0.0, 1e-12)
+    rep = parity.compare(C, Oc, tol, exact=E)
+    parity.assert_parity(rep, FP64_BOUND, nblocks=16)
+
+
+def test_gemm_screening_modes(ctx, torch):
+    """Norms spread over decades; absolute and per-area screening drop the same blocks as the oracle."""
+    log("gemm screening")
+    rows = [20, 31, 17, 25, 22, 30]
+    rc_a = random_blocks(130, rows, rows, p_zero=0.05, p_dense=0.5, scale_decay=4.0)
+    rc_b = random_blocks(131, rows, rows, p_zero=0.05, p_dense=0.5, scale_decay=4.0)
+    A, B = gpu_from_random(ctx, torch, rc_a), gpu_from_random(ctx, torch, rc_b)
+    Oa, Ob = orc_from_random(rc_a), orc_from_random(rc_b)
+    for screen, eps in (("abs", 1e-3), ("area", 1e-6)):
+        C = ctx.gemm(A, B, tol=0.0, eps_sp=eps, screen=screen)
+        Oc = orc.gemm(Oa, Ob, 0.0, eps, screen)
+        kind_g, _, _ = C.meta()
+        assert np.array_equal(kind_g, Oc.kinds()), screen
+        rep = parity.compare(C, Oc, 0.0)
+        parity.assert_parity(rep, FP64_BOUND, nblocks=36)
+
+
+def test_gemm_everything_screened(ctx, torch):
+    rc = random_blocks(132, [8, 9], [8, 9], p_zero=0.0, p_dense=1.0)
+    A = gpu_from_random(ctx, torch, rc)
+    C = ctx.gemm(A, A, tol=0.0, eps_sp=1e30)
+    kind, _, _ = C.meta()
+    assert np.all(kind == 0)
+    assert np.all(C.to_dense().cpu().numpy() == 0.0)
+
+
+def test_gemm_shape_mismatch(ctx, torch):
+    import paper_1509_00309_amd as clr
+    a = random_blocks(133, [8, 9], [8, 9], p_zero=0.0, p_dense=1.0)
+    b = random_blocks(134, [9, 8], [8, 9], p_zero=0.0, p_dense=1.0)
+    A, B = gpu_from_random(ctx, torch, a), gpu_from_random(ctx, torch, b)
+    with pytest.raises(clr.ClrError) as e:
+        ctx.gemm(A, B, 0.0, 0.0)
+    assert e.value.code == 2
+
+
+def test_gemm_config1(ctx, torch):
+    log("gemm config1 S*S")
+    wl = config1()
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    C = ctx.gemm(S, S, wl.tol, wl.eps_sp)
+    Oc = orc.gemm(O, O, wl.tol, wl.eps_sp)
+    E = orc.gemm(O, O, 0.0, wl.eps_sp)
+    rep = parity.compare(C, Oc, wl.tol, exact=E)
+    parity.assert_parity(rep, FP64_BOUND, nblocks=64)
+
+
+def test_gemm_3d_scaled(ctx, torch):
+    """Overlap-like 3D matrix (the N = 8192 physics) at N = 1536: several dozen blocks, ragged sizes."""
+    log("gemm 3D scaled N=1536")
+    wl = scaled_config("c2", 1536, seed=140)
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    C, st = ctx.gemm(S, S, wl.tol, wl.eps_sp, stats=True)
+    Oc = orc.gemm(O, O, wl.tol, wl.eps_sp)
+    E = orc.gemm(O, O, 0.0, wl.eps_sp)
+    rep = parity.compare(C, Oc, wl.tol, exact=E)
+    nb = len(wl.sizes) ** 2
+    parity.assert_parity(rep, FP64_BOUND, nblocks=nb)
+    log(f"  blocks={nb} computed={st.computed} dense={st.out_dense} lr={st.out_lowrank} "
+        f"err={rep.rel_err:.2e} ambiguous={len(rep.ambiguous)}")
+
+
+def test_axpby_ns_combination(ctx, torch):
+    """T = (-10 X + 3 X^2 + 15 I)/8 (Eq. (9)) with low-rank, dense and identity terms."""
+    log("axpby (NS T)")
+    wl = config1()
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    a = orc.default_alpha(O)
+    X = ctx.gemm(S, S, wl.tol, wl.eps_sp, alpha=a)
+    Q = ctx.gemm(X, X, wl.tol, wl.eps_sp)
+    T = ctx.axpby(-10 / 8, X, 3 / 8, Q, 15 / 8, wl.tol, wl.eps_sp)
+    Ox = orc.gemm(O, O, wl.tol, wl.eps_sp, alpha=a)
+    Oq = orc.gemm(Ox, Ox, wl.tol, wl.eps_sp)
+    Ot = orc.ns_T(Ox, Oq, wl.tol, wl.eps_sp)
+    rep = parity.compare(T, Ot, wl.tol)
+    parity.assert_parity(rep, 1e-11, nblocks=64)
+
+
+def test_sqrt_inv_config1(ctx, torch):
+    log("sqrt_inv config1")
+    wl = config1()
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=wl.extra["conv_tol"])
+    Ow, info = orc.sqrt_inv(O, wl.tol, wl.eps_sp, conv_tol=wl.extra["conv_tol"])
+    assert st.iterations == info.iterations
+    rep = parity.compare(W, Ow, wl.tol)
+    log(f"  iters={st.iterations} internal={st.internal_residual:.2e} "
+        f"explicit={st.explicit_residual:.2e} err={rep.rel_err:.2e}")
+    parity.assert_parity(rep, 1e-11, nblocks=64)
+    assert abs(st.explicit_residual - info.explicit[-1][1]) <= 1e-12
+
+
+def test_mixed_gemm_3d_scaled(ctx, torch):
+    """FP32-MFMA products with FP64 accumulation: within 10 x tol of the FP64 oracle."""
+    log("mixed gemm 3D scaled")
+    wl = scaled_config("c2", 1536, seed=141)
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    Oc = orc.gemm(O, O, wl.tol, wl.eps_sp)
+    for split in (0, 1):
+        C = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision="mixed", split=split)
+        got = C.to_dense().cpu().numpy()
+        ref = orc.to_dense(Oc)
+        err = np.sqrt(np.sum((got - ref) ** 2)) / np.sqrt(np.sum(ref ** 2))
+        log(f"  split={split} err={err:.2e}")
+        assert err <= 10 * wl.tol
