@@ -1,0 +1,234 @@
+"""Benchmark of the CLR block product C = S * S on one MI355X.
+
+Workload (one "step" = one full clr_gemm: screening, block products,
+accumulation, FP64 recompression and C's norm table): the overlap-like matrix
+of N = 8192 points on a jittered 3D lattice (spacing 1.5, jitter 0.3), kernel
+exp(-0.3 r^2) + 0.1 delta, contiguous clusters of U{96..160} points in lattice
+order, compressed at relative tolerance 1e-6 with blocks below 1e-10 dropped;
+products screened at 1e-10 and truncated at 1e-6.  Inputs are resident in HBM
+before timing starts.
+
+Prints one JSON line.  `value` is the FP64-form throughput in algorithmic
+TFLOP/s (DD 2mkn, LD 2 r k n, DL 2 m k r, LL 2 k rA rB + 2 side rA rB, plus
+2 m n r for low-rank terms added into dense accumulators), over the wall time
+of whole steps.  The mixed form (FP32 MFMA, FP64 accumulation) is reported
+alongside with its error against the FP64 oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "CLR-GEMM TFLOP/s & S^-1/2 time: mixed vs FP64 form, 1 GPU, at stated error"
+PEAK_F64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
+PEAK_F32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0       # GB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_form(ctx, S, wl, form, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        C = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision=form)
+        del C
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        C, st = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision=form, stats=True)
+        stats.append(st.as_dict())
+        del C
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    C, st = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision=form, stats=True)
+    return C, wall, stats
+
+
+def summarize(stats, wall, form):
+    flops = stats[-1]["flops_products"]
+    ms_dense = float(np.mean([s["ms_dense"] for s in stats]))
+    ms_thin = float(np.mean([s["ms_thin"] for s in stats]))
+    ms_rec = float(np.mean([s["ms_recompress"] for s in stats]))
+    ms_sym = float(np.mean([s["ms_symbolic"] for s in stats]))
+    f_dense = stats[-1]["flops_dd"] + stats[-1]["flops_densify"]
+    f_thin = stats[-1]["flops_ld"] + stats[-1]["flops_dl"] + stats[-1]["flops_ll"]
+    peak = PEAK_F64_MFMA if form == "fp64" else PEAK_F32_MFMA
+    return {
+        "tflops": flops / wall / 1e12,
+        "ms_per_step": wall * 1e3,
+        "flops_per_step": flops,
+        "phase_ms": {"symbolic": ms_sym, "thin_products": ms_thin, "dense_products": ms_dense,
+                     "recompress": ms_rec},
+        "dense_gemm_tflops": f_dense / (ms_dense * 1e-3) / 1e12 if ms_dense > 0 else None,
+        "thin_gemm_tflops": f_thin / (ms_thin * 1e-3) / 1e12 if ms_thin > 0 else None,
+        "flops_dense_launch": f_dense,
+        "peak": peak,
+        "bytes_compulsory": stats[-1]["bytes_compulsory"],
+        "computed_blocks": stats[-1]["computed"],
+        "out_dense": stats[-1]["out_dense"],
+        "out_lowrank": stats[-1]["out_lowrank"],
+    }
+
+
+def cpu_baseline(wl, Sd, gpu_blocks_fn, budget_s):
+    """Oracle (FP64 NumPy/LAPACK) on a bounded sample of the same product's result blocks."""
+    import oracle as orc
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    t_compress = time.perf_counter() - t0
+    nb = len(wl.sizes)
+    rng = np.random.Generator(np.random.PCG64(99))
+    order = rng.permutation(nb * nb)
+    flops = 0.0
+    done = 0
+    errs = []
+    t0 = time.perf_counter()
+    elapsed = 0.0
+    for idx in order:
+        i, j = int(idx // nb), int(idx % nb)
+        st = orc.GemmStats()
+        blk = orc.gemm_block(O, O, i, j, wl.tol, wl.eps_sp, stats=st)
+        elapsed = time.perf_counter() - t0
+        m, n = wl.sizes[i], wl.sizes[j]
+        flops += st.flops_dd + st.flops_ld + st.flops_dl + st.flops_ll + st.flops_densify
+        done += 1
+        ref = blk.dense() if blk is not None else np.zeros((m, n))
+        got = gpu_blocks_fn(i, j)
+        errs.append((float(np.sum((got - ref) ** 2)), float(np.sum(ref ** 2))))
+        if elapsed >= budget_s:
+            break
+    e_num = math.sqrt(sum(e[0] for e in errs))
+    e_den = math.sqrt(sum(e[1] for e in errs))
+    return {
+        "value": flops / elapsed / 1e12 if elapsed > 0 else None,
+        "unit": "TFLOP/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": f"{done} of {nb * nb} result blocks of the same S*S (random order, seed 99), "
+                  f"{elapsed:.1f} s of oracle time; flops counted as in the GPU figure; "
+                  f"oracle input compression took {t_compress:.1f} s untimed",
+    }, (e_num / e_den if e_den > 0 else 0.0), done
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1509_00309_amd as clr
+    from workloads import config2
+
+    torch.cuda.set_device(0)
+    wl = config2(args.n)
+    log(f"workload {wl.name}: N={wl.n}, {len(wl.sizes)} clusters")
+    Sd = wl.dense()
+    ctx = clr.Context()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    torch.cuda.synchronize()
+    log(f"compressed: stored {S.stored_elements()} of {wl.n * wl.n} elements")
+
+    forms = {}
+    results = {}
+    for form in args.forms.split(","):
+        log(f"timing form {form}: warmup {args.warmup}, steps {args.steps}")
+        C, wall, stats = run_form(ctx, S, wl, form, args.steps, args.warmup)
+        forms[form] = summarize(stats, wall, form)
+        results[form] = C
+        log(f"  {form}: {forms[form]['tflops']:.2f} TFLOP/s, {wall * 1e3:.2f} ms/step, "
+            f"phases {forms[form]['phase_ms']}")
+
+    base = "fp64" if "fp64" in forms else next(iter(forms))
+    fb = forms[base]
+    dense_equiv = 2.0 * wl.n ** 3 / (fb["ms_per_step"] * 1e-3) / 1e12
+
+    cpu = None
+    sample_err = {}
+    if not args.no_cpu_baseline:
+        dense_by_form = {f: results[f].to_dense().cpu().numpy() for f in results}
+        offs = wl.offsets()
+
+        def blocks_fn_for(form):
+            D = dense_by_form[form]
+            return lambda i, j: D[offs[i]:offs[i + 1], offs[j]:offs[j + 1]]
+
+        cpu, err, nsample = cpu_baseline(wl, Sd, blocks_fn_for(base), args.cpu_budget)
+        sample_err[base] = err
+        import oracle as orc  # noqa: F401  (already loaded by cpu_baseline)
+        for f in results:
+            if f == base:
+                continue
+            D = dense_by_form[f]
+            Db = dense_by_form[base]
+            sample_err[f"{f}_vs_{base}"] = float(np.linalg.norm(D - Db) / np.linalg.norm(Db))
+        log(f"cpu baseline: {cpu}")
+
+    roof = {
+        "bound": "mfma",
+        "kernel": "k_ggemm (dense accumulation launch)",
+        "achieved": fb["dense_gemm_tflops"],
+        "peak": fb["peak"],
+        "unit": "TFLOP/s",
+        "frac": (fb["dense_gemm_tflops"] / fb["peak"]) if fb["dense_gemm_tflops"] else None,
+        "traffic": None,
+    }
+    line = {
+        "metric": METRIC,
+        "value": fb["tflops"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fb["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if base == "fp64" else "f32-mfma/f64-acc",
+        "data": "synthetic",
+        "config": {
+            "workload": f"CLR C=S*S, N={wl.n} jittered 3D lattice overlap-like matrix "
+                        f"(exp(-0.3 r^2)+0.1 delta), {len(wl.sizes)} clusters U{{96..160}}, "
+                        f"tol 1e-6, screen 1e-10",
+            "n": wl.n,
+            "clusters": len(wl.sizes),
+            "tol": wl.tol,
+            "eps_sp": wl.eps_sp,
+        },
+        "dense_equivalent_tflops": dense_equiv,
+        "forms": forms,
+        "error_vs_oracle_sampled": sample_err,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

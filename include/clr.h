@@ -91,6 +91,8 @@ typedef struct {
   double flops_products;/* sum of the five above                                      */
   double bytes_compulsory; /* stored elements of A, B and C, 8 bytes each             */
   double ms_symbolic, ms_products, ms_recompress, ms_total; /* device time per phase */
+  double ms_thin;       /* launches of the thin factor products (LD, DL, LL terms)     */
+  double ms_dense;      /* launch of the dense accumulation GEMM (DD + densified terms) */
 } clr_gemm_stats;
 
 typedef struct {

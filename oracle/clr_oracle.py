@@ -298,6 +298,7 @@ class GemmStats:
     flops_ld: float = 0.0
     flops_dl: float = 0.0
     flops_ll: float = 0.0
+    flops_densify: float = 0.0
 
 
 def block_tau(eps_sp: float, m: int, n: int, screen: str) -> float:
@@ -340,6 +341,9 @@ def gemm_block(A: OMatrix, B: OMatrix, i: int, j: int, tol: float, eps_sp: float
                 stats.flops_ll += 2.0 * kk * a.rank * b.rank + 2.0 * side * a.rank * b.rank
     blk = combine(m, n, contribs, tol, tau, square and i == j)
     if stats is not None:
+        rcat = sum(c[1].shape[1] for c in contribs if c[0] == "L")
+        if (square and i == j) or any(c[0] == "D" for c in contribs) or 2 * rcat >= min(m, n):
+            stats.flops_densify += 2.0 * m * n * rcat
         stats.computed += 1
         if blk is None:
             stats.dropped += 1

@@ -41,7 +41,12 @@ struct clr_context {
   DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
       items_thin2, pieces, rec, pool, scratch, acc, status, terms, aux_items, aux_segs,
       aux_dense, ptrs;
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[8] = {};
+  // Stream-ordered cache of freed matrix allocations: a matrix released on the
+  // context stream can back the next matrix of a similar size without a
+  // hipMalloc (all users are ordered on the same stream).
+  std::vector<std::pair<void*, size_t>> cache;
+  size_t cache_bytes = 0;
 };
 
 struct clr_matrix {
@@ -55,6 +60,8 @@ struct clr_matrix {
   int* d_rank = nullptr;
   double* d_norm = nullptr;
   double* arena = nullptr;
+  void* block = nullptr;   // one allocation holding the arena and the metadata
+  size_t block_bytes = 0;
 
   MatView view() const {
     MatView v;
@@ -127,14 +134,51 @@ T* as(DevBuf& b) {
   return static_cast<T*>(b.p);
 }
 
+constexpr size_t kCacheLimit = (size_t)96 << 30;
+
+hipError_t ctx_malloc(clr_context* ctx, size_t bytes, void** p, size_t* got) {
+  int best = -1;
+  for (int i = 0; i < (int)ctx->cache.size(); ++i) {
+    const size_t b = ctx->cache[i].second;
+    if (b >= bytes && b <= bytes + bytes / 4 + 65536 &&
+        (best < 0 || b < ctx->cache[best].second))
+      best = i;
+  }
+  if (best >= 0) {
+    *p = ctx->cache[best].first;
+    *got = ctx->cache[best].second;
+    ctx->cache_bytes -= *got;
+    ctx->cache.erase(ctx->cache.begin() + best);
+    return hipSuccess;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess && !ctx->cache.empty()) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& c : ctx->cache) (void)hipFree(c.first);
+    ctx->cache.clear();
+    ctx->cache_bytes = 0;
+    e = hipMalloc(p, bytes);
+  }
+  *got = bytes;
+  return e;
+}
+
+void ctx_release(clr_context* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  ctx->cache.emplace_back(p, bytes);
+  ctx->cache_bytes += bytes;
+  while (ctx->cache_bytes > kCacheLimit && !ctx->cache.empty()) {
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->cache_bytes -= ctx->cache.front().second;
+    (void)hipFree(ctx->cache.front().first);
+    ctx->cache.erase(ctx->cache.begin());
+  }
+}
+
 void free_matrix(clr_matrix* m) {
   if (!m) return;
-  if (m->d_roff) (void)hipFree(m->d_roff);
-  if (m->d_coff) (void)hipFree(m->d_coff);
-  if (m->d_kind) (void)hipFree(m->d_kind);
-  if (m->d_rank) (void)hipFree(m->d_rank);
-  if (m->d_norm) (void)hipFree(m->d_norm);
-  if (m->arena) (void)hipFree(m->arena);
+  ctx_release(m->ctx, m->block, m->block_bytes);
   delete m;
 }
 
@@ -170,13 +214,23 @@ clr_status alloc_matrix(clr_context* ctx, const std::vector<int>& rs, const std:
     free_matrix(m);
     return fail(ctx, CLR_ERR_CAPACITY, "too many blocks");
   }
-  hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = hipMalloc(&m->d_roff, sizeof(int) * (m->nrb + 1));
-  if (e == hipSuccess) e = hipMalloc(&m->d_coff, sizeof(int) * (m->ncb + 1));
-  if (e == hipSuccess) e = hipMalloc(&m->d_kind, sizeof(int) * nb);
-  if (e == hipSuccess) e = hipMalloc(&m->d_rank, sizeof(int) * nb);
-  if (e == hipSuccess) e = hipMalloc(&m->d_norm, sizeof(double) * nb);
-  if (e == hipSuccess) e = hipMalloc(&m->arena, sizeof(double) * (size_t)m->rows * m->cols);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_arena = up(sizeof(double) * (size_t)m->rows * m->cols);
+  const size_t b_norm = up(sizeof(double) * nb);
+  const size_t b_kind = up(sizeof(int) * nb);
+  const size_t b_roff = up(sizeof(int) * (m->nrb + 1));
+  const size_t b_coff = up(sizeof(int) * (m->ncb + 1));
+  const size_t total = b_arena + b_norm + 2 * b_kind + b_roff + b_coff;
+  hipError_t e = ctx_malloc(ctx, total, &m->block, &m->block_bytes);
+  if (e == hipSuccess) {
+    char* base = static_cast<char*>(m->block);
+    m->arena = reinterpret_cast<double*>(base);
+    m->d_norm = reinterpret_cast<double*>(base + b_arena);
+    m->d_kind = reinterpret_cast<int*>(base + b_arena + b_norm);
+    m->d_rank = reinterpret_cast<int*>(base + b_arena + b_norm + b_kind);
+    m->d_roff = reinterpret_cast<int*>(base + b_arena + b_norm + 2 * b_kind);
+    m->d_coff = reinterpret_cast<int*>(base + b_arena + b_norm + 2 * b_kind + b_roff);
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->d_roff, m->roff.data(), sizeof(int) * (m->nrb + 1),
                        hipMemcpyHostToDevice, ctx->stream);
@@ -331,6 +385,8 @@ extern "C" clr_status clr_context_destroy(clr_context* ctx) {
                     &ctx->acc, &ctx->status, &ctx->terms, &ctx->aux_items, &ctx->aux_segs,
                     &ctx->aux_dense, &ctx->ptrs})
     free_buf(*b);
+  for (auto& c : ctx->cache) (void)hipFree(c.first);
+  ctx->cache.clear();
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   delete ctx;
@@ -674,6 +730,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], stream);
   if (e == hipSuccess) e = run_ggemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream);
   if (e == hipSuccess) e = run_ggemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[6], stream);
   if (e == hipSuccess) e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
   if (e == hipSuccess)
@@ -704,6 +761,8 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
     st->ms_products = elapsed(ctx->ev[1], ctx->ev[2]);
     st->ms_recompress = elapsed(ctx->ev[2], ctx->ev[3]);
     st->ms_total = elapsed(ctx->ev[0], ctx->ev[3]);
+    st->ms_thin = elapsed(ctx->ev[1], ctx->ev[6]);
+    st->ms_dense = elapsed(ctx->ev[6], ctx->ev[2]);
     HostMeta ha, hb, hcm;
     if ((s = fetch_meta(ctx, A, ha)) != CLR_OK) return bail(s);
     if ((s = fetch_meta(ctx, B, hb)) != CLR_OK) return bail(s);

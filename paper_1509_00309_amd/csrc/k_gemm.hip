@@ -19,7 +19,8 @@
 //
 // MFMA operand layout for the 16x16x4 shapes (64 lanes, lane = l):
 //   A(i, k): i = l % 16, k = l / 16;   B(k, j): j = l % 16, k = l / 16;
-//   D(i, j): lane l holds rows i = 4*(l/16) + v (v = 0..3) of column j = l % 16.
+//   D(i, j) is held by lane l = j + 16*g, element v, with
+//     f32: i = 4*g + v        f64: i = g + 4*v   (the f64 shape interleaves rows).
 #include "clr_internal.h"
 
 namespace clr {
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
     __syncthreads();
   }
 
-  // epilogue: D(i, j) lives in lane (j + 16*(i/4)), element i%4
+  // epilogue (output layout per precision, see the header comment)
 #pragma unroll
   for (int a = 0; a < WT; ++a) {
     if (wr + 2 * a >= mt) continue;
@@ -242,7 +243,8 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
       double* col = it.C + (int64_t)(it.col0 + j) * it.ldc + it.row0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = 16 * (wr + 2 * a) + 4 * kr + v;
+        // f64 16x16x4: row (lane/16) + 4v;  f32 16x16x4: row 4*(lane/16) + v
+        const int i = 16 * (wr + 2 * a) + (F32 ? 4 * kr + v : kr + 4 * v);
         if (i < it.m) {
           const double val = it.alpha * acc[a][b][v];
           col[i] = it.accumulate ? col[i] + val : val;
