@@ -18,7 +18,7 @@ constexpr int kMaxItemF64 = 32 * kF64WaveTiles;   // 160: largest output tile ed
 constexpr int kMaxItemF32 = 32 * kF32WaveTiles;   // 128
 constexpr int kRecThreads = 256;      // recompression workgroup (16 groups of 16 lanes)
 constexpr int kRecLdsBytes = 144 * 1024;  // dynamic LDS for the working set (160 KiB minus bookkeeping)
-constexpr int kJacobiMaxSweeps = 40;
+constexpr int kJacobiMaxSweeps = 60;
 
 // ---------------------------------------------------------------------------
 // Work descriptors (device resident, built by the planning kernels)

@@ -23,6 +23,7 @@
 namespace clr {
 
 constexpr int kMaxDim = 512;  // largest block edge handled by the recompression kernel
+constexpr double kNegligible2 = 1e-40;  // squared column norm, relative to the block's
 
 struct RecShared {
   double sigma[kMaxDim];
@@ -73,6 +74,10 @@ __device__ inline void tournament(int round, int k, int P, int& a, int& b) {
 }
 
 // One-sided Jacobi on the q columns (length p, leading dimension ldw) of W.
+// W is scaled to unit Frobenius norm by the callers; columns whose squared
+// norm is below kNegligible2 (1e-20 of the block norm) are left alone: they
+// lie far below any truncation threshold and rotating them only chases
+// rounding noise (in the subnormal range for strongly decaying kernels).
 // Returns false if it did not converge within kJacobiMaxSweeps sweeps.
 __device__ bool jacobi_columns(double* W, int p, int q, int64_t ldw, RecShared& sh) {
   const int tid = threadIdx.x;
@@ -101,7 +106,7 @@ __device__ bool jacobi_columns(double* W, int p, int q, int64_t ldw, RecShared& 
         al = group_sum16(al);
         be = group_sum16(be);
         ga = group_sum16(ga);
-        if (al > 0.0 && be > 0.0 && fabs(ga) > tolj * sqrt(al) * sqrt(be)) {
+        if (al > kNegligible2 && be > kNegligible2 && fabs(ga) > tolj * sqrt(al) * sqrt(be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
           const double c = 1.0 / sqrt(1.0 + t * t);
@@ -273,9 +278,10 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
   const bool trans = m < n;
   const int p = trans ? n : m;
   double* W = it.scratch != nullptr ? it.scratch : lds;
+  const double inv_norm = 1.0 / normc;
   for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
     const int i = (int)(e % m), j = (int)(e / m);
-    const double v = it.D[i + (int64_t)j * it.ldd];
+    const double v = it.D[i + (int64_t)j * it.ldd] * inv_norm;
     if (!trans)
       W[i + (int64_t)j * p] = v;
     else
@@ -285,7 +291,7 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
   if (!jacobi_columns(W, p, q, p, sh)) {
     if (threadIdx.x == 0) atomicOr(status, 1);
   }
-  const int r = rank_from_columns(W, p, q, p, tol, normc, sh);
+  const int r = rank_from_columns(W, p, q, p, tol, 1.0, sh);
   if (r == 0) {
     write_meta(it, 0, 0, 0.0);
     return;
@@ -300,6 +306,7 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
     const double s = sh.sigma[sh.order[k]];
     kept += s * s;
   }
+  kept *= normc * normc;
   // basis side: the orthonormal factor from the Jacobi columns
   double* basis = trans ? it.out + (int64_t)m * r : it.out;  // V' (n x r) or U' (m x r)
   double* other = trans ? it.out : it.out + (int64_t)m * r;  // U' (m x r) or V' (n x r)
@@ -355,23 +362,10 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
   }
   __syncthreads();
   if (tol == 0.0) {
-    // exact norm: ||U V^T||_F^2 = sum_ab (U^T U)_ab (V^T V)_ab; keep the concatenation as is
-    double part = 0.0;
-    for (int e = threadIdx.x; e < R * R; e += kRecThreads) {
-      const int a = e % R, b = e / R;
-      double gu = 0.0, gv = 0.0;
-      for (int i = 0; i < m; ++i) gu += Uc[i + (int64_t)a * m] * Uc[i + (int64_t)b * m];
-      for (int i = 0; i < n; ++i) gv += Vc[i + (int64_t)a * n] * Vc[i + (int64_t)b * n];
-      part += gu * gv;
-    }
-    const double normc = sqrt(fmax(block_sum(part, sh), 0.0));
-    if (normc < it.tau || (normc == 0.0 && it.tau == 0.0)) {
-      write_meta(it, 0, 0, 0.0);
-      return;
-    }
+    // no truncation: the concatenation itself is the result; keep a copy in the
+    // output slot before the QR below overwrites the working factors
     for (int64_t e = threadIdx.x; e < (int64_t)(m + n) * R; e += kRecThreads) it.out[e] = W[e];
-    write_meta(it, 2, R, normc);
-    return;
+    __syncthreads();
   }
   householder_qr(Uc, m, R, tauU, sh);
   householder_qr(Vc, n, R, tauV, sh);
@@ -385,6 +379,8 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
     Mc[e] = s;
     part += s * s;
   }
+  // ||U V^T||_F = ||R_U R_V^T||_F: the QR route keeps its accuracy when the
+  // concatenated terms cancel (a Gram-matrix formula would not)
   const double normc = sqrt(block_sum(part, sh));
   if (!(normc == normc) || normc > DBL_MAX) {
     if (threadIdx.x == 0) atomicOr(status, 2);
@@ -393,10 +389,17 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
     write_meta(it, 0, 0, 0.0);
     return;
   }
+  if (tol == 0.0) {
+    write_meta(it, 2, R, normc);
+    return;
+  }
+  const double inv_norm = 1.0 / normc;
+  for (int e = threadIdx.x; e < R * R; e += kRecThreads) M[e] *= inv_norm;
+  __syncthreads();
   if (!jacobi_columns(M, R, R, R, sh)) {
     if (threadIdx.x == 0) atomicOr(status, 1);
   }
-  const int r = rank_from_columns(M, R, R, R, tol, normc, sh);
+  const int r = rank_from_columns(M, R, R, R, tol, 1.0, sh);
   if (r == 0) {
     write_meta(it, 0, 0, 0.0);
     return;
@@ -406,6 +409,7 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
     const double s = sh.sigma[sh.order[k]];
     kept += s * s;
   }
+  kept *= normc * normc;
   double* Uo = it.out;
   double* Vo = it.out + (int64_t)m * r;
   // U' = Q_U [u_M ; 0]
