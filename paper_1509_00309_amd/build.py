@@ -1,6 +1,6 @@
 """Build the gfx950 shared library of the CLR block-product path.
 
-    python -m paper_1509_00309_amd.build
+    python paper_1509_00309_amd/build.py      (or __graft_entry__.build())
 
 compiles every HIP source under csrc/ with hipcc into
 paper_1509_00309_amd/libclr_mi355x.so (in-tree, so it travels with the source

@@ -45,17 +45,43 @@ struct RecShared {
   double drop2, tau;
 };
 
+// Cross-lane sums.  Within a row of 16 lanes the butterfly uses DPP lane
+// permutations, which stay in the vector ALU (quad_perm [1,0,3,2], quad_perm
+// [2,3,0,1], row_half_mirror, row_mirror): after the four steps every lane of
+// the row holds the row's sum.  Crossing rows (32 and 64 lanes) uses one
+// ds_swizzle (xor 16 inside each half-wave) and one bpermute (xor 32).
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double swizzle_xor16(double v) {
+  const long long b = __double_as_longlong(v);
+  // bit-mode swizzle: and_mask 0x1f, or_mask 0, xor_mask 0x10
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline double group_sum16(double v) {
-  v += __shfl_xor(v, 8, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 1, 16);
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
   return v;
 }
 
+__device__ inline double hw_sum(double v) {
+  v = group_sum16(v);
+  return v + swizzle_xor16(v);
+}
+
 __device__ inline double wave_sum(double v) {
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = hw_sum(v);
+  return v + __shfl_xor(v, 32, 64);
 }
 
 // Deterministic workgroup sum: per-thread partials, tree over LDS.
@@ -222,8 +248,67 @@ __device__ void transpose_r(double* G, int q, int k, int64_t ld) {
 // One-sided Jacobi on the kc columns (length rows, leading dimension ld) of X.
 // X has unit Frobenius norm; columns below kNegligible2 are left alone (they
 // lie far below any truncation threshold and rotating them only chases
-// rounding noise).  Returns false if it did not converge.
-__device__ bool jacobi_columns(double* X, int rows, int kc, int64_t ld, RecShared& sh) {
+// rounding noise).  Each 16-lane group reads its column pair once into
+// registers (rows <= 16 NR), forms the three inner products, and writes the
+// pair back only when it rotates: one LDS pass per pair instead of three.
+// Returns false if it did not converge.
+template <int NR>
+__device__ bool jacobi_columns_t(double* X, int rows, int kc, int64_t ld, RecShared& sh) {
+  const int tid = threadIdx.x;
+  const int g = tid >> 4, gl = tid & 15;
+  const int P = kc + (kc & 1);
+  const double tolj = (double)rows * DBL_EPSILON;
+  for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
+    if (tid == 0) sh.flag = 0;
+    __syncthreads();
+    for (int round = 0; round < P - 1; ++round) {
+      for (int pr = g; pr < P / 2; pr += kGroups) {
+        int a, b;
+        tournament(round, pr, P, a, b);
+        if (a >= kc || b >= kc) continue;
+        double* wa = X + (int64_t)a * ld;
+        double* wb = X + (int64_t)b * ld;
+        double xa[NR], xb[NR];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int t = 0; t < NR; ++t) {
+          const int i = gl + 16 * t;
+          xa[t] = i < rows ? wa[i] : 0.0;
+          xb[t] = i < rows ? wb[i] : 0.0;
+          al += xa[t] * xa[t];
+          be += xb[t] * xb[t];
+          ga += xa[t] * xb[t];
+        }
+        al = group_sum16(al);
+        be = group_sum16(be);
+        ga = group_sum16(ga);
+        if (al > kNegligible2 && be > kNegligible2 && fabs(ga) > tolj * sqrt(al) * sqrt(be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double s = c * t;
+#pragma unroll
+          for (int u = 0; u < NR; ++u) {
+            const int i = gl + 16 * u;
+            if (i < rows) {
+              wa[i] = c * xa[u] - s * xb[u];
+              wb[i] = s * xa[u] + c * xb[u];
+            }
+          }
+          if (gl == 0) sh.flag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int rotated = sh.flag;
+    __syncthreads();
+    if (!rotated) return true;
+  }
+  return false;
+}
+
+// Two-pass variant for columns longer than 160 (blocks beyond the register engine).
+__device__ bool jacobi_columns_long(double* X, int rows, int kc, int64_t ld, RecShared& sh) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
   const int P = kc + (kc & 1);
@@ -268,6 +353,11 @@ __device__ bool jacobi_columns(double* X, int rows, int kc, int64_t ld, RecShare
     if (!rotated) return true;
   }
   return false;
+}
+
+__device__ bool jacobi_columns(double* X, int rows, int kc, int64_t ld, RecShared& sh) {
+  if (rows <= 160) return jacobi_columns_t<10>(X, rows, kc, ld, sh);
+  return jacobi_columns_long(X, rows, kc, ld, sh);
 }
 
 // Singular values (column norms of X, rows x kc), descending order (ties by
@@ -336,6 +426,457 @@ __device__ int svd_rank(double* G, int p, int q, int64_t ld, double tol, int* st
     if (threadIdx.x == 0) atomicOr(status, 1);
   }
   return rank_from_columns(G, q, kc, ld, tol, sh);
+}
+
+
+// ---------------------------------------------------------------------------
+// Register-resident engine for blocks with both edges <= 160.
+//
+// The working matrix G (p x q, p >= q, unit Frobenius norm) is spread over the
+// 1024 threads as a 32 x 32 grid: thread (tr, tc) = (tid % 32, tid / 32) holds
+// G(i, j) for i = tr + 32 a, j = tc + 32 b (a, b < 5).  A column lives in one
+// half-wave (32 consecutive lanes), so column reductions are shuffles; rows are
+// reduced through LDS.  This keeps 160 x 160 FP64 blocks (200 KiB) on chip,
+// beyond the LDS capacity, and makes each Householder step a handful of
+// workgroup barriers.
+//
+//  * Householder bidiagonalisation G = U_B B V_B^T (left reflector on column k,
+//    right reflector on row k) gives the bidiagonal d, e of B.
+//  * Singular values of B: multisection on the Golub-Kahan tridiagonal (zero
+//    diagonal, off-diagonals d_0, e_0, d_1, ...) with Sturm counts; its
+//    eigenvalues are +-sigma_i.  Values are resolved to 1e-17 of ||G||_F.
+//  * Pivoted Householder QR (column norms recomputed exactly each step) for the
+//    truncated blocks, whose singular vectors then come from Jacobi on R^T.
+// ---------------------------------------------------------------------------
+constexpr int kRegEdge = 160;
+constexpr int kRE = kRegEdge / 32;
+
+struct RegLds {
+  double part[32][kRegEdge + 1];
+  double vcol[kRegEdge];
+  double vrow[kRegEdge];
+  double wrow[kRegEdge];
+  double colA[kRegEdge];
+  double colB[kRegEdge];
+  double d[kRegEdge];
+  double e[kRegEdge];
+  double b2[2 * kRegEdge];
+  double lo[kRegEdge];
+  double hi[kRegEdge];
+  int cnt[kRecThreads];
+  double tauL, tauR;
+};
+static_assert(sizeof(RegLds) <= (size_t)kRecLdsBytes, "register engine bookkeeping exceeds LDS");
+
+typedef double RegTile[kRE][kRE];
+
+
+__device__ void reg_load(RegTile& a, const double* D, int64_t ldd, bool trans, double scale,
+                         int p, int q) {
+  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5;
+#pragma unroll
+  for (int ir = 0; ir < kRE; ++ir)
+#pragma unroll
+    for (int jc = 0; jc < kRE; ++jc) {
+      const int i = tr + 32 * ir, j = tc + 32 * jc;
+      double v = 0.0;
+      if (i < p && j < q) v = (trans ? D[j + (int64_t)i * ldd] : D[i + (int64_t)j * ldd]) * scale;
+      a[ir][jc] = v;
+    }
+}
+
+// Left reflector annihilating G(k+1:p, k); applied to columns > k.  d[k] = beta.
+__device__ void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
+  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5;
+  const int kj = k >> 5;
+  if (tc == (k & 31)) {
+    double s2 = 0.0, x0p = 0.0;
+#pragma unroll
+    for (int ir = 0; ir < kRE; ++ir)
+#pragma unroll
+      for (int jc = 0; jc < kRE; ++jc)
+        if (jc == kj) {
+          const int i = tr + 32 * ir;
+          const double x = a[ir][jc];
+          if (i > k && i < p) s2 += x * x;
+          if (i == k) x0p = x;
+        }
+    s2 = hw_sum(s2);
+    const double x0 = hw_sum(x0p);
+    double t = 0.0, beta = x0, scal = 0.0;
+    if (s2 > 0.0) {
+      beta = -copysign(sqrt(x0 * x0 + s2), x0);
+      t = (beta - x0) / beta;
+      scal = 1.0 / (x0 - beta);
+    }
+#pragma unroll
+    for (int ir = 0; ir < kRE; ++ir)
+#pragma unroll
+      for (int jc = 0; jc < kRE; ++jc)
+        if (jc == kj) {
+          const int i = tr + 32 * ir;
+          if (i >= k && i < p) {
+            L.vcol[i] = (i == k) ? 1.0 : a[ir][jc] * scal;
+            a[ir][jc] = (i == k) ? beta : 0.0;
+          }
+        }
+    if (tr == 0) {
+      L.tauL = t;
+      L.d[k] = beta;
+    }
+  }
+  __syncthreads();
+  const double t = L.tauL;
+  if (t == 0.0) return;
+  double vr[kRE];
+#pragma unroll
+  for (int ir = 0; ir < kRE; ++ir) {
+    const int i = tr + 32 * ir;
+    vr[ir] = (i >= k && i < p) ? L.vcol[i] : 0.0;
+  }
+#pragma unroll
+  for (int jc = 0; jc < kRE; ++jc) {
+    const int j = tc + 32 * jc;
+    if (j > k && j < q) {
+      double w = 0.0;
+#pragma unroll
+      for (int ir = 0; ir < kRE; ++ir) w += vr[ir] * a[ir][jc];
+      w = hw_sum(w);
+#pragma unroll
+      for (int ir = 0; ir < kRE; ++ir) a[ir][jc] -= t * vr[ir] * w;
+    }
+  }
+}
+
+// Right reflector annihilating G(k, k+2:q); applied to rows > k.  e[k] = beta.
+__device__ void reg_right(RegTile& a, int k, int p, int q, RegLds& L) {
+  const int tid = threadIdx.x;
+  const int tr = tid & 31, tc = tid >> 5;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int ki = k >> 5;
+  if (tr == (k & 31)) {
+#pragma unroll
+    for (int ir = 0; ir < kRE; ++ir)
+#pragma unroll
+      for (int jc = 0; jc < kRE; ++jc)
+        if (ir == ki) {
+          const int j = tc + 32 * jc;
+          if (j > k && j < q) L.vrow[j] = a[ir][jc];
+        }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double s2 = 0.0;
+    for (int j = k + 2 + lane; j < q; j += 64) s2 += L.vrow[j] * L.vrow[j];
+    s2 = wave_sum(s2);
+    const double x0 = L.vrow[k + 1];
+    double t = 0.0, beta = x0, scal = 0.0;
+    if (s2 > 0.0) {
+      beta = -copysign(sqrt(x0 * x0 + s2), x0);
+      t = (beta - x0) / beta;
+      scal = 1.0 / (x0 - beta);
+    }
+    for (int j = k + 2 + lane; j < q; j += 64) L.vrow[j] *= scal;
+    if (lane == 0) {
+      L.vrow[k + 1] = 1.0;
+      L.tauR = t;
+      L.e[k] = beta;
+    }
+  }
+  __syncthreads();
+  const double t = L.tauR;
+  if (tr == (k & 31)) {
+#pragma unroll
+    for (int ir = 0; ir < kRE; ++ir)
+#pragma unroll
+      for (int jc = 0; jc < kRE; ++jc)
+        if (ir == ki) {
+          const int j = tc + 32 * jc;
+          if (j == k + 1) a[ir][jc] = L.e[k];
+          if (j > k + 1 && j < q) a[ir][jc] = 0.0;
+        }
+  }
+  if (t == 0.0) return;
+  double vc[kRE];
+#pragma unroll
+  for (int jc = 0; jc < kRE; ++jc) {
+    const int j = tc + 32 * jc;
+    vc[jc] = (j > k && j < q) ? L.vrow[j] : 0.0;
+  }
+#pragma unroll
+  for (int ir = 0; ir < kRE; ++ir) {
+    const int i = tr + 32 * ir;
+    if (i > k && i < p) {
+      double w = 0.0;
+#pragma unroll
+      for (int jc = 0; jc < kRE; ++jc) w += a[ir][jc] * vc[jc];
+      L.part[tc][i] = w;
+    }
+  }
+  __syncthreads();
+  if (tid > k && tid < p) {
+    double s = 0.0;
+    for (int c = 0; c < 32; ++c) s += L.part[c][tid];
+    L.wrow[tid] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ir = 0; ir < kRE; ++ir) {
+    const int i = tr + 32 * ir;
+    if (i > k && i < p) {
+      const double w = t * L.wrow[i];
+#pragma unroll
+      for (int jc = 0; jc < kRE; ++jc) a[ir][jc] -= w * vc[jc];
+    }
+  }
+}
+
+// #{sigma_i > x} for the bidiagonal whose Golub-Kahan off-diagonals squared
+// (d_0^2, e_0^2, d_1^2, ..., d_{q-1}^2) are in b2; x > 0.  Sylvester inertia of
+// T - x I through its leading principal minors d_k = -x d_{k-1} - b_{k-1}^2 d_{k-2}
+// (no divisions): every sign change is a negative pivot, i.e. an eigenvalue
+// below x.  The pair (d_{k-1}, d_k) is rescaled by a power of two every 8 steps
+// (growth per step is at most the golden ratio for a unit-norm matrix); an exact
+// zero minor is replaced by a tiny value of the opposite sign, which counts it
+// as a negative pivot as the pivot-floor rule of the quotient form does.
+__device__ int sturm_greater(const double* b2, int q, double x) {
+  double dm = 1.0, d = -x;
+  int neg = 1;
+  if (d == 0.0) d = -1e-300;
+  const int n = 2 * q - 1;
+  for (int s = 0; s < n; ++s) {
+    double dn = fma(-x, d, -b2[s] * dm);
+    if (dn == 0.0) dn = -d * 0x1p-80;
+    neg += (dn < 0.0) != (d < 0.0);
+    dm = d;
+    d = dn;
+    if ((s & 7) == 7) {
+      int e;
+      (void)frexp(d, &e);
+      d = ldexp(d, -e);
+      dm = ldexp(dm, -e);
+    }
+  }
+  return 2 * q - neg;
+}
+
+// Singular values of G (unit norm) into sh.sigma[0..q) in descending order, and
+// the kept rank for tol (tails accumulated from the smallest value upward).
+__device__ int reg_singular_values(RegTile& a, int p, int q, double tol, RegLds& L,
+                                   RecShared& sh) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < q; ++k) {
+    reg_left(a, k, p, q, L);
+    if (k < q - 1) reg_right(a, k, p, q, L);
+    __syncthreads();
+  }
+  if (tid < 2 * q - 1) {
+    const double b = (tid & 1) ? L.e[tid >> 1] : L.d[tid >> 1];
+    L.b2[tid] = b * b;
+  }
+  if (tid < q) {
+    L.lo[tid] = 0.0;
+    L.hi[tid] = 1.0 + 1e-12;
+  }
+  __syncthreads();
+  const int ts = kRecThreads / q > 0 ? kRecThreads / q : 1;
+  const int i = tid / ts, sub = tid % ts;
+  int rounds = 0;
+  for (double w = 1.0; w > 1e-17; w /= (double)(ts + 1)) ++rounds;
+  if (tid == 0) sh.flag = 0;
+  __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    if (i < q) {
+      const double lo = L.lo[i], hi = L.hi[i];
+      const double x = lo + (double)(sub + 1) * (hi - lo) / (double)(ts + 1);
+      L.cnt[tid] = sturm_greater(L.b2, q, x);
+    }
+    __syncthreads();
+    if (i < q && sub == 0) {
+      const double lo = L.lo[i], hi = L.hi[i];
+      double nlo = lo, nhi = hi;
+      for (int s2 = 0; s2 < ts; ++s2) {
+        const double x = lo + (double)(s2 + 1) * (hi - lo) / (double)(ts + 1);
+        if (L.cnt[i * ts + s2] > i) {
+          nlo = x;
+        } else {
+          nhi = x;
+          break;
+        }
+      }
+      L.lo[i] = nlo;
+      L.hi[i] = nhi;
+    }
+    __syncthreads();
+    // Stop once the brackets settle the decision: with T(k) = sum_{j>=k} s_j^2
+    // bracketed by the squared bounds, the kept rank lies in [r_lo, r_hi]; it is
+    // settled when r_lo == r_hi, or when even r_lo keeps the block dense.
+    if (tid == 0) {
+      const double bound = tol * tol;
+      double tlo = 0.0, thi = 0.0;
+      int r_lo = q, r_hi = q;
+      bool lo_set = false, hi_set = false;
+      // scan k from q down to 0: T(k) grows as k decreases
+      if (bound >= 0.0) {
+        r_lo = 0;
+        r_hi = 0;
+        for (int k = q; k >= 0; --k) {
+          if (k < q) {
+            tlo += L.lo[k] * L.lo[k];
+            thi += L.hi[k] * L.hi[k];
+          }
+          if (!lo_set && tlo > bound) {
+            r_lo = k + 1;
+            lo_set = true;
+          }
+          if (!hi_set && thi > bound) {
+            r_hi = k + 1;
+            hi_set = true;
+          }
+        }
+      }
+      if (r_lo == r_hi || 2 * r_lo > q) {
+        sh.flag = 1;
+        sh.rank = r_lo;
+      }
+    }
+    __syncthreads();
+    if (sh.flag) break;
+  }
+  const bool settled = sh.flag != 0;
+  if (tid < q) {
+    sh.sigma[tid] = 0.5 * (L.lo[tid] + L.hi[tid]);
+    sh.order[tid] = tid;
+  }
+  __syncthreads();
+  if (tid == 0 && !settled) {
+    double acc = 0.0;
+    sh.tails[q] = 0.0;
+    for (int k = q - 1; k >= 0; --k) {
+      acc += sh.sigma[k] * sh.sigma[k];
+      sh.tails[k] = acc;
+    }
+    int r = q;
+    for (int k = 0; k <= q; ++k)
+      if (sqrt(sh.tails[k]) <= tol) {
+        r = k;
+        break;
+      }
+    sh.rank = r;
+  }
+  __syncthreads();
+  return sh.rank;
+}
+
+// Pivoted Householder QR of the register-resident G; stops at the numerical
+// rank (trailing squared norm <= kRankFloor2).  Returns the number of steps k;
+// R(0:k, :) stays in the registers, sh.perm holds the permutation.
+__device__ int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh) {
+  const int tid = threadIdx.x;
+  const int tr = tid & 31, tc = tid >> 5;
+  const int lane = tid & 63, wave = tid >> 6;
+  auto column_norms = [&](int from_row, int from_col) {
+#pragma unroll
+    for (int jc = 0; jc < kRE; ++jc) {
+      const int j = tc + 32 * jc;
+      if (j >= from_col && j < q) {
+        double s = 0.0;
+#pragma unroll
+        for (int ir = 0; ir < kRE; ++ir) {
+          const int i = tr + 32 * ir;
+          if (i >= from_row && i < p) s += a[ir][jc] * a[ir][jc];
+        }
+        s = hw_sum(s);
+        if (tr == 0) sh.sigma[j] = s;
+      }
+    }
+  };
+  column_norms(0, 0);
+  if (tid < q) sh.perm[tid] = tid;
+  __syncthreads();
+  int k = 0;
+  for (; k < q; ++k) {
+    if (wave == 0) {
+      double best = -1.0, tot = 0.0;
+      int bj = q;
+      for (int j = k + lane; j < q; j += 64) {
+        const double v = sh.sigma[j];
+        tot += v;
+        if (v > best || (v == best && j < bj)) {
+          best = v;
+          bj = j;
+        }
+      }
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && oj < bj)) {
+          best = ob;
+          bj = oj;
+        }
+      }
+      tot = wave_sum(tot);
+      if (lane == 0) {
+        sh.piv = bj;
+        sh.drop2 = tot;
+      }
+    }
+    __syncthreads();
+    if (sh.drop2 <= kRankFloor2) break;
+    const int piv = sh.piv;
+    if (piv != k) {
+      const int kj = k >> 5, pj = piv >> 5;
+#pragma unroll
+      for (int ir = 0; ir < kRE; ++ir)
+#pragma unroll
+        for (int jc = 0; jc < kRE; ++jc) {
+          const int i = tr + 32 * ir;
+          if (i < p) {
+            if (tc == (k & 31) && jc == kj) L.colA[i] = a[ir][jc];
+            if (tc == (piv & 31) && jc == pj) L.colB[i] = a[ir][jc];
+          }
+        }
+      __syncthreads();
+#pragma unroll
+      for (int ir = 0; ir < kRE; ++ir)
+#pragma unroll
+        for (int jc = 0; jc < kRE; ++jc) {
+          const int i = tr + 32 * ir;
+          if (i < p) {
+            if (tc == (k & 31) && jc == kj) a[ir][jc] = L.colB[i];
+            if (tc == (piv & 31) && jc == pj) a[ir][jc] = L.colA[i];
+          }
+        }
+      if (tid == 0) {
+        const double t = sh.sigma[k];
+        sh.sigma[k] = sh.sigma[piv];
+        sh.sigma[piv] = t;
+        const int pi = sh.perm[k];
+        sh.perm[k] = sh.perm[piv];
+        sh.perm[piv] = pi;
+      }
+      __syncthreads();
+    }
+    reg_left(a, k, p, q, L);
+    column_norms(k + 1, k + 1);
+    __syncthreads();
+  }
+  if (k == q && tid == 0) sh.drop2 = 0.0;
+  __syncthreads();
+  return k;
+}
+
+// X (q x kq, leading dimension ldx) = R(0:kq, 0:q)^T from the registers.
+__device__ void reg_store_rt(const RegTile& a, int q, int kq, double* X, int64_t ldx) {
+  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5;
+#pragma unroll
+  for (int ir = 0; ir < kRE; ++ir)
+#pragma unroll
+    for (int jc = 0; jc < kRE; ++jc) {
+      const int i = tr + 32 * ir, j = tc + 32 * jc;
+      if (i < kq && j < q) X[j + (int64_t)i * ldx] = (j >= i) ? a[ir][jc] : 0.0;
+    }
+  __syncthreads();
 }
 
 __device__ void write_meta(const RecItem& it, int kind, int rank, double norm) {
@@ -415,6 +956,7 @@ __device__ void apply_q(const double* W, int rows, int kk, const double* tau, do
   __syncthreads();
 }
 
+template <bool REG>
 __device__ void dense_path(const RecItem& it, double tol, double* lds, int* status,
                            RecShared& sh) {
   const int m = it.m, n = it.n;
@@ -440,26 +982,62 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
   // working matrix G = D / ||D|| (m >= n) or D^T / ||D|| (m < n): p x q, p >= q
   const bool trans = m < n;
   const int p = trans ? n : m;
-  double* G = it.scratch != nullptr ? it.scratch : lds;
   const double inv_norm = 1.0 / normc;
-  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    const double v = it.D[i + (int64_t)j * it.ldd] * inv_norm;
-    if (!trans)
-      G[i + (int64_t)j * p] = v;
-    else
-      G[j + (int64_t)i * p] = v;
-  }
-  __syncthreads();
-  const int r = svd_rank(G, p, q, p, tol, status, sh);
-  if (r == 0) {
-    write_meta(it, 0, 0, 0.0);
-    return;
-  }
-  if (2 * r > q) {
-    copy_dense_out(it);
-    write_meta(it, 1, q, normc);
-    return;
+  double* G = it.scratch != nullptr ? it.scratch : lds;
+  double* X = G;           // Jacobi columns (q rows x kc)
+  int64_t ldx = p;
+  int r = 0;
+  if constexpr (REG) {
+    RegLds& L = *reinterpret_cast<RegLds*>(lds);
+    RegTile a;
+    reg_load(a, it.D, it.ldd, trans, inv_norm, p, q);
+    r = reg_singular_values(a, p, q, tol, L, sh);
+    if (r == 0) {
+      write_meta(it, 0, 0, 0.0);
+      return;
+    }
+    if (2 * r > q) {
+      copy_dense_out(it);
+      write_meta(it, 1, q, normc);
+      return;
+    }
+    // truncated: singular vectors from pivoted QR + Jacobi on R^T
+    reg_load(a, it.D, it.ldd, trans, inv_norm, p, q);
+    const int kc = reg_pivoted_qr(a, p, q, L, sh);
+    // odd leading dimension: the columns of one wave start in different LDS banks
+    ldx = q + 1 - (q & 1);
+    X = ((int64_t)ldx * kc * 8 <= (int64_t)kRecLdsBytes) ? lds : it.scratch;
+    if (X == nullptr) {   // cannot happen with the planner's scratch rule; fail safe
+      if (threadIdx.x == 0) atomicOr(status, 4);
+      return;
+    }
+    reg_store_rt(a, q, kc, X, ldx);
+    if (!jacobi_columns(X, q, kc, ldx, sh)) {
+      if (threadIdx.x == 0) atomicOr(status, 1);
+    }
+    // sorted Jacobi columns give the vectors; the rank decided from the bidiagonal stands
+    (void)rank_from_columns(X, q, kc, ldx, tol, sh);
+    if (r > kc) r = kc;
+  } else {
+    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
+      const int i = (int)(e % m), j = (int)(e / m);
+      const double v = it.D[i + (int64_t)j * it.ldd] * inv_norm;
+      if (!trans)
+        G[i + (int64_t)j * p] = v;
+      else
+        G[j + (int64_t)i * p] = v;
+    }
+    __syncthreads();
+    r = svd_rank(G, p, q, p, tol, status, sh);
+    if (r == 0) {
+      write_meta(it, 0, 0, 0.0);
+      return;
+    }
+    if (2 * r > q) {
+      copy_dense_out(it);
+      write_meta(it, 1, q, normc);
+      return;
+    }
   }
   double kept = 0.0;
   for (int c = 0; c < r; ++c) {
@@ -474,7 +1052,7 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
   double* Vo = it.out + (int64_t)m * r;
   double* basis = trans ? Uo : Vo;
   double* other = trans ? Vo : Uo;
-  write_basis(G, p, q, r, basis, q, sh);
+  write_basis(X, ldx, q, r, basis, q, sh);
   const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
   for (int o = g; o < p * r; o += kGroups) {
     const int i = o % p, c = o / p;
@@ -584,6 +1162,25 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
   write_meta(it, 2, r, sqrt(kept));
 }
 
+// Dense-path blocks whose edges are both <= 160 (and tol > 0) go to the
+// register-resident kernel; everything else to the general one.
+__device__ inline bool register_item(const RecItem& it, double tol) {
+  return it.path == kPathDense && tol != 0.0 && it.m <= kRegEdge && it.n <= kRegEdge;
+}
+
+__device__ inline bool item_guard(const RecItem& it, double tol, int* status) {
+  // the planner gives scratch to every block whose working set exceeds the LDS budget
+  if (it.scratch == nullptr && rec_scratch_doubles(it.path, it.m, it.n, it.R, tol) > 0) {
+    if (threadIdx.x == 0) atomicOr(status, 4);
+    return false;
+  }
+  if (it.m > kMaxDim || it.n > kMaxDim) {
+    if (threadIdx.x == 0) atomicOr(status, 8);
+    return false;
+  }
+  return true;
+}
+
 __global__ __launch_bounds__(kRecThreads) void k_recompress(const RecItem* __restrict__ items,
                                                             const Piece* __restrict__ pieces,
                                                             int nitems, double tol, int* status) {
@@ -593,20 +1190,26 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress(const RecItem* __res
   const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (item >= nitems) return;
   const RecItem it = items[item];
-  if (it.path == kPathSkip) return;
-  // the planner gives scratch to every block whose working set exceeds the LDS budget
-  if (it.scratch == nullptr && rec_scratch_doubles(it.path, it.m, it.n, it.R, tol) > 0) {
-    if (threadIdx.x == 0) atomicOr(status, 4);
-    return;
-  }
-  if (it.m > kMaxDim || it.n > kMaxDim) {
-    if (threadIdx.x == 0) atomicOr(status, 8);
-    return;
-  }
+  if (it.path == kPathSkip || register_item(it, tol)) return;
+  if (!item_guard(it, tol, status)) return;
   if (it.path == kPathLowRank)
     lowrank_path(it, pieces, tol, lds, status, sh);
   else
-    dense_path(it, tol, lds, status, sh);
+    dense_path<false>(it, tol, lds, status, sh);
+}
+
+__global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* __restrict__ items,
+                                                                int nitems, double tol,
+                                                                int* status) {
+  extern __shared__ double lds[];
+  __shared__ RecShared sh;
+  const int per = gridDim.x / 8;
+  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (item >= nitems) return;
+  const RecItem it = items[item];
+  if (!register_item(it, tol)) return;
+  if (!item_guard(it, tol, status)) return;
+  dense_path<true>(it, tol, lds, status, sh);
 }
 
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
@@ -616,10 +1219,17 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_recompress,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kRecLdsBytes);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_recompress_reg,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kRecLdsBytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const int grid = ((nitems + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_recompress_reg, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items,
+                     nitems, tol, status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_recompress, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items, pieces,
                      nitems, tol, status);
   return hipGetLastError();
