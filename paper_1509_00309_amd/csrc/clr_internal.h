@@ -16,8 +16,8 @@ constexpr int kF64WaveTiles = 5;      // 16x16 MFMA tiles per wave and dimension
 constexpr int kF32WaveTiles = 4;      // same for the FP32-MFMA (mixed) form
 constexpr int kMaxItemF64 = 32 * kF64WaveTiles;   // 160: largest output tile edge per item
 constexpr int kMaxItemF32 = 32 * kF32WaveTiles;   // 128
-constexpr int kRecThreads = 1024;     // recompression workgroup (64 groups of 16 lanes)
-constexpr int kRecLdsBytes = 136 * 1024;  // dynamic LDS for the working set (160 KiB minus bookkeeping)
+constexpr int kRecThreads = 512;      // recompression workgroup (32 groups of 16 lanes)
+constexpr int kRecLdsBytes = 140 * 1024;  // dynamic LDS for the working set (160 KiB minus bookkeeping)
 constexpr int kJacobiMaxSweeps = 60;
 
 // ---------------------------------------------------------------------------

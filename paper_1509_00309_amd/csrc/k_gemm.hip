@@ -27,6 +27,15 @@ namespace clr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+// Operand pointers are read back from LDS as generic pointers; loads through
+// them would compile to flat instructions, which count against the LDS wait
+// counter too and so serialise the MFMA operand reads behind the next slab's
+// global prefetch.  Casting to the global address space keeps them on the
+// vector-memory counter only.
+typedef const double __attribute__((address_space(1))) gdouble;
+typedef double __attribute__((address_space(1))) gdouble_mut;
+__device__ inline gdouble* as_global(const double* p) { return (gdouble*)p; }
+__device__ inline gdouble_mut* as_global_mut(double* p) { return (gdouble_mut*)p; }
 
 template <int WT, bool F32>
 struct GemmLds {
@@ -130,12 +139,12 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
       if (arow) { t = e / TM; i = e % TM; } else { t = e % kSlabK; i = e / kSlabK; }
       const double* p = sh.lp[buf][t];
       double v = 0.0;
-      if (p != nullptr && i < it.m) v = p[(int64_t)i * sh.sli[buf][t]] * sh.scale[buf][t];
+      if (p != nullptr && i < it.m) v = as_global(p)[(int64_t)i * sh.sli[buf][t]] * sh.scale[buf][t];
       ra[u] = v;
       if (brow) { t = e / TM; i = e % TM; } else { t = e % kSlabK; i = e / kSlabK; }
       const double* q = sh.rp[buf][t];
       double w = 0.0;
-      if (q != nullptr && i < it.n) w = q[(int64_t)i * sh.srj[buf][t]];
+      if (q != nullptr && i < it.n) w = as_global(q)[(int64_t)i * sh.srj[buf][t]];
       rb[u] = w;
     }
   };
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
       if (wc + 2 * b >= nt) continue;
       const int j = 16 * (wc + 2 * b) + lc;
       if (j >= it.n) continue;
-      double* col = it.C + (int64_t)(it.col0 + j) * it.ldc + it.row0;
+      gdouble_mut* col = as_global_mut(it.C) + (int64_t)(it.col0 + j) * it.ldc + it.row0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         // f64 16x16x4: row (lane/16) + 4v;  f32 16x16x4: row 4*(lane/16) + v

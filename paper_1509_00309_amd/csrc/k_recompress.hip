@@ -30,10 +30,21 @@
 
 namespace clr {
 
+// Working matrices live either in LDS or in global scratch.  The routines that
+// touch them are templates over the pointer's address space so that each use
+// compiles to ds_* or global_* instructions; generic (flat) accesses would
+// couple the LDS and vector-memory wait counters and defeat latency hiding.
+typedef double __attribute__((address_space(3))) ldbl;
+typedef double __attribute__((address_space(1))) gdbl;
+typedef const double __attribute__((address_space(1))) cgdbl;
+#define CLR_INLINE __device__ __attribute__((always_inline)) inline
+
 constexpr int kMaxDim = 512;            // largest block edge of the recompression kernel
 constexpr double kNegligible2 = 1e-40;  // Jacobi ignores columns below this squared (relative) norm
 constexpr double kRankFloor2 = 1e-38;   // pivoted QR stops at this squared (relative) trailing norm
 constexpr int kGroups = kRecThreads / 16;
+
+
 
 struct RecShared {
   double sigma[kMaxDim];      // pivoted QR: partial column norms^2; then singular values
@@ -85,7 +96,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Deterministic workgroup sum: per-thread partials, tree over LDS.
-__device__ double block_sum(double v, RecShared& sh) {
+CLR_INLINE double block_sum(double v, RecShared& sh) {
   const int tid = threadIdx.x;
   sh.red[tid] = v;
   __syncthreads();
@@ -114,12 +125,13 @@ __device__ inline void tournament(int round, int k, int P, int& a, int& b) {
 // kRankFloor2; returns the number of steps k.  sh.perm holds the column
 // permutation (G P = Q R), sh.drop2 the squared norm of what was left out.
 // Only R is kept: the reflector tails below the diagonal are dead afterwards.
-__device__ int pivoted_qr(double* G, int p, int q, int64_t ld, RecShared& sh) {
+template <typename PT>
+CLR_INLINE int pivoted_qr(PT* G, int p, int q, int64_t ld, RecShared& sh) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = tid >> 4, gl = tid & 15;
   for (int j = g; j < q; j += kGroups) {
-    const double* c = G + (int64_t)j * ld;
+    const PT* c = G + (int64_t)j * ld;
     double s = 0.0;
     for (int i = gl; i < p; i += 16) s += c[i] * c[i];
     s = group_sum16(s);
@@ -162,8 +174,8 @@ __device__ int pivoted_qr(double* G, int p, int q, int64_t ld, RecShared& sh) {
     if (sh.drop2 <= kRankFloor2) break;
     const int piv = sh.piv;
     if (piv != k) {
-      double* a = G + (int64_t)k * ld;
-      double* b = G + (int64_t)piv * ld;
+      PT* a = G + (int64_t)k * ld;
+      PT* b = G + (int64_t)piv * ld;
       for (int i = tid; i < p; i += kRecThreads) {
         const double t = a[i];
         a[i] = b[i];
@@ -176,7 +188,7 @@ __device__ int pivoted_qr(double* G, int p, int q, int64_t ld, RecShared& sh) {
       }
     }
     __syncthreads();
-    double* col = G + (int64_t)k * ld;
+    PT* col = G + (int64_t)k * ld;
     if (wave == 0) {
       double s2 = 0.0;
       for (int i = k + 1 + lane; i < p; i += 64) s2 += col[i] * col[i];
@@ -197,7 +209,7 @@ __device__ int pivoted_qr(double* G, int p, int q, int64_t ld, RecShared& sh) {
     __syncthreads();
     const double t = sh.tau;
     for (int j = k + 1 + g; j < q; j += kGroups) {
-      double* cj = G + (int64_t)j * ld;
+      PT* cj = G + (int64_t)j * ld;
       double rkj = cj[k];
       if (t != 0.0) {
         double w = 0.0;
@@ -232,7 +244,8 @@ __device__ int pivoted_qr(double* G, int p, int q, int64_t ld, RecShared& sh) {
 }
 
 // Overwrite the leading q x k part of G with R(0:k, 0:q)^T (lower triangular).
-__device__ void transpose_r(double* G, int q, int k, int64_t ld) {
+template <typename PT>
+CLR_INLINE void transpose_r(PT* G, int q, int k, int64_t ld) {
   // pairs (i, j), i < j < q, i < k: X(j, i) = R(i, j); X(i, j) = R(j, i) = 0 when j < k
   const int64_t total = (int64_t)k * q;
   for (int64_t e = threadIdx.x; e < total; e += kRecThreads) {
@@ -252,8 +265,8 @@ __device__ void transpose_r(double* G, int q, int k, int64_t ld) {
 // registers (rows <= 16 NR), forms the three inner products, and writes the
 // pair back only when it rotates: one LDS pass per pair instead of three.
 // Returns false if it did not converge.
-template <int NR>
-__device__ bool jacobi_columns_t(double* X, int rows, int kc, int64_t ld, RecShared& sh) {
+template <int NR, typename PT>
+CLR_INLINE bool jacobi_columns_t(PT* X, int rows, int kc, int64_t ld, RecShared& sh) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
   const int P = kc + (kc & 1);
@@ -266,8 +279,8 @@ __device__ bool jacobi_columns_t(double* X, int rows, int kc, int64_t ld, RecSha
         int a, b;
         tournament(round, pr, P, a, b);
         if (a >= kc || b >= kc) continue;
-        double* wa = X + (int64_t)a * ld;
-        double* wb = X + (int64_t)b * ld;
+        PT* wa = X + (int64_t)a * ld;
+        PT* wb = X + (int64_t)b * ld;
         double xa[NR], xb[NR];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -308,7 +321,8 @@ __device__ bool jacobi_columns_t(double* X, int rows, int kc, int64_t ld, RecSha
 }
 
 // Two-pass variant for columns longer than 160 (blocks beyond the register engine).
-__device__ bool jacobi_columns_long(double* X, int rows, int kc, int64_t ld, RecShared& sh) {
+template <typename PT>
+CLR_INLINE bool jacobi_columns_long(PT* X, int rows, int kc, int64_t ld, RecShared& sh) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
   const int P = kc + (kc & 1);
@@ -321,8 +335,8 @@ __device__ bool jacobi_columns_long(double* X, int rows, int kc, int64_t ld, Rec
         int a, b;
         tournament(round, pr, P, a, b);
         if (a >= kc || b >= kc) continue;
-        double* wa = X + (int64_t)a * ld;
-        double* wb = X + (int64_t)b * ld;
+        PT* wa = X + (int64_t)a * ld;
+        PT* wb = X + (int64_t)b * ld;
         double al = 0.0, be = 0.0, ga = 0.0;
         for (int i = gl; i < rows; i += 16) {
           const double x = wa[i], y = wb[i];
@@ -355,7 +369,8 @@ __device__ bool jacobi_columns_long(double* X, int rows, int kc, int64_t ld, Rec
   return false;
 }
 
-__device__ bool jacobi_columns(double* X, int rows, int kc, int64_t ld, RecShared& sh) {
+template <typename PT>
+CLR_INLINE bool jacobi_columns(PT* X, int rows, int kc, int64_t ld, RecShared& sh) {
   if (rows <= 160) return jacobi_columns_t<10>(X, rows, kc, ld, sh);
   return jacobi_columns_long(X, rows, kc, ld, sh);
 }
@@ -363,12 +378,13 @@ __device__ bool jacobi_columns(double* X, int rows, int kc, int64_t ld, RecShare
 // Singular values (column norms of X, rows x kc), descending order (ties by
 // index), tails including the part left out by the pivoted QR, and the kept
 // rank for relative tolerance tol (the working matrix has unit norm).
-__device__ int rank_from_columns(const double* X, int rows, int kc, int64_t ld, double tol,
+template <typename PT>
+CLR_INLINE int rank_from_columns(const PT* X, int rows, int kc, int64_t ld, double tol,
                                  RecShared& sh) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
   for (int j = g; j < kc; j += kGroups) {
-    const double* w = X + (int64_t)j * ld;
+    const PT* w = X + (int64_t)j * ld;
     double s = 0.0;
     for (int i = gl; i < rows; i += 16) s += w[i] * w[i];
     s = group_sum16(s);
@@ -406,8 +422,9 @@ __device__ int rank_from_columns(const double* X, int rows, int kc, int64_t ld, 
 }
 
 // Top-r right singular basis of G (q-long vectors): basis(:, c) = P x_{order[c]} / sigma.
-__device__ void write_basis(const double* X, int64_t ld, int q, int r, double* basis,
-                            int64_t ldb, RecShared& sh) {
+template <typename PT, typename BT>
+CLR_INLINE void write_basis(const PT* X, int64_t ld, int q, int r, BT* basis, int64_t ldb,
+                            RecShared& sh) {
   for (int64_t e = threadIdx.x; e < (int64_t)q * r; e += kRecThreads) {
     const int j = (int)(e % q), c = (int)(e / q);
     const int src = sh.order[c];
@@ -418,7 +435,8 @@ __device__ void write_basis(const double* X, int64_t ld, int q, int r, double* b
 
 // Pivoted QR + Jacobi on G (p x q, p >= q, unit norm): returns the kept rank;
 // the Jacobi columns stay in G's leading q x k part for write_basis.
-__device__ int svd_rank(double* G, int p, int q, int64_t ld, double tol, int* status,
+template <typename PT>
+CLR_INLINE int svd_rank(PT* G, int p, int q, int64_t ld, double tol, int* status,
                         RecShared& sh) {
   const int kc = pivoted_qr(G, p, q, ld, sh);
   transpose_r(G, q, kc, ld);
@@ -433,9 +451,9 @@ __device__ int svd_rank(double* G, int p, int q, int64_t ld, double tol, int* st
 // Register-resident engine for blocks with both edges <= 160.
 //
 // The working matrix G (p x q, p >= q, unit Frobenius norm) is spread over the
-// 1024 threads as a 32 x 32 grid: thread (tr, tc) = (tid % 32, tid / 32) holds
-// G(i, j) for i = tr + 32 a, j = tc + 32 b (a, b < 5).  A column lives in one
-// half-wave (32 consecutive lanes), so column reductions are shuffles; rows are
+// 512 threads as a 16 x 32 grid: thread (tr, tc) = (tid % 16, tid / 16) holds
+// G(i, j) for i = tr + 16 a, j = tc + 32 b (a < 10, b < 5).  A column lives in
+// one 16-lane DPP row, so column reductions stay in the vector ALU; rows are
 // reduced through LDS.  This keeps 160 x 160 FP64 blocks (200 KiB) on chip,
 // beyond the LDS capacity, and makes each Householder step a handful of
 // workgroup barriers.
@@ -449,7 +467,9 @@ __device__ int svd_rank(double* G, int p, int q, int64_t ld, double tol, int* st
 //    truncated blocks, whose singular vectors then come from Jacobi on R^T.
 // ---------------------------------------------------------------------------
 constexpr int kRegEdge = 160;
-constexpr int kRE = kRegEdge / 32;
+constexpr int kRowCls = kRecThreads / 32;      // 16 row classes (one DPP row per column class)
+constexpr int kRR = kRegEdge / kRowCls;        // 10 rows per thread
+constexpr int kRC = kRegEdge / 32;             // 5 columns per thread
 
 struct RegLds {
   double part[32][kRegEdge + 1];
@@ -468,41 +488,42 @@ struct RegLds {
 };
 static_assert(sizeof(RegLds) <= (size_t)kRecLdsBytes, "register engine bookkeeping exceeds LDS");
 
-typedef double RegTile[kRE][kRE];
+typedef double RegTile[kRR][kRC];
 
 
-__device__ void reg_load(RegTile& a, const double* D, int64_t ldd, bool trans, double scale,
+CLR_INLINE void reg_load(RegTile& a, const double* D, int64_t ldd, bool trans, double scale,
                          int p, int q) {
-  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5;
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
 #pragma unroll
-  for (int ir = 0; ir < kRE; ++ir)
+  for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
-    for (int jc = 0; jc < kRE; ++jc) {
-      const int i = tr + 32 * ir, j = tc + 32 * jc;
+    for (int jc = 0; jc < kRC; ++jc) {
+      const int i = tr + 16 * ir, j = tc + 32 * jc;
       double v = 0.0;
-      if (i < p && j < q) v = (trans ? D[j + (int64_t)i * ldd] : D[i + (int64_t)j * ldd]) * scale;
+      const cgdbl* gD = (const cgdbl*)D;
+      if (i < p && j < q) v = (trans ? gD[j + (int64_t)i * ldd] : gD[i + (int64_t)j * ldd]) * scale;
       a[ir][jc] = v;
     }
 }
 
 // Left reflector annihilating G(k+1:p, k); applied to columns > k.  d[k] = beta.
-__device__ void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
-  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5;
+CLR_INLINE void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
   const int kj = k >> 5;
   if (tc == (k & 31)) {
     double s2 = 0.0, x0p = 0.0;
 #pragma unroll
-    for (int ir = 0; ir < kRE; ++ir)
+    for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
-      for (int jc = 0; jc < kRE; ++jc)
+      for (int jc = 0; jc < kRC; ++jc)
         if (jc == kj) {
-          const int i = tr + 32 * ir;
+          const int i = tr + 16 * ir;
           const double x = a[ir][jc];
           if (i > k && i < p) s2 += x * x;
           if (i == k) x0p = x;
         }
-    s2 = hw_sum(s2);
-    const double x0 = hw_sum(x0p);
+    s2 = group_sum16(s2);
+    const double x0 = group_sum16(x0p);
     double t = 0.0, beta = x0, scal = 0.0;
     if (s2 > 0.0) {
       beta = -copysign(sqrt(x0 * x0 + s2), x0);
@@ -510,11 +531,11 @@ __device__ void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
       scal = 1.0 / (x0 - beta);
     }
 #pragma unroll
-    for (int ir = 0; ir < kRE; ++ir)
+    for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
-      for (int jc = 0; jc < kRE; ++jc)
+      for (int jc = 0; jc < kRC; ++jc)
         if (jc == kj) {
-          const int i = tr + 32 * ir;
+          const int i = tr + 16 * ir;
           if (i >= k && i < p) {
             L.vcol[i] = (i == k) ? 1.0 : a[ir][jc] * scal;
             a[ir][jc] = (i == k) ? beta : 0.0;
@@ -528,37 +549,37 @@ __device__ void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
   __syncthreads();
   const double t = L.tauL;
   if (t == 0.0) return;
-  double vr[kRE];
+  double vr[kRR];
 #pragma unroll
-  for (int ir = 0; ir < kRE; ++ir) {
-    const int i = tr + 32 * ir;
+  for (int ir = 0; ir < kRR; ++ir) {
+    const int i = tr + 16 * ir;
     vr[ir] = (i >= k && i < p) ? L.vcol[i] : 0.0;
   }
 #pragma unroll
-  for (int jc = 0; jc < kRE; ++jc) {
+  for (int jc = 0; jc < kRC; ++jc) {
     const int j = tc + 32 * jc;
     if (j > k && j < q) {
       double w = 0.0;
 #pragma unroll
-      for (int ir = 0; ir < kRE; ++ir) w += vr[ir] * a[ir][jc];
-      w = hw_sum(w);
+      for (int ir = 0; ir < kRR; ++ir) w += vr[ir] * a[ir][jc];
+      w = group_sum16(w);
 #pragma unroll
-      for (int ir = 0; ir < kRE; ++ir) a[ir][jc] -= t * vr[ir] * w;
+      for (int ir = 0; ir < kRR; ++ir) a[ir][jc] -= t * vr[ir] * w;
     }
   }
 }
 
 // Right reflector annihilating G(k, k+2:q); applied to rows > k.  e[k] = beta.
-__device__ void reg_right(RegTile& a, int k, int p, int q, RegLds& L) {
+CLR_INLINE void reg_right(RegTile& a, int k, int p, int q, RegLds& L) {
   const int tid = threadIdx.x;
-  const int tr = tid & 31, tc = tid >> 5;
+  const int tr = tid & 15, tc = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
-  const int ki = k >> 5;
-  if (tr == (k & 31)) {
+  const int ki = k >> 4;
+  if (tr == (k & 15)) {
 #pragma unroll
-    for (int ir = 0; ir < kRE; ++ir)
+    for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
-      for (int jc = 0; jc < kRE; ++jc)
+      for (int jc = 0; jc < kRC; ++jc)
         if (ir == ki) {
           const int j = tc + 32 * jc;
           if (j > k && j < q) L.vrow[j] = a[ir][jc];
@@ -585,11 +606,11 @@ __device__ void reg_right(RegTile& a, int k, int p, int q, RegLds& L) {
   }
   __syncthreads();
   const double t = L.tauR;
-  if (tr == (k & 31)) {
+  if (tr == (k & 15)) {
 #pragma unroll
-    for (int ir = 0; ir < kRE; ++ir)
+    for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
-      for (int jc = 0; jc < kRE; ++jc)
+      for (int jc = 0; jc < kRC; ++jc)
         if (ir == ki) {
           const int j = tc + 32 * jc;
           if (j == k + 1) a[ir][jc] = L.e[k];
@@ -597,19 +618,19 @@ __device__ void reg_right(RegTile& a, int k, int p, int q, RegLds& L) {
         }
   }
   if (t == 0.0) return;
-  double vc[kRE];
+  double vc[kRC];
 #pragma unroll
-  for (int jc = 0; jc < kRE; ++jc) {
+  for (int jc = 0; jc < kRC; ++jc) {
     const int j = tc + 32 * jc;
     vc[jc] = (j > k && j < q) ? L.vrow[j] : 0.0;
   }
 #pragma unroll
-  for (int ir = 0; ir < kRE; ++ir) {
-    const int i = tr + 32 * ir;
+  for (int ir = 0; ir < kRR; ++ir) {
+    const int i = tr + 16 * ir;
     if (i > k && i < p) {
       double w = 0.0;
 #pragma unroll
-      for (int jc = 0; jc < kRE; ++jc) w += a[ir][jc] * vc[jc];
+      for (int jc = 0; jc < kRC; ++jc) w += a[ir][jc] * vc[jc];
       L.part[tc][i] = w;
     }
   }
@@ -621,12 +642,12 @@ __device__ void reg_right(RegTile& a, int k, int p, int q, RegLds& L) {
   }
   __syncthreads();
 #pragma unroll
-  for (int ir = 0; ir < kRE; ++ir) {
-    const int i = tr + 32 * ir;
+  for (int ir = 0; ir < kRR; ++ir) {
+    const int i = tr + 16 * ir;
     if (i > k && i < p) {
       const double w = t * L.wrow[i];
 #pragma unroll
-      for (int jc = 0; jc < kRE; ++jc) a[ir][jc] -= w * vc[jc];
+      for (int jc = 0; jc < kRC; ++jc) a[ir][jc] -= w * vc[jc];
     }
   }
 }
@@ -639,7 +660,7 @@ __device__ void reg_right(RegTile& a, int k, int p, int q, RegLds& L) {
 // (growth per step is at most the golden ratio for a unit-norm matrix); an exact
 // zero minor is replaced by a tiny value of the opposite sign, which counts it
 // as a negative pivot as the pivot-floor rule of the quotient form does.
-__device__ int sturm_greater(const double* b2, int q, double x) {
+CLR_INLINE int sturm_greater(const double* b2, int q, double x) {
   double dm = 1.0, d = -x;
   int neg = 1;
   if (d == 0.0) d = -1e-300;
@@ -662,7 +683,7 @@ __device__ int sturm_greater(const double* b2, int q, double x) {
 
 // Singular values of G (unit norm) into sh.sigma[0..q) in descending order, and
 // the kept rank for tol (tails accumulated from the smallest value upward).
-__device__ int reg_singular_values(RegTile& a, int p, int q, double tol, RegLds& L,
+CLR_INLINE int reg_singular_values(RegTile& a, int p, int q, double tol, RegLds& L,
                                    RecShared& sh) {
   const int tid = threadIdx.x;
   for (int k = 0; k < q; ++k) {
@@ -771,22 +792,22 @@ __device__ int reg_singular_values(RegTile& a, int p, int q, double tol, RegLds&
 // Pivoted Householder QR of the register-resident G; stops at the numerical
 // rank (trailing squared norm <= kRankFloor2).  Returns the number of steps k;
 // R(0:k, :) stays in the registers, sh.perm holds the permutation.
-__device__ int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh) {
+CLR_INLINE int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh) {
   const int tid = threadIdx.x;
-  const int tr = tid & 31, tc = tid >> 5;
+  const int tr = tid & 15, tc = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
   auto column_norms = [&](int from_row, int from_col) {
 #pragma unroll
-    for (int jc = 0; jc < kRE; ++jc) {
+    for (int jc = 0; jc < kRC; ++jc) {
       const int j = tc + 32 * jc;
       if (j >= from_col && j < q) {
         double s = 0.0;
 #pragma unroll
-        for (int ir = 0; ir < kRE; ++ir) {
-          const int i = tr + 32 * ir;
+        for (int ir = 0; ir < kRR; ++ir) {
+          const int i = tr + 16 * ir;
           if (i >= from_row && i < p) s += a[ir][jc] * a[ir][jc];
         }
-        s = hw_sum(s);
+        s = group_sum16(s);
         if (tr == 0) sh.sigma[j] = s;
       }
     }
@@ -827,10 +848,10 @@ __device__ int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh
     if (piv != k) {
       const int kj = k >> 5, pj = piv >> 5;
 #pragma unroll
-      for (int ir = 0; ir < kRE; ++ir)
+      for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
-        for (int jc = 0; jc < kRE; ++jc) {
-          const int i = tr + 32 * ir;
+        for (int jc = 0; jc < kRC; ++jc) {
+          const int i = tr + 16 * ir;
           if (i < p) {
             if (tc == (k & 31) && jc == kj) L.colA[i] = a[ir][jc];
             if (tc == (piv & 31) && jc == pj) L.colB[i] = a[ir][jc];
@@ -838,10 +859,10 @@ __device__ int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh
         }
       __syncthreads();
 #pragma unroll
-      for (int ir = 0; ir < kRE; ++ir)
+      for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
-        for (int jc = 0; jc < kRE; ++jc) {
-          const int i = tr + 32 * ir;
+        for (int jc = 0; jc < kRC; ++jc) {
+          const int i = tr + 16 * ir;
           if (i < p) {
             if (tc == (k & 31) && jc == kj) a[ir][jc] = L.colB[i];
             if (tc == (piv & 31) && jc == pj) a[ir][jc] = L.colA[i];
@@ -867,19 +888,20 @@ __device__ int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh
 }
 
 // X (q x kq, leading dimension ldx) = R(0:kq, 0:q)^T from the registers.
-__device__ void reg_store_rt(const RegTile& a, int q, int kq, double* X, int64_t ldx) {
-  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5;
+template <typename PT>
+CLR_INLINE void reg_store_rt(const RegTile& a, int q, int kq, PT* X, int64_t ldx) {
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
 #pragma unroll
-  for (int ir = 0; ir < kRE; ++ir)
+  for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
-    for (int jc = 0; jc < kRE; ++jc) {
-      const int i = tr + 32 * ir, j = tc + 32 * jc;
+    for (int jc = 0; jc < kRC; ++jc) {
+      const int i = tr + 16 * ir, j = tc + 32 * jc;
       if (i < kq && j < q) X[j + (int64_t)i * ldx] = (j >= i) ? a[ir][jc] : 0.0;
     }
   __syncthreads();
 }
 
-__device__ void write_meta(const RecItem& it, int kind, int rank, double norm) {
+CLR_INLINE void write_meta(const RecItem& it, int kind, int rank, double norm) {
   if (threadIdx.x == 0) {
     *it.kind_out = kind;
     *it.rank_out = rank;
@@ -887,23 +909,26 @@ __device__ void write_meta(const RecItem& it, int kind, int rank, double norm) {
   }
 }
 
-__device__ void copy_dense_out(const RecItem& it) {
+CLR_INLINE void copy_dense_out(const RecItem& it) {
   const int64_t total = (int64_t)it.m * it.n;
+  const cgdbl* D = (const cgdbl*)it.D;
+  gdbl* out = (gdbl*)it.out;
   for (int64_t e = threadIdx.x; e < total; e += kRecThreads) {
     const int i = (int)(e % it.m), j = (int)(e / it.m);
-    it.out[e] = it.D[i + (int64_t)j * it.ldd];
+    out[e] = D[i + (int64_t)j * it.ldd];
   }
 }
 
 // Householder QR of W (rows x cols, ld rows) in place: R in the upper
 // triangle, reflector tails below the diagonal, tau[k] alongside
 // (H_k = I - tau_k v_k v_k^T, v_k = (1, W[k+1:, k])).
-__device__ void householder_qr(double* W, int rows, int cols, double* tau) {
+template <typename PT>
+CLR_INLINE void householder_qr(PT* W, int rows, int cols, PT* tau) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = tid >> 4, gl = tid & 15;
   for (int k = 0; k < cols && k < rows; ++k) {
-    double* col = W + (int64_t)k * rows;
+    PT* col = W + (int64_t)k * rows;
     if (wave == 0) {
       double s2 = 0.0;
       for (int i = k + 1 + lane; i < rows; i += 64) s2 += col[i] * col[i];
@@ -925,7 +950,7 @@ __device__ void householder_qr(double* W, int rows, int cols, double* tau) {
     const double t = tau[k];
     if (t != 0.0) {
       for (int j = k + 1 + g; j < cols; j += kGroups) {
-        double* cj = W + (int64_t)j * rows;
+        PT* cj = W + (int64_t)j * rows;
         double w = 0.0;
         for (int i = k + gl; i < rows; i += 16) w += (i == k ? 1.0 : col[i]) * cj[i];
         w = group_sum16(w);
@@ -937,16 +962,17 @@ __device__ void householder_qr(double* W, int rows, int cols, double* tau) {
 }
 
 // X (rows x ncol, ld ldx, global) <- Q X with Q = H_0 H_1 ... H_{kk-1} from householder_qr.
-__device__ void apply_q(const double* W, int rows, int kk, const double* tau, double* X,
-                        int64_t ldx, int ncol) {
+template <typename PT>
+CLR_INLINE void apply_q(const PT* W, int rows, int kk, const PT* tau, gdbl* X, int64_t ldx,
+                        int ncol) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
   for (int c = g; c < ncol; c += kGroups) {
-    double* x = X + (int64_t)c * ldx;
+    gdbl* x = X + (int64_t)c * ldx;
     for (int k = kk - 1; k >= 0; --k) {
       const double t = tau[k];
       if (t == 0.0) continue;
-      const double* v = W + (int64_t)k * rows;
+      const PT* v = W + (int64_t)k * rows;
       double w = 0.0;
       for (int i = k + gl; i < rows; i += 16) w += (i == k ? 1.0 : v[i]) * x[i];
       w = group_sum16(w);
@@ -956,13 +982,96 @@ __device__ void apply_q(const double* W, int rows, int kk, const double* tau, do
   __syncthreads();
 }
 
+// Factored output of a truncated dense-path block from the sorted Jacobi
+// columns X (q rows, leading dimension ldx) of the working matrix G:
+//   basis = right singular vectors of G (q-long), other = G_orig * basis;
+//   m >= n: V' = basis (n x r), U' = D basis (m x r)
+//   m <  n: U' = basis (m x r), V' = D^T basis (n x r)
+template <typename PT>
+CLR_INLINE void dense_truncated_out(const RecItem& it, const PT* X, int64_t ldx, int p, int q,
+                                    bool trans, int r, double normc, RecShared& sh) {
+  const int m = it.m, n = it.n;
+  double kept = 0.0;
+  for (int c = 0; c < r; ++c) {
+    const double s = sh.sigma[sh.order[c]];
+    kept += s * s;
+  }
+  kept *= normc * normc;
+  gdbl* Uo = (gdbl*)it.out;
+  gdbl* Vo = Uo + (int64_t)m * r;
+  gdbl* basis = trans ? Uo : Vo;
+  gdbl* other = trans ? Vo : Uo;
+  write_basis(X, ldx, q, r, basis, q, sh);
+  const cgdbl* D = (const cgdbl*)it.D;
+  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
+  for (int o = g; o < p * r; o += kGroups) {
+    const int i = o % p, c = o / p;
+    const gdbl* b = basis + (int64_t)c * q;
+    double s = 0.0;
+    if (!trans) {
+      for (int j = gl; j < n; j += 16) s += D[i + (int64_t)j * it.ldd] * b[j];
+    } else {
+      const cgdbl* dcol = D + (int64_t)i * it.ldd;   // column i of D (m long)
+      for (int j = gl; j < m; j += 16) s += dcol[j] * b[j];
+    }
+    s = group_sum16(s);
+    if (gl == 0) other[i + (int64_t)c * p] = s;
+  }
+  write_meta(it, 2, r, sqrt(kept));
+}
+
+// Jacobi on the register engine's R^T, then the factored output.
+template <typename PT>
+CLR_INLINE void reg_truncated(const RecItem& it, const RegTile& a, PT* X, int64_t ldx, int p,
+                              int q, int kc, bool trans, int r, double tol, double normc,
+                              int* status, RecShared& sh) {
+  reg_store_rt(a, q, kc, X, ldx);
+  if (!jacobi_columns(X, q, kc, ldx, sh)) {
+    if (threadIdx.x == 0) atomicOr(status, 1);
+  }
+  // sorted Jacobi columns give the vectors; the rank decided from the bidiagonal stands
+  (void)rank_from_columns(X, q, kc, ldx, tol, sh);
+  dense_truncated_out(it, X, ldx, p, q, trans, r < kc ? r : kc, normc, sh);
+}
+
+// Dense path on a working matrix in LDS or global scratch (blocks beyond the
+// register engine): pivoted QR + Jacobi decide the rank and give the vectors.
+template <typename PT>
+CLR_INLINE void dense_general(const RecItem& it, PT* G, int p, int q, bool trans, double tol,
+                              double normc, int* status, RecShared& sh) {
+  const int m = it.m, n = it.n;
+  const double inv_norm = 1.0 / normc;
+  const cgdbl* D = (const cgdbl*)it.D;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    const double v = D[i + (int64_t)j * it.ldd] * inv_norm;
+    if (!trans)
+      G[i + (int64_t)j * p] = v;
+    else
+      G[j + (int64_t)i * p] = v;
+  }
+  __syncthreads();
+  const int r = svd_rank(G, p, q, p, tol, status, sh);
+  if (r == 0) {
+    write_meta(it, 0, 0, 0.0);
+    return;
+  }
+  if (2 * r > q) {
+    copy_dense_out(it);
+    write_meta(it, 1, q, normc);
+    return;
+  }
+  dense_truncated_out(it, G, p, p, q, trans, r, normc, sh);
+}
+
 template <bool REG>
-__device__ void dense_path(const RecItem& it, double tol, double* lds, int* status,
+CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* status,
                            RecShared& sh) {
   const int m = it.m, n = it.n;
+  const cgdbl* D = (const cgdbl*)it.D;
   double part = 0.0;
   for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
-    const double v = it.D[(e % m) + (e / m) * it.ldd];
+    const double v = D[(e % m) + (e / m) * it.ldd];
     part += v * v;
   }
   const double normc = sqrt(block_sum(part, sh));
@@ -982,16 +1091,11 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
   // working matrix G = D / ||D|| (m >= n) or D^T / ||D|| (m < n): p x q, p >= q
   const bool trans = m < n;
   const int p = trans ? n : m;
-  const double inv_norm = 1.0 / normc;
-  double* G = it.scratch != nullptr ? it.scratch : lds;
-  double* X = G;           // Jacobi columns (q rows x kc)
-  int64_t ldx = p;
-  int r = 0;
   if constexpr (REG) {
     RegLds& L = *reinterpret_cast<RegLds*>(lds);
     RegTile a;
-    reg_load(a, it.D, it.ldd, trans, inv_norm, p, q);
-    r = reg_singular_values(a, p, q, tol, L, sh);
+    reg_load(a, it.D, it.ldd, trans, 1.0 / normc, p, q);
+    const int r = reg_singular_values(a, p, q, tol, L, sh);
     if (r == 0) {
       write_meta(it, 0, 0, 0.0);
       return;
@@ -1002,95 +1106,49 @@ __device__ void dense_path(const RecItem& it, double tol, double* lds, int* stat
       return;
     }
     // truncated: singular vectors from pivoted QR + Jacobi on R^T
-    reg_load(a, it.D, it.ldd, trans, inv_norm, p, q);
+    reg_load(a, it.D, it.ldd, trans, 1.0 / normc, p, q);
     const int kc = reg_pivoted_qr(a, p, q, L, sh);
     // odd leading dimension: the columns of one wave start in different LDS banks
-    ldx = q + 1 - (q & 1);
-    X = ((int64_t)ldx * kc * 8 <= (int64_t)kRecLdsBytes) ? lds : it.scratch;
-    if (X == nullptr) {   // cannot happen with the planner's scratch rule; fail safe
-      if (threadIdx.x == 0) atomicOr(status, 4);
-      return;
+    const int64_t ldx = q + 1 - (q & 1);
+    if (ldx * kc * 8 <= (int64_t)kRecLdsBytes) {
+      reg_truncated(it, a, (ldbl*)lds, ldx, p, q, kc, trans, r, tol, normc, status, sh);
+    } else if (it.scratch != nullptr) {
+      reg_truncated(it, a, (gdbl*)it.scratch, ldx, p, q, kc, trans, r, tol, normc, status, sh);
+    } else if (threadIdx.x == 0) {
+      atomicOr(status, 4);   // cannot happen with the planner's scratch rule
     }
-    reg_store_rt(a, q, kc, X, ldx);
-    if (!jacobi_columns(X, q, kc, ldx, sh)) {
-      if (threadIdx.x == 0) atomicOr(status, 1);
-    }
-    // sorted Jacobi columns give the vectors; the rank decided from the bidiagonal stands
-    (void)rank_from_columns(X, q, kc, ldx, tol, sh);
-    if (r > kc) r = kc;
   } else {
-    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
-      const int i = (int)(e % m), j = (int)(e / m);
-      const double v = it.D[i + (int64_t)j * it.ldd] * inv_norm;
-      if (!trans)
-        G[i + (int64_t)j * p] = v;
-      else
-        G[j + (int64_t)i * p] = v;
-    }
-    __syncthreads();
-    r = svd_rank(G, p, q, p, tol, status, sh);
-    if (r == 0) {
-      write_meta(it, 0, 0, 0.0);
-      return;
-    }
-    if (2 * r > q) {
-      copy_dense_out(it);
-      write_meta(it, 1, q, normc);
-      return;
-    }
+    if (it.scratch != nullptr)
+      dense_general(it, (gdbl*)it.scratch, p, q, trans, tol, normc, status, sh);
+    else
+      dense_general(it, (ldbl*)lds, p, q, trans, tol, normc, status, sh);
   }
-  double kept = 0.0;
-  for (int c = 0; c < r; ++c) {
-    const double s = sh.sigma[sh.order[c]];
-    kept += s * s;
-  }
-  kept *= normc * normc;
-  // basis: right singular vectors of G (q-long); other side: G_orig * basis (p-long)
-  //   m >= n: V' = basis (n x r), U' = D basis (m x r)
-  //   m <  n: U' = basis (m x r), V' = D^T basis (n x r)
-  double* Uo = it.out;
-  double* Vo = it.out + (int64_t)m * r;
-  double* basis = trans ? Uo : Vo;
-  double* other = trans ? Vo : Uo;
-  write_basis(X, ldx, q, r, basis, q, sh);
-  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
-  for (int o = g; o < p * r; o += kGroups) {
-    const int i = o % p, c = o / p;
-    const double* b = basis + (int64_t)c * q;
-    double s = 0.0;
-    if (!trans) {
-      for (int j = gl; j < n; j += 16) s += it.D[i + (int64_t)j * it.ldd] * b[j];
-    } else {
-      const double* dcol = it.D + (int64_t)i * it.ldd;   // column i of D (m long)
-      for (int j = gl; j < m; j += 16) s += dcol[j] * b[j];
-    }
-    s = group_sum16(s);
-    if (gl == 0) other[i + (int64_t)c * p] = s;
-  }
-  write_meta(it, 2, r, sqrt(kept));
 }
 
-__device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces, double tol,
-                             double* lds, int* status, RecShared& sh) {
+template <typename PT>
+CLR_INLINE void lowrank_body(const RecItem& it, const Piece* __restrict__ pieces, double tol,
+                             PT* W, int* status, RecShared& sh) {
   const int m = it.m, n = it.n, R = it.R;
-  double* W = it.scratch != nullptr ? it.scratch : lds;
-  double* Uc = W;
-  double* Vc = Uc + (int64_t)m * R;
-  double* G = Vc + (int64_t)n * R;     // working copy of M^T / ||M||
-  double* Mc = G + (int64_t)R * R;     // M itself
-  double* tauU = Mc + (int64_t)R * R;
-  double* tauV = tauU + R;
+  PT* Uc = W;
+  PT* Vc = Uc + (int64_t)m * R;
+  PT* G = Vc + (int64_t)n * R;     // working copy of M^T / ||M||
+  PT* Mc = G + (int64_t)R * R;     // M itself
+  PT* tauU = Mc + (int64_t)R * R;
+  PT* tauV = tauU + R;
+  gdbl* out = (gdbl*)it.out;
   // gather the concatenation (Eq. (5)); the scale rides on U
   int off = 0;
   for (int pc = 0; pc < it.npieces; ++pc) {
     const Piece pz = pieces[it.piece0 + pc];
+    const cgdbl* pu = (const cgdbl*)pz.U;
+    const cgdbl* pv = (const cgdbl*)pz.V;
     for (int64_t e = threadIdx.x; e < (int64_t)m * pz.r; e += kRecThreads) {
       const int i = (int)(e % m), c = (int)(e / m);
-      Uc[i + (int64_t)(off + c) * m] = pz.scale * pz.U[i + (int64_t)c * pz.ldu];
+      Uc[i + (int64_t)(off + c) * m] = pz.scale * pu[i + (int64_t)c * pz.ldu];
     }
     for (int64_t e = threadIdx.x; e < (int64_t)n * pz.r; e += kRecThreads) {
       const int i = (int)(e % n), c = (int)(e / n);
-      Vc[i + (int64_t)(off + c) * n] = pz.V[i + (int64_t)c * pz.ldv];
+      Vc[i + (int64_t)(off + c) * n] = pv[i + (int64_t)c * pz.ldv];
     }
     off += pz.r;
   }
@@ -1098,7 +1156,7 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
   if (tol == 0.0) {
     // no truncation: the concatenation itself is the result; keep a copy in the
     // output slot before the QR below overwrites the working factors
-    for (int64_t e = threadIdx.x; e < (int64_t)(m + n) * R; e += kRecThreads) it.out[e] = W[e];
+    for (int64_t e = threadIdx.x; e < (int64_t)(m + n) * R; e += kRecThreads) out[e] = W[e];
     __syncthreads();
   }
   householder_qr(Uc, m, R, tauU);
@@ -1142,8 +1200,8 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
     kept += s * s;
   }
   kept *= normc * normc;
-  double* Uo = it.out;
-  double* Vo = it.out + (int64_t)m * r;
+  gdbl* Uo = out;
+  gdbl* Vo = out + (int64_t)m * r;
   // left singular vectors of M (right ones of M^T) into the top of U'
   for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += kRecThreads) Uo[e] = 0.0;
   __syncthreads();
@@ -1160,6 +1218,14 @@ __device__ void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
   apply_q(Uc, m, R, tauU, Uo, m, r);
   apply_q(Vc, n, R, tauV, Vo, n, r);
   write_meta(it, 2, r, sqrt(kept));
+}
+
+CLR_INLINE void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces, double tol,
+                             double* lds, int* status, RecShared& sh) {
+  if (it.scratch != nullptr)
+    lowrank_body(it, pieces, tol, (gdbl*)it.scratch, status, sh);
+  else
+    lowrank_body(it, pieces, tol, (ldbl*)lds, status, sh);
 }
 
 // Dense-path blocks whose edges are both <= 160 (and tol > 0) go to the
