@@ -25,7 +25,9 @@ constexpr int kJacobiMaxSweeps = 60;
 // ---------------------------------------------------------------------------
 
 // One term of a grouped GEMM item:  scale * L (m x k) * R (k x n) where
-// L(i, kk) = L[i*sLi + kk*sLk] and R(kk, j) = R[kk*sRk + j*sRj].
+// L(i, kk) = L[i*sLi + kk*sLk] and R(kk, j) = R[kk*sRk + j*sRj].  Strides are
+// block-local (at most the largest block edge), so the GEMM kernel forms
+// i * sLi and j * sRj in 32 bits.
 struct Seg {
   const double* L;
   const double* R;

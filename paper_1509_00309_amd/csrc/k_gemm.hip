@@ -15,7 +15,11 @@
 //               (lo = fp32(x - hi)) go to a second FP32 partial.
 //
 // Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement; wave (wr, wc)
-// owns the 16 x 16 output tiles (wr + 2a, wc + 2b), a, b < WT.
+// owns the 16 x 16 output tiles (wr + 2a, wc + 2b), a < NA, b < NB, where
+// NA, NB <= WT are the item's valid tile counts for that wave.  The item loop
+// is instantiated per (NA, NB) and selected once per item by a scalar switch,
+// so no MFMA sits behind a per-tile branch and each variant keeps only its
+// own accumulators live.
 //
 // MFMA operand layout for the 16x16x4 shapes (64 lanes, lane = l):
 //   A(i, k): i = l % 16, k = l / 16;   B(k, j): j = l % 16, k = l / 16;
@@ -37,6 +41,15 @@ typedef double __attribute__((address_space(1))) gdouble_mut;
 __device__ inline gdouble* as_global(const double* p) { return (gdouble*)p; }
 __device__ inline gdouble_mut* as_global_mut(double* p) { return (gdouble_mut*)p; }
 
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uni64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+constexpr int kSegCache = 96;  // segment descriptors of an item kept in LDS
+
 template <int WT, bool F32>
 struct GemmLds {
   static constexpr int TM = 32 * WT;
@@ -46,69 +59,145 @@ struct GemmLds {
   T b[2][kSlabK][LD];
   T alo[F32 ? 2 : 1][F32 ? kSlabK : 1][F32 ? LD : 1];
   T blo[F32 ? 2 : 1][F32 ? kSlabK : 1][F32 ? LD : 1];
-  // per inner-row source descriptors of the slab being loaded next
+  // per inner-row source descriptors of the slabs in flight
   const double* lp[2][kSlabK];
   const double* rp[2][kSlabK];
   int64_t sli[2][kSlabK];
   int64_t srj[2][kSlabK];
-  double scale[2][kSlabK];
+  double scale[2][kSlabK];   // L scale of the row; 0 for rows past the item
+  double bok[2][kSlabK];     // 1 for R rows inside the item, 0 past it
+  Seg segs[kSegCache];
 };
 
 // Thread t < 16 resolves inner row t of slab `slab`: which segment it falls in
 // and where its L column / R row start.  `cur` is that thread's segment cursor
-// (monotone over slabs).
-__device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ segs, int slab,
-                                   int t, int& cur, const double*& lp, const double*& rp,
-                                   int64_t& sli, int64_t& srj, double& sc) {
+// (monotone over slabs).  The first kSegCache descriptors come from LDS.  A
+// row past the item gets the first segment's operands with zero strides and
+// zero weights, so every address the loader forms is valid.
+__device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ segs,
+                                   const Seg* cache, int slab, int t, int& cur,
+                                   const double*& lp, const double*& rp, int64_t& sli,
+                                   int64_t& srj, double& sc, double& bok) {
   const int g = slab * kSlabK + t;
-  lp = nullptr;
-  rp = nullptr;
+  lp = cache[0].L;
+  rp = cache[0].R;
   sli = 0;
   srj = 0;
   sc = 0.0;
+  bok = 0.0;
   if (g >= it.ktotal) return;
   while (cur < it.nseg) {
-    const Seg& s = segs[it.seg0 + cur];
+    const Seg& s = cur < kSegCache ? cache[cur] : segs[it.seg0 + cur];
     if (g < s.kbase + s.k) break;
     ++cur;
   }
   if (cur >= it.nseg) return;
-  const Seg& s = segs[it.seg0 + cur];
+  const Seg& s = cur < kSegCache ? cache[cur] : segs[it.seg0 + cur];
   const int kl = g - s.kbase;
   lp = s.L + (int64_t)it.row0 * s.sLi + (int64_t)kl * s.sLk;
   rp = s.R + (int64_t)it.col0 * s.sRj + (int64_t)kl * s.sRk;
   sli = s.sLi;
   srj = s.sRj;
   sc = s.scale;
+  bok = 1.0;
 }
 
-template <int WT, bool F32, bool SPLIT>
-__global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
-                                                           const Seg* __restrict__ segs,
-                                                           int nitems) {
-  using L = GemmLds<WT, F32>;
-  constexpr int TM = L::TM;
-  constexpr int NE = (kSlabK * TM) / kGemmThreads;  // staged elements per thread and operand
-  static_assert((kSlabK * TM) % kGemmThreads == 0, "tile/thread mismatch");
-  __shared__ L sh;
+// MFMA work of one LDS slab for a wave that owns NA x NB valid tiles.  The
+// tile counts are template constants so the body is straight-line code.
+template <int WT, bool F32, bool SPLIT, int NA, int NB>
+__device__ __attribute__((always_inline)) inline void slab_mfma(GemmLds<WT, F32>& sh, int cur,
+                                                                 int wr, int wc, int kr, int lc,
+                                                                 d4 (&acc)[WT][WT]) {
+  if constexpr (!F32) {
+    // all operands of the slab first, then the MFMA chain
+    double av[kSlabK / 4][NA], bv[kSlabK / 4][NB];
+#pragma unroll
+    for (int q = 0; q < kSlabK / 4; ++q) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) av[q][a] = sh.a[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[q][b] = sh.b[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
+    }
+#pragma unroll
+    for (int q = 0; q < kSlabK / 4; ++q)
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][a], bv[q][b], acc[a][b], 0, 0, 0);
+  } else {
+    f4 p[NA][NB];
+    f4 pl[SPLIT ? NA : 1][SPLIT ? NB : 1];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) p[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) pl[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int q = 0; q < kSlabK / 4; ++q) {
+      float av[NA], bv[NB];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) av[a] = sh.a[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = sh.b[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          p[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], p[a][b], 0, 0, 0);
+      if constexpr (SPLIT) {
+        float al[NA], bl[NB];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) al[a] = sh.alo[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bl[b] = sh.blo[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            pl[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bl[b], pl[a][b], 0, 0, 0);
+            pl[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[a], bv[b], pl[a][b], 0, 0, 0);
+          }
+      }
+    }
+    // FP64 flush of this slab's FP32 partials
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double add = (double)p[a][b][v];
+          if constexpr (SPLIT) add += (double)pl[a][b][v];
+          acc[a][b][v] += add;
+        }
+  }
+}
 
-  // XCD-aware order: consecutive items (tiles of one block row) share an XCD's L2.
-  const int per = gridDim.x / 8;
-  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (item >= nitems) return;
-  const GemmItem it = items[item];
+// Main loop and epilogue of one item for a wave that owns NA x NB valid
+// tiles (0 x 0 for waves with nothing to compute; they still stage operands).
+template <int WT, bool F32, bool SPLIT, int NA, int NB>
+__device__ __attribute__((always_inline)) inline void run_item(GemmLds<WT, F32>& sh,
+                                                                const GemmItem& it,
+                                                                const Seg* __restrict__ segs,
+                                                                int wr, int wc) {
+  constexpr int TM = GemmLds<WT, F32>::TM;
+  constexpr int NE = TM / 16;  // staged elements per thread and operand
+  static_assert(kSlabK == 16 && kGemmThreads == 256, "staging map assumes 16 x 16 threads");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int mt = (it.m + 15) >> 4, nt = (it.n + 15) >> 4;
   const int nslab = (it.ktotal + kSlabK - 1) / kSlabK;
 
   d4 acc[WT][WT];
 #pragma unroll
-  for (int a = 0; a < WT; ++a)
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int b = 0; b < WT; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
   int cursor = 0;  // meaningful for tid < 16 only
   double ra[NE], rb[NE];
@@ -118,58 +207,75 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
       const double* lp;
       const double* rp;
       int64_t sli, srj;
-      double sc;
-      resolve_row(it, segs, slab, tid, cursor, lp, rp, sli, srj, sc);
+      double sc, bok;
+      resolve_row(it, segs, sh.segs, slab, tid, cursor, lp, rp, sli, srj, sc, bok);
       sh.lp[buf][tid] = lp;
       sh.rp[buf][tid] = rp;
       sh.sli[buf][tid] = sli;
       sh.srj[buf][tid] = srj;
       sh.scale[buf][tid] = sc;
+      sh.bok[buf][tid] = bok;
     }
   };
-  // global -> registers; the thread->element map is chosen from inner row 0:
-  // rows contiguous in memory are read row-fast, otherwise inner-fast.
+  // Staging map: every thread serves one inner row t of the slab and the
+  // elements i0 + 16u of that row.  Rows contiguous in memory (unit stride
+  // along i) are read row-fast: t = tid / 16, i0 = tid % 16, so 16 lanes read
+  // 128 contiguous bytes; otherwise inner-fast: t = tid % 16, i0 = tid / 16,
+  // so 16 lanes read 16 consecutive inner indices.  The map is fixed per slab
+  // from row 0 and a thread needs one descriptor per operand and slab.
+  //
+  // Global -> registers without branches: an element outside the item (row
+  // or column beyond m / n, or an inner row past the last segment) reads a
+  // valid address of the same row instead; validity and the segment scale are
+  // applied when the registers go to LDS, so the loads stay in flight across
+  // the MFMA work of the current slab.
   auto load = [&](int buf) {
-    const bool arow = sh.sli[buf][0] == 1;
-    const bool brow = sh.srj[buf][0] == 1;
+    const bool arow = uni(sh.sli[buf][0] == 1);
+    const bool brow = uni(sh.srj[buf][0] == 1);
+    const int ta = arow ? tid >> 4 : tid & 15;
+    const int ia0 = arow ? tid & 15 : tid >> 4;
+    const int tb = brow ? tid >> 4 : tid & 15;
+    const int ib0 = brow ? tid & 15 : tid >> 4;
+    const double* pa = sh.lp[buf][ta];
+    const int sa = (int)sh.sli[buf][ta];
+    const double* pb = sh.rp[buf][tb];
+    const int sb = (int)sh.srj[buf][tb];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
-      const int e = tid + u * kGemmThreads;
-      int t, i;
-      if (arow) { t = e / TM; i = e % TM; } else { t = e % kSlabK; i = e / kSlabK; }
-      const double* p = sh.lp[buf][t];
-      double v = 0.0;
-      if (p != nullptr && i < it.m) v = as_global(p)[(int64_t)i * sh.sli[buf][t]] * sh.scale[buf][t];
-      ra[u] = v;
-      if (brow) { t = e / TM; i = e % TM; } else { t = e % kSlabK; i = e / kSlabK; }
-      const double* q = sh.rp[buf][t];
-      double w = 0.0;
-      if (q != nullptr && i < it.n) w = as_global(q)[(int64_t)i * sh.srj[buf][t]];
-      rb[u] = w;
+      const int i = ia0 + 16 * u;
+      const int j = ib0 + 16 * u;
+      ra[u] = *as_global(pa + ((i < it.m) ? i : 0) * sa);
+      rb[u] = *as_global(pb + ((j < it.n) ? j : 0) * sb);
     }
   };
-  auto store = [&](int buf, int pbuf) {
-    const bool arow = sh.sli[pbuf][0] == 1;
-    const bool brow = sh.srj[pbuf][0] == 1;
+  auto store = [&](int buf) {
+    const bool arow = uni(sh.sli[buf][0] == 1);
+    const bool brow = uni(sh.srj[buf][0] == 1);
+    const int ta = arow ? tid >> 4 : tid & 15;
+    const int ia0 = arow ? tid & 15 : tid >> 4;
+    const int tb = brow ? tid >> 4 : tid & 15;
+    const int ib0 = brow ? tid & 15 : tid >> 4;
+    const double sc = sh.scale[buf][ta];   // 0 for rows past the item
+    const double bk = sh.bok[buf][tb];     // 0 for rows past the item
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
-      const int e = tid + u * kGemmThreads;
-      int t, i;
-      if (arow) { t = e / TM; i = e % TM; } else { t = e % kSlabK; i = e / kSlabK; }
+      const int i = ia0 + 16 * u;
+      const int j = ib0 + 16 * u;
+      const bool va = (i < it.m) & (sc != 0.0);
+      const bool vb = (j < it.n) & (bk != 0.0);
+      const double xa = va ? ra[u] * sc : 0.0;
+      const double xb = vb ? rb[u] : 0.0;
       if constexpr (F32) {
-        const float hi = (float)ra[u];
-        sh.a[buf][t][i] = hi;
-        if constexpr (SPLIT) sh.alo[buf][t][i] = (float)(ra[u] - (double)hi);
+        const float ha = (float)xa, hb = (float)xb;
+        sh.a[buf][ta][i] = ha;
+        sh.b[buf][tb][j] = hb;
+        if constexpr (SPLIT) {
+          sh.alo[buf][ta][i] = (float)(xa - (double)ha);
+          sh.blo[buf][tb][j] = (float)(xb - (double)hb);
+        }
       } else {
-        sh.a[buf][t][i] = ra[u];
-      }
-      if (brow) { t = e / TM; i = e % TM; } else { t = e % kSlabK; i = e / kSlabK; }
-      if constexpr (F32) {
-        const float hi = (float)rb[u];
-        sh.b[buf][t][i] = hi;
-        if constexpr (SPLIT) sh.blo[buf][t][i] = (float)(rb[u] - (double)hi);
-      } else {
-        sh.b[buf][t][i] = rb[u];
+        sh.a[buf][ta][i] = xa;
+        sh.b[buf][tb][j] = xb;
       }
     }
   };
@@ -178,7 +284,7 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
     resolve(0, 0);
     __syncthreads();
     load(0);
-    store(0, 0);
+    store(0);
     if (nslab > 1) resolve(1, 1);
     __syncthreads();
   }
@@ -188,65 +294,22 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
   for (int s = 0; s < nslab; ++s) {
     const int cur = s & 1, nxt = cur ^ 1;
     if (s + 1 < nslab) load(nxt);
-    if constexpr (!F32) {
-#pragma unroll
-      for (int q = 0; q < kSlabK / 4; ++q) {
-        double av[WT], bv[WT];
-#pragma unroll
-        for (int a = 0; a < WT; ++a) av[a] = sh.a[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
-#pragma unroll
-        for (int b = 0; b < WT; ++b) bv[b] = sh.b[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
-#pragma unroll
-        for (int a = 0; a < WT; ++a) {
-          if (wr + 2 * a >= mt) continue;
-#pragma unroll
-          for (int b = 0; b < WT; ++b) {
-            if (wc + 2 * b >= nt) continue;
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-          }
-        }
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a < WT; ++a) {
-        if (wr + 2 * a >= mt) continue;
-#pragma unroll
-        for (int b = 0; b < WT; ++b) {
-          if (wc + 2 * b >= nt) continue;
-          f4 p = f4{0.f, 0.f, 0.f, 0.f};
-          f4 pl = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int q = 0; q < kSlabK / 4; ++q) {
-            const float av = sh.a[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
-            const float bv = sh.b[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
-            p = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, p, 0, 0, 0);
-            if constexpr (SPLIT) {
-              const float al = sh.alo[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
-              const float bl = sh.blo[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
-              pl = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bl, pl, 0, 0, 0);
-              pl = __builtin_amdgcn_mfma_f32_16x16x4f32(al, bv, pl, 0, 0, 0);
-            }
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            acc[a][b][v] += (double)p[v];
-            if constexpr (SPLIT) acc[a][b][v] += (double)pl[v];
-          }
-        }
-      }
-    }
-    if (s + 1 < nslab) store(nxt, nxt);
+    if constexpr (NA > 0 && NB > 0) slab_mfma<WT, F32, SPLIT, NA, NB>(sh, cur, wr, wc, kr, lc, acc);
+    if (s + 1 < nslab) store(nxt);
     if (s + 2 < nslab) resolve(s + 2, cur);
     __syncthreads();
   }
 
-  // epilogue (output layout per precision, see the header comment)
+  // epilogue (output layout per precision, see the header comment).  The
+  // accumulators leave through one more MFMA (+ 0 * 0): with only MFMA users
+  // inside and after the loop, the compiler keeps them in accumulation
+  // registers for the whole loop instead of copying them out every slab.
+  const double alpha = it.alpha;
 #pragma unroll
-  for (int a = 0; a < WT; ++a) {
-    if (wr + 2 * a >= mt) continue;
+  for (int a = 0; a < NA; ++a) {
 #pragma unroll
-    for (int b = 0; b < WT; ++b) {
-      if (wc + 2 * b >= nt) continue;
+    for (int b = 0; b < NB; ++b) {
+      const d4 fin = __builtin_amdgcn_mfma_f64_16x16x4f64(0.0, 0.0, acc[a][b], 0, 0, 0);
       const int j = 16 * (wc + 2 * b) + lc;
       if (j >= it.n) continue;
       gdouble_mut* col = as_global_mut(it.C) + (int64_t)(it.col0 + j) * it.ldc + it.row0;
@@ -255,11 +318,73 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
         // f64 16x16x4: row (lane/16) + 4v;  f32 16x16x4: row 4*(lane/16) + v
         const int i = 16 * (wr + 2 * a) + (F32 ? 4 * kr + v : kr + 4 * v);
         if (i < it.m) {
-          const double val = it.alpha * acc[a][b][v];
+          const double val = alpha * fin[v];
           col[i] = it.accumulate ? col[i] + val : val;
         }
       }
     }
+  }
+}
+
+template <int WT, bool F32, bool SPLIT, int NA>
+__device__ __attribute__((always_inline)) inline void run_nb(GemmLds<WT, F32>& sh,
+                                                              const GemmItem& it,
+                                                              const Seg* __restrict__ segs,
+                                                              int wr, int wc, int nb) {
+  static_assert(WT >= 3 && WT <= 5, "tile dispatch covers 3 to 5 tiles per wave and dimension");
+  switch (nb) {
+    case 0: run_item<WT, F32, SPLIT, NA, 0>(sh, it, segs, wr, wc); break;
+    case 1: run_item<WT, F32, SPLIT, NA, 1>(sh, it, segs, wr, wc); break;
+    case 2: run_item<WT, F32, SPLIT, NA, 2>(sh, it, segs, wr, wc); break;
+    case 3: run_item<WT, F32, SPLIT, NA, 3>(sh, it, segs, wr, wc); break;
+    case 4: run_item<WT, F32, SPLIT, NA, (WT < 4 ? WT : 4)>(sh, it, segs, wr, wc); break;
+    default: run_item<WT, F32, SPLIT, NA, WT>(sh, it, segs, wr, wc); break;
+  }
+}
+
+template <int WT, bool F32, bool SPLIT>
+__global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
+                                                           const Seg* __restrict__ segs,
+                                                           int nitems) {
+  __shared__ GemmLds<WT, F32> sh;
+
+  // XCD-aware order: consecutive items (tiles of one block row) share an XCD's L2.
+  const int per = gridDim.x / 8;
+  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (item >= nitems) return;
+  // Item fields are the same for every lane; readfirstlane lets the compiler
+  // keep them (and all control flow derived from them) in scalar registers.
+  GemmItem it = items[item];
+  it.m = uni(it.m);
+  it.n = uni(it.n);
+  it.row0 = uni(it.row0);
+  it.col0 = uni(it.col0);
+  it.seg0 = uni(it.seg0);
+  it.nseg = uni(it.nseg);
+  it.ktotal = uni(it.ktotal);
+  it.accumulate = uni(it.accumulate);
+  it.ldc = uni64(it.ldc);
+  const int tid = threadIdx.x;
+  const int wave = uni(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int mt = (it.m + 15) >> 4, nt = (it.n + 15) >> 4;
+  // valid tiles of this wave: a with wr + 2a < mt, b with wc + 2b < nt
+  const int na = min(WT, max(0, (mt - wr + 1) >> 1));
+  const int nb = min(WT, max(0, (nt - wc + 1) >> 1));
+
+  const int ncache = min(it.nseg, kSegCache);
+  for (int s = tid; s < ncache; s += kGemmThreads) sh.segs[s] = segs[it.seg0 + s];
+  __syncthreads();
+
+  // Every wave runs the same slab loop (the barriers are shared); only the
+  // MFMA body and epilogue differ with the wave's tile counts.
+  switch (na) {
+    case 0: run_item<WT, F32, SPLIT, 0, 0>(sh, it, segs, wr, wc); break;
+    case 1: run_nb<WT, F32, SPLIT, 1>(sh, it, segs, wr, wc, nb); break;
+    case 2: run_nb<WT, F32, SPLIT, 2>(sh, it, segs, wr, wc, nb); break;
+    case 3: run_nb<WT, F32, SPLIT, 3>(sh, it, segs, wr, wc, nb); break;
+    case 4: run_nb<WT, F32, SPLIT, (WT < 4 ? WT : 4)>(sh, it, segs, wr, wc, nb); break;
+    default: run_nb<WT, F32, SPLIT, WT>(sh, it, segs, wr, wc, nb); break;
   }
 }
 
