@@ -454,42 +454,83 @@ CLR_INLINE int svd_rank(PT* G, int p, int q, int64_t ld, double tol, int* status
 // 512 threads as a 16 x 32 grid: thread (tr, tc) = (tid % 16, tid / 16) holds
 // G(i, j) for i = tr + 16 a, j = tc + 32 b (a < 10, b < 5).  A column lives in
 // one 16-lane DPP row, so column reductions stay in the vector ALU; rows are
-// reduced through LDS.  This keeps 160 x 160 FP64 blocks (200 KiB) on chip,
-// beyond the LDS capacity, and makes each Householder step a handful of
-// workgroup barriers.
+// reduced inside each wave with two lane exchanges and across the 8 waves
+// through LDS.  This keeps 160 x 160 FP64 blocks (200 KiB) on chip, beyond the
+// LDS capacity.
 //
-//  * Householder bidiagonalisation G = U_B B V_B^T (left reflector on column k,
-//    right reflector on row k) gives the bidiagonal d, e of B.
-//  * Singular values of B: multisection on the Golub-Kahan tridiagonal (zero
-//    diagonal, off-diagonals d_0, e_0, d_1, ...) with Sturm counts; its
-//    eigenvalues are +-sigma_i.  Values are resolved to 1e-17 of ||G||_F.
-//  * Pivoted Householder QR (column norms recomputed exactly each step) for the
-//    truncated blocks, whose singular vectors then come from Jacobi on R^T.
+//  * Householder bidiagonalisation G = U_B B V_B^T.  Every wave computes each
+//    reflector itself from the column or row published in LDS (identical
+//    inputs and reduction order give bitwise identical reflectors), so a step
+//    costs four workgroup barriers.  The right reflectors stay in LDS.
+//  * Singular values of B by multisection on the Golub-Kahan tridiagonal
+//    (zero diagonal, off-diagonals d_0, e_0, d_1, ...; eigenvalues +-sigma_i)
+//    with Sturm counts.  A first round probes 512 log-spaced points, later
+//    rounds split only the brackets that can still move the kept rank.
+//  * Truncated blocks: the top-r values are refined to full precision and
+//    each singular vector of B comes from one twisted factorisation of
+//    T_GK - sigma I (one thread per vector); the right reflectors map them to
+//    singular vectors of G.  Vectors of values closer than 1e-3 (relative)
+//    are re-orthogonalised; if that collapses a vector (an unresolved
+//    multiple value) the block falls back to pivoted QR + Jacobi.
 // ---------------------------------------------------------------------------
 constexpr int kRegEdge = 160;
 constexpr int kRowCls = kRecThreads / 32;      // 16 row classes (one DPP row per column class)
 constexpr int kRR = kRegEdge / kRowCls;        // 10 rows per thread
 constexpr int kRC = kRegEdge / 32;             // 5 columns per thread
+constexpr int kWaves = kRecThreads / 64;
+constexpr int kVStore = kRegEdge * (kRegEdge - 1) / 2;
+constexpr int kSeg = 32;                               // twisted-factorisation checkpoint interval
+constexpr int kMaxSeg = (2 * kRegEdge + kSeg - 1) / kSeg;
+constexpr int kMaxVec = kRegEdge / 2;                  // truncated ranks satisfy 2 r <= q
+constexpr int kVecPerGroup = (kMaxVec + kGroups - 1) / kGroups;
+constexpr double kProbeFloor = 1e-20;                  // brackets narrower than this are settled
+static_assert(kWaves == 8 && kRecThreads == 512, "register engine layout assumes 512 threads");
 
 struct RegLds {
-  double part[32][kRegEdge + 1];
-  double vcol[kRegEdge];
-  double vrow[kRegEdge];
-  double wrow[kRegEdge];
-  double colA[kRegEdge];
-  double colB[kRegEdge];
+  double vstore[kVStore];     // right reflector of step k at vs_off(k, q), length q - k - 1
+  double tauR[kRegEdge];
   double d[kRegEdge];
   double e[kRegEdge];
-  double b2[2 * kRegEdge];
-  double lo[kRegEdge];
-  double hi[kRegEdge];
-  int cnt[kRecThreads];
-  double tauL, tauR;
+  double colk[kRegEdge];      // column of the next left reflector (pivoted QR: its vector)
+  double rowk[kRegEdge];      // row of the next right reflector
+  double tauL;
+  int flag;
+  union {
+    struct {
+      double part[kWaves][kRegEdge + 1];
+      double wrow[kRegEdge];
+    } bd;
+    struct {
+      double b2[2 * kRegEdge];
+      double lo[kRegEdge];
+      double hi[kRegEdge];
+      int cnt[kRecThreads];
+      int act[kRegEdge];
+      int nact, rlo, rhi, rmid;
+    } st;
+    struct {
+      double ckf[kMaxVec][kMaxSeg];
+      double ckb[kMaxVec][kMaxSeg];
+    } tw;
+    struct {
+      double colA[kRegEdge];
+      double colB[kRegEdge];
+    } qr;
+  } u;
 };
 static_assert(sizeof(RegLds) <= (size_t)kRecLdsBytes, "register engine bookkeeping exceeds LDS");
 
 typedef double RegTile[kRR][kRC];
 
+CLR_INLINE void write_meta(const RecItem& it, int kind, int rank, double norm) {
+  if (threadIdx.x == 0) {
+    *it.kind_out = kind;
+    *it.rank_out = rank;
+    *it.norm_out = norm;
+  }
+}
+
+CLR_INLINE int vs_off(int k, int q) { return k * (2 * q - k - 1) / 2; }
 
 CLR_INLINE void reg_load(RegTile& a, const double* D, int64_t ldd, bool trans, double scale,
                          int p, int q) {
@@ -506,149 +547,140 @@ CLR_INLINE void reg_load(RegTile& a, const double* D, int64_t ldd, bool trans, d
     }
 }
 
-// Left reflector annihilating G(k+1:p, k); applied to columns > k.  d[k] = beta.
-CLR_INLINE void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-  const int kj = k >> 5;
-  if (tc == (k & 31)) {
-    double s2 = 0.0, x0p = 0.0;
-#pragma unroll
-    for (int ir = 0; ir < kRR; ++ir)
-#pragma unroll
-      for (int jc = 0; jc < kRC; ++jc)
-        if (jc == kj) {
-          const int i = tr + 16 * ir;
-          const double x = a[ir][jc];
-          if (i > k && i < p) s2 += x * x;
-          if (i == k) x0p = x;
-        }
-    s2 = group_sum16(s2);
-    const double x0 = group_sum16(x0p);
-    double t = 0.0, beta = x0, scal = 0.0;
-    if (s2 > 0.0) {
-      beta = -copysign(sqrt(x0 * x0 + s2), x0);
-      t = (beta - x0) / beta;
-      scal = 1.0 / (x0 - beta);
-    }
-#pragma unroll
-    for (int ir = 0; ir < kRR; ++ir)
-#pragma unroll
-      for (int jc = 0; jc < kRC; ++jc)
-        if (jc == kj) {
-          const int i = tr + 16 * ir;
-          if (i >= k && i < p) {
-            L.vcol[i] = (i == k) ? 1.0 : a[ir][jc] * scal;
-            a[ir][jc] = (i == k) ? beta : 0.0;
-          }
-        }
-    if (tr == 0) {
-      L.tauL = t;
-      L.d[k] = beta;
-    }
-  }
-  __syncthreads();
-  const double t = L.tauL;
-  if (t == 0.0) return;
-  double vr[kRR];
-#pragma unroll
-  for (int ir = 0; ir < kRR; ++ir) {
-    const int i = tr + 16 * ir;
-    vr[ir] = (i >= k && i < p) ? L.vcol[i] : 0.0;
-  }
-#pragma unroll
-  for (int jc = 0; jc < kRC; ++jc) {
-    const int j = tc + 32 * jc;
-    if (j > k && j < q) {
-      double w = 0.0;
-#pragma unroll
-      for (int ir = 0; ir < kRR; ++ir) w += vr[ir] * a[ir][jc];
-      w = group_sum16(w);
-#pragma unroll
-      for (int ir = 0; ir < kRR; ++ir) a[ir][jc] -= t * vr[ir] * w;
-    }
+// Householder vector of x = src[first .. end) computed by every wave:
+// (I - tau v v^T) x = beta e_1 with v = (1, x[1:] * scal).
+CLR_INLINE void house_wave(const double* src, int first, int end, double& beta, double& tau,
+                           double& scal) {
+  const int lane = threadIdx.x & 63;
+  double s2 = 0.0;
+  for (int i = first + 1 + lane; i < end; i += 64) s2 += src[i] * src[i];
+  s2 = wave_sum(s2);
+  const double x0 = src[first];
+  beta = x0;
+  tau = 0.0;
+  scal = 0.0;
+  if (s2 > 0.0) {
+    beta = -copysign(sqrt(x0 * x0 + s2), x0);
+    tau = (beta - x0) / beta;
+    scal = 1.0 / (x0 - beta);
   }
 }
 
-// Right reflector annihilating G(k, k+2:q); applied to rows > k.  e[k] = beta.
-CLR_INLINE void reg_right(RegTile& a, int k, int p, int q, RegLds& L) {
+// Householder bidiagonalisation of the register-resident G: d, e, the right
+// reflectors (vstore, tauR) in LDS.  The tile is left in an unspecified state.
+CLR_INLINE void reg_bidiag(RegTile& a, int p, int q, RegLds& L) {
   const int tid = threadIdx.x;
   const int tr = tid & 15, tc = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
-  const int ki = k >> 4;
-  if (tr == (k & 15)) {
+  if (tc == 0) {
 #pragma unroll
-    for (int ir = 0; ir < kRR; ++ir)
-#pragma unroll
-      for (int jc = 0; jc < kRC; ++jc)
-        if (ir == ki) {
-          const int j = tc + 32 * jc;
-          if (j > k && j < q) L.vrow[j] = a[ir][jc];
-        }
+    for (int ir = 0; ir < kRR; ++ir) {
+      const int i = tr + 16 * ir;
+      if (i < p) L.colk[i] = a[ir][0];
+    }
   }
   __syncthreads();
-  if (wave == 0) {
-    double s2 = 0.0;
-    for (int j = k + 2 + lane; j < q; j += 64) s2 += L.vrow[j] * L.vrow[j];
-    s2 = wave_sum(s2);
-    const double x0 = L.vrow[k + 1];
-    double t = 0.0, beta = x0, scal = 0.0;
-    if (s2 > 0.0) {
-      beta = -copysign(sqrt(x0 * x0 + s2), x0);
-      t = (beta - x0) / beta;
-      scal = 1.0 / (x0 - beta);
+  for (int k = 0; k < q; ++k) {
+    // left reflector on column k, applied to columns > k
+    double beta, tau, scal;
+    house_wave(L.colk, k, p, beta, tau, scal);
+    if (tid == 0) L.d[k] = beta;
+    if (tau != 0.0) {
+      double vr[kRR];
+#pragma unroll
+      for (int ir = 0; ir < kRR; ++ir) {
+        const int i = tr + 16 * ir;
+        vr[ir] = (i == k) ? 1.0 : ((i > k && i < p) ? L.colk[i] * scal : 0.0);
+      }
+#pragma unroll
+      for (int jc = 0; jc < kRC; ++jc) {
+        const int j = tc + 32 * jc;
+        if (j > k && j < q) {   // uniform over the 16-lane row that holds column j
+          double w = 0.0;
+#pragma unroll
+          for (int ir = 0; ir < kRR; ++ir) w += vr[ir] * a[ir][jc];
+          w = tau * group_sum16(w);
+#pragma unroll
+          for (int ir = 0; ir < kRR; ++ir) a[ir][jc] -= vr[ir] * w;
+        }
+      }
     }
-    for (int j = k + 2 + lane; j < q; j += 64) L.vrow[j] *= scal;
-    if (lane == 0) {
-      L.vrow[k + 1] = 1.0;
-      L.tauR = t;
+    if (k == q - 1) break;
+    // right reflector on row k, applied to rows > k
+    const int ki = k >> 4;
+    if (tr == (k & 15)) {
+#pragma unroll
+      for (int ir = 0; ir < kRR; ++ir)
+        if (ir == ki) {
+#pragma unroll
+          for (int jc = 0; jc < kRC; ++jc) {
+            const int j = tc + 32 * jc;
+            if (j > k && j < q) L.rowk[j] = a[ir][jc];
+          }
+        }
+    }
+    __syncthreads();
+    house_wave(L.rowk, k + 1, q, beta, tau, scal);
+    if (tid == 0) {
       L.e[k] = beta;
+      L.tauR[k] = tau;
     }
-  }
-  __syncthreads();
-  const double t = L.tauR;
-  if (tr == (k & 15)) {
+    if (wave == 0) {
+      double* vs = L.vstore + vs_off(k, q);
+      for (int j = k + 1 + lane; j < q; j += 64) vs[j - k - 1] = (j == k + 1) ? 1.0 : L.rowk[j] * scal;
+    }
+    double vc[kRC];
 #pragma unroll
-    for (int ir = 0; ir < kRR; ++ir)
+    for (int jc = 0; jc < kRC; ++jc) {
+      const int j = tc + 32 * jc;
+      vc[jc] = (j == k + 1) ? 1.0 : ((j > k + 1 && j < q) ? L.rowk[j] * scal : 0.0);
+    }
+    if (tau != 0.0) {
+#pragma unroll
+      for (int ir = 0; ir < kRR; ++ir) {
+        double w = 0.0;
+#pragma unroll
+        for (int jc = 0; jc < kRC; ++jc) w += a[ir][jc] * vc[jc];
+        // the 4 column classes of this wave: lanes 16 and 32 apart
+        w += swizzle_xor16(w);
+        w += __shfl_xor(w, 32, 64);
+        const int i = tr + 16 * ir;
+        if (lane < 16 && i > k && i < p) L.u.bd.part[wave][i] = w;
+      }
+    }
+    __syncthreads();
+    if (tau != 0.0 && tid > k && tid < p) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) s += L.u.bd.part[w][tid];
+      L.u.bd.wrow[tid] = s;
+    }
+    __syncthreads();
+    if (tau != 0.0) {
+#pragma unroll
+      for (int ir = 0; ir < kRR; ++ir) {
+        const int i = tr + 16 * ir;
+        if (i > k && i < p) {
+          const double w = tau * L.u.bd.wrow[i];
+#pragma unroll
+          for (int jc = 0; jc < kRC; ++jc) a[ir][jc] -= w * vc[jc];
+        }
+      }
+    }
+    // publish column k + 1 for the next left reflector
+    const int k1 = k + 1, kj1 = k1 >> 5;
+    if (tc == (k1 & 31)) {
 #pragma unroll
       for (int jc = 0; jc < kRC; ++jc)
-        if (ir == ki) {
-          const int j = tc + 32 * jc;
-          if (j == k + 1) a[ir][jc] = L.e[k];
-          if (j > k + 1 && j < q) a[ir][jc] = 0.0;
+        if (jc == kj1) {
+#pragma unroll
+          for (int ir = 0; ir < kRR; ++ir) {
+            const int i = tr + 16 * ir;
+            if (i >= k1 && i < p) L.colk[i] = a[ir][jc];
+          }
         }
-  }
-  if (t == 0.0) return;
-  double vc[kRC];
-#pragma unroll
-  for (int jc = 0; jc < kRC; ++jc) {
-    const int j = tc + 32 * jc;
-    vc[jc] = (j > k && j < q) ? L.vrow[j] : 0.0;
-  }
-#pragma unroll
-  for (int ir = 0; ir < kRR; ++ir) {
-    const int i = tr + 16 * ir;
-    if (i > k && i < p) {
-      double w = 0.0;
-#pragma unroll
-      for (int jc = 0; jc < kRC; ++jc) w += a[ir][jc] * vc[jc];
-      L.part[tc][i] = w;
     }
-  }
-  __syncthreads();
-  if (tid > k && tid < p) {
-    double s = 0.0;
-    for (int c = 0; c < 32; ++c) s += L.part[c][tid];
-    L.wrow[tid] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int ir = 0; ir < kRR; ++ir) {
-    const int i = tr + 16 * ir;
-    if (i > k && i < p) {
-      const double w = t * L.wrow[i];
-#pragma unroll
-      for (int jc = 0; jc < kRC; ++jc) a[ir][jc] -= w * vc[jc];
-    }
+    __syncthreads();
   }
 }
 
@@ -681,112 +713,517 @@ CLR_INLINE int sturm_greater(const double* b2, int q, double x) {
   return 2 * q - neg;
 }
 
-// Singular values of G (unit norm) into sh.sigma[0..q) in descending order, and
-// the kept rank for tol (tails accumulated from the smallest value upward).
-CLR_INLINE int reg_singular_values(RegTile& a, int p, int q, double tol, RegLds& L,
-                                   RecShared& sh) {
-  const int tid = threadIdx.x;
-  for (int k = 0; k < q; ++k) {
-    reg_left(a, k, p, q, L);
-    if (k < q - 1) reg_right(a, k, p, q, L);
-    __syncthreads();
-  }
-  if (tid < 2 * q - 1) {
-    const double b = (tid & 1) ? L.e[tid >> 1] : L.d[tid >> 1];
-    L.b2[tid] = b * b;
-  }
-  if (tid < q) {
-    L.lo[tid] = 0.0;
-    L.hi[tid] = 1.0 + 1e-12;
-  }
-  __syncthreads();
-  const int ts = kRecThreads / q > 0 ? kRecThreads / q : 1;
-  const int i = tid / ts, sub = tid % ts;
-  int rounds = 0;
-  for (double w = 1.0; w > 1e-17; w /= (double)(ts + 1)) ++rounds;
-  if (tid == 0) sh.flag = 0;
-  __syncthreads();
-  for (int rd = 0; rd < rounds; ++rd) {
+CLR_INLINE double probe_point(int t) { return exp2(-0.125 * (double)t); }
+
+CLR_INLINE bool bracket_settled(double lo, double hi) {
+  return hi - lo <= fmax(0x1p-50 * hi, kProbeFloor);
+}
+
+CLR_INLINE int wave_isum(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Wave 0: kept-rank bounds from the brackets.  With T(r) = sum_{i>=r} s_i^2
+// the kept rank is #{r < q : T(r) > tol^2}; evaluated with the lower ends,
+// the upper ends and the midpoints of the brackets.
+CLR_INLINE void rank_counts(const RegLds& L, int q, double bound, int& rlo, int& rhi, int& rmid) {
+  const int lane = threadIdx.x & 63;
+  double sl[3], shh[3], sm[3];
+  double cl = 0.0, ch = 0.0, cm = 0.0;
+#pragma unroll
+  for (int t = 2; t >= 0; --t) {
+    const int i = 3 * lane + t;
     if (i < q) {
-      const double lo = L.lo[i], hi = L.hi[i];
-      const double x = lo + (double)(sub + 1) * (hi - lo) / (double)(ts + 1);
-      L.cnt[tid] = sturm_greater(L.b2, q, x);
+      const double lo = L.u.st.lo[i], hi = L.u.st.hi[i], mid = 0.5 * (lo + hi);
+      cl += lo * lo;
+      ch += hi * hi;
+      cm += mid * mid;
     }
-    __syncthreads();
-    if (i < q && sub == 0) {
-      const double lo = L.lo[i], hi = L.hi[i];
-      double nlo = lo, nhi = hi;
-      for (int s2 = 0; s2 < ts; ++s2) {
-        const double x = lo + (double)(s2 + 1) * (hi - lo) / (double)(ts + 1);
-        if (L.cnt[i * ts + s2] > i) {
-          nlo = x;
-        } else {
-          nhi = x;
-          break;
-        }
-      }
-      L.lo[i] = nlo;
-      L.hi[i] = nhi;
-    }
-    __syncthreads();
-    // Stop once the brackets settle the decision: with T(k) = sum_{j>=k} s_j^2
-    // bracketed by the squared bounds, the kept rank lies in [r_lo, r_hi]; it is
-    // settled when r_lo == r_hi, or when even r_lo keeps the block dense.
-    if (tid == 0) {
-      const double bound = tol * tol;
-      double tlo = 0.0, thi = 0.0;
-      int r_lo = q, r_hi = q;
-      bool lo_set = false, hi_set = false;
-      // scan k from q down to 0: T(k) grows as k decreases
-      if (bound >= 0.0) {
-        r_lo = 0;
-        r_hi = 0;
-        for (int k = q; k >= 0; --k) {
-          if (k < q) {
-            tlo += L.lo[k] * L.lo[k];
-            thi += L.hi[k] * L.hi[k];
-          }
-          if (!lo_set && tlo > bound) {
-            r_lo = k + 1;
-            lo_set = true;
-          }
-          if (!hi_set && thi > bound) {
-            r_hi = k + 1;
-            hi_set = true;
-          }
-        }
-      }
-      if (r_lo == r_hi || 2 * r_lo > q) {
-        sh.flag = 1;
-        sh.rank = r_lo;
-      }
-    }
-    __syncthreads();
-    if (sh.flag) break;
+    sl[t] = cl;
+    shh[t] = ch;
+    sm[t] = cm;
   }
-  const bool settled = sh.flag != 0;
-  if (tid < q) {
-    sh.sigma[tid] = 0.5 * (L.lo[tid] + L.hi[tid]);
-    sh.order[tid] = tid;
+  // sums over the chunks of the lanes above this one
+  double xl = cl, xh = ch, xm = cm;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double tl = __shfl_down(xl, o, 64), th = __shfl_down(xh, o, 64), tm = __shfl_down(xm, o, 64);
+    if (lane + o < 64) {
+      xl += tl;
+      xh += th;
+      xm += tm;
+    }
+  }
+  const double el = xl - cl, eh = xh - ch, em = xm - cm;
+  int nl = 0, nh = 0, nm = 0;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int i = 3 * lane + t;
+    if (i < q) {
+      nl += (sl[t] + el > bound);
+      nh += (shh[t] + eh > bound);
+      nm += (sm[t] + em > bound);
+    }
+  }
+  rlo = wave_isum(nl);
+  rhi = wave_isum(nh);
+  rmid = wave_isum(nm);
+}
+
+// One multisection round over the active brackets (S.act[0 .. nact)).
+CLR_INLINE void multisect_round(int q, int nact, RegLds& L) {
+  auto& S = L.u.st;
+  const int tid = threadIdx.x;
+  const int ts = kRecThreads / nact;
+  const int a = tid / ts, sub = tid % ts;
+  if (a < nact) {
+    const int i = S.act[a];
+    const double lo = S.lo[i], hi = S.hi[i];
+    const double x = lo + (double)(sub + 1) * (hi - lo) / (double)(ts + 1);
+    S.cnt[tid] = sturm_greater(S.b2, q, x);
   }
   __syncthreads();
-  if (tid == 0 && !settled) {
-    double acc = 0.0;
-    sh.tails[q] = 0.0;
-    for (int k = q - 1; k >= 0; --k) {
-      acc += sh.sigma[k] * sh.sigma[k];
-      sh.tails[k] = acc;
-    }
-    int r = q;
-    for (int k = 0; k <= q; ++k)
-      if (sqrt(sh.tails[k]) <= tol) {
-        r = k;
+  if (a < nact && sub == 0) {
+    const int i = S.act[a];
+    const double lo = S.lo[i], hi = S.hi[i];
+    double nlo = lo, nhi = hi;
+    for (int s2 = 0; s2 < ts; ++s2) {
+      const double x = lo + (double)(s2 + 1) * (hi - lo) / (double)(ts + 1);
+      if (S.cnt[a * ts + s2] > i) {
+        nlo = x;
+      } else {
+        nhi = x;
         break;
       }
-    sh.rank = r;
+    }
+    S.lo[i] = nlo;
+    S.hi[i] = nhi;
   }
   __syncthreads();
-  return sh.rank;
+}
+
+// Wave 0: active list of the unsettled brackets with index in [from, to).
+CLR_INLINE int collect_active(RegLds& L, int from, int to) {
+  auto& S = L.u.st;
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  for (int c0 = 0; c0 < to; c0 += 64) {
+    const int i = c0 + lane;
+    const bool act = i >= from && i < to && !bracket_settled(S.lo[i], S.hi[i]);
+    const unsigned long long msk = __ballot(act);
+    if (act) S.act[base + __popcll(msk & ((1ull << lane) - 1ull))] = i;
+    base += __popcll(msk);
+  }
+  return base;
+}
+
+// Singular values of the bidiagonal (d, e in LDS) and the kept rank for tol.
+// Brackets end in L.u.st.lo / hi; sh.sigma receives the midpoints.
+CLR_INLINE int reg_decide(int q, double tol, RegLds& L, RecShared& sh) {
+  auto& S = L.u.st;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid < 2 * q - 1) {
+    const double b = (tid & 1) ? L.e[tid >> 1] : L.d[tid >> 1];
+    S.b2[tid] = b * b;
+  }
+  __syncthreads();
+  S.cnt[tid] = sturm_greater(S.b2, q, probe_point(tid));
+  __syncthreads();
+  if (tid < q) {
+    int lo_t = 0, hi_t = kRecThreads;   // first probe with more than tid values above it
+    while (lo_t < hi_t) {
+      const int mid = (lo_t + hi_t) >> 1;
+      if (S.cnt[mid] > tid)
+        hi_t = mid;
+      else
+        lo_t = mid + 1;
+    }
+    if (lo_t == kRecThreads) {
+      S.lo[tid] = 0.0;
+      S.hi[tid] = probe_point(kRecThreads - 1);
+    } else {
+      S.lo[tid] = probe_point(lo_t);
+      S.hi[tid] = lo_t == 0 ? 1.0 + 1e-12 : probe_point(lo_t - 1);
+    }
+  }
+  __syncthreads();
+  const double bound = tol * tol;
+  for (int round = 0; round < 256; ++round) {
+    if (wave == 0) {
+      int rlo, rhi, rmid;
+      rank_counts(L, q, bound, rlo, rhi, rmid);
+      const bool settled = rlo == rhi || 2 * rlo > q;
+      const int nact = settled ? 0 : collect_active(L, rlo, q);
+      if (lane == 0) {
+        S.nact = nact;
+        S.rlo = rlo;
+        S.rmid = rmid;
+        sh.flag = settled ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    if (sh.flag || S.nact == 0) break;
+    multisect_round(q, S.nact, L);
+  }
+  const int r = sh.flag ? S.rlo : S.rmid;
+  __syncthreads();
+  return r;
+}
+
+// Full-precision brackets for values 0 .. r-1; midpoints into sh.sigma.
+CLR_INLINE void reg_refine_top(int q, int r, RegLds& L, RecShared& sh) {
+  auto& S = L.u.st;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int round = 0; round < 256; ++round) {
+    if (wave == 0) {
+      const int nact = collect_active(L, 0, r);
+      if (lane == 0) S.nact = nact;
+    }
+    __syncthreads();
+    if (S.nact == 0) break;
+    multisect_round(q, S.nact, L);
+  }
+  if (tid < q) sh.sigma[tid] = 0.5 * (S.lo[tid] + S.hi[tid]);
+  __syncthreads();
+}
+
+// Golub-Kahan off-diagonal c_i (i < 2q - 1): d_0, e_0, d_1, e_1, ...
+#define GK_C(L, i) (((i) & 1) ? (L).e[(i) >> 1] : (L).d[(i) >> 1])
+CLR_INLINE double pivot_floor(double x) { return x != 0.0 ? x : -1e-300; }
+
+// Right singular vector of the bidiagonal for the singular value lam, as the
+// even entries of the eigenvector z of T_GK (size n = 2q) for +lam, from the
+// twisted factorisation of T_GK - lam I: top-down pivots D+ (L D+ L^T) and
+// bottom-up pivots D- (U D- U^T) meet at the index k where
+// |gamma_k| = |D+_k + D-_k + lam| is smallest; z_k = 1 and the other entries
+// follow from the two bidiagonal factors.  Pivots are kept only every kSeg
+// entries (ckf, ckb) and recomputed segment by segment.  Writes the q entries
+// (unnormalised) to v; returns false on a non-finite result.
+CLR_INLINE bool twisted_vector(const RegLds& L, double* ckf, double* ckb, int q, double lam,
+                               gdbl* v) {
+  const int n = 2 * q;
+  const int nseg = (n + kSeg - 1) / kSeg;
+  // forward pivots; ckf[s] = D+_{32 s - 1}
+  {
+    double dp = pivot_floor(-lam);
+    for (int s = 0; s < nseg; ++s) {
+      if (s > 0) ckf[s] = dp;
+#pragma unroll
+      for (int t = 0; t < kSeg; ++t) {
+        const int i = kSeg * s + t;
+        if (i > 0 && i < n) {
+          const double c = GK_C(L, i - 1);
+          dp = pivot_floor(-lam - c * c / dp);
+        }
+      }
+    }
+  }
+  // backward pivots with the twist search; ckb[s] = D-_{32 s + 32}
+  double best = 1e300;
+  int kst = n - 1;
+  {
+    double dm = pivot_floor(-lam);
+    for (int s = nseg - 1; s >= 0; --s) {
+      double seg[kSeg];
+      double x = s > 0 ? ckf[s] : 0.0;
+#pragma unroll
+      for (int t = 0; t < kSeg; ++t) {
+        const int i = kSeg * s + t;
+        if (i < n) {
+          if (i == 0) {
+            x = pivot_floor(-lam);
+          } else {
+            const double c = GK_C(L, i - 1);
+            x = pivot_floor(-lam - c * c / x);
+          }
+        }
+        seg[t] = x;
+      }
+      if (s < nseg - 1) ckb[s] = dm;
+#pragma unroll
+      for (int t = kSeg - 1; t >= 0; --t) {
+        const int i = kSeg * s + t;
+        if (i < n) {
+          if (i < n - 1) {
+            const double c = GK_C(L, i);
+            dm = pivot_floor(-lam - c * c / dm);
+          }
+          const double g = fabs(seg[t] + dm + lam);
+          if (g < best) {
+            best = g;
+            kst = i;
+          }
+        }
+      }
+    }
+  }
+  double nrm2 = 0.0;
+  if ((kst & 1) == 0) {
+    v[kst >> 1] = 1.0;
+    nrm2 = 1.0;
+  }
+  // entries above the twist: z_i = -(c_i / D+_i) z_{i+1}
+  {
+    double z = 1.0;
+    for (int s = (kst - 1) / kSeg; kst > 0 && s >= 0; --s) {
+      double seg[kSeg];
+      double x = s > 0 ? ckf[s] : 0.0;
+#pragma unroll
+      for (int t = 0; t < kSeg; ++t) {
+        const int i = kSeg * s + t;
+        if (i < n) {
+          if (i == 0) {
+            x = pivot_floor(-lam);
+          } else {
+            const double c = GK_C(L, i - 1);
+            x = pivot_floor(-lam - c * c / x);
+          }
+        }
+        seg[t] = x;
+      }
+#pragma unroll
+      for (int t = kSeg - 1; t >= 0; --t) {
+        const int i = kSeg * s + t;
+        if (i < kst) {
+          z = -(GK_C(L, i) / seg[t]) * z;
+          if ((t & 1) == 0) {
+            v[i >> 1] = z;
+            nrm2 += z * z;
+          }
+        }
+      }
+    }
+  }
+  // entries below the twist: z_i = -(c_{i-1} / D-_i) z_{i-1}
+  {
+    double z = 1.0;
+    for (int s = (kst + 1) / kSeg; s < nseg; ++s) {
+      double seg[kSeg];
+      double y = s < nseg - 1 ? ckb[s] : 0.0;
+#pragma unroll
+      for (int t = kSeg - 1; t >= 0; --t) {
+        const int i = kSeg * s + t;
+        if (i < n) {
+          if (i == n - 1) {
+            y = pivot_floor(-lam);
+          } else {
+            const double c = GK_C(L, i);
+            y = pivot_floor(-lam - c * c / y);
+          }
+        }
+        seg[t] = y;
+      }
+#pragma unroll
+      for (int t = 0; t < kSeg; ++t) {
+        const int i = kSeg * s + t;
+        if (i > kst && i < n) {
+          z = -(GK_C(L, i - 1) / seg[t]) * z;
+          if ((t & 1) == 0) {
+            v[i >> 1] = z;
+            nrm2 += z * z;
+          }
+        }
+      }
+    }
+  }
+  return nrm2 > 0.0 && nrm2 < 1e300;
+}
+#undef GK_C
+
+// Values c - 1 and c belong to one cluster (vectors re-orthogonalised).
+CLR_INLINE bool close_values(const RecShared& sh, int c) {
+  return sh.sigma[c - 1] - sh.sigma[c] < 1e-3 * sh.sigma[c - 1];
+}
+
+// Top-r right singular basis of G (q-long, orthonormal) into basis (ld q) and
+// the other factor G_orig * basis, from the bidiagonal in LDS.  Returns false
+// (nothing final written) when a vector cannot be resolved this way.
+CLR_INLINE bool reg_vectors(const RecItem& it, int p, int q, bool trans, int r, double normc,
+                            RegLds& L, RecShared& sh) {
+  const int tid = threadIdx.x;
+  const int g = tid >> 4, gl = tid & 15;
+  const int m = it.m;
+  gdbl* Uo = (gdbl*)it.out;
+  gdbl* Vo = Uo + (int64_t)m * r;
+  gdbl* basis = trans ? Uo : Vo;
+  gdbl* other = trans ? Vo : Uo;   // p x r >= q x r: staging for the raw vectors
+  reg_refine_top(q, r, L, sh);
+  if (tid == 0) L.flag = 0;
+  __syncthreads();
+  if (tid < r) {
+    if (!twisted_vector(L, L.u.tw.ckf[tid], L.u.tw.ckb[tid], q, sh.sigma[tid],
+                        other + (int64_t)tid * q))
+      L.flag = 1;
+  }
+  __syncthreads();
+  if (L.flag) return false;
+  // normalise and map through the right reflectors: vectors c = g + 32 u,
+  // lane gl holds entries j = gl + 16 t
+  double vv[kVecPerGroup][kRR];
+#pragma unroll
+  for (int u = 0; u < kVecPerGroup; ++u) {
+    const int c = g + kGroups * u;
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < kRR; ++t) {
+      const int j = gl + 16 * t;
+      vv[u][t] = (c < r && j < q) ? other[j + (int64_t)c * q] : 0.0;
+      s += vv[u][t] * vv[u][t];
+    }
+    s = group_sum16(s);
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+#pragma unroll
+    for (int t = 0; t < kRR; ++t) vv[u][t] *= inv;
+  }
+  if (g < r) {
+    for (int k = q - 2; k >= 0; --k) {
+      const double tau = L.tauR[k];
+      if (tau == 0.0) continue;
+      const double* vs = L.vstore + vs_off(k, q);
+      double w[kRR];
+#pragma unroll
+      for (int t = 0; t < kRR; ++t) {
+        const int j = gl + 16 * t;
+        w[t] = (j > k && j < q) ? vs[j - k - 1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kVecPerGroup; ++u) {
+        if (g + kGroups * u < r) {
+          double dot = 0.0;
+#pragma unroll
+          for (int t = 0; t < kRR; ++t) dot += w[t] * vv[u][t];
+          dot = tau * group_sum16(dot);
+#pragma unroll
+          for (int t = 0; t < kRR; ++t) vv[u][t] -= w[t] * dot;
+        }
+      }
+    }
+  }
+  __syncthreads();   // reflectors consumed: vstore becomes the vector store X (q x r)
+  double* X = L.vstore;
+#pragma unroll
+  for (int u = 0; u < kVecPerGroup; ++u) {
+    const int c = g + kGroups * u;
+    if (c < r) {
+#pragma unroll
+      for (int t = 0; t < kRR; ++t) {
+        const int j = gl + 16 * t;
+        if (j < q) X[j + c * q] = vv[u][t];
+      }
+    }
+  }
+  __syncthreads();
+  // re-orthogonalise within clusters of close values (one vector at a time)
+  for (int c = 1; c < r; ++c) {
+    int c0 = c;
+    while (c0 > 0 && close_values(sh, c0)) --c0;
+    if (c0 == c) continue;
+    if (g == 0) {
+      double* xc = X + c * q;
+      for (int b = c0; b < c; ++b) {
+        const double* xb = X + b * q;
+        double dot = 0.0;
+        for (int j = gl; j < q; j += 16) dot += xb[j] * xc[j];
+        dot = group_sum16(dot);
+        for (int j = gl; j < q; j += 16) xc[j] -= dot * xb[j];
+      }
+      double s = 0.0;
+      for (int j = gl; j < q; j += 16) s += xc[j] * xc[j];
+      s = group_sum16(s);
+      if (!(s > 1e-2)) {
+        if (gl == 0) L.flag = 1;
+      } else {
+        const double inv = 1.0 / sqrt(s);
+        for (int j = gl; j < q; j += 16) xc[j] *= inv;
+      }
+    }
+    __syncthreads();
+  }
+  if (L.flag) return false;
+  for (int e = tid; e < q * r; e += kRecThreads) basis[e] = X[e];
+  __syncthreads();
+  // other factor: G_orig * basis  (G_orig = D for m >= n, D^T otherwise)
+  const cgdbl* D = (const cgdbl*)it.D;
+  const int n = it.n;
+  for (int o = g; o < p * r; o += kGroups) {
+    const int i = o % p, c = o / p;
+    const double* xb = X + c * q;
+    double s = 0.0;
+    if (!trans) {
+      for (int j = gl; j < n; j += 16) s += D[i + (int64_t)j * it.ldd] * xb[j];
+    } else {
+      const cgdbl* dcol = D + (int64_t)i * it.ldd;
+      for (int j = gl; j < m; j += 16) s += dcol[j] * xb[j];
+    }
+    s = group_sum16(s);
+    if (gl == 0) other[i + (int64_t)c * p] = s;
+  }
+  double kept = 0.0;
+  for (int c = 0; c < r; ++c) kept += sh.sigma[c] * sh.sigma[c];
+  write_meta(it, 2, r, normc * sqrt(kept));
+  return true;
+}
+
+// Left reflector of the pivoted QR on column k of the tile (vector in colk).
+CLR_INLINE void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  const int kj = k >> 5;
+  if (tc == (k & 31)) {
+    double s2 = 0.0, x0p = 0.0;
+#pragma unroll
+    for (int ir = 0; ir < kRR; ++ir)
+#pragma unroll
+      for (int jc = 0; jc < kRC; ++jc)
+        if (jc == kj) {
+          const int i = tr + 16 * ir;
+          const double x = a[ir][jc];
+          if (i > k && i < p) s2 += x * x;
+          if (i == k) x0p = x;
+        }
+    s2 = group_sum16(s2);
+    const double x0 = group_sum16(x0p);
+    double t = 0.0, beta = x0, scal = 0.0;
+    if (s2 > 0.0) {
+      beta = -copysign(sqrt(x0 * x0 + s2), x0);
+      t = (beta - x0) / beta;
+      scal = 1.0 / (x0 - beta);
+    }
+#pragma unroll
+    for (int ir = 0; ir < kRR; ++ir)
+#pragma unroll
+      for (int jc = 0; jc < kRC; ++jc)
+        if (jc == kj) {
+          const int i = tr + 16 * ir;
+          if (i >= k && i < p) {
+            L.colk[i] = (i == k) ? 1.0 : a[ir][jc] * scal;
+            a[ir][jc] = (i == k) ? beta : 0.0;
+          }
+        }
+    if (tr == 0) L.tauL = t;
+  }
+  __syncthreads();
+  const double t = L.tauL;
+  if (t == 0.0) return;
+  double vr[kRR];
+#pragma unroll
+  for (int ir = 0; ir < kRR; ++ir) {
+    const int i = tr + 16 * ir;
+    vr[ir] = (i >= k && i < p) ? L.colk[i] : 0.0;
+  }
+#pragma unroll
+  for (int jc = 0; jc < kRC; ++jc) {
+    const int j = tc + 32 * jc;
+    if (j > k && j < q) {
+      double w = 0.0;
+#pragma unroll
+      for (int ir = 0; ir < kRR; ++ir) w += vr[ir] * a[ir][jc];
+      w = group_sum16(w);
+#pragma unroll
+      for (int ir = 0; ir < kRR; ++ir) a[ir][jc] -= t * vr[ir] * w;
+    }
+  }
 }
 
 // Pivoted Householder QR of the register-resident G; stops at the numerical
@@ -853,8 +1290,8 @@ CLR_INLINE int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh
         for (int jc = 0; jc < kRC; ++jc) {
           const int i = tr + 16 * ir;
           if (i < p) {
-            if (tc == (k & 31) && jc == kj) L.colA[i] = a[ir][jc];
-            if (tc == (piv & 31) && jc == pj) L.colB[i] = a[ir][jc];
+            if (tc == (k & 31) && jc == kj) L.u.qr.colA[i] = a[ir][jc];
+            if (tc == (piv & 31) && jc == pj) L.u.qr.colB[i] = a[ir][jc];
           }
         }
       __syncthreads();
@@ -864,8 +1301,8 @@ CLR_INLINE int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh
         for (int jc = 0; jc < kRC; ++jc) {
           const int i = tr + 16 * ir;
           if (i < p) {
-            if (tc == (k & 31) && jc == kj) a[ir][jc] = L.colB[i];
-            if (tc == (piv & 31) && jc == pj) a[ir][jc] = L.colA[i];
+            if (tc == (k & 31) && jc == kj) a[ir][jc] = L.u.qr.colB[i];
+            if (tc == (piv & 31) && jc == pj) a[ir][jc] = L.u.qr.colA[i];
           }
         }
       if (tid == 0) {
@@ -899,14 +1336,6 @@ CLR_INLINE void reg_store_rt(const RegTile& a, int q, int kq, PT* X, int64_t ldx
       if (i < kq && j < q) X[j + (int64_t)i * ldx] = (j >= i) ? a[ir][jc] : 0.0;
     }
   __syncthreads();
-}
-
-CLR_INLINE void write_meta(const RecItem& it, int kind, int rank, double norm) {
-  if (threadIdx.x == 0) {
-    *it.kind_out = kind;
-    *it.rank_out = rank;
-    *it.norm_out = norm;
-  }
 }
 
 CLR_INLINE void copy_dense_out(const RecItem& it) {
@@ -1095,7 +1524,8 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
     RegLds& L = *reinterpret_cast<RegLds*>(lds);
     RegTile a;
     reg_load(a, it.D, it.ldd, trans, 1.0 / normc, p, q);
-    const int r = reg_singular_values(a, p, q, tol, L, sh);
+    reg_bidiag(a, p, q, L);
+    const int r = reg_decide(q, tol, L, sh);
     if (r == 0) {
       write_meta(it, 0, 0, 0.0);
       return;
@@ -1105,7 +1535,8 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
       write_meta(it, 1, q, normc);
       return;
     }
-    // truncated: singular vectors from pivoted QR + Jacobi on R^T
+    // truncated: singular vectors from the bidiagonal, else pivoted QR + Jacobi on R^T
+    if (reg_vectors(it, p, q, trans, r, normc, L, sh)) return;
     reg_load(a, it.D, it.ldd, trans, 1.0 / normc, p, q);
     const int kc = reg_pivoted_qr(a, p, q, L, sh);
     // odd leading dimension: the columns of one wave start in different LDS banks
