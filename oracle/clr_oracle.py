@@ -75,6 +75,7 @@ __all__ = [
     "sqrt_inv",
     "gemm_vjp",
     "sqrt_inv_vjp",
+    "structure_mask",
     "GemmStats",
 ]
 

@@ -21,7 +21,7 @@ from ._abi import (CLR_FP64, CLR_MIXED, CLR_SCREEN_ABS, CLR_SCREEN_AREA, ClrErro
 
 __all__ = [
     "Context", "CLRMatrix", "ClrError", "GemmStats", "SqrtInvStats", "lib", "LIB_PATH",
-    "CLR_FP64", "CLR_MIXED",
+    "CLR_FP64", "CLR_MIXED", "gemm_dense", "sqrt_inv_dense",
 ]
 
 
@@ -167,6 +167,39 @@ class Context:
         self._check(rc)
         return CLRMatrix(self, h), st
 
+    # -- adjoints -------------------------------------------------------------
+    def gemm_backward(self, A: "CLRMatrix", B: "CLRMatrix", dC, alpha: float = 1.0,
+                      want_a: bool = True, want_b: bool = True):
+        """(alpha dC B^T, alpha A^T dC) restricted to the stored blocks of A and B."""
+        torch = _torch()
+        dcb, ldc = _col_major(dC)
+        dA = torch.empty((A.cols, A.rows), dtype=torch.float64, device="cuda") if want_a else None
+        dB = torch.empty((B.cols, B.rows), dtype=torch.float64, device="cuda") if want_b else None
+        self._check(lib.clr_gemm_backward(
+            self._h, A._h, B._h, C.c_double(alpha), C.c_void_p(dcb.data_ptr()), C.c_int64(ldc),
+            C.c_void_p(dA.data_ptr()) if dA is not None else None, C.c_int64(A.rows),
+            C.c_void_p(dB.data_ptr()) if dB is not None else None, C.c_int64(B.rows)))
+        return (dA.t() if dA is not None else None, dB.t() if dB is not None else None)
+
+    def sqrt_inv_backward(self, S: "CLRMatrix", Wbar, iters: int, checkpoint_every: int,
+                          tol: float, eps_sp: float, alpha: float = 0.0, screen="abs",
+                          precision="fp64", split: int = 0):
+        """dS of sum(Wbar * W), W from `iters` unrolled iterations; returns (dS, W)."""
+        torch = _torch()
+        o = SqrtInvOpts()
+        o.g = _gemm_opts(tol, eps_sp, screen, precision, split, 1.0)
+        o.alpha = float(alpha)
+        o.conv_tol = 0.0
+        o.max_iter = int(iters)
+        o.fixed_iters = int(iters)
+        wb, ld = _col_major(Wbar)
+        dS = torch.empty((S.cols, S.rows), dtype=torch.float64, device="cuda")
+        h = C.c_void_p()
+        self._check(lib.clr_sqrt_inv_backward(self._h, S._h, C.byref(o), int(iters),
+                                              int(checkpoint_every), C.c_void_p(wb.data_ptr()),
+                                              C.c_void_p(dS.data_ptr()), C.c_int64(ld), C.byref(h)))
+        return dS.t(), CLRMatrix(self, h)
+
     def identity_residual(self, X: "CLRMatrix") -> float:
         out = C.c_double()
         self._check(lib.clr_identity_residual(self._h, X._h, C.byref(out)))
@@ -237,3 +270,64 @@ class CLRMatrix:
         self.ctx._check(lib.clr_get_block(self.ctx._h, self._h, I, J, C.c_void_p(u.data_ptr()),
                                           C.c_void_p(v.data_ptr())))
         return ("L", u.t(), v.t())
+
+
+# ---------------------------------------------------------------------------
+# torch.autograd entry points.  The differentiable inputs are the dense forms
+# of the CLR operands (the matrices the handles represent); gradients are
+# restricted to the operands' stored blocks, and truncation is treated as the
+# identity in the backward pass.
+# ---------------------------------------------------------------------------
+
+_FN = {}
+
+
+def _functions():
+    if _FN:
+        return _FN
+    torch = _torch()
+
+    class GemmFn(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, a_dense, b_dense, ctx, A, B, kw):
+            Cm = ctx.gemm(A, B, **kw)
+            fctx.clr = (ctx, A, B, float(kw.get("alpha", 1.0)))
+            return Cm.to_dense().contiguous()
+
+        @staticmethod
+        def backward(fctx, gC):
+            ctx, A, B, alpha = fctx.clr
+            dA, dB = ctx.gemm_backward(A, B, gC.contiguous(), alpha, fctx.needs_input_grad[0],
+                                       fctx.needs_input_grad[1])
+            return dA, dB, None, None, None, None
+
+    class SqrtInvFn(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, s_dense, ctx, S, iters, checkpoint_every, kw):
+            W, _st = ctx.sqrt_inv(S, fixed_iters=iters, **kw)
+            fctx.clr = (ctx, S, iters, checkpoint_every, kw)
+            return W.to_dense().contiguous()
+
+        @staticmethod
+        def backward(fctx, gW):
+            ctx, S, iters, every, kw = fctx.clr
+            dS, _W = ctx.sqrt_inv_backward(S, gW.contiguous(), iters, every, **kw)
+            return dS, None, None, None, None, None
+
+    _FN["gemm"] = GemmFn
+    _FN["sqrt_inv"] = SqrtInvFn
+    return _FN
+
+
+def gemm_dense(ctx: Context, A: CLRMatrix, B: CLRMatrix, a_dense, b_dense, **kw):
+    """Dense C = A B (CLR product) differentiable w.r.t. a_dense / b_dense.
+
+    a_dense and b_dense stand for the matrices A and B represent (their values
+    are not read); gradients come from the library's adjoint."""
+    return _functions()["gemm"].apply(a_dense, b_dense, ctx, A, B, kw)
+
+
+def sqrt_inv_dense(ctx: Context, S: CLRMatrix, s_dense, iters: int, checkpoint_every: int = 5,
+                   **kw):
+    """Dense W = S^-1/2 after `iters` unrolled iterations, differentiable w.r.t. s_dense."""
+    return _functions()["sqrt_inv"].apply(s_dense, ctx, S, iters, checkpoint_every, kw)

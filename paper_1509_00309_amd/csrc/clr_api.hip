@@ -637,7 +637,8 @@ extern "C" clr_status clr_to_dense(clr_context* ctx, const clr_matrix* m, double
 namespace {
 
 clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
-                     const clr_gemm_opts* o, clr_matrix** Cout, clr_gemm_stats* st) {
+                     const clr_gemm_opts* o, clr_matrix** Cout, clr_gemm_stats* st,
+                     const clr_matrix* mask = nullptr) {
   *Cout = nullptr;
   if (A->cs != B->rs)
     return fail(ctx, CLR_ERR_SHAPE, "column blocking of A differs from row blocking of B");
@@ -649,7 +650,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
     return code;
   };
   hipStream_t stream = ctx->stream;
-  PlanParams P;
+  PlanParams P{};
   P.A = A->view();
   P.B = B->view();
   P.nrb = A->nrb;
@@ -661,6 +662,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   P.tol = o->tol;
   P.square = (A->rs == B->cs) ? 1 : 0;
   P.max_item = max_item(o);
+  P.mask_kind = mask ? mask->d_kind : nullptr;
   const int64_t npairs = (int64_t)P.nrb * P.ncb;
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = ensure(ctx->cnt, sizeof(int64_t) * kNumCounters * npairs);
@@ -1172,17 +1174,321 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
 // Adjoints
 // ---------------------------------------------------------------------------
 
+namespace {
+
+// All-dense CLR matrix from a dense device matrix (ld); blocks outside `mask`
+// (if given) and exactly-zero blocks become zero blocks.
+clr_status dense_to_clr(clr_context* ctx, const double* D, int64_t ld, const std::vector<int>& rs,
+                        const std::vector<int>& cs, const clr_matrix* mask, clr_matrix** out) {
+  clr_matrix* M = nullptr;
+  clr_status s = alloc_matrix(ctx, rs, cs, &M);
+  if (s != CLR_OK) return s;
+  hipError_t e = launch_from_dense(M->view(), M->arena, M->d_kind, M->d_rank, M->d_norm, D, ld,
+                                   mask ? mask->d_kind : nullptr, ctx->stream);
+  if (e != hipSuccess) {
+    free_matrix(M);
+    return fail(ctx, CLR_ERR_HIP, "dense ingest: %s", hipGetErrorString(e));
+  }
+  *out = M;
+  return CLR_OK;
+}
+
+clr_status transpose_clr(clr_context* ctx, const clr_matrix* A, clr_matrix** out) {
+  clr_matrix* T = nullptr;
+  clr_status s = alloc_matrix(ctx, A->cs, A->rs, &T);
+  if (s != CLR_OK) return s;
+  hipError_t e = launch_transpose(A->view(), T->view(), T->arena, T->d_kind, T->d_rank, T->d_norm,
+                                  ctx->stream);
+  if (e != hipSuccess) {
+    free_matrix(T);
+    return fail(ctx, CLR_ERR_HIP, "transpose: %s", hipGetErrorString(e));
+  }
+  *out = T;
+  return CLR_OK;
+}
+
+// Exact (untruncated, unscreened) products and sums for cotangents.
+clr_gemm_opts exact_opts(const clr_gemm_opts* g, double alpha) {
+  clr_gemm_opts o{};
+  o.tol = 0.0;
+  o.eps_sp = 0.0;
+  o.screen = CLR_SCREEN_ABS;
+  o.precision = g ? g->precision : CLR_FP64;
+  o.split = g ? g->split : 0;
+  o.alpha = alpha;
+  return o;
+}
+
+// Owning handle list: frees every matrix on scope exit.
+struct Owned {
+  std::vector<clr_matrix*> v;
+  clr_matrix* keep(clr_matrix* m) {
+    v.push_back(m);
+    return m;
+  }
+  void drop(clr_matrix* m) {
+    for (auto& x : v)
+      if (x == m) {
+        free_matrix(x);
+        x = nullptr;
+      }
+  }
+  ~Owned() {
+    for (auto* m : v) free_matrix(m);
+  }
+};
+
+// P = a X + b Y exactly, where either operand may be absent (NULL = zero).
+clr_status exact_sum(clr_context* ctx, double a, const clr_matrix* X, double b, const clr_matrix* Y,
+                     const clr_gemm_opts* g, clr_matrix** out) {
+  *out = nullptr;
+  const clr_gemm_opts o = exact_opts(g, 1.0);
+  if (!X && !Y) return CLR_OK;
+  if (!X) return clr_axpby(ctx, b, Y, 0.0, nullptr, 0.0, &o, out);
+  return clr_axpby(ctx, a, X, Y ? b : 0.0, Y, 0.0, &o, out);
+}
+
+// alpha * L * R exactly (NULL operand = zero product).
+clr_status exact_product(clr_context* ctx, const clr_matrix* L, const clr_matrix* R, double alpha,
+                         const clr_gemm_opts* g, clr_matrix** out, double* flops,
+                         const clr_matrix* mask = nullptr) {
+  *out = nullptr;
+  if (!L || !R) return CLR_OK;
+  const clr_gemm_opts o = exact_opts(g, alpha);
+  clr_gemm_stats gs{};
+  clr_status s = gemm_impl(ctx, L, R, &o, out, &gs, mask);
+  if (flops) *flops += gs.flops_products;
+  return s;
+}
+
+clr_status write_dense(clr_context* ctx, const clr_matrix* M, const std::vector<int>& rs,
+                       const std::vector<int>& cs, double* out, int64_t ld) {
+  if (M) {
+    HIP_TRY(ctx, launch_to_dense(M->view(), out, ld, ctx->stream));
+  } else {
+    int64_t rows = 0, cols = 0;
+    for (int v : rs) rows += v;
+    for (int v : cs) cols += v;
+    HIP_TRY(ctx, hipMemset2DAsync(out, sizeof(double) * ld, 0, sizeof(double) * rows, cols, ctx->stream));
+  }
+  return CLR_OK;
+}
+
+}  // namespace
+
 extern "C" clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
                                         double alpha, const double* dC, int64_t ldc, double* dA,
                                         int64_t lda, double* dB, int64_t ldb) {
-  (void)A; (void)B; (void)alpha; (void)dC; (void)ldc; (void)dA; (void)lda; (void)dB; (void)ldb;
-  return fail(ctx, CLR_ERR_INVALID_ARG, "clr_gemm_backward: not available in this build");
+  if (!ctx || !A || !B || !dC) return CLR_ERR_INVALID_ARG;
+  if (A->cs != B->rs)
+    return fail(ctx, CLR_ERR_SHAPE, "column blocking of A differs from row blocking of B");
+  if (!std::isfinite(alpha)) return fail(ctx, CLR_ERR_INVALID_ARG, "alpha must be finite");
+  if (ldc < A->rows || (dA && lda < A->rows) || (dB && ldb < B->rows))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "leading dimension smaller than the row count");
+  Owned own;
+  clr_matrix* G = nullptr;
+  clr_status s = dense_to_clr(ctx, dC, ldc, A->rs, B->cs, nullptr, &G);
+  if (s != CLR_OK) return s;
+  own.keep(G);
+  const clr_gemm_opts g = exact_opts(nullptr, alpha);
+  if (dA) {
+    // dA = alpha dC B^T on A's stored blocks
+    clr_matrix *Bt = nullptr, *P = nullptr;
+    if ((s = transpose_clr(ctx, B, &Bt)) != CLR_OK) return s;
+    own.keep(Bt);
+    if ((s = exact_product(ctx, G, Bt, alpha, &g, &P, nullptr, A)) != CLR_OK) return s;
+    own.keep(P);
+    if ((s = write_dense(ctx, P, A->rs, A->cs, dA, lda)) != CLR_OK) return s;
+  }
+  if (dB) {
+    // dB = alpha A^T dC on B's stored blocks
+    clr_matrix *At = nullptr, *P = nullptr;
+    if ((s = transpose_clr(ctx, A, &At)) != CLR_OK) return s;
+    own.keep(At);
+    if ((s = exact_product(ctx, At, G, alpha, &g, &P, nullptr, B)) != CLR_OK) return s;
+    own.keep(P);
+    if ((s = write_dense(ctx, P, B->rs, B->cs, dB, ldb)) != CLR_OK) return s;
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return CLR_OK;
 }
 
+// Reverse of the iteration of Sec. 4.2, Eqs. (8)-(11), with alpha held
+// constant and truncation treated as the identity (straight-through):
+//   Zb_K = sqrt(alpha) Wbar, Yb_K = 0; for n = K-1 .. 0:
+//   Tb = Z_n^T Zb + Yb Y_n^T
+//   Xb = -(10/8) Tb + (3/8)(Tb X_n^T + X_n^T Tb)
+//   Zb <- Zb T_n^T + alpha Y_n^T Xb,   Yb <- T_n^T Yb + alpha Xb Z_n^T
+// dS = Yb_0 on S's stored blocks.  Forward iterates are kept at checkpoints
+// and recomputed one segment at a time.
 extern "C" clr_status clr_sqrt_inv_backward(clr_context* ctx, const clr_matrix* S,
-                                            const clr_sqrtinv_opts* opts, int iters,
+                                            const clr_sqrtinv_opts* o, int iters,
                                             int checkpoint_every, const double* Wbar, double* dS,
-                                            int64_t ld, clr_matrix** W) {
-  (void)S; (void)opts; (void)iters; (void)checkpoint_every; (void)Wbar; (void)dS; (void)ld; (void)W;
-  return fail(ctx, CLR_ERR_INVALID_ARG, "clr_sqrt_inv_backward: not available in this build");
+                                            int64_t ld, clr_matrix** Wout) {
+  if (!ctx || !S || !o || !Wbar || !dS) return CLR_ERR_INVALID_ARG;
+  if (Wout) *Wout = nullptr;
+  clr_status s = check_opts(ctx, &o->g);
+  if (s != CLR_OK) return s;
+  if (!S->square_blocked()) return fail(ctx, CLR_ERR_SHAPE, "S must be square-blocked");
+  if (iters < 1 || checkpoint_every < 1 || !(o->alpha >= 0.0))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "bad iteration options");
+  if (ld < S->rows) return fail(ctx, CLR_ERR_INVALID_ARG, "ld < N");
+  double alpha = o->alpha;
+  if (alpha == 0.0) {
+    HostMeta h;
+    if ((s = fetch_meta(ctx, S, h)) != CLR_OK) return s;
+    double worst = 0.0;
+    for (int I = 0; I < S->nrb; ++I) {
+      double row = 0.0;
+      for (int J = 0; J < S->ncb; ++J)
+        if (h.kind[(size_t)I * S->ncb + J]) row += h.norm[(size_t)I * S->ncb + J];
+      worst = std::max(worst, row);
+    }
+    if (!(worst > 0.0)) return fail(ctx, CLR_ERR_INVALID_ARG, "S has no nonzero blocks");
+    alpha = 1.0 / worst;
+  }
+  clr_gemm_opts g = o->g;
+  g.alpha = 1.0;
+  clr_gemm_opts ga = g;
+  ga.alpha = alpha;
+  // one forward step from (Y, Z): X, T, and the next pair
+  auto step = [&](const clr_matrix* Y, const clr_matrix* Z, clr_matrix** X, clr_matrix** T,
+                  clr_matrix** Yn, clr_matrix** Zn) -> clr_status {
+    clr_matrix* Q = nullptr;
+    clr_status r = gemm_impl(ctx, Y, Z, &ga, X, nullptr);
+    if (r == CLR_OK) r = gemm_impl(ctx, *X, *X, &g, &Q, nullptr);
+    if (r == CLR_OK) r = clr_axpby(ctx, -10.0 / 8.0, *X, 3.0 / 8.0, Q, 15.0 / 8.0, &g, T);
+    free_matrix(Q);
+    if (r == CLR_OK) r = gemm_impl(ctx, Z, *T, &g, Zn, nullptr);
+    if (r == CLR_OK) r = gemm_impl(ctx, *T, Y, &g, Yn, nullptr);
+    return r;
+  };
+  Owned own;
+  // forward with checkpoints of (Y_n, Z_n) at n = 0, c, 2c, ...
+  const int K = iters, c = checkpoint_every;
+  std::vector<clr_matrix*> ckY((K + c - 1) / c, nullptr), ckZ((K + c - 1) / c, nullptr);
+  clr_matrix *Z = nullptr, *Y = nullptr;
+  if ((s = identity_matrix(ctx, S->rs, &Z)) != CLR_OK) return s;
+  own.keep(Z);
+  if ((s = copy_matrix(ctx, S, &Y)) != CLR_OK) return s;
+  own.keep(Y);
+  for (int n = 0; n < K; ++n) {
+    if (n % c == 0) {
+      ckY[n / c] = Y;
+      ckZ[n / c] = Z;
+    }
+    clr_matrix *X = nullptr, *T = nullptr, *Yn = nullptr, *Zn = nullptr;
+    s = step(Y, Z, &X, &T, &Yn, &Zn);
+    free_matrix(X);
+    free_matrix(T);
+    if (Yn) own.keep(Yn);
+    if (Zn) own.keep(Zn);
+    if (s != CLR_OK) return s;
+    if (n % c != 0) {   // not a checkpoint: the previous pair is no longer needed
+      own.drop(Y);
+      own.drop(Z);
+    }
+    Y = Yn;
+    Z = Zn;
+  }
+  if (Wout) {
+    clr_matrix* W = nullptr;
+    if ((s = scaled_copy(ctx, Z, sqrt(alpha), &W)) != CLR_OK) return s;
+    *Wout = W;
+  }
+  own.drop(Y);
+  own.drop(Z);
+  auto fail_out = [&](clr_status code) {
+    if (Wout && *Wout) {
+      free_matrix(*Wout);
+      *Wout = nullptr;
+    }
+    return code;
+  };
+  // cotangents (NULL = zero)
+  clr_matrix* Zb = nullptr;
+  clr_matrix* Yb = nullptr;
+  {
+    clr_matrix* Wb = nullptr;
+    if ((s = dense_to_clr(ctx, Wbar, ld, S->rs, S->cs, nullptr, &Wb)) != CLR_OK) return fail_out(s);
+    HIP_TRY(ctx, launch_scale(Wb->view(), Wb->arena, Wb->d_norm, sqrt(alpha), ctx->stream));
+    Zb = Wb;
+  }
+  Owned cot;
+  cot.keep(Zb);
+  for (int seg = (K - 1) / c; seg >= 0; --seg) {
+    const int n0 = seg * c, n1 = std::min(K, n0 + c);
+    // recompute the segment's iterates
+    Owned segown;
+    std::vector<clr_matrix*> Ys, Zs, Xs, Ts;
+    const clr_matrix* Yc = ckY[seg];
+    const clr_matrix* Zc = ckZ[seg];
+    for (int n = n0; n < n1; ++n) {
+      clr_matrix *X = nullptr, *T = nullptr, *Yn = nullptr, *Zn = nullptr;
+      s = step(Yc, Zc, &X, &T, &Yn, &Zn);
+      for (clr_matrix* mm : {X, T, Yn, Zn})
+        if (mm) segown.keep(mm);
+      if (s != CLR_OK) return fail_out(s);
+      Ys.push_back(const_cast<clr_matrix*>(Yc));
+      Zs.push_back(const_cast<clr_matrix*>(Zc));
+      Xs.push_back(X);
+      Ts.push_back(T);
+      Yc = Yn;
+      Zc = Zn;
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      const int i = n - n0;
+      Owned tmp;
+      clr_matrix *Zt = nullptr, *Yt = nullptr, *Xt = nullptr, *Tt = nullptr;
+      if ((s = transpose_clr(ctx, Zs[i], &Zt)) != CLR_OK) return fail_out(s);
+      tmp.keep(Zt);
+      if ((s = transpose_clr(ctx, Ys[i], &Yt)) != CLR_OK) return fail_out(s);
+      tmp.keep(Yt);
+      if ((s = transpose_clr(ctx, Xs[i], &Xt)) != CLR_OK) return fail_out(s);
+      tmp.keep(Xt);
+      if ((s = transpose_clr(ctx, Ts[i], &Tt)) != CLR_OK) return fail_out(s);
+      tmp.keep(Tt);
+      clr_matrix *P1 = nullptr, *P2 = nullptr, *Tb = nullptr;
+      if ((s = exact_product(ctx, Zt, Zb, 1.0, &g, &P1, nullptr)) != CLR_OK) return fail_out(s);
+      if (P1) tmp.keep(P1);
+      if ((s = exact_product(ctx, Yb, Yt, 1.0, &g, &P2, nullptr)) != CLR_OK) return fail_out(s);
+      if (P2) tmp.keep(P2);
+      if ((s = exact_sum(ctx, 1.0, P1, 1.0, P2, &g, &Tb)) != CLR_OK) return fail_out(s);
+      if (Tb) tmp.keep(Tb);
+      clr_matrix *Q1 = nullptr, *Q2 = nullptr, *Q = nullptr, *Xb = nullptr;
+      if ((s = exact_product(ctx, Tb, Xt, 1.0, &g, &Q1, nullptr)) != CLR_OK) return fail_out(s);
+      if (Q1) tmp.keep(Q1);
+      if ((s = exact_product(ctx, Xt, Tb, 1.0, &g, &Q2, nullptr)) != CLR_OK) return fail_out(s);
+      if (Q2) tmp.keep(Q2);
+      if ((s = exact_sum(ctx, 1.0, Q1, 1.0, Q2, &g, &Q)) != CLR_OK) return fail_out(s);
+      if (Q) tmp.keep(Q);
+      if ((s = exact_sum(ctx, -10.0 / 8.0, Tb, 3.0 / 8.0, Q, &g, &Xb)) != CLR_OK) return fail_out(s);
+      if (Xb) tmp.keep(Xb);
+      clr_matrix *Z1 = nullptr, *Z2 = nullptr, *Zbn = nullptr;
+      if ((s = exact_product(ctx, Zb, Tt, 1.0, &g, &Z1, nullptr)) != CLR_OK) return fail_out(s);
+      if (Z1) tmp.keep(Z1);
+      if ((s = exact_product(ctx, Yt, Xb, alpha, &g, &Z2, nullptr)) != CLR_OK) return fail_out(s);
+      if (Z2) tmp.keep(Z2);
+      if ((s = exact_sum(ctx, 1.0, Z1, 1.0, Z2, &g, &Zbn)) != CLR_OK) return fail_out(s);
+      clr_matrix *Y1 = nullptr, *Y2 = nullptr, *Ybn = nullptr;
+      if ((s = exact_product(ctx, Tt, Yb, 1.0, &g, &Y1, nullptr)) != CLR_OK) return fail_out(s);
+      if (Y1) tmp.keep(Y1);
+      if ((s = exact_product(ctx, Xb, Zt, alpha, &g, &Y2, nullptr)) != CLR_OK) return fail_out(s);
+      if (Y2) tmp.keep(Y2);
+      if ((s = exact_sum(ctx, 1.0, Y1, 1.0, Y2, &g, &Ybn)) != CLR_OK) {
+        free_matrix(Zbn);
+        return fail_out(s);
+      }
+      if (Zb) cot.drop(Zb);
+      if (Yb) cot.drop(Yb);
+      Zb = Zbn;
+      Yb = Ybn;
+      if (Zb) cot.keep(Zb);
+      if (Yb) cot.keep(Yb);
+    }
+  }
+  if ((s = write_dense(ctx, Yb, S->rs, S->cs, dS, ld)) != CLR_OK) return fail_out(s);
+  HIP_TRY(ctx, launch_mask_dense(S->view(), dS, ld, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return CLR_OK;
 }

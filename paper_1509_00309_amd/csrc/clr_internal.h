@@ -151,6 +151,7 @@ struct PlanParams {
   double tol;
   int square;     // C's row and column blockings are identical
   int max_item;   // largest output tile edge of the grouped GEMM
+  const int* mask_kind;   // optional: only blocks stored in this kind table are computed
 };
 
 struct FillParams {
@@ -207,6 +208,11 @@ hipError_t launch_scale(const MatView& M, double* arena, double* norm, double sc
 hipError_t launch_identity_terms(const MatView& M, double* out, hipStream_t s);
 hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
+hipError_t launch_from_dense(const MatView& M, double* arena, int* kind, int* rank, double* norm,
+                             const double* D, int64_t ld, const int* mask_kind, hipStream_t s);
+hipError_t launch_transpose(const MatView& A, const MatView& T, double* tarena, int* tkind,
+                            int* trank, double* tnorm, hipStream_t s);
+hipError_t launch_mask_dense(const MatView& M, double* out, int64_t ld, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
 }  // namespace clr

@@ -1,7 +1,8 @@
 // Elementwise and per-block helper kernels of the CLR library: ingest of
 // caller factors into the slot arena with exact block norms, expansion to a
-// dense matrix, scaling, the blockwise terms of ||X - I||_F, and the dense
-// part of the blockwise combination a X + b Y + c I.
+// dense matrix, scaling, the blockwise terms of ||X - I||_F, the dense part of
+// the blockwise combination a X + b Y + c I, and the blockwise transpose,
+// dense ingest and structure masking used by the adjoints.
 #include "clr_internal.h"
 
 namespace clr {
@@ -150,6 +151,108 @@ __global__ void k_fill_f64(double* p, double v, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint helpers ------------------------------------------------------------
+
+// Dense device matrix D (column-major, ld) -> CLR matrix with all blocks dense:
+// kind 1 where the block is nonzero (and, if mask_kind is given, the mask block
+// is stored), kind 0 otherwise; exact block norms.
+__global__ __launch_bounds__(256) void k_from_dense(MatView M, double* arena, int* kind, int* rank,
+                                                    double* norm, const double* D, int64_t ld,
+                                                    const int* mask_kind) {
+  __shared__ double red[256];
+  const int blk = blockIdx.x;
+  const int I = blk / M.ncb, J = blk % M.ncb;
+  const int m = M.roff[I + 1] - M.roff[I];
+  const int n = M.coff[J + 1] - M.coff[J];
+  const bool keep = mask_kind == nullptr || mask_kind[blk] != 0;
+  double* dst = arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  const double* src = D + M.roff[I] + (int64_t)M.coff[J] * ld;
+  double part = 0.0;
+  if (keep) {
+    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
+      const int i = (int)(e % m), j = (int)(e / m);
+      const double v = src[i + (int64_t)j * ld];
+      dst[e] = v;
+      part += v * v;
+    }
+  }
+  const double s = wg_sum(part, red);
+  if (threadIdx.x == 0) {
+    const bool nz = keep && s > 0.0;
+    kind[blk] = nz ? 1 : 0;
+    rank[blk] = nz ? (m < n ? m : n) : 0;
+    norm[blk] = nz ? sqrt(s) : 0.0;
+  }
+}
+
+// T = A^T blockwise: block (J, I) of T is (A_IJ)^T; a dense block is
+// transposed, a factored block U V^T becomes V U^T (factors swapped).
+__global__ __launch_bounds__(256) void k_transpose(MatView A, MatView T, double* tarena, int* tkind,
+                                                   int* trank, double* tnorm) {
+  const int blk = blockIdx.x;
+  const int I = blk / A.ncb, J = blk % A.ncb;
+  const int tb = J * A.nrb + I;
+  const int m = A.roff[I + 1] - A.roff[I];
+  const int n = A.coff[J + 1] - A.coff[J];
+  const int kind = A.kind[blk];
+  if (threadIdx.x == 0) {
+    tkind[tb] = kind;
+    trank[tb] = A.rank[blk];
+    tnorm[tb] = A.norm[blk];
+  }
+  if (kind == 0) return;
+  const double* src = A.arena + slot_offset(A.roff, A.coff, A.ncols, I, J);
+  double* dst = tarena + slot_offset(T.roff, T.coff, T.ncols, J, I);
+  if (kind == 1) {
+    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
+      const int j = (int)(e % n), i = (int)(e / n);   // dst is n x m, ld n
+      dst[e] = src[i + (int64_t)j * m];
+    }
+  } else {
+    const int r = A.rank[blk];
+    const double* u = src;                      // m x r
+    const double* v = src + (int64_t)m * r;     // n x r
+    for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += 256) dst[e] = v[e];
+    for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += 256) dst[(int64_t)n * r + e] = u[e];
+  }
+}
+
+// Zero the blocks of a dense matrix (ld) whose block in the mask is not stored.
+__global__ __launch_bounds__(256) void k_mask_dense(MatView M, double* out, int64_t ld) {
+  const int blk = blockIdx.x;
+  if (M.kind[blk] != 0) return;
+  const int I = blk / M.ncb, J = blk % M.ncb;
+  const int m = M.roff[I + 1] - M.roff[I];
+  const int n = M.coff[J + 1] - M.coff[J];
+  double* dst = out + M.roff[I] + (int64_t)M.coff[J] * ld;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    dst[i + (int64_t)j * ld] = 0.0;
+  }
+}
+
+hipError_t launch_from_dense(const MatView& M, double* arena, int* kind, int* rank, double* norm,
+                             const double* D, int64_t ld, const int* mask_kind, hipStream_t s) {
+  const int nb = M.nrb * M.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_from_dense, dim3(nb), dim3(256), 0, s, M, arena, kind, rank, norm, D, ld,
+                     mask_kind);
+  return hipGetLastError();
+}
+hipError_t launch_transpose(const MatView& A, const MatView& T, double* tarena, int* tkind,
+                            int* trank, double* tnorm, hipStream_t s) {
+  const int nb = A.nrb * A.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose, dim3(nb), dim3(256), 0, s, A, T, tarena, tkind, trank, tnorm);
+  return hipGetLastError();
+}
+hipError_t launch_mask_dense(const MatView& M, double* out, int64_t ld, hipStream_t s) {
+  const int nb = M.nrb * M.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mask_dense, dim3(nb), dim3(256), 0, s, M, out, ld);
+  return hipGetLastError();
+}
+
 hipError_t launch_ingest(const MatView& M, double* arena, const double* const* f0,
                          const double* const* f1, double* norm_out, hipStream_t s) {
   const int nb = M.nrb * M.ncb;

@@ -82,7 +82,7 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
   lr_rank_sum = rcat;
   est *= fabs(P.alpha);
   const double tau = P.screen ? P.eps_sp * m * (double)n : P.eps_sp;
-  const bool candidate = nseg > 0;
+  const bool candidate = nseg > 0 && (P.mask_kind == nullptr || P.mask_kind[pair] != 0);
   const bool computed = candidate && est >= tau;
   const bool force = P.square && I == J;
   const int mn = m < n ? m : n;

@@ -283,3 +283,84 @@ def test_mixed_gemm_3d_scaled(ctx, torch):
         err = np.sqrt(np.sum((got - ref) ** 2)) / np.sqrt(np.sum(ref ** 2))
         log(f"  split={split} err={err:.2e}")
         assert err <= 10 * wl.tol
+
+
+# ---------------------------------------------------------------------------
+# Adjoints
+# ---------------------------------------------------------------------------
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("seed", [301, 302])
+def test_gemm_backward_matches_oracle(ctx, torch, seed):
+    """dA = alpha dC B^T, dB = alpha A^T dC on the stored blocks, all block kinds."""
+    log(f"gemm backward seed={seed}")
+    rs, ks, cs = [40, 17, 64, 33], [25, 48, 9, 70, 16], [31, 64, 12]
+    ra = random_blocks(seed, rs, ks, p_zero=0.3, p_dense=0.4, max_rank=8)
+    rb = random_blocks(seed + 50, ks, cs, p_zero=0.3, p_dense=0.4, max_rank=8)
+    A, B = gpu_from_random(ctx, torch, ra), gpu_from_random(ctx, torch, rb)
+    OA, OB = orc_from_random(ra), orc_from_random(rb)
+    dC = rng_for(seed + 99).standard_normal((sum(rs), sum(cs)))
+    alpha = 0.7
+    dA, dB = ctx.gemm_backward(A, B, torch.from_numpy(dC).cuda(), alpha)
+    rA, rB = orc.gemm_vjp(OA, OB, dC, alpha)
+    eA, eB = _rel(dA.cpu().numpy(), rA), _rel(dB.cpu().numpy(), rB)
+    log(f"  dA err {eA:.2e} dB err {eB:.2e}")
+    assert eA <= FP64_BOUND and eB <= FP64_BOUND
+    # zero blocks of A and B get exactly zero gradient
+    mA, mB = orc.structure_mask(OA), orc.structure_mask(OB)
+    assert np.all(dA.cpu().numpy()[mA == 0] == 0.0) and np.all(dB.cpu().numpy()[mB == 0] == 0.0)
+    only_a, none_b = ctx.gemm_backward(A, B, torch.from_numpy(dC).cuda(), alpha, want_b=False)
+    assert none_b is None and np.array_equal(only_a.cpu().numpy(), dA.cpu().numpy())
+
+
+def test_sqrt_inv_backward_matches_oracle(ctx, torch):
+    """dS through unrolled iterations (straight-through truncation) vs the oracle's VJP."""
+    log("sqrt_inv backward config1")
+    wl = config1()
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    mask = orc.structure_mask(O)
+    Wbar = rng_for(5101).standard_normal(Sd.shape) * mask
+    iters = 6
+    dS, W = ctx.sqrt_inv_backward(S, torch.from_numpy(Wbar).cuda(), iters, 2, wl.tol, wl.eps_sp)
+    ref, Ow, _info = orc.sqrt_inv_vjp(O, Wbar, iters, wl.tol, wl.eps_sp)
+    err = _rel(dS.cpu().numpy(), ref)
+    werr = _rel(W.to_dense().cpu().numpy(), orc.to_dense(Ow))
+    log(f"  dS err {err:.2e}  W err {werr:.2e}")
+    assert werr <= 1e-11
+    assert err <= 1e-11
+    assert np.all(dS.cpu().numpy()[mask == 0] == 0.0)
+    # checkpoint spacing does not change the result (iterates are recomputed exactly)
+    dS1, _ = ctx.sqrt_inv_backward(S, torch.from_numpy(Wbar).cuda(), iters, 1, wl.tol, wl.eps_sp)
+    dS4, _ = ctx.sqrt_inv_backward(S, torch.from_numpy(Wbar).cuda(), iters, 4, wl.tol, wl.eps_sp)
+    assert np.array_equal(dS1.cpu().numpy(), dS.cpu().numpy())
+    assert np.array_equal(dS4.cpu().numpy(), dS.cpu().numpy())
+
+
+def test_autograd_entry_points(ctx, torch):
+    """torch.autograd through gemm_dense / sqrt_inv_dense equals the direct adjoint calls."""
+    import paper_1509_00309_amd as clr
+    log("autograd entry points")
+    rs = [24, 40, 16]
+    ra = random_blocks(401, rs, rs, p_zero=0.2, p_dense=0.5, max_rank=6)
+    rb = random_blocks(402, rs, rs, p_zero=0.2, p_dense=0.5, max_rank=6)
+    A, B = gpu_from_random(ctx, torch, ra), gpu_from_random(ctx, torch, rb)
+    a = A.to_dense().clone().requires_grad_(True)
+    b = B.to_dense().clone().requires_grad_(True)
+    Cd = clr.gemm_dense(ctx, A, B, a, b, tol=0.0, eps_sp=0.0)
+    Wt = torch.from_numpy(rng_for(403).standard_normal(Cd.shape)).cuda()
+    (Cd * Wt).sum().backward()
+    dA, dB = ctx.gemm_backward(A, B, Wt)
+    assert torch.equal(a.grad, dA) and torch.equal(b.grad, dB)
+    wl = config1()
+    S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    s = S.to_dense().clone().requires_grad_(True)
+    W = clr.sqrt_inv_dense(ctx, S, s, 4, 2, tol=wl.tol, eps_sp=wl.eps_sp)
+    Wb = torch.from_numpy(rng_for(404).standard_normal(W.shape)).cuda()
+    (W * Wb).sum().backward()
+    dS, _ = ctx.sqrt_inv_backward(S, Wb, 4, 2, wl.tol, wl.eps_sp)
+    assert torch.equal(s.grad, dS)
