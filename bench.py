@@ -13,6 +13,12 @@ TFLOP/s (DD 2mkn, LD 2 r k n, DL 2 m k r, LL 2 k rA rB + 2 side rA rB, plus
 2 m n r for low-rank terms added into dense accumulators), over the wall time
 of whole steps.  The mixed form (FP32 MFMA, FP64 accumulation) is reported
 alongside with its error against the FP64 oracle.
+
+The S^-1/2 part of the metric is timed on the N = 8192 cut of the 3D
+square-root workload (lattice spacing 1.2, jitter 0.3, kernel
+exp(-0.2 r^2) + 0.05 delta, 64 clusters of 128 +- U{-32..32}, tol 1e-8,
+screen 1e-10, iterated until ||W S W - I||_F / sqrt(N) <= 1e-8), FP64 and
+mixed forms, one timed run each after one untimed run.
 """
 from __future__ import annotations
 
@@ -83,6 +89,50 @@ def summarize(stats, wall, form):
     }
 
 
+def run_sqrtinv(ctx, n, forms, log_fn):
+    """S^-1/2 to convergence, per form: time, iterations, residuals, GEMM throughput."""
+    import torch
+    from workloads import config4
+    wl = config4(n, max(2, n // 128))
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    del Sd
+    conv = wl.extra["conv_tol"]
+    out = {}
+    dense_w = {}
+    for form in forms:
+        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, precision=form)   # untimed
+        del W
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, precision=form)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d = st.as_dict()
+        out[form] = {
+            "ms_total": wall * 1e3,
+            "iterations": d["iterations"],
+            "converged": bool(d["converged"]),
+            "internal_residual": d["internal_residual"],
+            "explicit_residual": d["explicit_residual"],
+            "n_gemms": d["n_gemms"],
+            "gemm_tflops": d["flops_products"] / wall / 1e12,
+            "paper_convention_tflops": 4 * d["iterations"] * 2.0 * float(n) ** 3 / wall / 1e12,
+        }
+        dense_w[form] = W.to_dense()
+        del W
+        log_fn(f"  S^-1/2 {form}: {out[form]}")
+    if "fp64" in dense_w:
+        ref = dense_w["fp64"]
+        for f, w in dense_w.items():
+            if f != "fp64":
+                out[f]["rel_diff_vs_fp64"] = float(torch.linalg.norm(w - ref) / torch.linalg.norm(ref))
+    return {"workload": f"S^-1/2, N={n} 3D lattice (spacing 1.2, jitter 0.3) overlap-like "
+                        f"exp(-0.2 r^2)+0.05 delta, {len(wl.sizes)} clusters 128+-U{{-32..32}}, "
+                        f"tol {wl.tol:g}, screen 1e-10, conv 1e-8",
+            "forms": out}
+
+
 def cpu_baseline(wl, Sd, gpu_blocks_fn, budget_s):
     """Oracle (FP64 NumPy/LAPACK) on a bounded sample of the same product's result blocks."""
     import oracle as orc
@@ -137,6 +187,8 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sqrtinv-n", type=int, default=8192)
+    ap.add_argument("--no-sqrtinv", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -190,6 +242,11 @@ def main():
             sample_err[f"{f}_vs_{base}"] = float(np.linalg.norm(D - Db) / np.linalg.norm(Db))
         log(f"cpu baseline: {cpu}")
 
+    sqrtinv = None
+    if not args.no_sqrtinv:
+        log(f"S^-1/2 at N={args.sqrtinv_n}")
+        sqrtinv = run_sqrtinv(ctx, args.sqrtinv_n, [f for f in args.forms.split(",")], log)
+
     roof = {
         "bound": "mfma",
         "kernel": "k_ggemm (dense accumulation launch)",
@@ -224,6 +281,7 @@ def main():
         "dense_equivalent_tflops": dense_equiv,
         "forms": forms,
         "error_vs_oracle_sampled": sample_err,
+        "sqrt_inv": sqrtinv,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

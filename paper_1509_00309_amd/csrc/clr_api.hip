@@ -40,7 +40,7 @@ struct clr_context {
   std::string last_error;
   DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
       items_thin2, pieces, rec, pool, scratch, acc, status, terms, aux_items, aux_segs,
-      aux_dense, ptrs;
+      aux_dense, ptrs, recg;
   hipEvent_t ev[8] = {};
   // Stream-ordered cache of freed matrix allocations: a matrix released on the
   // context stream can back the next matrix of a similar size without a
@@ -328,6 +328,19 @@ clr_status upload(clr_context* ctx, DevBuf& b, const std::vector<T>& v) {
   return CLR_OK;
 }
 
+// Output-product slots of the recompression launch (one GEMM item and one
+// term per recompressed block).
+hipError_t launch_recompress_ctx(clr_context* ctx, const RecItem* items, const Piece* pieces,
+                                 int nitems, double tol) {
+  const size_t n = (size_t)std::max(nitems, 1);
+  const size_t gi_bytes = (sizeof(GemmItem) * n + 255) / 256 * 256;
+  hipError_t e = ensure(ctx->recg, gi_bytes + sizeof(Seg) * n);
+  if (e != hipSuccess) return e;
+  GemmItem* gi = static_cast<GemmItem*>(ctx->recg.p);
+  Seg* gs = reinterpret_cast<Seg*>(static_cast<char*>(ctx->recg.p) + gi_bytes);
+  return launch_recompress(items, pieces, nitems, tol, as<int>(ctx->status), gi, gs, ctx->stream);
+}
+
 clr_status copy_matrix(clr_context* ctx, const clr_matrix* src, clr_matrix** out) {
   clr_matrix* m = nullptr;
   clr_status s = alloc_matrix(ctx, src->rs, src->cs, &m);
@@ -383,7 +396,7 @@ extern "C" clr_status clr_context_destroy(clr_context* ctx) {
                     &ctx->items_dense, &ctx->seg_thin1, &ctx->items_thin1, &ctx->seg_thin2,
                     &ctx->items_thin2, &ctx->pieces, &ctx->rec, &ctx->pool, &ctx->scratch,
                     &ctx->acc, &ctx->status, &ctx->terms, &ctx->aux_items, &ctx->aux_segs,
-                    &ctx->aux_dense, &ctx->ptrs})
+                    &ctx->aux_dense, &ctx->ptrs, &ctx->recg})
     free_buf(*b);
   for (auto& c : ctx->cache) (void)hipFree(c.first);
   ctx->cache.clear();
@@ -546,8 +559,7 @@ extern "C" clr_status clr_compress(clr_context* ctx, const double* dense, int64_
     free_matrix(m);
     return s;
   }
-  e = launch_recompress(as<RecItem>(ctx->rec), nullptr, (int)items.size(), tol, as<int>(ctx->status),
-                        ctx->stream);
+  e = launch_recompress_ctx(ctx, as<RecItem>(ctx->rec), nullptr, (int)items.size(), tol);
   if (e != hipSuccess) {
     free_matrix(m);
     return fail(ctx, CLR_ERR_HIP, "recompress launch: %s", hipGetErrorString(e));
@@ -736,7 +748,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   if (e == hipSuccess) e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
   if (e == hipSuccess)
-    e = launch_recompress(F.rec, F.pieces, (int)hc[kCntComputed], o->tol, as<int>(ctx->status), stream);
+    e = launch_recompress_ctx(ctx, F.rec, F.pieces, (int)hc[kCntComputed], o->tol);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[3], stream);
   if (e != hipSuccess) {
     fail(ctx, CLR_ERR_HIP, "product launch: %s", hipGetErrorString(e));
@@ -942,8 +954,8 @@ extern "C" clr_status clr_axpby(clr_context* ctx, double a, const clr_matrix* X,
   if (e == hipSuccess)
     e = run_ggemm(o, as<GemmItem>(ctx->aux_items), as<Seg>(ctx->aux_segs), (int)items.size(), ctx->stream);
   if (e == hipSuccess)
-    e = launch_recompress(as<RecItem>(ctx->rec), as<Piece>(ctx->pieces), (int)rec.size(), o->tol,
-                          as<int>(ctx->status), ctx->stream);
+    e = launch_recompress_ctx(ctx, as<RecItem>(ctx->rec), as<Piece>(ctx->pieces), (int)rec.size(),
+                              o->tol);
   if (e != hipSuccess) return bail(fail(ctx, CLR_ERR_HIP, "axpby launch: %s", hipGetErrorString(e)));
   if ((s = check_status(ctx)) != CLR_OK) return bail(s);
   *Tout = T;

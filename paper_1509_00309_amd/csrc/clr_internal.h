@@ -194,7 +194,7 @@ hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, 
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
                             hipStream_t s);
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
-                             int* status, hipStream_t s);
+                             int* status, GemmItem* gout, Seg* gseg, hipStream_t s);
 hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
                            hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,

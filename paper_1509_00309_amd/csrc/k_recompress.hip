@@ -59,21 +59,13 @@ struct RecShared {
 // Cross-lane sums.  Within a row of 16 lanes the butterfly uses DPP lane
 // permutations, which stay in the vector ALU (quad_perm [1,0,3,2], quad_perm
 // [2,3,0,1], row_half_mirror, row_mirror): after the four steps every lane of
-// the row holds the row's sum.  Crossing rows (32 and 64 lanes) uses one
-// ds_swizzle (xor 16 inside each half-wave) and one bpermute (xor 32).
+// the row holds the row's sum.  Crossing rows (32 and 64 lanes) uses the lane
+// swaps below.
 template <int CTRL>
 __device__ inline double dpp_move(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-__device__ inline double swizzle_xor16(double v) {
-  const long long b = __double_as_longlong(v);
-  // bit-mode swizzle: and_mask 0x1f, or_mask 0, xor_mask 0x10
-  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), 0x401F);
-  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -85,15 +77,34 @@ __device__ inline double group_sum16(double v) {
   return v;
 }
 
-__device__ inline double hw_sum(double v) {
-  v = group_sum16(v);
-  return v + swizzle_xor16(v);
+// x[l] + x[l ^ 16] and x[l] + x[l ^ 32] in every lane with the gfx950 lane
+// swaps (v_permlane16_swap / v_permlane32_swap: vector ALU, no LDS round
+// trip).  With both operands the same register, the two results of a swap
+// are the even-row (lower-half) value and the odd-row (upper-half) value of
+// the lane's pair, so every lane adds the same two numbers in the same order.
+__device__ inline double xor16_sum(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)(b & 0xffffffffLL), hi = (unsigned)(b >> 32);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double e = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double o = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return e + o;
 }
 
-__device__ inline double wave_sum(double v) {
-  v = hw_sum(v);
-  return v + __shfl_xor(v, 32, 64);
+__device__ inline double xor32_sum(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)(b & 0xffffffffLL), hi = (unsigned)(b >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double e = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double o = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return e + o;
 }
+
+__device__ inline double hw_sum(double v) { return xor16_sum(group_sum16(v)); }
+
+__device__ inline double wave_sum(double v) { return xor32_sum(hw_sum(v)); }
 
 // Deterministic workgroup sum: per-thread partials, tree over LDS.
 CLR_INLINE double block_sum(double v, RecShared& sh) {
@@ -568,6 +579,10 @@ CLR_INLINE void house_wave(const double* src, int first, int end, double& beta, 
 
 // Householder bidiagonalisation of the register-resident G: d, e, the right
 // reflectors (vstore, tauR) in LDS.  The tile is left in an unspecified state.
+// The updates are written without per-element branches: rows and columns
+// outside the active part get zero weights, so a - v * 0 leaves them exactly
+// as they were, and the independent dot products of a thread's 5 columns (or
+// 10 rows) form one straight-line block the compiler can interleave.
 CLR_INLINE void reg_bidiag(RegTile& a, int p, int q, RegLds& L) {
   const int tid = threadIdx.x;
   const int tr = tid & 15, tc = tid >> 4;
@@ -586,24 +601,29 @@ CLR_INLINE void reg_bidiag(RegTile& a, int p, int q, RegLds& L) {
     house_wave(L.colk, k, p, beta, tau, scal);
     if (tid == 0) L.d[k] = beta;
     if (tau != 0.0) {
-      double vr[kRR];
+      double vr[kRR], w[kRC];
 #pragma unroll
       for (int ir = 0; ir < kRR; ++ir) {
         const int i = tr + 16 * ir;
-        vr[ir] = (i == k) ? 1.0 : ((i > k && i < p) ? L.colk[i] * scal : 0.0);
+        const double c = L.colk[i < p ? i : 0];
+        vr[ir] = (i == k) ? 1.0 : ((i > k && i < p) ? c * scal : 0.0);
+      }
+#pragma unroll
+      for (int jc = 0; jc < kRC; ++jc) {
+        w[jc] = 0.0;
+#pragma unroll
+        for (int ir = 0; ir < kRR; ++ir) w[jc] += vr[ir] * a[ir][jc];
       }
 #pragma unroll
       for (int jc = 0; jc < kRC; ++jc) {
         const int j = tc + 32 * jc;
-        if (j > k && j < q) {   // uniform over the 16-lane row that holds column j
-          double w = 0.0;
-#pragma unroll
-          for (int ir = 0; ir < kRR; ++ir) w += vr[ir] * a[ir][jc];
-          w = tau * group_sum16(w);
-#pragma unroll
-          for (int ir = 0; ir < kRR; ++ir) a[ir][jc] -= vr[ir] * w;
-        }
+        const double t = (j > k && j < q) ? tau : 0.0;
+        w[jc] = t * group_sum16(w[jc]);
       }
+#pragma unroll
+      for (int ir = 0; ir < kRR; ++ir)
+#pragma unroll
+        for (int jc = 0; jc < kRC; ++jc) a[ir][jc] -= vr[ir] * w[jc];
     }
     if (k == q - 1) break;
     // right reflector on row k, applied to rows > k
@@ -633,19 +653,26 @@ CLR_INLINE void reg_bidiag(RegTile& a, int p, int q, RegLds& L) {
 #pragma unroll
     for (int jc = 0; jc < kRC; ++jc) {
       const int j = tc + 32 * jc;
-      vc[jc] = (j == k + 1) ? 1.0 : ((j > k + 1 && j < q) ? L.rowk[j] * scal : 0.0);
+      const double r = L.rowk[j < q ? j : 0];
+      vc[jc] = (j == k + 1) ? 1.0 : ((j > k + 1 && j < q) ? r * scal : 0.0);
     }
     if (tau != 0.0) {
+      double w[kRR];
 #pragma unroll
       for (int ir = 0; ir < kRR; ++ir) {
-        double w = 0.0;
+        w[ir] = 0.0;
 #pragma unroll
-        for (int jc = 0; jc < kRC; ++jc) w += a[ir][jc] * vc[jc];
-        // the 4 column classes of this wave: lanes 16 and 32 apart
-        w += swizzle_xor16(w);
-        w += __shfl_xor(w, 32, 64);
-        const int i = tr + 16 * ir;
-        if (lane < 16 && i > k && i < p) L.u.bd.part[wave][i] = w;
+        for (int jc = 0; jc < kRC; ++jc) w[ir] += a[ir][jc] * vc[jc];
+      }
+      // the 4 column classes of this wave: lanes 16 and 32 apart
+#pragma unroll
+      for (int ir = 0; ir < kRR; ++ir) w[ir] = xor32_sum(xor16_sum(w[ir]));
+      if (lane < 16) {
+#pragma unroll
+        for (int ir = 0; ir < kRR; ++ir) {
+          const int i = tr + 16 * ir;
+          if (i > k && i < p) L.u.bd.part[wave][i] = w[ir];
+        }
       }
     }
     __syncthreads();
@@ -660,11 +687,10 @@ CLR_INLINE void reg_bidiag(RegTile& a, int p, int q, RegLds& L) {
 #pragma unroll
       for (int ir = 0; ir < kRR; ++ir) {
         const int i = tr + 16 * ir;
-        if (i > k && i < p) {
-          const double w = tau * L.u.bd.wrow[i];
+        const double wr = L.u.bd.wrow[i < p ? i : 0];
+        const double w = (i > k && i < p) ? tau * wr : 0.0;
 #pragma unroll
-          for (int jc = 0; jc < kRC; ++jc) a[ir][jc] -= w * vc[jc];
-        }
+        for (int jc = 0; jc < kRC; ++jc) a[ir][jc] -= w * vc[jc];
       }
     }
     // publish column k + 1 for the next left reflector
@@ -697,19 +723,28 @@ CLR_INLINE int sturm_greater(const double* b2, int q, double x) {
   int neg = 1;
   if (d == 0.0) d = -1e-300;
   const int n = 2 * q - 1;
-  for (int s = 0; s < n; ++s) {
-    double dn = fma(-x, d, -b2[s] * dm);
+  auto step = [&](double bb) {
+    double dn = fma(-x, d, -bb * dm);
     if (dn == 0.0) dn = -d * 0x1p-80;
     neg += (dn < 0.0) != (d < 0.0);
     dm = d;
     d = dn;
-    if ((s & 7) == 7) {
-      int e;
-      (void)frexp(d, &e);
-      d = ldexp(d, -e);
-      dm = ldexp(dm, -e);
-    }
+  };
+  int s = 0;
+  // eight squared off-diagonals at a time: the LDS reads of a chunk are issued
+  // together instead of one per dependent step
+  for (; s + 8 <= n; s += 8) {
+    double bb[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) bb[t] = b2[s + t];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) step(bb[t]);
+    int e;
+    (void)frexp(d, &e);
+    d = ldexp(d, -e);
+    dm = ldexp(dm, -e);
   }
+  for (; s < n; ++s) step(b2[s]);
   return 2 * q - neg;
 }
 
@@ -1041,7 +1076,7 @@ CLR_INLINE bool close_values(const RecShared& sh, int c) {
 // the other factor G_orig * basis, from the bidiagonal in LDS.  Returns false
 // (nothing final written) when a vector cannot be resolved this way.
 CLR_INLINE bool reg_vectors(const RecItem& it, int p, int q, bool trans, int r, double normc,
-                            RegLds& L, RecShared& sh) {
+                            RegLds& L, RecShared& sh, GemmItem* gout, Seg* gseg, int gidx) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
   const int m = it.m;
@@ -1143,22 +1178,34 @@ CLR_INLINE bool reg_vectors(const RecItem& it, int p, int q, bool trans, int r, 
   }
   if (L.flag) return false;
   for (int e = tid; e < q * r; e += kRecThreads) basis[e] = X[e];
-  __syncthreads();
-  // other factor: G_orig * basis  (G_orig = D for m >= n, D^T otherwise)
-  const cgdbl* D = (const cgdbl*)it.D;
-  const int n = it.n;
-  for (int o = g; o < p * r; o += kGroups) {
-    const int i = o % p, c = o / p;
-    const double* xb = X + c * q;
-    double s = 0.0;
-    if (!trans) {
-      for (int j = gl; j < n; j += 16) s += D[i + (int64_t)j * it.ldd] * xb[j];
-    } else {
-      const cgdbl* dcol = D + (int64_t)i * it.ldd;
-      for (int j = gl; j < m; j += 16) s += dcol[j] * xb[j];
-    }
-    s = group_sum16(s);
-    if (gl == 0) other[i + (int64_t)c * p] = s;
+  // The other factor, G_orig * basis (G_orig = D for m >= n, D^T otherwise),
+  // is an ordinary dense product: it is emitted as one grouped-GEMM item and
+  // computed on MFMA by the launch that follows this kernel.
+  if (tid == 0) {
+    Seg sg{};
+    sg.L = it.D;
+    sg.sLi = trans ? it.ldd : 1;
+    sg.sLk = trans ? 1 : it.ldd;
+    sg.R = (const double*)basis;
+    sg.sRk = 1;
+    sg.sRj = q;
+    sg.k = q;
+    sg.kbase = 0;
+    sg.scale = 1.0;
+    gseg[gidx] = sg;
+    GemmItem g{};
+    g.C = (double*)other;
+    g.ldc = p;
+    g.row0 = 0;
+    g.col0 = 0;
+    g.m = p;
+    g.n = r;
+    g.seg0 = gidx;   // this item's term sits at the same index of the term array
+    g.nseg = 1;
+    g.ktotal = q;
+    g.accumulate = 0;
+    g.alpha = 1.0;
+    gout[gidx] = g;
   }
   double kept = 0.0;
   for (int c = 0; c < r; ++c) kept += sh.sigma[c] * sh.sigma[c];
@@ -1495,7 +1542,8 @@ CLR_INLINE void dense_general(const RecItem& it, PT* G, int p, int q, bool trans
 
 template <bool REG>
 CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* status,
-                           RecShared& sh) {
+                           RecShared& sh, GemmItem* gout = nullptr, Seg* gseg = nullptr,
+                           int gidx = 0) {
   const int m = it.m, n = it.n;
   const cgdbl* D = (const cgdbl*)it.D;
   double part = 0.0;
@@ -1536,7 +1584,7 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
       return;
     }
     // truncated: singular vectors from the bidiagonal, else pivoted QR + Jacobi on R^T
-    if (reg_vectors(it, p, q, trans, r, normc, L, sh)) return;
+    if (reg_vectors(it, p, q, trans, r, normc, L, sh, gout, gseg, gidx)) return;
     reg_load(a, it.D, it.ldd, trans, 1.0 / normc, p, q);
     const int kc = reg_pivoted_qr(a, p, q, L, sh);
     // odd leading dimension: the columns of one wave start in different LDS banks
@@ -1697,7 +1745,8 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress(const RecItem* __res
 
 __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* __restrict__ items,
                                                                 int nitems, double tol,
-                                                                int* status) {
+                                                                int* status, GemmItem* gout,
+                                                                Seg* gseg) {
   extern __shared__ double lds[];
   __shared__ RecShared sh;
   const int per = gridDim.x / 8;
@@ -1706,11 +1755,11 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* _
   const RecItem it = items[item];
   if (!register_item(it, tol)) return;
   if (!item_guard(it, tol, status)) return;
-  dense_path<true>(it, tol, lds, status, sh);
+  dense_path<true>(it, tol, lds, status, sh, gout, gseg, item);
 }
 
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
-                             int* status, hipStream_t s) {
+                             int* status, GemmItem* gout, Seg* gseg, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   static bool attr_set = false;
   if (!attr_set) {
@@ -1723,13 +1772,21 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
     attr_set = true;
   }
   const int grid = ((nitems + 7) / 8) * 8;
+  // every item's output-product slot starts empty (m = 0: nothing to compute)
+  static_assert(sizeof(GemmItem) % sizeof(int) == 0, "GemmItem is filled as int words");
+  hipError_t e = launch_fill_i32(reinterpret_cast<int*>(gout), 0,
+                                 (int64_t)nitems * (int64_t)(sizeof(GemmItem) / sizeof(int)), s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_recompress_reg, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items,
-                     nitems, tol, status);
-  hipError_t e = hipGetLastError();
+                     nitems, tol, status, gout, gseg);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_recompress, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items, pieces,
                      nitems, tol, status);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // other factors of the truncated register-engine blocks: G_orig * basis on FP64 MFMA
+  return launch_ggemm_f64(gout, gseg, nitems, s);
 }
 
 }  // namespace clr
