@@ -45,6 +45,52 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ggemm_dense_c2_n8192_traffic.md")
+GEMM_SOURCES = [os.path.join(ROOT, "paper_1509_00309_amd", "csrc", f)
+                for f in ("k_gemm.h", "k_gemm_f64.hip", "clr_internal.h", "k_plan.hip")]
+
+
+def gemm_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per dense-accumulation launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None when
+    the kernel sources have changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and line.strip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != gemm_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes):
+    """One plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = nbytes // 8
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
+
+
 def run_form(ctx, S, wl, form, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -101,11 +147,12 @@ def run_sqrtinv(ctx, n, forms, log_fn):
     out = {}
     dense_w = {}
     for form in forms:
-        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, precision=form)   # untimed
-        del W
+        split = 1 if form == "mixed" else 0   # compensated products: FP64-level accuracy
+        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, precision=form, split=split)
+        del W   # untimed run
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, precision=form)
+        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, precision=form, split=split)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         d = st.as_dict()
@@ -113,6 +160,7 @@ def run_sqrtinv(ctx, n, forms, log_fn):
             "ms_total": wall * 1e3,
             "iterations": d["iterations"],
             "converged": bool(d["converged"]),
+            "split_products": bool(split),
             "internal_residual": d["internal_residual"],
             "explicit_residual": d["explicit_residual"],
             "n_gemms": d["n_gemms"],
@@ -189,12 +237,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sqrtinv-n", type=int, default=8192)
     ap.add_argument("--no-sqrtinv", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one device copy of BYTES (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        torch.cuda.set_device(0)
+        copy_calibration(args.copy_calibration)
+        return
     import paper_1509_00309_amd as clr
     from workloads import config2
 
@@ -249,12 +303,12 @@ def main():
 
     roof = {
         "bound": "mfma",
-        "kernel": "k_ggemm (dense accumulation launch)",
+        "kernel": "k_ggemm<5, false, false, true> (dense accumulation launch, FP64 form)",
         "achieved": fb["dense_gemm_tflops"],
         "peak": fb["peak"],
         "unit": "TFLOP/s",
         "frac": (fb["dense_gemm_tflops"] / fb["peak"]) if fb["dense_gemm_tflops"] else None,
-        "traffic": None,
+        "traffic": measured_traffic(),
     }
     line = {
         "metric": METRIC,

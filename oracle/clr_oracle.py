@@ -459,9 +459,9 @@ def sqrt_inv(S: OMatrix, tol: float, eps_sp: float, conv_tol: float = 1e-10,
     Stopping (fixed_iters == 0): once ||X_n - I||_F/sqrt(N) <= conv_tol the
     explicit residual ||W S W - I||_F/sqrt(N) of W = sqrt(alpha) Z_{n+1} is
     evaluated; stop when it is <= conv_tol ("converged"), or when it failed
-    to halve since the previous evaluation ("stalled"); stop with "diverged"
-    when ||X_n - I|| grew in two consecutive iterations while above
-    conv_tol; stop at max_iter.
+    to halve since the previous evaluation ("stalled"); when ||X_n - I||
+    grew in two consecutive iterations while above conv_tol, stop with
+    "diverged" if it exceeds 0.5 and "stalled" otherwise; stop at max_iter.
     """
     if alpha is None:
         alpha = default_alpha(S)
@@ -496,7 +496,10 @@ def sqrt_inv(S: OMatrix, tol: float, eps_sp: float, conv_tol: float = 1e-10,
                 status = "stalled"
                 break
         elif len(internal) >= 3 and internal[-1] > internal[-2] > internal[-3]:
-            status = "diverged"
+            # In exact arithmetic the residual falls monotonically once
+            # ||alpha S - I||_2 < 1 (Sec. 4.2); growth while it is small is the
+            # truncation / precision floor, growth beyond 0.5 is divergence.
+            status = "diverged" if internal[-1] > 0.5 else "stalled"
             break
     if fixed_iters > 0:
         status = "fixed"

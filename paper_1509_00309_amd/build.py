@@ -2,9 +2,10 @@
 
     python paper_1509_00309_amd/build.py      (or __graft_entry__.build())
 
-compiles every HIP source under csrc/ with hipcc into
-paper_1509_00309_amd/libclr_mi355x.so (in-tree, so it travels with the source
-tree).  Packed-FP32 instructions are disabled for all device code.
+compiles every HIP source under csrc/ with hipcc (in parallel, objects under
+_build/obj) and links paper_1509_00309_amd/libclr_mi355x.so (in-tree, so it
+travels with the source tree).  Packed-FP32 instructions are disabled for all
+device code.
 """
 from __future__ import annotations
 
@@ -41,19 +42,38 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I",
-           os.path.join(HERE, "csrc"), *sources(), "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in proc.stdout.splitlines()
                     if "packed-fp32-ops" not in l and l.strip() != "1 warning generated.")
-    if proc.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({proc.returncode}):\n{out}")
-    if verbose and out.strip():
-        print(out, flush=True)
+    return proc.returncode, out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel, then link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(ROOT, "_build", "obj")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for src in sources():
+        obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o")
+        jobs.append(([hipcc(), *compile_flags, *inc, "-c", src, "-o", obj], obj))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        results = list(ex.map(lambda j: _run(j[0], verbose), jobs))
+    for (cmd, _obj), (rc, out) in zip(jobs, results):
+        if rc != 0:
+            raise RuntimeError(f"hipcc failed ({rc}) on {cmd[-3]}:\n{out}")
+        if verbose and out.strip():
+            print(out, flush=True)
+    tmp = LIB_PATH + ".tmp"
+    rc, out = _run([hipcc(), *HIPCC_FLAGS, *[o for _c, o in jobs], "-o", tmp], verbose)
+    if rc != 0:
+        raise RuntimeError(f"link failed ({rc}):\n{out}")
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

@@ -262,9 +262,9 @@ clr_status check_opts(clr_context* ctx, const clr_gemm_opts* o) {
 }
 
 hipError_t run_ggemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
-                     hipStream_t s) {
-  if (o->precision == CLR_MIXED) return launch_ggemm_f32(items, segs, n, o->split, s);
-  return launch_ggemm_f64(items, segs, n, s);
+                     hipStream_t s, bool dense = false) {
+  if (o->precision == CLR_MIXED) return launch_ggemm_f32(items, segs, n, o->split, s, dense);
+  return launch_ggemm_f64(items, segs, n, s, dense);
 }
 
 int max_item(const clr_gemm_opts* o) {
@@ -745,7 +745,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   if (e == hipSuccess) e = run_ggemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream);
   if (e == hipSuccess) e = run_ggemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[6], stream);
-  if (e == hipSuccess) e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream);
+  if (e == hipSuccess) e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream, true);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
   if (e == hipSuccess)
     e = launch_recompress_ctx(ctx, F.rec, F.pieces, (int)hc[kCntComputed], o->tol);
@@ -1147,9 +1147,17 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
       last_explicit = e;
     } else if (internal.size() >= 3 && internal[internal.size() - 1] > internal[internal.size() - 2] &&
                internal[internal.size() - 2] > internal[internal.size() - 3]) {
-      free_matrix(Z);
-      free_matrix(Y);
-      return fail(ctx, CLR_ERR_DIVERGED, "||X_n - I|| grew in two consecutive iterations");
+      // the residual falls monotonically in exact arithmetic once
+      // ||alpha S - I||_2 < 1 (Sec. 4.2): growth while it is small is the
+      // truncation / precision floor (stalled), growth beyond 0.5 divergence
+      if (internal.back() > 0.5) {
+        free_matrix(Z);
+        free_matrix(Y);
+        return fail(ctx, CLR_ERR_DIVERGED, "||X_n - I|| grew in two consecutive iterations");
+      }
+      result = CLR_ERR_NOT_CONVERGED;
+      ++it;
+      break;
     }
   }
   if (s != CLR_OK) {

@@ -190,9 +190,10 @@ struct AxpbyDenseItem {
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
-hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s);
+hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
+                            bool dense = false);
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s);
+                            hipStream_t s, bool dense = false);
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
                              int* status, GemmItem* gout, Seg* gseg, hipStream_t s);
 hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,

@@ -25,6 +25,7 @@
 //   A(i, k): i = l % 16, k = l / 16;   B(k, j): j = l % 16, k = l / 16;
 //   D(i, j) is held by lane l = j + 16*g, element v, with
 //     f32: i = 4*g + v        f64: i = g + 4*v   (the f64 shape interleaves rows).
+#pragma once
 #include "clr_internal.h"
 
 namespace clr {
@@ -342,7 +343,10 @@ __device__ __attribute__((always_inline)) inline void run_nb(GemmLds<WT, F32>& s
   }
 }
 
-template <int WT, bool F32, bool SPLIT>
+// DENSE only names the instantiation: the dense-accumulation launch of a
+// product gets its own kernel symbol, so profiles separate it from the factor
+// products and the recompression output products that share the code.
+template <int WT, bool F32, bool SPLIT, bool DENSE>
 __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
                                                            const Seg* __restrict__ segs,
                                                            int nitems) {
@@ -389,24 +393,5 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
 }
 
 static inline int xcd_grid(int n) { return ((n + 7) / 8) * 8; }
-
-hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ggemm<kF64WaveTiles, false, false>), dim3(xcd_grid(nitems)),
-                     dim3(kGemmThreads), 0, s, items, segs, nitems);
-  return hipGetLastError();
-}
-
-hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-  if (split)
-    hipLaunchKernelGGL((k_ggemm<kF32WaveTiles, true, true>), dim3(xcd_grid(nitems)),
-                       dim3(kGemmThreads), 0, s, items, segs, nitems);
-  else
-    hipLaunchKernelGGL((k_ggemm<kF32WaveTiles, true, false>), dim3(xcd_grid(nitems)),
-                       dim3(kGemmThreads), 0, s, items, segs, nitems);
-  return hipGetLastError();
-}
 
 }  // namespace clr

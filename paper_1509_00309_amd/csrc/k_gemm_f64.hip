@@ -1,0 +1,18 @@
+// FP64 instantiations of the grouped block-product GEMM (k_gemm.h).
+#include "k_gemm.h"
+
+namespace clr {
+
+hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
+                            bool dense) {
+  if (nitems <= 0) return hipSuccess;
+  if (dense)
+    hipLaunchKernelGGL((k_ggemm<kF64WaveTiles, false, false, true>), dim3(xcd_grid(nitems)),
+                       dim3(kGemmThreads), 0, s, items, segs, nitems);
+  else
+    hipLaunchKernelGGL((k_ggemm<kF64WaveTiles, false, false, false>), dim3(xcd_grid(nitems)),
+                       dim3(kGemmThreads), 0, s, items, segs, nitems);
+  return hipGetLastError();
+}
+
+}  // namespace clr
