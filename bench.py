@@ -39,39 +39,46 @@ METRIC = "CLR-GEMM TFLOP/s & S^-1/2 time: mixed vs FP64 form, 1 GPU, at stated e
 PEAK_F64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
 PEAK_F32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0       # GB/s
+PEAK_F64_VALU = 78.6    # TFLOP/s, MI355X FP64 vector
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ggemm_dense_c2_n8192_traffic.md")
-GEMM_SOURCES = [os.path.join(ROOT, "paper_1509_00309_amd", "csrc", f)
-                for f in ("k_gemm.h", "k_gemm_f64.hip", "clr_internal.h", "k_plan.hip")]
+CSRC = os.path.join(ROOT, "paper_1509_00309_amd", "csrc")
+# Counter summaries (profiles/) and the sources whose change invalidates them.
+TRAFFIC = {
+    "k_recompress_reg": (os.path.join(ROOT, "profiles", "k_recompress_reg_c2_n8192_traffic.md"),
+                         ["k_recompress.hip", "clr_internal.h", "k_plan.hip"]),
+    "k_ggemm_dense": (os.path.join(ROOT, "profiles", "k_ggemm_dense_c2_n8192_traffic.md"),
+                      ["k_gemm.h", "k_gemm_f64.hip", "clr_internal.h", "k_plan.hip"]),
+}
 
 
-def gemm_source_hash():
+def source_hash(files):
     import hashlib
     h = hashlib.sha256()
-    for f in GEMM_SOURCES:
-        with open(f, "rb") as fh:
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per dense-accumulation launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None when
-    the kernel sources have changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, each scaled by a plain copy of known size), or None when the
+    kernel's sources have changed since the counters were taken."""
+    path, files = TRAFFIC[kernel]
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and line.strip().startswith("- "):
                 k, v = line.strip()[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != gemm_source_hash():
+    if vals.get("kernel_source_sha256") != source_hash(files):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -127,6 +134,8 @@ def summarize(stats, wall, form):
         "dense_gemm_tflops": f_dense / (ms_dense * 1e-3) / 1e12 if ms_dense > 0 else None,
         "thin_gemm_tflops": f_thin / (ms_thin * 1e-3) / 1e12 if ms_thin > 0 else None,
         "flops_dense_launch": f_dense,
+        "rec_engine_ms": float(np.mean([s["ms_rec_engine"] for s in stats])),
+        "rec_engine_flops": stats[-1]["flops_rec_engine"],
         "peak": peak,
         "bytes_compulsory": stats[-1]["bytes_compulsory"],
         "computed_blocks": stats[-1]["computed"],
@@ -301,14 +310,29 @@ def main():
         log(f"S^-1/2 at N={args.sqrtinv_n}")
         sqrtinv = run_sqrtinv(ctx, args.sqrtinv_n, [f for f in args.forms.split(",")], log)
 
+    # Dominant kernel by device time: the register-resident recompression (FP64
+    # vector ALU / latency bound; peak = 256 CUs x 4 SIMD x 16 lanes x FMA x 2.4 GHz
+    # = 78.6 TFLOP/s FP64), algorithmic work = Golub-Van Loan bidiagonalisation
+    # count of the blocks it truncates.
+    rec_achieved = (fb["rec_engine_flops"] / (fb["rec_engine_ms"] * 1e-3) / 1e12
+                    if fb["rec_engine_ms"] > 0 else None)
     roof = {
+        "bound": "alu",
+        "kernel": "k_recompress_reg (register-resident FP64 truncated SVD, one block per workgroup)",
+        "achieved": rec_achieved,
+        "peak": PEAK_F64_VALU,
+        "unit": "TFLOP/s",
+        "frac": rec_achieved / PEAK_F64_VALU if rec_achieved else None,
+        "traffic": measured_traffic("k_recompress_reg"),
+    }
+    roof_gemm = {
         "bound": "mfma",
         "kernel": "k_ggemm<5, false, false, true> (dense accumulation launch, FP64 form)",
         "achieved": fb["dense_gemm_tflops"],
         "peak": fb["peak"],
         "unit": "TFLOP/s",
         "frac": (fb["dense_gemm_tflops"] / fb["peak"]) if fb["dense_gemm_tflops"] else None,
-        "traffic": measured_traffic(),
+        "traffic": measured_traffic("k_ggemm_dense"),
     }
     line = {
         "metric": METRIC,
@@ -337,6 +361,7 @@ def main():
         "error_vs_oracle_sampled": sample_err,
         "sqrt_inv": sqrtinv,
         "roofline": roof,
+        "roofline_dense_gemm": roof_gemm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -93,6 +93,10 @@ typedef struct {
   double ms_symbolic, ms_products, ms_recompress, ms_total; /* device time per phase */
   double ms_thin;       /* launches of the thin factor products (LD, DL, LL terms)     */
   double ms_dense;      /* launch of the dense accumulation GEMM (DD + densified terms) */
+  double flops_rec_engine; /* Golub-Van Loan bidiagonalisation count 4 p q^2 - 4 q^3 / 3
+                              (p >= q the block edges) of the blocks truncated by the
+                              register-resident SVD kernel                              */
+  double ms_rec_engine; /* device time of that kernel                                   */
 } clr_gemm_stats;
 
 typedef struct {

@@ -52,7 +52,8 @@ class GemmStats(C.Structure):
                 ("flops_products", C.c_double), ("bytes_compulsory", C.c_double),
                 ("ms_symbolic", C.c_double), ("ms_products", C.c_double),
                 ("ms_recompress", C.c_double), ("ms_total", C.c_double),
-                ("ms_thin", C.c_double), ("ms_dense", C.c_double)]
+                ("ms_thin", C.c_double), ("ms_dense", C.c_double),
+                ("flops_rec_engine", C.c_double), ("ms_rec_engine", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -41,7 +41,7 @@ struct clr_context {
   DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
       items_thin2, pieces, rec, pool, scratch, acc, status, terms, aux_items, aux_segs,
       aux_dense, ptrs, recg;
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[10] = {};
   // Stream-ordered cache of freed matrix allocations: a matrix released on the
   // context stream can back the next matrix of a similar size without a
   // hipMalloc (all users are ordered on the same stream).
@@ -331,14 +331,15 @@ clr_status upload(clr_context* ctx, DevBuf& b, const std::vector<T>& v) {
 // Output-product slots of the recompression launch (one GEMM item and one
 // term per recompressed block).
 hipError_t launch_recompress_ctx(clr_context* ctx, const RecItem* items, const Piece* pieces,
-                                 int nitems, double tol) {
+                                 int nitems, double tol, bool timed = false) {
   const size_t n = (size_t)std::max(nitems, 1);
   const size_t gi_bytes = (sizeof(GemmItem) * n + 255) / 256 * 256;
   hipError_t e = ensure(ctx->recg, gi_bytes + sizeof(Seg) * n);
   if (e != hipSuccess) return e;
   GemmItem* gi = static_cast<GemmItem*>(ctx->recg.p);
   Seg* gs = reinterpret_cast<Seg*>(static_cast<char*>(ctx->recg.p) + gi_bytes);
-  return launch_recompress(items, pieces, nitems, tol, as<int>(ctx->status), gi, gs, ctx->stream);
+  return launch_recompress(items, pieces, nitems, tol, as<int>(ctx->status), gi, gs, ctx->stream,
+                           timed ? ctx->ev[8] : nullptr, timed ? ctx->ev[9] : nullptr);
 }
 
 clr_status copy_matrix(clr_context* ctx, const clr_matrix* src, clr_matrix** out) {
@@ -748,7 +749,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   if (e == hipSuccess) e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream, true);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
   if (e == hipSuccess)
-    e = launch_recompress_ctx(ctx, F.rec, F.pieces, (int)hc[kCntComputed], o->tol);
+    e = launch_recompress_ctx(ctx, F.rec, F.pieces, (int)hc[kCntComputed], o->tol, st != nullptr);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[3], stream);
   if (e != hipSuccess) {
     fail(ctx, CLR_ERR_HIP, "product launch: %s", hipGetErrorString(e));
@@ -777,6 +778,8 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
     st->ms_total = elapsed(ctx->ev[0], ctx->ev[3]);
     st->ms_thin = elapsed(ctx->ev[1], ctx->ev[6]);
     st->ms_dense = elapsed(ctx->ev[6], ctx->ev[2]);
+    st->flops_rec_engine = hs[kStFlopsRecEngine];
+    st->ms_rec_engine = hc[kCntComputed] > 0 ? elapsed(ctx->ev[8], ctx->ev[9]) : 0.0;
     HostMeta ha, hb, hcm;
     if ((s = fetch_meta(ctx, A, ha)) != CLR_OK) return bail(s);
     if ((s = fetch_meta(ctx, B, hb)) != CLR_OK) return bail(s);

@@ -106,7 +106,7 @@ enum PlanCounter : int {
 // Floating-point per-block statistics of the symbolic phase.
 enum PlanStat : int {
   kStEst = 0, kStFlopsDD, kStFlopsLD, kStFlopsDL, kStFlopsLL, kStFlopsDensify,
-  kStNDD, kStNLD, kStNDL, kStNLL, kStCandidate, kNumStats
+  kStNDD, kStNLD, kStNDL, kStNLL, kStCandidate, kStFlopsRecEngine, kNumStats
 };
 
 // Device view of a CLR matrix's metadata and arena.
@@ -195,7 +195,8 @@ hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, 
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
                             hipStream_t s, bool dense = false);
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
-                             int* status, GemmItem* gout, Seg* gseg, hipStream_t s);
+                             int* status, GemmItem* gout, Seg* gseg, hipStream_t s,
+                             hipEvent_t engine_begin = nullptr, hipEvent_t engine_end = nullptr);
 hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
                            hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,

@@ -1759,7 +1759,8 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* _
 }
 
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
-                             int* status, GemmItem* gout, Seg* gseg, hipStream_t s) {
+                             int* status, GemmItem* gout, Seg* gseg, hipStream_t s,
+                             hipEvent_t engine_begin, hipEvent_t engine_end) {
   if (nitems <= 0) return hipSuccess;
   static bool attr_set = false;
   if (!attr_set) {
@@ -1777,10 +1778,18 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
   hipError_t e = launch_fill_i32(reinterpret_cast<int*>(gout), 0,
                                  (int64_t)nitems * (int64_t)(sizeof(GemmItem) / sizeof(int)), s);
   if (e != hipSuccess) return e;
+  if (engine_begin) {
+    e = hipEventRecord(engine_begin, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_recompress_reg, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items,
                      nitems, tol, status, gout, gseg);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (engine_end) {
+    e = hipEventRecord(engine_end, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_recompress, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items, pieces,
                      nitems, tol, status);
   e = hipGetLastError();
