@@ -39,6 +39,7 @@ extern "C" {
 
 typedef struct clr_context clr_context;
 typedef struct clr_matrix clr_matrix;
+typedef struct clr_plan clr_plan;
 
 typedef enum {
   CLR_OK = 0,
@@ -201,6 +202,30 @@ clr_status clr_identity_residual(clr_context* ctx, const clr_matrix* X, double* 
 clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
                              double alpha, const double* dC, int64_t ldc, double* dA,
                              int64_t lda, double* dB, int64_t ldb);
+
+/* Batched products C_p = A_p B_p (p < nprod), each with the semantics of
+ * clr_gemm (Sec. 4.1).  Planning screens every product on the device and
+ * reads back all work totals once; execution runs one launch per phase for the
+ * whole batch (factor products, dense accumulation, recompression), so blocks
+ * of all products share each launch.
+ *
+ * clr_plan_create allocates the nprod outputs C[p] (owned by the caller, freed
+ * with clr_destroy) and the plan's own work buffers.  A, B and C must stay
+ * alive, with unchanged block structure (kinds and ranks), while the plan is
+ * executed; their values may change between executions.  With use_graph != 0
+ * the execution phase is recorded once as a HIP graph on the context stream
+ * and clr_plan_execute replays it.  clr_plan_execute writes C and, if st is
+ * given, aggregated counts and flops and the device time of the execution
+ * (ms_total).  On error the outputs are NULL (create) or unspecified
+ * (execute).  clr_gemm_batch = create (no graph) + execute + destroy. */
+clr_status clr_plan_create(clr_context* ctx, int nprod, const clr_matrix* const* A,
+                           const clr_matrix* const* B, const clr_gemm_opts* opts, int use_graph,
+                           clr_plan** plan, clr_matrix** C);
+clr_status clr_plan_execute(clr_context* ctx, clr_plan* plan, clr_gemm_stats* st);
+clr_status clr_plan_destroy(clr_plan* plan);
+clr_status clr_gemm_batch(clr_context* ctx, int nprod, const clr_matrix* const* A,
+                          const clr_matrix* const* B, const clr_gemm_opts* opts, clr_matrix** C,
+                          clr_gemm_stats* st);
 
 /* dS of L = sum(Wbar .* W) for W from `iters` unrolled iterations (alpha held
  * constant, truncation treated as the identity), restricted to S's stored

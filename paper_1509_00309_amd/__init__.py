@@ -21,7 +21,7 @@ from ._abi import (CLR_FP64, CLR_MIXED, CLR_SCREEN_ABS, CLR_SCREEN_AREA, ClrErro
 
 __all__ = [
     "Context", "CLRMatrix", "ClrError", "GemmStats", "SqrtInvStats", "lib", "LIB_PATH",
-    "CLR_FP64", "CLR_MIXED", "gemm_dense", "sqrt_inv_dense",
+    "CLR_FP64", "CLR_MIXED", "gemm_dense", "sqrt_inv_dense", "Plan",
 ]
 
 
@@ -167,6 +167,38 @@ class Context:
         self._check(rc)
         return CLRMatrix(self, h), st
 
+    # -- batches of products ----------------------------------------------------
+    def plan(self, As: Sequence["CLRMatrix"], Bs: Sequence["CLRMatrix"], tol: float,
+             eps_sp: float, screen="abs", precision="fp64", split: int = 0,
+             alpha: float = 1.0, graph: bool = False) -> "Plan":
+        """Plan C_p = A_p B_p for all p; execute() computes every product of the batch."""
+        if len(As) != len(Bs) or not As:
+            raise ValueError("need equally many (and at least one) A and B operands")
+        n = len(As)
+        o = _gemm_opts(tol, eps_sp, screen, precision, split, alpha)
+        pa = (C.c_void_p * n)(*[a._h.value for a in As])
+        pb = (C.c_void_p * n)(*[b._h.value for b in Bs])
+        pc = (C.c_void_p * n)()
+        h = C.c_void_p()
+        self._check(lib.clr_plan_create(self._h, n, pa, pb, C.byref(o), int(bool(graph)),
+                                        C.byref(h), pc))
+        outs = [CLRMatrix(self, C.c_void_p(pc[i])) for i in range(n)]
+        return Plan(self, h, outs, list(As), list(Bs))
+
+    def gemm_batch(self, As, Bs, tol: float, eps_sp: float, screen="abs", precision="fp64",
+                   split: int = 0, alpha: float = 1.0, stats: bool = False):
+        """C_p = A_p B_p for all p, one launch per phase for the whole batch."""
+        n = len(As)
+        o = _gemm_opts(tol, eps_sp, screen, precision, split, alpha)
+        pa = (C.c_void_p * n)(*[a._h.value for a in As])
+        pb = (C.c_void_p * n)(*[b._h.value for b in Bs])
+        pc = (C.c_void_p * n)()
+        st = GemmStats()
+        self._check(lib.clr_gemm_batch(self._h, n, pa, pb, C.byref(o), pc,
+                                       C.byref(st) if stats else None))
+        outs = [CLRMatrix(self, C.c_void_p(pc[i])) for i in range(n)]
+        return (outs, st) if stats else outs
+
     # -- adjoints -------------------------------------------------------------
     def gemm_backward(self, A: "CLRMatrix", B: "CLRMatrix", dC, alpha: float = 1.0,
                       want_a: bool = True, want_b: bool = True):
@@ -204,6 +236,32 @@ class Context:
         out = C.c_double()
         self._check(lib.clr_identity_residual(self._h, X._h, C.byref(out)))
         return out.value
+
+
+class Plan:
+    """A planned batch of products (optionally recorded as a HIP graph)."""
+
+    def __init__(self, ctx: Context, handle: C.c_void_p, outputs, As, Bs):
+        self.ctx = ctx
+        self._h = handle
+        self.outputs = outputs
+        self._keep = (As, Bs)   # operands must outlive the plan
+
+    def execute(self, stats: bool = False):
+        st = GemmStats()
+        self.ctx._check(lib.clr_plan_execute(self.ctx._h, self._h, C.byref(st) if stats else None))
+        return st if stats else None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.clr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class CLRMatrix:

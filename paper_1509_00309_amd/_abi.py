@@ -29,6 +29,7 @@ EXPORTS = [
     "clr_create", "clr_compress", "clr_destroy", "clr_matrix_info", "clr_get_meta",
     "clr_get_block", "clr_to_dense", "clr_gemm", "clr_axpby", "clr_sqrt_inv",
     "clr_identity_residual", "clr_gemm_backward", "clr_sqrt_inv_backward",
+    "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
 ]
 
 
@@ -103,6 +104,12 @@ def _load():
         "clr_gemm_backward": [P, P, P, D, P, I64, P, I64, P, I64],
         "clr_sqrt_inv_backward": [P, P, C.POINTER(SqrtInvOpts), C.c_int, C.c_int, P, P, I64,
                                   C.POINTER(P)],
+        "clr_plan_create": [P, C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(GemmOpts), C.c_int,
+                            C.POINTER(P), C.POINTER(P)],
+        "clr_plan_execute": [P, P, C.POINTER(GemmStats)],
+        "clr_plan_destroy": [P],
+        "clr_gemm_batch": [P, C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(GemmOpts),
+                           C.POINTER(P), C.POINTER(GemmStats)],
     }
     for name, args in sig.items():
         f = getattr(h, name)

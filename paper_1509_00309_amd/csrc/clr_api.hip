@@ -811,6 +811,316 @@ extern "C" clr_status clr_gemm(clr_context* ctx, const clr_matrix* A, const clr_
 }
 
 // ---------------------------------------------------------------------------
+// Batches of products: one plan, one launch per phase for the whole batch
+// ---------------------------------------------------------------------------
+
+struct clr_plan {
+  clr_context* ctx = nullptr;
+  int nprod = 0;
+  clr_gemm_opts o{};
+  std::vector<const clr_matrix*> A, B;
+  std::vector<clr_matrix*> C;
+  // execution buffers owned by the plan (a captured graph keeps their addresses)
+  DevBuf seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2, items_thin2, pieces, rec,
+      pool, scratch, acc, recg, status, bases;
+  int64_t n_thin1 = 0, n_thin2 = 0, n_dense = 0, n_rec = 0;
+  double flops[kNumStats] = {};
+  int64_t counts[kNumCounters] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void plan_free(clr_plan* pl) {
+  if (!pl) return;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  for (DevBuf* b : {&pl->seg_dense, &pl->items_dense, &pl->seg_thin1, &pl->items_thin1,
+                    &pl->seg_thin2, &pl->items_thin2, &pl->pieces, &pl->rec, &pl->pool,
+                    &pl->scratch, &pl->acc, &pl->recg, &pl->status, &pl->bases})
+    free_buf(*b);
+  delete pl;
+}
+
+// The execution phase of a planned batch: factor products, dense accumulation,
+// recompression (with its output products).  Only kernel launches on the
+// context stream, so it can be recorded into a graph.
+hipError_t plan_launch(clr_plan* pl, hipStream_t s) {
+  const clr_gemm_opts* o = &pl->o;
+  hipError_t e = run_ggemm(o, as<GemmItem>(pl->items_thin1), as<Seg>(pl->seg_thin1), (int)pl->n_thin1, s);
+  if (e == hipSuccess)
+    e = run_ggemm(o, as<GemmItem>(pl->items_thin2), as<Seg>(pl->seg_thin2), (int)pl->n_thin2, s);
+  if (e == hipSuccess)
+    e = run_ggemm(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense, s, true);
+  if (e == hipSuccess && pl->n_rec > 0) {
+    const size_t gi_bytes = (sizeof(GemmItem) * (size_t)pl->n_rec + 255) / 256 * 256;
+    GemmItem* gi = static_cast<GemmItem*>(pl->recg.p);
+    Seg* gs = reinterpret_cast<Seg*>(static_cast<char*>(pl->recg.p) + gi_bytes);
+    e = launch_recompress(as<RecItem>(pl->rec), as<Piece>(pl->pieces), (int)pl->n_rec, o->tol,
+                          as<int>(pl->status), gi, gs, s);
+  }
+  return e;
+}
+
+clr_status plan_status(clr_context* ctx, clr_plan* pl) {
+  int h = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&h, pl->status.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (h == 0) return CLR_OK;
+  HIP_TRY(ctx, launch_fill_i32(as<int>(pl->status), 0, 1, ctx->stream));
+  if (h & 2) return fail(ctx, CLR_ERR_NONFINITE, "non-finite block norm");
+  if (h & (4 | 8)) return fail(ctx, CLR_ERR_INTERNAL, "recompression working set mis-planned");
+  return fail(ctx, CLR_ERR_INTERNAL, "Jacobi SVD did not converge");
+}
+
+// Screening and work lists of every product (device symbolic phase per product,
+// one read-back of all totals), output matrices, and the filled lists.
+clr_status plan_build(clr_context* ctx, clr_plan* pl) {
+  const int np = pl->nprod;
+  hipStream_t stream = ctx->stream;
+  std::vector<PlanParams> P(np);
+  std::vector<int64_t> pb(np + 1, 0);
+  pl->C.assign(np, nullptr);
+  for (int p = 0; p < np; ++p) {
+    const clr_matrix* A = pl->A[p];
+    const clr_matrix* B = pl->B[p];
+    if (A->cs != B->rs)
+      return fail(ctx, CLR_ERR_SHAPE, "product %d: column blocking of A differs from row blocking of B", p);
+    clr_status s = alloc_matrix(ctx, A->rs, B->cs, &pl->C[p]);
+    if (s != CLR_OK) return s;
+    PlanParams& q = P[p];
+    q = PlanParams{};
+    q.A = A->view();
+    q.B = B->view();
+    q.nrb = A->nrb;
+    q.ncb = B->ncb;
+    q.nkb = A->ncb;
+    q.eps_sp = pl->o.eps_sp;
+    q.screen = pl->o.screen;
+    q.alpha = pl->o.alpha;
+    q.tol = pl->o.tol;
+    q.square = (A->rs == B->cs) ? 1 : 0;
+    q.max_item = max_item(&pl->o);
+    q.mask_kind = nullptr;
+    pb[p + 1] = pb[p] + (int64_t)q.nrb * q.ncb;
+  }
+  const int64_t tp = pb[np];
+  const size_t tot_bytes = (size_t)np * (sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats);
+  HIP_TRY(ctx, ensure(ctx->cnt, sizeof(int64_t) * kNumCounters * tp));
+  HIP_TRY(ctx, ensure(ctx->off, sizeof(int64_t) * kNumCounters * tp));
+  HIP_TRY(ctx, ensure(ctx->st, sizeof(double) * kNumStats * tp));
+  HIP_TRY(ctx, ensure(ctx->flags, sizeof(int) * tp));
+  HIP_TRY(ctx, ensure(ctx->totals, tot_bytes));
+  int64_t* tc = as<int64_t>(ctx->totals);
+  double* ts = reinterpret_cast<double*>(tc + (size_t)np * kNumCounters);
+  for (int p = 0; p < np; ++p) {
+    const int64_t npairs = pb[p + 1] - pb[p];
+    int64_t* cnt = as<int64_t>(ctx->cnt) + kNumCounters * pb[p];
+    int64_t* off = as<int64_t>(ctx->off) + kNumCounters * pb[p];
+    double* st = as<double>(ctx->st) + kNumStats * pb[p];
+    HIP_TRY(ctx, launch_symbolic(P[p], cnt, st, as<int>(ctx->flags) + pb[p], stream));
+    HIP_TRY(ctx, launch_scan(cnt, off, npairs, kNumCounters, tc + (size_t)p * kNumCounters, stream));
+    HIP_TRY(ctx, launch_reduce(st, npairs, kNumStats, ts + (size_t)p * kNumStats, stream));
+  }
+  std::vector<int64_t> hc((size_t)np * kNumCounters);
+  std::vector<double> hs((size_t)np * kNumStats);
+  HIP_TRY(ctx, hipMemcpyAsync(hc.data(), tc, sizeof(int64_t) * hc.size(), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(hs.data(), ts, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  // place of every product in the concatenated lists
+  std::vector<int64_t> base((size_t)np * kNumCounters);
+  int64_t sum[kNumCounters] = {};
+  for (int p = 0; p < np; ++p)
+    for (int c = 0; c < kNumCounters; ++c) {
+      const int64_t v = hc[(size_t)p * kNumCounters + c];
+      if (v < 0) return fail(ctx, CLR_ERR_INTERNAL, "negative work count");
+      base[(size_t)p * kNumCounters + c] = sum[c];
+      sum[c] += v;
+    }
+  for (int c = 0; c < kNumCounters; ++c) {
+    if (c != kCntPool && c != kCntScratch && sum[c] > INT32_MAX)
+      return fail(ctx, CLR_ERR_CAPACITY, "batch work list %d too long (%lld)", c, (long long)sum[c]);
+    pl->counts[c] = sum[c];
+  }
+  for (int p = 0; p < np; ++p)
+    for (int k = 0; k < kNumStats; ++k) pl->flops[k] += hs[(size_t)p * kNumStats + k];
+  pl->n_thin1 = sum[kCntThin1];
+  pl->n_thin2 = sum[kCntThin2];
+  pl->n_dense = sum[kCntGemmItems];
+  pl->n_rec = sum[kCntComputed];
+  int64_t acc_total = 0;
+  std::vector<int64_t> acc_base(np);
+  for (int p = 0; p < np; ++p) {
+    acc_base[p] = acc_total;
+    acc_total += pl->C[p]->rows * pl->C[p]->cols;
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = ensure(pl->seg_dense, sizeof(Seg) * sum[kCntSegDense]);
+  if (e == hipSuccess) e = ensure(pl->items_dense, sizeof(GemmItem) * sum[kCntGemmItems]);
+  if (e == hipSuccess) e = ensure(pl->seg_thin1, sizeof(Seg) * sum[kCntThin1]);
+  if (e == hipSuccess) e = ensure(pl->items_thin1, sizeof(GemmItem) * sum[kCntThin1]);
+  if (e == hipSuccess) e = ensure(pl->seg_thin2, sizeof(Seg) * sum[kCntThin2]);
+  if (e == hipSuccess) e = ensure(pl->items_thin2, sizeof(GemmItem) * sum[kCntThin2]);
+  if (e == hipSuccess) e = ensure(pl->pieces, sizeof(Piece) * sum[kCntPieces]);
+  if (e == hipSuccess) e = ensure(pl->rec, sizeof(RecItem) * sum[kCntComputed]);
+  if (e == hipSuccess) e = ensure(pl->pool, sizeof(double) * sum[kCntPool]);
+  if (e == hipSuccess) e = ensure(pl->scratch, sizeof(double) * sum[kCntScratch]);
+  if (e == hipSuccess && sum[kCntGemmItems] > 0) e = ensure(pl->acc, sizeof(double) * (size_t)acc_total);
+  if (e == hipSuccess) {
+    const size_t n = (size_t)std::max<int64_t>(sum[kCntComputed], 1);
+    e = ensure(pl->recg, (sizeof(GemmItem) * n + 255) / 256 * 256 + sizeof(Seg) * n);
+  }
+  if (e == hipSuccess) e = ensure(pl->status, sizeof(int));
+  if (e == hipSuccess) e = launch_fill_i32(as<int>(pl->status), 0, 1, stream);
+  if (e != hipSuccess) return fail(ctx, CLR_ERR_HIP, "batch work lists: %s", hipGetErrorString(e));
+  clr_status s = CLR_OK;
+  {
+    // the bases must stay valid until the shift kernels have run
+    HIP_TRY(ctx, ensure(pl->bases, sizeof(int64_t) * base.size()));
+    HIP_TRY(ctx, hipMemcpyAsync(pl->bases.p, base.data(), sizeof(int64_t) * base.size(),
+                                hipMemcpyHostToDevice, stream));
+  }
+  for (int p = 0; p < np; ++p) {
+    const int64_t npairs = pb[p + 1] - pb[p];
+    int64_t* off = as<int64_t>(ctx->off) + kNumCounters * pb[p];
+    HIP_TRY(ctx, launch_add_base(off, npairs, kNumCounters, as<int64_t>(pl->bases) + (size_t)p * kNumCounters, stream));
+    FillParams F;
+    F.off = off;
+    F.cnt = as<int64_t>(ctx->cnt) + kNumCounters * pb[p];
+    F.flags = as<int>(ctx->flags) + pb[p];
+    F.seg_dense = as<Seg>(pl->seg_dense);
+    F.items_dense = as<GemmItem>(pl->items_dense);
+    F.seg_thin1 = as<Seg>(pl->seg_thin1);
+    F.items_thin1 = as<GemmItem>(pl->items_thin1);
+    F.seg_thin2 = as<Seg>(pl->seg_thin2);
+    F.items_thin2 = as<GemmItem>(pl->items_thin2);
+    F.pieces = as<Piece>(pl->pieces);
+    F.rec = as<RecItem>(pl->rec);
+    F.pool = as<double>(pl->pool);
+    F.scratch = as<double>(pl->scratch);
+    F.acc = pl->acc.p ? as<double>(pl->acc) + acc_base[p] : nullptr;
+    F.c_arena = pl->C[p]->arena;
+    F.c_kind = pl->C[p]->d_kind;
+    F.c_rank = pl->C[p]->d_rank;
+    F.c_norm = pl->C[p]->d_norm;
+    F.c_ncols = pl->C[p]->cols;
+    HIP_TRY(ctx, launch_fill(P[p], F, stream));
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(stream));
+  return s;
+}
+
+void plan_stats(const clr_plan* pl, clr_gemm_stats* st) {
+  memset(st, 0, sizeof(*st));
+  st->candidates = (int64_t)pl->flops[kStCandidate];
+  st->computed = pl->counts[kCntComputed];
+  st->n_dd = (int64_t)pl->flops[kStNDD];
+  st->n_ld = (int64_t)pl->flops[kStNLD];
+  st->n_dl = (int64_t)pl->flops[kStNDL];
+  st->n_ll = (int64_t)pl->flops[kStNLL];
+  st->triples = st->n_dd + st->n_ld + st->n_dl + st->n_ll;
+  st->flops_dd = pl->flops[kStFlopsDD];
+  st->flops_ld = pl->flops[kStFlopsLD];
+  st->flops_dl = pl->flops[kStFlopsDL];
+  st->flops_ll = pl->flops[kStFlopsLL];
+  st->flops_densify = pl->flops[kStFlopsDensify];
+  st->flops_products = st->flops_dd + st->flops_ld + st->flops_dl + st->flops_ll + st->flops_densify;
+  st->flops_rec_engine = pl->flops[kStFlopsRecEngine];
+}
+
+}  // namespace
+
+extern "C" clr_status clr_plan_create(clr_context* ctx, int nprod, const clr_matrix* const* A,
+                                      const clr_matrix* const* B, const clr_gemm_opts* opts,
+                                      int use_graph, clr_plan** plan, clr_matrix** C) {
+  if (!ctx || !A || !B || !plan || !C || nprod < 1) return CLR_ERR_INVALID_ARG;
+  *plan = nullptr;
+  for (int p = 0; p < nprod; ++p) {
+    C[p] = nullptr;
+    if (!A[p] || !B[p]) return fail(ctx, CLR_ERR_INVALID_ARG, "null operand in product %d", p);
+  }
+  clr_status s = check_opts(ctx, opts);
+  if (s != CLR_OK) return s;
+  clr_plan* pl = new clr_plan();
+  pl->ctx = ctx;
+  pl->nprod = nprod;
+  pl->o = *opts;
+  pl->A.assign(A, A + nprod);
+  pl->B.assign(B, B + nprod);
+  auto bail = [&](clr_status code) {
+    for (auto* m : pl->C) free_matrix(m);
+    plan_free(pl);
+    return code;
+  };
+  if ((s = plan_build(ctx, pl)) != CLR_OK) return bail(s);
+  if (use_graph) {
+    // Record the execution phase once on a capture stream of its own (the
+    // context stream may be the legacy default stream, which cannot be
+    // captured); executing the plan replays the graph on the context stream.
+    HIP_TRY(ctx, prepare_recompress());
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t le = plan_launch(pl, cs);
+      e = hipStreamEndCapture(cs, &pl->graph);
+      if (e == hipSuccess) e = le;
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+      return bail(fail(ctx, CLR_ERR_HIP, "graph capture: %s", hipGetErrorString(e)));
+  }
+  for (int p = 0; p < nprod; ++p) C[p] = pl->C[p];
+  *plan = pl;
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_plan_execute(clr_context* ctx, clr_plan* pl, clr_gemm_stats* st) {
+  if (!ctx || !pl || pl->ctx != ctx) return CLR_ERR_INVALID_ARG;
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+  if (pl->exec) {
+    HIP_TRY(ctx, hipGraphLaunch(pl->exec, ctx->stream));
+  } else {
+    HIP_TRY(ctx, plan_launch(pl, ctx->stream));
+  }
+  HIP_TRY(ctx, hipEventRecord(ctx->ev[3], ctx->stream));
+  clr_status s = plan_status(ctx, pl);
+  if (s != CLR_OK) return s;
+  if (st) {
+    plan_stats(pl, st);
+    st->ms_total = elapsed(ctx->ev[0], ctx->ev[3]);
+    st->ms_products = st->ms_total;
+  }
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_plan_destroy(clr_plan* pl) {
+  if (!pl) return CLR_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(pl->ctx->stream);
+  plan_free(pl);
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_gemm_batch(clr_context* ctx, int nprod, const clr_matrix* const* A,
+                                     const clr_matrix* const* B, const clr_gemm_opts* opts,
+                                     clr_matrix** C, clr_gemm_stats* st) {
+  clr_plan* pl = nullptr;
+  clr_status s = clr_plan_create(ctx, nprod, A, B, opts, 0, &pl, C);
+  if (s != CLR_OK) return s;
+  s = clr_plan_execute(ctx, pl, st);
+  clr_plan_destroy(pl);
+  if (s != CLR_OK) {
+    for (int p = 0; p < nprod; ++p) {
+      free_matrix(C[p]);
+      C[p] = nullptr;
+    }
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
 // Blockwise combination a X + b Y + c I
 // ---------------------------------------------------------------------------
 

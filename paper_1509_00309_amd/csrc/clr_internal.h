@@ -203,6 +203,9 @@ hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, 
                        hipStream_t s);
 hipError_t launch_reduce(const double* in, int64_t n, int narrays, double* totals, hipStream_t s);
 hipError_t launch_fill(const PlanParams& P, const FillParams& F, hipStream_t s);
+hipError_t launch_add_base(int64_t* off, int64_t n, int narrays, const int64_t* base,
+                           hipStream_t s);
+hipError_t prepare_recompress();
 hipError_t launch_ingest(const MatView& M, double* arena, const double* const* f0,
                          const double* const* f1, double* norm_out, hipStream_t s);
 hipError_t launch_to_dense(const MatView& M, double* out, int64_t ld, hipStream_t s);

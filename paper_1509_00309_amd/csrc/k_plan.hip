@@ -383,6 +383,23 @@ hipError_t launch_reduce(const double* in, int64_t n, int narrays, double* total
   return hipGetLastError();
 }
 
+// Shift the exclusive prefix sums of one product of a batch by that product's
+// place in the batch's concatenated work lists (base[a] for array a).
+__global__ void k_add_base(int64_t* __restrict__ off, int64_t n, int narrays,
+                           const int64_t* __restrict__ base) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int a = 0; a < narrays; ++a) off[(int64_t)a * n + i] += base[a];
+}
+
+hipError_t launch_add_base(int64_t* off, int64_t n, int narrays, const int64_t* base,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_base, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, off, n,
+                     narrays, base);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(const PlanParams& P, const FillParams& F, hipStream_t s) {
   const int npairs = P.nrb * P.ncb;
   if (npairs == 0) return hipSuccess;

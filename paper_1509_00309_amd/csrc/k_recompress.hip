@@ -1758,19 +1758,27 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* _
   dense_path<true>(it, tol, lds, status, sh, gout, gseg, item);
 }
 
+// Dynamic-LDS limits of the recompression kernels; done once, before any
+// launch (and before any stream capture that records one).
+hipError_t prepare_recompress() {
+  static bool attr_set = false;
+  if (attr_set) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_recompress,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kRecLdsBytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_recompress_reg,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kRecLdsBytes);
+  if (e == hipSuccess) attr_set = true;
+  return e;
+}
+
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
                              int* status, GemmItem* gout, Seg* gseg, hipStream_t s,
                              hipEvent_t engine_begin, hipEvent_t engine_end) {
   if (nitems <= 0) return hipSuccess;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_recompress,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kRecLdsBytes);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_recompress_reg,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kRecLdsBytes);
+  {
+    hipError_t e = prepare_recompress();
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   const int grid = ((nitems + 7) / 8) * 8;
   // every item's output-product slot starts empty (m = 0: nothing to compute)

@@ -364,3 +364,60 @@ def test_autograd_entry_points(ctx, torch):
     (W * Wb).sum().backward()
     dS, _ = ctx.sqrt_inv_backward(S, Wb, 4, 2, wl.tol, wl.eps_sp)
     assert torch.equal(s.grad, dS)
+
+
+# ---------------------------------------------------------------------------
+# Batches: one launch per phase, HIP graph replay
+# ---------------------------------------------------------------------------
+
+def _batch_operands(ctx, torch):
+    ops = []
+    for seed in (501, 502):
+        rs, ks, cs = [40, 17, 64], [25, 48, 9, 70], [31, 64, 12, 20]
+        ra = random_blocks(seed, rs, ks, p_zero=0.3, p_dense=0.4, max_rank=8)
+        rb = random_blocks(seed + 50, ks, cs, p_zero=0.3, p_dense=0.4, max_rank=8)
+        ops.append((gpu_from_random(ctx, torch, ra), gpu_from_random(ctx, torch, rb)))
+    wl = config1()
+    S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    ops.append((S, S))
+    wl3 = scaled_config("c2", 1536, seed=143)
+    S3 = ctx.compress(torch.from_numpy(wl3.dense()).cuda(), wl3.sizes, wl3.sizes, wl3.tol, 1e-10)
+    ops.append((S3, S3))
+    return ops
+
+
+def test_gemm_batch_matches_single_products(ctx, torch):
+    """A batch of products of different blockings equals the products one by one, bit for bit."""
+    log("gemm batch vs single products")
+    ops = _batch_operands(ctx, torch)
+    As, Bs = [a for a, _ in ops], [b for _, b in ops]
+    Cs, st = ctx.gemm_batch(As, Bs, 1e-8, 1e-10, stats=True)
+    total = 0.0
+    for (A, B), Cb in zip(ops, Cs):
+        C1, s1 = ctx.gemm(A, B, 1e-8, 1e-10, stats=True)
+        assert np.array_equal(Cb.to_dense().cpu().numpy(), C1.to_dense().cpu().numpy())
+        kb, rb, nb = Cb.meta()
+        k1, r1, n1 = C1.meta()
+        assert np.array_equal(kb, k1) and np.array_equal(rb, r1) and np.array_equal(nb, n1)
+        total += s1.flops_products
+    assert abs(st.flops_products - total) <= 1e-9 * total
+    log(f"  {len(ops)} products, {st.computed} blocks, {st.flops_products:.3e} flops")
+
+
+def test_plan_graph_replay(ctx, torch):
+    """A plan recorded as a HIP graph gives the eager result on every replay."""
+    log("plan graph replay")
+    ops = _batch_operands(ctx, torch)
+    As, Bs = [a for a, _ in ops], [b for _, b in ops]
+    ref = [c.to_dense().cpu().numpy() for c in ctx.gemm_batch(As, Bs, 1e-8, 1e-10)]
+    plan = ctx.plan(As, Bs, 1e-8, 1e-10, graph=True)
+    for rep in range(3):
+        plan.execute()
+        got = [c.to_dense().cpu().numpy() for c in plan.outputs]
+        for g, r in zip(got, ref):
+            assert np.array_equal(g, r), f"replay {rep} differs"
+        # unrelated eager work between replays
+        X = ctx.gemm(As[0], Bs[0], 0.0, 0.0)
+        del X
+        torch.cuda.synchronize()
+    plan.close()
