@@ -203,6 +203,22 @@ clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_ma
                              double alpha, const double* dC, int64_t ldc, double* dA,
                              int64_t lda, double* dB, int64_t ldb);
 
+/* Largest output-tile edge of the grouped-GEMM items of the dense-accumulation
+ * launch and of the factor-product launches, per precision (CLR_FP64 or
+ * CLR_MIXED) for this context: 0 (default) is the kernel's full tile (160 in
+ * the FP64 form, 128 in the mixed form), otherwise a multiple of 16 up to it.
+ * Results do not depend on these edges, only the launch shapes do. */
+clr_status clr_set_tile_edges(clr_context* ctx, int precision, int dense_edge, int thin_edge);
+
+/* Autotuner: times the product A B (options as for clr_gemm; output discarded)
+ * with every candidate edge (multiples of 32 up to the full tile), best of two
+ * runs per candidate, and keeps the fastest edge per launch class for this
+ * context and precision.  Returns the chosen edges and their launch times (ms);
+ * any output pointer may be NULL. */
+clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
+                        const clr_gemm_opts* opts, int* dense_edge, int* thin_edge,
+                        double* ms_dense, double* ms_thin);
+
 /* Batched products C_p = A_p B_p (p < nprod), each with the semantics of
  * clr_gemm (Sec. 4.1).  Planning screens every product on the device and
  * reads back all work totals once; execution runs one launch per phase for the

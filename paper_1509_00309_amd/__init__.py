@@ -167,6 +167,22 @@ class Context:
         self._check(rc)
         return CLRMatrix(self, h), st
 
+    # -- launch shapes -----------------------------------------------------------
+    def set_tile_edges(self, precision="fp64", dense_edge: int = 0, thin_edge: int = 0):
+        prec = {"fp64": CLR_FP64, "mixed": CLR_MIXED}[precision]
+        self._check(lib.clr_set_tile_edges(self._h, prec, int(dense_edge), int(thin_edge)))
+
+    def autotune(self, A: "CLRMatrix", B: "CLRMatrix", tol: float, eps_sp: float, screen="abs",
+                 precision="fp64", split: int = 0) -> dict:
+        """Pick the grouped-GEMM item edges for this context by timing A B."""
+        o = _gemm_opts(tol, eps_sp, screen, precision, split, 1.0)
+        de, te = C.c_int(), C.c_int()
+        md, mt = C.c_double(), C.c_double()
+        self._check(lib.clr_autotune(self._h, A._h, B._h, C.byref(o), C.byref(de), C.byref(te),
+                                     C.byref(md), C.byref(mt)))
+        return {"dense_edge": de.value, "thin_edge": te.value, "ms_dense": md.value,
+                "ms_thin": mt.value}
+
     # -- batches of products ----------------------------------------------------
     def plan(self, As: Sequence["CLRMatrix"], Bs: Sequence["CLRMatrix"], tol: float,
              eps_sp: float, screen="abs", precision="fp64", split: int = 0,

@@ -30,6 +30,7 @@ EXPORTS = [
     "clr_get_block", "clr_to_dense", "clr_gemm", "clr_axpby", "clr_sqrt_inv",
     "clr_identity_residual", "clr_gemm_backward", "clr_sqrt_inv_backward",
     "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
+    "clr_set_tile_edges", "clr_autotune",
 ]
 
 
@@ -108,6 +109,8 @@ def _load():
                             C.POINTER(P), C.POINTER(P)],
         "clr_plan_execute": [P, P, C.POINTER(GemmStats)],
         "clr_plan_destroy": [P],
+        "clr_set_tile_edges": [P, C.c_int, C.c_int, C.c_int],
+        "clr_autotune": [P, P, P, C.POINTER(GemmOpts), IP, IP, DP, DP],
         "clr_gemm_batch": [P, C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(GemmOpts),
                            C.POINTER(P), C.POINTER(GemmStats)],
     }

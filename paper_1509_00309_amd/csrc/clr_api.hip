@@ -42,6 +42,10 @@ struct clr_context {
       items_thin2, pieces, rec, pool, scratch, acc, status, terms, aux_items, aux_segs,
       aux_dense, ptrs, recg;
   hipEvent_t ev[10] = {};
+  // grouped-GEMM item edges per precision (0: the kernel's largest tile), set
+  // explicitly or by clr_autotune
+  int tile_dense[2] = {0, 0};
+  int tile_thin[2] = {0, 0};
   // Stream-ordered cache of freed matrix allocations: a matrix released on the
   // context stream can back the next matrix of a similar size without a
   // hipMalloc (all users are ordered on the same stream).
@@ -269,6 +273,12 @@ hipError_t run_ggemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* s
 
 int max_item(const clr_gemm_opts* o) {
   return o->precision == CLR_MIXED ? kMaxItemF32 : kMaxItemF64;
+}
+
+int tile_edge(const clr_context* ctx, const clr_gemm_opts* o, bool thin) {
+  const int pi = o->precision == CLR_MIXED ? 1 : 0;
+  const int v = thin ? ctx->tile_thin[pi] : ctx->tile_dense[pi];
+  return v > 0 ? v : max_item(o);
 }
 
 // Read and clear the device status word; map it to a status code.
@@ -674,7 +684,8 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   P.alpha = o->alpha;
   P.tol = o->tol;
   P.square = (A->rs == B->cs) ? 1 : 0;
-  P.max_item = max_item(o);
+  P.max_item = tile_edge(ctx, o, false);
+  P.max_item_thin = tile_edge(ctx, o, true);
   P.mask_kind = mask ? mask->d_kind : nullptr;
   const int64_t npairs = (int64_t)P.nrb * P.ncb;
   hipError_t e = hipSuccess;
@@ -811,6 +822,75 @@ extern "C" clr_status clr_gemm(clr_context* ctx, const clr_matrix* A, const clr_
 }
 
 // ---------------------------------------------------------------------------
+// Tile edges of the grouped GEMM and their autotuner
+// ---------------------------------------------------------------------------
+
+extern "C" clr_status clr_set_tile_edges(clr_context* ctx, int precision, int dense_edge,
+                                         int thin_edge) {
+  if (!ctx) return CLR_ERR_INVALID_ARG;
+  if (precision != CLR_FP64 && precision != CLR_MIXED)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "bad precision");
+  const int top = precision == CLR_MIXED ? kMaxItemF32 : kMaxItemF64;
+  for (int v : {dense_edge, thin_edge})
+    if (v != 0 && (v < 16 || v > top || v % 16 != 0))
+      return fail(ctx, CLR_ERR_INVALID_ARG, "tile edge %d: 0 or a multiple of 16 in [16, %d]", v, top);
+  ctx->tile_dense[precision] = dense_edge;
+  ctx->tile_thin[precision] = thin_edge;
+  return CLR_OK;
+}
+
+// Empirical choice, on the caller's own product, of the largest item edge of
+// the dense-accumulation launch and of the factor-product launches: every
+// candidate edge (multiples of 32 up to the kernel's tile) is timed on the
+// product (best of two runs, device events around each launch class) and the
+// fastest per launch class is kept for this context and precision.  The
+// numerical result does not depend on the edges: every output element is
+// accumulated over the same inner sequence whatever the tiling.
+extern "C" clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
+                                   const clr_gemm_opts* opts, int* dense_edge, int* thin_edge,
+                                   double* ms_dense, double* ms_thin) {
+  if (!ctx || !A || !B) return CLR_ERR_INVALID_ARG;
+  clr_status s = check_opts(ctx, opts);
+  if (s != CLR_OK) return s;
+  const int pi = opts->precision == CLR_MIXED ? 1 : 0;
+  const int top = max_item(opts);
+  double best_d = 1e300, best_t = 1e300;
+  int arg_d = top, arg_t = top;
+  for (int edge = 32; edge <= top; edge += 32) {
+    ctx->tile_dense[pi] = edge;
+    ctx->tile_thin[pi] = edge;
+    double td = 1e300, tt = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      clr_matrix* C = nullptr;
+      clr_gemm_stats st{};
+      s = gemm_impl(ctx, A, B, opts, &C, &st);
+      free_matrix(C);
+      if (s != CLR_OK) {
+        ctx->tile_dense[pi] = ctx->tile_thin[pi] = 0;
+        return s;
+      }
+      td = std::min(td, st.ms_dense);
+      tt = std::min(tt, st.ms_thin);
+    }
+    if (td < best_d) {
+      best_d = td;
+      arg_d = edge;
+    }
+    if (tt < best_t) {
+      best_t = tt;
+      arg_t = edge;
+    }
+  }
+  ctx->tile_dense[pi] = arg_d;
+  ctx->tile_thin[pi] = arg_t;
+  if (dense_edge) *dense_edge = arg_d;
+  if (thin_edge) *thin_edge = arg_t;
+  if (ms_dense) *ms_dense = best_d;
+  if (ms_thin) *ms_thin = best_t;
+  return CLR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Batches of products: one plan, one launch per phase for the whole batch
 // ---------------------------------------------------------------------------
 
@@ -901,7 +981,8 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     q.alpha = pl->o.alpha;
     q.tol = pl->o.tol;
     q.square = (A->rs == B->cs) ? 1 : 0;
-    q.max_item = max_item(&pl->o);
+    q.max_item = tile_edge(ctx, &pl->o, false);
+    q.max_item_thin = tile_edge(ctx, &pl->o, true);
     q.mask_kind = nullptr;
     pb[p + 1] = pb[p] + (int64_t)q.nrb * q.ncb;
   }
@@ -1146,7 +1227,7 @@ extern "C" clr_status clr_axpby(clr_context* ctx, double a, const clr_matrix* X,
   std::vector<Seg> segs;
   std::vector<int64_t> scratch_off;
   int64_t scratch_total = 0;
-  const int maxe = max_item(o);
+  const int maxe = tile_edge(ctx, o, false);
   HIP_TRY(ctx, ensure(ctx->acc, sizeof(double) * (size_t)X->rows * X->cols));
   double* acc = as<double>(ctx->acc);
   for (int I = 0; I < X->nrb; ++I)

@@ -150,7 +150,8 @@ struct PlanParams {
   double alpha;
   double tol;
   int square;     // C's row and column blockings are identical
-  int max_item;   // largest output tile edge of the grouped GEMM
+  int max_item;       // largest output tile edge of a dense-accumulation GEMM item
+  int max_item_thin;  // largest output tile edge of a factor-product (thin) GEMM item
   const int* mask_kind;   // optional: only blocks stored in this kind table are computed
 };
 

@@ -51,30 +51,30 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
       ++nld;
       rcat += ra;
       pool += (int64_t)n * ra;
-      thin1 += parts2(n, ra, P.max_item);
+      thin1 += parts2(n, ra, P.max_item_thin);
       fld += 2.0 * ra * (double)k * n;
     } else if (ka == 1 && kb == 2) {
       const int rb = P.B.rank[K * P.ncb + J];
       ++ndl;
       rcat += rb;
       pool += (int64_t)m * rb;
-      thin1 += parts2(m, rb, P.max_item);
+      thin1 += parts2(m, rb, P.max_item_thin);
       fdl += 2.0 * m * (double)k * rb;
     } else {
       const int ra = P.A.rank[I * P.nkb + K];
       const int rb = P.B.rank[K * P.ncb + J];
       ++nll;
       pool += (int64_t)ra * rb;
-      thin1 += parts2(ra, rb, P.max_item);
+      thin1 += parts2(ra, rb, P.max_item_thin);
       if (rb < ra) {
         rcat += rb;
         pool += (int64_t)m * rb;
-        thin2 += parts2(m, rb, P.max_item);
+        thin2 += parts2(m, rb, P.max_item_thin);
         fll += 2.0 * k * (double)ra * rb + 2.0 * m * (double)ra * rb;
       } else {
         rcat += ra;
         pool += (int64_t)n * ra;
-        thin2 += parts2(n, ra, P.max_item);
+        thin2 += parts2(n, ra, P.max_item_thin);
         fll += 2.0 * k * (double)ra * rb + 2.0 * n * (double)ra * rb;
       }
     }
@@ -268,7 +268,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
       double* T = F.pool + po;
       po += (int64_t)n * ra;
       emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(b, k, 1, Va, 1, k, k, 1.0), T, n, n, ra,
-                P.max_item);
+                P.max_item_thin);
       dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
       pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
     } else if (ka == 1 && kbk == 2) {
@@ -279,7 +279,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
       double* T = F.pool + po;
       po += (int64_t)m * rb;
       emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(a, 1, m, Ub, 1, k, k, 1.0), T, m, m, rb,
-                P.max_item);
+                P.max_item_thin);
       dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
       pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
     } else {
@@ -293,18 +293,18 @@ __global__ void k_fill(PlanParams P, FillParams F) {
       double* Z = F.pool + po;
       po += (int64_t)ra * rb;
       emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(Va, k, 1, Ub, 1, k, k, 1.0), Z, ra, ra,
-                rb, P.max_item);
+                rb, P.max_item_thin);
       double* T = F.pool + po;
       if (rb < ra) {
         po += (int64_t)m * rb;   // T = U_A Z (m x rB)
         emit_thin(F.seg_thin2, F.items_thin2, t2, make_seg(Ua, 1, m, Z, 1, ra, ra, 1.0), T, m, m,
-                  rb, P.max_item);
+                  rb, P.max_item_thin);
         dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
         pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
       } else {
         po += (int64_t)n * ra;   // T = V_B Z^T (n x rA)
         emit_thin(F.seg_thin2, F.items_thin2, t2, make_seg(Vb, 1, n, Z, ra, 1, rb, 1.0), T, n, n,
-                  ra, P.max_item);
+                  ra, P.max_item_thin);
         dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
         pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
       }
