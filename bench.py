@@ -190,6 +190,91 @@ def run_sqrtinv(ctx, n, forms, log_fn):
             "forms": out}
 
 
+def run_batched(ctx, nprod, log_fn):
+    """Config-3 batch: nprod independent products S_p * S_p (N_p ~ U{512..4096}, 16..48
+    uneven clusters, tol 1e-8) planned once and executed as one graph replay per form;
+    plus the full-rank dense limit (N = 4096, 32 blocks, truncation and screening off)
+    against the dense FP64 GEMM of the same matrix."""
+    import torch
+    from workloads import config3_dense_limit, config3_product
+    t0 = time.perf_counter()
+    mats, dense_eq, total_n2 = [], 0.0, 0
+    for p in range(nprod):
+        wl = config3_product(p)
+        Sd = torch.from_numpy(wl.dense()).cuda()
+        mats.append(ctx.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10))
+        dense_eq += 2.0 * float(wl.n) ** 3
+        total_n2 += wl.n * wl.n
+        del Sd
+    torch.cuda.synchronize()
+    log_fn(f"  batch of {nprod} products built in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": f"{nprod} independent products S_p*S_p, N_p ~ U{{512..4096}} (seed 3000+p), "
+                       f"16..48 uneven clusters, 3D lattice exp(-0.3 r^2)+0.1 delta, tol 1e-8, "
+                       f"screen 1e-10; one plan, execution replayed as a HIP graph",
+           "products": nprod, "dense_equivalent_flops": dense_eq, "forms": {}}
+    for form in ("mixed", "fp64"):
+        plan = ctx.plan(mats, mats, 1e-8, 1e-10, precision=form, graph=True)
+        plan.execute()
+        torch.cuda.synchronize()
+        ms = []
+        st = None
+        for _ in range(3):
+            st = plan.execute(stats=True)
+            ms.append(st.ms_total)
+        d = st.as_dict()
+        t = float(np.median(ms))
+        out["forms"][form] = {"ms_per_batch": t, "flops": d["flops_products"],
+                              "tflops": d["flops_products"] / (t * 1e-3) / 1e12,
+                              "dense_equivalent_tflops": dense_eq / (t * 1e-3) / 1e12,
+                              "blocks_computed": d["computed"]}
+        if form == "fp64":
+            ref = [c.to_dense() for c in plan.outputs[:8]]
+        else:
+            mix = [c.to_dense() for c in plan.outputs[:8]]
+        plan.close()
+        del plan
+        log_fn(f"  batch {form}: {out['forms'][form]}")
+    num = sum(float(torch.linalg.norm(a - b) ** 2) for a, b in zip(mix, ref))
+    den = sum(float(torch.linalg.norm(b) ** 2) for b in ref)
+    out["forms"]["mixed"]["rel_diff_vs_fp64_first8"] = (num / den) ** 0.5
+    del mix, ref, mats
+    # dense limit
+    wl = config3_dense_limit()
+    Sd = torch.from_numpy(wl.dense()).cuda()
+    S = ctx.compress(Sd, wl.sizes, wl.sizes, 0.0, 0.0)
+    for _ in range(2):
+        C = ctx.gemm(S, S, 0.0, 0.0)
+        del C
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(5):
+        C, st = ctx.gemm(S, S, 0.0, 0.0, stats=True)
+        ms.append(st.as_dict()["ms_total"])
+    clr_ms = float(np.median(ms))
+    Cd = C.to_dense()
+    ref = torch.matmul(Sd, Sd)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(5):
+        e0.record()
+        ref = torch.matmul(Sd, Sd)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    dg_ms = float(np.median(ts))
+    fl = 2.0 * float(wl.n) ** 3
+    out["dense_limit"] = {
+        "workload": f"N={wl.n}, {len(wl.sizes)} equal blocks, tol 0, screen 0 (full rank)",
+        "clr_ms": clr_ms, "clr_tflops": fl / (clr_ms * 1e-3) / 1e12,
+        "dense_dgemm_ms": dg_ms, "dense_dgemm_tflops": fl / (dg_ms * 1e-3) / 1e12,
+        "dense_dgemm": "torch.matmul float64 (ROCm BLAS)",
+        "rel_diff": float(torch.linalg.norm(Cd - ref) / torch.linalg.norm(ref)),
+    }
+    log_fn(f"  dense limit: {out['dense_limit']}")
+    return out
+
+
 def cpu_baseline(wl, Sd, gpu_blocks_fn, budget_s):
     """Oracle (FP64 NumPy/LAPACK) on a bounded sample of the same product's result blocks."""
     import oracle as orc
@@ -246,6 +331,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sqrtinv-n", type=int, default=8192)
     ap.add_argument("--no-sqrtinv", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -316,6 +403,11 @@ def main():
     # count of the blocks it truncates.
     rec_achieved = (fb["rec_engine_flops"] / (fb["rec_engine_ms"] * 1e-3) / 1e12
                     if fb["rec_engine_ms"] > 0 else None)
+    batched = None
+    if not args.no_batch:
+        log(f"batched products: {args.batch_count}")
+        batched = run_batched(ctx, args.batch_count, log)
+
     roof = {
         "bound": "alu",
         "kernel": "k_recompress_reg (register-resident FP64 truncated SVD, one block per workgroup)",
@@ -360,6 +452,7 @@ def main():
         "forms": forms,
         "error_vs_oracle_sampled": sample_err,
         "sqrt_inv": sqrtinv,
+        "batched": batched,
         "roofline": roof,
         "roofline_dense_gemm": roof_gemm,
         "cpu_baseline": cpu,
