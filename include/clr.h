@@ -205,9 +205,10 @@ clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_ma
 
 /* Largest output-tile edge of the grouped-GEMM items of the dense-accumulation
  * launch and of the factor-product launches, per precision (CLR_FP64 or
- * CLR_MIXED) for this context: 0 (default) is the kernel's full tile (160 in
- * the FP64 form, 128 in the mixed form), otherwise a multiple of 16 up to it.
- * Results do not depend on these edges, only the launch shapes do. */
+ * CLR_MIXED) for this context: 0 (default) is the kernel's full tile (dense:
+ * 160 in the FP64 form, 128 in the mixed form; factor products: 64, one wave
+ * per item), otherwise a multiple of 16 up to it.  Results do not depend on
+ * these edges, only the launch shapes do. */
 clr_status clr_set_tile_edges(clr_context* ctx, int precision, int dense_edge, int thin_edge);
 
 /* Autotuner: times the product A B (options as for clr_gemm; output discarded)

@@ -275,10 +275,17 @@ int max_item(const clr_gemm_opts* o) {
   return o->precision == CLR_MIXED ? kMaxItemF32 : kMaxItemF64;
 }
 
+// Factor products (one side a rank) run on the wave-per-item kernel.
+hipError_t run_wgemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
+                     hipStream_t s) {
+  if (o->precision == CLR_MIXED) return launch_wgemm_f32(items, segs, n, o->split, s);
+  return launch_wgemm_f64(items, segs, n, s);
+}
+
 int tile_edge(const clr_context* ctx, const clr_gemm_opts* o, bool thin) {
   const int pi = o->precision == CLR_MIXED ? 1 : 0;
   const int v = thin ? ctx->tile_thin[pi] : ctx->tile_dense[pi];
-  return v > 0 ? v : max_item(o);
+  return v > 0 ? v : (thin ? kMaxItemThin : max_item(o));
 }
 
 // Read and clear the device status word; map it to a status code.
@@ -754,8 +761,8 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   F.c_ncols = C->cols;
   if (e == hipSuccess) e = launch_fill(P, F, stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], stream);
-  if (e == hipSuccess) e = run_ggemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream);
-  if (e == hipSuccess) e = run_ggemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
+  if (e == hipSuccess) e = run_wgemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream);
+  if (e == hipSuccess) e = run_wgemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[6], stream);
   if (e == hipSuccess) e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream, true);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
@@ -831,9 +838,12 @@ extern "C" clr_status clr_set_tile_edges(clr_context* ctx, int precision, int de
   if (precision != CLR_FP64 && precision != CLR_MIXED)
     return fail(ctx, CLR_ERR_INVALID_ARG, "bad precision");
   const int top = precision == CLR_MIXED ? kMaxItemF32 : kMaxItemF64;
-  for (int v : {dense_edge, thin_edge})
-    if (v != 0 && (v < 16 || v > top || v % 16 != 0))
-      return fail(ctx, CLR_ERR_INVALID_ARG, "tile edge %d: 0 or a multiple of 16 in [16, %d]", v, top);
+  if (dense_edge != 0 && (dense_edge < 16 || dense_edge > top || dense_edge % 16 != 0))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "dense tile edge %d: 0 or a multiple of 16 in [16, %d]",
+                dense_edge, top);
+  if (thin_edge != 0 && (thin_edge < 16 || thin_edge > kMaxItemThin || thin_edge % 16 != 0))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "thin tile edge %d: 0 or a multiple of 16 in [16, %d]",
+                thin_edge, kMaxItemThin);
   ctx->tile_dense[precision] = dense_edge;
   ctx->tile_thin[precision] = thin_edge;
   return CLR_OK;
@@ -855,10 +865,10 @@ extern "C" clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const 
   const int pi = opts->precision == CLR_MIXED ? 1 : 0;
   const int top = max_item(opts);
   double best_d = 1e300, best_t = 1e300;
-  int arg_d = top, arg_t = top;
+  int arg_d = top, arg_t = std::min(top, kMaxItemThin);
   for (int edge = 32; edge <= top; edge += 32) {
     ctx->tile_dense[pi] = edge;
-    ctx->tile_thin[pi] = edge;
+    ctx->tile_thin[pi] = std::min(edge, kMaxItemThin);
     double td = 1e300, tt = 1e300;
     for (int rep = 0; rep < 2; ++rep) {
       clr_matrix* C = nullptr;
@@ -878,7 +888,7 @@ extern "C" clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const 
     }
     if (tt < best_t) {
       best_t = tt;
-      arg_t = edge;
+      arg_t = ctx->tile_thin[pi];
     }
   }
   ctx->tile_dense[pi] = arg_d;
@@ -928,9 +938,9 @@ void plan_free(clr_plan* pl) {
 // context stream, so it can be recorded into a graph.
 hipError_t plan_launch(clr_plan* pl, hipStream_t s) {
   const clr_gemm_opts* o = &pl->o;
-  hipError_t e = run_ggemm(o, as<GemmItem>(pl->items_thin1), as<Seg>(pl->seg_thin1), (int)pl->n_thin1, s);
+  hipError_t e = run_wgemm(o, as<GemmItem>(pl->items_thin1), as<Seg>(pl->seg_thin1), (int)pl->n_thin1, s);
   if (e == hipSuccess)
-    e = run_ggemm(o, as<GemmItem>(pl->items_thin2), as<Seg>(pl->seg_thin2), (int)pl->n_thin2, s);
+    e = run_wgemm(o, as<GemmItem>(pl->items_thin2), as<Seg>(pl->seg_thin2), (int)pl->n_thin2, s);
   if (e == hipSuccess)
     e = run_ggemm(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense, s, true);
   if (e == hipSuccess && pl->n_rec > 0) {

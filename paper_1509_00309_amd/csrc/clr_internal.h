@@ -193,6 +193,10 @@ struct AxpbyDenseItem {
 // ---------------------------------------------------------------------------
 hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
                             bool dense = false);
+hipError_t launch_wgemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s);
+hipError_t launch_wgemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
+                            hipStream_t s);
+constexpr int kMaxItemThin = 64;   // largest edge of a wave-per-item (thin) GEMM item
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
                             hipStream_t s, bool dense = false);
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,

@@ -394,4 +394,175 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
 
 static inline int xcd_grid(int n) { return ((n + 7) / 8) * 8; }
 
+// ---------------------------------------------------------------------------
+// Wave-per-item grouped GEMM for narrow items (the factor products of Eq. (4):
+// one side is a rank).  Each wave computes one item of at most 4 x 4 tiles of
+// 16 x 16, reading its MFMA operands straight from global memory (lane l takes
+// row l % 16 and inner index l / 16 of each 16 x 4 fragment): no LDS and no
+// barriers, so many items are in flight per CU and their load latencies
+// overlap.  Terms of the item are walked in order, 16 inner indices per
+// unrolled group.
+// ---------------------------------------------------------------------------
+constexpr int kWaveTiles = 4;
+static_assert(kMaxItemThin == 16 * kWaveTiles, "thin item edge = wave kernel tiles");
+constexpr int kWaveItemsPerBlock = 4;
+
+template <bool F32, bool SPLIT, int NA, int NB>
+__device__ __attribute__((always_inline)) inline void wave_item(const GemmItem& it,
+                                                                const Seg* __restrict__ segs,
+                                                                int lane) {
+  const int kr = lane >> 4, lc = lane & 15;
+  d4 acc[NA][NB];
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int sgi = 0; sgi < it.nseg; ++sgi) {
+    const Seg& sg = segs[it.seg0 + sgi];
+    const int64_t sLi = uni64(sg.sLi), sLk = uni64(sg.sLk), sRk = uni64(sg.sRk), sRj = uni64(sg.sRj);
+    const int K = uni(sg.k);
+    const double scale = sg.scale;
+    gdouble* L = as_global(sg.L) + (int64_t)it.row0 * sLi;
+    gdouble* R = as_global(sg.R) + (int64_t)it.col0 * sRj;
+    // per-lane fixed parts of the fragment addresses (rows / columns clamped
+    // into the item; out-of-range entries are zeroed by selects)
+    int64_t aoff[NA], boff[NB];
+    bool aval[NA], bval[NB];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int i = 16 * a + lc;
+      aval[a] = i < it.m;
+      aoff[a] = (int64_t)(aval[a] ? i : 0) * sLi;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = 16 * b + lc;
+      bval[b] = j < it.n;
+      boff[b] = (int64_t)(bval[b] ? j : 0) * sRj;
+    }
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      double av[4][NA], bv[4][NB];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = k0 + 4 * q + kr;
+        const bool kv = kk < K;
+        const int kc = kv ? kk : 0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const double x = L[aoff[a] + (int64_t)kc * sLk];
+          av[q][a] = (kv & aval[a]) ? x * scale : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const double y = R[(int64_t)kc * sRk + boff[b]];
+          bv[q][b] = (kv & bval[b]) ? y : 0.0;
+        }
+      }
+      if constexpr (!F32) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][a], bv[q][b], acc[a][b], 0, 0, 0);
+      } else {
+        f4 p[NA][NB];
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) p[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float ah[NA], bh[NB];
+#pragma unroll
+          for (int a = 0; a < NA; ++a) ah[a] = (float)av[q][a];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) bh[b] = (float)bv[q][b];
+#pragma unroll
+          for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              p[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[a], bh[b], p[a][b], 0, 0, 0);
+              if constexpr (SPLIT) {
+                const float al = (float)(av[q][a] - (double)ah[a]);
+                const float bl = (float)(bv[q][b] - (double)bh[b]);
+                p[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[a], bl, p[a][b], 0, 0, 0);
+                p[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(al, bh[b], p[a][b], 0, 0, 0);
+              }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[a][b][v] += (double)p[a][b][v];
+      }
+    }
+  }
+  const double alpha = it.alpha;
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const d4 fin = acc[a][b];
+      const int j = 16 * b + lc;
+      if (j >= it.n) continue;
+      gdouble_mut* col = as_global_mut(it.C) + (int64_t)(it.col0 + j) * it.ldc + it.row0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * a + (F32 ? 4 * kr + v : kr + 4 * v);
+        if (i < it.m) {
+          const double val = alpha * fin[v];
+          col[i] = it.accumulate ? col[i] + val : val;
+        }
+      }
+    }
+}
+
+template <bool F32, bool SPLIT, int NA>
+__device__ __attribute__((always_inline)) inline void wave_nb(const GemmItem& it,
+                                                              const Seg* __restrict__ segs,
+                                                              int lane, int nb) {
+  switch (nb) {
+    case 1: wave_item<F32, SPLIT, NA, 1>(it, segs, lane); break;
+    case 2: wave_item<F32, SPLIT, NA, 2>(it, segs, lane); break;
+    case 3: wave_item<F32, SPLIT, NA, 3>(it, segs, lane); break;
+    default: wave_item<F32, SPLIT, NA, 4>(it, segs, lane); break;
+  }
+}
+
+template <bool F32, bool SPLIT>
+__global__ __launch_bounds__(64 * kWaveItemsPerBlock, 2) void k_wgemm(const GemmItem* __restrict__ items,
+                                                                  const Seg* __restrict__ segs,
+                                                                  int nitems) {
+  const int per = gridDim.x / 8;
+  const int blk = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  const int item = blk * kWaveItemsPerBlock + uni((int)threadIdx.x >> 6);
+  if (item >= nitems) return;
+  GemmItem it = items[item];
+  it.m = uni(it.m);
+  it.n = uni(it.n);
+  it.row0 = uni(it.row0);
+  it.col0 = uni(it.col0);
+  it.seg0 = uni(it.seg0);
+  it.nseg = uni(it.nseg);
+  it.accumulate = uni(it.accumulate);
+  it.ldc = uni64(it.ldc);
+  if (it.m <= 0 || it.n <= 0) return;
+  const int lane = threadIdx.x & 63;
+  const int na = (it.m + 15) >> 4, nb = (it.n + 15) >> 4;   // <= kWaveTiles (planner)
+  switch (na) {
+    case 1: wave_nb<F32, SPLIT, 1>(it, segs, lane, nb); break;
+    case 2: wave_nb<F32, SPLIT, 2>(it, segs, lane, nb); break;
+    case 3: wave_nb<F32, SPLIT, 3>(it, segs, lane, nb); break;
+    default: wave_nb<F32, SPLIT, 4>(it, segs, lane, nb); break;
+  }
+}
+
+static inline int wave_grid(int nitems) {
+  return xcd_grid((nitems + kWaveItemsPerBlock - 1) / kWaveItemsPerBlock);
+}
+
 }  // namespace clr

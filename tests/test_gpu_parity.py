@@ -430,7 +430,7 @@ def test_tile_edges_and_autotune(ctx, torch):
     wl = scaled_config("c2", 1536, seed=144)
     S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     ref = ctx.gemm(S, S, wl.tol, wl.eps_sp).to_dense().cpu().numpy()
-    for de, te in ((32, 64), (96, 160), (64, 32)):
+    for de, te in ((32, 64), (96, 48), (64, 32)):
         ctx.set_tile_edges("fp64", de, te)
         got = ctx.gemm(S, S, wl.tol, wl.eps_sp).to_dense().cpu().numpy()
         assert np.array_equal(got, ref), (de, te)
@@ -439,7 +439,7 @@ def test_tile_edges_and_autotune(ctx, torch):
         ctx.set_tile_edges("fp64", 40, 0)
     res = ctx.autotune(S, S, wl.tol, wl.eps_sp)
     log(f"  autotune: {res}")
-    assert res["dense_edge"] in (32, 64, 96, 128, 160) and res["thin_edge"] in (32, 64, 96, 128, 160)
+    assert res["dense_edge"] in (32, 64, 96, 128, 160) and res["thin_edge"] in (32, 64)
     got = ctx.gemm(S, S, wl.tol, wl.eps_sp).to_dense().cpu().numpy()
     assert np.array_equal(got, ref)
     ctx.set_tile_edges("fp64", 0, 0)
