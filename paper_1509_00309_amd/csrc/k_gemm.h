@@ -401,9 +401,10 @@ static inline int xcd_grid(int n) { return ((n + 7) / 8) * 8; }
 // row l % 16 and inner index l / 16 of each 16 x 4 fragment): no LDS and no
 // barriers, so many items are in flight per CU and their load latencies
 // overlap.  Terms of the item are walked in order, 16 inner indices per
-// unrolled group.
+// unrolled group (FP32 partials of the mixed form are flushed per group).
 // ---------------------------------------------------------------------------
 constexpr int kWaveTiles = 4;
+constexpr int kWaveKSteps = 4;   // MFMA k-steps (of 4) whose operands are loaded together
 static_assert(kMaxItemThin == 16 * kWaveTiles, "thin item edge = wave kernel tiles");
 constexpr int kWaveItemsPerBlock = 4;
 
@@ -440,10 +441,10 @@ __device__ __attribute__((always_inline)) inline void wave_item(const GemmItem& 
       bval[b] = j < it.n;
       boff[b] = (int64_t)(bval[b] ? j : 0) * sRj;
     }
-    for (int k0 = 0; k0 < K; k0 += 16) {
-      double av[4][NA], bv[4][NB];
+    for (int k0 = 0; k0 < K; k0 += 4 * kWaveKSteps) {
+      double av[kWaveKSteps][NA], bv[kWaveKSteps][NB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kWaveKSteps; ++q) {
         const int kk = k0 + 4 * q + kr;
         const bool kv = kk < K;
         const int kc = kv ? kk : 0;
@@ -460,7 +461,7 @@ __device__ __attribute__((always_inline)) inline void wave_item(const GemmItem& 
       }
       if constexpr (!F32) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < kWaveKSteps; ++q)
 #pragma unroll
           for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -473,7 +474,7 @@ __device__ __attribute__((always_inline)) inline void wave_item(const GemmItem& 
 #pragma unroll
           for (int b = 0; b < NB; ++b) p[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kWaveKSteps; ++q) {
           float ah[NA], bh[NB];
 #pragma unroll
           for (int a = 0; a < NA; ++a) ah[a] = (float)av[q][a];
