@@ -14,12 +14,14 @@
 //               accumulators; optionally the hi*lo + lo*hi correction terms
 //               (lo = fp32(x - hi)) go to a second FP32 partial.
 //
-// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement; wave (wr, wc)
-// owns the 16 x 16 output tiles (wr + 2a, wc + 2b), a < NA, b < NB, where
-// NA, NB <= WT are the item's valid tile counts for that wave.  The item loop
-// is instantiated per (NA, NB) and selected once per item by a scalar switch,
-// so no MFMA sits behind a per-tile branch and each variant keeps only its
-// own accumulators live.
+// Workgroup: 512 threads = 8 waves in a 2 x 4 arrangement (two waves per
+// SIMD, so one computes while the other stages operands or waits at the slab
+// barrier); wave (wr, wc) owns the 16 x 16 output tiles (wr + 2a, wc + 4b),
+// a < NA, b < NB, where NA, NB are the item's valid tile counts for that wave
+// (at most 5 x 3 of the 10 x 10 tiles of the FP64 form, 4 x 2 of the 8 x 8
+// tiles of the mixed form).  The item loop is instantiated per (NA, NB) and
+// selected once per item by a scalar switch, so no MFMA sits behind a
+// per-tile branch and each variant keeps only its own accumulators live.
 //
 // MFMA operand layout for the 16x16x4 shapes (64 lanes, lane = l):
 //   A(i, k): i = l % 16, k = l / 16;   B(k, j): j = l % 16, k = l / 16;
@@ -51,9 +53,23 @@ __device__ inline int64_t uni64(int64_t v) {
 
 constexpr int kSegCache = 96;  // segment descriptors of an item kept in LDS
 
-template <int WT, bool F32>
+// Wave grid and tiles of the LDS kernel per precision: WR x WC waves, a wave
+// owns up to TA x TB of the TILES x TILES tiles of 16 x 16.
+template <bool F32>
+struct GemmCfg;
+template <>
+struct GemmCfg<false> {
+  static constexpr int WR = 2, WC = 4, TA = 5, TB = 3, TILES = 10;   // 160 x 160
+};
+template <>
+struct GemmCfg<true> {
+  static constexpr int WR = 2, WC = 4, TA = 4, TB = 2, TILES = 8;    // 128 x 128
+};
+constexpr int kLdsGemmThreads = 512;
+
+template <bool F32>
 struct GemmLds {
-  static constexpr int TM = 32 * WT;
+  static constexpr int TM = 16 * GemmCfg<F32>::TILES;
   static constexpr int LD = TM + 1;  // odd stride: k-fast stores hit distinct banks
   using T = typename std::conditional<F32, float, double>::type;
   T a[2][kSlabK][LD];
@@ -103,21 +119,23 @@ __device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ s
   bok = 1.0;
 }
 
-// MFMA work of one LDS slab for a wave that owns NA x NB valid tiles.  The
-// tile counts are template constants so the body is straight-line code.
-template <int WT, bool F32, bool SPLIT, int NA, int NB>
-__device__ __attribute__((always_inline)) inline void slab_mfma(GemmLds<WT, F32>& sh, int cur,
-                                                                 int wr, int wc, int kr, int lc,
-                                                                 d4 (&acc)[WT][WT]) {
+// MFMA work of one LDS slab for a wave that owns NA x NB valid tiles
+// (tile rows wr + WR a, tile columns wc + WC b).  The tile counts are
+// template constants so the body is straight-line code.
+template <bool F32, bool SPLIT, int NA, int NB>
+__device__ __attribute__((always_inline)) inline void slab_mfma(
+    GemmLds<F32>& sh, int cur, int wr, int wc, int kr, int lc,
+    d4 (&acc)[GemmCfg<F32>::TA][GemmCfg<F32>::TB]) {
+  constexpr int WR = GemmCfg<F32>::WR, WC = GemmCfg<F32>::WC;
   if constexpr (!F32) {
     // all operands of the slab first, then the MFMA chain
     double av[kSlabK / 4][NA], bv[kSlabK / 4][NB];
 #pragma unroll
     for (int q = 0; q < kSlabK / 4; ++q) {
 #pragma unroll
-      for (int a = 0; a < NA; ++a) av[q][a] = sh.a[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
+      for (int a = 0; a < NA; ++a) av[q][a] = sh.a[cur][4 * q + kr][16 * (wr + WR * a) + lc];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) bv[q][b] = sh.b[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
+      for (int b = 0; b < NB; ++b) bv[q][b] = sh.b[cur][4 * q + kr][16 * (wc + WC * b) + lc];
     }
 #pragma unroll
     for (int q = 0; q < kSlabK / 4; ++q)
@@ -143,9 +161,9 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(GemmLds<WT, F32>
     for (int q = 0; q < kSlabK / 4; ++q) {
       float av[NA], bv[NB];
 #pragma unroll
-      for (int a = 0; a < NA; ++a) av[a] = sh.a[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
+      for (int a = 0; a < NA; ++a) av[a] = sh.a[cur][4 * q + kr][16 * (wr + WR * a) + lc];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) bv[b] = sh.b[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
+      for (int b = 0; b < NB; ++b) bv[b] = sh.b[cur][4 * q + kr][16 * (wc + WC * b) + lc];
 #pragma unroll
       for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -154,9 +172,9 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(GemmLds<WT, F32>
       if constexpr (SPLIT) {
         float al[NA], bl[NB];
 #pragma unroll
-        for (int a = 0; a < NA; ++a) al[a] = sh.alo[cur][4 * q + kr][16 * (wr + 2 * a) + lc];
+        for (int a = 0; a < NA; ++a) al[a] = sh.alo[cur][4 * q + kr][16 * (wr + WR * a) + lc];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) bl[b] = sh.blo[cur][4 * q + kr][16 * (wc + 2 * b) + lc];
+        for (int b = 0; b < NB; ++b) bl[b] = sh.blo[cur][4 * q + kr][16 * (wc + WC * b) + lc];
 #pragma unroll
         for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -182,19 +200,21 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(GemmLds<WT, F32>
 
 // Main loop and epilogue of one item for a wave that owns NA x NB valid
 // tiles (0 x 0 for waves with nothing to compute; they still stage operands).
-template <int WT, bool F32, bool SPLIT, int NA, int NB>
-__device__ __attribute__((always_inline)) inline void run_item(GemmLds<WT, F32>& sh,
+template <bool F32, bool SPLIT, int NA, int NB>
+__device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
                                                                 const GemmItem& it,
                                                                 const Seg* __restrict__ segs,
                                                                 int wr, int wc) {
-  constexpr int TM = GemmLds<WT, F32>::TM;
-  constexpr int NE = TM / 16;  // staged elements per thread and operand
-  static_assert(kSlabK == 16 && kGemmThreads == 256, "staging map assumes 16 x 16 threads");
+  using CF = GemmCfg<F32>;
+  constexpr int WR = CF::WR, WC = CF::WC;
+  constexpr int TM = GemmLds<F32>::TM;
+  constexpr int NE = TM / 32;  // staged elements per thread and operand
+  static_assert(kSlabK == 16 && kLdsGemmThreads == 512, "staging map assumes 16 x 32 threads");
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int nslab = (it.ktotal + kSlabK - 1) / kSlabK;
 
-  d4 acc[WT][WT];
+  d4 acc[CF::TA][CF::TB];
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -219,9 +239,9 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<WT, F32>&
     }
   };
   // Staging map: every thread serves one inner row t of the slab and the
-  // elements i0 + 16u of that row.  Rows contiguous in memory (unit stride
-  // along i) are read row-fast: t = tid / 16, i0 = tid % 16, so 16 lanes read
-  // 128 contiguous bytes; otherwise inner-fast: t = tid % 16, i0 = tid / 16,
+  // elements i0 + 32u of that row.  Rows contiguous in memory (unit stride
+  // along i) are read row-fast: t = tid / 32, i0 = tid % 32, so 32 lanes read
+  // 256 contiguous bytes; otherwise inner-fast: t = tid % 16, i0 = tid / 16,
   // so 16 lanes read 16 consecutive inner indices.  The map is fixed per slab
   // from row 0 and a thread needs one descriptor per operand and slab.
   //
@@ -233,18 +253,18 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<WT, F32>&
   auto load = [&](int buf) {
     const bool arow = uni(sh.sli[buf][0] == 1);
     const bool brow = uni(sh.srj[buf][0] == 1);
-    const int ta = arow ? tid >> 4 : tid & 15;
-    const int ia0 = arow ? tid & 15 : tid >> 4;
-    const int tb = brow ? tid >> 4 : tid & 15;
-    const int ib0 = brow ? tid & 15 : tid >> 4;
+    const int ta = arow ? tid >> 5 : tid & 15;
+    const int ia0 = arow ? tid & 31 : tid >> 4;
+    const int tb = brow ? tid >> 5 : tid & 15;
+    const int ib0 = brow ? tid & 31 : tid >> 4;
     const double* pa = sh.lp[buf][ta];
     const int sa = (int)sh.sli[buf][ta];
     const double* pb = sh.rp[buf][tb];
     const int sb = (int)sh.srj[buf][tb];
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
-      const int i = ia0 + 16 * u;
-      const int j = ib0 + 16 * u;
+      const int i = ia0 + 32 * u;
+      const int j = ib0 + 32 * u;
       ra[u] = *as_global(pa + ((i < it.m) ? i : 0) * sa);
       rb[u] = *as_global(pb + ((j < it.n) ? j : 0) * sb);
     }
@@ -252,16 +272,16 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<WT, F32>&
   auto store = [&](int buf) {
     const bool arow = uni(sh.sli[buf][0] == 1);
     const bool brow = uni(sh.srj[buf][0] == 1);
-    const int ta = arow ? tid >> 4 : tid & 15;
-    const int ia0 = arow ? tid & 15 : tid >> 4;
-    const int tb = brow ? tid >> 4 : tid & 15;
-    const int ib0 = brow ? tid & 15 : tid >> 4;
+    const int ta = arow ? tid >> 5 : tid & 15;
+    const int ia0 = arow ? tid & 31 : tid >> 4;
+    const int tb = brow ? tid >> 5 : tid & 15;
+    const int ib0 = brow ? tid & 31 : tid >> 4;
     const double sc = sh.scale[buf][ta];   // 0 for rows past the item
     const double bk = sh.bok[buf][tb];     // 0 for rows past the item
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
-      const int i = ia0 + 16 * u;
-      const int j = ib0 + 16 * u;
+      const int i = ia0 + 32 * u;
+      const int j = ib0 + 32 * u;
       const bool va = (i < it.m) & (sc != 0.0);
       const bool vb = (j < it.n) & (bk != 0.0);
       const double xa = va ? ra[u] * sc : 0.0;
@@ -295,7 +315,7 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<WT, F32>&
   for (int s = 0; s < nslab; ++s) {
     const int cur = s & 1, nxt = cur ^ 1;
     if (s + 1 < nslab) load(nxt);
-    if constexpr (NA > 0 && NB > 0) slab_mfma<WT, F32, SPLIT, NA, NB>(sh, cur, wr, wc, kr, lc, acc);
+    if constexpr (NA > 0 && NB > 0) slab_mfma<F32, SPLIT, NA, NB>(sh, cur, wr, wc, kr, lc, acc);
     if (s + 1 < nslab) store(nxt);
     if (s + 2 < nslab) resolve(s + 2, cur);
     __syncthreads();
@@ -311,13 +331,13 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<WT, F32>&
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const d4 fin = __builtin_amdgcn_mfma_f64_16x16x4f64(0.0, 0.0, acc[a][b], 0, 0, 0);
-      const int j = 16 * (wc + 2 * b) + lc;
+      const int j = 16 * (wc + WC * b) + lc;
       if (j >= it.n) continue;
       gdouble_mut* col = as_global_mut(it.C) + (int64_t)(it.col0 + j) * it.ldc + it.row0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         // f64 16x16x4: row (lane/16) + 4v;  f32 16x16x4: row 4*(lane/16) + v
-        const int i = 16 * (wr + 2 * a) + (F32 ? 4 * kr + v : kr + 4 * v);
+        const int i = 16 * (wr + WR * a) + (F32 ? 4 * kr + v : kr + 4 * v);
         if (i < it.m) {
           const double val = alpha * fin[v];
           col[i] = it.accumulate ? col[i] + val : val;
@@ -327,30 +347,30 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<WT, F32>&
   }
 }
 
-template <int WT, bool F32, bool SPLIT, int NA>
-__device__ __attribute__((always_inline)) inline void run_nb(GemmLds<WT, F32>& sh,
+template <bool F32, bool SPLIT, int NA>
+__device__ __attribute__((always_inline)) inline void run_nb(GemmLds<F32>& sh,
                                                               const GemmItem& it,
                                                               const Seg* __restrict__ segs,
                                                               int wr, int wc, int nb) {
-  static_assert(WT >= 3 && WT <= 5, "tile dispatch covers 3 to 5 tiles per wave and dimension");
+  constexpr int TB = GemmCfg<F32>::TB;
+  static_assert(TB >= 2 && TB <= 3, "column dispatch covers 2 or 3 tiles per wave");
   switch (nb) {
-    case 0: run_item<WT, F32, SPLIT, NA, 0>(sh, it, segs, wr, wc); break;
-    case 1: run_item<WT, F32, SPLIT, NA, 1>(sh, it, segs, wr, wc); break;
-    case 2: run_item<WT, F32, SPLIT, NA, 2>(sh, it, segs, wr, wc); break;
-    case 3: run_item<WT, F32, SPLIT, NA, 3>(sh, it, segs, wr, wc); break;
-    case 4: run_item<WT, F32, SPLIT, NA, (WT < 4 ? WT : 4)>(sh, it, segs, wr, wc); break;
-    default: run_item<WT, F32, SPLIT, NA, WT>(sh, it, segs, wr, wc); break;
+    case 0: run_item<F32, SPLIT, NA, 0>(sh, it, segs, wr, wc); break;
+    case 1: run_item<F32, SPLIT, NA, 1>(sh, it, segs, wr, wc); break;
+    case 2: run_item<F32, SPLIT, NA, 2>(sh, it, segs, wr, wc); break;
+    default: run_item<F32, SPLIT, NA, TB>(sh, it, segs, wr, wc); break;
   }
 }
 
 // DENSE only names the instantiation: the dense-accumulation launch of a
-// product gets its own kernel symbol, so profiles separate it from the factor
-// products and the recompression output products that share the code.
-template <int WT, bool F32, bool SPLIT, bool DENSE>
-__global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
-                                                           const Seg* __restrict__ segs,
-                                                           int nitems) {
-  __shared__ GemmLds<WT, F32> sh;
+// product gets its own kernel symbol, so profiles separate it from the other
+// launches that share the code.
+template <bool F32, bool SPLIT, bool DENSE>
+__global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
+                                                              const Seg* __restrict__ segs,
+                                                              int nitems) {
+  using CF = GemmCfg<F32>;
+  __shared__ GemmLds<F32> sh;
 
   // XCD-aware order: consecutive items (tiles of one block row) share an XCD's L2.
   const int per = gridDim.x / 8;
@@ -369,26 +389,29 @@ __global__ __launch_bounds__(kGemmThreads, 1) void k_ggemm(const GemmItem* __res
   it.accumulate = uni(it.accumulate);
   it.ldc = uni64(it.ldc);
   const int tid = threadIdx.x;
+  // Wave w runs on SIMD w % 4.  The two waves sharing a SIMD get tile-column
+  // classes WC/2 apart, so every SIMD carries a wide and a narrow class.
   const int wave = uni(tid >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / CF::WC;
+  const int wc = (wave % CF::WC + wr * (CF::WC / 2)) % CF::WC;
   const int mt = (it.m + 15) >> 4, nt = (it.n + 15) >> 4;
-  // valid tiles of this wave: a with wr + 2a < mt, b with wc + 2b < nt
-  const int na = min(WT, max(0, (mt - wr + 1) >> 1));
-  const int nb = min(WT, max(0, (nt - wc + 1) >> 1));
+  // valid tiles of this wave: a with wr + WR a < mt, b with wc + WC b < nt
+  const int na = min(CF::TA, max(0, (mt - wr + CF::WR - 1) / CF::WR));
+  const int nb = min(CF::TB, max(0, (nt - wc + CF::WC - 1) / CF::WC));
 
   const int ncache = min(it.nseg, kSegCache);
-  for (int s = tid; s < ncache; s += kGemmThreads) sh.segs[s] = segs[it.seg0 + s];
+  for (int s = tid; s < ncache; s += kLdsGemmThreads) sh.segs[s] = segs[it.seg0 + s];
   __syncthreads();
 
   // Every wave runs the same slab loop (the barriers are shared); only the
   // MFMA body and epilogue differ with the wave's tile counts.
   switch (na) {
-    case 0: run_item<WT, F32, SPLIT, 0, 0>(sh, it, segs, wr, wc); break;
-    case 1: run_nb<WT, F32, SPLIT, 1>(sh, it, segs, wr, wc, nb); break;
-    case 2: run_nb<WT, F32, SPLIT, 2>(sh, it, segs, wr, wc, nb); break;
-    case 3: run_nb<WT, F32, SPLIT, 3>(sh, it, segs, wr, wc, nb); break;
-    case 4: run_nb<WT, F32, SPLIT, (WT < 4 ? WT : 4)>(sh, it, segs, wr, wc, nb); break;
-    default: run_nb<WT, F32, SPLIT, WT>(sh, it, segs, wr, wc, nb); break;
+    case 0: run_item<F32, SPLIT, 0, 0>(sh, it, segs, wr, wc); break;
+    case 1: run_nb<F32, SPLIT, 1>(sh, it, segs, wr, wc, nb); break;
+    case 2: run_nb<F32, SPLIT, 2>(sh, it, segs, wr, wc, nb); break;
+    case 3: run_nb<F32, SPLIT, 3>(sh, it, segs, wr, wc, nb); break;
+    case 4: run_nb<F32, SPLIT, 4>(sh, it, segs, wr, wc, nb); break;
+    default: run_nb<F32, SPLIT, CF::TA>(sh, it, segs, wr, wc, nb); break;
   }
 }
 

@@ -7,15 +7,15 @@ namespace clr {
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
                             hipStream_t s, bool dense) {
   if (nitems <= 0) return hipSuccess;
-  const dim3 grid(xcd_grid(nitems)), block(kGemmThreads);
+  const dim3 grid(xcd_grid(nitems)), block(kLdsGemmThreads);
   if (split && dense)
-    hipLaunchKernelGGL((k_ggemm<kF32WaveTiles, true, true, true>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<true, true, true>), grid, block, 0, s, items, segs, nitems);
   else if (split)
-    hipLaunchKernelGGL((k_ggemm<kF32WaveTiles, true, true, false>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<true, true, false>), grid, block, 0, s, items, segs, nitems);
   else if (dense)
-    hipLaunchKernelGGL((k_ggemm<kF32WaveTiles, true, false, true>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<true, false, true>), grid, block, 0, s, items, segs, nitems);
   else
-    hipLaunchKernelGGL((k_ggemm<kF32WaveTiles, true, false, false>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<true, false, false>), grid, block, 0, s, items, segs, nitems);
   return hipGetLastError();
 }
 

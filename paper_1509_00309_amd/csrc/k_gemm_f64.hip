@@ -7,11 +7,11 @@ hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, 
                             bool dense) {
   if (nitems <= 0) return hipSuccess;
   if (dense)
-    hipLaunchKernelGGL((k_ggemm<kF64WaveTiles, false, false, true>), dim3(xcd_grid(nitems)),
-                       dim3(kGemmThreads), 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<false, false, true>), dim3(xcd_grid(nitems)),
+                       dim3(kLdsGemmThreads), 0, s, items, segs, nitems);
   else
-    hipLaunchKernelGGL((k_ggemm<kF64WaveTiles, false, false, false>), dim3(xcd_grid(nitems)),
-                       dim3(kGemmThreads), 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<false, false, false>), dim3(xcd_grid(nitems)),
+                       dim3(kLdsGemmThreads), 0, s, items, segs, nitems);
   return hipGetLastError();
 }
 
