@@ -443,3 +443,142 @@ def test_tile_edges_and_autotune(ctx, torch):
     got = ctx.gemm(S, S, wl.tol, wl.eps_sp).to_dense().cpu().numpy()
     assert np.array_equal(got, ref)
     ctx.set_tile_edges("fp64", 0, 0)
+
+
+# ---------------------------------------------------------------------------
+# Full size (the benchmark's workload and launch configuration), largest block
+# edge, and the adjoint against finite differences and the eigen-gradient
+# ---------------------------------------------------------------------------
+
+def test_gemm_full_size_sampled(ctx, torch):
+    """N = 8192 3D workload exactly as bench.py times it; 32 result blocks recomputed
+    one by one by the oracle (kinds, ranks and values)."""
+    log("gemm full size N=8192, sampled blocks")
+    wl = config2(8192)
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    C = ctx.gemm(S, S, wl.tol, wl.eps_sp)
+    kind, rank, _norm = C.meta()
+    Dg = C.to_dense().cpu().numpy()
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    offs = wl.offsets()
+    nb = len(wl.sizes)
+    rng = rng_for(8192)
+    picks = [(i, i) for i in rng.choice(nb, 4, replace=False)]
+    picks += [(i, min(nb - 1, i + 1)) for i in rng.choice(nb, 8, replace=False)]
+    picks += [(int(rng.integers(nb)), int(rng.integers(nb))) for _ in range(20)]
+    num = den = 0.0
+    seen = {0: 0, 1: 0, 2: 0}
+    ambiguous = 0
+    for (i, j) in picks:
+        ob = orc.gemm_block(O, O, i, j, wl.tol, wl.eps_sp)
+        m, n = wl.sizes[i], wl.sizes[j]
+        ref = ob.dense() if ob is not None else np.zeros((m, n))
+        got = Dg[offs[i]:offs[i + 1], offs[j]:offs[j + 1]]
+        ok = 0 if ob is None else (1 if ob.kind == "D" else 2)
+        seen[int(kind[i, j])] += 1
+        if int(kind[i, j]) != ok or (ok == 2 and int(rank[i, j]) != ob.rank):
+            # a cut on a tie of the truncation rule: judged on the untruncated block
+            eb = orc.gemm_block(O, O, i, j, 0.0, wl.eps_sp)
+            rk = [int(rank[i, j]) if kind[i, j] else 0, ob.rank if ok == 2 else 0]
+            assert eb is not None and parity.ambiguous_cut(eb.dense(), wl.tol, rk), \
+                (i, j, int(kind[i, j]), ok, int(rank[i, j]), ob.rank if ob else 0)
+            ambiguous += 1
+            continue
+        num += float(np.sum((got - ref) ** 2))
+        den += float(np.sum(ref ** 2))
+    err = math.sqrt(num / den)
+    log(f"  {len(picks)} blocks (kinds {seen}, {ambiguous} ambiguous cuts), rel err {err:.2e}")
+    assert ambiguous <= 1
+    assert err <= FP64_BOUND
+
+
+def test_gemm_largest_block_edge(ctx, torch):
+    """Blocks up to the largest supported edge (512) take the general recompression path."""
+    log("gemm with 512-edge blocks")
+    rs, ks = [512, 300, 48], [512, 200]
+    ra = random_blocks(601, rs, ks, p_zero=0.0, p_dense=0.5, max_rank=24)
+    rb = random_blocks(602, ks, rs, p_zero=0.0, p_dense=0.5, max_rank=24)
+    A, B = gpu_from_random(ctx, torch, ra), gpu_from_random(ctx, torch, rb)
+    OA, OB = orc_from_random(ra), orc_from_random(rb)
+    for tol in (1e-8, 0.0):
+        C = ctx.gemm(A, B, tol, 1e-10)
+        Oc = orc.gemm(OA, OB, tol, 1e-10)
+        rep = parity.compare(C, Oc, tol)
+        log(f"  tol={tol:g} err={rep.rel_err:.2e}")
+        parity.assert_parity(rep, FP64_BOUND, nblocks=9)
+
+
+def _alpha_of(S):
+    _k, _r, norm = S.meta()
+    return 1.0 / float(np.max(np.sum(norm, axis=1)))
+
+
+def test_sqrt_inv_backward_finite_differences(ctx, torch):
+    """dS by the adjoint vs central differences (h = 1e-6) on 32 stored entries,
+    truncation off, alpha held fixed."""
+    log("sqrt_inv backward vs finite differences")
+    wl = config1()
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, 0.0, 1e-10)
+    alpha = _alpha_of(S)
+    kind, _r, _n = S.meta()
+    offs = wl.offsets()
+    mask = np.zeros_like(Sd)
+    for I in range(len(wl.sizes)):
+        for J in range(len(wl.sizes)):
+            if kind[I, J]:
+                mask[offs[I]:offs[I + 1], offs[J]:offs[J + 1]] = 1.0
+    Wbar = rng_for(7101).standard_normal(Sd.shape) * mask
+    iters = 6
+    dS, _ = ctx.sqrt_inv_backward(S, torch.from_numpy(Wbar).cuda(), iters, 2, 0.0, 0.0, alpha=alpha)
+    dS = dS.cpu().numpy()
+    rng = rng_for(7102)
+    idx = np.argwhere(mask > 0)
+    pick = idx[rng.choice(len(idx), 32, replace=False)]
+    h = 1e-6
+
+    def loss(M):
+        X = ctx.compress(torch.from_numpy(M).cuda(), wl.sizes, wl.sizes, 0.0, 1e-10)
+        W, _st = ctx.sqrt_inv(X, 0.0, 0.0, fixed_iters=iters, alpha=alpha)
+        return float(np.sum(Wbar * W.to_dense().cpu().numpy()))
+
+    fd, ad = [], []
+    for (i, j) in pick:
+        Sp, Sm = Sd.copy(), Sd.copy()
+        Sp[i, j] += h
+        Sm[i, j] -= h
+        fd.append((loss(Sp) - loss(Sm)) / (2 * h))
+        ad.append(dS[i, j])
+    fd, ad = np.array(fd), np.array(ad)
+    err = float(np.max(np.abs(fd - ad)) / np.max(np.abs(ad)))
+    log(f"  max |fd - adjoint| / max |adjoint| = {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_sqrt_inv_backward_eigen_gradient(ctx, torch):
+    """Converged iteration (truncation off): dS equals the Daleckii-Krein gradient of
+    S^-1/2, Q (Gamma o (Q^T Wbar Q)) Q^T with Gamma_ij = -1/(sqrt(l_i) sqrt(l_j)
+    (sqrt(l_i) + sqrt(l_j))), on S's stored blocks."""
+    log("sqrt_inv backward vs Daleckii-Krein")
+    wl = scaled_config("c2", 768, nclusters=6, seed=145)
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, 0.0, 1e-10)
+    kind, _r, _n = S.meta()
+    offs = wl.offsets()
+    mask = np.zeros_like(Sd)
+    for I in range(len(wl.sizes)):
+        for J in range(len(wl.sizes)):
+            if kind[I, J]:
+                mask[offs[I]:offs[I + 1], offs[J]:offs[J + 1]] = 1.0
+    Wbar = rng_for(7201).standard_normal(Sd.shape) * mask
+    dS, W = ctx.sqrt_inv_backward(S, torch.from_numpy(Wbar).cuda(), 20, 5, 0.0, 0.0)
+    lam, Q = np.linalg.eigh(Sd)
+    sq = np.sqrt(lam)
+    gam = -1.0 / (np.outer(sq, sq) * (sq[:, None] + sq[None, :]))
+    ref = (Q @ (gam * (Q.T @ Wbar @ Q)) @ Q.T) * mask
+    err = float(np.linalg.norm(dS.cpu().numpy() - ref) / np.linalg.norm(ref))
+    werr = float(np.linalg.norm(W.to_dense().cpu().numpy() - (Q / sq) @ Q.T) / np.linalg.norm((Q / sq) @ Q.T))
+    log(f"  dS vs eigen-gradient {err:.2e}, W vs eigh {werr:.2e}")
+    assert werr <= 1e-10
+    assert err <= 1e-8
