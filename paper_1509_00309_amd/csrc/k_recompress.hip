@@ -102,6 +102,34 @@ __device__ inline double xor32_sum(double v) {
   return e + o;
 }
 
+// Reduce-scatter steps over lane pairs 16 and 32 apart.  A swap exchanges the
+// odd rows of its first operand with the even rows of its second, so with
+// (a, b) a lane of an even row ends up with a + a' (a' its partner's a) and a
+// lane of an odd row with b' + b: two values are summed over the pair in one
+// swap each instead of two all-reduces.  The 32-lane form pairs the lower
+// and upper halves of the wave the same way.
+__device__ inline double swap16_sum(double a, double b) {
+  const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+  const auto l = __builtin_amdgcn_permlane16_swap((unsigned)(ab & 0xffffffffLL),
+                                                  (unsigned)(bb & 0xffffffffLL), false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false,
+                                                  false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return x + y;
+}
+
+__device__ inline double swap32_sum(double a, double b) {
+  const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+  const auto l = __builtin_amdgcn_permlane32_swap((unsigned)(ab & 0xffffffffLL),
+                                                  (unsigned)(bb & 0xffffffffLL), false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(ab >> 32), (unsigned)(bb >> 32), false,
+                                                  false);
+  const double x = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double y = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return x + y;
+}
+
 __device__ inline double hw_sum(double v) { return xor16_sum(group_sum16(v)); }
 
 __device__ inline double wave_sum(double v) { return xor32_sum(hw_sum(v)); }
@@ -502,14 +530,15 @@ struct RegLds {
   double tauR[kRegEdge];
   double d[kRegEdge];
   double e[kRegEdge];
-  double colk[kRegEdge];      // column of the next left reflector (pivoted QR: its vector)
-  double rowk[kRegEdge];      // row of the next right reflector
+  double colk[kRegEdge];      // pivoted QR: vector of the next left reflector
+  double rowk[kRegEdge + 192];  // row of the next right reflector; zero tail for unmasked loads
   double tauL;
   int flag;
   union {
     struct {
       double part[kWaves][kRegEdge + 1];
       double wrow[kRegEdge];
+      double colb[2][kRegEdge];  // published column of the next left reflector, by parity
     } bd;
     struct {
       double b2[2 * kRegEdge];
@@ -558,156 +587,291 @@ CLR_INLINE void reg_load(RegTile& a, const double* D, int64_t ldd, bool trans, d
     }
 }
 
-// Householder vector of x = src[first .. end) computed by every wave:
-// (I - tau v v^T) x = beta e_1 with v = (1, x[1:] * scal).
-CLR_INLINE void house_wave(const double* src, int first, int end, double& beta, double& tau,
-                           double& scal) {
-  const int lane = threadIdx.x & 63;
-  double s2 = 0.0;
-  for (int i = first + 1 + lane; i < end; i += 64) s2 += src[i] * src[i];
-  s2 = wave_sum(s2);
-  const double x0 = src[first];
-  beta = x0;
-  tau = 0.0;
-  scal = 0.0;
-  if (s2 > 0.0) {
-    beta = -copysign(sqrt(x0 * x0 + s2), x0);
-    tau = (beta - x0) / beta;
-    scal = 1.0 / (x0 - beta);
-  }
+// Householder reflector (I - tau v v^T) x = beta e_1, v = (1, x[1:] * scal),
+// from x0 = x[0] and s2 = |x[1:]|^2.  Each quotient has operands of
+// comparable size, so columns whose norm is near the bottom of the exponent
+// range (trailing columns of rapidly decaying spectra) stay finite; s2 = 0
+// gives the identity (tau = 0), selected without a branch.
+CLR_INLINE void house_from(double x0, double s2, double& beta, double& tau, double& scal) {
+  const double bt = -copysign(sqrt(fma(x0, x0, s2)), x0);
+  const double ta = (bt - x0) / bt;
+  const double sc = 1.0 / (x0 - bt);
+  const bool refl = s2 > 0.0;
+  beta = refl ? bt : x0;
+  tau = refl ? ta : 0.0;
+  scal = refl ? sc : 0.0;
 }
 
-// Householder bidiagonalisation of the register-resident G: d, e, the right
-// reflectors (vstore, tauR) in LDS.  The tile is left in an unspecified state.
-// The updates are written without per-element branches: rows and columns
-// outside the active part get zero weights, so a - v * 0 leaves them exactly
-// as they were, and the independent dot products of a thread's 5 columns (or
-// 10 rows) form one straight-line block the compiler can interleave.
-CLR_INLINE void reg_bidiag(RegTile& a, int p, int q, RegLds& L) {
+// Sum over the 16 lanes of a DPP row for code where every lane is active:
+// the same butterfly as group_sum16 without a fill value for the moves.
+template <int CTRL>
+__device__ inline double dpp_move_full(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double row_sum16(double v) {
+  v += dpp_move_full<0xB1>(v);
+  v += dpp_move_full<0x4E>(v);
+  v += dpp_move_full<0x141>(v);
+  v += dpp_move_full<0x140>(v);
+  return v;
+}
+
+__device__ inline double row_sum64(double v) { return xor32_sum(xor16_sum(row_sum16(v))); }
+
+// Householder bidiagonalisation (Golub-Kahan) of the register-resident G:
+// d, e, the right reflectors (vstore, tauR) in LDS.  The tile is left in an
+// unspecified state.
+//
+// Layout: thread (tr, tc) = (tid & 15, tid >> 4) holds rows tr + 16 ir and
+// columns tc + 32 jc.  A DPP row of 16 lanes therefore holds a whole column
+// class, so sums over rows stay inside one wave; sums over columns cross the
+// 8 waves and go through LDS.  Rows >= p and columns >= q of the tile are zero
+// and stay zero (every weight built from them is zero).
+//
+// Phases: the steps k in [16 P, 16 P + 16) form phase P, compiled once per P.
+// In phase P the row blocks ir < P hold only finished rows (< k) and the
+// column blocks jc < P / 2 only finished columns (<= k), so the loops over
+// the register tile start at P and P / 2 at compile time: the arithmetic
+// follows the shrinking trailing matrix with no guards, and only the boundary
+// blocks ir = P and jc = P / 2 (P / 2 + 1 for the pivot column of the right
+// reflector at the end of an odd phase) carry element masks.  The finished
+// entries of every published row and column are written as zeros, and the
+// right-update row sums are stored with zeros on the rows they do not touch,
+// so the reflector vectors need no masks beyond the one pivot element.
+//
+// Three barriers per step.  The owners of column k + 1 publish it after the
+// left update of step k and before that step's right update; every thread
+// loads it right after the first barrier, loads the right-update row sums w
+// after the third, and rebuilds the updated column as published - tau w for
+// itself, so the column norm of the next left reflector is a row-local DPP
+// sum with no LDS round trip or barrier of its own.  The published column
+// alternates between two buffers so the next publish cannot overwrite a
+// column another wave is still reading.  Every LDS load is unconditional and
+// issued in a batch ahead of its use.  Every wave derives the reflectors from
+// bitwise identical sums (the butterflies add the same operands in the same
+// order in every lane), so the tau != 0 tests are uniform in the workgroup.
+struct BdCarry {
+  double cbn[kRR];   // published column of the step, this thread's rows
+  double wr[kRR];    // previous right-update row sums, this thread's rows
+  double x0c, x0w;   // the same two at the step's diagonal row
+  double tprev;      // tau of the previous right reflector (0 before the first)
+};
+
+// row_sum16 of v[B .. N), level by level so the chains interleave.
+template <int B, int N>
+__device__ inline void row_sum16_from(double (&v)[N]) {
+#pragma unroll
+  for (int i = B; i < N; ++i) v[i] += dpp_move_full<0xB1>(v[i]);
+#pragma unroll
+  for (int i = B; i < N; ++i) v[i] += dpp_move_full<0x4E>(v[i]);
+#pragma unroll
+  for (int i = B; i < N; ++i) v[i] += dpp_move_full<0x141>(v[i]);
+#pragma unroll
+  for (int i = B; i < N; ++i) v[i] += dpp_move_full<0x140>(v[i]);
+}
+
+// One step; returns false after the last column (left reflector only).
+template <int P>
+CLR_INLINE bool bd_step(RegTile& a, int k, int p, int q, RegLds& L, BdCarry& S) {
+  constexpr int JB = P >> 1;   // first column block with unfinished columns
   const int tid = threadIdx.x;
   const int tr = tid & 15, tc = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
-  if (tc == 0) {
+  const int kk = k - 16 * P;   // the diagonal row within block P
+  // ---- left reflector on column k (rows < k of the column are zero)
+  double c[kRR];
+  double s2 = 0.0;
 #pragma unroll
-    for (int ir = 0; ir < kRR; ++ir) {
-      const int i = tr + 16 * ir;
-      if (i < p) L.colk[i] = a[ir][0];
+  for (int ir = P; ir < kRR; ++ir) c[ir] = S.cbn[ir] - S.tprev * S.wr[ir];
+#pragma unroll
+  for (int ir = P + 1; ir < kRR; ++ir) s2 += c[ir] * c[ir];
+  s2 += (tr != kk) ? c[P] * c[P] : 0.0;
+  s2 = row_sum16(s2);
+  double beta, tau, scal;
+  house_from(S.x0c - S.tprev * S.x0w, s2, beta, tau, scal);
+  if (tid == 0) L.d[k] = beta;
+  if (tau != 0.0) {
+    double vr[kRR], w[kRC];
+#pragma unroll
+    for (int ir = P; ir < kRR; ++ir) vr[ir] = c[ir] * scal;
+    vr[P] = (tr == kk) ? 1.0 : vr[P];
+#pragma unroll
+    for (int jc = JB; jc < kRC; ++jc) {
+      w[jc] = 0.0;
+#pragma unroll
+      for (int ir = P; ir < kRR; ++ir) w[jc] += vr[ir] * a[ir][jc];
     }
+    row_sum16_from<JB>(w);
+    w[JB] *= (tc + 32 * JB > k) ? tau : 0.0;
+#pragma unroll
+    for (int jc = JB + 1; jc < kRC; ++jc) w[jc] *= tau;
+#pragma unroll
+    for (int ir = P; ir < kRR; ++ir)
+#pragma unroll
+      for (int jc = JB; jc < kRC; ++jc) a[ir][jc] -= vr[ir] * w[jc];
+  }
+  if (k == q - 1) return false;
+  // ---- publish column k + 1 (before the right update) and row k, with their
+  // finished entries as zeros
+  const int k1 = k + 1;
+  double* const nb = L.u.bd.colb[k1 & 1];
+  if (tc == (k1 & 31)) {
+    // column k + 1 lies in block JB, or in JB + 1 at the end of an odd phase
+    if ((k1 >> 5) == JB) {
+      nb[tr + 16 * P] = (tr > kk) ? a[P][JB] : 0.0;
+#pragma unroll
+      for (int ir = P + 1; ir < kRR; ++ir) nb[tr + 16 * ir] = a[ir][JB];
+    } else if (JB + 1 < kRC) {
+      nb[tr + 16 * P] = (tr > kk) ? a[P][JB + 1 < kRC ? JB + 1 : JB] : 0.0;
+#pragma unroll
+      for (int ir = P + 1; ir < kRR; ++ir) nb[tr + 16 * ir] = a[ir][JB + 1 < kRC ? JB + 1 : JB];
+    }
+  }
+  if (tr == kk) {
+    L.rowk[tc + 32 * JB] = (tc + 32 * JB > k) ? a[P][JB] : 0.0;
+#pragma unroll
+    for (int jc = JB + 1; jc < kRC; ++jc) L.rowk[tc + 32 * jc] = a[P][jc];
   }
   __syncthreads();
-  for (int k = 0; k < q; ++k) {
-    // left reflector on column k, applied to columns > k
-    double beta, tau, scal;
-    house_wave(L.colk, k, p, beta, tau, scal);
-    if (tid == 0) L.d[k] = beta;
-    if (tau != 0.0) {
-      double vr[kRR], w[kRC];
+  // ---- everything published before the barrier, loaded at once: row k for
+  // the right reflector, and column k + 1 for the next step
+  double rv[3], rr[kRC];
 #pragma unroll
-      for (int ir = 0; ir < kRR; ++ir) {
-        const int i = tr + 16 * ir;
-        const double c = L.colk[i < p ? i : 0];
-        vr[ir] = (i == k) ? 1.0 : ((i > k && i < p) ? c * scal : 0.0);
-      }
+  for (int t = 0; t < 3; ++t) rv[t] = L.rowk[k + 2 + lane + 64 * t];
+  const double rx0 = L.rowk[k1];
 #pragma unroll
-      for (int jc = 0; jc < kRC; ++jc) {
-        w[jc] = 0.0;
+  for (int jc = JB; jc < kRC; ++jc) rr[jc] = L.rowk[tc + 32 * jc];
 #pragma unroll
-        for (int ir = 0; ir < kRR; ++ir) w[jc] += vr[ir] * a[ir][jc];
-      }
+  for (int ir = P; ir < kRR; ++ir) S.cbn[ir] = nb[tr + 16 * ir];
+  S.x0c = nb[k1];
+  // ---- right reflector on row k, elements k + 1 .. q - 1 (entries >= q are
+  // zero), applied to rows > k
+  s2 = 0.0;
 #pragma unroll
-      for (int jc = 0; jc < kRC; ++jc) {
-        const int j = tc + 32 * jc;
-        const double t = (j > k && j < q) ? tau : 0.0;
-        w[jc] = t * group_sum16(w[jc]);
-      }
-#pragma unroll
-      for (int ir = 0; ir < kRR; ++ir)
-#pragma unroll
-        for (int jc = 0; jc < kRC; ++jc) a[ir][jc] -= vr[ir] * w[jc];
-    }
-    if (k == q - 1) break;
-    // right reflector on row k, applied to rows > k
-    const int ki = k >> 4;
-    if (tr == (k & 15)) {
-#pragma unroll
-      for (int ir = 0; ir < kRR; ++ir)
-        if (ir == ki) {
-#pragma unroll
-          for (int jc = 0; jc < kRC; ++jc) {
-            const int j = tc + 32 * jc;
-            if (j > k && j < q) L.rowk[j] = a[ir][jc];
-          }
-        }
-    }
-    __syncthreads();
-    house_wave(L.rowk, k + 1, q, beta, tau, scal);
-    if (tid == 0) {
-      L.e[k] = beta;
-      L.tauR[k] = tau;
-    }
-    if (wave == 0) {
-      double* vs = L.vstore + vs_off(k, q);
-      for (int j = k + 1 + lane; j < q; j += 64) vs[j - k - 1] = (j == k + 1) ? 1.0 : L.rowk[j] * scal;
-    }
-    double vc[kRC];
-#pragma unroll
-    for (int jc = 0; jc < kRC; ++jc) {
-      const int j = tc + 32 * jc;
-      const double r = L.rowk[j < q ? j : 0];
-      vc[jc] = (j == k + 1) ? 1.0 : ((j > k + 1 && j < q) ? r * scal : 0.0);
-    }
-    if (tau != 0.0) {
-      double w[kRR];
-#pragma unroll
-      for (int ir = 0; ir < kRR; ++ir) {
-        w[ir] = 0.0;
-#pragma unroll
-        for (int jc = 0; jc < kRC; ++jc) w[ir] += a[ir][jc] * vc[jc];
-      }
-      // the 4 column classes of this wave: lanes 16 and 32 apart
-#pragma unroll
-      for (int ir = 0; ir < kRR; ++ir) w[ir] = xor32_sum(xor16_sum(w[ir]));
-      if (lane < 16) {
-#pragma unroll
-        for (int ir = 0; ir < kRR; ++ir) {
-          const int i = tr + 16 * ir;
-          if (i > k && i < p) L.u.bd.part[wave][i] = w[ir];
-        }
-      }
-    }
-    __syncthreads();
-    if (tau != 0.0 && tid > k && tid < p) {
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) s += L.u.bd.part[w][tid];
-      L.u.bd.wrow[tid] = s;
-    }
-    __syncthreads();
-    if (tau != 0.0) {
-#pragma unroll
-      for (int ir = 0; ir < kRR; ++ir) {
-        const int i = tr + 16 * ir;
-        const double wr = L.u.bd.wrow[i < p ? i : 0];
-        const double w = (i > k && i < p) ? tau * wr : 0.0;
-#pragma unroll
-        for (int jc = 0; jc < kRC; ++jc) a[ir][jc] -= w * vc[jc];
-      }
-    }
-    // publish column k + 1 for the next left reflector
-    const int k1 = k + 1, kj1 = k1 >> 5;
-    if (tc == (k1 & 31)) {
-#pragma unroll
-      for (int jc = 0; jc < kRC; ++jc)
-        if (jc == kj1) {
-#pragma unroll
-          for (int ir = 0; ir < kRR; ++ir) {
-            const int i = tr + 16 * ir;
-            if (i >= k1 && i < p) L.colk[i] = a[ir][jc];
-          }
-        }
-    }
-    __syncthreads();
+  for (int t = 0; t < 3; ++t) s2 += rv[t] * rv[t];
+  s2 = row_sum64(s2);
+  house_from(rx0, s2, beta, tau, scal);
+  if (tid == 0) {
+    L.e[k] = beta;
+    L.tauR[k] = tau;
   }
+  if (wave == 0) {
+    double* vs = L.vstore + vs_off(k, q);
+    if (lane == 0) vs[0] = 1.0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int j = k + 2 + lane + 64 * t;
+      if (j < q) vs[j - k - 1] = rv[t] * scal;
+    }
+  }
+  double vc[kRC];
+#pragma unroll
+  for (int jc = JB; jc < kRC; ++jc) vc[jc] = rr[jc] * scal;
+  {
+    const bool piv = tc == (k1 & 31);
+    if ((k1 >> 5) == JB) {
+      vc[JB] = piv ? 1.0 : vc[JB];
+    } else if (JB + 1 < kRC) {
+      vc[JB + 1 < kRC ? JB + 1 : JB] = piv ? 1.0 : vc[JB + 1 < kRC ? JB + 1 : JB];
+    }
+  }
+  if (tau != 0.0) {
+    double w[kRR];
+#pragma unroll
+    for (int ir = 0; ir < kRR; ++ir) {
+      w[ir] = 0.0;
+      if (ir >= P) {
+#pragma unroll
+        for (int jc = JB; jc < kRC; ++jc) w[ir] += a[ir][jc] * vc[jc];
+      }
+    }
+    // sum over the 4 column classes of this wave (lanes 16 and 32 apart) as
+    // a reduce-scatter: row pair (0, 1) of lanes keeps blocks 0-4 vs 5-9,
+    // then halves (0-1, 2-3) keep blocks {0, 1} vs {3, 4}; block 2 (+5) is
+    // summed over the halves in both.  Lane row rw = lane >> 4 ends with the
+    // full sums of blocks b + {0, 1, 2} (rw = 0, 1) or b + {3, 4, 2} (rw = 2,
+    // 3), b = 5 on odd rw.
+    double u[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) u[i] = swap16_sum(w[i], w[i + 5]);
+    const double t0 = swap32_sum(u[0], u[3]);
+    const double t1 = swap32_sum(u[1], u[4]);
+    const double t2 = xor32_sum(u[2]);
+    const int rw = lane >> 4;
+    const int b = (rw & 1) ? 5 : 0, hi = (rw & 2) ? 3 : 0;
+    double* const pw = L.u.bd.part[wave];
+    pw[tr + 16 * (b + hi)] = t0;
+    pw[tr + 16 * (b + hi + 1)] = t1;
+    if (rw < 2) pw[tr + 16 * (b + 2)] = t2;
+  }
+  __syncthreads();
+  if (tau != 0.0 && tid < kRegEdge) {
+    double pw[kWaves];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) pw[w] = L.u.bd.part[w][tid];
+    const double s = ((pw[0] + pw[1]) + (pw[2] + pw[3])) + ((pw[4] + pw[5]) + (pw[6] + pw[7]));
+    L.u.bd.wrow[tid] = (tid > k && tid < p) ? s : 0.0;
+  }
+  __syncthreads();
+  if (tau != 0.0) {
+#pragma unroll
+    for (int ir = P; ir < kRR; ++ir) S.wr[ir] = L.u.bd.wrow[tr + 16 * ir];
+    S.x0w = L.u.bd.wrow[k1];
+#pragma unroll
+    for (int ir = P; ir < kRR; ++ir) {
+      const double w = tau * S.wr[ir];
+#pragma unroll
+      for (int jc = JB; jc < kRC; ++jc) a[ir][jc] -= w * vc[jc];
+    }
+  }
+  S.tprev = tau;
+  return true;
+}
+
+template <int P>
+CLR_INLINE bool bd_phase(RegTile& a, int p, int q, RegLds& L, BdCarry& S) {
+  const int ke = min(16 * P + 16, q);
+  for (int k = 16 * P; k < ke; ++k)
+    if (!bd_step<P>(a, k, p, q, L, S)) return false;
+  return true;
+}
+
+CLR_INLINE void reg_bidiag(RegTile& a, int p_in, int q_in, RegLds& L) {
+  static_assert(kRR == 10 && kRC == 5, "phase dispatch below assumes a 160 x 160 frame");
+  // uniform in the workgroup; made explicit so loop bounds are scalar
+  const int p = __builtin_amdgcn_readfirstlane(p_in), q = __builtin_amdgcn_readfirstlane(q_in);
+  const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;
+  if (tc == 0) {
+#pragma unroll
+    for (int ir = 0; ir < kRR; ++ir) L.u.bd.colb[0][tr + 16 * ir] = a[ir][0];
+  }
+  if (tid < 192) L.rowk[kRegEdge + tid] = 0.0;
+  __syncthreads();
+  BdCarry S;
+#pragma unroll
+  for (int ir = 0; ir < kRR; ++ir) {
+    S.cbn[ir] = L.u.bd.colb[0][tr + 16 * ir];
+    S.wr[ir] = 0.0;
+  }
+  S.x0c = L.u.bd.colb[0][0];
+  S.x0w = 0.0;
+  S.tprev = 0.0;
+  bool go = true;
+  if (go) go = bd_phase<0>(a, p, q, L, S);
+  if (go && q > 16) go = bd_phase<1>(a, p, q, L, S);
+  if (go && q > 32) go = bd_phase<2>(a, p, q, L, S);
+  if (go && q > 48) go = bd_phase<3>(a, p, q, L, S);
+  if (go && q > 64) go = bd_phase<4>(a, p, q, L, S);
+  if (go && q > 80) go = bd_phase<5>(a, p, q, L, S);
+  if (go && q > 96) go = bd_phase<6>(a, p, q, L, S);
+  if (go && q > 112) go = bd_phase<7>(a, p, q, L, S);
+  if (go && q > 128) go = bd_phase<8>(a, p, q, L, S);
+  if (go && q > 144) go = bd_phase<9>(a, p, q, L, S);
 }
 
 // #{sigma_i > x} for the bidiagonal whose Golub-Kahan off-diagonals squared
