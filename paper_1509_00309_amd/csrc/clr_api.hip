@@ -40,7 +40,7 @@ struct clr_context {
   std::string last_error;
   DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
       items_thin2, pieces, rec, pool, scratch, acc, status, terms, aux_items, aux_segs,
-      aux_dense, ptrs, recg;
+      aux_dense, ptrs, recg, order;
   hipEvent_t ev[10] = {};
   // grouped-GEMM item edges per precision (0: the kernel's largest tile), set
   // explicitly or by clr_autotune
@@ -266,9 +266,9 @@ clr_status check_opts(clr_context* ctx, const clr_gemm_opts* o) {
 }
 
 hipError_t run_ggemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
-                     hipStream_t s, bool dense = false) {
-  if (o->precision == CLR_MIXED) return launch_ggemm_f32(items, segs, n, o->split, s, dense);
-  return launch_ggemm_f64(items, segs, n, s, dense);
+                     hipStream_t s, bool dense = false, const int* order = nullptr) {
+  if (o->precision == CLR_MIXED) return launch_ggemm_f32(items, segs, n, o->split, s, dense, order);
+  return launch_ggemm_f64(items, segs, n, s, dense, order);
 }
 
 int max_item(const clr_gemm_opts* o) {
@@ -347,16 +347,34 @@ clr_status upload(clr_context* ctx, DevBuf& b, const std::vector<T>& v) {
 
 // Output-product slots of the recompression launch (one GEMM item and one
 // term per recompressed block).
+// Recompression workspace of n items: the emitted G * basis products (items
+// and segments) and the launch order of the register engine.
+struct RecWork {
+  GemmItem* gi;
+  Seg* gs;
+  int* order;
+};
+size_t rec_work_bytes(int64_t nitems) {
+  const size_t n = (size_t)std::max<int64_t>(nitems, 1);
+  return (sizeof(GemmItem) * n + 255) / 256 * 256 + (sizeof(Seg) * n + 255) / 256 * 256 +
+         sizeof(int) * n;
+}
+RecWork rec_work(void* base, int64_t nitems) {
+  const size_t n = (size_t)std::max<int64_t>(nitems, 1);
+  char* p = static_cast<char*>(base);
+  const size_t gi_bytes = (sizeof(GemmItem) * n + 255) / 256 * 256;
+  const size_t gs_bytes = (sizeof(Seg) * n + 255) / 256 * 256;
+  return RecWork{reinterpret_cast<GemmItem*>(p), reinterpret_cast<Seg*>(p + gi_bytes),
+                 reinterpret_cast<int*>(p + gi_bytes + gs_bytes)};
+}
+
 hipError_t launch_recompress_ctx(clr_context* ctx, const RecItem* items, const Piece* pieces,
                                  int nitems, double tol, bool timed = false) {
-  const size_t n = (size_t)std::max(nitems, 1);
-  const size_t gi_bytes = (sizeof(GemmItem) * n + 255) / 256 * 256;
-  hipError_t e = ensure(ctx->recg, gi_bytes + sizeof(Seg) * n);
+  hipError_t e = ensure(ctx->recg, rec_work_bytes(nitems));
   if (e != hipSuccess) return e;
-  GemmItem* gi = static_cast<GemmItem*>(ctx->recg.p);
-  Seg* gs = reinterpret_cast<Seg*>(static_cast<char*>(ctx->recg.p) + gi_bytes);
-  return launch_recompress(items, pieces, nitems, tol, as<int>(ctx->status), gi, gs, ctx->stream,
-                           timed ? ctx->ev[8] : nullptr, timed ? ctx->ev[9] : nullptr);
+  const RecWork w = rec_work(ctx->recg.p, nitems);
+  return launch_recompress(items, pieces, nitems, tol, as<int>(ctx->status), w.gi, w.gs, w.order,
+                           ctx->stream, timed ? ctx->ev[8] : nullptr, timed ? ctx->ev[9] : nullptr);
 }
 
 clr_status copy_matrix(clr_context* ctx, const clr_matrix* src, clr_matrix** out) {
@@ -414,7 +432,7 @@ extern "C" clr_status clr_context_destroy(clr_context* ctx) {
                     &ctx->items_dense, &ctx->seg_thin1, &ctx->items_thin1, &ctx->seg_thin2,
                     &ctx->items_thin2, &ctx->pieces, &ctx->rec, &ctx->pool, &ctx->scratch,
                     &ctx->acc, &ctx->status, &ctx->terms, &ctx->aux_items, &ctx->aux_segs,
-                    &ctx->aux_dense, &ctx->ptrs, &ctx->recg})
+                    &ctx->aux_dense, &ctx->ptrs, &ctx->recg, &ctx->order})
     free_buf(*b);
   for (auto& c : ctx->cache) (void)hipFree(c.first);
   ctx->cache.clear();
@@ -725,6 +743,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
       return bail(fail(ctx, CLR_ERR_CAPACITY, "work list %d too long (%lld)", i, (long long)hc[i]));
   if (e == hipSuccess) e = ensure(ctx->seg_dense, sizeof(Seg) * hc[kCntSegDense]);
   if (e == hipSuccess) e = ensure(ctx->items_dense, sizeof(GemmItem) * hc[kCntGemmItems]);
+  if (e == hipSuccess) e = ensure(ctx->order, sizeof(int) * hc[kCntGemmItems]);
   if (e == hipSuccess) e = ensure(ctx->seg_thin1, sizeof(Seg) * hc[kCntThin1]);
   if (e == hipSuccess) e = ensure(ctx->items_thin1, sizeof(GemmItem) * hc[kCntThin1]);
   if (e == hipSuccess) e = ensure(ctx->seg_thin2, sizeof(Seg) * hc[kCntThin2]);
@@ -760,11 +779,15 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   F.c_norm = C->d_norm;
   F.c_ncols = C->cols;
   if (e == hipSuccess) e = launch_fill(P, F, stream);
+  if (e == hipSuccess)
+    e = launch_item_order(F.items_dense, (int)hc[kCntGemmItems], as<int>(ctx->order), stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], stream);
   if (e == hipSuccess) e = run_wgemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream);
   if (e == hipSuccess) e = run_wgemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[6], stream);
-  if (e == hipSuccess) e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream, true);
+  if (e == hipSuccess)
+    e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream, true,
+                  as<int>(ctx->order));
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
   if (e == hipSuccess)
     e = launch_recompress_ctx(ctx, F.rec, F.pieces, (int)hc[kCntComputed], o->tol, st != nullptr);
@@ -912,7 +935,7 @@ struct clr_plan {
   std::vector<clr_matrix*> C;
   // execution buffers owned by the plan (a captured graph keeps their addresses)
   DevBuf seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2, items_thin2, pieces, rec,
-      pool, scratch, acc, recg, status, bases;
+      pool, scratch, acc, recg, status, bases, order;
   int64_t n_thin1 = 0, n_thin2 = 0, n_dense = 0, n_rec = 0;
   double flops[kNumStats] = {};
   int64_t counts[kNumCounters] = {};
@@ -928,7 +951,7 @@ void plan_free(clr_plan* pl) {
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   for (DevBuf* b : {&pl->seg_dense, &pl->items_dense, &pl->seg_thin1, &pl->items_thin1,
                     &pl->seg_thin2, &pl->items_thin2, &pl->pieces, &pl->rec, &pl->pool,
-                    &pl->scratch, &pl->acc, &pl->recg, &pl->status, &pl->bases})
+                    &pl->scratch, &pl->acc, &pl->recg, &pl->status, &pl->bases, &pl->order})
     free_buf(*b);
   delete pl;
 }
@@ -942,13 +965,12 @@ hipError_t plan_launch(clr_plan* pl, hipStream_t s) {
   if (e == hipSuccess)
     e = run_wgemm(o, as<GemmItem>(pl->items_thin2), as<Seg>(pl->seg_thin2), (int)pl->n_thin2, s);
   if (e == hipSuccess)
-    e = run_ggemm(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense, s, true);
+    e = run_ggemm(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense, s, true,
+                  as<int>(pl->order));
   if (e == hipSuccess && pl->n_rec > 0) {
-    const size_t gi_bytes = (sizeof(GemmItem) * (size_t)pl->n_rec + 255) / 256 * 256;
-    GemmItem* gi = static_cast<GemmItem*>(pl->recg.p);
-    Seg* gs = reinterpret_cast<Seg*>(static_cast<char*>(pl->recg.p) + gi_bytes);
+    const RecWork w = rec_work(pl->recg.p, pl->n_rec);
     e = launch_recompress(as<RecItem>(pl->rec), as<Piece>(pl->pieces), (int)pl->n_rec, o->tol,
-                          as<int>(pl->status), gi, gs, s);
+                          as<int>(pl->status), w.gi, w.gs, w.order, s);
   }
   return e;
 }
@@ -1049,6 +1071,7 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = ensure(pl->seg_dense, sizeof(Seg) * sum[kCntSegDense]);
   if (e == hipSuccess) e = ensure(pl->items_dense, sizeof(GemmItem) * sum[kCntGemmItems]);
+  if (e == hipSuccess) e = ensure(pl->order, sizeof(int) * sum[kCntGemmItems]);
   if (e == hipSuccess) e = ensure(pl->seg_thin1, sizeof(Seg) * sum[kCntThin1]);
   if (e == hipSuccess) e = ensure(pl->items_thin1, sizeof(GemmItem) * sum[kCntThin1]);
   if (e == hipSuccess) e = ensure(pl->seg_thin2, sizeof(Seg) * sum[kCntThin2]);
@@ -1058,10 +1081,7 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   if (e == hipSuccess) e = ensure(pl->pool, sizeof(double) * sum[kCntPool]);
   if (e == hipSuccess) e = ensure(pl->scratch, sizeof(double) * sum[kCntScratch]);
   if (e == hipSuccess && sum[kCntGemmItems] > 0) e = ensure(pl->acc, sizeof(double) * (size_t)acc_total);
-  if (e == hipSuccess) {
-    const size_t n = (size_t)std::max<int64_t>(sum[kCntComputed], 1);
-    e = ensure(pl->recg, (sizeof(GemmItem) * n + 255) / 256 * 256 + sizeof(Seg) * n);
-  }
+  if (e == hipSuccess) e = ensure(pl->recg, rec_work_bytes(sum[kCntComputed]));
   if (e == hipSuccess) e = ensure(pl->status, sizeof(int));
   if (e == hipSuccess) e = launch_fill_i32(as<int>(pl->status), 0, 1, stream);
   if (e != hipSuccess) return fail(ctx, CLR_ERR_HIP, "batch work lists: %s", hipGetErrorString(e));
@@ -1098,6 +1118,8 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     F.c_ncols = pl->C[p]->cols;
     HIP_TRY(ctx, launch_fill(P[p], F, stream));
   }
+  HIP_TRY(ctx, launch_item_order(as<GemmItem>(pl->items_dense), (int)sum[kCntGemmItems],
+                                 as<int>(pl->order), stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
   return s;
 }

@@ -191,16 +191,23 @@ struct AxpbyDenseItem {
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
+// order: optional item permutation (workgroup b runs item order[b]), e.g.
+// from launch_item_order; null keeps the XCD-blocked order.
 hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
-                            bool dense = false);
+                            bool dense = false, const int* order = nullptr);
 hipError_t launch_wgemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s);
 hipError_t launch_wgemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
                             hipStream_t s);
 constexpr int kMaxItemThin = 64;   // largest edge of a wave-per-item (thin) GEMM item
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s, bool dense = false);
+                            hipStream_t s, bool dense = false, const int* order = nullptr);
+// Items of the LDS grouped GEMM by decreasing estimated cost (slabs times the
+// busiest wave's tiles, in quarter-octave classes) into order[0 .. nitems).
+hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s);
+// order: workspace of nitems ints; when given, the register engine runs its
+// blocks in decreasing order of estimated cost (null: XCD-blocked order).
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
-                             int* status, GemmItem* gout, Seg* gseg, hipStream_t s,
+                             int* status, GemmItem* gout, Seg* gseg, int* order, hipStream_t s,
                              hipEvent_t engine_begin = nullptr, hipEvent_t engine_end = nullptr);
 hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
                            hipStream_t s);

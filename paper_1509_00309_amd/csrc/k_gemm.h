@@ -128,22 +128,31 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(
     d4 (&acc)[GemmCfg<F32>::TA][GemmCfg<F32>::TB]) {
   constexpr int WR = GemmCfg<F32>::WR, WC = GemmCfg<F32>::WC;
   if constexpr (!F32) {
-    // all operands of the slab first, then the MFMA chain
-    double av[kSlabK / 4][NA], bv[kSlabK / 4][NB];
+    // operands of 4-step q + 1 are read from LDS while the MFMAs of q run
+    // (two operand sets instead of the whole slab keeps registers free for
+    // the second global staging set)
+    double av[2][NA], bv[2][NB];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) av[0][a] = sh.a[cur][kr][16 * (wr + WR * a) + lc];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bv[0][b] = sh.b[cur][kr][16 * (wc + WC * b) + lc];
 #pragma unroll
     for (int q = 0; q < kSlabK / 4; ++q) {
+      if (q + 1 < kSlabK / 4) {
 #pragma unroll
-      for (int a = 0; a < NA; ++a) av[q][a] = sh.a[cur][4 * q + kr][16 * (wr + WR * a) + lc];
+        for (int a = 0; a < NA; ++a)
+          av[(q + 1) & 1][a] = sh.a[cur][4 * (q + 1) + kr][16 * (wr + WR * a) + lc];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) bv[q][b] = sh.b[cur][4 * q + kr][16 * (wc + WC * b) + lc];
-    }
-#pragma unroll
-    for (int q = 0; q < kSlabK / 4; ++q)
+        for (int b = 0; b < NB; ++b)
+          bv[(q + 1) & 1][b] = sh.b[cur][4 * (q + 1) + kr][16 * (wc + WC * b) + lc];
+      }
 #pragma unroll
       for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][a], bv[q][b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q & 1][a], bv[q & 1][b], acc[a][b], 0,
+                                                             0, 0);
+    }
   } else {
     f4 p[NA][NB];
     f4 pl[SPLIT ? NA : 1][SPLIT ? NB : 1];
@@ -368,14 +377,25 @@ __device__ __attribute__((always_inline)) inline void run_nb(GemmLds<F32>& sh,
 template <bool F32, bool SPLIT, bool DENSE>
 __global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
                                                               const Seg* __restrict__ segs,
-                                                              int nitems) {
+                                                              int nitems,
+                                                              const int* __restrict__ order) {
   using CF = GemmCfg<F32>;
   __shared__ GemmLds<F32> sh;
 
-  // XCD-aware order: consecutive items (tiles of one block row) share an XCD's L2.
-  const int per = gridDim.x / 8;
-  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (item >= nitems) return;
+  // With an order (items by decreasing cost), workgroup b runs item order[b]:
+  // the dispatcher deals workgroups to the 8 XCDs round-robin, so the long
+  // items start first on every XCD and the short ones fill the tail.
+  // Without one, the XCD-aware order: consecutive items (tiles of one block
+  // row) share an XCD's L2.
+  int item;
+  if (order) {
+    if ((int)blockIdx.x >= nitems) return;
+    item = order[blockIdx.x];
+  } else {
+    const int per = gridDim.x / 8;
+    item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (item >= nitems) return;
+  }
   // Item fields are the same for every lane; readfirstlane lets the compiler
   // keep them (and all control flow derived from them) in scalar registers.
   GemmItem it = items[item];

@@ -5,17 +5,17 @@
 namespace clr {
 
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s, bool dense) {
+                            hipStream_t s, bool dense, const int* order) {
   if (nitems <= 0) return hipSuccess;
   const dim3 grid(xcd_grid(nitems)), block(kLdsGemmThreads);
   if (split && dense)
-    hipLaunchKernelGGL((k_ggemm<true, true, true>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<true, true, true>), grid, block, 0, s, items, segs, nitems, order);
   else if (split)
-    hipLaunchKernelGGL((k_ggemm<true, true, false>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<true, true, false>), grid, block, 0, s, items, segs, nitems, order);
   else if (dense)
-    hipLaunchKernelGGL((k_ggemm<true, false, true>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<true, false, true>), grid, block, 0, s, items, segs, nitems, order);
   else
-    hipLaunchKernelGGL((k_ggemm<true, false, false>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_ggemm<true, false, false>), grid, block, 0, s, items, segs, nitems, order);
   return hipGetLastError();
 }
 

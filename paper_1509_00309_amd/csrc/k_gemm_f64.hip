@@ -4,14 +4,14 @@
 namespace clr {
 
 hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
-                            bool dense) {
+                            bool dense, const int* order) {
   if (nitems <= 0) return hipSuccess;
   if (dense)
     hipLaunchKernelGGL((k_ggemm<false, false, true>), dim3(xcd_grid(nitems)),
-                       dim3(kLdsGemmThreads), 0, s, items, segs, nitems);
+                       dim3(kLdsGemmThreads), 0, s, items, segs, nitems, order);
   else
     hipLaunchKernelGGL((k_ggemm<false, false, false>), dim3(xcd_grid(nitems)),
-                       dim3(kLdsGemmThreads), 0, s, items, segs, nitems);
+                       dim3(kLdsGemmThreads), 0, s, items, segs, nitems, order);
   return hipGetLastError();
 }
 

@@ -294,4 +294,49 @@ hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Longest-first order of grouped-GEMM items.  One workgroup: a histogram of
+// the items' cost classes, an exclusive scan from the most expensive class
+// down, and a scatter.  The order inside a class is whatever the atomics give,
+// which changes no result: every item is computed on its own.
+// ---------------------------------------------------------------------------
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderClasses = 64;
+
+__device__ inline int item_cost_class(const GemmItem& it) {
+  // slabs of 16 inner indices times (1 + tiles of the busiest wave of the
+  // 2 x 4 wave grid), the per-slab overhead counted as one tile
+  const int mt = (it.m + 15) >> 4, nt = (it.n + 15) >> 4;
+  const int worst = min(5, (mt + 1) >> 1) * min(3, (nt + 3) >> 2);
+  const double cost = (double)((it.ktotal + 15) >> 4) * (double)(worst + 1);
+  const int c = cost > 1.0 ? (int)(4.0 * log2(cost)) : 0;
+  return min(c, kOrderClasses - 1);
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_item_order(const GemmItem* __restrict__ items,
+                                                             int n, int* __restrict__ order) {
+  __shared__ int cnt[kOrderClasses];
+  const int tid = threadIdx.x;
+  if (tid < kOrderClasses) cnt[tid] = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&cnt[item_cost_class(items[i])], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int c = kOrderClasses - 1; c >= 0; --c) {
+      const int k = cnt[c];
+      cnt[c] = run;
+      run += k;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kOrderThreads) order[atomicAdd(&cnt[item_cost_class(items[i])], 1)] = i;
+}
+
+hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_order, dim3(1), dim3(kOrderThreads), 0, s, items, nitems, order);
+  return hipGetLastError();
+}
+
 }  // namespace clr

@@ -1907,15 +1907,58 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress(const RecItem* __res
     dense_path<false>(it, tol, lds, status, sh);
 }
 
+// Longest-first launch order of the register engine's blocks (one workgroup
+// per block, so a long block started last sets the end of the launch).  The
+// bidiagonalisation dominates and costs about q steps of a fixed overhead
+// plus the trailing-matrix work, so the class is 4 log2(q (q + p + 64));
+// blocks off the register path exit at once and go last.  Histogram, scan
+// from the most expensive class down, scatter (the order inside a class does
+// not change any result).
+constexpr int kRecOrderClasses = 64;
+
+__device__ inline int rec_cost_class(const RecItem& it, double tol) {
+  if (!register_item(it, tol)) return 0;
+  const int q = min(it.m, it.n), p = max(it.m, it.n);
+  const double cost = (double)q * (double)(q + p + 64);
+  return min(kRecOrderClasses - 1, max(1, (int)(4.0 * log2(cost)) - 40));
+}
+
+__global__ __launch_bounds__(1024) void k_rec_order(const RecItem* __restrict__ items, int n,
+                                                    double tol, int* __restrict__ order) {
+  __shared__ int cnt[kRecOrderClasses];
+  const int tid = threadIdx.x;
+  if (tid < kRecOrderClasses) cnt[tid] = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += 1024) atomicAdd(&cnt[rec_cost_class(items[i], tol)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int c = kRecOrderClasses - 1; c >= 0; --c) {
+      const int k = cnt[c];
+      cnt[c] = run;
+      run += k;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += 1024) order[atomicAdd(&cnt[rec_cost_class(items[i], tol)], 1)] = i;
+}
+
 __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* __restrict__ items,
                                                                 int nitems, double tol,
                                                                 int* status, GemmItem* gout,
-                                                                Seg* gseg) {
+                                                                Seg* gseg,
+                                                                const int* __restrict__ order) {
   extern __shared__ double lds[];
   __shared__ RecShared sh;
-  const int per = gridDim.x / 8;
-  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (item >= nitems) return;
+  int item;
+  if (order) {
+    if ((int)blockIdx.x >= nitems) return;
+    item = order[blockIdx.x];
+  } else {
+    const int per = gridDim.x / 8;
+    item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (item >= nitems) return;
+  }
   const RecItem it = items[item];
   if (!register_item(it, tol)) return;
   if (!item_guard(it, tol, status)) return;
@@ -1937,7 +1980,7 @@ hipError_t prepare_recompress() {
 }
 
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
-                             int* status, GemmItem* gout, Seg* gseg, hipStream_t s,
+                             int* status, GemmItem* gout, Seg* gseg, int* order, hipStream_t s,
                              hipEvent_t engine_begin, hipEvent_t engine_end) {
   if (nitems <= 0) return hipSuccess;
   {
@@ -1950,12 +1993,17 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
   hipError_t e = launch_fill_i32(reinterpret_cast<int*>(gout), 0,
                                  (int64_t)nitems * (int64_t)(sizeof(GemmItem) / sizeof(int)), s);
   if (e != hipSuccess) return e;
+  if (order) {
+    hipLaunchKernelGGL(k_rec_order, dim3(1), dim3(1024), 0, s, items, nitems, tol, order);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (engine_begin) {
     e = hipEventRecord(engine_begin, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_recompress_reg, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items,
-                     nitems, tol, status, gout, gseg);
+                     nitems, tol, status, gout, gseg, order);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (engine_end) {
