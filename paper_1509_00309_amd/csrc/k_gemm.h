@@ -447,7 +447,7 @@ static inline int xcd_grid(int n) { return ((n + 7) / 8) * 8; }
 // unrolled group (FP32 partials of the mixed form are flushed per group).
 // ---------------------------------------------------------------------------
 constexpr int kWaveTiles = 4;
-constexpr int kWaveKSteps = 4;   // MFMA k-steps (of 4) whose operands are loaded together
+constexpr int kWaveKSteps = 2;   // MFMA k-steps (of 4) per operand group; two groups in flight
 static_assert(kMaxItemThin == 16 * kWaveTiles, "thin item edge = wave kernel tiles");
 constexpr int kWaveItemsPerBlock = 4;
 
@@ -484,23 +484,34 @@ __device__ __attribute__((always_inline)) inline void wave_item(const GemmItem& 
       bval[b] = j < it.n;
       boff[b] = (int64_t)(bval[b] ? j : 0) * sRj;
     }
-    for (int k0 = 0; k0 < K; k0 += 4 * kWaveKSteps) {
-      double av[kWaveKSteps][NA], bv[kWaveKSteps][NB];
+    // Two operand groups in flight: the raw loads of group g + 1 are issued
+    // before the MFMAs of group g, so their latency hides behind that work.
+    // Loads are unconditional (an inner index past K reads index 0 of the
+    // segment); validity and the segment scale are applied by selects right
+    // before the MFMAs, so no load result is consumed early.
+    constexpr int G = 4 * kWaveKSteps;
+    double ra0[kWaveKSteps][NA], rb0[kWaveKSteps][NB], ra1[kWaveKSteps][NA], rb1[kWaveKSteps][NB];
+    auto load = [&](double (&ra)[kWaveKSteps][NA], double (&rb)[kWaveKSteps][NB], int k0) {
 #pragma unroll
       for (int q = 0; q < kWaveKSteps; ++q) {
         const int kk = k0 + 4 * q + kr;
-        const bool kv = kk < K;
-        const int kc = kv ? kk : 0;
+        const int kc = kk < K ? kk : 0;
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          const double x = L[aoff[a] + (int64_t)kc * sLk];
-          av[q][a] = (kv & aval[a]) ? x * scale : 0.0;
-        }
+        for (int a = 0; a < NA; ++a) ra[q][a] = L[aoff[a] + (int64_t)kc * sLk];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const double y = R[(int64_t)kc * sRk + boff[b]];
-          bv[q][b] = (kv & bval[b]) ? y : 0.0;
-        }
+        for (int b = 0; b < NB; ++b) rb[q][b] = R[(int64_t)kc * sRk + boff[b]];
+      }
+    };
+    auto compute = [&](const double (&ra)[kWaveKSteps][NA], const double (&rb)[kWaveKSteps][NB],
+                       int k0) {
+      double av[kWaveKSteps][NA], bv[kWaveKSteps][NB];
+#pragma unroll
+      for (int q = 0; q < kWaveKSteps; ++q) {
+        const bool kv = k0 + 4 * q + kr < K;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) av[q][a] = (kv & aval[a]) ? ra[q][a] * scale : 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bv[q][b] = (kv & bval[b]) ? rb[q][b] : 0.0;
       }
       if constexpr (!F32) {
 #pragma unroll
@@ -542,6 +553,23 @@ __device__ __attribute__((always_inline)) inline void wave_item(const GemmItem& 
           for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[a][b][v] += (double)p[a][b][v];
+      }
+    };
+    // (the scheduling barriers keep the compiler from sinking the prefetch
+    // next to its use, which it otherwise does under register pressure)
+    if (K > 0) {
+      load(ra0, rb0, 0);
+      for (int k0 = 0;;) {
+        load(ra1, rb1, k0 + G);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra0, rb0, k0);
+        k0 += G;
+        if (k0 >= K) break;
+        load(ra0, rb0, k0 + G);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(ra1, rb1, k0);
+        k0 += G;
+        if (k0 >= K) break;
       }
     }
   }
