@@ -129,8 +129,7 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(
   constexpr int WR = GemmCfg<F32>::WR, WC = GemmCfg<F32>::WC;
   if constexpr (!F32) {
     // operands of 4-step q + 1 are read from LDS while the MFMAs of q run
-    // (two operand sets instead of the whole slab keeps registers free for
-    // the second global staging set)
+    // (two operand sets instead of the whole slab's)
     double av[2][NA], bv[2][NB];
 #pragma unroll
     for (int a = 0; a < NA; ++a) av[0][a] = sh.a[cur][kr][16 * (wr + WR * a) + lc];
