@@ -786,10 +786,8 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   if (e == hipSuccess) e = run_wgemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[6], stream);
   if (e == hipSuccess)
-    e = P.max_item <= kMaxItemThin
-            ? run_wgemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream)
-            : run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream, true,
-                        as<int>(ctx->order));
+    e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream, true,
+                  as<int>(ctx->order));
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
   if (e == hipSuccess)
     e = launch_recompress_ctx(ctx, F.rec, F.pieces, (int)hc[kCntComputed], o->tol, st != nullptr);
@@ -939,7 +937,6 @@ struct clr_plan {
   DevBuf seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2, items_thin2, pieces, rec,
       pool, scratch, acc, recg, status, bases, order;
   int64_t n_thin1 = 0, n_thin2 = 0, n_dense = 0, n_rec = 0;
-  bool dense_on_waves = false;   // dense items at most the wave kernel's edge
   double flops[kNumStats] = {};
   int64_t counts[kNumCounters] = {};
   hipGraph_t graph = nullptr;
@@ -968,10 +965,8 @@ hipError_t plan_launch(clr_plan* pl, hipStream_t s) {
   if (e == hipSuccess)
     e = run_wgemm(o, as<GemmItem>(pl->items_thin2), as<Seg>(pl->seg_thin2), (int)pl->n_thin2, s);
   if (e == hipSuccess)
-    e = pl->dense_on_waves
-            ? run_wgemm(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense, s)
-            : run_ggemm(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense,
-                        s, true, as<int>(pl->order));
+    e = run_ggemm(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense, s, true,
+                  as<int>(pl->order));
   if (e == hipSuccess && pl->n_rec > 0) {
     const RecWork w = rec_work(pl->recg.p, pl->n_rec);
     e = launch_recompress(as<RecItem>(pl->rec), as<Piece>(pl->pieces), (int)pl->n_rec, o->tol,
@@ -1021,7 +1016,6 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     q.max_item = tile_edge(ctx, &pl->o, false);
     q.max_item_thin = tile_edge(ctx, &pl->o, true);
     q.mask_kind = nullptr;
-    pl->dense_on_waves = q.max_item <= kMaxItemThin;
     pb[p + 1] = pb[p] + (int64_t)q.nrb * q.ncb;
   }
   const int64_t tp = pb[np];

@@ -485,32 +485,77 @@ __device__ __attribute__((always_inline)) inline void wave_item(const GemmItem& 
     }
     // Two operand groups in flight: the raw loads of group g + 1 are issued
     // before the MFMAs of group g, so their latency hides behind that work.
-    // Loads are unconditional (an inner index past K reads index 0 of the
-    // segment); validity and the segment scale are applied by selects right
-    // before the MFMAs, so no load result is consumed early.
+    // Loads are unconditional; validity and the segment scale are applied by
+    // selects right before the MFMAs, so no load result is consumed early.
+    //
+    // Inner-index order: the two k-steps of a group starting at k0 give lane
+    // row kr the inner indices kp = k0 + 2 kr and kp + 1 (a fixed permutation
+    // of the group's 8 indices, the same for A and B and for every item and
+    // tiling).  An operand contiguous along the inner index then loads both
+    // of a lane's values with one 16-byte load, starting at min(kp, K - 2) so
+    // the pair stays inside the segment; the other operands load the two
+    // values separately (an index past K reads index 0).
     constexpr int G = 4 * kWaveKSteps;
+    static_assert(kWaveKSteps == 2, "inner pairs: two k-steps per group");
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef const d2 __attribute__((address_space(1), aligned(8))) gd2;
+    const bool apair = sLk == 1 && K >= 2;   // A contiguous along the inner index
+    const bool bpair = sRk == 1 && K >= 2;
     double ra0[kWaveKSteps][NA], rb0[kWaveKSteps][NB], ra1[kWaveKSteps][NA], rb1[kWaveKSteps][NB];
     auto load = [&](double (&ra)[kWaveKSteps][NA], double (&rb)[kWaveKSteps][NB], int k0) {
+      const int kp = k0 + 2 * kr;
+      if (apair) {
+        const int s0 = min(kp, K - 2);
 #pragma unroll
-      for (int q = 0; q < kWaveKSteps; ++q) {
-        const int kk = k0 + 4 * q + kr;
-        const int kc = kk < K ? kk : 0;
+        for (int a = 0; a < NA; ++a) {
+          const d2 v = *(gd2*)(L + aoff[a] + s0);
+          ra[0][a] = v.x;
+          ra[1][a] = v.y;
+        }
+      } else {
 #pragma unroll
-        for (int a = 0; a < NA; ++a) ra[q][a] = L[aoff[a] + (int64_t)kc * sLk];
+        for (int q = 0; q < kWaveKSteps; ++q) {
+          const int kc = kp + q < K ? kp + q : 0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) rb[q][b] = R[(int64_t)kc * sRk + boff[b]];
+          for (int a = 0; a < NA; ++a) ra[q][a] = L[aoff[a] + (int64_t)kc * sLk];
+        }
+      }
+      if (bpair) {
+        const int s0 = min(kp, K - 2);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const d2 v = *(gd2*)(R + boff[b] + s0);
+          rb[0][b] = v.x;
+          rb[1][b] = v.y;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < kWaveKSteps; ++q) {
+          const int kc = kp + q < K ? kp + q : 0;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) rb[q][b] = R[(int64_t)kc * sRk + boff[b]];
+        }
       }
     };
     auto compute = [&](const double (&ra)[kWaveKSteps][NA], const double (&rb)[kWaveKSteps][NB],
                        int k0) {
       double av[kWaveKSteps][NA], bv[kWaveKSteps][NB];
+      const int kp = k0 + 2 * kr;
+      // a pair clamped to start at K - 2 holds the wanted index K - 1 second
+      const bool shifted = kp == K - 1;
 #pragma unroll
       for (int q = 0; q < kWaveKSteps; ++q) {
-        const bool kv = k0 + 4 * q + kr < K;
+        const bool kv = kp + q < K;
 #pragma unroll
-        for (int a = 0; a < NA; ++a) av[q][a] = (kv & aval[a]) ? ra[q][a] * scale : 0.0;
+        for (int a = 0; a < NA; ++a) {
+          const double x = (q == 0 && apair && shifted) ? ra[1][a] : ra[q][a];
+          av[q][a] = (kv & aval[a]) ? x * scale : 0.0;
+        }
 #pragma unroll
-        for (int b = 0; b < NB; ++b) bv[q][b] = (kv & bval[b]) ? rb[q][b] : 0.0;
+        for (int b = 0; b < NB; ++b) {
+          const double y = (q == 0 && bpair && shifted) ? rb[1][b] : rb[q][b];
+          bv[q][b] = (kv & bval[b]) ? y : 0.0;
+        }
       }
       if constexpr (!F32) {
 #pragma unroll
