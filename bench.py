@@ -52,7 +52,8 @@ TRAFFIC = {
     "k_recompress_reg": (os.path.join(ROOT, "profiles", "k_recompress_reg_c2_n8192_traffic.md"),
                          ["k_recompress.hip", "clr_internal.h", "k_plan.hip"]),
     "k_ggemm_dense": (os.path.join(ROOT, "profiles", "k_ggemm_dense_c2_n8192_traffic.md"),
-                      ["k_gemm.h", "k_gemm_f64.hip", "clr_internal.h", "k_plan.hip"]),
+                      ["k_gemm.h", "k_gemm_f64.hip", "clr_internal.h", "k_plan.hip", "k_misc.hip",
+                       "clr_api.hip"]),
 }
 
 
@@ -419,7 +420,7 @@ def main():
     }
     roof_gemm = {
         "bound": "mfma",
-        "kernel": "k_ggemm<5, false, false, true> (dense accumulation launch, FP64 form)",
+        "kernel": "k_ggemm<false, false, true> (dense accumulation launch, FP64 form)",
         "achieved": fb["dense_gemm_tflops"],
         "peak": fb["peak"],
         "unit": "TFLOP/s",
