@@ -49,9 +49,9 @@ def log(msg):
 CSRC = os.path.join(ROOT, "paper_1509_00309_amd", "csrc")
 # Counter summaries (profiles/) and the sources whose change invalidates them.
 TRAFFIC = {
-    "k_recompress_reg": (os.path.join(ROOT, "profiles", "k_recompress_reg_c2_n8192_traffic.md"),
+    "k_recompress_reg": (os.path.join(ROOT, "profiles", "k_recompress_reg_lattice3d_n8192_traffic.md"),
                          ["k_recompress.hip", "clr_internal.h", "k_plan.hip"]),
-    "k_ggemm_dense": (os.path.join(ROOT, "profiles", "k_ggemm_dense_c2_n8192_traffic.md"),
+    "k_ggemm_dense": (os.path.join(ROOT, "profiles", "k_ggemm_dense_lattice3d_n8192_traffic.md"),
                       ["k_gemm.h", "k_gemm_f64.hip", "clr_internal.h", "k_plan.hip", "k_misc.hip",
                        "clr_api.hip"]),
 }
@@ -148,8 +148,8 @@ def summarize(stats, wall, form):
 def run_sqrtinv(ctx, n, forms, log_fn):
     """S^-1/2 to convergence, per form: time, iterations, residuals, GEMM throughput."""
     import torch
-    from workloads import config4
-    wl = config4(n, max(2, n // 128))
+    from workloads import lattice_3d_wide
+    wl = lattice_3d_wide(n, max(2, n // 128))
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     del Sd
@@ -192,16 +192,16 @@ def run_sqrtinv(ctx, n, forms, log_fn):
 
 
 def run_batched(ctx, nprod, log_fn):
-    """Config-3 batch: nprod independent products S_p * S_p (N_p ~ U{512..4096}, 16..48
+    """Batch of mixed-size products: nprod independent products S_p * S_p (N_p ~ U{512..4096}, 16..48
     uneven clusters, tol 1e-8) planned once and executed as one graph replay per form;
     plus the full-rank dense limit (N = 4096, 32 blocks, truncation and screening off)
     against the dense FP64 GEMM of the same matrix."""
     import torch
-    from workloads import config3_dense_limit, config3_product
+    from workloads import dense_limit, batch_product
     t0 = time.perf_counter()
     mats, dense_eq, total_n2 = [], 0.0, 0
     for p in range(nprod):
-        wl = config3_product(p)
+        wl = batch_product(p)
         Sd = torch.from_numpy(wl.dense()).cuda()
         mats.append(ctx.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10))
         dense_eq += 2.0 * float(wl.n) ** 3
@@ -240,7 +240,7 @@ def run_batched(ctx, nprod, log_fn):
     out["forms"]["mixed"]["rel_diff_vs_fp64_first8"] = (num / den) ** 0.5
     del mix, ref, mats
     # dense limit
-    wl = config3_dense_limit()
+    wl = dense_limit()
     Sd = torch.from_numpy(wl.dense()).cuda()
     S = ctx.compress(Sd, wl.sizes, wl.sizes, 0.0, 0.0)
     for _ in range(2):
@@ -347,10 +347,10 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     import paper_1509_00309_amd as clr
-    from workloads import config2
+    from workloads import lattice_3d
 
     torch.cuda.set_device(0)
-    wl = config2(args.n)
+    wl = lattice_3d(args.n)
     log(f"workload {wl.name}: N={wl.n}, {len(wl.sizes)} clusters")
     Sd = wl.dense()
     ctx = clr.Context()

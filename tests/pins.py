@@ -12,7 +12,7 @@ from fractions import Fraction
 
 import numpy as np
 
-from workloads import config1, random_blocks, rng_for
+from workloads import line_n512, random_blocks, rng_for
 
 
 # ---------------------------------------------------------------------------
@@ -243,7 +243,7 @@ def pin_ns_diagonal(orc):
 
 def pin_sqrt_inv_eigh(orc):
     """S^-1/2 of the 1D N = 512 overlap-like matrix against an eigendecomposition of the same S."""
-    wl = config1()
+    wl = line_n512()
     S = orc.compress(wl.dense(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     W, info = orc.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=wl.extra["conv_tol"])
     Sd = orc.to_dense(S)
@@ -283,7 +283,7 @@ def pin_cubic_rate(orc):
 
 def pin_dense_limit(orc):
     """tol -> 0, eps_sp -> 0: the CLR product is the dense product (Sec. 4.1, accuracy knobs)."""
-    wl = config1()
+    wl = line_n512()
     Sd = wl.dense()
     S = orc.compress(Sd, wl.sizes, wl.sizes, tol=0.0, drop=0.0)
     C = orc.to_dense(orc.gemm(S, S, tol=0.0, eps_sp=0.0))

@@ -7,8 +7,8 @@ import pytest
 
 import oracle as orc
 import parity
-from workloads import (config1, config2, kernel_matrix, points_3d, random_blocks, rng_for,
-                       scaled_config, sizes_weighted)
+from workloads import (line_n512, lattice_3d, kernel_matrix, points_3d, random_blocks, rng_for,
+                       scaled_workload, sizes_weighted)
 
 pytestmark = pytest.mark.gpu
 
@@ -92,9 +92,9 @@ def test_create_rejects_bad_input(ctx, torch):
 # Compression of an input (drop, diagonal dense, truncated SVD, dense switch)
 # ---------------------------------------------------------------------------
 
-def test_compress_config1(ctx, torch):
-    log("compress config1 (N=512, 1D)")
-    wl = config1()
+def test_compress_line_n512(ctx, torch):
+    log("compress line_n512 (N=512, 1D)")
+    wl = line_n512()
     Sd = wl.dense()
     G = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
@@ -204,9 +204,9 @@ def test_gemm_shape_mismatch(ctx, torch):
     assert e.value.code == 2
 
 
-def test_gemm_config1(ctx, torch):
-    log("gemm config1 S*S")
-    wl = config1()
+def test_gemm_line_n512(ctx, torch):
+    log("gemm line_n512 S*S")
+    wl = line_n512()
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
@@ -220,7 +220,7 @@ def test_gemm_config1(ctx, torch):
 def test_gemm_3d_scaled(ctx, torch):
     """Overlap-like 3D matrix (the N = 8192 physics) at N = 1536: several dozen blocks, ragged sizes."""
     log("gemm 3D scaled N=1536")
-    wl = scaled_config("c2", 1536, seed=140)
+    wl = scaled_workload("lattice", 1536, seed=140)
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
@@ -237,7 +237,7 @@ def test_gemm_3d_scaled(ctx, torch):
 def test_axpby_ns_combination(ctx, torch):
     """T = (-10 X + 3 X^2 + 15 I)/8 (Eq. (9)) with low-rank, dense and identity terms."""
     log("axpby (NS T)")
-    wl = config1()
+    wl = line_n512()
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
@@ -252,9 +252,9 @@ def test_axpby_ns_combination(ctx, torch):
     parity.assert_parity(rep, 1e-11, nblocks=64)
 
 
-def test_sqrt_inv_config1(ctx, torch):
-    log("sqrt_inv config1")
-    wl = config1()
+def test_sqrt_inv_line_n512(ctx, torch):
+    log("sqrt_inv line_n512")
+    wl = line_n512()
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
@@ -271,7 +271,7 @@ def test_sqrt_inv_config1(ctx, torch):
 def test_mixed_gemm_3d_scaled(ctx, torch):
     """FP32-MFMA products with FP64 accumulation: within 10 x tol of the FP64 oracle."""
     log("mixed gemm 3D scaled")
-    wl = scaled_config("c2", 1536, seed=141)
+    wl = scaled_workload("lattice", 1536, seed=141)
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
@@ -318,8 +318,8 @@ def test_gemm_backward_matches_oracle(ctx, torch, seed):
 
 def test_sqrt_inv_backward_matches_oracle(ctx, torch):
     """dS through unrolled iterations (straight-through truncation) vs the oracle's VJP."""
-    log("sqrt_inv backward config1")
-    wl = config1()
+    log("sqrt_inv backward line_n512")
+    wl = line_n512()
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
@@ -356,7 +356,7 @@ def test_autograd_entry_points(ctx, torch):
     (Cd * Wt).sum().backward()
     dA, dB = ctx.gemm_backward(A, B, Wt)
     assert torch.equal(a.grad, dA) and torch.equal(b.grad, dB)
-    wl = config1()
+    wl = line_n512()
     S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     s = S.to_dense().clone().requires_grad_(True)
     W = clr.sqrt_inv_dense(ctx, S, s, 4, 2, tol=wl.tol, eps_sp=wl.eps_sp)
@@ -377,10 +377,10 @@ def _batch_operands(ctx, torch):
         ra = random_blocks(seed, rs, ks, p_zero=0.3, p_dense=0.4, max_rank=8)
         rb = random_blocks(seed + 50, ks, cs, p_zero=0.3, p_dense=0.4, max_rank=8)
         ops.append((gpu_from_random(ctx, torch, ra), gpu_from_random(ctx, torch, rb)))
-    wl = config1()
+    wl = line_n512()
     S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     ops.append((S, S))
-    wl3 = scaled_config("c2", 1536, seed=143)
+    wl3 = scaled_workload("lattice", 1536, seed=143)
     S3 = ctx.compress(torch.from_numpy(wl3.dense()).cuda(), wl3.sizes, wl3.sizes, wl3.tol, 1e-10)
     ops.append((S3, S3))
     return ops
@@ -427,7 +427,7 @@ def test_tile_edges_and_autotune(ctx, torch):
     """Item edges change launch shapes only: results are bit-identical; the autotuner
     returns admissible edges and leaves them set."""
     log("tile edges and autotune")
-    wl = scaled_config("c2", 1536, seed=144)
+    wl = scaled_workload("lattice", 1536, seed=144)
     S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     ref = ctx.gemm(S, S, wl.tol, wl.eps_sp).to_dense().cpu().numpy()
     for de, te in ((32, 64), (96, 48), (64, 32)):
@@ -454,7 +454,7 @@ def test_gemm_full_size_sampled(ctx, torch):
     """N = 8192 3D workload exactly as bench.py times it; 32 result blocks recomputed
     one by one by the oracle (kinds, ranks and values)."""
     log("gemm full size N=8192, sampled blocks")
-    wl = config2(8192)
+    wl = lattice_3d(8192)
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     C = ctx.gemm(S, S, wl.tol, wl.eps_sp)
@@ -518,7 +518,7 @@ def test_sqrt_inv_backward_finite_differences(ctx, torch):
     """dS by the adjoint vs central differences (h = 1e-6) on 32 stored entries,
     truncation off, alpha held fixed."""
     log("sqrt_inv backward vs finite differences")
-    wl = config1()
+    wl = line_n512()
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, 0.0, 1e-10)
     alpha = _alpha_of(S)
@@ -561,7 +561,7 @@ def test_sqrt_inv_backward_eigen_gradient(ctx, torch):
     S^-1/2, Q (Gamma o (Q^T Wbar Q)) Q^T with Gamma_ij = -1/(sqrt(l_i) sqrt(l_j)
     (sqrt(l_i) + sqrt(l_j))), on S's stored blocks."""
     log("sqrt_inv backward vs Daleckii-Krein")
-    wl = scaled_config("c2", 768, nclusters=6, seed=145)
+    wl = scaled_workload("lattice", 768, nclusters=6, seed=145)
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, 0.0, 1e-10)
     kind, _r, _n = S.meta()

@@ -9,7 +9,7 @@ import pytest
 import oracle as orc
 from oracle import clr_oracle
 import pins
-from workloads import config1, random_blocks, rng_for
+from workloads import line_n512, random_blocks, rng_for
 
 
 def test_triple_loop_bit_exact():
@@ -51,7 +51,7 @@ def test_dense_limit_exact():
     assert pins.pin_dense_limit(orc) < 1e-14
 
 
-def test_sqrt_inv_matches_eigh_config1():
+def test_sqrt_inv_matches_eigh_line_n512():
     """With per-product truncation at relative 1e-8 the explicit residual settles near 1e-9, so
     the iteration ends "stalled" above the 1e-10 target; the internal measure reaches 1e-16."""
     err, info = pins.pin_sqrt_inv_eigh(orc)
@@ -62,7 +62,7 @@ def test_sqrt_inv_matches_eigh_config1():
 
 
 def test_alpha_gershgorin_bound():
-    wl = config1()
+    wl = line_n512()
     S = orc.compress(wl.dense(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     a = orc.default_alpha(S)
     Sd = orc.to_dense(S)
@@ -70,9 +70,9 @@ def test_alpha_gershgorin_bound():
     assert np.max(np.abs(a * lam - 1.0)) <= 1.0
 
 
-def test_compress_rules_config1():
+def test_compress_rules_line_n512():
     """Drop below 1e-10, diagonal blocks dense, off-diagonal truncated; dense iff 2r > min."""
-    wl = config1()
+    wl = line_n512()
     Sd = wl.dense()
     S = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
     ro, co = S.offsets()
@@ -97,7 +97,7 @@ def test_compress_rules_config1():
 
 def test_gemm_truncation_error_bound():
     """Each computed C block is within tol * ||C_IJ|| of the exact screened sum (Eckart-Young per block)."""
-    wl = config1()
+    wl = line_n512()
     S = orc.compress(wl.dense(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     C = orc.gemm(S, S, wl.tol, wl.eps_sp)
     E = orc.gemm(S, S, 0.0, wl.eps_sp)

@@ -40,13 +40,13 @@ __all__ = [
     "sizes_weighted",
     "kernel_matrix",
     "kernel_block",
-    "config1",
-    "config2",
-    "config3_product",
-    "config3_dense_limit",
-    "config4",
-    "config5",
-    "scaled_config",
+    "line_n512",
+    "lattice_3d",
+    "batch_product",
+    "dense_limit",
+    "lattice_3d_wide",
+    "adjoint_n4096",
+    "scaled_workload",
     "random_blocks",
     "RandomCLR",
 ]
@@ -153,76 +153,77 @@ def kernel_matrix(points: np.ndarray, a: float, diag: float, chunk: int = 4096) 
 
 
 # ---------------------------------------------------------------------------
-# The five workloads.  Seed = 1000 * config + product index.
+# The named workloads.  Seeds: 1000 (line), 2000 (3-D lattice), 3000 + p
+# (batch product p), 3999 (dense limit), 4000 (wide 3-D lattice), 5000 (adjoint).
 # ---------------------------------------------------------------------------
 
-def config1() -> Workload:
+def line_n512() -> Workload:
     """N = 512 points on a line, 8 clusters of the given sizes, a = 0.5, d = 0.1."""
     rng = rng_for(1000)
     pts = points_1d(rng, 512, 1.0, 0.2)
     sizes = [48, 80, 64, 72, 56, 64, 60, 68]
-    return Workload("c1-1d-n512", pts, sizes, a=0.5, diag=0.1, tol=1e-8, eps_sp=1e-10,
+    return Workload("line-n512", pts, sizes, a=0.5, diag=0.1, tol=1e-8, eps_sp=1e-10,
                     extra={"conv_tol": 1e-10})
 
 
-def config2(n: int = 8192, seed: int = 2000) -> Workload:
+def lattice_3d(n: int = 8192, seed: int = 2000) -> Workload:
     """Jittered 3D lattice (spacing 1.5, jitter 0.3), a = 0.3, d = 0.1, clusters U{96..160}."""
     rng = rng_for(seed)
     pts = points_3d(rng, n, 1.5, 0.3)
     sizes = sizes_until(rng, n, 96, 160)
-    return Workload(f"c2-3d-n{n}", pts, sizes, a=0.3, diag=0.1, tol=1e-6, eps_sp=1e-10)
+    return Workload(f"lattice3d-n{n}", pts, sizes, a=0.3, diag=0.1, tol=1e-6, eps_sp=1e-10)
 
 
-def config3_product(p: int) -> Workload:
-    """Product p of the batch: N ~ U{512..4096}, 16..48 clusters of uneven sizes, c2 physics, tol 1e-8."""
+def batch_product(p: int) -> Workload:
+    """Product p of the batch: N ~ U{512..4096}, 16..48 clusters of uneven sizes, 3-D lattice physics, tol 1e-8."""
     rng = rng_for(3000 + p)
     n = int(rng.integers(512, 4097))
     c = int(rng.integers(16, 49))
     pts = points_3d(rng, n, 1.5, 0.3)
     sizes = sizes_weighted(rng, n, c)
-    return Workload(f"c3-p{p}-n{n}", pts, sizes, a=0.3, diag=0.1, tol=1e-8, eps_sp=1e-10)
+    return Workload(f"batch-p{p}-n{n}", pts, sizes, a=0.3, diag=0.1, tol=1e-8, eps_sp=1e-10)
 
 
-def config3_dense_limit(n: int = 4096, nblocks: int = 32) -> Workload:
+def dense_limit(n: int = 4096, nblocks: int = 32) -> Workload:
     """Full-rank dense limit: truncation and screening off, equal blocks."""
     rng = rng_for(3999)
     pts = points_3d(rng, n, 1.5, 0.3)
     sizes = [n // nblocks] * nblocks
-    return Workload(f"c3-dense-n{n}", pts, sizes, a=0.3, diag=0.1, tol=0.0, eps_sp=0.0)
+    return Workload(f"dense-limit-n{n}", pts, sizes, a=0.3, diag=0.1, tol=0.0, eps_sp=0.0)
 
 
-def config4(n: int = 32768, nclusters: int = 256, seed: int = 4000) -> Workload:
+def lattice_3d_wide(n: int = 32768, nclusters: int = 256, seed: int = 4000) -> Workload:
     """3D lattice spacing 1.2, jitter 0.3, a = 0.2, d = 0.05, sizes {128 +- U{-32..32}}."""
     rng = rng_for(seed)
     pts = points_3d(rng, n, 1.2, 0.3)
     sizes = sizes_pm(rng, n // nclusters, nclusters // 2, 32)
-    return Workload(f"c4-3d-n{n}", pts, sizes, a=0.2, diag=0.05, tol=1e-8, eps_sp=1e-10,
+    return Workload(f"wide3d-n{n}", pts, sizes, a=0.2, diag=0.05, tol=1e-8, eps_sp=1e-10,
                     extra={"conv_tol": 1e-8})
 
 
-def config5(seed: int = 5000) -> Workload:
-    """N = 4096, 32 clusters {128 +- d}, c2 physics, tol 1e-8; 20 fixed iterations."""
+def adjoint_n4096(seed: int = 5000) -> Workload:
+    """N = 4096, 32 clusters {128 +- d}, 3-D lattice physics, tol 1e-8; 20 fixed iterations."""
     rng = rng_for(seed)
     pts = points_3d(rng, 4096, 1.5, 0.3)
     sizes = sizes_pm(rng, 128, 16, 32)
     w = rng.standard_normal((4096, 4096))
-    return Workload("c5-3d-n4096", pts, sizes, a=0.3, diag=0.1, tol=1e-8, eps_sp=1e-10,
+    return Workload("adjoint3d-n4096", pts, sizes, a=0.3, diag=0.1, tol=1e-8, eps_sp=1e-10,
                     extra={"weights": w, "iters": 20, "checkpoint_every": 5})
 
 
-def scaled_config(kind: str, n: int, nclusters: Optional[int] = None, seed: int = 7000,
-                  tol: Optional[float] = None) -> Workload:
+def scaled_workload(kind: str, n: int, nclusters: Optional[int] = None, seed: int = 7000,
+                    tol: Optional[float] = None) -> Workload:
     """Smaller copies of the 3D workloads (same physics) for parity tests the oracle finishes fast."""
     rng = rng_for(seed)
-    if kind == "c2":
+    if kind == "lattice":
         pts = points_3d(rng, n, 1.5, 0.3)
         sizes = sizes_until(rng, n, 96, 160) if nclusters is None else sizes_weighted(rng, n, nclusters)
-        return Workload(f"c2s-n{n}", pts, sizes, 0.3, 0.1, 1e-6 if tol is None else tol, 1e-10)
-    if kind == "c4":
+        return Workload(f"lattice3d-small-n{n}", pts, sizes, 0.3, 0.1, 1e-6 if tol is None else tol, 1e-10)
+    if kind == "wide":
         pts = points_3d(rng, n, 1.2, 0.3)
         nc = nclusters or max(2, n // 128)
         sizes = sizes_weighted(rng, n, nc)
-        return Workload(f"c4s-n{n}", pts, sizes, 0.2, 0.05, 1e-8 if tol is None else tol, 1e-10,
+        return Workload(f"wide3d-small-n{n}", pts, sizes, 0.2, 0.05, 1e-8 if tol is None else tol, 1e-10,
                         extra={"conv_tol": 1e-8})
     raise ValueError(kind)
 
