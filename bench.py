@@ -142,6 +142,7 @@ def summarize(stats, wall, form):
         "computed_blocks": stats[-1]["computed"],
         "out_dense": stats[-1]["out_dense"],
         "out_lowrank": stats[-1]["out_lowrank"],
+        "certified_dense": stats[-1]["certified_dense"],
     }
 
 

@@ -95,9 +95,10 @@ typedef struct {
   double ms_thin;       /* launches of the thin factor products (LD, DL, LL terms)     */
   double ms_dense;      /* launch of the dense accumulation GEMM (DD + densified terms) */
   double flops_rec_engine; /* Golub-Van Loan bidiagonalisation count 4 p q^2 - 4 q^3 / 3
-                              (p >= q the block edges) of the blocks truncated by the
-                              register-resident SVD kernel                              */
+                              (p >= q the block edges) of the blocks the register-resident
+                              SVD kernel bidiagonalises                                 */
   double ms_rec_engine; /* device time of that kernel                                   */
+  int64_t certified_dense; /* dense-accumulated blocks proved dense without an SVD      */
 } clr_gemm_stats;
 
 typedef struct {
@@ -210,6 +211,17 @@ clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_ma
  * per item), otherwise a multiple of 16 up to it.  Results do not depend on
  * these edges, only the launch shapes do. */
 clr_status clr_set_tile_edges(clr_context* ctx, int precision, int dense_edge, int thin_edge);
+
+/* Dense certificate (on by default).  A dense-accumulated block D (m x n,
+ * q = min(m, n), h = floor(q / 2)) is stored dense when its kept rank exceeds
+ * q / 2 (Sec. 4.1 rank rule), which holds as soon as s_h(D) > tol ||D||_F.
+ * Before the truncated SVD, a Cholesky factorisation with diagonal pivoting of
+ * D^T D (or D D^T) shifted by a rounding-safe multiple of tol^2 ||D||_F^2 tries
+ * to prove s_h(D) above that bound with h + 1 columns; proved blocks are
+ * copied out dense without the SVD.  Results are the same either way (the
+ * proof's margin exceeds the SVD's rounding error); only the work differs.
+ * Applies to products and plans created afterwards on this context. */
+clr_status clr_set_dense_certificate(clr_context* ctx, int enable);
 
 /* Autotuner: times the product A B (options as for clr_gemm; output discarded)
  * with every candidate edge (multiples of 32 up to the full tile), best of two

@@ -172,6 +172,10 @@ class Context:
         prec = {"fp64": CLR_FP64, "mixed": CLR_MIXED}[precision]
         self._check(lib.clr_set_tile_edges(self._h, prec, int(dense_edge), int(thin_edge)))
 
+    def set_dense_certificate(self, enable: bool = True):
+        """Prove dense-accumulated blocks dense from their Gram matrix before the SVD."""
+        self._check(lib.clr_set_dense_certificate(self._h, 1 if enable else 0))
+
     def autotune(self, A: "CLRMatrix", B: "CLRMatrix", tol: float, eps_sp: float, screen="abs",
                  precision="fp64", split: int = 0) -> dict:
         """Pick the grouped-GEMM item edges for this context by timing A B."""

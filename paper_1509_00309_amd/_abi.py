@@ -30,7 +30,7 @@ EXPORTS = [
     "clr_get_block", "clr_to_dense", "clr_gemm", "clr_axpby", "clr_sqrt_inv",
     "clr_identity_residual", "clr_gemm_backward", "clr_sqrt_inv_backward",
     "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
-    "clr_set_tile_edges", "clr_autotune",
+    "clr_set_tile_edges", "clr_autotune", "clr_set_dense_certificate",
 ]
 
 
@@ -55,7 +55,8 @@ class GemmStats(C.Structure):
                 ("ms_symbolic", C.c_double), ("ms_products", C.c_double),
                 ("ms_recompress", C.c_double), ("ms_total", C.c_double),
                 ("ms_thin", C.c_double), ("ms_dense", C.c_double),
-                ("flops_rec_engine", C.c_double), ("ms_rec_engine", C.c_double)]
+                ("flops_rec_engine", C.c_double), ("ms_rec_engine", C.c_double),
+                ("certified_dense", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -110,6 +111,7 @@ def _load():
         "clr_plan_execute": [P, P, C.POINTER(GemmStats)],
         "clr_plan_destroy": [P],
         "clr_set_tile_edges": [P, C.c_int, C.c_int, C.c_int],
+        "clr_set_dense_certificate": [P, C.c_int],
         "clr_autotune": [P, P, P, C.POINTER(GemmOpts), IP, IP, DP, DP],
         "clr_gemm_batch": [P, C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(GemmOpts),
                            C.POINTER(P), C.POINTER(GemmStats)],

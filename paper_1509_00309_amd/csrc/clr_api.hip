@@ -46,6 +46,8 @@ struct clr_context {
   // explicitly or by clr_autotune
   int tile_dense[2] = {0, 0};
   int tile_thin[2] = {0, 0};
+  // dense certificate before the truncated SVD of dense-accumulated blocks
+  int dense_cert = 1;
   // Stream-ordered cache of freed matrix allocations: a matrix released on the
   // context stream can back the next matrix of a similar size without a
   // hipMalloc (all users are ordered on the same stream).
@@ -348,24 +350,35 @@ clr_status upload(clr_context* ctx, DevBuf& b, const std::vector<T>& v) {
 // Output-product slots of the recompression launch (one GEMM item and one
 // term per recompressed block).
 // Recompression workspace of n items: the emitted G * basis products (items
-// and segments) and the launch order of the register engine.
+// and segments), the launch order of the register engine, the dense
+// certificates and the launch's counters.
 struct RecWork {
   GemmItem* gi;
   Seg* gs;
   int* order;
+  int* cert;
+  RecCounters* ctr;
 };
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 size_t rec_work_bytes(int64_t nitems) {
   const size_t n = (size_t)std::max<int64_t>(nitems, 1);
-  return (sizeof(GemmItem) * n + 255) / 256 * 256 + (sizeof(Seg) * n + 255) / 256 * 256 +
-         sizeof(int) * n;
+  return align256(sizeof(GemmItem) * n) + align256(sizeof(Seg) * n) + align256(sizeof(int) * n) +
+         align256(sizeof(int) * n) + sizeof(RecCounters);
 }
 RecWork rec_work(void* base, int64_t nitems) {
   const size_t n = (size_t)std::max<int64_t>(nitems, 1);
   char* p = static_cast<char*>(base);
-  const size_t gi_bytes = (sizeof(GemmItem) * n + 255) / 256 * 256;
-  const size_t gs_bytes = (sizeof(Seg) * n + 255) / 256 * 256;
-  return RecWork{reinterpret_cast<GemmItem*>(p), reinterpret_cast<Seg*>(p + gi_bytes),
-                 reinterpret_cast<int*>(p + gi_bytes + gs_bytes)};
+  RecWork w;
+  w.gi = reinterpret_cast<GemmItem*>(p);
+  p += align256(sizeof(GemmItem) * n);
+  w.gs = reinterpret_cast<Seg*>(p);
+  p += align256(sizeof(Seg) * n);
+  w.order = reinterpret_cast<int*>(p);
+  p += align256(sizeof(int) * n);
+  w.cert = reinterpret_cast<int*>(p);
+  p += align256(sizeof(int) * n);
+  w.ctr = reinterpret_cast<RecCounters*>(p);
+  return w;
 }
 
 hipError_t launch_recompress_ctx(clr_context* ctx, const RecItem* items, const Piece* pieces,
@@ -374,7 +387,8 @@ hipError_t launch_recompress_ctx(clr_context* ctx, const RecItem* items, const P
   if (e != hipSuccess) return e;
   const RecWork w = rec_work(ctx->recg.p, nitems);
   return launch_recompress(items, pieces, nitems, tol, as<int>(ctx->status), w.gi, w.gs, w.order,
-                           ctx->stream, timed ? ctx->ev[8] : nullptr, timed ? ctx->ev[9] : nullptr);
+                           ctx->dense_cert ? w.cert : nullptr, w.ctr, ctx->stream,
+                           timed ? ctx->ev[8] : nullptr, timed ? ctx->ev[9] : nullptr);
 }
 
 clr_status copy_matrix(clr_context* ctx, const clr_matrix* src, clr_matrix** out) {
@@ -819,8 +833,14 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
     st->ms_total = elapsed(ctx->ev[0], ctx->ev[3]);
     st->ms_thin = elapsed(ctx->ev[1], ctx->ev[6]);
     st->ms_dense = elapsed(ctx->ev[6], ctx->ev[2]);
-    st->flops_rec_engine = hs[kStFlopsRecEngine];
     st->ms_rec_engine = hc[kCntComputed] > 0 ? elapsed(ctx->ev[8], ctx->ev[9]) : 0.0;
+    if (hc[kCntComputed] > 0) {
+      RecCounters rc;
+      HIP_TRY(ctx, hipMemcpy(&rc, rec_work(ctx->recg.p, hc[kCntComputed]).ctr, sizeof(rc),
+                             hipMemcpyDeviceToHost));
+      st->flops_rec_engine = rc.flops_bidiag;
+      st->certified_dense = (int64_t)rc.certified;
+    }
     HostMeta ha, hb, hcm;
     if ((s = fetch_meta(ctx, A, ha)) != CLR_OK) return bail(s);
     if ((s = fetch_meta(ctx, B, hb)) != CLR_OK) return bail(s);
@@ -869,6 +889,14 @@ extern "C" clr_status clr_set_tile_edges(clr_context* ctx, int precision, int de
                 thin_edge, kMaxItemThin);
   ctx->tile_dense[precision] = dense_edge;
   ctx->tile_thin[precision] = thin_edge;
+  return CLR_OK;
+}
+
+// Dense certificate (a proof from the Gram matrix that a dense-accumulated
+// block keeps more than half its rank, Sec. 4.1 rank rule) before the SVD.
+extern "C" clr_status clr_set_dense_certificate(clr_context* ctx, int enable) {
+  if (!ctx) return CLR_ERR_INVALID_ARG;
+  ctx->dense_cert = enable ? 1 : 0;
   return CLR_OK;
 }
 
@@ -937,6 +965,7 @@ struct clr_plan {
   DevBuf seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2, items_thin2, pieces, rec,
       pool, scratch, acc, recg, status, bases, order;
   int64_t n_thin1 = 0, n_thin2 = 0, n_dense = 0, n_rec = 0;
+  int dense_cert = 1;
   double flops[kNumStats] = {};
   int64_t counts[kNumCounters] = {};
   hipGraph_t graph = nullptr;
@@ -970,7 +999,8 @@ hipError_t plan_launch(clr_plan* pl, hipStream_t s) {
   if (e == hipSuccess && pl->n_rec > 0) {
     const RecWork w = rec_work(pl->recg.p, pl->n_rec);
     e = launch_recompress(as<RecItem>(pl->rec), as<Piece>(pl->pieces), (int)pl->n_rec, o->tol,
-                          as<int>(pl->status), w.gi, w.gs, w.order, s);
+                          as<int>(pl->status), w.gi, w.gs, w.order,
+                          pl->dense_cert ? w.cert : nullptr, w.ctr, s);
   }
   return e;
 }
@@ -1124,7 +1154,7 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   return s;
 }
 
-void plan_stats(const clr_plan* pl, clr_gemm_stats* st) {
+clr_status plan_stats(clr_context* ctx, const clr_plan* pl, clr_gemm_stats* st) {
   memset(st, 0, sizeof(*st));
   st->candidates = (int64_t)pl->flops[kStCandidate];
   st->computed = pl->counts[kCntComputed];
@@ -1139,7 +1169,14 @@ void plan_stats(const clr_plan* pl, clr_gemm_stats* st) {
   st->flops_ll = pl->flops[kStFlopsLL];
   st->flops_densify = pl->flops[kStFlopsDensify];
   st->flops_products = st->flops_dd + st->flops_ld + st->flops_dl + st->flops_ll + st->flops_densify;
-  st->flops_rec_engine = pl->flops[kStFlopsRecEngine];
+  if (pl->n_rec > 0) {
+    RecCounters rc;
+    HIP_TRY(ctx, hipMemcpy(&rc, rec_work(pl->recg.p, pl->n_rec).ctr, sizeof(rc),
+                           hipMemcpyDeviceToHost));
+    st->flops_rec_engine = rc.flops_bidiag;
+    st->certified_dense = (int64_t)rc.certified;
+  }
+  return CLR_OK;
 }
 
 }  // namespace
@@ -1157,6 +1194,7 @@ extern "C" clr_status clr_plan_create(clr_context* ctx, int nprod, const clr_mat
   if (s != CLR_OK) return s;
   clr_plan* pl = new clr_plan();
   pl->ctx = ctx;
+  pl->dense_cert = ctx->dense_cert;
   pl->nprod = nprod;
   pl->o = *opts;
   pl->A.assign(A, A + nprod);
@@ -1202,7 +1240,8 @@ extern "C" clr_status clr_plan_execute(clr_context* ctx, clr_plan* pl, clr_gemm_
   clr_status s = plan_status(ctx, pl);
   if (s != CLR_OK) return s;
   if (st) {
-    plan_stats(pl, st);
+    s = plan_stats(ctx, pl, st);
+    if (s != CLR_OK) return s;
     st->ms_total = elapsed(ctx->ev[0], ctx->ev[3]);
     st->ms_products = st->ms_total;
   }

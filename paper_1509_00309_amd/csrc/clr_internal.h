@@ -19,6 +19,7 @@ constexpr int kMaxItemF32 = 32 * kF32WaveTiles;   // 128
 constexpr int kRecThreads = 512;      // recompression workgroup (32 groups of 16 lanes)
 constexpr int kRecLdsBytes = 140 * 1024;  // dynamic LDS for the working set (160 KiB minus bookkeeping)
 constexpr int kJacobiMaxSweeps = 60;
+constexpr int kCertEdge = 160;        // largest short edge of a block the dense certificate examines
 
 // ---------------------------------------------------------------------------
 // Work descriptors (device resident, built by the planning kernels)
@@ -106,7 +107,7 @@ enum PlanCounter : int {
 // Floating-point per-block statistics of the symbolic phase.
 enum PlanStat : int {
   kStEst = 0, kStFlopsDD, kStFlopsLD, kStFlopsDL, kStFlopsLL, kStFlopsDensify,
-  kStNDD, kStNLD, kStNDL, kStNLL, kStCandidate, kStFlopsRecEngine, kNumStats
+  kStNDD, kStNLD, kStNDL, kStNLL, kStCandidate, kNumStats
 };
 
 // Device view of a CLR matrix's metadata and arena.
@@ -204,11 +205,24 @@ hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, 
 // Items of the LDS grouped GEMM by decreasing estimated cost (slabs times the
 // busiest wave's tiles, in quarter-octave classes) into order[0 .. nitems).
 hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s);
+// Per item, 1 if a dense-path block is proved to stay dense (kept rank above
+// half its short edge), else 0; count (optional) is incremented per proof.
+hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* cert,
+                             unsigned long long* count, hipStream_t s);
+// Device-side statistics of one recompression launch (zeroed by the caller).
+struct RecCounters {
+  double flops_bidiag;              // 4 p q^2 - 4 q^3 / 3 per block the register engine reduces
+  unsigned long long certified;     // blocks proved dense without an SVD
+};
 // order: workspace of nitems ints; when given, the register engine runs its
 // blocks in decreasing order of estimated cost (null: XCD-blocked order).
+// cert: workspace of nitems ints; when given, dense-path blocks are first
+// tested by the dense certificate and the proved ones are copied out without
+// an SVD.  ctr (optional) receives the launch's counters.
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
-                             int* status, GemmItem* gout, Seg* gseg, int* order, hipStream_t s,
-                             hipEvent_t engine_begin = nullptr, hipEvent_t engine_end = nullptr);
+                             int* status, GemmItem* gout, Seg* gseg, int* order, int* cert,
+                             RecCounters* ctr, hipStream_t s, hipEvent_t engine_begin = nullptr,
+                             hipEvent_t engine_end = nullptr);
 hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
                            hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,

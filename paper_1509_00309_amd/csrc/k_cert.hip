@@ -1,0 +1,312 @@
+// Certificate that a dense-accumulated result block stays dense under the
+// rank rule of Sec. 4.1, so that its truncated SVD can be skipped.
+//
+// A block D (m x n) is stored dense when its kept rank r satisfies
+// 2 r > min(m, n), where r is the smallest rank whose discarded tail
+// sqrt(sum_{i >= r} s_i^2) is at most tol ||D||_F.  With q = min(m, n),
+// p = max(m, n) and h = floor(q / 2), the block is dense as soon as
+// s_h > tol ||D||_F (singular values in decreasing order, s_0 the largest).
+//
+// Orient D so that its q columns are the short side (D or D^T, p x q).  By
+// the Courant-Fischer minimax characterisation, s_h(D) >= s_min(D_S) for any
+// h + 1 of those columns S.  The columns are chosen greedily: Cholesky with
+// diagonal pivoting of the Gram matrix D^T D - c I takes at every step the
+// column of largest residual norm (the Gram-matrix form of QR with column
+// pivoting).  If h + 1 steps complete with positive pivots, D_S^T D_S - c I is
+// positive definite up to rounding, and the rounding is bounded by
+//  * the Gram matrix's error, at most gamma_p ||D||_F^2 in the 2-norm
+//    (gamma_k = k u / (1 - k u), u = 2^-53);
+//  * the Cholesky backward error: a factorisation R^T R of A that completes in
+//    floating point satisfies R^T R = A + E with ||E||_2 <= gamma_{q+1}
+//    trace(A) (Higham, Accuracy and Stability of Numerical Algorithms,
+//    Thm. 10.3), and trace(A) <= ||D||_F^2;
+//  * the subtraction of c from the diagonal, at most u ||D||_F^2.
+// The shift c = ||D||_F^2 (9/8 tol^2 + 4 (p + q + 2) u) covers the three
+// terms twice, so success proves s_h(D)^2 > (9/8 tol^2 + 2 (p + q + 2) u)
+// ||D||_F^2.  The margin this leaves between s_h and tol ||D||_F is at least
+// about 7e-9 ||D||_F for every tol, three orders of magnitude above the
+// worst-case error bound of a Householder-based SVD of a block of edge <= 160,
+// so the SVD path reaches the same decision: the certificate changes no
+// result (a certified block is copied out exactly as a block the SVD finds
+// dense), it only skips work.
+//
+// One 512-thread workgroup per block.  The Gram matrix (q x q) is held in
+// registers, NI x NJ entries per thread (rows rc + 16 i, columns cc + 32 j of a
+// 16 x 32 thread grid; NI = ceil(q / 16) and NJ = ceil(q / 32) per size class,
+// one kernel per class), accumulated from 16-deep slabs of D staged in LDS
+// with the next slab's loads in flight.  The right-looking pivoted Cholesky
+// then updates it in place.  Every wave keeps its own copy of the residual
+// diagonal in registers and updates it from the published pivot column with
+// the same arithmetic, so every wave picks the same pivot without a barrier;
+// with the pivot column double-buffered in LDS a step costs one barrier.
+#include "clr_internal.h"
+
+namespace clr {
+namespace {
+
+typedef const double __attribute__((address_space(1))) cgdbl;
+
+constexpr int kCertThreads = 512;
+constexpr int kCertSlab = 16;               // inner indices staged per slab
+constexpr int kCertLd = kCertEdge + 1;
+constexpr int kCertPre = (kCertSlab * kCertEdge + kCertThreads - 1) / kCertThreads;
+constexpr int kCertDiag = (kCertEdge + 63) / 64;   // residual diagonal entries per lane
+
+struct CertLds {
+  double slab[kCertSlab][kCertLd];
+  double col[2][kCertEdge];
+  double dg[kCertEdge];
+};
+
+// Lane permutations inside a DPP row of 16 (vector ALU, no LDS round trip).
+template <int CTRL>
+__device__ __attribute__((always_inline)) inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __attribute__((always_inline)) inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL));
+  const int hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// The value of the partner row: lanes 16 apart (permlane16 swap) or 32 apart
+// (permlane32 swap).  With both operands the same register the two results
+// are the even-row and odd-row values; the lane's partner value is the one
+// that is not its own.
+__device__ __attribute__((always_inline)) inline double other_d16(double v, bool odd) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)(b & 0xffffffffLL), hi = (unsigned)(b >> 32);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const unsigned rl = odd ? l[0] : l[1], rh = odd ? h[0] : h[1];
+  return __longlong_as_double((long long)(((unsigned long long)rh << 32) | rl));
+}
+__device__ __attribute__((always_inline)) inline double other_d32(double v, bool upper) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)(b & 0xffffffffLL), hi = (unsigned)(b >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const unsigned rl = upper ? l[0] : l[1], rh = upper ? h[0] : h[1];
+  return __longlong_as_double((long long)(((unsigned long long)rh << 32) | rl));
+}
+__device__ __attribute__((always_inline)) inline int other_i16(int v, bool odd) {
+  const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  return (int)(odd ? r[0] : r[1]);
+}
+__device__ __attribute__((always_inline)) inline int other_i32(int v, bool upper) {
+  const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return (int)(upper ? r[0] : r[1]);
+}
+
+// Largest value over the wave and, among the lanes holding it, the smallest
+// index: max is exact, so every lane (and every wave given the same values)
+// ends with the same pair.
+__device__ __attribute__((always_inline)) inline void wave_argmax(double& v, int& i, int lane) {
+  const bool odd = (lane >> 4) & 1, upper = lane >= 32;
+  double m = v;
+  m = fmax(m, dpp_d<0xB1>(m));    // quad_perm [1,0,3,2]
+  m = fmax(m, dpp_d<0x4E>(m));    // quad_perm [2,3,0,1]
+  m = fmax(m, dpp_d<0x141>(m));   // row_half_mirror
+  m = fmax(m, dpp_d<0x140>(m));   // row_mirror
+  m = fmax(m, other_d16(m, odd));
+  m = fmax(m, other_d32(m, upper));
+  int k = v == m ? i : 0x7fffffff;
+  k = min(k, dpp_i<0xB1>(k));
+  k = min(k, dpp_i<0x4E>(k));
+  k = min(k, dpp_i<0x141>(k));
+  k = min(k, dpp_i<0x140>(k));
+  k = min(k, other_i16(k, odd));
+  k = min(k, other_i32(k, upper));
+  v = m;
+  i = k;
+}
+
+template <int NI, int NJ>
+__device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& it, double tol,
+                                                                 CertLds& L) {
+  const int tid = threadIdx.x;
+  const int m = it.m, n = it.n;
+  const int q = m < n ? m : n, p = m < n ? n : m;
+  const bool trans = m < n;   // columns of D^T are the short side
+  cgdbl* D = (cgdbl*)it.D;
+  const int64_t ldd = it.ldd;
+  const int rc = tid & 15, cc = tid >> 4, lane = tid & 63;
+
+  // ---- Gram matrix G^T G of the p x q orientation G
+  double acc[NI][NJ];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[i][j] = 0.0;
+  for (int e = tid; e < kCertSlab * kCertLd; e += kCertThreads) {
+    const int a = e % kCertLd;
+    if (a >= q) L.slab[e / kCertLd][a] = 0.0;
+  }
+  // staging slots of this thread: consecutive threads read consecutive
+  // addresses of D
+  int skk[kCertPre], sa[kCertPre];
+#pragma unroll
+  for (int u = 0; u < kCertPre; ++u) {
+    const int e = tid + kCertThreads * u;
+    skk[u] = trans ? e / q : e % kCertSlab;
+    sa[u] = trans ? e % q : e / kCertSlab;
+    if (e >= kCertSlab * q) skk[u] = -1;
+  }
+  double pre[kCertPre];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < kCertPre; ++u) {
+      const int k = k0 + skk[u];
+      pre[u] = 0.0;
+      if (skk[u] >= 0 && k < p)
+        pre[u] = trans ? D[sa[u] + (int64_t)k * ldd] : D[k + (int64_t)sa[u] * ldd];
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < p; k0 += kCertSlab) {
+    __syncthreads();   // previous slab consumed
+#pragma unroll
+    for (int u = 0; u < kCertPre; ++u)
+      if (skk[u] >= 0) L.slab[skk[u]][sa[u]] = pre[u];
+    __syncthreads();
+    if (k0 + kCertSlab < p) fetch(k0 + kCertSlab);
+#pragma unroll 2
+    for (int kk = 0; kk < kCertSlab; ++kk) {
+      double x[NI], y[NJ];
+#pragma unroll
+      for (int i = 0; i < NI; ++i) x[i] = L.slab[kk][rc + 16 * i];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) y[j] = L.slab[kk][cc + 32 * j];
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
+    }
+  }
+
+  // ---- residual diagonal (every wave's own copy), ||D||_F^2, the shift
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int a = rc + 16 * i;
+      if (a == cc + 32 * j && a < q) L.dg[a] = acc[i][j];
+    }
+  __syncthreads();
+  double dgr[kCertDiag];
+  bool cb[kCertDiag];
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < kCertDiag; ++t) {
+    const int a = lane + 64 * t;
+    dgr[t] = a < q ? L.dg[a] : 0.0;
+    cb[t] = a >= q;
+    s += dgr[t];
+  }
+  // every wave sums the same values in the same order, then takes lane 0's sum
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  s = __shfl(s, 0, 64);
+  const double c = s * (1.125 * tol * tol + 4.0 * (double)(p + q + 2) * 0x1p-53);
+  // no underflow in the Gram matrix and no overflow
+  if (!(s > 0x1p-600 && s < 0x1p+1000)) return false;
+#pragma unroll
+  for (int t = 0; t < kCertDiag; ++t) dgr[t] -= c;
+
+  // ---- h + 1 steps of Cholesky with diagonal pivoting
+  const int h = q / 2;
+  int buf = 0;
+  for (int step = 0; step <= h; ++step) {
+    double bv = -__builtin_huge_val();
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < kCertDiag; ++t)
+      if (!cb[t] && dgr[t] > bv) {
+        bv = dgr[t];
+        bi = lane + 64 * t;
+      }
+    wave_argmax(bv, bi, lane);
+    // identical in every wave: the whole workgroup leaves together
+    if (!(bv > 0.0)) return false;
+    const int piv = __builtin_amdgcn_readfirstlane(bi);
+    const double inv = 1.0 / sqrt(bv);
+    double* colb = L.col[buf];
+    if (cc == (piv & 31)) {
+      // one branch per register column (piv is uniform), so acc is only ever
+      // indexed by constants and stays in registers
+      const int jj = piv >> 5;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (j == jj) {
+#pragma unroll
+          for (int i = 0; i < NI; ++i) {
+            const int a = rc + 16 * i;
+            if (a < q) colb[a] = acc[i][j];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    double x[NI], y[NJ];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) x[i] = colb[min(rc + 16 * i, q - 1)] * inv;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) y[j] = colb[min(cc + 32 * j, q - 1)] * inv;
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = fma(-x[i], y[j], acc[i][j]);
+#pragma unroll
+    for (int t = 0; t < kCertDiag; ++t) {
+      const int a = lane + 64 * t;
+      if (a == piv) {
+        cb[t] = true;
+      } else if (!cb[t]) {
+        const double l = colb[a] * inv;
+        dgr[t] = fma(-l, l, dgr[t]);
+      }
+    }
+    buf ^= 1;
+  }
+  return true;
+}
+
+// Size class (qlo, 16 NI]: NI x NJ Gram entries per thread.
+template <int NI, int NJ>
+__global__ __launch_bounds__(kCertThreads, NI * NJ <= 32 ? 2 : 1) void k_dense_cert(
+    const RecItem* __restrict__ items, int nitems, double tol, int qlo, int* __restrict__ cert,
+    unsigned long long* __restrict__ count) {
+  __shared__ CertLds L;
+  const int per = gridDim.x / 8;
+  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (item >= nitems) return;
+  const RecItem it = items[item];
+  const int q = it.m < it.n ? it.m : it.n;
+  if (!(it.path == kPathDense && tol > 0.0 && q > qlo && q <= 16 * NI && it.D != nullptr)) return;
+  const bool ok = cert_block<NI, NJ>(it, tol, L);
+  if (ok && threadIdx.x == 0) {
+    cert[item] = 1;
+    if (count) atomicAdd(count, 1ull);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* cert,
+                             unsigned long long* count, hipStream_t s) {
+  static_assert(16 * 10 == kCertEdge && 32 * 5 == kCertEdge, "largest size class covers kCertEdge");
+  if (nitems <= 0) return hipSuccess;
+  hipError_t e = launch_fill_i32(cert, 0, nitems, s);
+  if (e != hipSuccess) return e;
+  const int grid = ((nitems + 7) / 8) * 8;
+  hipLaunchKernelGGL((k_dense_cert<6, 3>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
+                     0, cert, count);
+  hipLaunchKernelGGL((k_dense_cert<8, 4>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
+                     96, cert, count);
+  hipLaunchKernelGGL((k_dense_cert<10, 5>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems,
+                     tol, 128, cert, count);
+  return hipGetLastError();
+}
+
+}  // namespace clr

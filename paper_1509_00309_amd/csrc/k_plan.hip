@@ -87,12 +87,6 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
   const bool force = P.square && I == J;
   const int mn = m < n ? m : n;
   const bool densify = force || anydd || 2 * rcat >= mn;
-  // Golub-Van Loan count of the register-resident truncation (dense path,
-  // truncation on, both edges <= 160): bidiagonalisation 4 p q^2 - 4 q^3 / 3
-  const int pe = m > n ? m : n, qe = mn;
-  const double frec = (densify && !force && P.tol != 0.0 && pe <= 160)
-                          ? 4.0 * pe * (double)qe * qe - 4.0 * (double)qe * qe * qe / 3.0
-                          : 0.0;
   int64_t c[kNumCounters];
   for (int i = 0; i < kNumCounters; ++i) c[i] = 0;
   if (computed) {
@@ -118,8 +112,7 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
                                computed ? (double)nld : 0.0,
                                computed ? (double)ndl : 0.0,
                                computed ? (double)nll : 0.0,
-                               candidate ? 1.0 : 0.0,
-                               computed ? frec : 0.0};
+                               candidate ? 1.0 : 0.0};
   for (int i = 0; i < kNumStats; ++i) st[(int64_t)i * npairs + pair] = s[i];
   flags[pair] = (computed ? kFlagComputed : 0) | (densify ? kFlagDensify : 0) |
                 (force ? kFlagForce : 0);

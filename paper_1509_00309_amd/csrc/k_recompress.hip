@@ -1,6 +1,6 @@
 // Recompression of accumulated result blocks, FP64 (Sec. 4.1, Eqs. (5)-(7)).
 //
-// One workgroup (1024 threads) per result block.  Two paths:
+// One workgroup (512 threads) per result block.  Two paths:
 //  * dense path: the block D (m x n) was accumulated densely.  ||D||_F
 //    decides the drop; the singular values decide the kept rank r (smallest r
 //    whose discarded tail sqrt(sum_{i>=r} s_i^2) is <= tol * ||D||_F).  If
@@ -500,7 +500,7 @@ CLR_INLINE int svd_rank(PT* G, int p, int q, int64_t ld, double tol, int* status
 //  * Householder bidiagonalisation G = U_B B V_B^T.  Every wave computes each
 //    reflector itself from the column or row published in LDS (identical
 //    inputs and reduction order give bitwise identical reflectors), so a step
-//    costs four workgroup barriers.  The right reflectors stay in LDS.
+//    costs three workgroup barriers.  The right reflectors stay in LDS.
 //  * Singular values of B by multisection on the Golub-Kahan tridiagonal
 //    (zero diagonal, off-diagonals d_0, e_0, d_1, ...; eigenvalues +-sigma_i)
 //    with Sturm counts.  A first round probes 512 log-spaced points, later
@@ -1704,10 +1704,12 @@ CLR_INLINE void dense_general(const RecItem& it, PT* G, int p, int q, bool trans
   dense_truncated_out(it, G, p, p, q, trans, r, normc, sh);
 }
 
+// certified: the dense certificate proved the kept rank above q / 2, so the
+// block is copied out without the SVD (the SVD would reach the same result).
 template <bool REG>
 CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* status,
-                           RecShared& sh, GemmItem* gout = nullptr, Seg* gseg = nullptr,
-                           int gidx = 0) {
+                           RecShared& sh, bool certified, GemmItem* gout = nullptr,
+                           Seg* gseg = nullptr, int gidx = 0, double* flops_bidiag = nullptr) {
   const int m = it.m, n = it.n;
   const cgdbl* D = (const cgdbl*)it.D;
   double part = 0.0;
@@ -1724,7 +1726,7 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
     return;
   }
   const int q = m < n ? m : n;
-  if (it.path == kPathForceDense || tol == 0.0) {
+  if (it.path == kPathForceDense || tol == 0.0 || certified) {
     copy_dense_out(it);
     write_meta(it, 1, q, normc);
     return;
@@ -1737,6 +1739,8 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
     RegTile a;
     reg_load(a, it.D, it.ldd, trans, 1.0 / normc, p, q);
     reg_bidiag(a, p, q, L);
+    if (flops_bidiag && threadIdx.x == 0)
+      atomicAdd(flops_bidiag, 4.0 * p * (double)q * q - 4.0 * (double)q * q * q / 3.0);
     const int r = reg_decide(q, tol, L, sh);
     if (r == 0) {
       write_meta(it, 0, 0, 0.0);
@@ -1892,7 +1896,8 @@ __device__ inline bool item_guard(const RecItem& it, double tol, int* status) {
 
 __global__ __launch_bounds__(kRecThreads) void k_recompress(const RecItem* __restrict__ items,
                                                             const Piece* __restrict__ pieces,
-                                                            int nitems, double tol, int* status) {
+                                                            int nitems, double tol, int* status,
+                                                            const int* __restrict__ cert) {
   extern __shared__ double lds[];
   __shared__ RecShared sh;
   const int per = gridDim.x / 8;
@@ -1904,32 +1909,35 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress(const RecItem* __res
   if (it.path == kPathLowRank)
     lowrank_path(it, pieces, tol, lds, status, sh);
   else
-    dense_path<false>(it, tol, lds, status, sh);
+    dense_path<false>(it, tol, lds, status, sh, cert != nullptr && cert[item] != 0);
 }
 
 // Longest-first launch order of the register engine's blocks (one workgroup
 // per block, so a long block started last sets the end of the launch).  The
 // bidiagonalisation dominates and costs about q steps of a fixed overhead
 // plus the trailing-matrix work, so the class is 4 log2(q (q + p + 64));
-// blocks off the register path exit at once and go last.  Histogram, scan
+// blocks off the register path exit at once and, with the blocks proved dense
+// (a copy), go last.  Histogram, scan
 // from the most expensive class down, scatter (the order inside a class does
 // not change any result).
 constexpr int kRecOrderClasses = 64;
 
-__device__ inline int rec_cost_class(const RecItem& it, double tol) {
-  if (!register_item(it, tol)) return 0;
+__device__ inline int rec_cost_class(const RecItem& it, double tol, bool certified) {
+  if (!register_item(it, tol) || certified) return 0;
   const int q = min(it.m, it.n), p = max(it.m, it.n);
   const double cost = (double)q * (double)(q + p + 64);
   return min(kRecOrderClasses - 1, max(1, (int)(4.0 * log2(cost)) - 40));
 }
 
 __global__ __launch_bounds__(1024) void k_rec_order(const RecItem* __restrict__ items, int n,
-                                                    double tol, int* __restrict__ order) {
+                                                    double tol, const int* __restrict__ cert,
+                                                    int* __restrict__ order) {
   __shared__ int cnt[kRecOrderClasses];
   const int tid = threadIdx.x;
   if (tid < kRecOrderClasses) cnt[tid] = 0;
   __syncthreads();
-  for (int i = tid; i < n; i += 1024) atomicAdd(&cnt[rec_cost_class(items[i], tol)], 1);
+  for (int i = tid; i < n; i += 1024)
+    atomicAdd(&cnt[rec_cost_class(items[i], tol, cert != nullptr && cert[i] != 0)], 1);
   __syncthreads();
   if (tid == 0) {
     int run = 0;
@@ -1940,14 +1948,17 @@ __global__ __launch_bounds__(1024) void k_rec_order(const RecItem* __restrict__ 
     }
   }
   __syncthreads();
-  for (int i = tid; i < n; i += 1024) order[atomicAdd(&cnt[rec_cost_class(items[i], tol)], 1)] = i;
+  for (int i = tid; i < n; i += 1024)
+    order[atomicAdd(&cnt[rec_cost_class(items[i], tol, cert != nullptr && cert[i] != 0)], 1)] = i;
 }
 
 __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* __restrict__ items,
                                                                 int nitems, double tol,
                                                                 int* status, GemmItem* gout,
                                                                 Seg* gseg,
-                                                                const int* __restrict__ order) {
+                                                                const int* __restrict__ order,
+                                                                const int* __restrict__ cert,
+                                                                double* flops_bidiag) {
   extern __shared__ double lds[];
   __shared__ RecShared sh;
   int item;
@@ -1962,7 +1973,8 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* _
   const RecItem it = items[item];
   if (!register_item(it, tol)) return;
   if (!item_guard(it, tol, status)) return;
-  dense_path<true>(it, tol, lds, status, sh, gout, gseg, item);
+  dense_path<true>(it, tol, lds, status, sh, cert != nullptr && cert[item] != 0, gout, gseg, item,
+                   flops_bidiag);
 }
 
 // Dynamic-LDS limits of the recompression kernels; done once, before any
@@ -1980,8 +1992,9 @@ hipError_t prepare_recompress() {
 }
 
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
-                             int* status, GemmItem* gout, Seg* gseg, int* order, hipStream_t s,
-                             hipEvent_t engine_begin, hipEvent_t engine_end) {
+                             int* status, GemmItem* gout, Seg* gseg, int* order, int* cert,
+                             RecCounters* ctr, hipStream_t s, hipEvent_t engine_begin,
+                             hipEvent_t engine_end) {
   if (nitems <= 0) return hipSuccess;
   {
     hipError_t e = prepare_recompress();
@@ -1993,8 +2006,20 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
   hipError_t e = launch_fill_i32(reinterpret_cast<int*>(gout), 0,
                                  (int64_t)nitems * (int64_t)(sizeof(GemmItem) / sizeof(int)), s);
   if (e != hipSuccess) return e;
+  if (ctr) {
+    static_assert(sizeof(RecCounters) % sizeof(double) == 0, "counters are cleared as doubles");
+    e = launch_fill_f64(reinterpret_cast<double*>(ctr), 0.0,
+                        (int64_t)(sizeof(RecCounters) / sizeof(double)), s);
+    if (e != hipSuccess) return e;
+  }
+  if (cert && tol > 0.0) {
+    e = launch_dense_cert(items, nitems, tol, cert, ctr ? &ctr->certified : nullptr, s);
+    if (e != hipSuccess) return e;
+  } else {
+    cert = nullptr;
+  }
   if (order) {
-    hipLaunchKernelGGL(k_rec_order, dim3(1), dim3(1024), 0, s, items, nitems, tol, order);
+    hipLaunchKernelGGL(k_rec_order, dim3(1), dim3(1024), 0, s, items, nitems, tol, cert, order);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -2003,7 +2028,8 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_recompress_reg, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items,
-                     nitems, tol, status, gout, gseg, order);
+                     nitems, tol, status, gout, gseg, order, cert,
+                     ctr ? &ctr->flops_bidiag : nullptr);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (engine_end) {
@@ -2011,7 +2037,7 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_recompress, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items, pieces,
-                     nitems, tol, status);
+                     nitems, tol, status, cert);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // other factors of the truncated register-engine blocks: G_orig * basis on FP64 MFMA

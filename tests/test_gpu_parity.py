@@ -7,8 +7,8 @@ import pytest
 
 import oracle as orc
 import parity
-from workloads import (line_n512, lattice_3d, kernel_matrix, points_3d, random_blocks, rng_for,
-                       scaled_workload, sizes_weighted)
+from workloads import (line_n512, lattice_3d, kernel_matrix, points_1d, points_3d, random_blocks,
+                       rng_for, scaled_workload, sizes_weighted)
 
 pytestmark = pytest.mark.gpu
 
@@ -232,6 +232,64 @@ def test_gemm_3d_scaled(ctx, torch):
     parity.assert_parity(rep, FP64_BOUND, nblocks=nb)
     log(f"  blocks={nb} computed={st.computed} dense={st.out_dense} lr={st.out_lowrank} "
         f"err={rep.rel_err:.2e} ambiguous={len(rep.ambiguous)}")
+
+
+def _bitwise_same(A, B):
+    ka, ra, na = A.meta()
+    kb, rb, nb = B.meta()
+    assert np.array_equal(ka, kb) and np.array_equal(ra, rb) and np.array_equal(na, nb)
+    assert np.array_equal(A.to_dense().cpu().numpy(), B.to_dense().cpu().numpy())
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-8])
+def test_dense_certificate_changes_nothing(torch, tol):
+    """Blocks proved dense from their Gram matrix skip the SVD: the product is bit for bit the one
+    computed without the proof (3D workload at N = 1536, blocks of the register engine)."""
+    import paper_1509_00309_amd as clr
+    log(f"dense certificate on/off, 3D N=1536, tol {tol}")
+    wl = scaled_workload("lattice", 1536, seed=146, tol=tol)
+    Sd = wl.dense()
+    c = clr.Context()
+    S = c.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, tol, 1e-10)
+    C_on, st_on = c.gemm(S, S, tol, wl.eps_sp, stats=True)
+    c.set_dense_certificate(False)
+    C_off, st_off = c.gemm(S, S, tol, wl.eps_sp, stats=True)
+    log(f"  certified {st_on.certified_dense} of {st_on.out_dense} dense; bidiagonalisation flops "
+        f"{st_on.flops_rec_engine:.3e} vs {st_off.flops_rec_engine:.3e} without the proof")
+    assert 0 < st_on.certified_dense <= st_on.out_dense
+    assert st_off.certified_dense == 0
+    assert st_on.flops_rec_engine < st_off.flops_rec_engine
+    _bitwise_same(C_on, C_off)
+
+
+def test_dense_certificate_general_kernel(torch):
+    """Blocks whose long edge exceeds 160 go to the general recompression kernel; the certificate
+    proves the dense ones there as well.  Compression (dense and low-rank results) and the product
+    are unchanged by it and match the oracle."""
+    import paper_1509_00309_amd as clr
+    log("dense certificate, general-kernel blocks")
+    sizes = [120, 230, 64, 300, 150]
+    n = sum(sizes)
+    Sd3 = kernel_matrix(points_3d(rng_for(148), n, 1.5, 0.3), 0.3, 0.1)   # dense blocks
+    Sd1 = kernel_matrix(points_1d(rng_for(149), n, 1.0, 0.2), 0.05, 0.1)  # low-rank blocks
+    c = clr.Context()
+    for Sd, tol in ((Sd3, 1e-6), (Sd1, 1e-6), (Sd1, 1e-8)):
+        c.set_dense_certificate(True)
+        G_on = c.compress(torch.from_numpy(Sd).cuda(), sizes, sizes, tol, 1e-12)
+        c.set_dense_certificate(False)
+        G_off = c.compress(torch.from_numpy(Sd).cuda(), sizes, sizes, tol, 1e-12)
+        _bitwise_same(G_on, G_off)
+        O = orc.compress(Sd, sizes, sizes, tol, 1e-12)
+        E = orc.compress(Sd, sizes, sizes, 0.0, 1e-12)
+        parity.assert_parity(parity.compare(G_on, O, tol, exact=E), FP64_BOUND, nblocks=25)
+    c.set_dense_certificate(True)
+    S = c.compress(torch.from_numpy(Sd3).cuda(), sizes, sizes, 1e-6, 1e-12)
+    C, st = c.gemm(S, S, 1e-6, 1e-10, stats=True)
+    log(f"  product: certified {st.certified_dense} of {st.out_dense} dense")
+    assert st.certified_dense > 0
+    O = orc.compress(Sd3, sizes, sizes, 1e-6, 1e-12)
+    rep = parity.compare(C, orc.gemm(O, O, 1e-6, 1e-10), 1e-6, exact=orc.gemm(O, O, 0.0, 1e-10))
+    parity.assert_parity(rep, FP64_BOUND, nblocks=25)
 
 
 def test_axpby_ns_combination(ctx, torch):
