@@ -30,12 +30,13 @@
 // result (a certified block is copied out exactly as a block the SVD finds
 // dense), it only skips work.
 //
-// One 512-thread workgroup per block.  The Gram matrix (q x q) is held in
-// registers, NI x NJ entries per thread (rows rc + 16 i, columns cc + 32 j of a
-// 16 x 32 thread grid; NI = ceil(q / 16) and NJ = ceil(q / 32) per size class,
-// one kernel per class), accumulated from 16-deep slabs of D staged in LDS
-// with the next slab's loads in flight.  The right-looking pivoted Cholesky
-// then updates it in place.  Every wave keeps its own copy of the residual
+// One 512-thread workgroup per block.  The Gram matrix (q x q) is computed on
+// FP64 MFMA (v_mfma_f64_16x16x4) from 16-deep slabs of D staged in LDS, with
+// the next slab's loads in flight, and stays in the MFMA output registers:
+// the 8 waves form a 2 x 4 grid, wave (wr, wc) owns the 16 x 16 tiles
+// (wr + 2 u, wc + 4 w) for u < TU, w < TW (TU = ceil(T / 2), TW = ceil(T / 4),
+// T = ceil(q / 16), one kernel per size class of q).  The right-looking
+// pivoted Cholesky then updates those registers in place.  Every wave keeps its own copy of the residual
 // diagonal in registers and updates it from the published pivot column with
 // the same arithmetic, so every wave picks the same pivot without a barrier;
 // with the pivot column double-buffered in LDS a step costs one barrier.
@@ -49,12 +50,12 @@ typedef const double __attribute__((address_space(1))) cgdbl;
 constexpr int kCertThreads = 512;
 constexpr int kCertSlab = 16;               // inner indices staged per slab
 constexpr int kCertLd = kCertEdge + 1;
-constexpr int kCertPre = (kCertSlab * kCertEdge + kCertThreads - 1) / kCertThreads;
 constexpr int kCertDiag = (kCertEdge + 63) / 64;   // residual diagonal entries per lane
+constexpr int kCertColLd = 64 * kCertDiag;          // pivot column, zero beyond q
 
 struct CertLds {
   double slab[kCertSlab][kCertLd];
-  double col[2][kCertEdge];
+  double col[2][kCertColLd];
   double dg[kCertEdge];
 };
 
@@ -122,77 +123,94 @@ __device__ __attribute__((always_inline)) inline void wave_argmax(double& v, int
   i = k;
 }
 
-template <int NI, int NJ>
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int TU, int TW>
 __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& it, double tol,
                                                                  CertLds& L) {
   const int tid = threadIdx.x;
   const int m = it.m, n = it.n;
   const int q = m < n ? m : n, p = m < n ? n : m;
-  const bool trans = m < n;   // columns of D^T are the short side
+  const int T = (q + 15) >> 4;   // 16 x 16 tiles per dimension
+  const bool trans = m < n;      // columns of D^T are the short side
   cgdbl* D = (cgdbl*)it.D;
   const int64_t ldd = it.ldd;
-  const int rc = tid & 15, cc = tid >> 4, lane = tid & 63;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  static_assert(16 + 15 + 32 * (TU - 1) + 12 < kCertColLd && 48 + 15 + 64 * (TW - 1) < kCertColLd,
+                "pivot-column reads stay inside the zero-padded column");
+  // MFMA f64 16x16x4 lanes: operand row/column lc, inner index kr; output
+  // rows kr + 4 v (v < 4) of column lc
+  const int lc = lane & 15, kr = lane >> 4;
 
   // ---- Gram matrix G^T G of the p x q orientation G
-  double acc[NI][NJ];
+  d4 acc[TU][TW];
 #pragma unroll
-  for (int i = 0; i < NI; ++i)
+  for (int u = 0; u < TU; ++u)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[i][j] = 0.0;
+    for (int w = 0; w < TW; ++w) acc[u][w] = d4{0.0, 0.0, 0.0, 0.0};
   for (int e = tid; e < kCertSlab * kCertLd; e += kCertThreads) {
     const int a = e % kCertLd;
     if (a >= q) L.slab[e / kCertLd][a] = 0.0;
   }
-  // staging slots of this thread: consecutive threads read consecutive
-  // addresses of D
-  int skk[kCertPre], sa[kCertPre];
+  // pivot-column entries beyond q stay zero: reads need no clamping, so their
+  // addresses are one base register plus constant offsets
+  for (int e = tid; e < 2 * kCertColLd; e += kCertThreads)
+    if (e % kCertColLd >= q) L.col[e / kCertColLd][e % kCertColLd] = 0.0;
+  // staging slots of this thread (16 q <= 512 TU elements per slab):
+  // consecutive threads read consecutive addresses of D; slot = (kk << 8) | a
+  constexpr int PRE = TU;
+  int slot[PRE];
 #pragma unroll
-  for (int u = 0; u < kCertPre; ++u) {
+  for (int u = 0; u < PRE; ++u) {
     const int e = tid + kCertThreads * u;
-    skk[u] = trans ? e / q : e % kCertSlab;
-    sa[u] = trans ? e % q : e / kCertSlab;
-    if (e >= kCertSlab * q) skk[u] = -1;
+    const int kk = trans ? e / q : e % kCertSlab;
+    const int a = trans ? e % q : e / kCertSlab;
+    slot[u] = e < kCertSlab * q ? (kk << 8) | a : -1;
   }
-  double pre[kCertPre];
+  double pre[PRE];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < kCertPre; ++u) {
-      const int k = k0 + skk[u];
+    for (int u = 0; u < PRE; ++u) {
+      const int k = k0 + (slot[u] >> 8), a = slot[u] & 255;
       pre[u] = 0.0;
-      if (skk[u] >= 0 && k < p)
-        pre[u] = trans ? D[sa[u] + (int64_t)k * ldd] : D[k + (int64_t)sa[u] * ldd];
+      if (slot[u] >= 0 && k < p) pre[u] = trans ? D[a + (int64_t)k * ldd] : D[k + (int64_t)a * ldd];
     }
   };
   fetch(0);
   for (int k0 = 0; k0 < p; k0 += kCertSlab) {
     __syncthreads();   // previous slab consumed
 #pragma unroll
-    for (int u = 0; u < kCertPre; ++u)
-      if (skk[u] >= 0) L.slab[skk[u]][sa[u]] = pre[u];
+    for (int u = 0; u < PRE; ++u)
+      if (slot[u] >= 0) L.slab[slot[u] >> 8][slot[u] & 255] = pre[u];
     __syncthreads();
     if (k0 + kCertSlab < p) fetch(k0 + kCertSlab);
 #pragma unroll 2
-    for (int kk = 0; kk < kCertSlab; ++kk) {
-      double x[NI], y[NJ];
+    for (int s4 = 0; s4 < kCertSlab / 4; ++s4) {
+      double av[TU], bv[TW];
 #pragma unroll
-      for (int i = 0; i < NI; ++i) x[i] = L.slab[kk][rc + 16 * i];
+      for (int u = 0; u < TU; ++u) av[u] = L.slab[4 * s4 + kr][min(16 * (wr + 2 * u) + lc, kCertEdge - 1)];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) y[j] = L.slab[kk][cc + 32 * j];
+      for (int w = 0; w < TW; ++w) bv[w] = L.slab[4 * s4 + kr][min(16 * (wc + 4 * w) + lc, kCertEdge - 1)];
 #pragma unroll
-      for (int i = 0; i < NI; ++i)
+      for (int u = 0; u < TU; ++u)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[i][j] = fma(x[i], y[j], acc[i][j]);
+        for (int w = 0; w < TW; ++w)
+          if (wr + 2 * u < T && wc + 4 * w < T)   // wave-uniform
+            acc[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[w], acc[u][w], 0, 0, 0);
     }
   }
 
   // ---- residual diagonal (every wave's own copy), ||D||_F^2, the shift
 #pragma unroll
-  for (int i = 0; i < NI; ++i)
+  for (int u = 0; u < TU; ++u)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int a = rc + 16 * i;
-      if (a == cc + 32 * j && a < q) L.dg[a] = acc[i][j];
-    }
+    for (int w = 0; w < TW; ++w)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * (wr + 2 * u) + kr + 4 * v, b = 16 * (wc + 4 * w) + lc;
+        if (a == b && a < q) L.dg[a] = acc[u][w][v];
+      }
   __syncthreads();
   double dgr[kCertDiag];
   bool cb[kCertDiag];
@@ -232,49 +250,57 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
     const int piv = __builtin_amdgcn_readfirstlane(bi);
     const double inv = 1.0 / sqrt(bv);
     double* colb = L.col[buf];
-    if (cc == (piv & 31)) {
-      // one branch per register column (piv is uniform), so acc is only ever
-      // indexed by constants and stays in registers
-      const int jj = piv >> 5;
+    const int tp = piv >> 4;   // tile column of the pivot
+    if (wc == (tp & 3) && lc == (piv & 15)) {
+      // one branch per register tile column (uniform in the wave), so acc is
+      // only ever indexed by constants and stays in registers
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        if (j == jj) {
+      for (int w = 0; w < TW; ++w) {
+        if (w == (tp >> 2)) {
 #pragma unroll
-          for (int i = 0; i < NI; ++i) {
-            const int a = rc + 16 * i;
-            if (a < q) colb[a] = acc[i][j];
-          }
+          for (int u = 0; u < TU; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int a = 16 * (wr + 2 * u) + kr + 4 * v;
+              if (a < q) colb[a] = acc[u][w][v];
+            }
         }
       }
     }
     __syncthreads();
-    double x[NI], y[NJ];
+    const double* xcol = colb + 16 * wr + kr;
+    const double* ycol = colb + 16 * wc + lc;
+    double y[TW];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) x[i] = colb[min(rc + 16 * i, q - 1)] * inv;
+    for (int w = 0; w < TW; ++w) y[w] = ycol[64 * w] * inv;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) y[j] = colb[min(cc + 32 * j, q - 1)] * inv;
+    for (int u = 0; u < TU; ++u) {
+      double x[4];
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
+      for (int v = 0; v < 4; ++v) x[v] = xcol[32 * u + 4 * v] * inv;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) acc[i][j] = fma(-x[i], y[j], acc[i][j]);
+      for (int w = 0; w < TW; ++w)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][w][v] = fma(-x[v], y[w], acc[u][w][v]);
+      // one tile row at a time: keeps the live operands within the register
+      // budget of two workgroups per CU
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int t = 0; t < kCertDiag; ++t) {
-      const int a = lane + 64 * t;
-      if (a == piv) {
-        cb[t] = true;
-      } else if (!cb[t]) {
-        const double l = colb[a] * inv;
-        dgr[t] = fma(-l, l, dgr[t]);
-      }
+      const double l = colb[lane + 64 * t] * inv;
+      const bool done = cb[t] || lane + 64 * t == piv;
+      dgr[t] = done ? dgr[t] : fma(-l, l, dgr[t]);
+      cb[t] = done;
     }
     buf ^= 1;
   }
   return true;
 }
 
-// Size class (qlo, 16 NI]: NI x NJ Gram entries per thread.
-template <int NI, int NJ>
-__global__ __launch_bounds__(kCertThreads, NI * NJ <= 32 ? 2 : 1) void k_dense_cert(
+// Size class (qlo, 32 TU]: TU x TW tiles of 16 x 16 per wave.
+template <int TU, int TW>
+__global__ __launch_bounds__(kCertThreads, TU * TW <= 8 ? 4 : 2) void k_dense_cert(
     const RecItem* __restrict__ items, int nitems, double tol, int qlo, int* __restrict__ cert,
     unsigned long long* __restrict__ count) {
   __shared__ CertLds L;
@@ -283,8 +309,8 @@ __global__ __launch_bounds__(kCertThreads, NI * NJ <= 32 ? 2 : 1) void k_dense_c
   if (item >= nitems) return;
   const RecItem it = items[item];
   const int q = it.m < it.n ? it.m : it.n;
-  if (!(it.path == kPathDense && tol > 0.0 && q > qlo && q <= 16 * NI && it.D != nullptr)) return;
-  const bool ok = cert_block<NI, NJ>(it, tol, L);
+  if (!(it.path == kPathDense && tol > 0.0 && q > qlo && q <= 32 * TU && it.D != nullptr)) return;
+  const bool ok = cert_block<TU, TW>(it, tol, L);
   if (ok && threadIdx.x == 0) {
     cert[item] = 1;
     if (count) atomicAdd(count, 1ull);
@@ -295,17 +321,19 @@ __global__ __launch_bounds__(kCertThreads, NI * NJ <= 32 ? 2 : 1) void k_dense_c
 
 hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* cert,
                              unsigned long long* count, hipStream_t s) {
-  static_assert(16 * 10 == kCertEdge && 32 * 5 == kCertEdge, "largest size class covers kCertEdge");
+  static_assert(32 * 5 == kCertEdge, "largest size class covers kCertEdge");
   if (nitems <= 0) return hipSuccess;
   hipError_t e = launch_fill_i32(cert, 0, nitems, s);
   if (e != hipSuccess) return e;
   const int grid = ((nitems + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_dense_cert<6, 3>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
+  // T = ceil(q / 16) tiles per dimension: q <= 96 -> 2 x 4 waves of 3 x 2
+  // tiles, q <= 128 -> 4 x 2, q <= 160 -> 5 x 3
+  hipLaunchKernelGGL((k_dense_cert<3, 2>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
                      0, cert, count);
-  hipLaunchKernelGGL((k_dense_cert<8, 4>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
+  hipLaunchKernelGGL((k_dense_cert<4, 2>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
                      96, cert, count);
-  hipLaunchKernelGGL((k_dense_cert<10, 5>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems,
-                     tol, 128, cert, count);
+  hipLaunchKernelGGL((k_dense_cert<5, 3>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
+                     128, cert, count);
   return hipGetLastError();
 }
 
