@@ -30,13 +30,15 @@
 // result (a certified block is copied out exactly as a block the SVD finds
 // dense), it only skips work.
 //
-// One 512-thread workgroup per block.  The Gram matrix (q x q) is computed on
-// FP64 MFMA (v_mfma_f64_16x16x4) from 16-deep slabs of D staged in LDS, with
-// the next slab's loads in flight, and stays in the MFMA output registers:
-// the 8 waves form a 2 x 4 grid, wave (wr, wc) owns the 16 x 16 tiles
-// (wr + 2 u, wc + 4 w) for u < TU, w < TW (TU = ceil(T / 2), TW = ceil(T / 4),
-// T = ceil(q / 16), one kernel per size class of q).  The right-looking
-// pivoted Cholesky then updates those registers in place.  Every wave keeps its own copy of the residual
+// One workgroup per block.  The Gram matrix (q x q) is computed on FP64 MFMA
+// (v_mfma_f64_16x16x4) from 16-deep slabs of D staged in LDS, with the next
+// slab's loads in flight, and stays in the MFMA output registers: the waves
+// form a WR x WC grid, wave (wr, wc) owns the 16 x 16 tiles (wr + WR u,
+// wc + WC w) for u < TU, w < TW, T = ceil(q / 16) <= WR TU, WC TW.  One
+// kernel per size class of q: q <= 128 on 512 threads (2 x 4 waves of 4 x 2
+// tiles, two workgroups per CU), q <= 160 on 1024 threads (4 x 4 waves of
+// 3 x 3 tiles).  The right-looking pivoted Cholesky then updates those
+// registers in place.  Every wave keeps its own copy of the residual
 // diagonal in registers and updates it from the published pivot column with
 // the same arithmetic, so every wave picks the same pivot without a barrier;
 // with the pivot column double-buffered in LDS a step costs one barrier.
@@ -47,7 +49,6 @@ namespace {
 
 typedef const double __attribute__((address_space(1))) cgdbl;
 
-constexpr int kCertThreads = 512;
 constexpr int kCertSlab = 16;               // inner indices staged per slab
 constexpr int kCertLd = kCertEdge + 1;
 constexpr int kCertDiag = (kCertEdge + 63) / 64;   // residual diagonal entries per lane
@@ -125,9 +126,10 @@ __device__ __attribute__((always_inline)) inline void wave_argmax(double& v, int
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int TU, int TW>
+template <int WR, int WC, int TU, int TW>
 __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& it, double tol,
                                                                  CertLds& L) {
+  constexpr int NT = 64 * WR * WC;
   const int tid = threadIdx.x;
   const int m = it.m, n = it.n;
   const int q = m < n ? m : n, p = m < n ? n : m;
@@ -136,8 +138,9 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
   cgdbl* D = (cgdbl*)it.D;
   const int64_t ldd = it.ldd;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1;
-  static_assert(16 + 15 + 32 * (TU - 1) + 12 < kCertColLd && 48 + 15 + 64 * (TW - 1) < kCertColLd,
+  const int wr = wave % WR, wc = wave / WR;
+  static_assert(16 * (WR - 1) + 3 + 16 * WR * (TU - 1) + 12 < kCertColLd &&
+                    16 * (WC - 1) + 15 + 16 * WC * (TW - 1) < kCertColLd,
                 "pivot-column reads stay inside the zero-padded column");
   // MFMA f64 16x16x4 lanes: operand row/column lc, inner index kr; output
   // rows kr + 4 v (v < 4) of column lc
@@ -149,21 +152,21 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
   for (int u = 0; u < TU; ++u)
 #pragma unroll
     for (int w = 0; w < TW; ++w) acc[u][w] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int e = tid; e < kCertSlab * kCertLd; e += kCertThreads) {
+  for (int e = tid; e < kCertSlab * kCertLd; e += NT) {
     const int a = e % kCertLd;
     if (a >= q) L.slab[e / kCertLd][a] = 0.0;
   }
   // pivot-column entries beyond q stay zero: reads need no clamping, so their
   // addresses are one base register plus constant offsets
-  for (int e = tid; e < 2 * kCertColLd; e += kCertThreads)
+  for (int e = tid; e < 2 * kCertColLd; e += NT)
     if (e % kCertColLd >= q) L.col[e / kCertColLd][e % kCertColLd] = 0.0;
-  // staging slots of this thread (16 q <= 512 TU elements per slab):
+  // staging slots of this thread (16 q <= 16 * 16 WR TU elements per slab):
   // consecutive threads read consecutive addresses of D; slot = (kk << 8) | a
-  constexpr int PRE = TU;
+  constexpr int PRE = (kCertSlab * 16 * WR * TU + NT - 1) / NT;
   int slot[PRE];
 #pragma unroll
   for (int u = 0; u < PRE; ++u) {
-    const int e = tid + kCertThreads * u;
+    const int e = tid + NT * u;
     const int kk = trans ? e / q : e % kCertSlab;
     const int a = trans ? e % q : e / kCertSlab;
     slot[u] = e < kCertSlab * q ? (kk << 8) | a : -1;
@@ -189,14 +192,16 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
     for (int s4 = 0; s4 < kCertSlab / 4; ++s4) {
       double av[TU], bv[TW];
 #pragma unroll
-      for (int u = 0; u < TU; ++u) av[u] = L.slab[4 * s4 + kr][min(16 * (wr + 2 * u) + lc, kCertEdge - 1)];
+      for (int u = 0; u < TU; ++u)
+        av[u] = L.slab[4 * s4 + kr][min(16 * (wr + WR * u) + lc, kCertEdge - 1)];
 #pragma unroll
-      for (int w = 0; w < TW; ++w) bv[w] = L.slab[4 * s4 + kr][min(16 * (wc + 4 * w) + lc, kCertEdge - 1)];
+      for (int w = 0; w < TW; ++w)
+        bv[w] = L.slab[4 * s4 + kr][min(16 * (wc + WC * w) + lc, kCertEdge - 1)];
 #pragma unroll
       for (int u = 0; u < TU; ++u)
 #pragma unroll
         for (int w = 0; w < TW; ++w)
-          if (wr + 2 * u < T && wc + 4 * w < T)   // wave-uniform
+          if (wr + WR * u < T && wc + WC * w < T)   // wave-uniform
             acc[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[w], acc[u][w], 0, 0, 0);
     }
   }
@@ -208,7 +213,7 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
     for (int w = 0; w < TW; ++w)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int a = 16 * (wr + 2 * u) + kr + 4 * v, b = 16 * (wc + 4 * w) + lc;
+        const int a = 16 * (wr + WR * u) + kr + 4 * v, b = 16 * (wc + WC * w) + lc;
         if (a == b && a < q) L.dg[a] = acc[u][w][v];
       }
   __syncthreads();
@@ -251,17 +256,17 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
     const double inv = 1.0 / sqrt(bv);
     double* colb = L.col[buf];
     const int tp = piv >> 4;   // tile column of the pivot
-    if (wc == (tp & 3) && lc == (piv & 15)) {
+    if (wc == tp % WC && lc == (piv & 15)) {
       // one branch per register tile column (uniform in the wave), so acc is
       // only ever indexed by constants and stays in registers
 #pragma unroll
       for (int w = 0; w < TW; ++w) {
-        if (w == (tp >> 2)) {
+        if (w == tp / WC) {
 #pragma unroll
           for (int u = 0; u < TU; ++u)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int a = 16 * (wr + 2 * u) + kr + 4 * v;
+              const int a = 16 * (wr + WR * u) + kr + 4 * v;
               if (a < q) colb[a] = acc[u][w][v];
             }
         }
@@ -272,12 +277,12 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
     const double* ycol = colb + 16 * wc + lc;
     double y[TW];
 #pragma unroll
-    for (int w = 0; w < TW; ++w) y[w] = ycol[64 * w] * inv;
+    for (int w = 0; w < TW; ++w) y[w] = ycol[16 * WC * w] * inv;
 #pragma unroll
     for (int u = 0; u < TU; ++u) {
       double x[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) x[v] = xcol[32 * u + 4 * v] * inv;
+      for (int v = 0; v < 4; ++v) x[v] = xcol[16 * WR * u + 4 * v] * inv;
 #pragma unroll
       for (int w = 0; w < TW; ++w)
 #pragma unroll
@@ -298,9 +303,10 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
   return true;
 }
 
-// Size class (qlo, 32 TU]: TU x TW tiles of 16 x 16 per wave.
-template <int TU, int TW>
-__global__ __launch_bounds__(kCertThreads, TU * TW <= 8 ? 4 : 2) void k_dense_cert(
+// Size class (qlo, 16 WR TU]: WR x WC waves of TU x TW tiles of 16 x 16;
+// four waves per SIMD (two 512-thread or one 1024-thread workgroup per CU).
+template <int WR, int WC, int TU, int TW>
+__global__ __launch_bounds__(64 * WR * WC, 4) void k_dense_cert(
     const RecItem* __restrict__ items, int nitems, double tol, int qlo, int* __restrict__ cert,
     unsigned long long* __restrict__ count) {
   __shared__ CertLds L;
@@ -309,8 +315,9 @@ __global__ __launch_bounds__(kCertThreads, TU * TW <= 8 ? 4 : 2) void k_dense_ce
   if (item >= nitems) return;
   const RecItem it = items[item];
   const int q = it.m < it.n ? it.m : it.n;
-  if (!(it.path == kPathDense && tol > 0.0 && q > qlo && q <= 32 * TU && it.D != nullptr)) return;
-  const bool ok = cert_block<TU, TW>(it, tol, L);
+  if (!(it.path == kPathDense && tol > 0.0 && q > qlo && q <= 16 * WR * TU && it.D != nullptr))
+    return;
+  const bool ok = cert_block<WR, WC, TU, TW>(it, tol, L);
   if (ok && threadIdx.x == 0) {
     cert[item] = 1;
     if (count) atomicAdd(count, 1ull);
@@ -321,19 +328,15 @@ __global__ __launch_bounds__(kCertThreads, TU * TW <= 8 ? 4 : 2) void k_dense_ce
 
 hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* cert,
                              unsigned long long* count, hipStream_t s) {
-  static_assert(32 * 5 == kCertEdge, "largest size class covers kCertEdge");
+  static_assert(16 * 4 * 3 >= kCertEdge, "the largest size class covers kCertEdge");
   if (nitems <= 0) return hipSuccess;
   hipError_t e = launch_fill_i32(cert, 0, nitems, s);
   if (e != hipSuccess) return e;
   const int grid = ((nitems + 7) / 8) * 8;
-  // T = ceil(q / 16) tiles per dimension: q <= 96 -> 2 x 4 waves of 3 x 2
-  // tiles, q <= 128 -> 4 x 2, q <= 160 -> 5 x 3
-  hipLaunchKernelGGL((k_dense_cert<3, 2>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
+  hipLaunchKernelGGL((k_dense_cert<2, 4, 4, 2>), dim3(grid), dim3(512), 0, s, items, nitems, tol,
                      0, cert, count);
-  hipLaunchKernelGGL((k_dense_cert<4, 2>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
-                     96, cert, count);
-  hipLaunchKernelGGL((k_dense_cert<5, 3>), dim3(grid), dim3(kCertThreads), 0, s, items, nitems, tol,
-                     128, cert, count);
+  hipLaunchKernelGGL((k_dense_cert<4, 4, 3, 3>), dim3(grid), dim3(1024), 0, s, items, nitems,
+                     tol, 128, cert, count);
   return hipGetLastError();
 }
 
