@@ -234,6 +234,26 @@ def test_gemm_3d_scaled(ctx, torch):
         f"err={rep.rel_err:.2e} ambiguous={len(rep.ambiguous)}")
 
 
+@pytest.mark.parametrize("kind,n", [("morton", 2048), ("coulomb", 1536)])
+def test_gemm_low_rank_regime(ctx, torch, kind, n):
+    """Rank-sparse inputs: Morton-ordered compact clusters of the 3D Gaussian workload and a
+    Coulomb-like 1/sqrt(r^2 + 1) kernel; most result blocks take the low-rank recompression path."""
+    log(f"gemm low-rank regime: {kind} N={n}")
+    wl = scaled_workload(kind, n, seed=150)
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    C, st = ctx.gemm(S, S, wl.tol, wl.eps_sp, stats=True)
+    Oc = orc.gemm(O, O, wl.tol, wl.eps_sp)
+    E = orc.gemm(O, O, 0.0, wl.eps_sp)
+    rep = parity.compare(C, Oc, wl.tol, exact=E)
+    nb = len(wl.sizes) ** 2
+    log(f"  blocks={nb} computed={st.computed} dense={st.out_dense} lr={st.out_lowrank} "
+        f"err={rep.rel_err:.2e} ambiguous={len(rep.ambiguous)}")
+    assert st.out_lowrank > st.out_dense
+    parity.assert_parity(rep, FP64_BOUND, nblocks=nb)
+
+
 def _bitwise_same(A, B):
     ka, ra, na = A.meta()
     kb, rb, nb = B.meta()

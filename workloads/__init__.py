@@ -21,6 +21,10 @@ Recipe (all draws from ``numpy.random.Generator(PCG64(seed))``):
   Clusters are contiguous runs of idx ("lattice order", k fastest).
 * Jitter is drawn first, shape (N, d); cluster sizes afterwards.
 * Kernel: S_ij = exp(-a * |x_i - x_j|**2) + d * delta_ij.
+* Low-rank regime: the same lattice sites visited in Morton (Z-curve) order of
+  their integer coordinates, so that contiguous clusters are compact boxes
+  instead of lattice slabs; and a slowly decaying Coulomb-like kernel
+  S_ij = 1 / sqrt(|x_i - x_j|**2 + delta**2) + d * delta_ij on those sites.
 """
 from __future__ import annotations
 
@@ -40,6 +44,10 @@ __all__ = [
     "sizes_weighted",
     "kernel_matrix",
     "kernel_block",
+    "coulomb_block",
+    "coulomb_matrix",
+    "morton_order",
+    "points_3d_morton",
     "line_n512",
     "lattice_3d",
     "batch_product",
@@ -47,6 +55,8 @@ __all__ = [
     "lattice_3d_wide",
     "adjoint_n4096",
     "scaled_workload",
+    "lattice_3d_morton",
+    "coulomb_3d_morton",
     "random_blocks",
     "RandomCLR",
 ]
@@ -63,7 +73,7 @@ class Workload:
     name: str
     points: np.ndarray          # (N, d) float64
     sizes: List[int]            # cluster sizes, sum == N
-    a: float                    # Gaussian exponent
+    a: float                    # Gaussian exponent (Coulomb-like kernel: the softening length)
     diag: float                 # diagonal shift d
     tol: float                  # relative truncation tolerance
     eps_sp: float               # screening threshold
@@ -74,6 +84,8 @@ class Workload:
         return int(self.points.shape[0])
 
     def dense(self) -> np.ndarray:
+        if self.extra.get("kernel") == "coulomb":
+            return coulomb_matrix(self.points, self.a, self.diag)
         return kernel_matrix(self.points, self.a, self.diag)
 
     def offsets(self) -> np.ndarray:
@@ -100,6 +112,24 @@ def points_3d(rng: np.random.Generator, n: int, spacing: float, jit: float) -> n
     idx = np.arange(n, dtype=np.int64)
     site = np.stack([idx // (ns * ns), (idx // ns) % ns, idx % ns], axis=1).astype(np.float64)
     return site * spacing + jitter
+
+
+def morton_order(n: int) -> np.ndarray:
+    """Lattice indices 0..n-1 (site (idx // ns**2, (idx // ns) % ns, idx % ns)) sorted by the
+    Morton code of their integer coordinates: bit b of i, j, k goes to bit 3b + 2, 3b + 1, 3b."""
+    ns = lattice_side(n)
+    idx = np.arange(n, dtype=np.int64)
+    ijk = [idx // (ns * ns), (idx // ns) % ns, idx % ns]
+    code = np.zeros(n, dtype=np.int64)
+    for b in range(int(ns).bit_length()):
+        for shift, c in ((2, ijk[0]), (1, ijk[1]), (0, ijk[2])):
+            code |= ((c >> b) & 1) << (3 * b + shift)
+    return np.argsort(code, kind="stable")
+
+
+def points_3d_morton(rng: np.random.Generator, n: int, spacing: float, jit: float) -> np.ndarray:
+    """points_3d (same draws), visited in Morton order of their lattice sites."""
+    return points_3d(rng, n, spacing, jit)[morton_order(n)]
 
 
 def sizes_until(rng: np.random.Generator, n: int, lo: int, hi: int) -> List[int]:
@@ -139,6 +169,26 @@ def kernel_block(xi: np.ndarray, xj: np.ndarray, a: float) -> np.ndarray:
         diff = xi[:, c][:, None] - xj[:, c][None, :]
         d2 += diff * diff
     return np.exp(-a * d2)
+
+
+def coulomb_block(xi: np.ndarray, xj: np.ndarray, delta: float) -> np.ndarray:
+    """1 / sqrt(|x_i - x_j|^2 + delta^2) for two point sets (no diagonal shift)."""
+    d2 = np.full((xi.shape[0], xj.shape[0]), delta * delta, dtype=np.float64)
+    for c in range(xi.shape[1]):
+        diff = xi[:, c][:, None] - xj[:, c][None, :]
+        d2 += diff * diff
+    return 1.0 / np.sqrt(d2)
+
+
+def coulomb_matrix(points: np.ndarray, delta: float, diag: float, chunk: int = 4096) -> np.ndarray:
+    """Dense S_ij = 1 / sqrt(|x_i - x_j|^2 + delta^2) + diag * delta_ij, built in row chunks."""
+    n = points.shape[0]
+    s = np.empty((n, n), dtype=np.float64)
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        s[r0:r1] = coulomb_block(points[r0:r1], points, delta)
+    s[np.arange(n), np.arange(n)] += diag
+    return s
 
 
 def kernel_matrix(points: np.ndarray, a: float, diag: float, chunk: int = 4096) -> np.ndarray:
@@ -211,6 +261,25 @@ def adjoint_n4096(seed: int = 5000) -> Workload:
                     extra={"weights": w, "iters": 20, "checkpoint_every": 5})
 
 
+def lattice_3d_morton(n: int = 8192, seed: int = 2000) -> Workload:
+    """lattice_3d's points and physics in Morton order: compact clusters U{96..160}, far more
+    low-rank blocks (the paper's rank-sparse regime)."""
+    rng = rng_for(seed)
+    pts = points_3d_morton(rng, n, 1.5, 0.3)
+    sizes = sizes_until(rng, n, 96, 160)
+    return Workload(f"morton3d-n{n}", pts, sizes, a=0.3, diag=0.1, tol=1e-6, eps_sp=1e-10)
+
+
+def coulomb_3d_morton(n: int = 8192, seed: int = 6000) -> Workload:
+    """Coulomb-like 1 / sqrt(r^2 + 1) + 0.1 delta on a Morton-ordered jittered lattice (spacing 1.0,
+    jitter 0.3), clusters U{96..160}, tol 1e-6: no block is negligible, ranks decay slowly."""
+    rng = rng_for(seed)
+    pts = points_3d_morton(rng, n, 1.0, 0.3)
+    sizes = sizes_until(rng, n, 96, 160)
+    return Workload(f"coulomb3d-n{n}", pts, sizes, a=1.0, diag=0.1, tol=1e-6, eps_sp=1e-10,
+                    extra={"kernel": "coulomb"})
+
+
 def scaled_workload(kind: str, n: int, nclusters: Optional[int] = None, seed: int = 7000,
                     tol: Optional[float] = None) -> Workload:
     """Smaller copies of the 3D workloads (same physics) for parity tests the oracle finishes fast."""
@@ -225,6 +294,15 @@ def scaled_workload(kind: str, n: int, nclusters: Optional[int] = None, seed: in
         sizes = sizes_weighted(rng, n, nc)
         return Workload(f"wide3d-small-n{n}", pts, sizes, 0.2, 0.05, 1e-8 if tol is None else tol, 1e-10,
                         extra={"conv_tol": 1e-8})
+    if kind == "morton":
+        pts = points_3d_morton(rng, n, 1.5, 0.3)
+        sizes = sizes_until(rng, n, 96, 160) if nclusters is None else sizes_weighted(rng, n, nclusters)
+        return Workload(f"morton3d-small-n{n}", pts, sizes, 0.3, 0.1, 1e-6 if tol is None else tol, 1e-10)
+    if kind == "coulomb":
+        pts = points_3d_morton(rng, n, 1.0, 0.3)
+        sizes = sizes_until(rng, n, 96, 160) if nclusters is None else sizes_weighted(rng, n, nclusters)
+        return Workload(f"coulomb3d-small-n{n}", pts, sizes, 1.0, 0.1, 1e-6 if tol is None else tol, 1e-10,
+                        extra={"kernel": "coulomb"})
     raise ValueError(kind)
 
 
