@@ -197,6 +197,34 @@ def run_sqrtinv(ctx, n, forms, log_fn):
             "forms": out}
 
 
+def run_low_rank(ctx, forms, steps, warmup, log_fn):
+    """The rank-sparse regime: C = S*S at N = 8192 on Morton-ordered compact clusters of the
+    3D Gaussian lattice and on a Coulomb-like 1/sqrt(r^2 + 1) kernel (tol 1e-6)."""
+    import torch
+    from workloads import coulomb_3d_morton, lattice_3d_morton
+    out = {}
+    for wl, desc in ((lattice_3d_morton(8192), "3D lattice exp(-0.3 r^2)+0.1 delta, Morton-ordered "
+                      "compact clusters U{96..160}, tol 1e-6, screen 1e-10"),
+                     (coulomb_3d_morton(8192), "3D lattice (spacing 1.0) 1/sqrt(r^2+1)+0.1 delta, "
+                      "Morton-ordered clusters U{96..160}, tol 1e-6, screen 1e-10")):
+        Sd = torch.from_numpy(wl.dense()).cuda()
+        S = ctx.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+        del Sd
+        res = {"workload": f"C=S*S, N={wl.n}, " + desc, "forms": {}}
+        for form in forms:
+            _C, wall, stats = run_form(ctx, S, wl, form, steps, warmup)
+            del _C
+            sm = summarize(stats, wall, form)
+            res["forms"][form] = {k: sm[k] for k in ("tflops", "ms_per_step", "phase_ms",
+                                                     "rec_engine_ms", "computed_blocks",
+                                                     "out_dense", "out_lowrank", "certified_dense")}
+            log_fn(f"  {wl.name} {form}: {sm['tflops']:.2f} TFLOP/s, {sm['ms_per_step']:.2f} ms/step, "
+                   f"phases {sm['phase_ms']}")
+        out[wl.name] = res
+        del S
+    return out
+
+
 def run_batched(ctx, nprod, log_fn):
     """Batch of mixed-size products: nprod independent products S_p * S_p (N_p ~ U{512..4096}, 16..48
     uneven clusters, tol 1e-8) planned once and executed as one graph replay per form;
@@ -340,6 +368,7 @@ def main():
     ap.add_argument("--no-sqrtinv", action="store_true")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-lowrank", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -412,6 +441,10 @@ def main():
     # is the one with the larger device time in this run.
     rec_achieved = (fb["rec_engine_flops"] / (fb["rec_engine_ms"] * 1e-3) / 1e12
                     if fb["rec_engine_ms"] > 0 else None)
+    low_rank = None
+    if not args.no_lowrank:
+        log("low-rank regime products")
+        low_rank = run_low_rank(ctx, [f for f in args.forms.split(",")], args.steps, args.warmup, log)
     batched = None
     if not args.no_batch:
         log(f"batched products: {args.batch_count}")
@@ -463,6 +496,7 @@ def main():
         "forms": forms,
         "error_vs_oracle_sampled": sample_err,
         "sqrt_inv": sqrtinv,
+        "low_rank_regime": low_rank,
         "batched": batched,
         "roofline": roof_gemm if fb["phase_ms"]["dense_products"] >= fb["rec_engine_ms"] else roof,
         "roofline_recompress": roof,
