@@ -879,17 +879,20 @@ CLR_INLINE void reg_bidiag(RegTile& a, int p_in, int q_in, RegLds& L) {
 // T - x I through its leading principal minors d_k = -x d_{k-1} - b_{k-1}^2 d_{k-2}
 // (no divisions): every sign change is a negative pivot, i.e. an eigenvalue
 // below x.  The pair (d_{k-1}, d_k) is rescaled by a power of two every 8 steps
-// (growth per step is at most the golden ratio for a unit-norm matrix); an exact
-// zero minor is replaced by a tiny value of the opposite sign, which counts it
-// as a negative pivot as the pivot-floor rule of the quotient form does.
+// (growth per step is at most the golden ratio for a unit-norm matrix).  An
+// exact zero minor needs no special case: it counts as non-negative, and since
+// every b2 is positive (floored at 2^-600 where the off-diagonal vanishes) the
+// next minor is -b2 d_{k-1}, of the opposite sign to d_{k-1}, so the two steps
+// together add one sign change, as the pivot-floor rule of the quotient form
+// does (a zero minor cannot be followed by another).  Only a zero last minor
+// (x exactly an eigenvalue) may count either way.
 CLR_INLINE int sturm_greater(const double* b2, int q, double x) {
   double dm = 1.0, d = -x;
   int neg = 1;
   if (d == 0.0) d = -1e-300;
   const int n = 2 * q - 1;
   auto step = [&](double bb) {
-    double dn = fma(-x, d, -bb * dm);
-    if (dn == 0.0) dn = -d * 0x1p-80;
+    const double dn = fma(-x, d, -bb * dm);
     neg += (dn < 0.0) != (d < 0.0);
     dm = d;
     d = dn;
@@ -1025,7 +1028,7 @@ CLR_INLINE int reg_decide(int q, double tol, RegLds& L, RecShared& sh) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   if (tid < 2 * q - 1) {
     const double b = (tid & 1) ? L.e[tid >> 1] : L.d[tid >> 1];
-    S.b2[tid] = b * b;
+    S.b2[tid] = fmax(b * b, 0x1p-600);   // positive: see sturm_greater
   }
   __syncthreads();
   S.cnt[tid] = sturm_greater(S.b2, q, probe_point(tid));
