@@ -980,19 +980,21 @@ CLR_INLINE void multisect_round(int q, int nact, RegLds& L) {
   const int tid = threadIdx.x;
   const int ts = kRecThreads / nact;
   const int a = tid / ts, sub = tid % ts;
+  // probe points lo + (s + 1) w, w = (hi - lo) / (ts + 1), computed the same
+  // way by the probing threads and by the bracket update
   if (a < nact) {
     const int i = S.act[a];
-    const double lo = S.lo[i], hi = S.hi[i];
-    const double x = lo + (double)(sub + 1) * (hi - lo) / (double)(ts + 1);
+    const double lo = S.lo[i], w = (S.hi[i] - lo) / (double)(ts + 1);
+    const double x = lo + (double)(sub + 1) * w;
     S.cnt[tid] = sturm_greater(S.b2, q, x);
   }
   __syncthreads();
   if (a < nact && sub == 0) {
     const int i = S.act[a];
-    const double lo = S.lo[i], hi = S.hi[i];
+    const double lo = S.lo[i], hi = S.hi[i], w = (hi - lo) / (double)(ts + 1);
     double nlo = lo, nhi = hi;
     for (int s2 = 0; s2 < ts; ++s2) {
-      const double x = lo + (double)(s2 + 1) * (hi - lo) / (double)(ts + 1);
+      const double x = lo + (double)(s2 + 1) * w;
       if (S.cnt[a * ts + s2] > i) {
         nlo = x;
       } else {
