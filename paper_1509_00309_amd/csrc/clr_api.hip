@@ -581,6 +581,7 @@ extern "C" clr_status clr_compress(clr_context* ctx, const double* dense, int64_
     for (int J = 0; J < ncb; ++J) {
       RecItem r{};
       r.path = (square && I == J) ? kPathForceDense : kPathDense;
+      r.cert_hint = 1;
       r.m = rs[I];
       r.n = cs[J];
       r.R = 0;
@@ -1332,6 +1333,7 @@ extern "C" clr_status clr_axpby(clr_context* ctx, double a, const clr_matrix* X,
       const double* ys = Y ? Y->arena + so : nullptr;
       if (densify) {
         r.path = diag ? kPathForceDense : kPathDense;
+        r.cert_hint = 1;
         r.D = acc + so;
         r.ldd = m;
         AxpbyDenseItem d{};

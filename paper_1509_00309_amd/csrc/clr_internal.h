@@ -68,6 +68,7 @@ struct RecItem {
   int path;
   int m, n;
   int piece0, npieces, R;     // low-rank path: concatenated factors
+  int cert_hint;              // dense path: 1 to try the dense certificate first
   const double* D;            // dense path: accumulated block
   int64_t ldd;
   double tau;                 // drop threshold

@@ -315,7 +315,8 @@ __global__ __launch_bounds__(64 * WR * WC, 4) void k_dense_cert(
   if (item >= nitems) return;
   const RecItem it = items[item];
   const int q = it.m < it.n ? it.m : it.n;
-  if (!(it.path == kPathDense && tol > 0.0 && q > qlo && q <= 16 * WR * TU && it.D != nullptr))
+  if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > qlo && q <= 16 * WR * TU &&
+        it.D != nullptr))
     return;
   const bool ok = cert_block<WR, WC, TU, TW>(it, tol, L);
   if (ok && threadIdx.x == 0) {

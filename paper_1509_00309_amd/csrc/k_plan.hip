@@ -239,6 +239,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   double* accb = F.acc + cslot;
   int kb = 0;
   int rcat = 0;
+  bool anydd = false;
   for (int K = 0; K < P.nkb; ++K) {
     const int ka = P.A.kind[I * P.nkb + K];
     if (ka == 0) continue;
@@ -252,6 +253,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
     pc.pad = 0;
     pc.scale = P.alpha;
     if (ka == 1 && kbk == 1) {
+      anydd = true;
       dense_term = make_seg(a, 1, m, b, 1, k, k, 1.0);
     } else if (ka == 2 && kbk == 1) {
       // LD: U_A (B^T V_A)^T; T = B^T V_A is n x rA
@@ -344,6 +346,9 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   r.piece0 = (int)pi0;
   r.npieces = (int)(pi - pi0);
   r.R = rcat;
+  // blocks with a dense x dense term are the ones that tend to stay dense;
+  // blocks densified only by the number of low-rank terms mostly end low-rank
+  r.cert_hint = anydd ? 1 : 0;
   r.D = accb;
   r.ldd = m;
   r.tau = tau;
