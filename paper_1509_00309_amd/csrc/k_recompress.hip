@@ -1286,25 +1286,19 @@ CLR_INLINE bool reg_vectors(const RecItem& it, int p, int q, bool trans, int r, 
       const double tau = L.tauR[k];
       if (tau == 0.0) continue;
       const double* vs = L.vstore + vs_off(k, q);
-      // unconditional loads from a clamped index inside the reflector, then
-      // a select: the loads issue together instead of one masked load each
       double w[kRR];
 #pragma unroll
       for (int t = 0; t < kRR; ++t) {
         const int j = gl + 16 * t;
-        const double x = vs[min(max(j - k - 1, 0), q - k - 2)];
-        w[t] = (j > k && j < q) ? x : 0.0;
+        w[t] = (j > k && j < q) ? vs[j - k - 1] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < kVecPerGroup; ++u) {
         if (g + kGroups * u < r) {
-          double d0 = 0.0, d1 = 0.0;
+          double dot = 0.0;
 #pragma unroll
-          for (int t = 0; t < kRR; t += 2) {
-            d0 += w[t] * vv[u][t];
-            if (t + 1 < kRR) d1 += w[t + 1] * vv[u][t + 1];
-          }
-          const double dot = tau * group_sum16(d0 + d1);
+          for (int t = 0; t < kRR; ++t) dot += w[t] * vv[u][t];
+          dot = tau * group_sum16(dot);
 #pragma unroll
           for (int t = 0; t < kRR; ++t) vv[u][t] -= w[t] * dot;
         }
