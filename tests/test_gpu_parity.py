@@ -528,11 +528,14 @@ def test_tile_edges_and_autotune(ctx, torch):
 # edge, and the adjoint against finite differences and the eigen-gradient
 # ---------------------------------------------------------------------------
 
-def test_gemm_full_size_sampled(ctx, torch):
-    """N = 8192 3D workload exactly as bench.py times it; 32 result blocks recomputed
-    one by one by the oracle (kinds, ranks and values)."""
-    log("gemm full size N=8192, sampled blocks")
-    wl = lattice_3d(8192)
+@pytest.mark.parametrize("name", ["lattice_3d", "lattice_3d_morton", "coulomb_3d_morton"])
+def test_gemm_full_size_sampled(ctx, torch, name):
+    """The N = 8192 workloads exactly as bench.py times them (the 3D lattice product and the two
+    low-rank-regime products); 32 result blocks recomputed one by one by the oracle (kinds, ranks
+    and values)."""
+    import workloads
+    log(f"gemm full size N=8192 ({name}), sampled blocks")
+    wl = getattr(workloads, name)(8192)
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     C = ctx.gemm(S, S, wl.tol, wl.eps_sp)
