@@ -43,6 +43,10 @@ path and listed in the design notes):
   block whose accumulated value is exactly zero is a zero block.
 * Factor convention: X (here U) carries the orthonormal basis, W (here V)
   carries the singular values, as X = Q_r in the paper.
+* Construction by rank-revealing QR (``compress_rrqr``, the paper's own
+  factorisation of an input block): column pivoting of the block M itself,
+  M P = Q R, with the same relative per-block truncation: the smallest r with
+  ||M - Q_r R_r P^T||_F = ||R[r:, :]||_F <= tol * ||M||_F.
 * Ties in the low-rank x low-rank absorb rule go to the W side (V_B Z^T).
 * alpha defaults to 1 / max_I sum_J ||S_IJ||_F (a block-Gershgorin bound on
   the largest eigenvalue, so ||alpha S - I||_2 <= 1 for symmetric positive S).
@@ -60,6 +64,8 @@ __all__ = [
     "OMatrix",
     "from_factors",
     "compress",
+    "compress_rrqr",
+    "rrqr_truncate",
     "to_dense",
     "truncation_rank",
     "combine",
@@ -268,6 +274,57 @@ def compress(S: np.ndarray, row_sizes: Sequence[int], col_sizes: Sequence[int], 
             b = combine(D.shape[0], D.shape[1], [("D", D)], tol, drop, square and i == j)
             if b is not None:
                 blocks[(i, j)] = b
+    return OMatrix(list(row_sizes), list(col_sizes), blocks)
+
+
+def rrqr_truncate(M: np.ndarray, tol: float) -> Tuple[int, np.ndarray, np.ndarray, np.ndarray]:
+    """Rank-revealing QR of one block (Sec. 4.1): M P = Q R by Householder QR with column
+    pivoting (LAPACK's greedy rule: the remaining column of largest norm goes next), then the
+    smallest r whose dropped part ||R[r:, :]||_F is <= tol * ||M||_F.
+
+    Returns (r, X, W, tails) with M ~ X W^T, X = Q[:, :r] (orthonormal), W^T = R[:r] P^T, and
+    tails[k] = ||R[k:, :]||_F for k = 0 .. min(m, n).
+    """
+    import scipy.linalg as sl
+    Q, R, piv = sl.qr(M, mode="economic", pivoting=True)
+    k = R.shape[0]
+    tails = np.zeros(k + 1, dtype=np.float64)
+    acc = 0.0
+    for i in range(k - 1, -1, -1):
+        acc += float(np.sum(R[i, i:] ** 2))
+        tails[i] = math.sqrt(acc)
+    bound = tol * frob(M)
+    r = next(i for i in range(k + 1) if tails[i] <= bound)
+    Wt = np.zeros((r, M.shape[1]), dtype=np.float64)
+    Wt[:, piv] = R[:r, :]
+    return r, Q[:, :r].copy(), Wt.T.copy(), tails
+
+
+def compress_rrqr(S: np.ndarray, row_sizes: Sequence[int], col_sizes: Sequence[int], tol: float,
+                  drop: float) -> OMatrix:
+    """CLR form of a dense matrix built with the paper's rank-revealing QR (Sec. 4.1): blocks
+    with norm < drop are dropped, diagonal blocks of a square blocking stay dense, the others
+    are truncated by ``rrqr_truncate`` and stored dense iff 2 r > min(m, n)."""
+    ro = np.concatenate([[0], np.cumsum(row_sizes)]).astype(int)
+    co = np.concatenate([[0], np.cumsum(col_sizes)]).astype(int)
+    square = list(row_sizes) == list(col_sizes)
+    blocks = {}
+    for i in range(len(row_sizes)):
+        for j in range(len(col_sizes)):
+            D = np.array(S[ro[i]:ro[i + 1], co[j]:co[j + 1]], dtype=np.float64)
+            normc = frob(D)
+            if normc < drop or normc == 0.0:
+                continue
+            if (square and i == j) or tol == 0.0:
+                blocks[(i, j)] = Block("D", D=D, norm=normc)
+                continue
+            r, X, W, _tails = rrqr_truncate(D, tol)
+            if r == 0:
+                continue
+            if 2 * r > min(D.shape):
+                blocks[(i, j)] = Block("D", D=D, norm=normc)
+            else:
+                blocks[(i, j)] = Block("L", U=X, V=W, norm=frob(X @ W.T))
     return OMatrix(list(row_sizes), list(col_sizes), blocks)
 
 

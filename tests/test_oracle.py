@@ -278,3 +278,68 @@ def test_unmutated_oracle_passes_fast_pins():
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_planted_mistake_is_caught(name):
     assert not _pins_pass(_mutant(MUTANTS[name]))
+
+
+# ---------------------------------------------------------------------------
+# Construction by rank-revealing QR (Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def test_rrqr_diagonal_example():
+    # M = diag(1, 3, 2): greedy pivots take columns 1, 2, 0; R's rows have norms 3, 2, 1, so
+    # the dropped parts are sqrt(14), sqrt(5), 1, 0 and tol ||M|| = 1.5 keeps rank 2: diag(0, 3, 2)
+    M = np.diag([1.0, 3.0, 2.0])
+    r, X, W, tails = orc.rrqr_truncate(M, 1.5 / math.sqrt(14.0))
+    assert np.allclose(tails, [math.sqrt(14.0), math.sqrt(5.0), 1.0, 0.0], rtol=1e-15, atol=1e-15)
+    assert r == 2
+    assert np.allclose(X @ W.T, np.diag([0.0, 3.0, 2.0]), rtol=0, atol=1e-15)
+
+
+def test_rrqr_exact_rank_error_identity_and_minimality():
+    rng = rng_for(31)
+    for (m, n, k) in ((40, 30, 7), (25, 60, 11), (50, 50, 1)):
+        M = rng.standard_normal((m, k)) @ rng.standard_normal((k, n))
+        r, X, W, tails = orc.rrqr_truncate(M, 1e-12)
+        assert r == k
+        assert np.allclose(X.T @ X, np.eye(r), atol=1e-13)
+        # a smooth block: the kept error is exactly the dropped part of R, and r is minimal
+        P = rng.standard_normal((m, 3))
+        K = np.exp(-0.5 * (P[:, :1] - rng.standard_normal((1, n))) ** 2)
+        for tol in (1e-3, 1e-6, 1e-9):
+            r, X, W, tails = orc.rrqr_truncate(K, tol)
+            nk = np.linalg.norm(K)
+            err = np.linalg.norm(K - X @ W.T)
+            assert abs(err - tails[r]) <= 1e-12 * nk
+            assert tails[r] <= tol * nk and (r == 0 or tails[r - 1] > tol * nk)
+
+
+def test_rrqr_rank_at_least_svd_rank():
+    # Eckart-Young: no rank-r approximation beats the truncated SVD, so RRQR keeps at least as
+    # many columns as the SVD for the same tolerance
+    wl = line_n512()
+    Sd = wl.dense()
+    offs = wl.offsets()
+    for (i, j) in ((0, 1), (2, 5), (3, 4), (1, 6)):
+        D = Sd[offs[i]:offs[i + 1], offs[j]:offs[j + 1]]
+        for tol in (1e-4, 1e-8, 1e-12):
+            r, _X, _W, _t = orc.rrqr_truncate(D, tol)
+            s = np.linalg.svd(D, compute_uv=False)
+            assert r >= orc.truncation_rank(s, tol, float(np.linalg.norm(D)))
+
+
+def test_compress_rrqr_rules_line_n512():
+    wl = line_n512()
+    Sd = wl.dense()
+    O = orc.compress_rrqr(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    offs = wl.offsets()
+    kinds = O.kinds()
+    for i in range(len(wl.sizes)):
+        assert kinds[i, i] == 1
+        for j in range(len(wl.sizes)):
+            D = Sd[offs[i]:offs[i + 1], offs[j]:offs[j + 1]]
+            b = O.blocks.get((i, j))
+            if b is None:
+                assert np.linalg.norm(D) < 1e-10
+                continue
+            assert np.linalg.norm(D - b.dense()) <= wl.tol * np.linalg.norm(D) * (1 + 1e-12)
+            if b.kind == "L":
+                assert 2 * b.rank <= min(D.shape)
