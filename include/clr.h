@@ -56,6 +56,10 @@ typedef enum {
 
 typedef enum { CLR_FP64 = 0, CLR_MIXED = 1 } clr_precision;
 
+/* Truncating factorisation of clr_compress (Sec. 4.1): the truncated SVD
+ * (default) or the paper's rank-revealing QR with column pivoting.          */
+typedef enum { CLR_COMPRESS_SVD = 0, CLR_COMPRESS_RRQR = 1 } clr_compression;
+
 /* Screening threshold tau of a result block (I, J) of size m x n (Sec. 4.1,
  * last paragraph): ABS uses tau = eps_sp, AREA uses tau = eps_sp * m * n.    */
 typedef enum { CLR_SCREEN_ABS = 0, CLR_SCREEN_AREA = 1 } clr_screen_mode;
@@ -142,7 +146,11 @@ clr_status clr_create(clr_context* ctx, int nrb, const int* row_sizes, int ncb,
 /* CLR form of a dense matrix (device, column-major, leading dimension ld >=
  * rows): blocks with ||block||_F < drop become zero, diagonal blocks of a
  * square blocking stay dense, every other block is truncated to relative
- * `tol` by SVD and stored dense iff its rank exceeds half of min(m, n). */
+ * `tol` and stored dense iff its rank exceeds half of min(m, n).  The
+ * truncation is the SVD's, or with CLR_COMPRESS_RRQR (clr_set_compression)
+ * the paper's rank-revealing QR (Sec. 4.1): M P = Q R with column pivoting,
+ * U = Q_r, V^T = R_r P^T, r the smallest rank with ||M - U V^T||_F <= tol
+ * ||M||_F (the dropped rows of R). */
 clr_status clr_compress(clr_context* ctx, const double* dense, int64_t ld, int nrb,
                         const int* row_sizes, int ncb, const int* col_sizes, double tol,
                         double drop, clr_matrix** out);
@@ -222,6 +230,10 @@ clr_status clr_set_tile_edges(clr_context* ctx, int precision, int dense_edge, i
  * proof's margin exceeds the SVD's rounding error); only the work differs.
  * Applies to products and plans created afterwards on this context. */
 clr_status clr_set_dense_certificate(clr_context* ctx, int enable);
+
+/* Truncating factorisation of clr_compress on this context (CLR_COMPRESS_SVD,
+ * the default, or CLR_COMPRESS_RRQR); products always recompress by SVD. */
+clr_status clr_set_compression(clr_context* ctx, int method);
 
 /* Autotuner: times the product A B (options as for clr_gemm; output discarded)
  * with every candidate edge (multiples of 32 up to the full tile), best of two

@@ -119,15 +119,23 @@ class Context:
                                    C.byref(h)))
         return CLRMatrix(self, h)
 
-    def compress(self, dense, row_sizes, col_sizes, tol: float, drop: float) -> "CLRMatrix":
-        """CLR form of a dense float64 cuda matrix (truncated SVD per block, see clr.h)."""
+    def compress(self, dense, row_sizes, col_sizes, tol: float, drop: float,
+                 method: str = "svd") -> "CLRMatrix":
+        """CLR form of a dense float64 cuda matrix, each block truncated by its SVD or, with
+        method="rrqr", by the paper's column-pivoted QR (see clr.h)."""
         buf, ld = _col_major(dense)
         nrb, ncb = len(row_sizes), len(col_sizes)
         rs = (C.c_int * nrb)(*map(int, row_sizes))
         cs = (C.c_int * ncb)(*map(int, col_sizes))
         h = C.c_void_p()
-        self._check(lib.clr_compress(self._h, C.c_void_p(buf.data_ptr()), C.c_int64(ld), nrb, rs,
-                                     ncb, cs, C.c_double(tol), C.c_double(drop), C.byref(h)))
+        code = {"svd": _abi.CLR_COMPRESS_SVD, "rrqr": _abi.CLR_COMPRESS_RRQR}[method]
+        self._check(lib.clr_set_compression(self._h, code))
+        try:
+            self._check(lib.clr_compress(self._h, C.c_void_p(buf.data_ptr()), C.c_int64(ld), nrb,
+                                         rs, ncb, cs, C.c_double(tol), C.c_double(drop),
+                                         C.byref(h)))
+        finally:
+            lib.clr_set_compression(self._h, _abi.CLR_COMPRESS_SVD)
         return CLRMatrix(self, h)
 
     # -- the method ----------------------------------------------------------

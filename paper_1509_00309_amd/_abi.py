@@ -19,6 +19,7 @@ CLR_ERR_DIVERGED = 8
 CLR_ERR_INTERNAL = 9
 
 CLR_FP64 = 0
+CLR_COMPRESS_SVD, CLR_COMPRESS_RRQR = 0, 1
 CLR_MIXED = 1
 CLR_SCREEN_ABS = 0
 CLR_SCREEN_AREA = 1
@@ -30,7 +31,7 @@ EXPORTS = [
     "clr_get_block", "clr_to_dense", "clr_gemm", "clr_axpby", "clr_sqrt_inv",
     "clr_identity_residual", "clr_gemm_backward", "clr_sqrt_inv_backward",
     "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
-    "clr_set_tile_edges", "clr_autotune", "clr_set_dense_certificate",
+    "clr_set_tile_edges", "clr_autotune", "clr_set_dense_certificate", "clr_set_compression",
 ]
 
 
@@ -112,6 +113,7 @@ def _load():
         "clr_plan_destroy": [P],
         "clr_set_tile_edges": [P, C.c_int, C.c_int, C.c_int],
         "clr_set_dense_certificate": [P, C.c_int],
+        "clr_set_compression": [P, C.c_int],
         "clr_autotune": [P, P, P, C.POINTER(GemmOpts), IP, IP, DP, DP],
         "clr_gemm_batch": [P, C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(GemmOpts),
                            C.POINTER(P), C.POINTER(GemmStats)],

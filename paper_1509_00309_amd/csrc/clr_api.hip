@@ -48,6 +48,8 @@ struct clr_context {
   int tile_thin[2] = {0, 0};
   // dense certificate before the truncated SVD of dense-accumulated blocks
   int dense_cert = 1;
+  // clr_compress truncates by column-pivoted QR instead of the SVD
+  int compress_rrqr = 0;
   // Stream-ordered cache of freed matrix allocations: a matrix released on the
   // context stream can back the next matrix of a similar size without a
   // hipMalloc (all users are ordered on the same stream).
@@ -582,6 +584,7 @@ extern "C" clr_status clr_compress(clr_context* ctx, const double* dense, int64_
       RecItem r{};
       r.path = (square && I == J) ? kPathForceDense : kPathDense;
       r.cert_hint = 1;
+      r.rrqr = ctx->compress_rrqr;
       r.m = rs[I];
       r.n = cs[J];
       r.R = 0;
@@ -898,6 +901,16 @@ extern "C" clr_status clr_set_tile_edges(clr_context* ctx, int precision, int de
 extern "C" clr_status clr_set_dense_certificate(clr_context* ctx, int enable) {
   if (!ctx) return CLR_ERR_INVALID_ARG;
   ctx->dense_cert = enable ? 1 : 0;
+  return CLR_OK;
+}
+
+// Factorisation used by clr_compress (the paper builds its input blocks by
+// rank-revealing QR, Sec. 4.1; products keep the truncated SVD).
+extern "C" clr_status clr_set_compression(clr_context* ctx, int method) {
+  if (!ctx) return CLR_ERR_INVALID_ARG;
+  if (method != CLR_COMPRESS_SVD && method != CLR_COMPRESS_RRQR)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "compression method %d", method);
+  ctx->compress_rrqr = method == CLR_COMPRESS_RRQR ? 1 : 0;
   return CLR_OK;
 }
 

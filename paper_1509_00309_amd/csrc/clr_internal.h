@@ -69,6 +69,7 @@ struct RecItem {
   int m, n;
   int piece0, npieces, R;     // low-rank path: concatenated factors
   int cert_hint;              // dense path: 1 to try the dense certificate first
+  int rrqr;                   // dense path: truncate by column-pivoted QR instead of the SVD
   const double* D;            // dense path: accumulated block
   int64_t ldd;
   double tau;                 // drop threshold

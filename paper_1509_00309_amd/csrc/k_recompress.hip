@@ -164,8 +164,13 @@ __device__ inline void tournament(int round, int k, int P, int& a, int& b) {
 // kRankFloor2; returns the number of steps k.  sh.perm holds the column
 // permutation (G P = Q R), sh.drop2 the squared norm of what was left out.
 // Only R is kept: the reflector tails below the diagonal are dead afterwards.
+// stop2: the factorisation stops once the squared norm of the remaining
+// columns is at most stop2 (relative to a unit-norm G).  keep_tau: the
+// reflector scalars are kept in sh.sigma[0 .. k) (each slot is free once its
+// column has been chosen).
 template <typename PT>
-CLR_INLINE int pivoted_qr(PT* G, int p, int q, int64_t ld, RecShared& sh) {
+CLR_INLINE int pivoted_qr(PT* G, int p, int q, int64_t ld, RecShared& sh,
+                          double stop2 = kRankFloor2, bool keep_tau = false) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = tid >> 4, gl = tid & 15;
@@ -210,7 +215,7 @@ CLR_INLINE int pivoted_qr(PT* G, int p, int q, int64_t ld, RecShared& sh) {
       }
     }
     __syncthreads();
-    if (sh.drop2 <= kRankFloor2) break;
+    if (sh.drop2 <= stop2) break;
     const int piv = sh.piv;
     if (piv != k) {
       PT* a = G + (int64_t)k * ld;
@@ -243,6 +248,7 @@ CLR_INLINE int pivoted_qr(PT* G, int p, int q, int64_t ld, RecShared& sh) {
       if (lane == 0) {
         col[k] = beta;
         sh.tau = t;
+        if (keep_tau) sh.sigma[k] = t;
       }
     }
     __syncthreads();
@@ -1607,8 +1613,8 @@ CLR_INLINE void householder_qr(PT* W, int rows, int cols, PT* tau) {
 }
 
 // X (rows x ncol, ld ldx, global) <- Q X with Q = H_0 H_1 ... H_{kk-1} from householder_qr.
-template <typename PT>
-CLR_INLINE void apply_q(const PT* W, int rows, int kk, const PT* tau, gdbl* X, int64_t ldx,
+template <typename PT, typename TT = PT>
+CLR_INLINE void apply_q(const PT* W, int rows, int kk, const TT* tau, gdbl* X, int64_t ldx,
                         int ncol) {
   const int tid = threadIdx.x;
   const int g = tid >> 4, gl = tid & 15;
@@ -1709,6 +1715,51 @@ CLR_INLINE void dense_general(const RecItem& it, PT* G, int p, int q, bool trans
   dense_truncated_out(it, G, p, p, q, trans, r, normc, sh);
 }
 
+// Truncation of a dense block by the paper's rank-revealing QR (Sec. 4.1):
+// column-pivoted Householder QR of G = D / ||D||_F (m x n, columns of D
+// pivoted), stopped at the first k whose remaining columns have squared norm
+// <= tol^2, i.e. ||D - Q_k R_k P^T||_F <= tol ||D||_F.  r = k; dense iff
+// 2 r > min(m, n); otherwise U = Q_r (Q applied to [I_r; 0]) and
+// V = ||D||_F (R_r P^T)^T, the pivoted rows of R.
+template <typename PT>
+CLR_INLINE void dense_rrqr(const RecItem& it, PT* G, double tol, double normc, RecShared& sh) {
+  const int m = it.m, n = it.n, q = m < n ? m : n;
+  const double inv_norm = 1.0 / normc;
+  const cgdbl* D = (const cgdbl*)it.D;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    G[i + (int64_t)j * m] = D[i + (int64_t)j * it.ldd] * inv_norm;
+  }
+  __syncthreads();
+  const int r = pivoted_qr(G, m, n, m, sh, tol * tol, true);
+  if (r == 0) {
+    write_meta(it, 0, 0, 0.0);
+    return;
+  }
+  if (2 * r > q) {
+    copy_dense_out(it);
+    write_meta(it, 1, q, normc);
+    return;
+  }
+  gdbl* Uo = (gdbl*)it.out;
+  gdbl* Vo = Uo + (int64_t)m * r;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += kRecThreads) {
+    const int i = (int)(e % m), c = (int)(e / m);
+    Uo[e] = i == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  apply_q(G, m, r, sh.sigma, Uo, m, r);
+  double part = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += kRecThreads) {
+    const int j = (int)(e % n), i = (int)(e / n);
+    const double v = j >= i ? G[i + (int64_t)j * m] : 0.0;
+    part += v * v;
+    Vo[sh.perm[j] + (int64_t)i * n] = normc * v;
+  }
+  const double kept = block_sum(part, sh);
+  write_meta(it, 2, r, normc * sqrt(kept));
+}
+
 // certified: the dense certificate proved the kept rank above q / 2, so the
 // block is copied out without the SVD (the SVD would reach the same result).
 template <bool REG>
@@ -1769,6 +1820,11 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
     } else if (threadIdx.x == 0) {
       atomicOr(status, 4);   // cannot happen with the planner's scratch rule
     }
+  } else if (it.rrqr) {
+    if (it.scratch != nullptr)
+      dense_rrqr(it, (gdbl*)it.scratch, tol, normc, sh);
+    else
+      dense_rrqr(it, (ldbl*)lds, tol, normc, sh);
   } else {
     if (it.scratch != nullptr)
       dense_general(it, (gdbl*)it.scratch, p, q, trans, tol, normc, status, sh);
@@ -1883,7 +1939,7 @@ CLR_INLINE void lowrank_path(const RecItem& it, const Piece* __restrict__ pieces
 // Dense-path blocks whose edges are both <= 160 (and tol > 0) go to the
 // register-resident kernel; everything else to the general one.
 __device__ inline bool register_item(const RecItem& it, double tol) {
-  return it.path == kPathDense && tol != 0.0 && it.m <= kRegEdge && it.n <= kRegEdge;
+  return it.path == kPathDense && !it.rrqr && tol != 0.0 && it.m <= kRegEdge && it.n <= kRegEdge;
 }
 
 __device__ inline bool item_guard(const RecItem& it, double tol, int* status) {

@@ -121,6 +121,72 @@ def test_compress_rectangular_blocks_and_edges(ctx, torch):
         parity.assert_parity(rep, FP64_BOUND, nblocks=16)
 
 
+def _check_rrqr(G, Sd, O, rows, cols, tol):
+    """RRQR construction against the oracle's: kinds and ranks agree (a rank may differ only at a
+    cut within 1e-6 of the threshold); every factored block satisfies U^T U = I and V = M^T U
+    (the rows of R), its error is within tol ||M||, and its reconstruction matches the oracle's
+    unless the two took different pivots at a near tie."""
+    kind, rank, norm = G.meta()
+    ro = np.concatenate([[0], np.cumsum(rows)])
+    co = np.concatenate([[0], np.cumsum(cols)])
+    ko = O.kinds()
+    same = differ = 0
+    for i in range(len(rows)):
+        for j in range(len(cols)):
+            M = Sd[ro[i]:ro[i + 1], co[j]:co[j + 1]]
+            nm = np.linalg.norm(M)
+            k = int(kind[i, j])
+            ob = O.blocks.get((i, j))
+            if k != int(ko[i, j]) or (k == 2 and int(rank[i, j]) != ob.rank):
+                r, _X, _W, tails = orc.rrqr_truncate(M, tol)
+                near = [abs(tails[x] - tol * nm) <= 1e-6 * tol * nm for x in range(len(tails))]
+                assert any(near), (i, j, k, int(ko[i, j]), int(rank[i, j]))
+                differ += 1
+                continue
+            if k != 2:
+                continue
+            _t, U, V = G.block(i, j, rows[i], cols[j], 2, int(rank[i, j]))
+            U, V = U.cpu().numpy(), V.cpu().numpy()
+            r = U.shape[1]
+            assert np.linalg.norm(U.T @ U - np.eye(r)) <= 1e-13 * r
+            assert np.linalg.norm(V - M.T @ U) <= 1e-13 * nm
+            assert np.linalg.norm(M - U @ V.T) <= tol * nm * (1 + 1e-9)
+            if np.linalg.norm(U @ V.T - ob.dense()) <= 1e-12 * nm:
+                same += 1
+            else:
+                differ += 1
+    return same, differ
+
+
+def test_compress_rrqr(ctx, torch):
+    """clr_compress with the paper's rank-revealing QR: register-size, LDS and global-scratch
+    working sets, rectangular blocks, against the oracle's column-pivoted QR."""
+    log("compress by RRQR")
+    wl = line_n512()
+    Sd = wl.dense()
+    G = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10, method="rrqr")
+    O = orc.compress_rrqr(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    same, differ = _check_rrqr(G, Sd, O, wl.sizes, wl.sizes, wl.tol)
+    log(f"  line N=512: {same} factored blocks equal to the oracle's, {differ} at pivot ties")
+    assert differ <= max(1, 0.1 * (same + differ))
+    rng = rng_for(151)
+    rows, cols = [1, 37, 96, 150, 200], [80, 1, 23, 130, 300]
+    pts_r = rng.uniform(0, 30, size=(sum(rows), 1))
+    pts_c = rng.uniform(0, 30, size=(sum(cols), 1))
+    from workloads import kernel_block
+    Sr = kernel_block(np.sort(pts_r, axis=0), np.sort(pts_c, axis=0), 0.05)
+    for tol in (1e-6, 1e-10):
+        G = ctx.compress(torch.from_numpy(Sr).cuda(), rows, cols, tol, 1e-12, method="rrqr")
+        O = orc.compress_rrqr(Sr, rows, cols, tol, 1e-12)
+        same, differ = _check_rrqr(G, Sr, O, rows, cols, tol)
+        log(f"  rectangular tol {tol}: {same} equal, {differ} at pivot ties")
+        assert differ <= max(1, 0.1 * (same + differ))
+    # the default stays the SVD
+    G = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    rep = parity.compare(G, orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10), wl.tol)
+    parity.assert_parity(rep, FP64_BOUND, nblocks=64)
+
+
 # ---------------------------------------------------------------------------
 # The product
 # ---------------------------------------------------------------------------
