@@ -225,6 +225,28 @@ def run_low_rank(ctx, forms, steps, warmup, log_fn):
     return out
 
 
+def run_compression(ctx, Sd_t, wl, reps, log_fn):
+    """Construction of the CLR input from the dense matrix (already in HBM): the truncated SVD
+    against the paper's column-pivoted QR (Sec. 4.1), wall time per call and what each stores."""
+    import torch
+    out = {}
+    for method in ("svd", "rrqr"):
+        G = ctx.compress(Sd_t, wl.sizes, wl.sizes, wl.tol, 1e-10, method=method)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            G = ctx.compress(Sd_t, wl.sizes, wl.sizes, wl.tol, 1e-10, method=method)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        kind, rank, _norm = G.meta()
+        out[method] = {"ms": ms, "stored_elements": int(G.stored_elements()),
+                       "low_rank_blocks": int(np.sum(kind == 2)),
+                       "dense_blocks": int(np.sum(kind == 1)),
+                       "mean_rank": float(rank[kind == 2].mean()) if np.any(kind == 2) else 0.0}
+        log_fn(f"  compress {method}: {ms:.2f} ms, stored {out[method]['stored_elements']}")
+    return out
+
+
 def run_batched(ctx, nprod, log_fn):
     """Batch of mixed-size products: nprod independent products S_p * S_p (N_p ~ U{512..4096}, 16..48
     uneven clusters, tol 1e-8) planned once and executed as one graph replay per form;
@@ -369,6 +391,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-lowrank", action="store_true")
+    ap.add_argument("--no-compression", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -445,6 +468,10 @@ def main():
     if not args.no_lowrank:
         log("low-rank regime products")
         low_rank = run_low_rank(ctx, [f for f in args.forms.split(",")], args.steps, args.warmup, log)
+    compression = None
+    if not args.no_compression:
+        log("input construction: truncated SVD and rank-revealing QR")
+        compression = run_compression(ctx, torch.from_numpy(Sd).cuda(), wl, 3, log)
     batched = None
     if not args.no_batch:
         log(f"batched products: {args.batch_count}")
@@ -498,6 +525,7 @@ def main():
         "sqrt_inv": sqrtinv,
         "low_rank_regime": low_rank,
         "batched": batched,
+        "compression": compression,
         "roofline": roof_gemm if fb["phase_ms"]["dense_products"] >= fb["rec_engine_ms"] else roof,
         "roofline_recompress": roof,
         "roofline_dense_gemm": roof_gemm,
