@@ -40,7 +40,7 @@ struct clr_context {
   std::string last_error;
   DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
       items_thin2, pieces, rec, pool, scratch, acc, status, terms, aux_items, aux_segs,
-      aux_dense, ptrs, recg, order;
+      aux_dense, ptrs, recg, order, order_thin, sortw;
   hipEvent_t ev[10] = {};
   // grouped-GEMM item edges per precision (0: the kernel's largest tile), set
   // explicitly or by clr_autotune
@@ -281,9 +281,9 @@ int max_item(const clr_gemm_opts* o) {
 
 // Factor products (one side a rank) run on the wave-per-item kernel.
 hipError_t run_wgemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
-                     hipStream_t s) {
-  if (o->precision == CLR_MIXED) return launch_wgemm_f32(items, segs, n, o->split, s);
-  return launch_wgemm_f64(items, segs, n, s);
+                     hipStream_t s, const int* order = nullptr) {
+  if (o->precision == CLR_MIXED) return launch_wgemm_f32(items, segs, n, o->split, s, order);
+  return launch_wgemm_f64(items, segs, n, s, order);
 }
 
 int tile_edge(const clr_context* ctx, const clr_gemm_opts* o, bool thin) {
@@ -448,7 +448,8 @@ extern "C" clr_status clr_context_destroy(clr_context* ctx) {
                     &ctx->items_dense, &ctx->seg_thin1, &ctx->items_thin1, &ctx->seg_thin2,
                     &ctx->items_thin2, &ctx->pieces, &ctx->rec, &ctx->pool, &ctx->scratch,
                     &ctx->acc, &ctx->status, &ctx->terms, &ctx->aux_items, &ctx->aux_segs,
-                    &ctx->aux_dense, &ctx->ptrs, &ctx->recg, &ctx->order})
+                    &ctx->aux_dense, &ctx->ptrs, &ctx->recg, &ctx->order, &ctx->order_thin,
+                    &ctx->sortw})
     free_buf(*b);
   for (auto& c : ctx->cache) (void)hipFree(c.first);
   ctx->cache.clear();
@@ -762,6 +763,8 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   if (e == hipSuccess) e = ensure(ctx->seg_dense, sizeof(Seg) * hc[kCntSegDense]);
   if (e == hipSuccess) e = ensure(ctx->items_dense, sizeof(GemmItem) * hc[kCntGemmItems]);
   if (e == hipSuccess) e = ensure(ctx->order, sizeof(int) * hc[kCntGemmItems]);
+  if (e == hipSuccess) e = ensure(ctx->order_thin, sizeof(int) * hc[kCntThin1]);
+  if (e == hipSuccess) e = ensure(ctx->sortw, operand_order_bytes((int)hc[kCntThin1]));
   if (e == hipSuccess) e = ensure(ctx->seg_thin1, sizeof(Seg) * hc[kCntThin1]);
   if (e == hipSuccess) e = ensure(ctx->items_thin1, sizeof(GemmItem) * hc[kCntThin1]);
   if (e == hipSuccess) e = ensure(ctx->seg_thin2, sizeof(Seg) * hc[kCntThin2]);
@@ -799,8 +802,13 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   if (e == hipSuccess) e = launch_fill(P, F, stream);
   if (e == hipSuccess)
     e = launch_item_order(F.items_dense, (int)hc[kCntGemmItems], as<int>(ctx->order), stream);
+  if (e == hipSuccess)
+    e = launch_operand_order(F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], ctx->sortw.p,
+                             as<int>(ctx->order_thin), stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], stream);
-  if (e == hipSuccess) e = run_wgemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream);
+  if (e == hipSuccess)
+    e = run_wgemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream,
+                  as<int>(ctx->order_thin));
   if (e == hipSuccess) e = run_wgemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[6], stream);
   if (e == hipSuccess)
@@ -977,7 +985,7 @@ struct clr_plan {
   std::vector<clr_matrix*> C;
   // execution buffers owned by the plan (a captured graph keeps their addresses)
   DevBuf seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2, items_thin2, pieces, rec,
-      pool, scratch, acc, recg, status, bases, order;
+      pool, scratch, acc, recg, status, bases, order, order_thin;
   int64_t n_thin1 = 0, n_thin2 = 0, n_dense = 0, n_rec = 0;
   int dense_cert = 1;
   double flops[kNumStats] = {};
@@ -994,7 +1002,8 @@ void plan_free(clr_plan* pl) {
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   for (DevBuf* b : {&pl->seg_dense, &pl->items_dense, &pl->seg_thin1, &pl->items_thin1,
                     &pl->seg_thin2, &pl->items_thin2, &pl->pieces, &pl->rec, &pl->pool,
-                    &pl->scratch, &pl->acc, &pl->recg, &pl->status, &pl->bases, &pl->order})
+                    &pl->scratch, &pl->acc, &pl->recg, &pl->status, &pl->bases, &pl->order,
+                    &pl->order_thin})
     free_buf(*b);
   delete pl;
 }
@@ -1004,7 +1013,8 @@ void plan_free(clr_plan* pl) {
 // context stream, so it can be recorded into a graph.
 hipError_t plan_launch(clr_plan* pl, hipStream_t s) {
   const clr_gemm_opts* o = &pl->o;
-  hipError_t e = run_wgemm(o, as<GemmItem>(pl->items_thin1), as<Seg>(pl->seg_thin1), (int)pl->n_thin1, s);
+  hipError_t e = run_wgemm(o, as<GemmItem>(pl->items_thin1), as<Seg>(pl->seg_thin1),
+                           (int)pl->n_thin1, s, as<int>(pl->order_thin));
   if (e == hipSuccess)
     e = run_wgemm(o, as<GemmItem>(pl->items_thin2), as<Seg>(pl->seg_thin2), (int)pl->n_thin2, s);
   if (e == hipSuccess)
@@ -1164,6 +1174,11 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   }
   HIP_TRY(ctx, launch_item_order(as<GemmItem>(pl->items_dense), (int)sum[kCntGemmItems],
                                  as<int>(pl->order), stream));
+  HIP_TRY(ctx, ensure(pl->order_thin, sizeof(int) * sum[kCntThin1]));
+  HIP_TRY(ctx, ensure(ctx->sortw, operand_order_bytes((int)sum[kCntThin1])));
+  HIP_TRY(ctx, launch_operand_order(as<GemmItem>(pl->items_thin1), as<Seg>(pl->seg_thin1),
+                                    (int)sum[kCntThin1], ctx->sortw.p, as<int>(pl->order_thin),
+                                    stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
   return s;
 }

@@ -198,15 +198,23 @@ struct AxpbyDenseItem {
 // from launch_item_order; null keeps the XCD-blocked order.
 hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
                             bool dense = false, const int* order = nullptr);
-hipError_t launch_wgemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s);
+hipError_t launch_wgemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
+                            const int* order = nullptr);
 hipError_t launch_wgemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s);
+                            hipStream_t s, const int* order = nullptr);
 constexpr int kMaxItemThin = 64;   // largest edge of a wave-per-item (thin) GEMM item
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
                             hipStream_t s, bool dense = false, const int* order = nullptr);
 // Items of the LDS grouped GEMM by decreasing estimated cost (slabs times the
 // busiest wave's tiles, in quarter-octave classes) into order[0 .. nitems).
 hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s);
+// Items of the wave-per-item GEMM grouped by their first term's left operand
+// (the dense block of a low-rank x dense product), so that the items reading
+// one block run next to each other: a radix sort of the operand addresses.
+// work must hold operand_order_bytes(nitems) bytes.
+size_t operand_order_bytes(int nitems);
+hipError_t launch_operand_order(const GemmItem* items, const Seg* segs, int nitems, void* work,
+                                int* order, hipStream_t s);
 // Per item, 1 if a dense-path block is proved to stay dense (kept rank above
 // half its short edge), else 0; count (optional) is incremented per proof.
 hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* cert,

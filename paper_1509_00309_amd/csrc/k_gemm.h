@@ -652,11 +652,16 @@ __device__ __attribute__((always_inline)) inline void wave_nb(const GemmItem& it
 template <bool F32, bool SPLIT>
 __global__ __launch_bounds__(64 * kWaveItemsPerBlock, 2) void k_wgemm(const GemmItem* __restrict__ items,
                                                                   const Seg* __restrict__ segs,
-                                                                  int nitems) {
+                                                                  int nitems,
+                                                                  const int* __restrict__ order) {
+  // Workgroups are dealt to the 8 XCDs round-robin; blk numbers the
+  // workgroups of one XCD consecutively, so neighbouring slots (items that
+  // share an operand block once ordered by it) run on one XCD's L2.
   const int per = gridDim.x / 8;
   const int blk = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  const int item = blk * kWaveItemsPerBlock + uni((int)threadIdx.x >> 6);
-  if (item >= nitems) return;
+  const int slot = blk * kWaveItemsPerBlock + uni((int)threadIdx.x >> 6);
+  if (slot >= nitems) return;
+  const int item = order ? uni(order[slot]) : slot;
   GemmItem it = items[item];
   it.m = uni(it.m);
   it.n = uni(it.n);

@@ -20,13 +20,13 @@ hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, 
 }
 
 hipError_t launch_wgemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s) {
+                            hipStream_t s, const int* order) {
   if (nitems <= 0) return hipSuccess;
   const dim3 grid(wave_grid(nitems)), block(64 * kWaveItemsPerBlock);
   if (split)
-    hipLaunchKernelGGL((k_wgemm<true, true>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_wgemm<true, true>), grid, block, 0, s, items, segs, nitems, order);
   else
-    hipLaunchKernelGGL((k_wgemm<true, false>), grid, block, 0, s, items, segs, nitems);
+    hipLaunchKernelGGL((k_wgemm<true, false>), grid, block, 0, s, items, segs, nitems, order);
   return hipGetLastError();
 }
 

@@ -15,10 +15,11 @@ hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, 
   return hipGetLastError();
 }
 
-hipError_t launch_wgemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s) {
+hipError_t launch_wgemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
+                            const int* order) {
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_wgemm<false, false>), dim3(wave_grid(nitems)),
-                     dim3(64 * kWaveItemsPerBlock), 0, s, items, segs, nitems);
+                     dim3(64 * kWaveItemsPerBlock), 0, s, items, segs, nitems, order);
   return hipGetLastError();
 }
 

@@ -3,6 +3,8 @@
 // dense matrix, scaling, the blockwise terms of ||X - I||_F, the dense part of
 // the blockwise combination a X + b Y + c I, and the blockwise transpose,
 // dense ingest and structure masking used by the adjoints.
+#include <hipcub/hipcub.hpp>
+
 #include "clr_internal.h"
 
 namespace clr {
@@ -337,6 +339,57 @@ hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipS
   if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_item_order, dim3(1), dim3(kOrderThreads), 0, s, items, nitems, order);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Operand-grouped order of the wave-per-item items.  A low-rank x dense term
+// reads a whole dense block for a thin result, and the same dense block
+// serves every low-rank partner on the other side, so in pair order those
+// reads miss L2.  Sorting the items by the address of their left operand (the
+// dense block of LD and DL terms, V_A of LL cores) puts the readers of one
+// block next to each other; the key is the element index of that address
+// (low 32 bits: two distinct blocks sharing a key only costs locality).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+size_t sort_temp_bytes(int n) {
+  size_t t = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, t, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (const int*)nullptr, (int*)nullptr, n, 0, 32);
+  return t;
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_operand_keys(const GemmItem* __restrict__ items,
+                                                      const Seg* __restrict__ segs, int n,
+                                                      uint32_t* __restrict__ keys,
+                                                      int* __restrict__ vals) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = (uint32_t)((uintptr_t)segs[items[i].seg0].L >> 3);
+  vals[i] = i;
+}
+
+size_t operand_order_bytes(int nitems) {
+  if (nitems <= 0) return 0;
+  return 3 * align256(sizeof(uint32_t) * (size_t)nitems) + align256(sort_temp_bytes(nitems));
+}
+
+hipError_t launch_operand_order(const GemmItem* items, const Seg* segs, int nitems, void* work,
+                                int* order, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  const size_t a = align256(sizeof(uint32_t) * (size_t)nitems);
+  char* w = static_cast<char*>(work);
+  uint32_t* kin = reinterpret_cast<uint32_t*>(w);
+  uint32_t* kout = reinterpret_cast<uint32_t*>(w + a);
+  int* vin = reinterpret_cast<int*>(w + 2 * a);
+  void* temp = w + 3 * a;
+  size_t tb = sort_temp_bytes(nitems);
+  hipLaunchKernelGGL(k_operand_keys, dim3((unsigned)((nitems + 255) / 256)), dim3(256), 0, s, items,
+                     segs, nitems, kin, vin);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipcub::DeviceRadixSort::SortPairs(temp, tb, kin, kout, vin, order, nitems, 0, 32, s);
 }
 
 }  // namespace clr
