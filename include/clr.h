@@ -60,6 +60,11 @@ typedef enum { CLR_FP64 = 0, CLR_MIXED = 1 } clr_precision;
  * (default) or the paper's rank-revealing QR with column pivoting.          */
 typedef enum { CLR_COMPRESS_SVD = 0, CLR_COMPRESS_RRQR = 1 } clr_compression;
 
+/* Kernels of clr_kernel_matrix: the overlap-like exp(-a r^2) and the
+ * Coulomb-like 1 / sqrt(r^2 + a^2) stand-ins for the paper's test matrices
+ * (Sec. 5: overlap and Coulomb matrices of water clusters).                  */
+typedef enum { CLR_KERNEL_GAUSSIAN = 0, CLR_KERNEL_COULOMB = 1 } clr_kernel;
+
 /* Screening threshold tau of a result block (I, J) of size m x n (Sec. 4.1,
  * last paragraph): ABS uses tau = eps_sp, AREA uses tau = eps_sp * m * n.    */
 typedef enum { CLR_SCREEN_ABS = 0, CLR_SCREEN_AREA = 1 } clr_screen_mode;
@@ -154,6 +159,24 @@ clr_status clr_create(clr_context* ctx, int nrb, const int* row_sizes, int ncb,
 clr_status clr_compress(clr_context* ctx, const double* dense, int64_t ld, int nrb,
                         const int* row_sizes, int ncb, const int* col_sizes, double tol,
                         double drop, clr_matrix** out);
+
+/* Dense kernel matrix generated on the device, the input of clr_compress
+ * (the step before the product, Sec. 4.1: a matrix whose blocks are then
+ * truncated).  For i < nrows, j < ncols:
+ *   r2 = sum_c (x_i[c] - y_j[c])^2   (c = 0 .. dim-1, each step rounded, no FMA;
+ *        sqrt and the division correctly rounded, exp within one unit in the
+ *        last place)
+ *   out[i + j*ld] = exp(-a r2)            (CLR_KERNEL_GAUSSIAN)
+ *                 = 1 / sqrt(r2 + a^2)    (CLR_KERNEL_COULOMB, r2 starts at a^2)
+ *                 + diag where i == j.
+ * row_points (nrows x dim) and col_points (ncols x dim) are device, row-major;
+ * pass the same pointer twice for a symmetric matrix.  out is device,
+ * column-major, ld >= nrows, caller-owned.  dim is 1, 2 or 3; a must be
+ * finite, >= 0 for GAUSSIAN and > 0 for COULOMB.  Enqueued on the context
+ * stream; returns CLR_ERR_INVALID_ARG for a bad argument. */
+clr_status clr_kernel_matrix(clr_context* ctx, const double* row_points, int64_t nrows,
+                             const double* col_points, int64_t ncols, int dim, int kernel,
+                             double a, double diag, double* out, int64_t ld);
 
 clr_status clr_destroy(clr_matrix* m);
 

@@ -138,6 +138,29 @@ class Context:
             lib.clr_set_compression(self._h, _abi.CLR_COMPRESS_SVD)
         return CLRMatrix(self, h)
 
+    def kernel_matrix(self, points, kernel: str = "gaussian", a: float = 0.3, diag: float = 0.0,
+                      col_points=None):
+        """Dense kernel matrix generated on the device (see clr.h): exp(-a r^2) ("gaussian") or
+        1 / sqrt(r^2 + a^2) ("coulomb"), plus diag where i == j.  points: (n, dim) float64
+        cuda tensor; col_points (default: points) gives the columns.  Returns an
+        (n, n_cols) float64 cuda tensor (a transposed view of column-major storage)."""
+        torch = _torch()
+        x = points.contiguous()
+        y = x if col_points is None else col_points.contiguous()
+        for t in (x, y):
+            if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2:
+                raise TypeError("points must be 2-D float64 cuda tensors")
+        if x.shape[1] != y.shape[1]:
+            raise ValueError("row and column points differ in dimension")
+        nr, nc = x.shape[0], y.shape[0]
+        out = torch.empty((nc, nr), dtype=torch.float64, device=x.device)
+        code = {"gaussian": _abi.CLR_KERNEL_GAUSSIAN, "coulomb": _abi.CLR_KERNEL_COULOMB}[kernel]
+        self._check(lib.clr_kernel_matrix(self._h, C.c_void_p(x.data_ptr()), C.c_int64(nr),
+                                          C.c_void_p(y.data_ptr()), C.c_int64(nc),
+                                          int(x.shape[1]), code, C.c_double(a), C.c_double(diag),
+                                          C.c_void_p(out.data_ptr()), C.c_int64(nr)))
+        return out.t()
+
     # -- the method ----------------------------------------------------------
     def gemm(self, A: "CLRMatrix", B: "CLRMatrix", tol: float, eps_sp: float, screen="abs",
              precision="fp64", split: int = 0, alpha: float = 1.0, stats: bool = False):

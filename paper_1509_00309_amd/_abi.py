@@ -20,6 +20,7 @@ CLR_ERR_INTERNAL = 9
 
 CLR_FP64 = 0
 CLR_COMPRESS_SVD, CLR_COMPRESS_RRQR = 0, 1
+CLR_KERNEL_GAUSSIAN, CLR_KERNEL_COULOMB = 0, 1
 CLR_MIXED = 1
 CLR_SCREEN_ABS = 0
 CLR_SCREEN_AREA = 1
@@ -32,6 +33,7 @@ EXPORTS = [
     "clr_identity_residual", "clr_gemm_backward", "clr_sqrt_inv_backward",
     "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
     "clr_set_tile_edges", "clr_autotune", "clr_set_dense_certificate", "clr_set_compression",
+    "clr_kernel_matrix",
 ]
 
 
@@ -114,6 +116,8 @@ def _load():
         "clr_set_tile_edges": [P, C.c_int, C.c_int, C.c_int],
         "clr_set_dense_certificate": [P, C.c_int],
         "clr_set_compression": [P, C.c_int],
+        "clr_kernel_matrix": [P, P, C.c_int64, P, C.c_int64, C.c_int, C.c_int, C.c_double,
+                              C.c_double, P, C.c_int64],
         "clr_autotune": [P, P, P, C.POINTER(GemmOpts), IP, IP, DP, DP],
         "clr_gemm_batch": [P, C.c_int, C.POINTER(P), C.POINTER(P), C.POINTER(GemmOpts),
                            C.POINTER(P), C.POINTER(GemmStats)],

@@ -914,6 +914,28 @@ extern "C" clr_status clr_set_dense_certificate(clr_context* ctx, int enable) {
 
 // Factorisation used by clr_compress (the paper builds its input blocks by
 // rank-revealing QR, Sec. 4.1; products keep the truncated SVD).
+extern "C" clr_status clr_kernel_matrix(clr_context* ctx, const double* row_points,
+                                        int64_t nrows, const double* col_points, int64_t ncols,
+                                        int dim, int kernel, double a, double diag, double* out,
+                                        int64_t ld) {
+  if (!ctx) return CLR_ERR_INVALID_ARG;
+  if (!row_points || !col_points || !out) return fail(ctx, CLR_ERR_INVALID_ARG, "null pointer");
+  if (nrows < 1 || ncols < 1 || ld < nrows)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "bad sizes (%lld x %lld, ld %lld)", (long long)nrows,
+                (long long)ncols, (long long)ld);
+  if ((ncols + 31) / 32 > 65535 || (nrows + 255) / 256 > INT32_MAX)
+    return fail(ctx, CLR_ERR_CAPACITY, "kernel matrix too large");
+  if (dim < 1 || dim > 3) return fail(ctx, CLR_ERR_INVALID_ARG, "dim must be 1, 2 or 3");
+  if (kernel != CLR_KERNEL_GAUSSIAN && kernel != CLR_KERNEL_COULOMB)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "kernel %d", kernel);
+  if (!std::isfinite(a) || !std::isfinite(diag) || a < 0.0 ||
+      (kernel == CLR_KERNEL_COULOMB && !(a > 0.0)))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "bad kernel parameters");
+  HIP_TRY(ctx, launch_kernel_matrix(row_points, nrows, col_points, ncols, dim, kernel, a, diag,
+                                    out, ld, ctx->stream));
+  return CLR_OK;
+}
+
 extern "C" clr_status clr_set_compression(clr_context* ctx, int method) {
   if (!ctx) return CLR_ERR_INVALID_ARG;
   if (method != CLR_COMPRESS_SVD && method != CLR_COMPRESS_RRQR)

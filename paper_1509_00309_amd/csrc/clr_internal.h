@@ -213,6 +213,10 @@ hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipS
 // one block run next to each other: a radix sort of the operand addresses.
 // work must hold operand_order_bytes(nitems) bytes.
 size_t operand_order_bytes(int nitems);
+// Dense kernel matrix (clr_kernel_matrix): kind 0 exp(-a r^2), 1 1/sqrt(r^2 + a^2).
+hipError_t launch_kernel_matrix(const double* xr, int64_t nr, const double* xc, int64_t nc,
+                                int dim, int kind, double a, double diag, double* out,
+                                int64_t ld, hipStream_t s);
 hipError_t launch_operand_order(const GemmItem* items, const Seg* segs, int nitems, void* work,
                                 int* order, hipStream_t s);
 // Per item, 1 if a dense-path block is proved to stay dense (kept rank above

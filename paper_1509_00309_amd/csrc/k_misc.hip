@@ -370,6 +370,53 @@ __global__ __launch_bounds__(256) void k_operand_keys(const GemmItem* __restrict
   vals[i] = i;
 }
 
+// ---------------------------------------------------------------------------
+// Kernel-generated dense matrix.  Thread i of a workgroup column owns row i
+// and walks kKmCols columns, so the column-major stores are coalesced and
+// the column points are read as uniform (scalar) loads.  Every step of r^2
+// is rounded on its own (no contraction: plain operators under the pragma,
+// since the *_rn helpers are inline functions the pragma does not reach), so
+// with correctly rounded sqrt and division the Coulomb-like kernel equals a
+// host evaluation of the same formula bit for bit; exp may differ in the
+// last bit.
+// ---------------------------------------------------------------------------
+constexpr int kKmCols = 32;
+
+__global__ __launch_bounds__(256) void k_kernel_matrix(const double* __restrict__ xr, int64_t nr,
+                                                       const double* __restrict__ xc, int64_t nc,
+                                                       int dim, int kind, double a, double diag,
+                                                       double* __restrict__ out, int64_t ld) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nr) return;
+  double xi[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < dim; ++c) xi[c] = xr[i * dim + c];
+  const double r0 = kind == 1 ? a * a : 0.0;
+  const int64_t j0 = (int64_t)blockIdx.y * kKmCols;
+  const int64_t j1 = j0 + kKmCols < nc ? j0 + kKmCols : nc;
+  for (int64_t j = j0; j < j1; ++j) {
+    double r2 = r0;
+    for (int c = 0; c < dim; ++c) {
+      const double d = xi[c] - xc[j * dim + c];
+      const double sq = d * d;
+      r2 = r2 + sq;
+    }
+    double v = kind == 1 ? 1.0 / sqrt(r2) : exp(-a * r2);
+    if (i == j) v = v + diag;
+    out[i + j * ld] = v;
+  }
+}
+
+hipError_t launch_kernel_matrix(const double* xr, int64_t nr, const double* xc, int64_t nc,
+                                int dim, int kind, double a, double diag, double* out,
+                                int64_t ld, hipStream_t s) {
+  if (nr <= 0 || nc <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((nr + 255) / 256), (unsigned)((nc + kKmCols - 1) / kKmCols));
+  hipLaunchKernelGGL(k_kernel_matrix, grid, dim3(256), 0, s, xr, nr, xc, nc, dim, kind, a, diag,
+                     out, ld);
+  return hipGetLastError();
+}
+
 size_t operand_order_bytes(int nitems) {
   if (nitems <= 0) return 0;
   return 3 * align256(sizeof(uint32_t) * (size_t)nitems) + align256(sort_temp_bytes(nitems));
