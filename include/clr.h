@@ -54,7 +54,13 @@ typedef enum {
   CLR_ERR_INTERNAL = 9       /* a kernel reported an inconsistent state             */
 } clr_status;
 
-typedef enum { CLR_FP64 = 0, CLR_MIXED = 1 } clr_precision;
+/* Block products in FP64 MFMA; FP32 MFMA with FP64 accumulation (MIXED); or
+ * the dense accumulation on INT8 MFMA by operand splitting (OZAKI: every
+ * 64-deep chunk of an operand row / column scaled by a power of two and cut
+ * into `split` signed 7-bit digits, digit products summed exactly in int32,
+ * groups added in FP64; factor products stay FP64).  Recompression and
+ * convergence checks are FP64 in every form.                                */
+typedef enum { CLR_FP64 = 0, CLR_MIXED = 1, CLR_OZAKI = 2 } clr_precision;
 
 /* Truncating factorisation of clr_compress (Sec. 4.1): the truncated SVD
  * (default) or the paper's rank-revealing QR with column pivoting.          */
@@ -75,8 +81,9 @@ typedef struct {
   int screen;      /* clr_screen_mode                                                  */
   int precision;   /* clr_precision: block products in FP64, or FP32 MFMA with FP64
                       accumulation every 16 inner indices (MIXED)                      */
-  int split;       /* MIXED only: 1 adds the hi*lo and lo*hi correction products,
-                      0 uses the FP32-rounded operands alone                           */
+  int split;       /* MIXED: 1 adds the hi*lo and lo*hi correction products, 0 uses
+                      the FP32-rounded operands alone.  OZAKI: digits per operand,
+                      2..7 (0 selects 7, near FP64 accuracy)                           */
   double alpha;    /* result is alpha * A * B (screening estimate scaled by |alpha|)   */
 } clr_gemm_opts;
 

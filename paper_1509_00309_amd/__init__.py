@@ -16,12 +16,12 @@ from typing import Dict, Optional, Sequence, Tuple
 import numpy as np
 
 from . import _abi
-from ._abi import (CLR_FP64, CLR_MIXED, CLR_SCREEN_ABS, CLR_SCREEN_AREA, ClrError,
+from ._abi import (CLR_FP64, CLR_MIXED, CLR_OZAKI, CLR_SCREEN_ABS, CLR_SCREEN_AREA, ClrError,
                    GemmOpts, GemmStats, SqrtInvOpts, SqrtInvStats, lib, LIB_PATH)
 
 __all__ = [
     "Context", "CLRMatrix", "ClrError", "GemmStats", "SqrtInvStats", "lib", "LIB_PATH",
-    "CLR_FP64", "CLR_MIXED", "gemm_dense", "sqrt_inv_dense", "Plan",
+    "CLR_FP64", "CLR_MIXED", "CLR_OZAKI", "gemm_dense", "sqrt_inv_dense", "Plan",
 ]
 
 
@@ -46,7 +46,8 @@ def _gemm_opts(tol, eps_sp, screen, precision, split, alpha) -> GemmOpts:
     o.tol = float(tol)
     o.eps_sp = float(eps_sp)
     o.screen = {"abs": CLR_SCREEN_ABS, "area": CLR_SCREEN_AREA}[screen] if isinstance(screen, str) else int(screen)
-    o.precision = {"fp64": CLR_FP64, "mixed": CLR_MIXED}[precision] if isinstance(precision, str) else int(precision)
+    o.precision = ({"fp64": CLR_FP64, "mixed": CLR_MIXED, "ozaki": CLR_OZAKI}[precision]
+                   if isinstance(precision, str) else int(precision))
     o.split = int(split)
     o.alpha = float(alpha)
     return o

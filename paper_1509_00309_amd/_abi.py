@@ -22,6 +22,7 @@ CLR_FP64 = 0
 CLR_COMPRESS_SVD, CLR_COMPRESS_RRQR = 0, 1
 CLR_KERNEL_GAUSSIAN, CLR_KERNEL_COULOMB = 0, 1
 CLR_MIXED = 1
+CLR_OZAKI = 2
 CLR_SCREEN_ABS = 0
 CLR_SCREEN_AREA = 1
 

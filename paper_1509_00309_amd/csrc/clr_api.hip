@@ -263,8 +263,11 @@ clr_status check_opts(clr_context* ctx, const clr_gemm_opts* o) {
   if (!(o->eps_sp >= 0.0)) return fail(ctx, CLR_ERR_INVALID_ARG, "eps_sp must be >= 0");
   if (o->screen != CLR_SCREEN_ABS && o->screen != CLR_SCREEN_AREA)
     return fail(ctx, CLR_ERR_INVALID_ARG, "bad screen mode");
-  if (o->precision != CLR_FP64 && o->precision != CLR_MIXED)
+  if (o->precision != CLR_FP64 && o->precision != CLR_MIXED && o->precision != CLR_OZAKI)
     return fail(ctx, CLR_ERR_INVALID_ARG, "bad precision");
+  if (o->precision == CLR_OZAKI && o->split != 0 && (o->split < 2 || o->split > kOzMaxSlices))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "OZAKI digits must be 2..%d (0: %d)", kOzMaxSlices,
+                kOzMaxSlices);
   if (!std::isfinite(o->alpha)) return fail(ctx, CLR_ERR_INVALID_ARG, "alpha must be finite");
   return CLR_OK;
 }
@@ -272,10 +275,13 @@ clr_status check_opts(clr_context* ctx, const clr_gemm_opts* o) {
 hipError_t run_ggemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
                      hipStream_t s, bool dense = false, const int* order = nullptr) {
   if (o->precision == CLR_MIXED) return launch_ggemm_f32(items, segs, n, o->split, s, dense, order);
+  if (o->precision == CLR_OZAKI && dense)
+    return launch_ggemm_ozaki(items, segs, n, o->split ? o->split : kOzMaxSlices, s, order);
   return launch_ggemm_f64(items, segs, n, s, dense, order);
 }
 
 int max_item(const clr_gemm_opts* o) {
+  if (o->precision == CLR_OZAKI) return kMaxItemOzaki;
   return o->precision == CLR_MIXED ? kMaxItemF32 : kMaxItemF64;
 }
 
@@ -287,9 +293,10 @@ hipError_t run_wgemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* s
 }
 
 int tile_edge(const clr_context* ctx, const clr_gemm_opts* o, bool thin) {
-  const int pi = o->precision == CLR_MIXED ? 1 : 0;
+  const int pi = o->precision == CLR_MIXED ? 1 : 0;   // OZAKI shares the FP64 edges, capped
   const int v = thin ? ctx->tile_thin[pi] : ctx->tile_dense[pi];
-  return v > 0 ? v : (thin ? kMaxItemThin : max_item(o));
+  const int top = thin ? kMaxItemThin : max_item(o);
+  return v > 0 ? std::min(v, top) : top;
 }
 
 // Read and clear the device status word; map it to a status code.
@@ -957,6 +964,8 @@ extern "C" clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const 
   if (!ctx || !A || !B) return CLR_ERR_INVALID_ARG;
   clr_status s = check_opts(ctx, opts);
   if (s != CLR_OK) return s;
+  if (opts->precision == CLR_OZAKI)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "autotune covers the FP64 and MIXED forms");
   const int pi = opts->precision == CLR_MIXED ? 1 : 0;
   const int top = max_item(opts);
   double best_d = 1e300, best_t = 1e300;

@@ -16,6 +16,8 @@ constexpr int kF64WaveTiles = 5;      // 16x16 MFMA tiles per wave and dimension
 constexpr int kF32WaveTiles = 4;      // same for the FP32-MFMA (mixed) form
 constexpr int kMaxItemF64 = 32 * kF64WaveTiles;   // 160: largest output tile edge per item
 constexpr int kMaxItemF32 = 32 * kF32WaveTiles;   // 128
+constexpr int kMaxItemOzaki = 64;                  // item edge of the INT8 (operand-split) form
+constexpr int kOzMaxSlices = 7;                    // digits per operand in that form
 constexpr int kRecThreads = 512;      // recompression workgroup (32 groups of 16 lanes)
 constexpr int kRecLdsBytes = 140 * 1024;  // dynamic LDS for the working set (160 KiB minus bookkeeping)
 constexpr int kJacobiMaxSweeps = 60;
@@ -208,6 +210,10 @@ hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, 
 // Items of the LDS grouped GEMM by decreasing estimated cost (slabs times the
 // busiest wave's tiles, in quarter-octave classes) into order[0 .. nitems).
 hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s);
+// Dense accumulation on INT8 MFMA with `slices` digits per operand (2..7);
+// items of at most kMaxItemOzaki x kMaxItemOzaki.
+hipError_t launch_ggemm_ozaki(const GemmItem* items, const Seg* segs, int nitems, int slices,
+                              hipStream_t s, const int* order = nullptr);
 // Items of the wave-per-item GEMM grouped by their first term's left operand
 // (the dense block of a low-rank x dense product), so that the items reading
 // one block run next to each other: a radix sort of the operand addresses.

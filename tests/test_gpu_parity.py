@@ -475,6 +475,51 @@ def test_mixed_gemm_3d_scaled(ctx, torch):
         assert err <= 10 * wl.tol
 
 
+def test_ozaki_gemm_3d_scaled(ctx, torch):
+    """Dense accumulation on INT8 MFMA by operand splitting: with 7 digits the product meets the
+    FP64 bar against the oracle (ambiguous cuts judged on the exact product); with 4 digits it
+    stays within 10 x tol.  Items are at most 64 x 64, so blocks of 96..160 span several."""
+    log("ozaki gemm 3D scaled")
+    wl = scaled_workload("lattice", 1536, seed=142)
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    Oc = orc.gemm(O, O, wl.tol, wl.eps_sp)
+    E = orc.gemm(O, O, 0.0, wl.eps_sp)
+    C = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision="ozaki", split=7)
+    rep = parity.compare(C, Oc, wl.tol, exact=E)
+    nb = len(wl.sizes) ** 2
+    log(f"  7 digits: err={rep.rel_err:.2e} ambiguous={len(rep.ambiguous)}")
+    parity.assert_parity(rep, FP64_BOUND, nblocks=nb)
+    ref = orc.to_dense(Oc)
+    C4 = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision="ozaki", split=4)
+    got = C4.to_dense().cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    log(f"  4 digits: err={err:.2e}")
+    assert err <= 10 * wl.tol
+
+
+@pytest.mark.parametrize("seed", [171, 172])
+def test_ozaki_gemm_all_kinds_untruncated(ctx, torch, seed):
+    """Every block kind and ragged edges (items cut at 64, partial 16-tiles, inner ranges that
+    end inside a 64-chunk), no truncation: 7 digits against the oracle's product."""
+    import paper_1509_00309_amd as clr
+    log(f"ozaki all kinds seed={seed}")
+    rs, ks, cs = [40, 130, 17, 71], [25, 150, 9, 70, 66], [31, 129, 12]
+    ra = random_blocks(seed, rs, ks, p_zero=0.2, p_dense=0.5, max_rank=8)
+    rb = random_blocks(seed + 50, ks, cs, p_zero=0.2, p_dense=0.5, max_rank=8)
+    A, B = gpu_from_random(ctx, torch, ra), gpu_from_random(ctx, torch, rb)
+    OA, OB = orc_from_random(ra), orc_from_random(rb)
+    C = ctx.gemm(A, B, 0.0, 0.0, precision="ozaki", split=7, alpha=0.7)
+    ref = orc.to_dense(orc.gemm(OA, OB, 0.0, 0.0, alpha=0.7))
+    got = C.to_dense().cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    log(f"  err={err:.2e}")
+    assert err <= 1e-12
+    with pytest.raises(clr.ClrError):
+        ctx.gemm(A, B, 0.0, 0.0, precision="ozaki", split=9)
+
+
 # ---------------------------------------------------------------------------
 # Adjoints
 # ---------------------------------------------------------------------------
