@@ -18,7 +18,8 @@
 // product near FP64 accuracy.
 //
 // Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement, a wave owns the
-// 2 x 2 tiles of 16 x 16 of one 32 x 32 quadrant.  Per chunk: resolve the
+// 2 x 2 tiles of 16 x 16 of one 32 x 32 quadrant; two workgroups per CU, so
+// one's digit expansion and barriers overlap the other's MFMA work.  Per chunk: resolve the
 // inner rows' terms, load and take per-row / per-column maxima, exponents,
 // digit expansion into LDS (16 consecutive inner indices of one row per
 // thread, one 16-byte store per digit), then the MFMA groups.
@@ -47,8 +48,9 @@ struct OzLds {
   const double* rp[kOzK];
   int64_t sli[kOzK], srj[kOzK];
   double scale[kOzK], bok[kOzK];
-  Seg segs[kSegCache];
 };
+// two workgroups per CU (the term descriptors are read through L2, not cached in LDS)
+static_assert(sizeof(OzLds) <= 160 * 1024 / 2, "two workgroups per CU");
 
 // Smallest e with m < 2^e for m > 0; a zero row or column gets 0 (its digits
 // are all zero whatever the exponent).
@@ -83,7 +85,7 @@ __device__ inline void expand(const double (&x)[16], int e, int S, uint32_t (&w)
 
 }  // namespace
 
-__global__ __launch_bounds__(kOzThreads) void k_ggemm_ozaki(const GemmItem* __restrict__ items,
+__global__ __launch_bounds__(kOzThreads, 2) void k_ggemm_ozaki(const GemmItem* __restrict__ items,
                                                            const Seg* __restrict__ segs,
                                                            int nitems,
                                                            const int* __restrict__ order,
@@ -115,8 +117,7 @@ __global__ __launch_bounds__(kOzThreads) void k_ggemm_ozaki(const GemmItem* __re
   const int wave = uni(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
 
-  const int ncache = min(it.nseg, kSegCache);
-  for (int s = tid; s < ncache; s += kOzThreads) sh.segs[s] = segs[it.seg0 + s];
+  const Seg* terms = segs + it.seg0;   // resolve_row's cache, here in global memory
 
   // this thread's operand share: row (L) / column (R) `own`, inner quarter kq
   const int own = tid & 63, kq = tid >> 6;
@@ -133,13 +134,13 @@ __global__ __launch_bounds__(kOzThreads) void k_ggemm_ozaki(const GemmItem* __re
   const int lk = (lane >> 4) * 16;   // first inner byte of this lane's 16
   const int nchunk = (it.ktotal + kOzK - 1) / kOzK;
   for (int c = 0; c < nchunk; ++c) {
-    __syncthreads();   // previous chunk's MFMA reads are done; segment cache written
+    __syncthreads();   // previous chunk's MFMA reads are done
     if (tid < kOzK) {
       const double* lp;
       const double* rp;
       int64_t sli, srj;
       double sc, bok;
-      resolve_row(it, segs, sh.segs, c * (kOzK / kSlabK) + (tid >> 4), tid & 15, cursor, lp, rp,
+      resolve_row(it, segs, terms, c * (kOzK / kSlabK) + (tid >> 4), tid & 15, cursor, lp, rp,
                   sli, srj, sc, bok);
       sh.lp[tid] = lp;
       sh.rp[tid] = rp;
@@ -197,15 +198,14 @@ __global__ __launch_bounds__(kOzThreads) void k_ggemm_ozaki(const GemmItem* __re
     __syncthreads();
 
     // MFMA groups g = p + q < S of this wave's tiles; tiles outside the item
-    // compute on zero digits and are never stored.
-    i4v da[kOzMaxSlices][2], db[kOzMaxSlices][2];
+    // compute on zero digits and are never stored.  The left digits stay in
+    // registers, the right ones are read per product.
+    i4v da[kOzMaxSlices][2];
 #pragma unroll
     for (int p = 0; p < kOzMaxSlices; ++p) {
       if (p < S) {
 #pragma unroll
         for (int a = 0; a < 2; ++a) da[p][a] = *(const i4v*)&sh.la[p][32 * wr + 16 * a + lr][lk];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) db[p][b] = *(const i4v*)&sh.rb[p][32 * wc + 16 * b + lr][lk];
       }
     }
     // output (row 4 (lane / 16) + v, column lane % 16) of each tile: its weight
@@ -226,11 +226,14 @@ __global__ __launch_bounds__(kOzThreads) void k_ggemm_ozaki(const GemmItem* __re
           for (int b = 0; b < 2; ++b) s[a][b] = i4v{0, 0, 0, 0};
 #pragma unroll
         for (int p = 0; p <= g; ++p) {
+          i4v db[2];
+#pragma unroll
+          for (int b = 0; b < 2; ++b) db[b] = *(const i4v*)&sh.rb[g - p][32 * wc + 16 * b + lr][lk];
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
-              s[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(da[p][a], db[g - p][b], s[a][b], 0, 0, 0);
+              s[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(da[p][a], db[b], s[a][b], 0, 0, 0);
         }
         const double wg = ldexp(1.0, -7 * (g + 2));
 #pragma unroll
