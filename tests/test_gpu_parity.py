@@ -499,6 +499,44 @@ def test_ozaki_gemm_3d_scaled(ctx, torch):
     assert err <= 10 * wl.tol
 
 
+def test_ozaki_digit_error_bound(ctx, torch):
+    """Element-wise bound of the operand-split arithmetic.  With every block dense and no
+    truncation, an item's inner range is the plain inner index, cut into 64-wide chunks.  For a
+    chunk scaled by 2^e <= 2 max|x| (rows) and 2^f <= 2 max|y| (columns), S digits leave at
+    most (S + 3) 2^(-7S) 2^(e+f) per inner index (remainders and dropped digit products), so
+        |C_ij - (A B)_ij| <= sum_c 4 * 64 (S + 3) 2^(-7S) max_c|A_i.| max_c|B_.j| + FP64 slack.
+    Entries span four decades, so a wrong digit weight or exponent breaks the bound."""
+    log("ozaki digit error bound")
+    rng = rng_for(181)
+    rs, ks, cs = [64, 50], [100, 92], [64, 30]
+    M, K, N = sum(rs), sum(ks), sum(cs)
+    Ad = rng.standard_normal((M, K)) * 10.0 ** rng.uniform(-2, 2, size=(M, K))
+    Bd = rng.standard_normal((K, N)) * 10.0 ** rng.uniform(-2, 2, size=(K, N))
+    A = ctx.compress(torch.from_numpy(Ad).cuda(), rs, ks, 0.0, 0.0)
+    B = ctx.compress(torch.from_numpy(Bd).cuda(), ks, cs, 0.0, 0.0)
+    for Mx in (A, B):
+        assert np.all(Mx.meta()[0] == 1)
+    ref = Ad @ Bd
+    absprod = np.abs(Ad) @ np.abs(Bd)
+    nch = (K + 63) // 64
+    mx = np.stack([np.abs(Ad[:, 64 * c:64 * c + 64]).max(axis=1) for c in range(nch)], axis=1)
+    my = np.stack([np.abs(Bd[64 * c:64 * c + 64, :]).max(axis=0) for c in range(nch)], axis=0)
+    chunk_bound = mx @ my   # sum over chunks of max|x| max|y|
+    prev = None
+    for S in (2, 4, 7):
+        C = ctx.gemm(A, B, 0.0, 0.0, precision="ozaki", split=S)
+        err = np.abs(C.to_dense().cpu().numpy() - ref)
+        bound = 4 * 64 * (S + 3) * 2.0 ** (-7 * S) * chunk_bound \
+            + (K + 4 * S * nch) * 2.0 ** -53 * absprod
+        worst = float(np.max(err / bound))
+        rel = float(np.linalg.norm(err) / np.linalg.norm(ref))
+        log(f"  S={S}: relative error {rel:.2e}, largest error / bound {worst:.3f}")
+        assert worst <= 1.0
+        if prev is not None:
+            assert rel < prev
+        prev = rel
+
+
 @pytest.mark.parametrize("seed", [171, 172])
 def test_ozaki_gemm_all_kinds_untruncated(ctx, torch, seed):
     """Every block kind and ragged edges (items cut at 64, partial 16-tiles, inner ranges that
