@@ -537,6 +537,37 @@ def test_ozaki_digit_error_bound(ctx, torch):
         prev = rel
 
 
+def test_ozaki_sqrt_inv_line_n512(ctx, torch):
+    """S^-1/2 with every dense accumulation in the operand-split form (7 digits): the same
+    iteration count and the oracle's result to the FP64 iteration's bar."""
+    log("ozaki sqrt_inv line_n512")
+    wl = line_n512()
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=wl.extra["conv_tol"], precision="ozaki")
+    Ow, info = orc.sqrt_inv(O, wl.tol, wl.eps_sp, conv_tol=wl.extra["conv_tol"])
+    assert st.iterations == info.iterations
+    rep = parity.compare(W, Ow, wl.tol)
+    log(f"  iters={st.iterations} explicit={st.explicit_residual:.2e} err={rep.rel_err:.2e}")
+    parity.assert_parity(rep, 1e-11, nblocks=64)
+    assert abs(st.explicit_residual - info.explicit[-1][1]) <= 1e-11
+
+
+def test_ozaki_batch_matches_single_products(ctx, torch):
+    """The operand-split form in a planned batch (one launch per phase) equals the products one
+    by one in the same form, bit for bit."""
+    log("ozaki batch vs single products")
+    ops = _batch_operands(ctx, torch)
+    As, Bs = [a for a, _ in ops], [b for _, b in ops]
+    Cs = ctx.gemm_batch(As, Bs, 1e-8, 1e-10, precision="ozaki")
+    for (A, B), Cb in zip(ops, Cs):
+        C1 = ctx.gemm(A, B, 1e-8, 1e-10, precision="ozaki")
+        assert np.array_equal(Cb.to_dense().cpu().numpy(), C1.to_dense().cpu().numpy())
+        for x, y in zip(Cb.meta(), C1.meta()):
+            assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("seed", [171, 172])
 def test_ozaki_gemm_all_kinds_untruncated(ctx, torch, seed):
     """Every block kind and ragged edges (items cut at 64, partial 16-tiles, inner ranges that
