@@ -754,6 +754,54 @@ def test_tile_edges_and_autotune(ctx, torch):
 # edge, and the adjoint against finite differences and the eigen-gradient
 # ---------------------------------------------------------------------------
 
+def test_construction_rrqr_full_size_sampled(ctx, torch):
+    """The N = 8192 input as the construction leg of bench.py builds it, but generated on the
+    device: 28 sampled blocks of the generated matrix against the host generator, and of the
+    RRQR-compressed matrix against the oracle's column-pivoted QR one block at a time (kind,
+    rank, U^T U = I, V = M^T U, the error bound, and the oracle's reconstruction unless a
+    pivot near-tie or a cut on the threshold separates them)."""
+    log("construction by RRQR, N=8192, sampled blocks")
+    wl = lattice_3d(8192)
+    Sd = wl.dense()
+    G = ctx.kernel_matrix(torch.from_numpy(wl.points).cuda(), "gaussian", wl.a, wl.diag)
+    S = ctx.compress(G, wl.sizes, wl.sizes, wl.tol, 1e-10, method="rrqr")
+    kind, rank, _norm = S.meta()
+    offs = wl.offsets()
+    nb = len(wl.sizes)
+    rng = rng_for(8193)
+    picks = [(i, i) for i in rng.choice(nb, 4, replace=False)]
+    picks += [(i, min(nb - 1, i + 1)) for i in rng.choice(nb, 8, replace=False)]
+    picks += [(int(rng.integers(nb)), int(rng.integers(nb))) for _ in range(16)]
+    same = differ = 0
+    for (i, j) in picks:
+        M = Sd[offs[i]:offs[i + 1], offs[j]:offs[j + 1]]
+        g = G[offs[i]:offs[i + 1], offs[j]:offs[j + 1]].cpu().numpy()
+        assert np.all(np.abs(g - M) <= 4.5e-16 * np.abs(M) + 1e-300)
+        m, n = M.shape
+        nm = np.linalg.norm(M)
+        r, _X, _W, tails = orc.rrqr_truncate(M, wl.tol)
+        want = 0 if nm < 1e-10 else (1 if i == j or 2 * r > min(m, n) else 2)
+        k = int(kind[i, j])
+        if k != want or (k == 2 and int(rank[i, j]) != r):
+            assert any(abs(t - wl.tol * nm) <= 1e-6 * wl.tol * nm for t in tails), \
+                (i, j, k, want, int(rank[i, j]), r)
+            differ += 1
+            continue
+        if k != 2:
+            continue
+        _t, U, V = S.block(i, j, m, n, 2, int(rank[i, j]))
+        U, V = U.cpu().numpy(), V.cpu().numpy()
+        assert np.linalg.norm(U.T @ U - np.eye(U.shape[1])) <= 1e-13 * U.shape[1]
+        assert np.linalg.norm(V - M.T @ U) <= 1e-13 * nm
+        assert np.linalg.norm(M - U @ V.T) <= wl.tol * nm * (1 + 1e-9)
+        if np.linalg.norm(U @ V.T - _X @ _W.T) <= 1e-12 * nm:
+            same += 1
+        else:
+            differ += 1
+    log(f"  {len(picks)} blocks: {same} factored blocks equal to the oracle's, {differ} at ties")
+    assert differ <= 2
+
+
 @pytest.mark.parametrize("name", ["lattice_3d", "lattice_3d_morton", "coulomb_3d_morton"])
 def test_gemm_full_size_sampled(ctx, torch, name):
     """The N = 8192 workloads exactly as bench.py times them (the 3D lattice product and the two
