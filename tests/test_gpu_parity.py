@@ -802,17 +802,18 @@ def test_construction_rrqr_full_size_sampled(ctx, torch):
     assert differ <= 2
 
 
-@pytest.mark.parametrize("name", ["lattice_3d", "lattice_3d_morton", "coulomb_3d_morton"])
-def test_gemm_full_size_sampled(ctx, torch, name):
-    """The N = 8192 workloads exactly as bench.py times them (the 3D lattice product and the two
-    low-rank-regime products); 32 result blocks recomputed one by one by the oracle (kinds, ranks
-    and values)."""
+@pytest.mark.parametrize("name,precision", [("lattice_3d", "fp64"), ("lattice_3d_morton", "fp64"),
+                                            ("coulomb_3d_morton", "fp64"), ("lattice_3d", "ozaki")])
+def test_gemm_full_size_sampled(ctx, torch, name, precision):
+    """The N = 8192 workloads exactly as bench.py times them (the 3D lattice product in the FP64
+    and operand-split forms, and the two low-rank-regime products); 32 result blocks recomputed
+    one by one by the oracle (kinds, ranks and values)."""
     import workloads
-    log(f"gemm full size N=8192 ({name}), sampled blocks")
+    log(f"gemm full size N=8192 ({name}, {precision}), sampled blocks")
     wl = getattr(workloads, name)(8192)
     Sd = wl.dense()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
-    C = ctx.gemm(S, S, wl.tol, wl.eps_sp)
+    C = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision=precision)
     kind, rank, _norm = C.meta()
     Dg = C.to_dense().cpu().numpy()
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
