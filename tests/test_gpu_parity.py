@@ -226,6 +226,15 @@ def test_kernel_matrix_generator(ctx, torch):
     # far entries underflow to zero on both sides
     assert np.all(np.abs(G.cpu().numpy() - ref) <= 4.5e-16 * np.abs(ref) + 1e-300)
 
+    # two dimensions, the Coulomb-like kernel with a diagonal shift, rectangular by columns
+    from workloads import coulomb_block
+    p2 = rng_for(164).uniform(0, 10, size=(200, 2))
+    G = ctx.kernel_matrix(torch.from_numpy(p2).cuda(), "coulomb", 0.7, 0.3,
+                          col_points=torch.from_numpy(p2[:150]).cuda())
+    ref = coulomb_block(p2, p2[:150], 0.7)
+    ref[np.arange(150), np.arange(150)] += 0.3
+    assert G.shape == (200, 150) and np.array_equal(G.cpu().numpy(), ref)
+
     # argument errors are reported, nothing is launched
     with pytest.raises(clr.ClrError):
         ctx.kernel_matrix(pts, "coulomb", 0.0, 0.1)
