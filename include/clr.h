@@ -68,7 +68,7 @@ typedef enum { CLR_COMPRESS_SVD = 0, CLR_COMPRESS_RRQR = 1 } clr_compression;
 
 /* Kernels of clr_kernel_matrix: the overlap-like exp(-a r^2) and the
  * Coulomb-like 1 / sqrt(r^2 + a^2) stand-ins for the paper's test matrices
- * (Sec. 5: overlap and Coulomb matrices of water clusters).                  */
+ * (Sec. 4.2: overlap and Coulomb matrices of water clusters).                */
 typedef enum { CLR_KERNEL_GAUSSIAN = 0, CLR_KERNEL_COULOMB = 1 } clr_kernel;
 
 /* Screening threshold tau of a result block (I, J) of size m x n (Sec. 4.1,
@@ -283,7 +283,14 @@ clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const clr_matrix*
  * clr_plan_create allocates the nprod outputs C[p] (owned by the caller, freed
  * with clr_destroy) and the plan's own work buffers.  A, B and C must stay
  * alive, with unchanged block structure (kinds and ranks), while the plan is
- * executed; their values may change between executions.  With use_graph != 0
+ * executed.  Screening, the block products and the accumulation paths are
+ * fixed at planning time from the block norms the operands have then: an
+ * execution computes the values of the planned blocks from the operands'
+ * current factors (recompression and truncation are redone from those
+ * values), so it equals clr_gemm of the current operands whenever their block
+ * norms are the planning-time ones, for instance after the factors are
+ * rewritten with values of the same norms.  Operands whose norms changed
+ * need a new plan.  With use_graph != 0
  * the execution phase is recorded once as a HIP graph on the context stream
  * and clr_plan_execute replays it.  clr_plan_execute writes C and, if st is
  * given, aggregated counts and flops and the device time of the execution

@@ -183,8 +183,12 @@ class Context:
 
     def sqrt_inv(self, S: "CLRMatrix", tol: float, eps_sp: float, conv_tol: float = 1e-10,
                  max_iter: int = 50, fixed_iters: int = 0, alpha: float = 0.0, screen="abs",
-                 precision="fp64", split: int = 0, allow_not_converged: bool = True):
-        """W = S^-1/2 (Newton-Schulz, Eqs. (8)-(11)); returns (W, SqrtInvStats)."""
+                 precision="fp64", split: int = 0, allow_not_converged: bool = False):
+        """W = S^-1/2 (Newton-Schulz, Eqs. (8)-(11)); returns (W, SqrtInvStats).
+
+        An iteration that stops without meeting conv_tol raises ClrError
+        (CLR_ERR_NOT_CONVERGED) unless allow_not_converged is set; then W is
+        returned and SqrtInvStats.converged is 0."""
         o = SqrtInvOpts()
         o.g = _gemm_opts(tol, eps_sp, screen, precision, split, 1.0)
         o.alpha = float(alpha)

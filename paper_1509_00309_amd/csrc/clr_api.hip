@@ -919,8 +919,8 @@ extern "C" clr_status clr_set_dense_certificate(clr_context* ctx, int enable) {
   return CLR_OK;
 }
 
-// Factorisation used by clr_compress (the paper builds its input blocks by
-// rank-revealing QR, Sec. 4.1; products keep the truncated SVD).
+// Dense overlap-like or Coulomb-like kernel matrix on the device: the input
+// that clr_compress turns into a CLR matrix.
 extern "C" clr_status clr_kernel_matrix(clr_context* ctx, const double* row_points,
                                         int64_t nrows, const double* col_points, int64_t ncols,
                                         int dim, int kernel, double a, double diag, double* out,
@@ -943,6 +943,8 @@ extern "C" clr_status clr_kernel_matrix(clr_context* ctx, const double* row_poin
   return CLR_OK;
 }
 
+// Factorisation used by clr_compress (the paper builds its input blocks by
+// rank-revealing QR, Sec. 4.1; products keep the truncated SVD).
 extern "C" clr_status clr_set_compression(clr_context* ctx, int method) {
   if (!ctx) return CLR_ERR_INVALID_ARG;
   if (method != CLR_COMPRESS_SVD && method != CLR_COMPRESS_RRQR)

@@ -289,3 +289,115 @@ def pin_dense_limit(orc):
     C = orc.to_dense(orc.gemm(S, S, tol=0.0, eps_sp=0.0))
     ref = Sd @ Sd
     return float(np.sqrt(np.sum((C - ref) ** 2)) / np.sqrt(np.sum(ref ** 2)))
+
+
+def pin_default_alpha(orc):
+    """alpha = 1 / max_I sum_J ||S_IJ||_F (the block-Gershgorin reading of Sec. 4.2's condition
+    ||alpha S - I||_2 <= 1), on hand-set block norms whose row sums (3.75, 2.5, 4.0) and column
+    sums (4.5, 2.0, 3.75) differ, so a column-sum, a max-norm or a smaller alpha all fail.
+    Returns |alpha - 1/4|; the exact value is a power of two, so the check is exact."""
+    def blk(v):
+        return orc.Block("D", D=np.array([[v]]), norm=abs(v))
+    blocks = {(0, 0): blk(1.0), (0, 1): blk(2.0), (0, 2): blk(0.75),
+              (1, 0): blk(-0.5), (1, 2): blk(2.0),
+              (2, 0): blk(3.0), (2, 2): blk(-1.0)}
+    S = orc.OMatrix([1, 1, 1], [1, 1, 1], blocks)
+    return abs(orc.default_alpha(S) - 0.25)
+
+
+def pin_screening_area(orc, seed=19):
+    """Per-area screening (tau = eps_sp * m * n, the paper's literal threshold of Sec. 4.1): with
+    blocks of very different areas, the kept blocks are exactly those whose norm estimate is at
+    least eps_sp * m * n (brute force over all pairs), and a kept block equals the exact sum."""
+    rows, inner, cols = [2, 9, 4, 12], [5, 3, 8], [11, 2, 6, 3]
+    ra = random_blocks(seed, rows, inner, p_zero=0.1, scale_decay=2.0)
+    rb = random_blocks(seed + 1, inner, cols, p_zero=0.1, scale_decay=2.0)
+    A = orc.from_factors(ra.row_sizes, ra.col_sizes, ra.kind, ra.f0, ra.f1)
+    B = orc.from_factors(rb.row_sizes, rb.col_sizes, rb.kind, rb.f0, rb.f1)
+    Ad, Bd = dense_from_factors(ra), dense_from_factors(rb)
+    ro = np.concatenate([[0], np.cumsum(rows)])
+    co = np.concatenate([[0], np.cumsum(cols)])
+    ko = np.concatenate([[0], np.cumsum(inner)])
+    est = np.zeros((len(rows), len(cols)))
+    for i in range(len(rows)):
+        for j in range(len(cols)):
+            for k in range(len(inner)):
+                na = float(np.sqrt(np.sum(Ad[ro[i]:ro[i + 1], ko[k]:ko[k + 1]] ** 2)))
+                nb = float(np.sqrt(np.sum(Bd[ko[k]:ko[k + 1], co[j]:co[j + 1]] ** 2)))
+                est[i, j] += na * nb
+    area = np.outer(rows, cols).astype(float)
+    # a threshold per unit area that separates the blocks: the median of est / area
+    eps = float(np.median(est / area))
+    C = orc.gemm(A, B, tol=0.0, eps_sp=eps, screen="area")
+    worst = 0.0
+    nkept = 0
+    for i in range(len(rows)):
+        for j in range(len(cols)):
+            want = est[i, j] >= eps * area[i, j]
+            exact = Ad[ro[i]:ro[i + 1]] @ Bd[:, co[j]:co[j + 1]]
+            nrm = float(np.sqrt(np.sum(exact ** 2)))
+            want = want and nrm >= eps * area[i, j]      # dropped after compute if below tau
+            if ((i, j) in C.blocks) != want:
+                return math.inf
+            if want:
+                nkept += 1
+                d = C.blocks[(i, j)].dense() - exact
+                worst = max(worst, float(np.sqrt(np.sum(d ** 2))) / nrm)
+    if nkept == 0 or nkept == len(rows) * len(cols):
+        return math.inf   # the case must screen some blocks and keep others
+    return worst
+
+
+def ns_scalar_residuals(lam, alpha, iters):
+    """Internal residuals of Eqs. (8)-(11) for diagonal S = diag(lam): x_n = alpha lam z_n^2
+    (X_n = alpha Y_n Z_n with Y_n = lam z_n for diagonal iterates), and the explicit residual of
+    W = sqrt(alpha) z_{n+1}: sqrt(mean((alpha lam z_{n+1}^2 - 1)^2))."""
+    lam = np.asarray(lam, dtype=np.float64)
+    z = np.ones_like(lam)
+    internal, explicit = [], []
+    for _ in range(iters):
+        x = alpha * lam * z * z
+        internal.append(float(np.sqrt(np.mean((x - 1.0) ** 2))))
+        z = z * (15.0 - 10.0 * x + 3.0 * x * x) / 8.0
+        explicit.append(float(np.sqrt(np.mean((alpha * lam * z * z - 1.0) ** 2))))
+    return internal, explicit
+
+
+def pin_stop_statuses(orc):
+    """The stopping rule (reading C9 of Sec. 4.2's iteration) on cases whose outcome is fixed by
+    the scalar recurrence, not by rounding:
+      converged: diagonal S, no truncation; the run stops after the first iteration whose
+        internal residual is <= conv_tol (its explicit residual is then far below conv_tol);
+      diverged: alpha = 2.5 / lambda_max, outside ||alpha S - I||_2 <= 1, so x p(x)^2 grows
+        without bound from x = 2.5 (p(2.5) > 1); stops after the third iteration;
+      stalled: a 1-D overlap-like matrix truncated at tol 1e-4 per product with an unreachable
+        target (conv_tol 1e-15): the truncation keeps W's explicit residual near 1e-5, and the
+        internal residual settles at its own floor and grows in two consecutive iterations.
+    Returns a list of (case, ok, detail)."""
+    out = []
+    lam = [0.2, 0.5, 0.9, 1.3, 1.7, 0.35]
+    sizes = [2, 3, 1]
+    S = orc.compress(np.diag(lam), sizes, sizes, tol=0.0, drop=0.0)
+    alpha = 0.5
+    conv = 1e-10
+    internal, explicit = ns_scalar_residuals(lam, alpha, 30)
+    n_stop = next(i for i, r in enumerate(internal) if r <= conv)
+    clear = internal[n_stop] < 0.1 * conv and (n_stop == 0 or internal[n_stop - 1] > 10 * conv) \
+        and explicit[n_stop] < 0.1 * conv
+    _W, info = orc.sqrt_inv(S, 0.0, 0.0, conv_tol=conv, alpha=alpha)
+    out.append(("converged", clear and info.status == "converged" and info.iterations == n_stop + 1,
+                (info.status, info.iterations, n_stop + 1)))
+    _W, info = orc.sqrt_inv(S, 0.0, 0.0, conv_tol=conv, alpha=2.5 / max(lam))
+    out.append(("diverged", info.status == "diverged" and info.iterations == 3,
+                (info.status, info.iterations)))
+    from workloads import kernel_matrix, points_1d
+    Sd = kernel_matrix(points_1d(rng_for(22), 96, 1.0, 0.2), 0.5, 0.1)
+    S2 = orc.compress(Sd, [16] * 6, [16] * 6, 1e-4, 1e-12)
+    W, info = orc.sqrt_inv(S2, 1e-4, 1e-12, conv_tol=1e-15)
+    Wd, Sc = orc.to_dense(W), orc.to_dense(S2)
+    expl = float(np.sqrt(np.sum((Wd @ Sc @ Wd - np.eye(96)) ** 2)) / math.sqrt(96))
+    r = info.internal
+    grew = len(r) >= 3 and r[-1] > r[-2] > r[-3] and r[-1] < 0.5
+    out.append(("stalled", info.status == "stalled" and expl > 1e-6 and grew,
+                (info.status, info.iterations, expl)))
+    return out

@@ -70,6 +70,23 @@ def test_alpha_gershgorin_bound():
     assert np.max(np.abs(a * lam - 1.0)) <= 1.0
 
 
+def test_default_alpha_hand_value():
+    """alpha of hand-set block norms: 1 / max row sum = 1/4 exactly (not a column sum, not smaller)."""
+    assert pins.pin_default_alpha(orc) == 0.0
+
+
+def test_screening_area_brute_force():
+    """Per-area screening (tau = eps_sp m n): kept blocks are exactly the brute-force ones."""
+    assert pins.pin_screening_area(orc) < 1e-13
+
+
+@pytest.mark.parametrize("case", ["converged", "diverged", "stalled"])
+def test_stop_statuses(case):
+    res = {name: (ok, detail) for name, ok, detail in pins.pin_stop_statuses(orc)}
+    ok, detail = res[case]
+    assert ok, detail
+
+
 def test_compress_rules_line_n512():
     """Drop below 1e-10, diagonal blocks dense, off-diagonal truncated; dense iff 2r > min."""
     wl = line_n512()
@@ -242,6 +259,24 @@ def _dropped_term(mod):
     mod.combine = comb
 
 
+def _alpha_column_sums(mod):
+    def da(S):
+        cols = np.zeros(S.ncb)
+        for (_i, j), b in S.blocks.items():
+            cols[j] += b.norm
+        return 1.0 / float(np.max(cols))
+    mod.default_alpha = da
+
+
+def _alpha_smaller(mod):
+    orig = mod.default_alpha
+    mod.default_alpha = lambda S: 0.5 * orig(S)
+
+
+def _area_as_abs(mod):
+    mod.block_tau = lambda eps, m, n, screen: eps   # per-area mode ignored
+
+
 MUTANTS = {
     "ld-operand": _wrong_ld,
     "ll-core-transpose": _wrong_absorb,
@@ -249,6 +284,9 @@ MUTANTS = {
     "ns-sign": _wrong_ns_sign,
     "screen-threshold": _wrong_screen,
     "dropped-term": _dropped_term,
+    "alpha-column-sums": _alpha_column_sums,
+    "alpha-smaller": _alpha_smaller,
+    "area-screen-as-abs": _area_as_abs,
 }
 
 
@@ -261,6 +299,8 @@ def _pins_pass(mod):
         lambda: pins.pin_screening(mod) < 1e-12,
         lambda: pins.pin_ns_coefficients(mod) < 1e-15,
         lambda: pins.pin_ns_diagonal(mod) < 1e-13,
+        lambda: pins.pin_default_alpha(mod) == 0.0,
+        lambda: pins.pin_screening_area(mod) < 1e-13,
     ]
     for c in checks:
         try:
