@@ -52,6 +52,8 @@ __device__ inline int64_t uni64(int64_t v) {
 }
 
 constexpr int kSegCache = 96;  // segment descriptors of an item kept in LDS
+typedef const Seg __attribute__((address_space(1))) gseg;   // descriptors in global memory
+typedef const Seg __attribute__((address_space(3))) lseg;   // descriptors cached in LDS
 
 // Wave grid and tiles of the LDS kernel per precision: WR x WC waves, a wave
 // owns up to TA x TB of the TILES x TILES tiles of 16 x 16.
@@ -82,7 +84,6 @@ struct GemmLds {
   int64_t sli[2][kSlabK];
   int64_t srj[2][kSlabK];
   double scale[2][kSlabK];   // L scale of the row; 0 for rows past the item
-  double bok[2][kSlabK];     // 1 for R rows inside the item, 0 past it
   Seg segs[kSegCache];
 };
 
@@ -91,8 +92,12 @@ struct GemmLds {
 // (monotone over slabs).  The first kSegCache descriptors come from LDS.  A
 // row past the item gets the first segment's operands with zero strides and
 // zero weights, so every address the loader forms is valid.
+// CacheP is the type of the cached-descriptor pointer: an LDS-qualified
+// pointer in the LDS kernel (so its loads stay LDS loads), a plain pointer
+// where the "cache" is global memory.
+template <typename CacheP>
 __device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ segs,
-                                   const Seg* cache, int slab, int t, int& cur,
+                                   CacheP cache, int slab, int t, int& cur,
                                    const double*& lp, const double*& rp, int64_t& sli,
                                    int64_t& srj, double& sc, double& bok) {
   const int g = slab * kSlabK + t;
@@ -103,29 +108,55 @@ __device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ s
   sc = 0.0;
   bok = 0.0;
   if (g >= it.ktotal) return;
+  // The cached descriptors and the global ones are read on separate paths, so
+  // each load keeps its own address space (a pointer selected between the two
+  // would be generic, and flat loads also wait on the global-load counter).
   while (cur < it.nseg) {
-    const Seg& s = cur < kSegCache ? cache[cur] : segs[it.seg0 + cur];
-    if (g < s.kbase + s.k) break;
+    int kend;
+    if (cur < kSegCache) {
+      kend = cache[cur].kbase + cache[cur].k;
+    } else {
+      const gseg* sg = (const gseg*)(segs + it.seg0 + cur);
+      kend = sg->kbase + sg->k;
+    }
+    if (g < kend) break;
     ++cur;
   }
   if (cur >= it.nseg) return;
-  const Seg& s = cur < kSegCache ? cache[cur] : segs[it.seg0 + cur];
-  const int kl = g - s.kbase;
-  lp = s.L + (int64_t)it.row0 * s.sLi + (int64_t)kl * s.sLk;
-  rp = s.R + (int64_t)it.col0 * s.sRj + (int64_t)kl * s.sRk;
-  sli = s.sLi;
-  srj = s.sRj;
-  sc = s.scale;
+  const double* L;
+  const double* R;
+  int64_t sLi, sLk, sRk, sRj;
+  int kbase;
+  double scale;
+  if (cur < kSegCache) {
+    const auto& s = cache[cur];
+    L = s.L; R = s.R; sLi = s.sLi; sLk = s.sLk; sRk = s.sRk; sRj = s.sRj; kbase = s.kbase;
+    scale = s.scale;
+  } else {
+    const gseg& s = *(const gseg*)(segs + it.seg0 + cur);
+    L = s.L; R = s.R; sLi = s.sLi; sLk = s.sLk; sRk = s.sRk; sRj = s.sRj; kbase = s.kbase;
+    scale = s.scale;
+  }
+  const int kl = g - kbase;
+  lp = L + (int64_t)it.row0 * sLi + (int64_t)kl * sLk;
+  rp = R + (int64_t)it.col0 * sRj + (int64_t)kl * sRk;
+  sli = sLi;
+  srj = sRj;
+  sc = scale;
   bok = 1.0;
 }
 
 // MFMA work of one LDS slab for a wave that owns NA x NB valid tiles
 // (tile rows wr + WR a, tile columns wc + WC b).  The tile counts are
-// template constants so the body is straight-line code.
-template <bool F32, bool SPLIT, int NA, int NB>
+// template constants so the body is straight-line code.  `mid(q)` runs after
+// the MFMAs of 4-step q are issued: the staging stores of the next slab go
+// there, so they execute while the matrix pipe works through those MFMAs
+// (the scheduling barriers keep the compiler from moving them back behind the
+// whole chain).
+template <bool F32, bool SPLIT, int NA, int NB, typename Mid>
 __device__ __attribute__((always_inline)) inline void slab_mfma(
     GemmLds<F32>& sh, int cur, int wr, int wc, int kr, int lc,
-    d4 (&acc)[GemmCfg<F32>::TA][GemmCfg<F32>::TB]) {
+    d4 (&acc)[GemmCfg<F32>::TA][GemmCfg<F32>::TB], Mid&& mid) {
   constexpr int WR = GemmCfg<F32>::WR, WC = GemmCfg<F32>::WC;
   if constexpr (!F32) {
     // operands of 4-step q + 1 are read from LDS while the MFMAs of q run
@@ -151,6 +182,9 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(
         for (int b = 0; b < NB; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q & 1][a], bv[q & 1][b], acc[a][b], 0,
                                                              0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      mid(q);
+      __builtin_amdgcn_sched_barrier(0);
     }
   } else {
     f4 p[NA][NB];
@@ -191,6 +225,9 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(
             pl[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[a], bv[b], pl[a][b], 0, 0, 0);
           }
       }
+      __builtin_amdgcn_sched_barrier(0);
+      mid(q);
+      __builtin_amdgcn_sched_barrier(0);
     }
     // FP64 flush of this slab's FP32 partials
 #pragma unroll
@@ -208,6 +245,14 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(
 
 // Main loop and epilogue of one item for a wave that owns NA x NB valid
 // tiles (0 x 0 for waves with nothing to compute; they still stage operands).
+//
+// Pipeline over 16-deep slabs with one barrier per slab.  While the MFMAs of
+// slab s read LDS buffer s & 1, the staging registers, which hold slab s + 1
+// (loaded during slab s - 1), are written to the other buffer between the
+// MFMA steps: the L values after the first 4-step, the R values after the
+// second.  Right after each store the same registers receive the global loads
+// of slab s + 2.  Every load thus has a whole slab of MFMA work to land, and
+// the staging stores run while the matrix pipe is busy instead of after it.
 template <bool F32, bool SPLIT, int NA, int NB>
 __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
                                                                 const GemmItem& it,
@@ -216,6 +261,7 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
   using CF = GemmCfg<F32>;
   constexpr int WR = CF::WR, WC = CF::WC;
   constexpr int TM = GemmLds<F32>::TM;
+  constexpr int LD = GemmLds<F32>::LD;
   constexpr int NE = TM / 32;  // staged elements per thread and operand
   static_assert(kSlabK == 16 && kLdsGemmThreads == 512, "staging map assumes 16 x 32 threads");
   const int tid = threadIdx.x;
@@ -229,21 +275,20 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
     for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
   int cursor = 0;  // meaningful for tid < 16 only
-  double ra[NE], rb[NE];
-
-  auto resolve = [&](int slab, int buf) {
+  // Inner row `tid` of slab `slab`: its operand pointers, strides and scale
+  // go to descriptor buffer `d` (two buffers, by slab parity).
+  auto resolve = [&](int slab, int d) {
     if (tid < kSlabK) {
       const double* lp;
       const double* rp;
       int64_t sli, srj;
       double sc, bok;
-      resolve_row(it, segs, sh.segs, slab, tid, cursor, lp, rp, sli, srj, sc, bok);
-      sh.lp[buf][tid] = lp;
-      sh.rp[buf][tid] = rp;
-      sh.sli[buf][tid] = sli;
-      sh.srj[buf][tid] = srj;
-      sh.scale[buf][tid] = sc;
-      sh.bok[buf][tid] = bok;
+      resolve_row(it, segs, (lseg*)sh.segs, slab, tid, cursor, lp, rp, sli, srj, sc, bok);
+      sh.lp[d][tid] = lp;
+      sh.rp[d][tid] = rp;
+      sh.sli[d][tid] = sli;
+      sh.srj[d][tid] = srj;
+      sh.scale[d][tid] = sc;
     }
   };
   // Staging map: every thread serves one inner row t of the slab and the
@@ -253,80 +298,107 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
   // so 16 lanes read 16 consecutive inner indices.  The map is fixed per slab
   // from row 0 and a thread needs one descriptor per operand and slab.
   //
-  // Global -> registers without branches: an element outside the item (row
-  // or column beyond m / n, or an inner row past the last segment) reads a
-  // valid address of the same row instead; validity and the segment scale are
-  // applied when the registers go to LDS, so the loads stay in flight across
-  // the MFMA work of the current slab.
-  auto load = [&](int buf) {
-    const bool arow = uni(sh.sli[buf][0] == 1);
-    const bool brow = uni(sh.srj[buf][0] == 1);
+  // Global -> registers without branches or selects: an element past the
+  // item's m rows (n columns) reads row m - 1 (column n - 1) instead.  Such an
+  // element only enters output rows (columns) that are never stored, so its
+  // value does not matter.  An inner row past the item's last term reads the
+  // first term's operands with zero strides and scale 0, so its L values
+  // become exact zeros (the R values are finite) and it adds nothing.
+  double ra[NE], rb[NE];
+  int aoff = 0, boff = 0;   // LDS offsets (inner row * LD + first element) of the staged values
+  double sc = 0.0;          // term scale of the thread's L row
+  auto load_a = [&](int d) {
+    const bool arow = uni(sh.sli[d][0] == 1);
     const int ta = arow ? tid >> 5 : tid & 15;
     const int ia0 = arow ? tid & 31 : tid >> 4;
+    gdouble* pa = as_global(sh.lp[d][ta]);
+    const int sa = (int)sh.sli[d][ta];
+    const int mlast = it.m - 1;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) ra[u] = pa[min(ia0 + 32 * u, mlast) * sa];
+    aoff = ta * LD + ia0;
+    sc = sh.scale[d][ta];
+  };
+  auto load_b = [&](int d) {
+    const bool brow = uni(sh.srj[d][0] == 1);
     const int tb = brow ? tid >> 5 : tid & 15;
     const int ib0 = brow ? tid & 31 : tid >> 4;
-    const double* pa = sh.lp[buf][ta];
-    const int sa = (int)sh.sli[buf][ta];
-    const double* pb = sh.rp[buf][tb];
-    const int sb = (int)sh.srj[buf][tb];
+    gdouble* pb = as_global(sh.rp[d][tb]);
+    const int sb = (int)sh.srj[d][tb];
+    const int nlast = it.n - 1;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) rb[u] = pb[min(ib0 + 32 * u, nlast) * sb];
+    boff = tb * LD + ib0;
+  };
+  auto store_a = [&](int buf) {
+    auto* dst = &sh.a[buf][0][0] + aoff;
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
-      const int i = ia0 + 32 * u;
-      const int j = ib0 + 32 * u;
-      ra[u] = *as_global(pa + ((i < it.m) ? i : 0) * sa);
-      rb[u] = *as_global(pb + ((j < it.n) ? j : 0) * sb);
+      const double xa = ra[u] * sc;
+      if constexpr (F32) {
+        const float ha = (float)xa;
+        dst[32 * u] = ha;
+        if constexpr (SPLIT) (&sh.alo[buf][0][0] + aoff)[32 * u] = (float)(xa - (double)ha);
+      } else {
+        dst[32 * u] = xa;
+      }
     }
   };
-  auto store = [&](int buf) {
-    const bool arow = uni(sh.sli[buf][0] == 1);
-    const bool brow = uni(sh.srj[buf][0] == 1);
-    const int ta = arow ? tid >> 5 : tid & 15;
-    const int ia0 = arow ? tid & 31 : tid >> 4;
-    const int tb = brow ? tid >> 5 : tid & 15;
-    const int ib0 = brow ? tid & 31 : tid >> 4;
-    const double sc = sh.scale[buf][ta];   // 0 for rows past the item
-    const double bk = sh.bok[buf][tb];     // 0 for rows past the item
+  auto store_b = [&](int buf) {
+    auto* dst = &sh.b[buf][0][0] + boff;
 #pragma unroll
     for (int u = 0; u < NE; ++u) {
-      const int i = ia0 + 32 * u;
-      const int j = ib0 + 32 * u;
-      const bool va = (i < it.m) & (sc != 0.0);
-      const bool vb = (j < it.n) & (bk != 0.0);
-      const double xa = va ? ra[u] * sc : 0.0;
-      const double xb = vb ? rb[u] : 0.0;
+      const double xb = rb[u];
       if constexpr (F32) {
-        const float ha = (float)xa, hb = (float)xb;
-        sh.a[buf][ta][i] = ha;
-        sh.b[buf][tb][j] = hb;
-        if constexpr (SPLIT) {
-          sh.alo[buf][ta][i] = (float)(xa - (double)ha);
-          sh.blo[buf][tb][j] = (float)(xb - (double)hb);
-        }
+        const float hb = (float)xb;
+        dst[32 * u] = hb;
+        if constexpr (SPLIT) (&sh.blo[buf][0][0] + boff)[32 * u] = (float)(xb - (double)hb);
       } else {
-        sh.a[buf][ta][i] = xa;
-        sh.b[buf][tb][j] = xb;
+        dst[32 * u] = xb;
       }
     }
   };
 
-  if (nslab > 0) {
-    resolve(0, 0);
-    __syncthreads();
-    load(0);
-    store(0);
-    if (nslab > 1) resolve(1, 1);
-    __syncthreads();
-  }
-
   const int kr = lane >> 4;   // inner row within a 4-step
   const int lc = lane & 15;   // row (A) / column (B) within a tile
-  for (int s = 0; s < nslab; ++s) {
-    const int cur = s & 1, nxt = cur ^ 1;
-    if (s + 1 < nslab) load(nxt);
-    if constexpr (NA > 0 && NB > 0) slab_mfma<F32, SPLIT, NA, NB>(sh, cur, wr, wc, kr, lc, acc);
-    if (s + 1 < nslab) store(nxt);
-    if (s + 2 < nslab) resolve(s + 2, cur);
+  if (nslab > 0) {
+    resolve(0, 0);
+    if (nslab > 1) resolve(1, 1);
     __syncthreads();
+    load_a(0);
+    load_b(0);
+    store_a(0);
+    store_b(0);
+    if (nslab > 1) {
+      load_a(1);
+      load_b(1);
+    }
+    __syncthreads();                 // buffer 0 holds slab 0; descriptors 0 and 1 consumed
+    if (nslab > 2) resolve(2, 0);
+    __syncthreads();
+    for (int s = 0; s < nslab; ++s) {
+      const int cur = s & 1, nxt = cur ^ 1;
+      // descriptors of slab s + 2 sit in buffer s & 1, those of s + 1 were consumed
+      if (s + 3 < nslab) resolve(s + 3, nxt);
+      const bool st_next = s + 1 < nslab, ld_next = s + 2 < nslab;
+      auto mid = [&](int q) {
+        if (q == 0 && st_next) {
+          store_a(nxt);
+          if (ld_next) load_a(cur);
+        }
+        if (q == 1 && st_next) {
+          store_b(nxt);
+          if (ld_next) load_b(cur);
+        }
+      };
+      if constexpr (NA > 0 && NB > 0) {
+        slab_mfma<F32, SPLIT, NA, NB>(sh, cur, wr, wc, kr, lc, acc, mid);
+      } else {
+        mid(0);
+        mid(1);
+      }
+      __syncthreads();
+    }
   }
 
   // epilogue (output layout per precision, see the header comment).  The
