@@ -232,6 +232,18 @@ clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const clr_sqrtinv
 /* ||X - I||_F / sqrt(N) of a square-blocked matrix (host result). */
 clr_status clr_identity_residual(clr_context* ctx, const clr_matrix* X, double* out);
 
+/* The same residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * writes ||X - I||_F / sqrt(N) to out[0] (device, one double, caller-owned) on
+ * the context stream, without allocating and without synchronising.  The
+ * per-block terms go to a fixed device array of 65536 doubles (512 KiB) that
+ * every device the library runs on keeps until the process ends; X may have at
+ * most 65536 blocks (else CLR_ERR_CAPACITY, nothing launched).  All calls on one
+ * device share that array and overwrite it: calls that overlap on a device
+ * (different streams or contexts without ordering between them) race, and the
+ * caller must order them.  Errors as clr_identity_residual. */
+clr_status clr_identity_residual_noalloc(clr_context* ctx, const clr_matrix* X, double* out);
+
 /* ---- adjoints (truncation treated as the identity) ------------------------ */
 
 /* Given dC (device, dense rows(A) x cols(B), column-major, leading dimension

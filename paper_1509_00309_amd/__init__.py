@@ -293,6 +293,16 @@ class Context:
         self._check(lib.clr_identity_residual(self._h, X._h, C.byref(out)))
         return out.value
 
+    def identity_residual_noalloc(self, X: "CLRMatrix", out):
+        """||X - I||_F / sqrt(N) written to out[0] (a caller-owned float64 cuda tensor) on the
+        context stream, with no allocation inside the library (see clr.h)."""
+        torch = _torch()
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 1:
+            raise TypeError("out must be a float64 cuda tensor with at least one element")
+        self._check(lib.clr_identity_residual_noalloc(self._h, X._h, C.c_void_p(out.data_ptr())))
+        return out
+
+
 
 class Plan:
     """A planned batch of products (optionally recorded as a HIP graph)."""

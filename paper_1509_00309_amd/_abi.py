@@ -31,7 +31,7 @@ EXPORTS = [
     "clr_context_create", "clr_context_destroy", "clr_last_error", "clr_status_string",
     "clr_create", "clr_compress", "clr_destroy", "clr_matrix_info", "clr_get_meta",
     "clr_get_block", "clr_to_dense", "clr_gemm", "clr_axpby", "clr_sqrt_inv",
-    "clr_identity_residual", "clr_gemm_backward", "clr_sqrt_inv_backward",
+    "clr_identity_residual", "clr_identity_residual_noalloc", "clr_gemm_backward", "clr_sqrt_inv_backward",
     "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
     "clr_set_tile_edges", "clr_autotune", "clr_set_dense_certificate", "clr_set_compression",
     "clr_kernel_matrix",
@@ -107,6 +107,7 @@ def _load():
         "clr_axpby": [P, D, P, D, P, D, C.POINTER(GemmOpts), C.POINTER(P)],
         "clr_sqrt_inv": [P, P, C.POINTER(SqrtInvOpts), C.POINTER(P), C.POINTER(SqrtInvStats)],
         "clr_identity_residual": [P, P, DP],
+        "clr_identity_residual_noalloc": [P, P, P],
         "clr_gemm_backward": [P, P, P, D, P, I64, P, I64, P, I64],
         "clr_sqrt_inv_backward": [P, P, C.POINTER(SqrtInvOpts), C.c_int, C.c_int, P, P, I64,
                                   C.POINTER(P)],

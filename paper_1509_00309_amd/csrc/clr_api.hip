@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -90,6 +91,35 @@ struct clr_matrix {
 namespace {
 
 constexpr int kMaxBlockEdge = 512;
+
+// Device memory of clr_identity_residual_noalloc: the per-block terms of the
+// residual, at most kNoAllocMaxBlocks of them.  Every device the library runs
+// on holds its own copy for the life of the process.  Host code never uses the
+// array's name as an address: its device address is looked up once per device
+// (noalloc_setup, at context creation) and kept in noalloc_ptr.
+constexpr int64_t kNoAllocMaxBlocks = 65536;
+static __device__ __align__(256) double noalloc_scratch[kNoAllocMaxBlocks];
+constexpr int kMaxDevices = 256;
+std::mutex noalloc_mu;
+double* noalloc_ptr[kMaxDevices] = {};
+
+// With `device` current: record the device address of noalloc_scratch.
+hipError_t noalloc_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (noalloc_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+  if (e != hipSuccess) return e;
+  noalloc_ptr[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* noalloc_terms(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  return noalloc_ptr[device];
+}
 
 clr_status fail(clr_context* ctx, clr_status s, const char* fmt, ...) {
   if (ctx) {
@@ -429,7 +459,7 @@ extern "C" clr_status clr_context_create(clr_context** ctx, void* stream) {
   if (!ctx) return CLR_ERR_INVALID_ARG;
   *ctx = nullptr;
   clr_context* c = new clr_context();
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess || noalloc_setup(c->device) != hipSuccess) {
     delete c;
     return CLR_ERR_HIP;
   }
@@ -1506,6 +1536,24 @@ extern "C" clr_status clr_identity_residual(clr_context* ctx, const clr_matrix* 
   double s = 0.0;
   for (double v : t) s += v;
   *out = sqrt(s) / sqrt((double)X->rows);
+  return CLR_OK;
+}
+
+// Allocation-free form of the above: the per-block terms go to the device's
+// fixed array and the sum is taken on the device, so nothing is allocated and
+// the host does not wait.
+extern "C" clr_status clr_identity_residual_noalloc(clr_context* ctx, const clr_matrix* X,
+                                                   double* out) {
+  if (!ctx || !X || !out) return CLR_ERR_INVALID_ARG;
+  if (!X->square_blocked()) return fail(ctx, CLR_ERR_SHAPE, "identity residual needs a square blocking");
+  const int64_t nb = (int64_t)X->nrb * X->ncb;
+  if (nb > kNoAllocMaxBlocks)
+    return fail(ctx, CLR_ERR_CAPACITY, "%lld blocks exceed the %lld of the fixed array",
+                (long long)nb, (long long)kNoAllocMaxBlocks);
+  double* terms = noalloc_terms(ctx->device);
+  if (!terms) return fail(ctx, CLR_ERR_HIP, "fixed array not set up on device %d", ctx->device);
+  HIP_TRY(ctx, launch_identity_terms(X->view(), terms, ctx->stream));
+  HIP_TRY(ctx, launch_residual_finish(terms, nb, (double)X->rows, out, ctx->stream));
   return CLR_OK;
 }
 

@@ -258,6 +258,9 @@ hipError_t launch_to_dense(const MatView& M, double* out, int64_t ld, hipStream_
 hipError_t launch_scale(const MatView& M, double* arena, double* norm, double sc, hipStream_t s);
 hipError_t launch_identity_terms(const MatView& M, double* out, hipStream_t s);
 hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s);
+// out[0] = sqrt(sum of n terms) / sqrt(rows) on the device (one workgroup).
+hipError_t launch_residual_finish(const double* terms, int64_t n, double rows, double* out,
+                                  hipStream_t s);
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_from_dense(const MatView& M, double* arena, int* kind, int* rank, double* norm,
                              const double* D, int64_t ld, const int* mask_kind, hipStream_t s);

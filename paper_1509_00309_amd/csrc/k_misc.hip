@@ -130,6 +130,19 @@ __global__ __launch_bounds__(256) void k_identity_terms(MatView M, double* out) 
   if (threadIdx.x == 0) out[blk] = tot;
 }
 
+// out[0] = sqrt(sum_b terms[b]) / sqrt(rows): the identity residual from the
+// per-block terms of k_identity_terms, summed on the device by one workgroup
+// (each thread a strided subset in index order, then a fixed tree).
+__global__ __launch_bounds__(256) void k_residual_finish(const double* __restrict__ terms,
+                                                         int64_t n, double rows,
+                                                         double* __restrict__ out) {
+  __shared__ double red[256];
+  double part = 0.0;
+  for (int64_t b = threadIdx.x; b < n; b += 256) part += terms[b];
+  const double tot = wg_sum(part, red);
+  if (threadIdx.x == 0) out[0] = sqrt(tot) / sqrt(rows);
+}
+
 // D = a X + b Y + c I over the dense parts of one block.
 __global__ __launch_bounds__(256) void k_axpby_dense(const AxpbyDenseItem* items) {
   const AxpbyDenseItem it = items[blockIdx.x];
@@ -278,6 +291,11 @@ hipError_t launch_identity_terms(const MatView& M, double* out, hipStream_t s) {
   const int nb = M.nrb * M.ncb;
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_identity_terms, dim3(nb), dim3(256), 0, s, M, out);
+  return hipGetLastError();
+}
+hipError_t launch_residual_finish(const double* terms, int64_t n, double rows, double* out,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(256), 0, s, terms, n, rows, out);
   return hipGetLastError();
 }
 hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s) {
