@@ -1,24 +1,31 @@
-"""Benchmark of the CLR block product C = S * S on one MI355X.
+"""Benchmark of the CLR block product and the S^-1/2 iteration on one MI355X.
 
-Workload (one "step" = one full clr_gemm: screening, block products,
-accumulation, FP64 recompression and C's norm table): the overlap-like matrix
-of N = 8192 points on a jittered 3D lattice (spacing 1.5, jitter 0.3), kernel
-exp(-0.3 r^2) + 0.1 delta, contiguous clusters of U{96..160} points in lattice
-order, compressed at relative tolerance 1e-6 with blocks below 1e-10 dropped;
-products screened at 1e-10 and truncated at 1e-6.  Inputs are resident in HBM
-before timing starts.
+Workload of `value` (one "step" = one full clr_gemm: screening, block
+products, accumulation, FP64 recompression and C's norm table): the
+overlap-like matrix of N = 8192 points on a jittered 3D lattice (spacing 1.5,
+jitter 0.3), kernel exp(-0.3 r^2) + 0.1 delta, contiguous clusters of
+U{96..160} points in lattice order, compressed at relative tolerance 1e-6 with
+blocks below 1e-10 dropped; products screened at 1e-10 and truncated at 1e-6.
+Inputs are resident in HBM before timing starts.
 
 Prints one JSON line.  `value` is the FP64-form throughput in algorithmic
 TFLOP/s (DD 2mkn, LD 2 r k n, DL 2 m k r, LL 2 k rA rB + 2 side rA rB, plus
 2 m n r for low-rank terms added into dense accumulators), over the wall time
-of whole steps.  The mixed form (FP32 MFMA, FP64 accumulation) is reported
-alongside with its error against the FP64 oracle.
+of whole steps.  The mixed form (FP32 MFMA, FP64 accumulation) and the
+operand-split form (INT8 MFMA) are reported alongside, each with its error
+against the FP64 oracle on sampled result blocks.
 
-The S^-1/2 part of the metric is timed on the N = 8192 cut of the 3D
-square-root workload (lattice spacing 1.2, jitter 0.3, kernel
-exp(-0.2 r^2) + 0.05 delta, 64 clusters of 128 +- U{-32..32}, tol 1e-8,
-screen 1e-10, iterated until ||W S W - I||_F / sqrt(N) <= 1e-8), FP64 and
-mixed forms, one timed run each after one untimed run.
+Further legs (all on synthetic inputs of the shapes below):
+* sqrt_inv_scale: S^-1/2 at N = 32768 (32^3 lattice, spacing 1.2, jitter 0.3,
+  exp(-0.2 r^2) + 0.05 delta, 256 clusters of 128 +- U{-32..32}, tol 1e-8,
+  screen 1e-10, iterated until ||W S W - I||_F / sqrt(N) <= 1e-8), input
+  generated and compressed on the device, one timed run;
+* sqrt_inv: the same physics at N = 8192 (64 clusters) in every form;
+* adjoint: dL/dS of L = sum(Wbar o W) through 20 unrolled iterations with a
+  checkpoint every 5 at N = 4096 (32 clusters, tol 1e-8), forward and backward
+  time, error against the Daleckii-Krein gradient of the dense S^-1/2;
+* line: the N = 512 1D workload (product and S^-1/2), GPU and oracle times;
+* low_rank_regime, compression, batched (256 products and the dense limit).
 """
 from __future__ import annotations
 
@@ -152,6 +159,13 @@ def summarize(stats, wall, form):
     }
 
 
+def explicit_residual(ctx, W, S):
+    """||W S W - I||_F / sqrt(N) with untruncated, unscreened FP64 products (library calls)."""
+    WS = ctx.gemm(W, S, 0.0, 0.0)
+    WSW = ctx.gemm(WS, W, 0.0, 0.0)
+    return ctx.identity_residual(WSW)
+
+
 def run_sqrtinv(ctx, n, forms, log_fn):
     """S^-1/2 to convergence, per form: time, iterations, residuals, GEMM throughput."""
     import torch
@@ -186,6 +200,9 @@ def run_sqrtinv(ctx, n, forms, log_fn):
             "gemm_tflops": d["flops_products"] / wall / 1e12,
             "paper_convention_tflops": 4 * d["iterations"] * 2.0 * float(n) ** 3 / wall / 1e12,
         }
+        out[form]["error"] = {"explicit_residual": explicit_residual(ctx, W, S),
+                              "oracle": "unpinned at this size; the same physics at N = 1536 is "
+                                        "compared with the oracle in tests"}
         dense_w[form] = W.to_dense()
         del W
         log_fn(f"  S^-1/2 {form}: {out[form]}")
@@ -200,7 +217,7 @@ def run_sqrtinv(ctx, n, forms, log_fn):
             "forms": out}
 
 
-def run_low_rank(ctx, forms, steps, warmup, log_fn):
+def run_low_rank(ctx, forms, steps, warmup, log_fn, with_oracle=True):
     """The rank-sparse regime: C = S*S at N = 8192 on Morton-ordered compact clusters of the
     3D Gaussian lattice and on a Coulomb-like 1/sqrt(r^2 + 1) kernel (tol 1e-6)."""
     import torch
@@ -210,19 +227,25 @@ def run_low_rank(ctx, forms, steps, warmup, log_fn):
                       "compact clusters U{96..160}, tol 1e-6, screen 1e-10"),
                      (coulomb_3d_morton(8192), "3D lattice (spacing 1.0) 1/sqrt(r^2+1)+0.1 delta, "
                       "Morton-ordered clusters U{96..160}, tol 1e-6, screen 1e-10")):
-        Sd = torch.from_numpy(wl.dense()).cuda()
+        Sh = wl.dense()
+        Sd = torch.from_numpy(Sh).cuda()
         S = ctx.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
         del Sd
+        sample = oracle_sampled_blocks(wl, Sh, 6, 77) if with_oracle else None
         res = {"workload": f"C=S*S, N={wl.n}, " + desc, "forms": {}}
         for form in forms:
             _C, wall, stats = run_form(ctx, S, wl, form, steps, warmup)
+            err = sampled_error(sample, _C.to_dense().cpu().numpy(), wl.offsets()) if sample else None
             del _C
             sm = summarize(stats, wall, form)
             res["forms"][form] = {k: sm[k] for k in ("tflops", "ms_per_step", "phase_ms",
                                                      "rec_engine_ms", "computed_blocks",
                                                      "out_dense", "out_lowrank", "certified_dense")}
+            res["forms"][form]["error_vs_oracle"] = err
             log_fn(f"  {wl.name} {form}: {sm['tflops']:.2f} TFLOP/s, {sm['ms_per_step']:.2f} ms/step, "
                    f"phases {sm['phase_ms']}")
+        if sample:
+            res["oracle_sample"] = f"{len(sample)} random result blocks (seed 77) by the oracle"
         out[wl.name] = res
         del S
     return out
@@ -242,7 +265,9 @@ def run_compression(ctx, Sd_t, wl, reps, log_fn):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / reps * 1e3
         kind, rank, _norm = G.meta()
+        err = float(torch.linalg.norm(G.to_dense() - Sd_t) / torch.linalg.norm(Sd_t))
         out[method] = {"ms": ms, "stored_elements": int(G.stored_elements()),
+                       "error_vs_input": err,
                        "low_rank_blocks": int(np.sum(kind == 2)),
                        "dense_blocks": int(np.sum(kind == 1)),
                        "mean_rank": float(rank[kind == 2].mean()) if np.any(kind == 2) else 0.0}
@@ -250,7 +275,7 @@ def run_compression(ctx, Sd_t, wl, reps, log_fn):
     return out
 
 
-def run_batched(ctx, nprod, log_fn):
+def run_batched(ctx, nprod, log_fn, with_oracle=True):
     """Batch of mixed-size products: nprod independent products S_p * S_p (N_p ~ U{512..4096}, 16..48
     uneven clusters, tol 1e-8) planned once and executed as one graph replay per form;
     plus the full-rank dense limit (N = 4096, 32 blocks, truncation and screening off)
@@ -259,16 +284,21 @@ def run_batched(ctx, nprod, log_fn):
     from workloads import dense_limit, batch_product
     t0 = time.perf_counter()
     mats, dense_eq, total_n2 = [], 0.0, 0
+    checks = {}
     for p in range(nprod):
         wl = batch_product(p)
-        Sd = torch.from_numpy(wl.dense()).cuda()
+        Sh = wl.dense()
+        if with_oracle and p < 2:
+            checks[p] = (wl, oracle_sampled_blocks(wl, Sh, 3, 300 + p))
+        Sd = torch.from_numpy(Sh).cuda()
         mats.append(ctx.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10))
         dense_eq += 2.0 * float(wl.n) ** 3
         total_n2 += wl.n * wl.n
         del Sd
     torch.cuda.synchronize()
     log_fn(f"  batch of {nprod} products built in {time.perf_counter() - t0:.1f} s")
-    out = {"workload": f"{nprod} independent products S_p*S_p, N_p ~ U{{512..4096}} (seed 3000+p), "
+    out = {"oracle_sample": "3 random result blocks of each of products 0 and 1 by the oracle",
+           "workload": f"{nprod} independent products S_p*S_p, N_p ~ U{{512..4096}} (seed 3000+p), "
                        f"16..48 uneven clusters, 3D lattice exp(-0.3 r^2)+0.1 delta, tol 1e-8, "
                        f"screen 1e-10; one plan, execution replayed as a HIP graph",
            "products": nprod, "dense_equivalent_flops": dense_eq, "forms": {}}
@@ -287,6 +317,10 @@ def run_batched(ctx, nprod, log_fn):
                               "tflops": d["flops_products"] / (t * 1e-3) / 1e12,
                               "dense_equivalent_tflops": dense_eq / (t * 1e-3) / 1e12,
                               "blocks_computed": d["computed"]}
+        if checks:
+            errs = [sampled_error(smp, plan.outputs[p].to_dense().cpu().numpy(), w.offsets())
+                    for p, (w, smp) in checks.items()]
+            out["forms"][form]["error_vs_oracle"] = max(errs)
         if form == "fp64":
             ref = [c.to_dense() for c in plan.outputs[:8]]
         else:
@@ -335,23 +369,37 @@ def run_batched(ctx, nprod, log_fn):
     return out
 
 
-def cpu_baseline(wl, Sd, gpu_blocks_fn, budget_s):
-    """Oracle (FP64 NumPy/LAPACK) on a bounded sample of the same product's result blocks."""
-    import oracle as orc
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
-        cores = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(wl, Sd, budget_s, seed=99):
+    """Oracle (FP64 NumPy/LAPACK) on a bounded sample of the same product's result blocks:
+    returns the baseline record and the sampled blocks [(i, j, oracle block)]."""
+    import oracle as orc
     t0 = time.perf_counter()
     O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
     t_compress = time.perf_counter() - t0
     nb = len(wl.sizes)
-    rng = np.random.Generator(np.random.PCG64(99))
+    rng = np.random.Generator(np.random.PCG64(seed))
     order = rng.permutation(nb * nb)
     flops = 0.0
-    done = 0
-    errs = []
+    sample = []
     t0 = time.perf_counter()
     elapsed = 0.0
     for idx in order:
@@ -361,23 +409,215 @@ def cpu_baseline(wl, Sd, gpu_blocks_fn, budget_s):
         elapsed = time.perf_counter() - t0
         m, n = wl.sizes[i], wl.sizes[j]
         flops += st.flops_dd + st.flops_ld + st.flops_dl + st.flops_ll + st.flops_densify
-        done += 1
-        ref = blk.dense() if blk is not None else np.zeros((m, n))
-        got = gpu_blocks_fn(i, j)
-        errs.append((float(np.sum((got - ref) ** 2)), float(np.sum(ref ** 2))))
+        sample.append((i, j, blk.dense() if blk is not None else np.zeros((m, n))))
         if elapsed >= budget_s:
             break
-    e_num = math.sqrt(sum(e[0] for e in errs))
-    e_den = math.sqrt(sum(e[1] for e in errs))
-    return {
+    rec = {
         "value": flops / elapsed / 1e12 if elapsed > 0 else None,
         "unit": "TFLOP/s",
-        "cores": int(cores),
+        "cores": int(blas_threads()),
+        "cpu": cpu_model(),
         "kind": "oracle",
-        "sample": f"{done} of {nb * nb} result blocks of the same S*S (random order, seed 99), "
-                  f"{elapsed:.1f} s of oracle time; flops counted as in the GPU figure; "
+        "sample": f"{len(sample)} of {nb * nb} result blocks of the same S*S (random order, seed "
+                  f"{seed}), {elapsed:.1f} s of oracle time; flops counted as in the GPU figure; "
                   f"oracle input compression took {t_compress:.1f} s untimed",
-    }, (e_num / e_den if e_den > 0 else 0.0), done
+    }
+    return rec, sample
+
+
+def sampled_error(sample, dense, offs):
+    """Relative Frobenius error of a dense result on the oracle's sampled blocks."""
+    num = den = 0.0
+    for i, j, ref in sample:
+        got = dense[offs[i]:offs[i + 1], offs[j]:offs[j + 1]]
+        num += float(np.sum((got - ref) ** 2))
+        den += float(np.sum(ref ** 2))
+    return math.sqrt(num / den) if den > 0 else 0.0
+
+
+def run_sqrtinv_scale(ctx, n, nclusters, log_fn):
+    """S^-1/2 of the at-scale workload: the dense input generated on the device (never on the
+    host), compressed there, then one timed run of the FP64 iteration to convergence."""
+    import torch
+    from workloads import lattice_3d_wide
+    wl = lattice_3d_wide(n, nclusters)
+    t0 = time.perf_counter()
+    D = ctx.kernel_matrix(torch.from_numpy(wl.points).cuda(), "gaussian", wl.a, wl.diag)
+    S = ctx.compress(D, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    del D
+    torch.cuda.synchronize()
+    kind, rank, _ = S.meta()
+    log_fn(f"  N={n}: input generated and compressed in {time.perf_counter() - t0:.1f} s; "
+           f"{int(np.sum(kind != 0))} nonzero blocks of {kind.size}, {int(np.sum(kind == 2))} low rank")
+    conv = wl.extra["conv_tol"]
+    # a warm-up product of the same size (kernel code objects, workspace)
+    C = ctx.gemm(S, S, wl.tol, wl.eps_sp)
+    del C
+    torch.cuda.synchronize()
+    out = {}
+    t0 = time.perf_counter()
+    W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    d = st.as_dict()
+    out["fp64"] = {
+        "ms_total": wall * 1e3,
+        "iterations": d["iterations"],
+        "converged": bool(d["converged"]),
+        "internal_residual": d["internal_residual"],
+        "explicit_residual": d["explicit_residual"],
+        "error": {"explicit_residual": d["explicit_residual"],
+                  "oracle": "unpinned at this size; the same physics at N = 1536 is compared with "
+                            "the oracle block by block in tests (iterations, status, residuals)"},
+        "n_gemms": d["n_gemms"],
+        "gemm_tflops": d["flops_products"] / wall / 1e12,
+        "paper_convention_tflops": 4 * d["iterations"] * 2.0 * float(n) ** 3 / wall / 1e12,
+    }
+    log_fn(f"  S^-1/2 N={n} fp64: {out['fp64']}")
+    del W, S
+    torch.cuda.synchronize()
+    return {"workload": f"S^-1/2, N={n} 3D lattice (spacing 1.2, jitter 0.3) overlap-like "
+                        f"exp(-0.2 r^2)+0.05 delta, {nclusters} clusters 128+-U{{-32..32}}, "
+                        f"tol {wl.tol:g}, screen 1e-10, conv 1e-8; input generated on the device",
+            "forms": out}
+
+
+def run_adjoint(ctx, forms, log_fn):
+    """dS of L = sum(Wbar o W), W after 20 unrolled iterations, checkpoint every 5, at N = 4096
+    (32 clusters, tol 1e-8); Wbar seeded N(0, 1) masked to S's stored blocks.  The error is
+    against the Daleckii-Krein gradient Q (Gamma o (Q^T Wbar Q)) Q^T of the dense S^-1/2 of the
+    same compressed S (eigendecomposition in FP64, torch on the GPU: a check value, not part of
+    the path)."""
+    import torch
+    from workloads import adjoint_n4096
+    wl = adjoint_n4096()
+    S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    iters, every = wl.extra["iters"], wl.extra["checkpoint_every"]
+    kind, _r, _n = S.meta()
+    offs = wl.offsets()
+    mask = torch.zeros((wl.n, wl.n), dtype=torch.float64, device="cuda")
+    for I in range(len(wl.sizes)):
+        for J in range(len(wl.sizes)):
+            if kind[I, J]:
+                mask[offs[I]:offs[I + 1], offs[J]:offs[J + 1]] = 1.0
+    Wbar = torch.from_numpy(wl.extra["weights"]).cuda() * mask
+    Sd = S.to_dense().contiguous()
+    lam, Q = torch.linalg.eigh(0.5 * (Sd + Sd.T))
+    sq = torch.sqrt(lam)
+    gam = -1.0 / (torch.outer(sq, sq) * (sq[:, None] + sq[None, :]))
+    ref = (Q @ (gam * (Q.T @ Wbar @ Q)) @ Q.T) * mask
+    w_ref = (Q / sq) @ Q.T
+    out = {"workload": f"L = sum(Wbar o S^-1/2), N={wl.n} 3D lattice exp(-0.3 r^2)+0.1 delta, "
+                       f"{len(wl.sizes)} clusters 128+-U{{-32..32}}, tol {wl.tol:g}, {iters} unrolled "
+                       f"iterations, checkpoint every {every}; Wbar ~ N(0,1) masked to S's blocks",
+           "lambda_min": float(lam[0]), "lambda_max": float(lam[-1]), "forms": {}}
+    for form in forms:
+        split = 1 if form == "mixed" else 0
+        kw = dict(tol=wl.tol, eps_sp=wl.eps_sp, precision=form, split=split)
+        W, _st = ctx.sqrt_inv(S, fixed_iters=iters, **kw)
+        del W
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W, _st = ctx.sqrt_inv(S, fixed_iters=iters, **kw)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        dS, Wb = ctx.sqrt_inv_backward(S, Wbar, iters, every, **kw)
+        torch.cuda.synchronize()
+        t_bwd = time.perf_counter() - t0
+        Wd = W.to_dense()
+        out["forms"][form] = {
+            "ms_forward": t_fwd * 1e3,
+            "ms_backward": t_bwd * 1e3,
+            "grad_rel_err_vs_daleckii_krein": float(torch.linalg.norm(dS - ref) / torch.linalg.norm(ref)),
+            "w_rel_err_vs_eigh": float(torch.linalg.norm(Wd - w_ref) / torch.linalg.norm(w_ref)),
+        }
+        log_fn(f"  adjoint {form}: {out['forms'][form]}")
+        del W, Wb, dS, Wd
+    return out
+
+
+def run_line(ctx, budget_s, log_fn, want_cpu):
+    """The N = 512 line workload: product and S^-1/2 on the GPU, and the oracle's time for the
+    same two results on the host (the whole workload, not a sample)."""
+    import torch
+    from workloads import line_n512
+    wl = line_n512()
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    conv = wl.extra["conv_tol"]
+    for _ in range(3):
+        C = ctx.gemm(S, S, wl.tol, wl.eps_sp)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        C, st = ctx.gemm(S, S, wl.tol, wl.eps_sp, stats=True)
+    torch.cuda.synchronize()
+    ms_gemm = (time.perf_counter() - t0) / reps * 1e3
+    flops = st.flops_products
+    W, sst = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W, sst = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True)
+    torch.cuda.synchronize()
+    ms_si = (time.perf_counter() - t0) * 1e3
+    out = {"workload": "N=512 points on a line (spacing 1, jitter 0.2), exp(-0.5 r^2)+0.1 delta, "
+                       "8 clusters, tol 1e-8, screen 1e-10, conv 1e-10",
+           "gpu": {"gemm_ms": ms_gemm, "gemm_tflops": flops / (ms_gemm * 1e-3) / 1e12,
+                   "sqrt_inv_ms": ms_si, "iterations": sst.iterations,
+                   "explicit_residual": sst.explicit_residual}}
+    if want_cpu:
+        import oracle as orc
+        t0 = time.perf_counter()
+        O = orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+        t_c = time.perf_counter() - t0
+        gs = orc.GemmStats()
+        t0 = time.perf_counter()
+        Oc = orc.gemm(O, O, wl.tol, wl.eps_sp, stats=gs)
+        t_g = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Ow, info = orc.sqrt_inv(O, wl.tol, wl.eps_sp, conv_tol=conv)
+        t_s = time.perf_counter() - t0
+        of = gs.flops_dd + gs.flops_ld + gs.flops_dl + gs.flops_ll + gs.flops_densify
+        Cd = C.to_dense().cpu().numpy()
+        Wd = W.to_dense().cpu().numpy()
+        out["error_vs_oracle"] = {
+            "gemm": float(np.linalg.norm(Cd - orc.to_dense(Oc)) / np.linalg.norm(orc.to_dense(Oc))),
+            "sqrt_inv": float(np.linalg.norm(Wd - orc.to_dense(Ow)) / np.linalg.norm(orc.to_dense(Ow)))}
+        out["cpu_baseline"] = {"value": of / t_g / 1e12, "unit": "TFLOP/s", "cores": int(blas_threads()),
+                               "cpu": cpu_model(), "kind": "oracle",
+                               "sample": f"the whole workload: one product {t_g * 1e3:.0f} ms, S^-1/2 "
+                                         f"{t_s * 1e3:.0f} ms ({info.iterations} iterations), input "
+                                         f"compression {t_c * 1e3:.0f} ms untimed",
+                               "gemm_ms": t_g * 1e3, "sqrt_inv_ms": t_s * 1e3}
+    log_fn(f"  line N=512: {out}")
+    return out
+
+
+def oracle_sampled_blocks(wl, Sd, npick, seed, alpha=1.0):
+    """The oracle's result blocks (i, j) of S*S for npick random (i, j), with only the blocks of
+    row i and column j of S compressed (each exactly as the oracle's compress does it)."""
+    import oracle as orc
+    nb = len(wl.sizes)
+    offs = wl.offsets()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    picks = [(int(rng.integers(nb)), int(rng.integers(nb))) for _ in range(npick)]
+    need = set()
+    for i, j in picks:
+        need |= {(i, k) for k in range(nb)} | {(k, j) for k in range(nb)}
+    blocks = {}
+    for (a, b) in sorted(need):
+        D = np.array(Sd[offs[a]:offs[a + 1], offs[b]:offs[b + 1]])
+        blk = orc.combine(D.shape[0], D.shape[1], [("D", D)], wl.tol, 1e-10, a == b)
+        if blk is not None:
+            blocks[(a, b)] = blk
+    O = orc.OMatrix(list(wl.sizes), list(wl.sizes), blocks)
+    out = []
+    for i, j in picks:
+        blk = orc.gemm_block(O, O, i, j, wl.tol, wl.eps_sp, alpha=alpha)
+        out.append((i, j, blk.dense() if blk is not None else np.zeros((wl.sizes[i], wl.sizes[j]))))
+    return out
 
 
 def main():
@@ -388,9 +628,16 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--forms", default="fp64,mixed,ozaki")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip every oracle leg (baselines and errors against the oracle)")
     ap.add_argument("--sqrtinv-n", type=int, default=8192)
     ap.add_argument("--no-sqrtinv", action="store_true")
+    ap.add_argument("--sqrtinv-scale-n", type=int, default=32768,
+                    help="N of the at-scale S^-1/2 leg (0 skips it)")
+    ap.add_argument("--sqrtinv-scale-clusters", type=int, default=256)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-line", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-lowrank", action="store_true")
@@ -411,10 +658,15 @@ def main():
     from workloads import lattice_3d
 
     torch.cuda.set_device(0)
+    ctx = clr.Context()
+    peaks = None
+    if not args.no_peaks:
+        peaks = ctx.measure_peaks()
+        peaks.update({"datasheet_mfma_f64_tflops": PEAK_F64_MFMA, "datasheet_hbm_gbps": PEAK_HBM})
+        log(f"measured peaks: {peaks}")
     wl = lattice_3d(args.n)
     log(f"workload {wl.name}: N={wl.n}, {len(wl.sizes)} clusters")
     Sd = wl.dense()
-    ctx = clr.Context()
     S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
     torch.cuda.synchronize()
     log(f"compressed: stored {S.stored_elements()} of {wl.n * wl.n} elements")
@@ -434,30 +686,36 @@ def main():
     dense_equiv = 2.0 * wl.n ** 3 / (fb["ms_per_step"] * 1e-3) / 1e12
 
     cpu = None
-    sample_err = {}
+    err_oracle = {}
+    offs = wl.offsets()
     if not args.no_cpu_baseline:
-        dense_by_form = {f: results[f].to_dense().cpu().numpy() for f in results}
-        offs = wl.offsets()
+        cpu, sample = cpu_baseline(wl, Sd, args.cpu_budget)
+        for f, C in results.items():
+            err_oracle[f] = sampled_error(sample, C.to_dense().cpu().numpy(), offs)
+        log(f"cpu baseline: {cpu}; errors against the oracle on its {len(sample)} blocks: {err_oracle}")
+    for f in results:
+        forms[f]["error_vs_oracle"] = err_oracle.get(f)
+    results = None
 
-        def blocks_fn_for(form):
-            D = dense_by_form[form]
-            return lambda i, j: D[offs[i]:offs[i + 1], offs[j]:offs[j + 1]]
+    line_leg = None
+    if not args.no_line:
+        log("line workload N=512")
+        line_leg = run_line(ctx, args.cpu_budget, log, not args.no_cpu_baseline)
 
-        cpu, err, nsample = cpu_baseline(wl, Sd, blocks_fn_for(base), args.cpu_budget)
-        sample_err[base] = err
-        import oracle as orc  # noqa: F401  (already loaded by cpu_baseline)
-        for f in results:
-            if f == base:
-                continue
-            D = dense_by_form[f]
-            Db = dense_by_form[base]
-            sample_err[f"{f}_vs_{base}"] = float(np.linalg.norm(D - Db) / np.linalg.norm(Db))
-        log(f"cpu baseline: {cpu}")
+    scale = None
+    if args.sqrtinv_scale_n > 0:
+        log(f"S^-1/2 at N={args.sqrtinv_scale_n}")
+        scale = run_sqrtinv_scale(ctx, args.sqrtinv_scale_n, args.sqrtinv_scale_clusters, log)
 
     sqrtinv = None
     if not args.no_sqrtinv:
         log(f"S^-1/2 at N={args.sqrtinv_n}")
         sqrtinv = run_sqrtinv(ctx, args.sqrtinv_n, [f for f in args.forms.split(",")], log)
+
+    adjoint = None
+    if not args.no_adjoint:
+        log("adjoint N=4096")
+        adjoint = run_adjoint(ctx, [f for f in args.forms.split(",") if f in ("fp64", "mixed")], log)
 
     # The two largest kernels by device time: the register-resident
     # recompression (FP64 vector ALU / latency bound; peak = 256 CUs x 4 SIMD x
@@ -470,7 +728,8 @@ def main():
     low_rank = None
     if not args.no_lowrank:
         log("low-rank regime products")
-        low_rank = run_low_rank(ctx, [f for f in args.forms.split(",")], args.steps, args.warmup, log)
+        low_rank = run_low_rank(ctx, [f for f in args.forms.split(",")], args.steps, args.warmup, log,
+                                not args.no_cpu_baseline)
     compression = None
     if not args.no_compression:
         log("input construction: truncated SVD and rank-revealing QR")
@@ -478,7 +737,7 @@ def main():
     batched = None
     if not args.no_batch:
         log(f"batched products: {args.batch_count}")
-        batched = run_batched(ctx, args.batch_count, log)
+        batched = run_batched(ctx, args.batch_count, log, not args.no_cpu_baseline)
 
     roof = {
         "bound": "alu",
@@ -500,6 +759,8 @@ def main():
         "frac": (fb["dense_gemm_tflops"] / fb["peak"]) if fb["dense_gemm_tflops"] else None,
         "traffic": measured_traffic("k_ggemm_dense"),
     }
+    if peaks:
+        roof_gemm["frac_of_measured_mfma_loop"] = fb["dense_gemm_tflops"] / peaks["mfma_f64_tflops"]
     line = {
         "metric": METRIC,
         "value": fb["tflops"],
@@ -524,8 +785,12 @@ def main():
         },
         "dense_equivalent_tflops": dense_equiv,
         "forms": forms,
-        "error_vs_oracle_sampled": sample_err,
+        "error_vs_oracle_sampled": err_oracle,
+        "measured_peaks": peaks,
+        "sqrt_inv_scale": scale,
         "sqrt_inv": sqrtinv,
+        "adjoint": adjoint,
+        "line": line_leg,
         "low_rank_regime": low_rank,
         "batched": batched,
         "compression": compression,

@@ -79,8 +79,9 @@ typedef struct {
   double tol;      /* relative truncation tolerance per block; 0 = no truncation       */
   double eps_sp;   /* screening threshold (see clr_screen_mode)                        */
   int screen;      /* clr_screen_mode                                                  */
-  int precision;   /* clr_precision: block products in FP64, or FP32 MFMA with FP64
-                      accumulation every 16 inner indices (MIXED)                      */
+  int precision;   /* clr_precision: block products in FP64, or FP32 MFMA with the
+                      FP32 partials added into FP64 every 32 inner indices of the dense
+                      accumulation (every 8 of the factor products) (MIXED)            */
   int split;       /* MIXED: 1 adds the hi*lo and lo*hi correction products, 0 uses
                       the FP32-rounded operands alone.  OZAKI: digits per operand,
                       2..7 (0 selects 7, near FP64 accuracy)                           */
@@ -93,6 +94,19 @@ typedef struct {
   double conv_tol;     /* target of ||X_n - I||_F/sqrt(N) and of ||W S W - I||_F/sqrt(N) */
   int max_iter;        /* iteration cap when fixed_iters == 0                          */
   int fixed_iters;     /* > 0: run exactly this many iterations, no stopping test       */
+  /* Precision schedule of the reduced-precision forms (g.precision != CLR_FP64).
+   * reduced_below == 0: every product in g.precision.  reduced_below > 0: the
+   * products run in FP64 until an iteration ends with ||X_n - I||_F/sqrt(N) <=
+   * reduced_below; from the next iteration on, X_n = alpha Y_n Z_n stays FP64
+   * and the other three products run in g.precision.                          */
+  double reduced_below;
+  /* With reduced_below > 0 and correction != 0, those later iterations form
+   * Eqs. (9)-(11) through D_n = T_n - I = -E_n / 2 + 3 E_n^2 / 8, E_n = X_n - I
+   * (the same T_n in exact arithmetic): Z_{n+1} = Z_n + Z_n D_n and
+   * Y_{n+1} = Y_n + D_n Y_n, the sums and E_n, D_n recompressed in FP64.  The
+   * reduced-precision products E_n^2, Z_n D_n, D_n Y_n then carry the small
+   * D_n, so their rounding scales with ||X_n - I|| instead of ||T_n||.        */
+  int correction;
 } clr_sqrtinv_opts;
 
 typedef struct {
@@ -257,9 +271,10 @@ clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_ma
 /* Largest output-tile edge of the grouped-GEMM items of the dense-accumulation
  * launch and of the factor-product launches, per precision (CLR_FP64 or
  * CLR_MIXED) for this context: 0 (default) is the kernel's full tile (dense:
- * 160 in the FP64 form, 128 in the mixed form; factor products: 64, one wave
- * per item), otherwise a multiple of 16 up to it.  Results do not depend on
- * these edges, only the launch shapes do. */
+ * 160, or 128 in the mixed form with split = 1; factor products: 64, one wave
+ * per item), otherwise a multiple of 16 up to 160 (a larger edge than the
+ * kernel's tile is capped to it).  Results do not depend on these edges, only
+ * the launch shapes do. */
 clr_status clr_set_tile_edges(clr_context* ctx, int precision, int dense_edge, int thin_edge);
 
 /* Dense certificate (on by default).  A dense-accumulated block D (m x n,
@@ -272,6 +287,14 @@ clr_status clr_set_tile_edges(clr_context* ctx, int precision, int dense_edge, i
  * proof's margin exceeds the SVD's rounding error); only the work differs.
  * Applies to products and plans created afterwards on this context. */
 clr_status clr_set_dense_certificate(clr_context* ctx, int enable);
+
+/* Measurement helper: the sustained FP64 MFMA rate of a long chain of
+ * independent v_mfma_f64_16x16x4 per wave (16 waves per compute unit, operands
+ * in registers), in TFLOP/s, and the bandwidth of a plain device copy of
+ * 1 GiB (read + write bytes over time), in GB/s; best of three timed runs each
+ * after one warm-up run.  Allocates and frees 2 GiB of device memory and
+ * synchronises the context stream.  Either output may be NULL. */
+clr_status clr_measure_peaks(clr_context* ctx, double* mfma_f64_tflops, double* copy_gbps);
 
 /* Truncating factorisation of clr_compress on this context (CLR_COMPRESS_SVD,
  * the default, or CLR_COMPRESS_RRQR); products always recompress by SVD. */
@@ -321,7 +344,9 @@ clr_status clr_gemm_batch(clr_context* ctx, int nprod, const clr_matrix* const* 
  * constant, truncation treated as the identity), restricted to S's stored
  * blocks.  Wbar and dS are dense device matrices N x N with leading dimension
  * ld.  Iterates are re-computed from checkpoints kept every
- * `checkpoint_every` iterations.  W (nullable) receives the forward result. */
+ * `checkpoint_every` iterations.  W (nullable) receives the forward result.
+ * The iteration is unrolled as printed: opts->reduced_below and
+ * opts->correction must be 0 (CLR_ERR_INVALID_ARG otherwise). */
 clr_status clr_sqrt_inv_backward(clr_context* ctx, const clr_matrix* S,
                                  const clr_sqrtinv_opts* opts, int iters,
                                  int checkpoint_every, const double* Wbar, double* dS,

@@ -183,18 +183,22 @@ class Context:
 
     def sqrt_inv(self, S: "CLRMatrix", tol: float, eps_sp: float, conv_tol: float = 1e-10,
                  max_iter: int = 50, fixed_iters: int = 0, alpha: float = 0.0, screen="abs",
-                 precision="fp64", split: int = 0, allow_not_converged: bool = False):
+                 precision="fp64", split: int = 0, allow_not_converged: bool = False,
+                 reduced_below: float = 0.0, correction: bool = False):
         """W = S^-1/2 (Newton-Schulz, Eqs. (8)-(11)); returns (W, SqrtInvStats).
 
         An iteration that stops without meeting conv_tol raises ClrError
         (CLR_ERR_NOT_CONVERGED) unless allow_not_converged is set; then W is
-        returned and SqrtInvStats.converged is 0."""
+        returned and SqrtInvStats.converged is 0.  reduced_below / correction:
+        the precision schedule of the reduced-precision forms (see clr.h)."""
         o = SqrtInvOpts()
         o.g = _gemm_opts(tol, eps_sp, screen, precision, split, 1.0)
         o.alpha = float(alpha)
         o.conv_tol = float(conv_tol)
         o.max_iter = int(max_iter)
         o.fixed_iters = int(fixed_iters)
+        o.reduced_below = float(reduced_below)
+        o.correction = 1 if correction else 0
         h = C.c_void_p()
         st = SqrtInvStats()
         rc = lib.clr_sqrt_inv(self._h, S._h, C.byref(o), C.byref(h), C.byref(st))
@@ -293,6 +297,12 @@ class Context:
         self._check(lib.clr_identity_residual(self._h, X._h, C.byref(out)))
         return out.value
 
+    def measure_peaks(self) -> dict:
+        """Measured FP64 MFMA loop rate (TFLOP/s) and device copy bandwidth (GB/s)."""
+        t, b = C.c_double(), C.c_double()
+        self._check(lib.clr_measure_peaks(self._h, C.byref(t), C.byref(b)))
+        return {"mfma_f64_tflops": t.value, "copy_gbps": b.value}
+
     def identity_residual_noalloc(self, X: "CLRMatrix", out):
         """||X - I||_F / sqrt(N) written to out[0] (a caller-owned float64 cuda tensor) on the
         context stream, with no allocation inside the library (see clr.h)."""
@@ -301,7 +311,6 @@ class Context:
             raise TypeError("out must be a float64 cuda tensor with at least one element")
         self._check(lib.clr_identity_residual_noalloc(self._h, X._h, C.c_void_p(out.data_ptr())))
         return out
-
 
 
 class Plan:

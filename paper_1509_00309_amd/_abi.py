@@ -34,7 +34,7 @@ EXPORTS = [
     "clr_identity_residual", "clr_identity_residual_noalloc", "clr_gemm_backward", "clr_sqrt_inv_backward",
     "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
     "clr_set_tile_edges", "clr_autotune", "clr_set_dense_certificate", "clr_set_compression",
-    "clr_kernel_matrix",
+    "clr_kernel_matrix", "clr_measure_peaks",
 ]
 
 
@@ -45,7 +45,8 @@ class GemmOpts(C.Structure):
 
 class SqrtInvOpts(C.Structure):
     _fields_ = [("g", GemmOpts), ("alpha", C.c_double), ("conv_tol", C.c_double),
-                ("max_iter", C.c_int), ("fixed_iters", C.c_int)]
+                ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("reduced_below", C.c_double),
+                ("correction", C.c_int)]
 
 
 class GemmStats(C.Structure):
@@ -108,6 +109,7 @@ def _load():
         "clr_sqrt_inv": [P, P, C.POINTER(SqrtInvOpts), C.POINTER(P), C.POINTER(SqrtInvStats)],
         "clr_identity_residual": [P, P, DP],
         "clr_identity_residual_noalloc": [P, P, P],
+        "clr_measure_peaks": [P, DP, DP],
         "clr_gemm_backward": [P, P, P, D, P, I64, P, I64, P, I64],
         "clr_sqrt_inv_backward": [P, P, C.POINTER(SqrtInvOpts), C.c_int, C.c_int, P, P, I64,
                                   C.POINTER(P)],

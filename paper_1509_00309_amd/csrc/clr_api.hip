@@ -312,7 +312,8 @@ hipError_t run_ggemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* s
 
 int max_item(const clr_gemm_opts* o) {
   if (o->precision == CLR_OZAKI) return kMaxItemOzaki;
-  return o->precision == CLR_MIXED ? kMaxItemF32 : kMaxItemF64;
+  if (o->precision == CLR_MIXED) return o->split ? kMaxItemF32Split : kMaxItemF32;
+  return kMaxItemF64;
 }
 
 // Factor products (one side a rank) run on the wave-per-item kernel.
@@ -971,6 +972,41 @@ extern "C" clr_status clr_kernel_matrix(clr_context* ctx, const double* row_poin
   HIP_TRY(ctx, launch_kernel_matrix(row_points, nrows, col_points, ncols, dim, kernel, a, diag,
                                     out, ld, ctx->stream));
   return CLR_OK;
+}
+
+// Measured FP64 MFMA rate and copy bandwidth (best of several timed runs).
+extern "C" clr_status clr_measure_peaks(clr_context* ctx, double* mfma_f64_tflops,
+                                        double* copy_gbps) {
+  if (!ctx) return CLR_ERR_INVALID_ARG;
+  int ncu = 0;
+  HIP_TRY(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  const int blocks = 4 * std::max(ncu, 1);   // 16 waves per CU: four per SIMD
+  const int iters = 4096;
+  const size_t bytes = (size_t)1 << 30;     // per buffer, far above L2 and the last-level cache
+  double* buf = nullptr;
+  HIP_TRY(ctx, hipMalloc(&buf, 2 * bytes + 256));
+  auto run = [&]() -> clr_status {
+    float best_mfma = 1e30f, best_copy = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      HIP_TRY(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+      HIP_TRY(ctx, launch_mfma_loop(blocks, iters, buf, ctx->stream));
+      HIP_TRY(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+      HIP_TRY(ctx, launch_copy(buf + 32, buf + 32 + bytes / 8, (int64_t)(bytes / 8), ctx->stream));
+      HIP_TRY(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+      HIP_TRY(ctx, hipEventSynchronize(ctx->ev[2]));
+      if (rep == 0) continue;   // the first round warms up
+      best_mfma = std::min(best_mfma, elapsed(ctx->ev[0], ctx->ev[1]));
+      best_copy = std::min(best_copy, elapsed(ctx->ev[1], ctx->ev[2]));
+    }
+    if (mfma_f64_tflops) *mfma_f64_tflops = mfma_loop_flops(blocks, iters) / (best_mfma * 1e-3) / 1e12;
+    if (copy_gbps) *copy_gbps = 2.0 * (double)bytes / (best_copy * 1e-3) / 1e9;
+    return CLR_OK;
+  };
+  HIP_TRY(ctx, launch_fill_f64(buf, 0.0, (int64_t)((2 * bytes + 256) / 8), ctx->stream));
+  const clr_status s = run();
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(buf);
+  return s;
 }
 
 // Factorisation used by clr_compress (the paper builds its input blocks by
@@ -1633,7 +1669,8 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
   clr_status s = check_opts(ctx, &o->g);
   if (s != CLR_OK) return s;
   if (!S->square_blocked()) return fail(ctx, CLR_ERR_SHAPE, "S must be square-blocked");
-  if (!(o->conv_tol >= 0.0) || o->max_iter < 1 || o->fixed_iters < 0 || !(o->alpha >= 0.0))
+  if (!(o->conv_tol >= 0.0) || o->max_iter < 1 || o->fixed_iters < 0 || !(o->alpha >= 0.0) ||
+      !(o->reduced_below >= 0.0))
     return fail(ctx, CLR_ERR_INVALID_ARG, "bad iteration options");
   HIP_TRY(ctx, hipEventRecord(ctx->ev[4], ctx->stream));
   double alpha = o->alpha;
@@ -1654,6 +1691,11 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
   g.alpha = 1.0;
   clr_gemm_opts ga = g;
   ga.alpha = alpha;
+  // the FP64 options of the precision schedule's early iterations and of X_n
+  clr_gemm_opts g64 = g, ga64 = ga;
+  g64.precision = ga64.precision = CLR_FP64;
+  g64.split = ga64.split = 0;
+  const bool scheduled = o->g.precision != CLR_FP64 && o->reduced_below > 0.0;
   clr_matrix *Z = nullptr, *Y = nullptr;
   if ((s = identity_matrix(ctx, S->rs, &Z)) != CLR_OK) return s;
   if ((s = copy_matrix(ctx, S, &Y)) != CLR_OK) {
@@ -1673,15 +1715,40 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
     clr_matrix *X = nullptr, *Q = nullptr, *T = nullptr, *Zn = nullptr, *Yn = nullptr;
     clr_gemm_stats gs{};
     double r = 0.0;
-    s = gemm_impl(ctx, Y, Z, &ga, &X, &gs);                 // X_n = alpha Y_n Z_n   (Eq. (8))
+    // precision of this iteration's products: everything in g.precision, or (the
+    // schedule) FP64 until the residual has fallen to reduced_below, then X_n in
+    // FP64 and the other products in g.precision
+    const bool reduced = !scheduled || (!internal.empty() && internal.back() <= o->reduced_below);
+    const clr_gemm_opts* gx = scheduled ? &ga64 : &ga;
+    const clr_gemm_opts* gr = reduced ? &g : &g64;
+    s = gemm_impl(ctx, Y, Z, gx, &X, &gs);                  // X_n = alpha Y_n Z_n   (Eq. (8))
     flops += gs.flops_products;
-    if (s == CLR_OK) s = gemm_impl(ctx, X, X, &g, &Q, &gs); // X_n^2
-    flops += gs.flops_products;
-    if (s == CLR_OK) s = clr_axpby(ctx, -10.0 / 8.0, X, 3.0 / 8.0, Q, 15.0 / 8.0, &g, &T);  // Eq. (9)
-    if (s == CLR_OK) s = gemm_impl(ctx, Z, T, &g, &Zn, &gs);  // Z_{n+1} = Z_n T_n     (Eq. (10))
-    flops += gs.flops_products;
-    if (s == CLR_OK) s = gemm_impl(ctx, T, Y, &g, &Yn, &gs);  // Y_{n+1} = T_n Y_n     (Eq. (11))
-    flops += gs.flops_products;
+    if (scheduled && reduced && o->correction) {
+      // T_n = I + D_n, D_n = -E_n/2 + 3 E_n^2/8 with E_n = X_n - I (Eq. (9) expanded)
+      clr_matrix *E = nullptr, *E2 = nullptr, *P = nullptr, *R = nullptr;
+      if (s == CLR_OK) s = clr_axpby(ctx, 1.0, X, 0.0, nullptr, -1.0, &g64, &E);
+      if (s == CLR_OK) s = gemm_impl(ctx, E, E, gr, &E2, &gs);
+      flops += gs.flops_products;
+      if (s == CLR_OK) s = clr_axpby(ctx, -0.5, E, 3.0 / 8.0, E2, 0.0, &g64, &T);   // T holds D_n
+      if (s == CLR_OK) s = gemm_impl(ctx, Z, T, gr, &P, &gs);                        // Z_n D_n
+      flops += gs.flops_products;
+      if (s == CLR_OK) s = clr_axpby(ctx, 1.0, Z, 1.0, P, 0.0, &g64, &Zn);          // Eq. (10)
+      if (s == CLR_OK) s = gemm_impl(ctx, T, Y, gr, &R, &gs);                        // D_n Y_n
+      flops += gs.flops_products;
+      if (s == CLR_OK) s = clr_axpby(ctx, 1.0, Y, 1.0, R, 0.0, &g64, &Yn);          // Eq. (11)
+      free_matrix(E);
+      free_matrix(E2);
+      free_matrix(P);
+      free_matrix(R);
+    } else {
+      if (s == CLR_OK) s = gemm_impl(ctx, X, X, gr, &Q, &gs);  // X_n^2
+      flops += gs.flops_products;
+      if (s == CLR_OK) s = clr_axpby(ctx, -10.0 / 8.0, X, 3.0 / 8.0, Q, 15.0 / 8.0, &g64, &T);  // Eq. (9)
+      if (s == CLR_OK) s = gemm_impl(ctx, Z, T, gr, &Zn, &gs);  // Z_{n+1} = Z_n T_n     (Eq. (10))
+      flops += gs.flops_products;
+      if (s == CLR_OK) s = gemm_impl(ctx, T, Y, gr, &Yn, &gs);  // Y_{n+1} = T_n Y_n     (Eq. (11))
+      flops += gs.flops_products;
+    }
     if (s == CLR_OK) s = clr_identity_residual(ctx, X, &r);
     n_gemms += 4;
     free_matrix(X);
@@ -1928,6 +1995,8 @@ extern "C" clr_status clr_sqrt_inv_backward(clr_context* ctx, const clr_matrix* 
   if (!S->square_blocked()) return fail(ctx, CLR_ERR_SHAPE, "S must be square-blocked");
   if (iters < 1 || checkpoint_every < 1 || !(o->alpha >= 0.0))
     return fail(ctx, CLR_ERR_INVALID_ARG, "bad iteration options");
+  if (o->reduced_below != 0.0 || o->correction != 0)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "the adjoint unrolls the iteration as printed (no precision schedule)");
   if (ld < S->rows) return fail(ctx, CLR_ERR_INVALID_ARG, "ld < N");
   double alpha = o->alpha;
   if (alpha == 0.0) {

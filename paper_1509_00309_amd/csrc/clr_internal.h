@@ -15,7 +15,8 @@ constexpr int kGemmThreads = 256;     // 4 waves, arranged 2 x 2 over the output
 constexpr int kF64WaveTiles = 5;      // 16x16 MFMA tiles per wave and dimension (FP64 form)
 constexpr int kF32WaveTiles = 4;      // same for the FP32-MFMA (mixed) form
 constexpr int kMaxItemF64 = 32 * kF64WaveTiles;   // 160: largest output tile edge per item
-constexpr int kMaxItemF32 = 32 * kF32WaveTiles;   // 128
+constexpr int kMaxItemF32 = kMaxItemF64;          // 160: the FP32-MFMA form without correction
+constexpr int kMaxItemF32Split = 32 * kF32WaveTiles;   // 128: with the hi*lo + lo*hi products
 constexpr int kMaxItemOzaki = 64;                  // item edge of the INT8 (operand-split) form
 constexpr int kOzMaxSlices = 7;                    // digits per operand in that form
 constexpr int kRecThreads = 512;      // recompression workgroup (32 groups of 16 lanes)
@@ -268,5 +269,10 @@ hipError_t launch_transpose(const MatView& A, const MatView& T, double* tarena, 
                             int* trank, double* tnorm, hipStream_t s);
 hipError_t launch_mask_dense(const MatView& M, double* out, int64_t ld, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+// Measurement kernels (k_peaks.hip): a chain of FP64 MFMAs per wave (4 waves
+// per workgroup) and a plain copy of n_doubles (even) doubles.
+double mfma_loop_flops(int blocks, int iters);
+hipError_t launch_mfma_loop(int blocks, int iters, double* sink, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, int64_t n_doubles, hipStream_t s);
 
 }  // namespace clr

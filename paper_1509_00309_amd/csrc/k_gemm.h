@@ -10,7 +10,7 @@
 // with a two-deep pipeline, and multiplies on MFMA:
 //   FP64 form:  v_mfma_f64_16x16x4_f64, FP64 accumulation in registers.
 //   Mixed form: v_mfma_f32_16x16x4_f32 on FP32-rounded operands, the FP32
-//               partial of every 16 inner indices is added into FP64
+//               partial of every 32 inner indices is added into FP64
 //               accumulators; optionally the hi*lo + lo*hi correction terms
 //               (lo = fp32(x - hi)) go to a second FP32 partial.
 //
@@ -18,8 +18,8 @@
 // SIMD, so one computes while the other stages operands or waits at the slab
 // barrier); wave (wr, wc) owns the 16 x 16 output tiles (wr + 2a, wc + 4b),
 // a < NA, b < NB, where NA, NB are the item's valid tile counts for that wave
-// (at most 5 x 3 of the 10 x 10 tiles of the FP64 form, 4 x 2 of the 8 x 8
-// tiles of the mixed form).  The item loop is instantiated per (NA, NB) and
+// (at most 5 x 3 of the 10 x 10 tiles of the FP64 form and of the plain
+// FP32 form, 4 x 2 of the 8 x 8 tiles of the corrected FP32 form).  The item loop is instantiated per (NA, NB) and
 // selected once per item by a scalar switch, so no MFMA sits behind a
 // per-tile branch and each variant keeps only its own accumulators live.
 //
@@ -55,29 +55,33 @@ constexpr int kSegCache = 96;  // segment descriptors of an item kept in LDS
 typedef const Seg __attribute__((address_space(1))) gseg;   // descriptors in global memory
 typedef const Seg __attribute__((address_space(3))) lseg;   // descriptors cached in LDS
 
-// Wave grid and tiles of the LDS kernel per precision: WR x WC waves, a wave
-// owns up to TA x TB of the TILES x TILES tiles of 16 x 16.
-template <bool F32>
-struct GemmCfg;
-template <>
-struct GemmCfg<false> {
+// Wave grid and tiles of the LDS kernel per form: WR x WC waves, a wave owns
+// up to TA x TB of the TILES x TILES tiles of 16 x 16.  The FP64 form and the
+// FP32-MFMA form without correction products take items of up to 160 x 160
+// (every block of the 96..160 workloads in one item); the corrected FP32 form
+// holds a second FP32 partial per tile and keeps to 128 x 128.
+template <bool F32, bool SPLIT>
+struct GemmCfg {
   static constexpr int WR = 2, WC = 4, TA = 5, TB = 3, TILES = 10;   // 160 x 160
 };
 template <>
-struct GemmCfg<true> {
+struct GemmCfg<true, true> {
   static constexpr int WR = 2, WC = 4, TA = 4, TB = 2, TILES = 8;    // 128 x 128
 };
 constexpr int kLdsGemmThreads = 512;
+// FP32 partials of the mixed form are added into the FP64 accumulators every
+// kF32FlushSlabs slabs (32 inner indices).
+constexpr int kF32FlushSlabs = 2;
 
-template <bool F32>
+template <bool F32, bool SPLIT>
 struct GemmLds {
-  static constexpr int TM = 16 * GemmCfg<F32>::TILES;
+  static constexpr int TM = 16 * GemmCfg<F32, SPLIT>::TILES;
   static constexpr int LD = TM + 1;  // odd stride: k-fast stores hit distinct banks
   using T = typename std::conditional<F32, float, double>::type;
   T a[2][kSlabK][LD];
   T b[2][kSlabK][LD];
-  T alo[F32 ? 2 : 1][F32 ? kSlabK : 1][F32 ? LD : 1];
-  T blo[F32 ? 2 : 1][F32 ? kSlabK : 1][F32 ? LD : 1];
+  T alo[SPLIT ? 2 : 1][SPLIT ? kSlabK : 1][SPLIT ? LD : 1];
+  T blo[SPLIT ? 2 : 1][SPLIT ? kSlabK : 1][SPLIT ? LD : 1];
   // per inner-row source descriptors of the slabs in flight
   const double* lp[2][kSlabK];
   const double* rp[2][kSlabK];
@@ -155,9 +159,12 @@ __device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ s
 // whole chain).
 template <bool F32, bool SPLIT, int NA, int NB, typename Mid>
 __device__ __attribute__((always_inline)) inline void slab_mfma(
-    GemmLds<F32>& sh, int cur, int wr, int wc, int kr, int lc,
-    d4 (&acc)[GemmCfg<F32>::TA][GemmCfg<F32>::TB], Mid&& mid) {
-  constexpr int WR = GemmCfg<F32>::WR, WC = GemmCfg<F32>::WC;
+    GemmLds<F32, SPLIT>& sh, int cur, int wr, int wc, int kr, int lc,
+    d4 (&acc)[GemmCfg<F32, SPLIT>::TA][GemmCfg<F32, SPLIT>::TB],
+    f4 (&p)[GemmCfg<F32, SPLIT>::TA][GemmCfg<F32, SPLIT>::TB],
+    f4 (&pl)[SPLIT ? GemmCfg<F32, SPLIT>::TA : 1][SPLIT ? GemmCfg<F32, SPLIT>::TB : 1], bool flush,
+    Mid&& mid) {
+  constexpr int WR = GemmCfg<F32, SPLIT>::WR, WC = GemmCfg<F32, SPLIT>::WC;
   if constexpr (!F32) {
     // operands of 4-step q + 1 are read from LDS while the MFMAs of q run
     // (two operand sets instead of the whole slab's)
@@ -187,18 +194,6 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(
       __builtin_amdgcn_sched_barrier(0);
     }
   } else {
-    f4 p[NA][NB];
-    f4 pl[SPLIT ? NA : 1][SPLIT ? NB : 1];
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) p[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    if constexpr (SPLIT) {
-#pragma unroll
-      for (int a = 0; a < NA; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) pl[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    }
 #pragma unroll
     for (int q = 0; q < kSlabK / 4; ++q) {
       float av[NA], bv[NB];
@@ -229,17 +224,22 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(
       mid(q);
       __builtin_amdgcn_sched_barrier(0);
     }
-    // FP64 flush of this slab's FP32 partials
+    // FP64 flush of the FP32 partials (every kF32FlushSlabs slabs and after the last)
+    if (flush) {
 #pragma unroll
-    for (int a = 0; a < NA; ++a)
+      for (int a = 0; a < NA; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NB; ++b) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          double add = (double)p[a][b][v];
-          if constexpr (SPLIT) add += (double)pl[a][b][v];
-          acc[a][b][v] += add;
+          for (int v = 0; v < 4; ++v) {
+            double add = (double)p[a][b][v];
+            if constexpr (SPLIT) add += (double)pl[a][b][v];
+            acc[a][b][v] += add;
+          }
+          p[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+          if constexpr (SPLIT) pl[a][b] = f4{0.f, 0.f, 0.f, 0.f};
         }
+    }
   }
 }
 
@@ -254,14 +254,14 @@ __device__ __attribute__((always_inline)) inline void slab_mfma(
 // of slab s + 2.  Every load thus has a whole slab of MFMA work to land, and
 // the staging stores run while the matrix pipe is busy instead of after it.
 template <bool F32, bool SPLIT, int NA, int NB>
-__device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
+__device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32, SPLIT>& sh,
                                                                 const GemmItem& it,
                                                                 const Seg* __restrict__ segs,
                                                                 int wr, int wc) {
-  using CF = GemmCfg<F32>;
+  using CF = GemmCfg<F32, SPLIT>;
   constexpr int WR = CF::WR, WC = CF::WC;
-  constexpr int TM = GemmLds<F32>::TM;
-  constexpr int LD = GemmLds<F32>::LD;
+  constexpr int TM = GemmLds<F32, SPLIT>::TM;
+  constexpr int LD = GemmLds<F32, SPLIT>::LD;
   constexpr int NE = TM / 32;  // staged elements per thread and operand
   static_assert(kSlabK == 16 && kLdsGemmThreads == 512, "staging map assumes 16 x 32 threads");
   const int tid = threadIdx.x;
@@ -269,10 +269,17 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
   const int nslab = (it.ktotal + kSlabK - 1) / kSlabK;
 
   d4 acc[CF::TA][CF::TB];
+  // FP32 partials of the mixed form (unused in the FP64 form)
+  f4 p[CF::TA][CF::TB];
+  f4 pl[SPLIT ? CF::TA : 1][SPLIT ? CF::TB : 1];
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NB; ++b) {
+      acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+      if constexpr (F32) p[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (SPLIT) pl[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    }
 
   int cursor = 0;  // meaningful for tid < 16 only
   // Inner row `tid` of slab `slab`: its operand pointers, strides and scale
@@ -392,7 +399,8 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
         }
       };
       if constexpr (NA > 0 && NB > 0) {
-        slab_mfma<F32, SPLIT, NA, NB>(sh, cur, wr, wc, kr, lc, acc, mid);
+        const bool flush = (s % kF32FlushSlabs) == kF32FlushSlabs - 1 || s + 1 == nslab;
+        slab_mfma<F32, SPLIT, NA, NB>(sh, cur, wr, wc, kr, lc, acc, p, pl, flush, mid);
       } else {
         mid(0);
         mid(1);
@@ -428,11 +436,11 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32>& sh,
 }
 
 template <bool F32, bool SPLIT, int NA>
-__device__ __attribute__((always_inline)) inline void run_nb(GemmLds<F32>& sh,
+__device__ __attribute__((always_inline)) inline void run_nb(GemmLds<F32, SPLIT>& sh,
                                                               const GemmItem& it,
                                                               const Seg* __restrict__ segs,
                                                               int wr, int wc, int nb) {
-  constexpr int TB = GemmCfg<F32>::TB;
+  constexpr int TB = GemmCfg<F32, SPLIT>::TB;
   static_assert(TB >= 2 && TB <= 3, "column dispatch covers 2 or 3 tiles per wave");
   switch (nb) {
     case 0: run_item<F32, SPLIT, NA, 0>(sh, it, segs, wr, wc); break;
@@ -450,8 +458,8 @@ __global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __
                                                               const Seg* __restrict__ segs,
                                                               int nitems,
                                                               const int* __restrict__ order) {
-  using CF = GemmCfg<F32>;
-  __shared__ GemmLds<F32> sh;
+  using CF = GemmCfg<F32, SPLIT>;
+  __shared__ GemmLds<F32, SPLIT> sh;
 
   // With an order (items by decreasing cost), workgroup b runs item order[b]:
   // the dispatcher deals workgroups to the 8 XCDs round-robin, so the long
