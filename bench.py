@@ -166,6 +166,18 @@ def explicit_residual(ctx, W, S):
     return ctx.identity_residual(WSW)
 
 
+# S^-1/2 forms: FP64; the mixed form with its precision schedule (FP64 products until
+# ||X_n - I||_F/sqrt(N) <= 0.3, then X_n in FP64 and the other products on FP32 MFMA in the
+# correction form T = I + D); the mixed form with every product on FP32 MFMA (hi/lo split); and
+# the operand-split form (7 digits).
+SQRTINV_FORMS = {
+    "fp64": {"precision": "fp64"},
+    "mixed": {"precision": "mixed", "split": 0, "reduced_below": 0.3, "correction": True},
+    "mixed_every_product": {"precision": "mixed", "split": 1},
+    "ozaki": {"precision": "ozaki"},
+}
+
+
 def run_sqrtinv(ctx, n, forms, log_fn):
     """S^-1/2 to convergence, per form: time, iterations, residuals, GEMM throughput."""
     import torch
@@ -178,22 +190,20 @@ def run_sqrtinv(ctx, n, forms, log_fn):
     out = {}
     dense_w = {}
     for form in forms:
-        split = 1 if form == "mixed" else 0   # compensated products: FP64-level accuracy
-        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, precision=form, split=split,
-                             allow_not_converged=True)
+        kw = SQRTINV_FORMS[form]
+        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True, **kw)
         del W   # untimed run
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, precision=form, split=split,
-                             allow_not_converged=True)
+        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True, **kw)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         d = st.as_dict()
         out[form] = {
+            "options": kw,
             "ms_total": wall * 1e3,
             "iterations": d["iterations"],
             "converged": bool(d["converged"]),
-            "split_products": bool(split),
             "internal_residual": d["internal_residual"],
             "explicit_residual": d["explicit_residual"],
             "n_gemms": d["n_gemms"],
@@ -435,9 +445,9 @@ def sampled_error(sample, dense, offs):
     return math.sqrt(num / den) if den > 0 else 0.0
 
 
-def run_sqrtinv_scale(ctx, n, nclusters, log_fn):
+def run_sqrtinv_scale(ctx, n, nclusters, forms, log_fn):
     """S^-1/2 of the at-scale workload: the dense input generated on the device (never on the
-    host), compressed there, then one timed run of the FP64 iteration to convergence."""
+    host), compressed there, then one timed run per form to convergence."""
     import torch
     from workloads import lattice_3d_wide
     wl = lattice_3d_wide(n, nclusters)
@@ -450,31 +460,43 @@ def run_sqrtinv_scale(ctx, n, nclusters, log_fn):
     log_fn(f"  N={n}: input generated and compressed in {time.perf_counter() - t0:.1f} s; "
            f"{int(np.sum(kind != 0))} nonzero blocks of {kind.size}, {int(np.sum(kind == 2))} low rank")
     conv = wl.extra["conv_tol"]
-    # a warm-up product of the same size (kernel code objects, workspace)
-    C = ctx.gemm(S, S, wl.tol, wl.eps_sp)
-    del C
+    # a warm-up product of the same size per form (kernel code objects, workspace)
+    for prec in ("fp64", "mixed"):
+        C = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision=prec)
+        del C
     torch.cuda.synchronize()
     out = {}
-    t0 = time.perf_counter()
-    W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    d = st.as_dict()
-    out["fp64"] = {
-        "ms_total": wall * 1e3,
-        "iterations": d["iterations"],
-        "converged": bool(d["converged"]),
-        "internal_residual": d["internal_residual"],
-        "explicit_residual": d["explicit_residual"],
-        "error": {"explicit_residual": d["explicit_residual"],
-                  "oracle": "unpinned at this size; the same physics at N = 1536 is compared with "
-                            "the oracle block by block in tests (iterations, status, residuals)"},
-        "n_gemms": d["n_gemms"],
-        "gemm_tflops": d["flops_products"] / wall / 1e12,
-        "paper_convention_tflops": 4 * d["iterations"] * 2.0 * float(n) ** 3 / wall / 1e12,
-    }
-    log_fn(f"  S^-1/2 N={n} fp64: {out['fp64']}")
-    del W, S
+    Wref = None
+    for form in forms:
+        kw = SQRTINV_FORMS[form]
+        t0 = time.perf_counter()
+        W, st = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d = st.as_dict()
+        out[form] = {
+            "options": kw,
+            "ms_total": wall * 1e3,
+            "iterations": d["iterations"],
+            "converged": bool(d["converged"]),
+            "internal_residual": d["internal_residual"],
+            "explicit_residual": d["explicit_residual"],
+            "error": {"explicit_residual": d["explicit_residual"],
+                      "oracle": "unpinned at this size; the same physics at N = 1536 is compared with "
+                                "the oracle block by block in tests (iterations, status, residuals)"},
+            "n_gemms": d["n_gemms"],
+            "gemm_tflops": d["flops_products"] / wall / 1e12,
+            "paper_convention_tflops": 4 * d["iterations"] * 2.0 * float(n) ** 3 / wall / 1e12,
+        }
+        Wd = W.to_dense()
+        if Wref is None:
+            Wref = Wd
+        else:
+            out[form]["rel_diff_vs_" + forms[0]] = float(torch.linalg.norm(Wd - Wref) /
+                                                         torch.linalg.norm(Wref))
+        del W, Wd
+        log_fn(f"  S^-1/2 N={n} {form}: {out[form]}")
+    del Wref, S
     torch.cuda.synchronize()
     return {"workload": f"S^-1/2, N={n} 3D lattice (spacing 1.2, jitter 0.3) overlap-like "
                         f"exp(-0.2 r^2)+0.05 delta, {nclusters} clusters 128+-U{{-32..32}}, "
@@ -635,6 +657,10 @@ def main():
     ap.add_argument("--sqrtinv-scale-n", type=int, default=32768,
                     help="N of the at-scale S^-1/2 leg (0 skips it)")
     ap.add_argument("--sqrtinv-scale-clusters", type=int, default=256)
+    ap.add_argument("--sqrtinv-scale-forms", default="fp64,mixed",
+                    help="forms of the at-scale S^-1/2 leg (keys of SQRTINV_FORMS)")
+    ap.add_argument("--sqrtinv-forms", default="fp64,mixed,mixed_every_product,ozaki",
+                    help="forms of the N = 8192 S^-1/2 leg (keys of SQRTINV_FORMS)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-line", action="store_true")
     ap.add_argument("--no-peaks", action="store_true")
@@ -705,12 +731,13 @@ def main():
     scale = None
     if args.sqrtinv_scale_n > 0:
         log(f"S^-1/2 at N={args.sqrtinv_scale_n}")
-        scale = run_sqrtinv_scale(ctx, args.sqrtinv_scale_n, args.sqrtinv_scale_clusters, log)
+        scale = run_sqrtinv_scale(ctx, args.sqrtinv_scale_n, args.sqrtinv_scale_clusters,
+                                  args.sqrtinv_scale_forms.split(","), log)
 
     sqrtinv = None
     if not args.no_sqrtinv:
         log(f"S^-1/2 at N={args.sqrtinv_n}")
-        sqrtinv = run_sqrtinv(ctx, args.sqrtinv_n, [f for f in args.forms.split(",")], log)
+        sqrtinv = run_sqrtinv(ctx, args.sqrtinv_n, args.sqrtinv_forms.split(","), log)
 
     adjoint = None
     if not args.no_adjoint:

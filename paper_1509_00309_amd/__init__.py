@@ -452,15 +452,41 @@ def _functions():
     return _FN
 
 
-def gemm_dense(ctx: Context, A: CLRMatrix, B: CLRMatrix, a_dense, b_dense, **kw):
+def _check_stand_in(name, t, M: CLRMatrix, verify_tol):
+    """A dense stand-in must have its handle's shape, be FP64 on the GPU and,
+    with verify_tol set, equal the matrix the handle represents to that
+    relative Frobenius tolerance (the product's result depends on the
+    handle only, so a mismatched stand-in would get a gradient that belongs
+    to another matrix)."""
+    torch = _torch()
+    if tuple(t.shape) != (M.rows, M.cols):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} does not match the handle's "
+                         f"{(M.rows, M.cols)}")
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise ValueError(f"{name}: expected a float64 tensor on the GPU, got {t.dtype} on {t.device}")
+    if verify_tol is not None:
+        ref = M.to_dense()
+        err = float(torch.linalg.norm(t.detach() - ref)) / max(float(torch.linalg.norm(ref)), 1e-300)
+        if err > verify_tol:
+            raise ValueError(f"{name}: differs from the matrix its handle represents by {err:.3e} "
+                             f"(relative Frobenius) > {verify_tol:.1e}")
+
+
+def gemm_dense(ctx: Context, A: CLRMatrix, B: CLRMatrix, a_dense, b_dense, verify_tol=None, **kw):
     """Dense C = A B (CLR product) differentiable w.r.t. a_dense / b_dense.
 
-    a_dense and b_dense stand for the matrices A and B represent (their values
-    are not read); gradients come from the library's adjoint."""
+    a_dense and b_dense stand for the matrices A and B represent: the values
+    are taken from the handles and gradients come from the library's adjoint.
+    Shapes, dtype and device are always checked; with verify_tol the values
+    are compared with the handles' dense forms too (ValueError beyond it)."""
+    _check_stand_in("a_dense", a_dense, A, verify_tol)
+    _check_stand_in("b_dense", b_dense, B, verify_tol)
     return _functions()["gemm"].apply(a_dense, b_dense, ctx, A, B, kw)
 
 
 def sqrt_inv_dense(ctx: Context, S: CLRMatrix, s_dense, iters: int, checkpoint_every: int = 5,
-                   **kw):
-    """Dense W = S^-1/2 after `iters` unrolled iterations, differentiable w.r.t. s_dense."""
+                   verify_tol=None, **kw):
+    """Dense W = S^-1/2 after `iters` unrolled iterations, differentiable w.r.t. s_dense
+    (a stand-in for the matrix S represents, checked as in gemm_dense)."""
+    _check_stand_in("s_dense", s_dense, S, verify_tol)
     return _functions()["sqrt_inv"].apply(s_dense, ctx, S, iters, checkpoint_every, kw)

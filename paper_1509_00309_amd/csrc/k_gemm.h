@@ -51,7 +51,8 @@ __device__ inline int64_t uni64(int64_t v) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-constexpr int kSegCache = 96;  // segment descriptors of an item kept in LDS
+constexpr int kSegCache = 96;  // segment descriptors of an item kept in LDS (operand-split kernel)
+constexpr int kSegCacheLds = 256;  // same in the LDS GEMM kernel
 typedef const Seg __attribute__((address_space(1))) gseg;   // descriptors in global memory
 typedef const Seg __attribute__((address_space(3))) lseg;   // descriptors cached in LDS
 
@@ -88,18 +89,19 @@ struct GemmLds {
   int64_t sli[2][kSlabK];
   int64_t srj[2][kSlabK];
   double scale[2][kSlabK];   // L scale of the row; 0 for rows past the item
-  Seg segs[kSegCache];
+  Seg segs[kSegCacheLds];
 };
 
 // Thread t < 16 resolves inner row t of slab `slab`: which segment it falls in
 // and where its L column / R row start.  `cur` is that thread's segment cursor
-// (monotone over slabs).  The first kSegCache descriptors come from LDS.  A
-// row past the item gets the first segment's operands with zero strides and
+// (monotone over slabs).  With kAll, `cache` holds every descriptor of the
+// item; otherwise the first kSegCache come from it and the rest from `segs`.
+// A row past the item gets the first segment's operands with zero strides and
 // zero weights, so every address the loader forms is valid.
 // CacheP is the type of the cached-descriptor pointer: an LDS-qualified
 // pointer in the LDS kernel (so its loads stay LDS loads), a plain pointer
 // where the "cache" is global memory.
-template <typename CacheP>
+template <typename CacheP, bool kAll = false>
 __device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ segs,
                                    CacheP cache, int slab, int t, int& cur,
                                    const double*& lp, const double*& rp, int64_t& sli,
@@ -117,7 +119,7 @@ __device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ s
   // would be generic, and flat loads also wait on the global-load counter).
   while (cur < it.nseg) {
     int kend;
-    if (cur < kSegCache) {
+    if (kAll || cur < kSegCache) {
       kend = cache[cur].kbase + cache[cur].k;
     } else {
       const gseg* sg = (const gseg*)(segs + it.seg0 + cur);
@@ -132,7 +134,7 @@ __device__ inline void resolve_row(const GemmItem& it, const Seg* __restrict__ s
   int64_t sLi, sLk, sRk, sRj;
   int kbase;
   double scale;
-  if (cur < kSegCache) {
+  if (kAll || cur < kSegCache) {
     const auto& s = cache[cur];
     L = s.L; R = s.R; sLi = s.sLi; sLk = s.sLk; sRk = s.sRk; sRj = s.sRj; kbase = s.kbase;
     scale = s.scale;
@@ -284,13 +286,22 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32, SPLI
   int cursor = 0;  // meaningful for tid < 16 only
   // Inner row `tid` of slab `slab`: its operand pointers, strides and scale
   // go to descriptor buffer `d` (two buffers, by slab parity).
+  // Every term descriptor comes from the LDS cache when the item has at most
+  // kSegCacheLds terms (the choice is uniform over the item), else from global
+  // memory: a lane-by-lane mix of the two would make each lookup wait for all of
+  // the wave's global loads, the operand prefetch included.
   auto resolve = [&](int slab, int d) {
     if (tid < kSlabK) {
       const double* lp;
       const double* rp;
       int64_t sli, srj;
       double sc, bok;
-      resolve_row(it, segs, (lseg*)sh.segs, slab, tid, cursor, lp, rp, sli, srj, sc, bok);
+      if (it.nseg <= kSegCacheLds)
+        resolve_row<lseg*, true>(it, segs, (lseg*)sh.segs, slab, tid, cursor, lp, rp, sli, srj, sc,
+                                 bok);
+      else
+        resolve_row<gseg*, true>(it, segs, (gseg*)(segs + it.seg0), slab, tid, cursor, lp, rp, sli,
+                                 srj, sc, bok);
       sh.lp[d][tid] = lp;
       sh.rp[d][tid] = rp;
       sh.sli[d][tid] = sli;
@@ -314,24 +325,52 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32, SPLI
   double ra[NE], rb[NE];
   int aoff = 0, boff = 0;   // LDS offsets (inner row * LD + first element) of the staged values
   double sc = 0.0;          // term scale of the thread's L row
-  auto load_a = [&](int d) {
-    const bool arow = uni(sh.sli[d][0] == 1);
-    const int ta = arow ? tid >> 5 : tid & 15;
-    const int ia0 = arow ? tid & 31 : tid >> 4;
-    gdouble* pa = as_global(sh.lp[d][ta]);
-    const int sa = (int)sh.sli[d][ta];
+  // Descriptors of the slab to load next, read at the top of a slab so their
+  // LDS latency passes under its first MFMA step.  Both candidate rows of the
+  // staging map (row-fast: tid / 32, inner-fast: tid % 16) are read
+  // unconditionally, so no read waits for another; the map is chosen when
+  // the loads are issued.
+  struct Desc {
+    int64_t s0;                 // stride of inner row 0 (selects the map)
+    const double* p[2];         // operand pointers of the two candidate rows
+    int64_t st[2];              // their strides along the tile
+    double sc[2];               // their term scales (L only)
+  };
+  Desc da, db;
+  const int t_row = tid >> 5, i_row = tid & 31;   // row-fast map
+  const int t_inn = tid & 15, i_inn = tid >> 4;   // inner-fast map
+  auto prep = [&](int d) {
+    da.s0 = sh.sli[d][0];
+    da.p[0] = sh.lp[d][t_row];
+    da.p[1] = sh.lp[d][t_inn];
+    da.st[0] = sh.sli[d][t_row];
+    da.st[1] = sh.sli[d][t_inn];
+    da.sc[0] = sh.scale[d][t_row];
+    da.sc[1] = sh.scale[d][t_inn];
+    db.s0 = sh.srj[d][0];
+    db.p[0] = sh.rp[d][t_row];
+    db.p[1] = sh.rp[d][t_inn];
+    db.st[0] = sh.srj[d][t_row];
+    db.st[1] = sh.srj[d][t_inn];
+  };
+  auto load_a = [&]() {
+    const bool arow = da.s0 == 1;
+    const int ta = arow ? t_row : t_inn;
+    const int ia0 = arow ? i_row : i_inn;
+    gdouble* pa = as_global(arow ? da.p[0] : da.p[1]);
+    const int sa = (int)(arow ? da.st[0] : da.st[1]);
     const int mlast = it.m - 1;
 #pragma unroll
     for (int u = 0; u < NE; ++u) ra[u] = pa[min(ia0 + 32 * u, mlast) * sa];
     aoff = ta * LD + ia0;
-    sc = sh.scale[d][ta];
+    sc = arow ? da.sc[0] : da.sc[1];
   };
-  auto load_b = [&](int d) {
-    const bool brow = uni(sh.srj[d][0] == 1);
-    const int tb = brow ? tid >> 5 : tid & 15;
-    const int ib0 = brow ? tid & 31 : tid >> 4;
-    gdouble* pb = as_global(sh.rp[d][tb]);
-    const int sb = (int)sh.srj[d][tb];
+  auto load_b = [&]() {
+    const bool brow = db.s0 == 1;
+    const int tb = brow ? t_row : t_inn;
+    const int ib0 = brow ? i_row : i_inn;
+    gdouble* pb = as_global(brow ? db.p[0] : db.p[1]);
+    const int sb = (int)(brow ? db.st[0] : db.st[1]);
     const int nlast = it.n - 1;
 #pragma unroll
     for (int u = 0; u < NE; ++u) rb[u] = pb[min(ib0 + 32 * u, nlast) * sb];
@@ -372,13 +411,15 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32, SPLI
     resolve(0, 0);
     if (nslab > 1) resolve(1, 1);
     __syncthreads();
-    load_a(0);
-    load_b(0);
+    prep(0);
+    load_a();
+    load_b();
     store_a(0);
     store_b(0);
     if (nslab > 1) {
-      load_a(1);
-      load_b(1);
+      prep(1);
+      load_a();
+      load_b();
     }
     __syncthreads();                 // buffer 0 holds slab 0; descriptors 0 and 1 consumed
     if (nslab > 2) resolve(2, 0);
@@ -386,16 +427,17 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32, SPLI
     for (int s = 0; s < nslab; ++s) {
       const int cur = s & 1, nxt = cur ^ 1;
       // descriptors of slab s + 2 sit in buffer s & 1, those of s + 1 were consumed
-      if (s + 3 < nslab) resolve(s + 3, nxt);
       const bool st_next = s + 1 < nslab, ld_next = s + 2 < nslab;
+      if (ld_next) prep(cur);
+      if (s + 3 < nslab) resolve(s + 3, nxt);
       auto mid = [&](int q) {
         if (q == 0 && st_next) {
           store_a(nxt);
-          if (ld_next) load_a(cur);
+          if (ld_next) load_a();
         }
         if (q == 1 && st_next) {
           store_b(nxt);
-          if (ld_next) load_b(cur);
+          if (ld_next) load_b();
         }
       };
       if constexpr (NA > 0 && NB > 0) {
@@ -498,7 +540,7 @@ __global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __
   const int na = min(CF::TA, max(0, (mt - wr + CF::WR - 1) / CF::WR));
   const int nb = min(CF::TB, max(0, (nt - wc + CF::WC - 1) / CF::WC));
 
-  const int ncache = min(it.nseg, kSegCache);
+  const int ncache = it.nseg <= kSegCacheLds ? it.nseg : 0;
   for (int s = tid; s < ncache; s += kLdsGemmThreads) sh.segs[s] = segs[it.seg0 + s];
   __syncthreads();
 

@@ -764,6 +764,27 @@ def test_autograd_entry_points(ctx, torch):
     assert torch.equal(s.grad, dS)
 
 
+def test_autograd_stand_in_checks(ctx, torch):
+    """The dense stand-ins of gemm_dense / sqrt_inv_dense are checked against their handles:
+    shape and dtype always, values on request."""
+    import paper_1509_00309_amd as clr
+    rs = [24, 40, 16]
+    ra = random_blocks(405, rs, rs, p_zero=0.2, p_dense=0.5, max_rank=6)
+    A = gpu_from_random(ctx, torch, ra)
+    a = A.to_dense().clone().requires_grad_(True)
+    with pytest.raises(ValueError, match="shape"):
+        clr.gemm_dense(ctx, A, A, a[:, :-1], a, tol=0.0, eps_sp=0.0)
+    with pytest.raises(ValueError, match="float64"):
+        clr.gemm_dense(ctx, A, A, a.float(), a, tol=0.0, eps_sp=0.0)
+    other = (a.detach() + 1e-3 * torch.ones_like(a)).requires_grad_(True)
+    with pytest.raises(ValueError, match="differs"):
+        clr.gemm_dense(ctx, A, A, other, a, verify_tol=1e-12, tol=0.0, eps_sp=0.0)
+    Cd = clr.gemm_dense(ctx, A, A, a, a, verify_tol=1e-14, tol=0.0, eps_sp=0.0)
+    assert Cd.shape == a.shape
+    with pytest.raises(ValueError, match="differs"):
+        clr.sqrt_inv_dense(ctx, A, other, 2, 1, verify_tol=1e-12, tol=1e-8, eps_sp=1e-10)
+
+
 # ---------------------------------------------------------------------------
 # Batches: one launch per phase, HIP graph replay
 # ---------------------------------------------------------------------------
@@ -800,6 +821,29 @@ def test_gemm_batch_matches_single_products(ctx, torch):
         total += s1.flops_products
     assert abs(st.flops_products - total) <= 1e-9 * total
     log(f"  {len(ops)} products, {st.computed} blocks, {st.flops_products:.3e} flops")
+
+
+def test_gemm_batch_against_oracle(ctx, torch):
+    """Two products of different blockings and physics in one planned batch (one launch per
+    phase for both, replayed as a HIP graph): the 3-D lattice at N = 1536 and the 1-D line at
+    N = 512, both truncated at 1e-8, each against the oracle block by block."""
+    log("gemm batch against the oracle")
+    tol, eps = 1e-8, 1e-10
+    mats, orcs, nbs = [], [], []
+    for wl in (scaled_workload("lattice", 1536, seed=147), line_n512()):
+        Sd = wl.dense()
+        mats.append(ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10))
+        orcs.append(orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10))
+        nbs.append(len(wl.sizes) ** 2)
+    plan = ctx.plan(mats, mats, tol, eps, graph=True)
+    for _ in range(2):
+        plan.execute()
+    for C, O, nb in zip(plan.outputs, orcs, nbs):
+        rep = parity.compare(C, orc.gemm(O, O, tol, eps), tol, exact=orc.gemm(O, O, 0.0, eps),
+                             operands=(O, O))
+        log("  " + parity.summary(rep))
+        parity.assert_parity(rep, FP64_BOUND, nblocks=nb)
+    plan.close()
 
 
 def test_plan_graph_replay(ctx, torch):
