@@ -172,6 +172,7 @@ def explicit_residual(ctx, W, S):
 # the operand-split form (7 digits).
 SQRTINV_FORMS = {
     "fp64": {"precision": "fp64"},
+    "fp64_graph": {"precision": "fp64", "graph": True},
     "mixed": {"precision": "mixed", "split": 0, "reduced_below": 0.3, "correction": True},
     "mixed_every_product": {"precision": "mixed", "split": 1},
     "ozaki": {"precision": "ozaki"},
@@ -210,6 +211,9 @@ def run_sqrtinv(ctx, n, forms, log_fn):
             "gemm_tflops": d["flops_products"] / wall / 1e12,
             "paper_convention_tflops": 4 * d["iterations"] * 2.0 * float(n) ** 3 / wall / 1e12,
         }
+        if kw.get("graph"):
+            out[form]["graph_replays"] = d["graph_replays"]
+            out[form]["graph_captures"] = d["graph_captures"]
         out[form]["error"] = {"explicit_residual": explicit_residual(ctx, W, S),
                               "oracle": "unpinned at this size; the same physics at N = 1536 is "
                                         "compared with the oracle in tests"}
@@ -221,6 +225,7 @@ def run_sqrtinv(ctx, n, forms, log_fn):
         for f, w in dense_w.items():
             if f != "fp64":
                 out[f]["rel_diff_vs_fp64"] = float(torch.linalg.norm(w - ref) / torch.linalg.norm(ref))
+                out[f]["bit_equal_to_fp64"] = bool(torch.equal(w, ref))
     return {"workload": f"S^-1/2, N={n} 3D lattice (spacing 1.2, jitter 0.3) overlap-like "
                         f"exp(-0.2 r^2)+0.05 delta, {len(wl.sizes)} clusters 128+-U{{-32..32}}, "
                         f"tol {wl.tol:g}, screen 1e-10, conv 1e-8",
@@ -584,11 +589,22 @@ def run_line(ctx, budget_s, log_fn, want_cpu):
     W, sst = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True)
     torch.cuda.synchronize()
     ms_si = (time.perf_counter() - t0) * 1e3
+    # the same iteration replayed from a recorded graph (bit-equal result)
+    Wg, gst = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Wg, gst = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, conv_tol=conv, allow_not_converged=True, graph=True)
+    torch.cuda.synchronize()
+    ms_sig = (time.perf_counter() - t0) * 1e3
+    same = bool(torch.equal(Wg.to_dense(), W.to_dense()))
+    del Wg
     out = {"workload": "N=512 points on a line (spacing 1, jitter 0.2), exp(-0.5 r^2)+0.1 delta, "
                        "8 clusters, tol 1e-8, screen 1e-10, conv 1e-10",
            "gpu": {"gemm_ms": ms_gemm, "gemm_tflops": flops / (ms_gemm * 1e-3) / 1e12,
                    "sqrt_inv_ms": ms_si, "iterations": sst.iterations,
-                   "explicit_residual": sst.explicit_residual}}
+                   "explicit_residual": sst.explicit_residual,
+                   "sqrt_inv_graph_ms": ms_sig, "graph_replays": gst.graph_replays,
+                   "graph_result_bit_equal": same}}
     if want_cpu:
         import oracle as orc
         t0 = time.perf_counter()
@@ -659,7 +675,7 @@ def main():
     ap.add_argument("--sqrtinv-scale-clusters", type=int, default=256)
     ap.add_argument("--sqrtinv-scale-forms", default="fp64,mixed",
                     help="forms of the at-scale S^-1/2 leg (keys of SQRTINV_FORMS)")
-    ap.add_argument("--sqrtinv-forms", default="fp64,mixed,mixed_every_product,ozaki",
+    ap.add_argument("--sqrtinv-forms", default="fp64,fp64_graph,mixed,mixed_every_product,ozaki",
                     help="forms of the N = 8192 S^-1/2 leg (keys of SQRTINV_FORMS)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-line", action="store_true")

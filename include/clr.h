@@ -107,6 +107,22 @@ typedef struct {
    * reduced-precision products E_n^2, Z_n D_n, D_n Y_n then carry the small
    * D_n, so their rounding scales with ||X_n - I|| instead of ||T_n||.        */
   int correction;
+  /* graph != 0: one iteration (the four products of Eqs. (8)-(11), the
+   * combination of Eq. (9) and the block terms of ||X_n - I||) is recorded
+   * once as a HIP graph and replayed, each replay with no host read-back or
+   * allocation inside.  The first iteration runs directly and measures its
+   * work-list lengths; the lists of the graph get graph_margin (0 selects 2)
+   * times those lengths.  A replay whose lists would exceed their capacity is
+   * detected on the device (nothing runs past a list's end); that iteration
+   * is redone directly and the graph recorded again with capacities of at
+   * least twice the lengths seen (stats: graph_replays + graph_captures / 2
+   * equals the iteration count).  The results equal those with
+   * graph == 0 bit for bit.  Needs
+   * reduced_below == 0 and g.precision FP64 or MIXED.  The graph's fixed
+   * iterates are allocated for the call; its work lists stay with the context
+   * (grown as needed, released by clr_context_destroy).                      */
+  int graph;
+  double graph_margin;
 } clr_sqrtinv_opts;
 
 typedef struct {
@@ -140,6 +156,8 @@ typedef struct {
   int n_gemms;
   double flops_products;    /* sum over every product of clr_gemm_stats.flops_products  */
   double ms_total;
+  int graph_replays;        /* iterations replayed from a graph (opts.graph)            */
+  int graph_captures;       /* graphs recorded (two per capacity: ping and pong)        */
 } clr_sqrtinv_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -273,9 +291,20 @@ clr_status clr_gemm_backward(clr_context* ctx, const clr_matrix* A, const clr_ma
  * CLR_MIXED) for this context: 0 (default) is the kernel's full tile (dense:
  * 160, or 128 in the mixed form with split = 1; factor products: 64, one wave
  * per item), otherwise a multiple of 16 up to 160 (a larger edge than the
- * kernel's tile is capped to it).  Results do not depend on these edges, only
- * the launch shapes do. */
+ * kernel's tile is capped to it).  Sets the edge of every shape class (below).
+ * Results do not depend on these edges, only the launch shapes do. */
 clr_status clr_set_tile_edges(clr_context* ctx, int precision, int dense_edge, int thin_edge);
+
+/* The same edges per shape class.  Dense-accumulation items are classed by
+ * their block's longer edge: dense_edges[0..5] for (0, 32], (32, 64], (64, 96],
+ * (96, 128], (128, 160] and above 160; factor-product items by the narrow
+ * extent of their output (a rank): thin_edges[0..4] for (0, 8], (8, 16],
+ * (16, 32], (32, 64] and above 64.  Host arrays; values as for
+ * clr_set_tile_edges (0 = full tile).  clr_get_tile_classes reads them back. */
+clr_status clr_set_tile_classes(clr_context* ctx, int precision, const int* dense_edges,
+                                const int* thin_edges);
+clr_status clr_get_tile_classes(const clr_context* ctx, int precision, int* dense_edges,
+                                int* thin_edges);
 
 /* Dense certificate (on by default).  A dense-accumulated block D (m x n,
  * q = min(m, n), h = floor(q / 2)) is stored dense when its kept rank exceeds
@@ -300,11 +329,14 @@ clr_status clr_measure_peaks(clr_context* ctx, double* mfma_f64_tflops, double* 
  * the default, or CLR_COMPRESS_RRQR); products always recompress by SVD. */
 clr_status clr_set_compression(clr_context* ctx, int method);
 
-/* Autotuner: times the product A B (options as for clr_gemm; output discarded)
- * with every candidate edge (multiples of 32 up to the full tile), best of two
- * runs per candidate, and keeps the fastest edge per launch class for this
- * context and precision.  Returns the chosen edges and their launch times (ms);
- * any output pointer may be NULL. */
+/* Autotuner: times the product A B (options as for clr_gemm; output discarded),
+ * best of two runs per candidate.  First one edge per launch class (multiples
+ * of 32 up to the full tile), then each shape class on its own from that choice
+ * (dense classes: multiples of 32; factor-product classes: multiples of 16 up
+ * to 64), keeping an edge only when it shortens its launch by more than 2 %.
+ * The table stays set for this context and precision (clr_get_tile_classes).
+ * Returns the launch-class edges of the first stage and the launch times (ms)
+ * after the second; any output pointer may be NULL. */
 clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
                         const clr_gemm_opts* opts, int* dense_edge, int* thin_edge,
                         double* ms_dense, double* ms_thin);

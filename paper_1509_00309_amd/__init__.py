@@ -184,13 +184,15 @@ class Context:
     def sqrt_inv(self, S: "CLRMatrix", tol: float, eps_sp: float, conv_tol: float = 1e-10,
                  max_iter: int = 50, fixed_iters: int = 0, alpha: float = 0.0, screen="abs",
                  precision="fp64", split: int = 0, allow_not_converged: bool = False,
-                 reduced_below: float = 0.0, correction: bool = False):
+                 reduced_below: float = 0.0, correction: bool = False, graph: bool = False,
+                 graph_margin: float = 0.0):
         """W = S^-1/2 (Newton-Schulz, Eqs. (8)-(11)); returns (W, SqrtInvStats).
 
         An iteration that stops without meeting conv_tol raises ClrError
         (CLR_ERR_NOT_CONVERGED) unless allow_not_converged is set; then W is
         returned and SqrtInvStats.converged is 0.  reduced_below / correction:
-        the precision schedule of the reduced-precision forms (see clr.h)."""
+        the precision schedule of the reduced-precision forms; graph /
+        graph_margin: iterations replayed from a recorded HIP graph (see clr.h)."""
         o = SqrtInvOpts()
         o.g = _gemm_opts(tol, eps_sp, screen, precision, split, 1.0)
         o.alpha = float(alpha)
@@ -199,6 +201,8 @@ class Context:
         o.fixed_iters = int(fixed_iters)
         o.reduced_below = float(reduced_below)
         o.correction = 1 if correction else 0
+        o.graph = 1 if graph else 0
+        o.graph_margin = float(graph_margin)
         h = C.c_void_p()
         st = SqrtInvStats()
         rc = lib.clr_sqrt_inv(self._h, S._h, C.byref(o), C.byref(h), C.byref(st))
@@ -224,8 +228,28 @@ class Context:
         md, mt = C.c_double(), C.c_double()
         self._check(lib.clr_autotune(self._h, A._h, B._h, C.byref(o), C.byref(de), C.byref(te),
                                      C.byref(md), C.byref(mt)))
+        dense, thin = self.get_tile_classes(precision)
         return {"dense_edge": de.value, "thin_edge": te.value, "ms_dense": md.value,
-                "ms_thin": mt.value}
+                "ms_thin": mt.value, "dense_classes": dense, "thin_classes": thin}
+
+    # Shape classes of the item edges (clr.h): dense items by their block's longer edge
+    # (<=32, <=64, <=96, <=128, <=160, >160), factor-product items by their rank
+    # (<=8, <=16, <=32, <=64, >64).
+    DENSE_CLASSES = 6
+    THIN_CLASSES = 5
+
+    def set_tile_classes(self, precision, dense_edges, thin_edges):
+        prec = {"fp64": CLR_FP64, "mixed": CLR_MIXED}[precision]
+        d = (C.c_int * self.DENSE_CLASSES)(*[int(v) for v in dense_edges])
+        t = (C.c_int * self.THIN_CLASSES)(*[int(v) for v in thin_edges])
+        self._check(lib.clr_set_tile_classes(self._h, prec, d, t))
+
+    def get_tile_classes(self, precision="fp64"):
+        prec = {"fp64": CLR_FP64, "mixed": CLR_MIXED}[precision]
+        d = (C.c_int * self.DENSE_CLASSES)()
+        t = (C.c_int * self.THIN_CLASSES)()
+        self._check(lib.clr_get_tile_classes(self._h, prec, d, t))
+        return list(d), list(t)
 
     # -- batches of products ----------------------------------------------------
     def plan(self, As: Sequence["CLRMatrix"], Bs: Sequence["CLRMatrix"], tol: float,

@@ -33,7 +33,8 @@ EXPORTS = [
     "clr_get_block", "clr_to_dense", "clr_gemm", "clr_axpby", "clr_sqrt_inv",
     "clr_identity_residual", "clr_identity_residual_noalloc", "clr_gemm_backward", "clr_sqrt_inv_backward",
     "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
-    "clr_set_tile_edges", "clr_autotune", "clr_set_dense_certificate", "clr_set_compression",
+    "clr_set_tile_edges", "clr_set_tile_classes", "clr_get_tile_classes", "clr_autotune",
+    "clr_set_dense_certificate", "clr_set_compression",
     "clr_kernel_matrix", "clr_measure_peaks",
 ]
 
@@ -46,7 +47,7 @@ class GemmOpts(C.Structure):
 class SqrtInvOpts(C.Structure):
     _fields_ = [("g", GemmOpts), ("alpha", C.c_double), ("conv_tol", C.c_double),
                 ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("reduced_below", C.c_double),
-                ("correction", C.c_int)]
+                ("correction", C.c_int), ("graph", C.c_int), ("graph_margin", C.c_double)]
 
 
 class GemmStats(C.Structure):
@@ -70,7 +71,8 @@ class GemmStats(C.Structure):
 class SqrtInvStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("alpha", C.c_double),
                 ("internal_residual", C.c_double), ("explicit_residual", C.c_double),
-                ("n_gemms", C.c_int), ("flops_products", C.c_double), ("ms_total", C.c_double)]
+                ("n_gemms", C.c_int), ("flops_products", C.c_double), ("ms_total", C.c_double),
+                ("graph_replays", C.c_int), ("graph_captures", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -118,6 +120,8 @@ def _load():
         "clr_plan_execute": [P, P, C.POINTER(GemmStats)],
         "clr_plan_destroy": [P],
         "clr_set_tile_edges": [P, C.c_int, C.c_int, C.c_int],
+        "clr_set_tile_classes": [P, C.c_int, IP, IP],
+        "clr_get_tile_classes": [P, C.c_int, IP, IP],
         "clr_set_dense_certificate": [P, C.c_int],
         "clr_set_compression": [P, C.c_int],
         "clr_kernel_matrix": [P, P, C.c_int64, P, C.c_int64, C.c_int, C.c_int, C.c_double,

@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <mutex>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "clr.h"
@@ -35,18 +36,32 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Workspace of the product and combination pipelines: per-block counts and
+// offsets, the work lists, the thin-product pool, recompression scratch, the
+// dense accumulators and the device-resident list lengths.  The context holds
+// one set for its calls; a captured iteration owns another, whose buffers
+// must not move once a graph has recorded their addresses.
+struct Work {
+  DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
+      items_thin2, pieces, rec, pool, scratch, acc, terms, comb_dense, recg, order, order_thin,
+      sortw, live, flops;
+  clr::Caps seen{};   // largest list lengths of the runs sized on the host
+  double host_flops = 0.0;   // product flops of those runs (their symbolic statistics)
+};
+
 struct clr_context {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
-  DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
-      items_thin2, pieces, rec, pool, scratch, acc, status, terms, aux_items, aux_segs,
-      aux_dense, ptrs, recg, order, order_thin, sortw;
+  Work w;
+  Work gw;   // work lists of graph-replayed iterations (kept between calls, only grown)
+  DevBuf status, ptrs;
   hipEvent_t ev[10] = {};
   // grouped-GEMM item edges per precision (0: the kernel's largest tile), set
   // explicitly or by clr_autotune
-  int tile_dense[2] = {0, 0};
-  int tile_thin[2] = {0, 0};
+  // per precision (0: FP64 and OZAKI, 1: MIXED) and shape class; 0 is the
+  // kernel's full tile
+  clr::EdgeTable tiles[2] = {};
   // dense certificate before the truncated SVD of dense-accumulated blocks
   int dense_cert = 1;
   // clr_compress truncates by column-pivoted QR instead of the SVD
@@ -165,6 +180,14 @@ void free_buf(DevBuf& b) {
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
+}
+
+void free_work(Work& w) {
+  for (DevBuf* b : {&w.cnt, &w.off, &w.st, &w.flags, &w.totals, &w.seg_dense, &w.items_dense,
+                    &w.seg_thin1, &w.items_thin1, &w.seg_thin2, &w.items_thin2, &w.pieces, &w.rec,
+                    &w.pool, &w.scratch, &w.acc, &w.terms, &w.comb_dense, &w.recg, &w.order,
+                    &w.order_thin, &w.sortw, &w.live, &w.flops})
+    free_buf(*b);
 }
 
 template <typename T>
@@ -302,12 +325,17 @@ clr_status check_opts(clr_context* ctx, const clr_gemm_opts* o) {
   return CLR_OK;
 }
 
+// live: optional device-resident item count (n is then the launch's capacity).
 hipError_t run_ggemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
-                     hipStream_t s, bool dense = false, const int* order = nullptr) {
-  if (o->precision == CLR_MIXED) return launch_ggemm_f32(items, segs, n, o->split, s, dense, order);
-  if (o->precision == CLR_OZAKI && dense)
+                     hipStream_t s, bool dense = false, const int* order = nullptr,
+                     const int64_t* live = nullptr) {
+  if (o->precision == CLR_MIXED)
+    return launch_ggemm_f32(items, segs, n, o->split, s, dense, order, live);
+  if (o->precision == CLR_OZAKI && dense) {
+    if (live) return hipErrorNotSupported;   // the INT8 form sizes its launch on the host
     return launch_ggemm_ozaki(items, segs, n, o->split ? o->split : kOzMaxSlices, s, order);
-  return launch_ggemm_f64(items, segs, n, s, dense, order);
+  }
+  return launch_ggemm_f64(items, segs, n, s, dense, order, live);
 }
 
 int max_item(const clr_gemm_opts* o) {
@@ -318,16 +346,22 @@ int max_item(const clr_gemm_opts* o) {
 
 // Factor products (one side a rank) run on the wave-per-item kernel.
 hipError_t run_wgemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
-                     hipStream_t s, const int* order = nullptr) {
-  if (o->precision == CLR_MIXED) return launch_wgemm_f32(items, segs, n, o->split, s, order);
-  return launch_wgemm_f64(items, segs, n, s, order);
+                     hipStream_t s, const int* order = nullptr, const int64_t* live = nullptr) {
+  if (o->precision == CLR_MIXED) return launch_wgemm_f32(items, segs, n, o->split, s, order, live);
+  return launch_wgemm_f64(items, segs, n, s, order, live);
 }
 
-int tile_edge(const clr_context* ctx, const clr_gemm_opts* o, bool thin) {
-  const int pi = o->precision == CLR_MIXED ? 1 : 0;   // OZAKI shares the FP64 edges, capped
-  const int v = thin ? ctx->tile_thin[pi] : ctx->tile_dense[pi];
-  const int top = thin ? kMaxItemThin : max_item(o);
-  return v > 0 ? std::min(v, top) : top;
+// Item edges of one call: the context's table for the precision (OZAKI shares
+// the FP64 one), unset classes at the kernel's full tile, capped to it.
+EdgeTable edge_table(const clr_context* ctx, const clr_gemm_opts* o) {
+  const int pi = o->precision == CLR_MIXED ? 1 : 0;
+  const EdgeTable& t = ctx->tiles[pi];
+  const int top = max_item(o);
+  EdgeTable e;
+  for (int c = 0; c < kDenseClasses; ++c) e.dense[c] = t.dense[c] > 0 ? std::min(t.dense[c], top) : top;
+  for (int c = 0; c < kThinClasses; ++c)
+    e.thin[c] = t.thin[c] > 0 ? std::min(t.thin[c], kMaxItemThin) : kMaxItemThin;
+  return e;
 }
 
 // Read and clear the device status word; map it to a status code.
@@ -421,14 +455,90 @@ RecWork rec_work(void* base, int64_t nitems) {
   return w;
 }
 
+// Recompression of nitems result blocks with workspace W.  With live (a
+// device-resident count), nitems is the capacity and W.recg must already
+// hold it: nothing is allocated.
+hipError_t launch_recompress_work(clr_context* ctx, Work& W, const RecItem* items,
+                                  const Piece* pieces, int nitems, double tol, bool timed = false,
+                                  const int64_t* live = nullptr) {
+  if (live) {
+    if (W.recg.bytes < rec_work_bytes(nitems)) return hipErrorInvalidValue;
+  } else {
+    hipError_t e = ensure(W.recg, rec_work_bytes(nitems));
+    if (e != hipSuccess) return e;
+  }
+  const RecWork w = rec_work(W.recg.p, nitems);
+  return launch_recompress(items, pieces, nitems, tol, as<int>(ctx->status), w.gi, w.gs, w.order,
+                           ctx->dense_cert ? w.cert : nullptr, live ? nullptr : w.ctr, ctx->stream,
+                           timed ? ctx->ev[8] : nullptr, timed ? ctx->ev[9] : nullptr, live);
+}
+
 hipError_t launch_recompress_ctx(clr_context* ctx, const RecItem* items, const Piece* pieces,
                                  int nitems, double tol, bool timed = false) {
-  hipError_t e = ensure(ctx->recg, rec_work_bytes(nitems));
-  if (e != hipSuccess) return e;
-  const RecWork w = rec_work(ctx->recg.p, nitems);
-  return launch_recompress(items, pieces, nitems, tol, as<int>(ctx->status), w.gi, w.gs, w.order,
-                           ctx->dense_cert ? w.cert : nullptr, w.ctr, ctx->stream,
-                           timed ? ctx->ev[8] : nullptr, timed ? ctx->ev[9] : nullptr);
+  return launch_recompress_work(ctx, ctx->w, items, pieces, nitems, tol, timed);
+}
+
+// Buffer sizes of a pipeline run over npairs result blocks of a rows x cols
+// matrix whose work lists hold at most caps.c[*] entries.
+struct WorkSizes {
+  std::vector<std::pair<DevBuf Work::*, size_t>> bufs;
+};
+WorkSizes work_sizes(int64_t npairs, const Caps& caps, int64_t rows, int64_t cols) {
+  auto n = [&](int c) { return (size_t)std::max<int64_t>(caps.c[c], 0); };
+  WorkSizes w;
+  w.bufs = {
+      {&Work::cnt, sizeof(int64_t) * kNumCounters * (size_t)npairs},
+      {&Work::off, sizeof(int64_t) * kNumCounters * (size_t)npairs},
+      {&Work::st, sizeof(double) * kNumStats * (size_t)npairs},
+      {&Work::flags, sizeof(int) * (size_t)npairs},
+      {&Work::totals, sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats},
+      {&Work::seg_dense, sizeof(Seg) * n(kCntSegDense)},
+      {&Work::items_dense, sizeof(GemmItem) * n(kCntGemmItems)},
+      {&Work::order, sizeof(int) * n(kCntGemmItems)},
+      {&Work::order_thin, sizeof(int) * n(kCntThin1)},
+      {&Work::seg_thin1, sizeof(Seg) * n(kCntThin1)},
+      {&Work::items_thin1, sizeof(GemmItem) * n(kCntThin1)},
+      {&Work::seg_thin2, sizeof(Seg) * n(kCntThin2)},
+      {&Work::items_thin2, sizeof(GemmItem) * n(kCntThin2)},
+      {&Work::pieces, sizeof(Piece) * n(kCntPieces)},
+      {&Work::rec, sizeof(RecItem) * n(kCntComputed)},
+      {&Work::pool, sizeof(double) * n(kCntPool)},
+      {&Work::scratch, sizeof(double) * n(kCntScratch)},
+      {&Work::comb_dense, sizeof(AxpbyDenseItem) * n(kCntCombDense)},
+      {&Work::acc, sizeof(double) * (size_t)rows * (size_t)cols},
+      {&Work::recg, rec_work_bytes(caps.c[kCntComputed])},
+      {&Work::terms, sizeof(double) * (size_t)npairs},
+      {&Work::live, sizeof(int64_t) * kNumLive},
+      {&Work::flops, sizeof(double)},
+  };
+  return w;
+}
+hipError_t reserve_work(Work& W, const WorkSizes& ws) {
+  for (const auto& b : ws.bufs) {
+    hipError_t e = ensure(W.*(b.first), b.second);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+bool work_fits(const Work& W, const WorkSizes& ws) {
+  for (const auto& b : ws.bufs)
+    if ((W.*(b.first)).bytes < std::max<size_t>(b.second, 8)) return false;
+  return true;
+}
+
+// A run whose work-list lengths stay on the device: every list has the
+// capacity caps and the launches read their lengths from W.live (see Caps).
+struct DevRun {
+  Caps caps;
+};
+
+// Zero kinds, ranks and norms of a matrix about to be rewritten in place.
+hipError_t reset_meta(clr_context* ctx, clr_matrix* m) {
+  const int64_t nb = (int64_t)m->nrb * m->ncb;
+  hipError_t e = launch_fill_i32(m->d_kind, 0, nb, ctx->stream);
+  if (e == hipSuccess) e = launch_fill_i32(m->d_rank, 0, nb, ctx->stream);
+  if (e == hipSuccess) e = launch_fill_f64(m->d_norm, 0.0, nb, ctx->stream);
+  return e;
 }
 
 clr_status copy_matrix(clr_context* ctx, const clr_matrix* src, clr_matrix** out) {
@@ -482,13 +592,10 @@ extern "C" clr_status clr_context_create(clr_context** ctx, void* stream) {
 extern "C" clr_status clr_context_destroy(clr_context* ctx) {
   if (!ctx) return CLR_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(ctx->stream);
-  for (DevBuf* b : {&ctx->cnt, &ctx->off, &ctx->st, &ctx->flags, &ctx->totals, &ctx->seg_dense,
-                    &ctx->items_dense, &ctx->seg_thin1, &ctx->items_thin1, &ctx->seg_thin2,
-                    &ctx->items_thin2, &ctx->pieces, &ctx->rec, &ctx->pool, &ctx->scratch,
-                    &ctx->acc, &ctx->status, &ctx->terms, &ctx->aux_items, &ctx->aux_segs,
-                    &ctx->aux_dense, &ctx->ptrs, &ctx->recg, &ctx->order, &ctx->order_thin,
-                    &ctx->sortw})
-    free_buf(*b);
+  free_work(ctx->w);
+  free_work(ctx->gw);
+  free_buf(ctx->status);
+  free_buf(ctx->ptrs);
   for (auto& c : ctx->cache) (void)hipFree(c.first);
   ctx->cache.clear();
   for (auto& e : ctx->ev)
@@ -640,19 +747,19 @@ extern "C" clr_status clr_compress(clr_context* ctx, const double* dense, int64_
       r.norm_out = m->d_norm + b;
       items.push_back(r);
     }
-  hipError_t e = ensure(ctx->scratch, sizeof(double) * std::max<int64_t>(scratch_total, 1));
+  hipError_t e = ensure(ctx->w.scratch, sizeof(double) * std::max<int64_t>(scratch_total, 1));
   if (e != hipSuccess) {
     free_matrix(m);
     return fail(ctx, CLR_ERR_HIP, "scratch allocation: %s", hipGetErrorString(e));
   }
   for (size_t i = 0; i < items.size(); ++i)
-    items[i].scratch = scratch_off[i] >= 0 ? as<double>(ctx->scratch) + scratch_off[i] : nullptr;
-  s = upload(ctx, ctx->rec, items);
+    items[i].scratch = scratch_off[i] >= 0 ? as<double>(ctx->w.scratch) + scratch_off[i] : nullptr;
+  s = upload(ctx, ctx->w.rec, items);
   if (s != CLR_OK) {
     free_matrix(m);
     return s;
   }
-  e = launch_recompress_ctx(ctx, as<RecItem>(ctx->rec), nullptr, (int)items.size(), tol);
+  e = launch_recompress_ctx(ctx, as<RecItem>(ctx->w.rec), nullptr, (int)items.size(), tol);
   if (e != hipSuccess) {
     free_matrix(m);
     return fail(ctx, CLR_ERR_HIP, "recompress launch: %s", hipGetErrorString(e));
@@ -741,17 +848,32 @@ extern "C" clr_status clr_to_dense(clr_context* ctx, const clr_matrix* m, double
 
 namespace {
 
-clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
+// The product C = alpha A B with workspace W.  C is a new matrix, or Cinto
+// (same blocking) rewritten in place.  With dev, the work lists have the
+// capacities dev->caps and their lengths stay on the device: no host
+// read-back, allocation or synchronisation, so the call can be recorded into
+// a graph (W must already hold the capacities; statistics and the status
+// word are then read by the caller after the run).
+clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_matrix* B,
                      const clr_gemm_opts* o, clr_matrix** Cout, clr_gemm_stats* st,
-                     const clr_matrix* mask = nullptr) {
+                     const clr_matrix* mask = nullptr, clr_matrix* Cinto = nullptr,
+                     const DevRun* dev = nullptr) {
   *Cout = nullptr;
   if (A->cs != B->rs)
     return fail(ctx, CLR_ERR_SHAPE, "column blocking of A differs from row blocking of B");
-  clr_matrix* C = nullptr;
-  clr_status s = alloc_matrix(ctx, A->rs, B->cs, &C);
-  if (s != CLR_OK) return s;
+  if (dev && (st || o->precision == CLR_OZAKI || !Cinto))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "device-sized product: in place, FP64 or mixed, no statistics");
+  clr_matrix* C = Cinto;
+  if (C) {
+    if (C->rs != A->rs || C->cs != B->cs)
+      return fail(ctx, CLR_ERR_SHAPE, "output blocking differs from the product's");
+    HIP_TRY(ctx, reset_meta(ctx, C));
+  } else {
+    clr_status s = alloc_matrix(ctx, A->rs, B->cs, &C);
+    if (s != CLR_OK) return s;
+  }
   auto bail = [&](clr_status code) {
-    free_matrix(C);
+    if (!Cinto) free_matrix(C);
     return code;
   };
   hipStream_t stream = ctx->stream;
@@ -766,103 +888,134 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
   P.alpha = o->alpha;
   P.tol = o->tol;
   P.square = (A->rs == B->cs) ? 1 : 0;
-  P.max_item = tile_edge(ctx, o, false);
-  P.max_item_thin = tile_edge(ctx, o, true);
+  P.edges = edge_table(ctx, o);
   P.mask_kind = mask ? mask->d_kind : nullptr;
   const int64_t npairs = (int64_t)P.nrb * P.ncb;
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = ensure(ctx->cnt, sizeof(int64_t) * kNumCounters * npairs);
-  if (e == hipSuccess) e = ensure(ctx->off, sizeof(int64_t) * kNumCounters * npairs);
-  if (e == hipSuccess) e = ensure(ctx->st, sizeof(double) * kNumStats * npairs);
-  if (e == hipSuccess) e = ensure(ctx->flags, sizeof(int) * npairs);
-  if (e == hipSuccess) e = ensure(ctx->totals, sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats);
-  if (e != hipSuccess) {
-    fail(ctx, CLR_ERR_HIP, "workspace: %s", hipGetErrorString(e));
-    return bail(CLR_ERR_HIP);
+  if (dev) {
+    if (!work_fits(W, work_sizes(npairs, dev->caps, C->rows, C->cols)))
+      return bail(fail(ctx, CLR_ERR_CAPACITY, "workspace smaller than the run's capacities"));
+  } else {
+    if (e == hipSuccess) e = ensure(W.cnt, sizeof(int64_t) * kNumCounters * npairs);
+    if (e == hipSuccess) e = ensure(W.off, sizeof(int64_t) * kNumCounters * npairs);
+    if (e == hipSuccess) e = ensure(W.st, sizeof(double) * kNumStats * npairs);
+    if (e == hipSuccess) e = ensure(W.flags, sizeof(int) * npairs);
+    if (e == hipSuccess) e = ensure(W.totals, sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats);
+    if (e != hipSuccess) {
+      fail(ctx, CLR_ERR_HIP, "workspace: %s", hipGetErrorString(e));
+      return bail(CLR_ERR_HIP);
+    }
   }
-  int64_t* tot_cnt = as<int64_t>(ctx->totals);
+  int64_t* tot_cnt = as<int64_t>(W.totals);
   double* tot_st = reinterpret_cast<double*>(tot_cnt + kNumCounters);
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], stream);
-  if (e == hipSuccess) e = launch_symbolic(P, as<int64_t>(ctx->cnt), as<double>(ctx->st), as<int>(ctx->flags), stream);
-  if (e == hipSuccess) e = launch_scan(as<int64_t>(ctx->cnt), as<int64_t>(ctx->off), npairs, kNumCounters, tot_cnt, stream);
-  if (e == hipSuccess) e = launch_reduce(as<double>(ctx->st), npairs, kNumStats, tot_st, stream);
-  int64_t hc[kNumCounters];
+  if (!dev && e == hipSuccess) e = hipEventRecord(ctx->ev[0], stream);
+  if (e == hipSuccess) e = launch_symbolic(P, as<int64_t>(W.cnt), as<double>(W.st), as<int>(W.flags), stream);
+  if (e == hipSuccess) e = launch_scan(as<int64_t>(W.cnt), as<int64_t>(W.off), npairs, kNumCounters, tot_cnt, stream);
+  // n[c]: length (eager) or capacity (device-sized) of list c; live: the
+  // device-resident lengths of a device-sized run
+  int64_t n[kNumCounters];
   double hs[kNumStats];
-  if (e == hipSuccess) e = hipMemcpyAsync(hc, tot_cnt, sizeof(hc), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(hs, tot_st, sizeof(hs), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  int64_t* live = nullptr;
+  if (dev) {
+    live = as<int64_t>(W.live);
+    if (e == hipSuccess) e = launch_caps(tot_cnt, dev->caps, live, stream);
+    if (e == hipSuccess) e = launch_reduce(as<double>(W.st), npairs, kNumStats, tot_st, stream);
+    if (e == hipSuccess) e = launch_add_flops(tot_st, as<double>(W.flops), stream);
+    for (int i = 0; i < kNumCounters; ++i) n[i] = dev->caps.c[i];
+  } else {
+    if (e == hipSuccess) e = launch_reduce(as<double>(W.st), npairs, kNumStats, tot_st, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(n, tot_cnt, sizeof(n), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hs, tot_st, sizeof(hs), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  }
   if (e != hipSuccess) {
     fail(ctx, CLR_ERR_HIP, "symbolic phase: %s", hipGetErrorString(e));
     return bail(CLR_ERR_HIP);
   }
   for (int i = 0; i < kNumCounters; ++i)
-    if (hc[i] < 0 || (i != kCntPool && i != kCntScratch && hc[i] > INT32_MAX))
-      return bail(fail(ctx, CLR_ERR_CAPACITY, "work list %d too long (%lld)", i, (long long)hc[i]));
-  if (e == hipSuccess) e = ensure(ctx->seg_dense, sizeof(Seg) * hc[kCntSegDense]);
-  if (e == hipSuccess) e = ensure(ctx->items_dense, sizeof(GemmItem) * hc[kCntGemmItems]);
-  if (e == hipSuccess) e = ensure(ctx->order, sizeof(int) * hc[kCntGemmItems]);
-  if (e == hipSuccess) e = ensure(ctx->order_thin, sizeof(int) * hc[kCntThin1]);
-  if (e == hipSuccess) e = ensure(ctx->sortw, operand_order_bytes((int)hc[kCntThin1]));
-  if (e == hipSuccess) e = ensure(ctx->seg_thin1, sizeof(Seg) * hc[kCntThin1]);
-  if (e == hipSuccess) e = ensure(ctx->items_thin1, sizeof(GemmItem) * hc[kCntThin1]);
-  if (e == hipSuccess) e = ensure(ctx->seg_thin2, sizeof(Seg) * hc[kCntThin2]);
-  if (e == hipSuccess) e = ensure(ctx->items_thin2, sizeof(GemmItem) * hc[kCntThin2]);
-  if (e == hipSuccess) e = ensure(ctx->pieces, sizeof(Piece) * hc[kCntPieces]);
-  if (e == hipSuccess) e = ensure(ctx->rec, sizeof(RecItem) * hc[kCntComputed]);
-  if (e == hipSuccess) e = ensure(ctx->pool, sizeof(double) * hc[kCntPool]);
-  if (e == hipSuccess) e = ensure(ctx->scratch, sizeof(double) * hc[kCntScratch]);
-  if (e == hipSuccess && hc[kCntGemmItems] > 0)
-    e = ensure(ctx->acc, sizeof(double) * (size_t)C->rows * C->cols);
-  if (e != hipSuccess) {
-    fail(ctx, CLR_ERR_HIP, "work lists: %s", hipGetErrorString(e));
-    return bail(CLR_ERR_HIP);
+    if (n[i] < 0 || (i != kCntPool && i != kCntScratch && n[i] > INT32_MAX))
+      return bail(fail(ctx, CLR_ERR_CAPACITY, "work list %d too long (%lld)", i, (long long)n[i]));
+  if (!dev) {
+    for (int i = 0; i < kNumCounters; ++i) W.seen.c[i] = std::max(W.seen.c[i], n[i]);
+    W.host_flops += hs[kStFlopsDD] + hs[kStFlopsLD] + hs[kStFlopsDL] + hs[kStFlopsLL] +
+                    hs[kStFlopsDensify];
+    Caps exact;
+    for (int i = 0; i < kNumCounters; ++i) exact.c[i] = n[i];
+    WorkSizes ws = work_sizes(npairs, exact, C->rows, C->cols);
+    if (n[kCntGemmItems] == 0)   // no dense accumulation: no accumulators needed
+      for (auto& b : ws.bufs)
+        if (b.first == &Work::acc) b.second = 0;
+    e = reserve_work(W, ws);
+    if (e == hipSuccess) e = ensure(W.order_thin, sizeof(int) * n[kCntThin1]);
+    if (e == hipSuccess) e = ensure(W.sortw, operand_order_bytes((int)n[kCntThin1]));
+    if (e != hipSuccess) {
+      fail(ctx, CLR_ERR_HIP, "work lists: %s", hipGetErrorString(e));
+      return bail(CLR_ERR_HIP);
+    }
   }
-  FillParams F;
-  F.off = as<int64_t>(ctx->off);
-  F.cnt = as<int64_t>(ctx->cnt);
-  F.flags = as<int>(ctx->flags);
-  F.seg_dense = as<Seg>(ctx->seg_dense);
-  F.items_dense = as<GemmItem>(ctx->items_dense);
-  F.seg_thin1 = as<Seg>(ctx->seg_thin1);
-  F.items_thin1 = as<GemmItem>(ctx->items_thin1);
-  F.seg_thin2 = as<Seg>(ctx->seg_thin2);
-  F.items_thin2 = as<GemmItem>(ctx->items_thin2);
-  F.pieces = as<Piece>(ctx->pieces);
-  F.rec = as<RecItem>(ctx->rec);
-  F.pool = as<double>(ctx->pool);
-  F.scratch = as<double>(ctx->scratch);
-  F.acc = as<double>(ctx->acc);
+  auto lv = [&](int c) { return live ? live + c : nullptr; };
+  FillParams F{};
+  F.off = as<int64_t>(W.off);
+  F.cnt = as<int64_t>(W.cnt);
+  F.flags = as<int>(W.flags);
+  F.seg_dense = as<Seg>(W.seg_dense);
+  F.items_dense = as<GemmItem>(W.items_dense);
+  F.seg_thin1 = as<Seg>(W.seg_thin1);
+  F.items_thin1 = as<GemmItem>(W.items_thin1);
+  F.seg_thin2 = as<Seg>(W.seg_thin2);
+  F.items_thin2 = as<GemmItem>(W.items_thin2);
+  F.pieces = as<Piece>(W.pieces);
+  F.rec = as<RecItem>(W.rec);
+  F.pool = as<double>(W.pool);
+  F.scratch = as<double>(W.scratch);
+  F.acc = as<double>(W.acc);
   F.c_arena = C->arena;
   F.c_kind = C->d_kind;
   F.c_rank = C->d_rank;
   F.c_norm = C->d_norm;
   F.c_ncols = C->cols;
+  F.abort = lv(kLiveOverflow);
+  // The operand-grouped order of the factor products only improves L2 reuse
+  // (each item is computed on its own).  A device-sized run groups them with
+  // the hashed counting sort, which a graph can record.
+  const int* order_thin = as<int>(W.order_thin);
   if (e == hipSuccess) e = launch_fill(P, F, stream);
   if (e == hipSuccess)
-    e = launch_item_order(F.items_dense, (int)hc[kCntGemmItems], as<int>(ctx->order), stream);
+    e = launch_item_order(F.items_dense, (int)n[kCntGemmItems], as<int>(W.order), stream,
+                          lv(kCntGemmItems));
+  if (e == hipSuccess && !dev)
+    e = launch_operand_order(F.items_thin1, F.seg_thin1, (int)n[kCntThin1], W.sortw.p,
+                             as<int>(W.order_thin), stream);
+  if (e == hipSuccess && dev)
+    e = launch_operand_group(F.items_thin1, F.seg_thin1, (int)n[kCntThin1], as<int>(W.order_thin),
+                             stream, lv(kCntThin1));
+  if (e == hipSuccess && !dev) e = hipEventRecord(ctx->ev[1], stream);
   if (e == hipSuccess)
-    e = launch_operand_order(F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], ctx->sortw.p,
-                             as<int>(ctx->order_thin), stream);
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], stream);
+    e = run_wgemm(o, F.items_thin1, F.seg_thin1, (int)n[kCntThin1], stream, order_thin,
+                  lv(kCntThin1));
   if (e == hipSuccess)
-    e = run_wgemm(o, F.items_thin1, F.seg_thin1, (int)hc[kCntThin1], stream,
-                  as<int>(ctx->order_thin));
-  if (e == hipSuccess) e = run_wgemm(o, F.items_thin2, F.seg_thin2, (int)hc[kCntThin2], stream);
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev[6], stream);
+    e = run_wgemm(o, F.items_thin2, F.seg_thin2, (int)n[kCntThin2], stream, nullptr, lv(kCntThin2));
+  if (e == hipSuccess && !dev) e = hipEventRecord(ctx->ev[6], stream);
   if (e == hipSuccess)
-    e = run_ggemm(o, F.items_dense, F.seg_dense, (int)hc[kCntGemmItems], stream, true,
-                  as<int>(ctx->order));
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], stream);
+    e = run_ggemm(o, F.items_dense, F.seg_dense, (int)n[kCntGemmItems], stream, true,
+                  as<int>(W.order), lv(kCntGemmItems));
+  if (e == hipSuccess && !dev) e = hipEventRecord(ctx->ev[2], stream);
   if (e == hipSuccess)
-    e = launch_recompress_ctx(ctx, F.rec, F.pieces, (int)hc[kCntComputed], o->tol, st != nullptr);
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev[3], stream);
+    e = launch_recompress_work(ctx, W, F.rec, F.pieces, (int)n[kCntComputed], o->tol,
+                               st != nullptr, lv(kCntComputed));
+  if (e == hipSuccess && !dev) e = hipEventRecord(ctx->ev[3], stream);
   if (e != hipSuccess) {
     fail(ctx, CLR_ERR_HIP, "product launch: %s", hipGetErrorString(e));
     return bail(CLR_ERR_HIP);
   }
-  s = check_status(ctx);
+  if (dev) {
+    *Cout = C;
+    return CLR_OK;
+  }
+  clr_status s = check_status(ctx);
   if (s != CLR_OK) return bail(s);
   if (st) {
+    const int64_t* hc = n;
     memset(st, 0, sizeof(*st));
     st->candidates = (int64_t)hs[kStCandidate];
     st->computed = hc[kCntComputed];
@@ -886,7 +1039,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
     st->ms_rec_engine = hc[kCntComputed] > 0 ? elapsed(ctx->ev[8], ctx->ev[9]) : 0.0;
     if (hc[kCntComputed] > 0) {
       RecCounters rc;
-      HIP_TRY(ctx, hipMemcpy(&rc, rec_work(ctx->recg.p, hc[kCntComputed]).ctr, sizeof(rc),
+      HIP_TRY(ctx, hipMemcpy(&rc, rec_work(W.recg.p, hc[kCntComputed]).ctr, sizeof(rc),
                              hipMemcpyDeviceToHost));
       st->flops_rec_engine = rc.flops_bidiag;
       st->certified_dense = (int64_t)rc.certified;
@@ -897,7 +1050,7 @@ clr_status gemm_impl(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
     if ((s = fetch_meta(ctx, C, hcm)) != CLR_OK) return bail(s);
     st->bytes_compulsory = 8.0 * (stored_elements(A, ha) + stored_elements(B, hb) + stored_elements(C, hcm));
     std::vector<int> fl(npairs);
-    HIP_TRY(ctx, hipMemcpy(fl.data(), ctx->flags.p, sizeof(int) * npairs, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(fl.data(), W.flags.p, sizeof(int) * npairs, hipMemcpyDeviceToHost));
     for (int64_t b = 0; b < npairs; ++b) {
       if (!(fl[b] & kFlagComputed)) continue;
       if (fl[b] & kFlagDensify) st->densified++;
@@ -918,7 +1071,7 @@ extern "C" clr_status clr_gemm(clr_context* ctx, const clr_matrix* A, const clr_
   *C = nullptr;
   clr_status s = check_opts(ctx, opts);
   if (s != CLR_OK) return s;
-  return gemm_impl(ctx, A, B, opts, C, st);
+  return gemm_impl(ctx, ctx->w, A, B, opts, C, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -937,8 +1090,43 @@ extern "C" clr_status clr_set_tile_edges(clr_context* ctx, int precision, int de
   if (thin_edge != 0 && (thin_edge < 16 || thin_edge > kMaxItemThin || thin_edge % 16 != 0))
     return fail(ctx, CLR_ERR_INVALID_ARG, "thin tile edge %d: 0 or a multiple of 16 in [16, %d]",
                 thin_edge, kMaxItemThin);
-  ctx->tile_dense[precision] = dense_edge;
-  ctx->tile_thin[precision] = thin_edge;
+  EdgeTable& t = ctx->tiles[precision == CLR_MIXED ? 1 : 0];
+  for (int c = 0; c < kDenseClasses; ++c) t.dense[c] = dense_edge;
+  for (int c = 0; c < kThinClasses; ++c) t.thin[c] = thin_edge;
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_set_tile_classes(clr_context* ctx, int precision, const int* dense_edges,
+                                           const int* thin_edges) {
+  if (!ctx || !dense_edges || !thin_edges) return CLR_ERR_INVALID_ARG;
+  if (precision != CLR_FP64 && precision != CLR_MIXED)
+    return fail(ctx, CLR_ERR_INVALID_ARG, "bad precision");
+  const int top = precision == CLR_MIXED ? kMaxItemF32 : kMaxItemF64;
+  for (int c = 0; c < kDenseClasses; ++c) {
+    const int v = dense_edges[c];
+    if (v != 0 && (v < 16 || v > top || v % 16 != 0))
+      return fail(ctx, CLR_ERR_INVALID_ARG, "dense class %d edge %d: 0 or a multiple of 16 in [16, %d]",
+                  c, v, top);
+  }
+  for (int c = 0; c < kThinClasses; ++c) {
+    const int v = thin_edges[c];
+    if (v != 0 && (v < 16 || v > kMaxItemThin || v % 16 != 0))
+      return fail(ctx, CLR_ERR_INVALID_ARG, "thin class %d edge %d: 0 or a multiple of 16 in [16, %d]",
+                  c, v, kMaxItemThin);
+  }
+  EdgeTable& t = ctx->tiles[precision == CLR_MIXED ? 1 : 0];
+  for (int c = 0; c < kDenseClasses; ++c) t.dense[c] = dense_edges[c];
+  for (int c = 0; c < kThinClasses; ++c) t.thin[c] = thin_edges[c];
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_get_tile_classes(const clr_context* ctx, int precision, int* dense_edges,
+                                           int* thin_edges) {
+  if (!ctx || !dense_edges || !thin_edges) return CLR_ERR_INVALID_ARG;
+  if (precision != CLR_FP64 && precision != CLR_MIXED) return CLR_ERR_INVALID_ARG;
+  const EdgeTable& t = ctx->tiles[precision == CLR_MIXED ? 1 : 0];
+  for (int c = 0; c < kDenseClasses; ++c) dense_edges[c] = t.dense[c];
+  for (int c = 0; c < kThinClasses; ++c) thin_edges[c] = t.thin[c];
   return CLR_OK;
 }
 
@@ -1019,13 +1207,14 @@ extern "C" clr_status clr_set_compression(clr_context* ctx, int method) {
   return CLR_OK;
 }
 
-// Empirical choice, on the caller's own product, of the largest item edge of
-// the dense-accumulation launch and of the factor-product launches: every
-// candidate edge (multiples of 32 up to the kernel's tile) is timed on the
-// product (best of two runs, device events around each launch class) and the
-// fastest per launch class is kept for this context and precision.  The
-// numerical result does not depend on the edges: every output element is
-// accumulated over the same inner sequence whatever the tiling.
+// Empirical choice, on the caller's own product, of the item edges of the
+// dense-accumulation launch and of the factor-product launches: first one edge
+// per launch class (every multiple of 32 up to the kernel's tile), then each
+// shape class of items on its own (coordinate descent from that choice), each
+// candidate timed on the product (best of two runs, device events around each
+// launch class).  The numerical result does not depend on the edges: every
+// output element is accumulated over the same inner sequence whatever the
+// tiling.
 extern "C" clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const clr_matrix* B,
                                    const clr_gemm_opts* opts, int* dense_edge, int* thin_edge,
                                    double* ms_dense, double* ms_thin) {
@@ -1036,23 +1225,35 @@ extern "C" clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const 
     return fail(ctx, CLR_ERR_INVALID_ARG, "autotune covers the FP64 and MIXED forms");
   const int pi = opts->precision == CLR_MIXED ? 1 : 0;
   const int top = max_item(opts);
-  double best_d = 1e300, best_t = 1e300;
-  int arg_d = top, arg_t = std::min(top, kMaxItemThin);
-  for (int edge = 32; edge <= top; edge += 32) {
-    ctx->tile_dense[pi] = edge;
-    ctx->tile_thin[pi] = std::min(edge, kMaxItemThin);
-    double td = 1e300, tt = 1e300;
+  EdgeTable& T = ctx->tiles[pi];
+  const EdgeTable saved = T;
+  // launch times of the product with the current table (best of two runs)
+  auto measure = [&](double* td, double* tt) -> clr_status {
+    *td = *tt = 1e300;
     for (int rep = 0; rep < 2; ++rep) {
       clr_matrix* C = nullptr;
       clr_gemm_stats st{};
-      s = gemm_impl(ctx, A, B, opts, &C, &st);
+      clr_status r = gemm_impl(ctx, ctx->w, A, B, opts, &C, &st);
       free_matrix(C);
-      if (s != CLR_OK) {
-        ctx->tile_dense[pi] = ctx->tile_thin[pi] = 0;
-        return s;
-      }
-      td = std::min(td, st.ms_dense);
-      tt = std::min(tt, st.ms_thin);
+      if (r != CLR_OK) return r;
+      *td = std::min(*td, (double)st.ms_dense);
+      *tt = std::min(*tt, (double)st.ms_thin);
+    }
+    return CLR_OK;
+  };
+  auto set_all = [&](int de, int te) {
+    for (int c = 0; c < kDenseClasses; ++c) T.dense[c] = de;
+    for (int c = 0; c < kThinClasses; ++c) T.thin[c] = te;
+  };
+  // 1. one edge per launch class: multiples of 32 up to the full tile
+  double best_d = 1e300, best_t = 1e300;
+  int arg_d = top, arg_t = std::min(top, kMaxItemThin);
+  for (int edge = 32; edge <= top; edge += 32) {
+    set_all(edge, std::min(edge, kMaxItemThin));
+    double td, tt;
+    if ((s = measure(&td, &tt)) != CLR_OK) {
+      T = saved;
+      return s;
     }
     if (td < best_d) {
       best_d = td;
@@ -1060,11 +1261,53 @@ extern "C" clr_status clr_autotune(clr_context* ctx, const clr_matrix* A, const 
     }
     if (tt < best_t) {
       best_t = tt;
-      arg_t = ctx->tile_thin[pi];
+      arg_t = std::min(edge, kMaxItemThin);
     }
   }
-  ctx->tile_dense[pi] = arg_d;
-  ctx->tile_thin[pi] = arg_t;
+  set_all(arg_d, arg_t);
+  // 2. per shape class, one class at a time from that choice: an edge is kept
+  // only if it shortens its launch by more than 2 % (classes absent from the
+  // product change nothing and keep the launch-class edge)
+  for (int c = 0; c < kDenseClasses; ++c) {
+    const int cur = T.dense[c];
+    int best = cur;
+    double bt = best_d;
+    for (int edge = 32; edge <= top; edge += 32) {
+      if (edge == cur) continue;
+      T.dense[c] = edge;
+      double td, tt;
+      if ((s = measure(&td, &tt)) != CLR_OK) {
+        T = saved;
+        return s;
+      }
+      if (td < 0.98 * bt) {
+        bt = td;
+        best = edge;
+      }
+    }
+    T.dense[c] = best;
+    best_d = bt;
+  }
+  for (int c = 0; c < kThinClasses; ++c) {
+    const int cur = T.thin[c];
+    int best = cur;
+    double bt = best_t;
+    for (int edge = 16; edge <= kMaxItemThin; edge += 16) {
+      if (edge == cur) continue;
+      T.thin[c] = edge;
+      double td, tt;
+      if ((s = measure(&td, &tt)) != CLR_OK) {
+        T = saved;
+        return s;
+      }
+      if (tt < 0.98 * bt) {
+        bt = tt;
+        best = edge;
+      }
+    }
+    T.thin[c] = best;
+    best_t = bt;
+  }
   if (dense_edge) *dense_edge = arg_d;
   if (thin_edge) *thin_edge = arg_t;
   if (ms_dense) *ms_dense = best_d;
@@ -1166,26 +1409,25 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     q.alpha = pl->o.alpha;
     q.tol = pl->o.tol;
     q.square = (A->rs == B->cs) ? 1 : 0;
-    q.max_item = tile_edge(ctx, &pl->o, false);
-    q.max_item_thin = tile_edge(ctx, &pl->o, true);
+    q.edges = edge_table(ctx, &pl->o);
     q.mask_kind = nullptr;
     pb[p + 1] = pb[p] + (int64_t)q.nrb * q.ncb;
   }
   const int64_t tp = pb[np];
   const size_t tot_bytes = (size_t)np * (sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats);
-  HIP_TRY(ctx, ensure(ctx->cnt, sizeof(int64_t) * kNumCounters * tp));
-  HIP_TRY(ctx, ensure(ctx->off, sizeof(int64_t) * kNumCounters * tp));
-  HIP_TRY(ctx, ensure(ctx->st, sizeof(double) * kNumStats * tp));
-  HIP_TRY(ctx, ensure(ctx->flags, sizeof(int) * tp));
-  HIP_TRY(ctx, ensure(ctx->totals, tot_bytes));
-  int64_t* tc = as<int64_t>(ctx->totals);
+  HIP_TRY(ctx, ensure(ctx->w.cnt, sizeof(int64_t) * kNumCounters * tp));
+  HIP_TRY(ctx, ensure(ctx->w.off, sizeof(int64_t) * kNumCounters * tp));
+  HIP_TRY(ctx, ensure(ctx->w.st, sizeof(double) * kNumStats * tp));
+  HIP_TRY(ctx, ensure(ctx->w.flags, sizeof(int) * tp));
+  HIP_TRY(ctx, ensure(ctx->w.totals, tot_bytes));
+  int64_t* tc = as<int64_t>(ctx->w.totals);
   double* ts = reinterpret_cast<double*>(tc + (size_t)np * kNumCounters);
   for (int p = 0; p < np; ++p) {
     const int64_t npairs = pb[p + 1] - pb[p];
-    int64_t* cnt = as<int64_t>(ctx->cnt) + kNumCounters * pb[p];
-    int64_t* off = as<int64_t>(ctx->off) + kNumCounters * pb[p];
-    double* st = as<double>(ctx->st) + kNumStats * pb[p];
-    HIP_TRY(ctx, launch_symbolic(P[p], cnt, st, as<int>(ctx->flags) + pb[p], stream));
+    int64_t* cnt = as<int64_t>(ctx->w.cnt) + kNumCounters * pb[p];
+    int64_t* off = as<int64_t>(ctx->w.off) + kNumCounters * pb[p];
+    double* st = as<double>(ctx->w.st) + kNumStats * pb[p];
+    HIP_TRY(ctx, launch_symbolic(P[p], cnt, st, as<int>(ctx->w.flags) + pb[p], stream));
     HIP_TRY(ctx, launch_scan(cnt, off, npairs, kNumCounters, tc + (size_t)p * kNumCounters, stream));
     HIP_TRY(ctx, launch_reduce(st, npairs, kNumStats, ts + (size_t)p * kNumStats, stream));
   }
@@ -1247,12 +1489,12 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   }
   for (int p = 0; p < np; ++p) {
     const int64_t npairs = pb[p + 1] - pb[p];
-    int64_t* off = as<int64_t>(ctx->off) + kNumCounters * pb[p];
+    int64_t* off = as<int64_t>(ctx->w.off) + kNumCounters * pb[p];
     HIP_TRY(ctx, launch_add_base(off, npairs, kNumCounters, as<int64_t>(pl->bases) + (size_t)p * kNumCounters, stream));
-    FillParams F;
+    FillParams F{};
     F.off = off;
-    F.cnt = as<int64_t>(ctx->cnt) + kNumCounters * pb[p];
-    F.flags = as<int>(ctx->flags) + pb[p];
+    F.cnt = as<int64_t>(ctx->w.cnt) + kNumCounters * pb[p];
+    F.flags = as<int>(ctx->w.flags) + pb[p];
     F.seg_dense = as<Seg>(pl->seg_dense);
     F.items_dense = as<GemmItem>(pl->items_dense);
     F.seg_thin1 = as<Seg>(pl->seg_thin1);
@@ -1274,9 +1516,9 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   HIP_TRY(ctx, launch_item_order(as<GemmItem>(pl->items_dense), (int)sum[kCntGemmItems],
                                  as<int>(pl->order), stream));
   HIP_TRY(ctx, ensure(pl->order_thin, sizeof(int) * sum[kCntThin1]));
-  HIP_TRY(ctx, ensure(ctx->sortw, operand_order_bytes((int)sum[kCntThin1])));
+  HIP_TRY(ctx, ensure(ctx->w.sortw, operand_order_bytes((int)sum[kCntThin1])));
   HIP_TRY(ctx, launch_operand_order(as<GemmItem>(pl->items_thin1), as<Seg>(pl->seg_thin1),
-                                    (int)sum[kCntThin1], ctx->sortw.p, as<int>(pl->order_thin),
+                                    (int)sum[kCntThin1], ctx->w.sortw.p, as<int>(pl->order_thin),
                                     stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
   return s;
@@ -1404,6 +1646,113 @@ extern "C" clr_status clr_gemm_batch(clr_context* ctx, int nprod, const clr_matr
 // Blockwise combination a X + b Y + c I
 // ---------------------------------------------------------------------------
 
+namespace {
+
+// T = a X + b Y + c I with workspace W, planned on the device (k_comb_count,
+// scan, k_comb_fill): dense parts summed elementwise, low-rank operands of
+// densified blocks added by the grouped GEMM, then every computed block
+// recompressed.  T is new or Tinto rewritten in place; dev as in gemm_impl.
+clr_status axpby_impl(clr_context* ctx, Work& W, double a, const clr_matrix* X, double b,
+                      const clr_matrix* Y, double c, const clr_gemm_opts* o, clr_matrix** Tout,
+                      clr_matrix* Tinto = nullptr, const DevRun* dev = nullptr) {
+  *Tout = nullptr;
+  if (Y && (Y->rs != X->rs || Y->cs != X->cs))
+    return fail(ctx, CLR_ERR_SHAPE, "clr_axpby: blockings differ");
+  if (dev && !Tinto) return fail(ctx, CLR_ERR_INVALID_ARG, "device-sized combination: in place only");
+  clr_matrix* T = Tinto;
+  if (T) {
+    if (T->rs != X->rs || T->cs != X->cs) return fail(ctx, CLR_ERR_SHAPE, "clr_axpby: output blocking");
+    HIP_TRY(ctx, reset_meta(ctx, T));
+  } else {
+    clr_status s = alloc_matrix(ctx, X->rs, X->cs, &T);
+    if (s != CLR_OK) return s;
+  }
+  auto bail = [&](clr_status code) {
+    if (!Tinto) free_matrix(T);
+    return code;
+  };
+  hipStream_t stream = ctx->stream;
+  const int64_t nb = (int64_t)X->nrb * X->ncb;
+  hipError_t e = hipSuccess;
+  if (dev) {
+    if (!work_fits(W, work_sizes(nb, dev->caps, X->rows, X->cols)))
+      return bail(fail(ctx, CLR_ERR_CAPACITY, "workspace smaller than the run's capacities"));
+  } else {
+    if (e == hipSuccess) e = ensure(W.cnt, sizeof(int64_t) * kNumCounters * nb);
+    if (e == hipSuccess) e = ensure(W.off, sizeof(int64_t) * kNumCounters * nb);
+    if (e == hipSuccess) e = ensure(W.totals, sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats);
+    if (e != hipSuccess) return bail(fail(ctx, CLR_ERR_HIP, "workspace: %s", hipGetErrorString(e)));
+  }
+  CombParams P{};
+  P.X = X->view();
+  if (Y) P.Y = Y->view();
+  P.a = a;
+  P.b = b;
+  P.c = c;
+  P.square = X->square_blocked() ? 1 : 0;
+  P.eps_sp = o->eps_sp;
+  P.screen = o->screen;
+  P.tol = o->tol;
+  P.edges = edge_table(ctx, o);
+  P.t_arena = T->arena;
+  P.t_kind = T->d_kind;
+  P.t_rank = T->d_rank;
+  P.t_norm = T->d_norm;
+  int64_t* tot = as<int64_t>(W.totals);
+  if (e == hipSuccess) e = launch_comb_count(P, as<int64_t>(W.cnt), stream);
+  if (e == hipSuccess) e = launch_scan(as<int64_t>(W.cnt), as<int64_t>(W.off), nb, kNumCounters, tot, stream);
+  int64_t n[kNumCounters];
+  int64_t* live = nullptr;
+  if (dev) {
+    live = as<int64_t>(W.live);
+    if (e == hipSuccess) e = launch_caps(tot, dev->caps, live, stream);
+    for (int i = 0; i < kNumCounters; ++i) n[i] = dev->caps.c[i];
+  } else {
+    if (e == hipSuccess) e = hipMemcpyAsync(n, tot, sizeof(n), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) {
+      for (int i = 0; i < kNumCounters; ++i) W.seen.c[i] = std::max(W.seen.c[i], n[i]);
+      Caps exact;
+      for (int i = 0; i < kNumCounters; ++i) exact.c[i] = n[i];
+      e = reserve_work(W, work_sizes(nb, exact, X->rows, X->cols));
+    }
+  }
+  if (e != hipSuccess) return bail(fail(ctx, CLR_ERR_HIP, "combination plan: %s", hipGetErrorString(e)));
+  for (int i = 0; i < kNumCounters; ++i)
+    if (n[i] < 0 || (i != kCntScratch && n[i] > INT32_MAX))
+      return bail(fail(ctx, CLR_ERR_CAPACITY, "work list %d too long (%lld)", i, (long long)n[i]));
+  auto lv = [&](int k) { return live ? live + k : nullptr; };
+  P.acc = as<double>(W.acc);
+  CombLists L{};
+  L.off = as<int64_t>(W.off);
+  L.cnt = as<int64_t>(W.cnt);
+  L.dense = as<AxpbyDenseItem>(W.comb_dense);
+  L.segs = as<Seg>(W.seg_dense);
+  L.items = as<GemmItem>(W.items_dense);
+  L.pieces = as<Piece>(W.pieces);
+  L.rec = as<RecItem>(W.rec);
+  L.scratch = as<double>(W.scratch);
+  L.abort = lv(kLiveOverflow);
+  if (e == hipSuccess) e = launch_comb_fill(P, L, stream);
+  if (e == hipSuccess)
+    e = launch_axpby_dense(L.dense, (int)n[kCntCombDense], stream, lv(kCntCombDense));
+  if (e == hipSuccess)
+    e = run_ggemm(o, L.items, L.segs, (int)n[kCntGemmItems], stream, false, nullptr,
+                  lv(kCntGemmItems));
+  if (e == hipSuccess)
+    e = launch_recompress_work(ctx, W, L.rec, L.pieces, (int)n[kCntComputed], o->tol, false,
+                               lv(kCntComputed));
+  if (e != hipSuccess) return bail(fail(ctx, CLR_ERR_HIP, "axpby launch: %s", hipGetErrorString(e)));
+  if (!dev) {
+    clr_status s = check_status(ctx);
+    if (s != CLR_OK) return bail(s);
+  }
+  *Tout = T;
+  return CLR_OK;
+}
+
+}  // namespace
+
 extern "C" clr_status clr_axpby(clr_context* ctx, double a, const clr_matrix* X, double b,
                                 const clr_matrix* Y, double c, const clr_gemm_opts* o,
                                 clr_matrix** Tout) {
@@ -1411,149 +1760,7 @@ extern "C" clr_status clr_axpby(clr_context* ctx, double a, const clr_matrix* X,
   *Tout = nullptr;
   clr_status s = check_opts(ctx, o);
   if (s != CLR_OK) return s;
-  if (Y && (Y->rs != X->rs || Y->cs != X->cs))
-    return fail(ctx, CLR_ERR_SHAPE, "clr_axpby: blockings differ");
-  HostMeta hx, hy;
-  if ((s = fetch_meta(ctx, X, hx)) != CLR_OK) return s;
-  if (Y && (s = fetch_meta(ctx, Y, hy)) != CLR_OK) return s;
-  clr_matrix* T = nullptr;
-  if ((s = alloc_matrix(ctx, X->rs, X->cs, &T)) != CLR_OK) return s;
-  const bool square = X->square_blocked();
-  std::vector<RecItem> rec;
-  std::vector<Piece> pieces;
-  std::vector<AxpbyDenseItem> dense;
-  std::vector<GemmItem> items;
-  std::vector<Seg> segs;
-  std::vector<int64_t> scratch_off;
-  int64_t scratch_total = 0;
-  const int maxe = tile_edge(ctx, o, false);
-  HIP_TRY(ctx, ensure(ctx->acc, sizeof(double) * (size_t)X->rows * X->cols));
-  double* acc = as<double>(ctx->acc);
-  for (int I = 0; I < X->nrb; ++I)
-    for (int J = 0; J < X->ncb; ++J) {
-      const size_t blk = (size_t)I * X->ncb + J;
-      const int m = X->rs[I], n = X->cs[J];
-      const int64_t so = slot_offset(X->roff.data(), X->coff.data(), X->cols, I, J);
-      const int kx = hx.kind[blk];
-      const int ky = Y ? hy.kind[blk] : 0;
-      const bool diag = square && I == J;
-      const bool has_i = diag && c != 0.0;
-      double est = 0.0;
-      if (kx) est += fabs(a) * hx.norm[blk];
-      if (ky) est += fabs(b) * hy.norm[blk];
-      if (has_i) est += fabs(c) * sqrt((double)m);
-      if (!kx && !ky && !has_i) continue;
-      const double tau = o->screen == CLR_SCREEN_AREA ? o->eps_sp * m * (double)n : o->eps_sp;
-      if (est < tau) continue;
-      const int R = (kx == 2 ? hx.rank[blk] : 0) + (ky == 2 ? hy.rank[blk] : 0);
-      const bool any_dense = kx == 1 || ky == 1 || has_i;
-      const bool densify = diag || any_dense || 2 * R >= std::min(m, n);
-      RecItem r{};
-      r.m = m;
-      r.n = n;
-      r.tau = tau;
-      r.out = T->arena + so;
-      r.kind_out = T->d_kind + blk;
-      r.rank_out = T->d_rank + blk;
-      r.norm_out = T->d_norm + blk;
-      const double* xs = X->arena + so;
-      const double* ys = Y ? Y->arena + so : nullptr;
-      if (densify) {
-        r.path = diag ? kPathForceDense : kPathDense;
-        r.cert_hint = 1;
-        r.D = acc + so;
-        r.ldd = m;
-        AxpbyDenseItem d{};
-        d.D = acc + so;
-        d.X = kx == 1 ? xs : nullptr;
-        d.Y = ky == 1 ? ys : nullptr;
-        d.a = a;
-        d.b = b;
-        d.c = diag ? c : 0.0;
-        d.m = m;
-        d.n = n;
-        dense.push_back(d);
-        const int seg0 = (int)segs.size();
-        int kb = 0;
-        auto add_lr = [&](const double* f, int rk, double sc) {
-          Seg sg{};
-          sg.L = f;                     // U (m x r)
-          sg.sLi = 1;
-          sg.sLk = m;
-          sg.R = f + (int64_t)m * rk;   // V (n x r) used transposed
-          sg.sRk = n;
-          sg.sRj = 1;
-          sg.k = rk;
-          sg.kbase = kb;
-          sg.scale = sc;
-          kb += rk;
-          segs.push_back(sg);
-        };
-        if (kx == 2) add_lr(xs, hx.rank[blk], a);
-        if (ky == 2) add_lr(ys, hy.rank[blk], b);
-        if (kb > 0) {
-          const int pr = num_parts(m, maxe), pc = num_parts(n, maxe);
-          for (int pa = 0; pa < pr; ++pa)
-            for (int pb = 0; pb < pc; ++pb) {
-              GemmItem g{};
-              part_range(m, pr, pa, &g.row0, &g.m);
-              part_range(n, pc, pb, &g.col0, &g.n);
-              g.C = acc + so;
-              g.ldc = m;
-              g.seg0 = seg0;
-              g.nseg = (int)segs.size() - seg0;
-              g.ktotal = kb;
-              g.accumulate = 1;
-              g.alpha = 1.0;
-              items.push_back(g);
-            }
-        }
-      } else {
-        r.path = kPathLowRank;
-        r.piece0 = (int)pieces.size();
-        r.R = R;
-        auto add_piece = [&](const double* f, int rk, double sc) {
-          Piece p{};
-          p.U = f;
-          p.ldu = m;
-          p.V = f + (int64_t)m * rk;
-          p.ldv = n;
-          p.r = rk;
-          p.scale = sc;
-          pieces.push_back(p);
-        };
-        if (kx == 2) add_piece(xs, hx.rank[blk], a);
-        if (ky == 2) add_piece(ys, hy.rank[blk], b);
-        r.npieces = (int)pieces.size() - r.piece0;
-      }
-      const int64_t need = rec_scratch_doubles(r.path, m, n, r.R, o->tol);
-      scratch_off.push_back(need > 0 ? scratch_total : -1);
-      scratch_total += need;
-      rec.push_back(r);
-    }
-  auto bail = [&](clr_status code) {
-    free_matrix(T);
-    return code;
-  };
-  if (ensure(ctx->scratch, sizeof(double) * std::max<int64_t>(scratch_total, 1)) != hipSuccess)
-    return bail(fail(ctx, CLR_ERR_HIP, "scratch allocation failed"));
-  for (size_t i = 0; i < rec.size(); ++i)
-    rec[i].scratch = scratch_off[i] >= 0 ? as<double>(ctx->scratch) + scratch_off[i] : nullptr;
-  if ((s = upload(ctx, ctx->aux_dense, dense)) != CLR_OK) return bail(s);
-  if ((s = upload(ctx, ctx->aux_segs, segs)) != CLR_OK) return bail(s);
-  if ((s = upload(ctx, ctx->aux_items, items)) != CLR_OK) return bail(s);
-  if ((s = upload(ctx, ctx->pieces, pieces)) != CLR_OK) return bail(s);
-  if ((s = upload(ctx, ctx->rec, rec)) != CLR_OK) return bail(s);
-  hipError_t e = launch_axpby_dense(ctx->aux_dense.p, (int)dense.size(), ctx->stream);
-  if (e == hipSuccess)
-    e = run_ggemm(o, as<GemmItem>(ctx->aux_items), as<Seg>(ctx->aux_segs), (int)items.size(), ctx->stream);
-  if (e == hipSuccess)
-    e = launch_recompress_ctx(ctx, as<RecItem>(ctx->rec), as<Piece>(ctx->pieces), (int)rec.size(),
-                              o->tol);
-  if (e != hipSuccess) return bail(fail(ctx, CLR_ERR_HIP, "axpby launch: %s", hipGetErrorString(e)));
-  if ((s = check_status(ctx)) != CLR_OK) return bail(s);
-  *Tout = T;
-  return CLR_OK;
+  return axpby_impl(ctx, ctx->w, a, X, b, Y, c, o, Tout);
 }
 
 // ---------------------------------------------------------------------------
@@ -1564,10 +1771,10 @@ extern "C" clr_status clr_identity_residual(clr_context* ctx, const clr_matrix* 
   if (!ctx || !X || !out) return CLR_ERR_INVALID_ARG;
   if (!X->square_blocked()) return fail(ctx, CLR_ERR_SHAPE, "identity residual needs a square blocking");
   const int64_t nb = (int64_t)X->nrb * X->ncb;
-  HIP_TRY(ctx, ensure(ctx->terms, sizeof(double) * nb));
-  HIP_TRY(ctx, launch_identity_terms(X->view(), as<double>(ctx->terms), ctx->stream));
+  HIP_TRY(ctx, ensure(ctx->w.terms, sizeof(double) * nb));
+  HIP_TRY(ctx, launch_identity_terms(X->view(), as<double>(ctx->w.terms), ctx->stream));
   std::vector<double> t(nb);
-  HIP_TRY(ctx, hipMemcpyAsync(t.data(), ctx->terms.p, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(t.data(), ctx->w.terms.p, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   double s = 0.0;
   for (double v : t) s += v;
@@ -1621,11 +1828,11 @@ clr_status identity_matrix(clr_context* ctx, const std::vector<int>& sizes, clr_
     rank[I * nb + I] = sizes[I];
     norm[I * nb + I] = sqrt((double)sizes[I]);
   }
-  if ((s = upload(ctx, ctx->aux_dense, items)) != CLR_OK) {
+  if ((s = upload(ctx, ctx->w.comb_dense, items)) != CLR_OK) {
     free_matrix(Z);
     return s;
   }
-  hipError_t e = launch_axpby_dense(ctx->aux_dense.p, nb, ctx->stream);
+  hipError_t e = launch_axpby_dense(ctx->w.comb_dense.p, nb, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(Z->d_kind, kind.data(), sizeof(int) * nb * nb, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(Z->d_rank, rank.data(), sizeof(int) * nb * nb, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(Z->d_norm, norm.data(), sizeof(double) * nb * nb, hipMemcpyHostToDevice, ctx->stream);
@@ -1649,9 +1856,9 @@ clr_status explicit_residual(clr_context* ctx, const clr_matrix* W, const clr_ma
   ex.alpha = 1.0;
   clr_matrix *WS = nullptr, *WSW = nullptr;
   clr_gemm_stats g1{}, g2{};
-  clr_status s = gemm_impl(ctx, W, S, &ex, &WS, &g1);
+  clr_status s = gemm_impl(ctx, ctx->w, W, S, &ex, &WS, &g1);
   if (s != CLR_OK) return s;
-  s = gemm_impl(ctx, WS, W, &ex, &WSW, &g2);
+  s = gemm_impl(ctx, ctx->w, WS, W, &ex, &WSW, &g2);
   free_matrix(WS);
   if (s != CLR_OK) return s;
   s = clr_identity_residual(ctx, WSW, out);
@@ -1659,6 +1866,177 @@ clr_status explicit_residual(clr_context* ctx, const clr_matrix* W, const clr_ma
   if (flops) *flops += g1.flops_products + g2.flops_products;
   return s;
 }
+
+}  // namespace
+
+namespace {
+
+// One iteration of Eqs. (8)-(11) recorded as a HIP graph and replayed.
+//
+// The iterates live in two fixed pairs (Z, Y)[0..1] (ping-pong) next to fixed
+// X_n, X_n^2 and T_n, and every product and the combination run with their
+// work-list lengths left on the device (gemm_impl / axpby_impl with a DevRun),
+// so a replay needs no host read-back: the host reads the residual's block
+// terms and the overflow flag after it.  graph[p] reads pair p and writes pair
+// 1 - p.  Capacities come from the lengths of the iteration run directly
+// (times the margin); a replay that would exceed one leaves its inputs intact,
+// so that iteration is redone directly and both graphs are recorded again.
+constexpr double kGraphMargin = 2.0;    // default capacity over the lengths seen
+
+struct IterGraph {
+  clr_context* ctx;
+  Work& W;   // the context's graph workspace: buffers persist (and only grow) between calls
+  clr_matrix* Zb[2] = {};
+  clr_matrix* Yb[2] = {};
+  clr_matrix *X = nullptr, *Q = nullptr, *T = nullptr;
+  hipGraph_t graph[2] = {};
+  hipGraphExec_t exec[2] = {};
+  DevRun run{};
+  double margin = kGraphMargin;
+  int cur = 0;        // the pair holding the current iterates
+  int captures = 0, replays = 0;
+  double flops = 0.0;
+
+  explicit IterGraph(clr_context* c) : ctx(c), W(c->gw) {
+    W.seen = Caps{};
+  }
+  ~IterGraph() {
+    drop_graphs();
+    for (clr_matrix* m : {Zb[0], Zb[1], Yb[0], Yb[1], X, Q, T}) free_matrix(m);
+  }
+  void drop_graphs() {
+    for (int p = 0; p < 2; ++p) {
+      if (exec[p]) (void)hipGraphExecDestroy(exec[p]);
+      if (graph[p]) (void)hipGraphDestroy(graph[p]);
+      exec[p] = nullptr;
+      graph[p] = nullptr;
+    }
+  }
+  // X_n, X_n^2, T_n and the next pair from pair p; the block terms of
+  // ||X_n - I|| go to W.terms.  dev: device-sized (recordable) or direct.
+  clr_status iterate(int p, const clr_gemm_opts* gx, const clr_gemm_opts* gr,
+                     const clr_gemm_opts* g64, const DevRun* dev) {
+    clr_matrix* out = nullptr;
+    clr_status s = gemm_impl(ctx, W, Yb[p], Zb[p], gx, &out, nullptr, nullptr, X, dev);  // Eq. (8)
+    if (s == CLR_OK) s = gemm_impl(ctx, W, X, X, gr, &out, nullptr, nullptr, Q, dev);
+    if (s == CLR_OK)
+      s = axpby_impl(ctx, W, -10.0 / 8.0, X, 3.0 / 8.0, Q, 15.0 / 8.0, g64, &out, T, dev);  // Eq. (9)
+    if (s == CLR_OK) s = gemm_impl(ctx, W, Zb[p], T, gr, &out, nullptr, nullptr, Zb[1 - p], dev);
+    if (s == CLR_OK) s = gemm_impl(ctx, W, T, Yb[p], gr, &out, nullptr, nullptr, Yb[1 - p], dev);
+    if (s == CLR_OK) HIP_TRY(ctx, launch_identity_terms(X->view(), as<double>(W.terms), ctx->stream));
+    return s;
+  }
+
+  // Record graph[p] on a capture stream of its own (the context stream may be
+  // the legacy default stream, which cannot be captured).
+  clr_status capture(int p, const clr_gemm_opts* gx, const clr_gemm_opts* gr,
+                     const clr_gemm_opts* g64) {
+    hipStream_t cs = nullptr;
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    clr_status s = CLR_OK;
+    if (e == hipSuccess) {
+      ctx->stream = cs;
+      // the overflow flag starts clear on every replay (a kernel, not a memset)
+      hipError_t le = launch_fill_i32(reinterpret_cast<int*>(as<int64_t>(W.live) + kLiveOverflow), 0,
+                                      2, cs);
+      if (le == hipSuccess)
+        le = launch_fill_f64(as<double>(W.flops), 0.0, 1, cs);
+      s = le == hipSuccess ? iterate(p, gx, gr, g64, &run) : fail(ctx, CLR_ERR_HIP, "capture: %s", hipGetErrorString(le));
+      ctx->stream = saved;
+      e = hipStreamEndCapture(cs, &graph[p]);
+    }
+    (void)hipStreamDestroy(cs);
+    if (s != CLR_OK) return s;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec[p], graph[p], nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(ctx, CLR_ERR_HIP, "iteration graph: %s", hipGetErrorString(e));
+    ++captures;
+    return CLR_OK;
+  }
+
+  // Capacities from the lengths seen (times m) and both graphs.
+  clr_status prepare(double m, const clr_gemm_opts* gx, const clr_gemm_opts* gr,
+                     const clr_gemm_opts* g64) {
+    drop_graphs();
+    for (int c = 0; c < kNumCounters; ++c)
+      run.caps.c[c] = std::max<int64_t>(run.caps.c[c],
+                                        (int64_t)std::ceil(m * (double)W.seen.c[c]) + 16);
+    const int64_t nb = (int64_t)X->nrb * X->ncb;
+    HIP_TRY(ctx, reserve_work(W, work_sizes(nb, run.caps, X->rows, X->cols)));
+    HIP_TRY(ctx, launch_fill_i32(reinterpret_cast<int*>(as<int64_t>(W.live)), 0, 2 * kNumLive,
+                                 ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int p = 0; p < 2; ++p) {
+      clr_status s = capture(p, gx, gr, g64);
+      if (s != CLR_OK) return s;
+    }
+    return CLR_OK;
+  }
+
+  // ||X_n - I||_F / sqrt(N) from the block terms in W.terms, summed on the
+  // host in block order (as clr_identity_residual does).
+  clr_status residual(double* r) {
+    const int64_t nb = (int64_t)X->nrb * X->ncb;
+    std::vector<double> t(nb);
+    HIP_TRY(ctx, hipMemcpyAsync(t.data(), W.terms.p, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    double sum = 0.0;
+    for (double v : t) sum += v;
+    *r = sqrt(sum) / sqrt((double)X->rows);
+    return CLR_OK;
+  }
+
+  // One iteration from the current pair: directly the first time (which sizes
+  // the graphs), replayed afterwards.
+  clr_status step(const clr_gemm_opts* gx, const clr_gemm_opts* gr, const clr_gemm_opts* g64,
+                  double* r) {
+    clr_status s;
+    if (!exec[0]) {
+      s = direct(gx, gr, g64);
+      if (s == CLR_OK) s = prepare(margin, gx, gr, g64);
+    } else {
+      HIP_TRY(ctx, hipGraphLaunch(exec[cur], ctx->stream));
+      int64_t flag = 0;
+      double f = 0.0;
+      HIP_TRY(ctx, hipMemcpyAsync(&flag, as<int64_t>(W.live) + kLiveOverflow, sizeof(flag),
+                                  hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(ctx, hipMemcpyAsync(&f, W.flops.p, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      s = check_status(ctx);
+      if (s != CLR_OK) return s;
+      if (flag) {
+        // a list outgrew its capacity: the inputs are intact, so redo the
+        // iteration directly and record the graphs for the lengths seen
+        Caps need;
+        HIP_TRY(ctx, hipMemcpy(need.c, as<int64_t>(W.live) + kLiveNeed, sizeof(need.c),
+                               hipMemcpyDeviceToHost));
+        for (int c = 0; c < kNumCounters; ++c) W.seen.c[c] = std::max(W.seen.c[c], need.c[c]);
+        s = direct(gx, gr, g64);
+        if (s == CLR_OK) s = prepare(std::max(margin, kGraphMargin), gx, gr, g64);
+      } else {
+        flops += f;
+        ++replays;
+        s = CLR_OK;
+      }
+    }
+    if (s != CLR_OK) return s;
+    s = residual(r);
+    cur = 1 - cur;
+    return s;
+  }
+
+  // The iteration from the current pair with every list sized on the host
+  // (which also records the lengths in W.seen and the flops).
+  clr_status direct(const clr_gemm_opts* gx, const clr_gemm_opts* gr, const clr_gemm_opts* g64) {
+    const double f0 = W.host_flops;
+    clr_status s = iterate(cur, gx, gr, g64, nullptr);
+    if (s == CLR_OK) s = check_status(ctx);
+    flops += W.host_flops - f0;
+    return s;
+  }
+};
 
 }  // namespace
 
@@ -1670,8 +2048,11 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
   if (s != CLR_OK) return s;
   if (!S->square_blocked()) return fail(ctx, CLR_ERR_SHAPE, "S must be square-blocked");
   if (!(o->conv_tol >= 0.0) || o->max_iter < 1 || o->fixed_iters < 0 || !(o->alpha >= 0.0) ||
-      !(o->reduced_below >= 0.0))
+      !(o->reduced_below >= 0.0) || !(o->graph_margin >= 0.0))
     return fail(ctx, CLR_ERR_INVALID_ARG, "bad iteration options");
+  if (o->graph && (o->reduced_below > 0.0 || o->g.precision == CLR_OZAKI))
+    return fail(ctx, CLR_ERR_INVALID_ARG,
+                "graph replay needs reduced_below == 0 and the FP64 or MIXED form");
   HIP_TRY(ctx, hipEventRecord(ctx->ev[4], ctx->stream));
   double alpha = o->alpha;
   if (alpha == 0.0) {
@@ -1702,6 +2083,25 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
     free_matrix(Z);
     return s;
   }
+  // graph replay: the iterates move into the graph's fixed pairs, which it owns
+  std::unique_ptr<IterGraph> G;
+  if (o->graph) {
+    G.reset(new IterGraph(ctx));
+    G->margin = o->graph_margin > 0.0 ? o->graph_margin : kGraphMargin;
+    G->Zb[0] = Z;
+    G->Yb[0] = Y;
+    for (clr_matrix** m : {&G->Zb[1], &G->Yb[1], &G->X, &G->Q, &G->T})
+      if ((s = alloc_matrix(ctx, S->rs, S->rs, m)) != CLR_OK) return s;
+  }
+  auto release = [&]() {
+    if (G) {
+      G.reset();
+    } else {
+      free_matrix(Z);
+      free_matrix(Y);
+    }
+    Z = Y = nullptr;
+  };
   std::vector<double> internal;
   std::vector<double> expl;
   double flops = 0.0;
@@ -1712,59 +2112,69 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
   double last_explicit = -1.0;
   const int n_iter = o->fixed_iters > 0 ? o->fixed_iters : o->max_iter;
   for (it = 0; it < n_iter; ++it) {
-    clr_matrix *X = nullptr, *Q = nullptr, *T = nullptr, *Zn = nullptr, *Yn = nullptr;
-    clr_gemm_stats gs{};
     double r = 0.0;
-    // precision of this iteration's products: everything in g.precision, or (the
-    // schedule) FP64 until the residual has fallen to reduced_below, then X_n in
-    // FP64 and the other products in g.precision
-    const bool reduced = !scheduled || (!internal.empty() && internal.back() <= o->reduced_below);
-    const clr_gemm_opts* gx = scheduled ? &ga64 : &ga;
-    const clr_gemm_opts* gr = reduced ? &g : &g64;
-    s = gemm_impl(ctx, Y, Z, gx, &X, &gs);                  // X_n = alpha Y_n Z_n   (Eq. (8))
-    flops += gs.flops_products;
-    if (scheduled && reduced && o->correction) {
-      // T_n = I + D_n, D_n = -E_n/2 + 3 E_n^2/8 with E_n = X_n - I (Eq. (9) expanded)
-      clr_matrix *E = nullptr, *E2 = nullptr, *P = nullptr, *R = nullptr;
-      if (s == CLR_OK) s = clr_axpby(ctx, 1.0, X, 0.0, nullptr, -1.0, &g64, &E);
-      if (s == CLR_OK) s = gemm_impl(ctx, E, E, gr, &E2, &gs);
-      flops += gs.flops_products;
-      if (s == CLR_OK) s = clr_axpby(ctx, -0.5, E, 3.0 / 8.0, E2, 0.0, &g64, &T);   // T holds D_n
-      if (s == CLR_OK) s = gemm_impl(ctx, Z, T, gr, &P, &gs);                        // Z_n D_n
-      flops += gs.flops_products;
-      if (s == CLR_OK) s = clr_axpby(ctx, 1.0, Z, 1.0, P, 0.0, &g64, &Zn);          // Eq. (10)
-      if (s == CLR_OK) s = gemm_impl(ctx, T, Y, gr, &R, &gs);                        // D_n Y_n
-      flops += gs.flops_products;
-      if (s == CLR_OK) s = clr_axpby(ctx, 1.0, Y, 1.0, R, 0.0, &g64, &Yn);          // Eq. (11)
-      free_matrix(E);
-      free_matrix(E2);
-      free_matrix(P);
-      free_matrix(R);
+    if (G) {
+      s = G->step(&ga, &g, &g64, &r);
+      n_gemms += 4;
+      if (s != CLR_OK) {
+        release();
+        return s;
+      }
+      Z = G->Zb[G->cur];
+      Y = G->Yb[G->cur];
     } else {
-      if (s == CLR_OK) s = gemm_impl(ctx, X, X, gr, &Q, &gs);  // X_n^2
+      clr_matrix *X = nullptr, *Q = nullptr, *T = nullptr, *Zn = nullptr, *Yn = nullptr;
+      clr_gemm_stats gs{};
+      // precision of this iteration's products: everything in g.precision, or (the
+      // schedule) FP64 until the residual has fallen to reduced_below, then X_n in
+      // FP64 and the other products in g.precision
+      const bool reduced = !scheduled || (!internal.empty() && internal.back() <= o->reduced_below);
+      const clr_gemm_opts* gx = scheduled ? &ga64 : &ga;
+      const clr_gemm_opts* gr = reduced ? &g : &g64;
+      s = gemm_impl(ctx, ctx->w, Y, Z, gx, &X, &gs);                  // X_n = alpha Y_n Z_n   (Eq. (8))
       flops += gs.flops_products;
-      if (s == CLR_OK) s = clr_axpby(ctx, -10.0 / 8.0, X, 3.0 / 8.0, Q, 15.0 / 8.0, &g64, &T);  // Eq. (9)
-      if (s == CLR_OK) s = gemm_impl(ctx, Z, T, gr, &Zn, &gs);  // Z_{n+1} = Z_n T_n     (Eq. (10))
-      flops += gs.flops_products;
-      if (s == CLR_OK) s = gemm_impl(ctx, T, Y, gr, &Yn, &gs);  // Y_{n+1} = T_n Y_n     (Eq. (11))
-      flops += gs.flops_products;
-    }
-    if (s == CLR_OK) s = clr_identity_residual(ctx, X, &r);
-    n_gemms += 4;
-    free_matrix(X);
-    free_matrix(Q);
-    free_matrix(T);
-    if (s != CLR_OK) {
-      free_matrix(Zn);
-      free_matrix(Yn);
+      if (scheduled && reduced && o->correction) {
+        // T_n = I + D_n, D_n = -E_n/2 + 3 E_n^2/8 with E_n = X_n - I (Eq. (9) expanded)
+        clr_matrix *E = nullptr, *E2 = nullptr, *P = nullptr, *R = nullptr;
+        if (s == CLR_OK) s = clr_axpby(ctx, 1.0, X, 0.0, nullptr, -1.0, &g64, &E);
+        if (s == CLR_OK) s = gemm_impl(ctx, ctx->w, E, E, gr, &E2, &gs);
+        flops += gs.flops_products;
+        if (s == CLR_OK) s = clr_axpby(ctx, -0.5, E, 3.0 / 8.0, E2, 0.0, &g64, &T);   // T holds D_n
+        if (s == CLR_OK) s = gemm_impl(ctx, ctx->w, Z, T, gr, &P, &gs);                        // Z_n D_n
+        flops += gs.flops_products;
+        if (s == CLR_OK) s = clr_axpby(ctx, 1.0, Z, 1.0, P, 0.0, &g64, &Zn);          // Eq. (10)
+        if (s == CLR_OK) s = gemm_impl(ctx, ctx->w, T, Y, gr, &R, &gs);                        // D_n Y_n
+        flops += gs.flops_products;
+        if (s == CLR_OK) s = clr_axpby(ctx, 1.0, Y, 1.0, R, 0.0, &g64, &Yn);          // Eq. (11)
+        free_matrix(E);
+        free_matrix(E2);
+        free_matrix(P);
+        free_matrix(R);
+      } else {
+        if (s == CLR_OK) s = gemm_impl(ctx, ctx->w, X, X, gr, &Q, &gs);  // X_n^2
+        flops += gs.flops_products;
+        if (s == CLR_OK) s = clr_axpby(ctx, -10.0 / 8.0, X, 3.0 / 8.0, Q, 15.0 / 8.0, &g64, &T);  // Eq. (9)
+        if (s == CLR_OK) s = gemm_impl(ctx, ctx->w, Z, T, gr, &Zn, &gs);  // Z_{n+1} = Z_n T_n     (Eq. (10))
+        flops += gs.flops_products;
+        if (s == CLR_OK) s = gemm_impl(ctx, ctx->w, T, Y, gr, &Yn, &gs);  // Y_{n+1} = T_n Y_n     (Eq. (11))
+        flops += gs.flops_products;
+      }
+      if (s == CLR_OK) s = clr_identity_residual(ctx, X, &r);
+      n_gemms += 4;
+      free_matrix(X);
+      free_matrix(Q);
+      free_matrix(T);
+      if (s != CLR_OK) {
+        free_matrix(Zn);
+        free_matrix(Yn);
+        release();
+        return s;
+      }
       free_matrix(Z);
       free_matrix(Y);
-      return s;
+      Z = Zn;
+      Y = Yn;
     }
-    free_matrix(Z);
-    free_matrix(Y);
-    Z = Zn;
-    Y = Yn;
     internal.push_back(r);
     if (o->fixed_iters > 0) continue;
     if (r <= o->conv_tol) {
@@ -1794,8 +2204,7 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
       // ||alpha S - I||_2 < 1 (Sec. 4.2): growth while it is small is the
       // truncation / precision floor (stalled), growth beyond 0.5 divergence
       if (internal.back() > 0.5) {
-        free_matrix(Z);
-        free_matrix(Y);
+        release();
         return fail(ctx, CLR_ERR_DIVERGED, "||X_n - I|| grew in two consecutive iterations");
       }
       result = CLR_ERR_NOT_CONVERGED;
@@ -1804,15 +2213,15 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
     }
   }
   if (s != CLR_OK) {
-    free_matrix(Z);
-    free_matrix(Y);
+    release();
     return s;
   }
   if (o->fixed_iters > 0) result = CLR_OK;
   clr_matrix* W = nullptr;
   s = scaled_copy(ctx, Z, sqrt(alpha), &W);
-  free_matrix(Z);
-  free_matrix(Y);
+  const int replays = G ? G->replays : 0, captures = G ? G->captures : 0;
+  if (G) flops += G->flops;
+  release();
   if (s != CLR_OK) return s;
   HIP_TRY(ctx, hipEventRecord(ctx->ev[5], ctx->stream));
   HIP_TRY(ctx, hipEventSynchronize(ctx->ev[5]));
@@ -1826,6 +2235,8 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
     st->n_gemms = n_gemms;
     st->flops_products = flops;
     st->ms_total = elapsed(ctx->ev[4], ctx->ev[5]);
+    st->graph_replays = replays;
+    st->graph_captures = captures;
   }
   *Wout = W;
   if (result != CLR_OK)
@@ -1919,7 +2330,7 @@ clr_status exact_product(clr_context* ctx, const clr_matrix* L, const clr_matrix
   if (!L || !R) return CLR_OK;
   const clr_gemm_opts o = exact_opts(g, alpha);
   clr_gemm_stats gs{};
-  clr_status s = gemm_impl(ctx, L, R, &o, out, &gs, mask);
+  clr_status s = gemm_impl(ctx, ctx->w, L, R, &o, out, &gs, mask);
   if (flops) *flops += gs.flops_products;
   return s;
 }
@@ -2020,12 +2431,12 @@ extern "C" clr_status clr_sqrt_inv_backward(clr_context* ctx, const clr_matrix* 
   auto step = [&](const clr_matrix* Y, const clr_matrix* Z, clr_matrix** X, clr_matrix** T,
                   clr_matrix** Yn, clr_matrix** Zn) -> clr_status {
     clr_matrix* Q = nullptr;
-    clr_status r = gemm_impl(ctx, Y, Z, &ga, X, nullptr);
-    if (r == CLR_OK) r = gemm_impl(ctx, *X, *X, &g, &Q, nullptr);
+    clr_status r = gemm_impl(ctx, ctx->w, Y, Z, &ga, X, nullptr);
+    if (r == CLR_OK) r = gemm_impl(ctx, ctx->w, *X, *X, &g, &Q, nullptr);
     if (r == CLR_OK) r = clr_axpby(ctx, -10.0 / 8.0, *X, 3.0 / 8.0, Q, 15.0 / 8.0, &g, T);
     free_matrix(Q);
-    if (r == CLR_OK) r = gemm_impl(ctx, Z, *T, &g, Zn, nullptr);
-    if (r == CLR_OK) r = gemm_impl(ctx, *T, Y, &g, Yn, nullptr);
+    if (r == CLR_OK) r = gemm_impl(ctx, ctx->w, Z, *T, &g, Zn, nullptr);
+    if (r == CLR_OK) r = gemm_impl(ctx, ctx->w, *T, Y, &g, Yn, nullptr);
     return r;
   };
   Owned own;

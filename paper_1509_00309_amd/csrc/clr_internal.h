@@ -106,7 +106,21 @@ enum PlanCounter : int {
   kCntScratch,        // doubles of recompression scratch
   kCntComputed,       // 1 if the block passed screening
   kCntGemmItems,      // output tiles of the dense accumulation GEMM
+  kCntCombDense,      // dense parts of a combination a X + b Y + c I (zero in a product)
   kNumCounters
+};
+
+// Work-list lengths that stay on the device (a captured graph replays the
+// pipeline without reading them back).  live[0 .. kNumCounters) are the
+// lengths the launches use, live[kLiveOverflow] is set once a length exceeded
+// its capacity (from then on every length reads 0, so nothing runs past a
+// list's end), and live[kLiveNeed + c] keeps the largest length of counter c
+// seen, for growing the capacities.
+constexpr int kLiveOverflow = kNumCounters;
+constexpr int kLiveNeed = kNumCounters + 1;
+constexpr int kNumLive = 2 * kNumCounters + 1;
+struct Caps {
+  int64_t c[kNumCounters];
 };
 
 // Floating-point per-block statistics of the symbolic phase.
@@ -148,6 +162,32 @@ __host__ __device__ inline void part_range(int extent, int parts, int p, int* st
   *len = e - s;
 }
 
+// Item edges per shape class.  Dense-accumulation items are classed by the
+// block's longer edge: (0, 32], (32, 64], (64, 96], (96, 128], (128, 160],
+// above 160; factor-product (thin) items by the narrow extent of their output,
+// which is a rank: (0, 8], (8, 16], (16, 32], (32, 64], above 64.  A block is
+// split into items of at most its class's edge on 16-element boundaries.
+constexpr int kDenseClasses = 6;
+constexpr int kThinClasses = 5;
+struct EdgeTable {
+  int dense[kDenseClasses];
+  int thin[kThinClasses];
+};
+__host__ __device__ inline int dense_class(int m, int n) {
+  const int e = m > n ? m : n;
+  return e <= 32 ? 0 : e <= 64 ? 1 : e <= 96 ? 2 : e <= 128 ? 3 : e <= 160 ? 4 : 5;
+}
+__host__ __device__ inline int thin_class(int rows, int cols) {
+  const int r = rows < cols ? rows : cols;
+  return r <= 8 ? 0 : r <= 16 ? 1 : r <= 32 ? 2 : r <= 64 ? 3 : 4;
+}
+__host__ __device__ inline int dense_edge(const EdgeTable& E, int m, int n) {
+  return E.dense[dense_class(m, n)];
+}
+__host__ __device__ inline int thin_edge(const EdgeTable& E, int rows, int cols) {
+  return E.thin[thin_class(rows, cols)];
+}
+
 struct PlanParams {
   MatView A, B;
   int nrb, ncb, nkb;
@@ -156,8 +196,7 @@ struct PlanParams {
   double alpha;
   double tol;
   int square;     // C's row and column blockings are identical
-  int max_item;       // largest output tile edge of a dense-accumulation GEMM item
-  int max_item_thin;  // largest output tile edge of a factor-product (thin) GEMM item
+  EdgeTable edges;    // item edges of the dense-accumulation and factor-product launches
   const int* mask_kind;   // optional: only blocks stored in this kind table are computed
 };
 
@@ -181,6 +220,7 @@ struct FillParams {
   int* c_rank;
   double* c_norm;
   int64_t c_ncols;
+  const int64_t* abort;   // optional: nothing is written while *abort != 0
 };
 
 enum : int { kFlagComputed = 1, kFlagDensify = 2, kFlagForce = 4 };
@@ -194,23 +234,58 @@ struct AxpbyDenseItem {
   int m, n;
 };
 
+// Blockwise combination T = a X + b Y + c I planned on the device: one thread
+// per block decides screening and path and counts its work (k_comb_count);
+// after the scan, k_comb_fill writes the lists at the offsets.
+struct CombParams {
+  MatView X, Y;           // Y.kind null when there is no Y
+  double a, b, c;
+  int square;             // X is square-blocked (the identity term lives on diagonal blocks)
+  double eps_sp;
+  int screen;
+  double tol;
+  EdgeTable edges;        // item edges of the low-rank-term GEMM items (dense classes)
+  double* acc;            // dense accumulators, same slot layout as T
+  double* t_arena;
+  int* t_kind;
+  int* t_rank;
+  double* t_norm;
+};
+struct CombLists {
+  const int64_t* off;     // [kNumCounters][nblocks]
+  const int64_t* cnt;
+  AxpbyDenseItem* dense;
+  Seg* segs;
+  GemmItem* items;
+  Piece* pieces;
+  RecItem* rec;
+  double* scratch;
+  const int64_t* abort;   // optional, as in FillParams
+};
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 // order: optional item permutation (workgroup b runs item order[b]), e.g.
 // from launch_item_order; null keeps the XCD-blocked order.
+// live: optional device-resident item count; the launch covers nitems
+// items (its capacity) and the kernels stop at min(nitems, *live).
 hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
-                            bool dense = false, const int* order = nullptr);
+                            bool dense = false, const int* order = nullptr,
+                            const int64_t* live = nullptr);
 hipError_t launch_wgemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
-                            const int* order = nullptr);
+                            const int* order = nullptr, const int64_t* live = nullptr);
 hipError_t launch_wgemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s, const int* order = nullptr);
+                            hipStream_t s, const int* order = nullptr,
+                            const int64_t* live = nullptr);
 constexpr int kMaxItemThin = 64;   // largest edge of a wave-per-item (thin) GEMM item
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s, bool dense = false, const int* order = nullptr);
+                            hipStream_t s, bool dense = false, const int* order = nullptr,
+                            const int64_t* live = nullptr);
 // Items of the LDS grouped GEMM by decreasing estimated cost (slabs times the
 // busiest wave's tiles, in quarter-octave classes) into order[0 .. nitems).
-hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s);
+hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s,
+                             const int64_t* live = nullptr);
 // Dense accumulation on INT8 MFMA with `slices` digits per operand (2..7);
 // items of at most kMaxItemOzaki x kMaxItemOzaki.
 hipError_t launch_ggemm_ozaki(const GemmItem* items, const Seg* segs, int nitems, int slices,
@@ -226,10 +301,15 @@ hipError_t launch_kernel_matrix(const double* xr, int64_t nr, const double* xc, 
                                 int64_t ld, hipStream_t s);
 hipError_t launch_operand_order(const GemmItem* items, const Seg* segs, int nitems, void* work,
                                 int* order, hipStream_t s);
+// The same grouping by a hashed counting sort in one workgroup (no library
+// call, no workspace): order[0 .. min(nitems, *live)) for recorded launches.
+hipError_t launch_operand_group(const GemmItem* items, const Seg* segs, int nitems, int* order,
+                                hipStream_t s, const int64_t* live = nullptr);
 // Per item, 1 if a dense-path block is proved to stay dense (kept rank above
 // half its short edge), else 0; count (optional) is incremented per proof.
 hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* cert,
-                             unsigned long long* count, hipStream_t s);
+                             unsigned long long* count, hipStream_t s,
+                             const int64_t* live = nullptr);
 // Device-side statistics of one recompression launch (zeroed by the caller).
 struct RecCounters {
   double flops_bidiag;              // 4 p q^2 - 4 q^3 / 3 per block the register engine reduces
@@ -243,7 +323,7 @@ struct RecCounters {
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
                              int* status, GemmItem* gout, Seg* gseg, int* order, int* cert,
                              RecCounters* ctr, hipStream_t s, hipEvent_t engine_begin = nullptr,
-                             hipEvent_t engine_end = nullptr);
+                             hipEvent_t engine_end = nullptr, const int64_t* live = nullptr);
 hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
                            hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,
@@ -252,13 +332,21 @@ hipError_t launch_reduce(const double* in, int64_t n, int narrays, double* total
 hipError_t launch_fill(const PlanParams& P, const FillParams& F, hipStream_t s);
 hipError_t launch_add_base(int64_t* off, int64_t n, int narrays, const int64_t* base,
                            hipStream_t s);
+// Capacity check of one pipeline run (after the scan wrote totals): the live
+// lengths become the totals, or 0 once any total exceeds its capacity.
+hipError_t launch_caps(const int64_t* totals, const Caps& caps, int64_t* live, hipStream_t s);
+// acc[0] += the flop totals (kStFlops*) of one product, on the device.
+hipError_t launch_add_flops(const double* tot_st, double* acc, hipStream_t s);
+hipError_t launch_comb_count(const CombParams& P, int64_t* cnt, hipStream_t s);
+hipError_t launch_comb_fill(const CombParams& P, const CombLists& L, hipStream_t s);
 hipError_t prepare_recompress();
 hipError_t launch_ingest(const MatView& M, double* arena, const double* const* f0,
                          const double* const* f1, double* norm_out, hipStream_t s);
 hipError_t launch_to_dense(const MatView& M, double* out, int64_t ld, hipStream_t s);
 hipError_t launch_scale(const MatView& M, double* arena, double* norm, double sc, hipStream_t s);
 hipError_t launch_identity_terms(const MatView& M, double* out, hipStream_t s);
-hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s);
+hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s,
+                              const int64_t* live = nullptr);
 // out[0] = sqrt(sum of n terms) / sqrt(rows) on the device (one workgroup).
 hipError_t launch_residual_finish(const double* terms, int64_t n, double rows, double* out,
                                   hipStream_t s);

@@ -308,8 +308,9 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
 template <int WR, int WC, int TU, int TW>
 __global__ __launch_bounds__(64 * WR * WC, 4) void k_dense_cert(
     const RecItem* __restrict__ items, int nitems, double tol, int qlo, int* __restrict__ cert,
-    unsigned long long* __restrict__ count) {
+    unsigned long long* __restrict__ count, const int64_t* __restrict__ live) {
   __shared__ CertLds L;
+  if (live) nitems = (int)min((int64_t)nitems, *live);
   const int per = gridDim.x / 8;
   const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (item >= nitems) return;
@@ -328,16 +329,16 @@ __global__ __launch_bounds__(64 * WR * WC, 4) void k_dense_cert(
 }  // namespace
 
 hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* cert,
-                             unsigned long long* count, hipStream_t s) {
+                             unsigned long long* count, hipStream_t s, const int64_t* live) {
   static_assert(16 * 4 * 3 >= kCertEdge, "the largest size class covers kCertEdge");
   if (nitems <= 0) return hipSuccess;
   hipError_t e = launch_fill_i32(cert, 0, nitems, s);
   if (e != hipSuccess) return e;
   const int grid = ((nitems + 7) / 8) * 8;
   hipLaunchKernelGGL((k_dense_cert<2, 4, 4, 2>), dim3(grid), dim3(512), 0, s, items, nitems, tol,
-                     0, cert, count);
+                     0, cert, count, live);
   hipLaunchKernelGGL((k_dense_cert<4, 4, 3, 3>), dim3(grid), dim3(1024), 0, s, items, nitems,
-                     tol, 128, cert, count);
+                     tol, 128, cert, count, live);
   return hipGetLastError();
 }
 

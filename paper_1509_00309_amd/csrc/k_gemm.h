@@ -499,9 +499,12 @@ template <bool F32, bool SPLIT, bool DENSE>
 __global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
                                                               const Seg* __restrict__ segs,
                                                               int nitems,
-                                                              const int* __restrict__ order) {
+                                                              const int* __restrict__ order,
+                                                              const int64_t* __restrict__ live) {
   using CF = GemmCfg<F32, SPLIT>;
   __shared__ GemmLds<F32, SPLIT> sh;
+  // a device-resident count (captured launches) caps the grid's capacity
+  if (live) nitems = uni((int)min((int64_t)nitems, *live));
 
   // With an order (items by decreasing cost), workgroup b runs item order[b]:
   // the dispatcher deals workgroups to the 8 XCDs round-robin, so the long
@@ -775,7 +778,9 @@ template <bool F32, bool SPLIT>
 __global__ __launch_bounds__(64 * kWaveItemsPerBlock, 2) void k_wgemm(const GemmItem* __restrict__ items,
                                                                   const Seg* __restrict__ segs,
                                                                   int nitems,
-                                                                  const int* __restrict__ order) {
+                                                                  const int* __restrict__ order,
+                                                                  const int64_t* __restrict__ live) {
+  if (live) nitems = uni((int)min((int64_t)nitems, *live));
   // Workgroups are dealt to the 8 XCDs round-robin; blk numbers the
   // workgroups of one XCD consecutively, so neighbouring slots (items that
   // share an operand block once ordered by it) run on one XCD's L2.

@@ -5,28 +5,28 @@
 namespace clr {
 
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s, bool dense, const int* order) {
+                            hipStream_t s, bool dense, const int* order, const int64_t* live) {
   if (nitems <= 0) return hipSuccess;
   const dim3 grid(xcd_grid(nitems)), block(kLdsGemmThreads);
   if (split && dense)
-    hipLaunchKernelGGL((k_ggemm<true, true, true>), grid, block, 0, s, items, segs, nitems, order);
+    hipLaunchKernelGGL((k_ggemm<true, true, true>), grid, block, 0, s, items, segs, nitems, order, live);
   else if (split)
-    hipLaunchKernelGGL((k_ggemm<true, true, false>), grid, block, 0, s, items, segs, nitems, order);
+    hipLaunchKernelGGL((k_ggemm<true, true, false>), grid, block, 0, s, items, segs, nitems, order, live);
   else if (dense)
-    hipLaunchKernelGGL((k_ggemm<true, false, true>), grid, block, 0, s, items, segs, nitems, order);
+    hipLaunchKernelGGL((k_ggemm<true, false, true>), grid, block, 0, s, items, segs, nitems, order, live);
   else
-    hipLaunchKernelGGL((k_ggemm<true, false, false>), grid, block, 0, s, items, segs, nitems, order);
+    hipLaunchKernelGGL((k_ggemm<true, false, false>), grid, block, 0, s, items, segs, nitems, order, live);
   return hipGetLastError();
 }
 
 hipError_t launch_wgemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s, const int* order) {
+                            hipStream_t s, const int* order, const int64_t* live) {
   if (nitems <= 0) return hipSuccess;
   const dim3 grid(wave_grid(nitems)), block(64 * kWaveItemsPerBlock);
   if (split)
-    hipLaunchKernelGGL((k_wgemm<true, true>), grid, block, 0, s, items, segs, nitems, order);
+    hipLaunchKernelGGL((k_wgemm<true, true>), grid, block, 0, s, items, segs, nitems, order, live);
   else
-    hipLaunchKernelGGL((k_wgemm<true, false>), grid, block, 0, s, items, segs, nitems, order);
+    hipLaunchKernelGGL((k_wgemm<true, false>), grid, block, 0, s, items, segs, nitems, order, live);
   return hipGetLastError();
 }
 

@@ -144,7 +144,9 @@ __global__ __launch_bounds__(256) void k_residual_finish(const double* __restric
 }
 
 // D = a X + b Y + c I over the dense parts of one block.
-__global__ __launch_bounds__(256) void k_axpby_dense(const AxpbyDenseItem* items) {
+__global__ __launch_bounds__(256) void k_axpby_dense(const AxpbyDenseItem* items,
+                                                     const int64_t* __restrict__ live) {
+  if (live && (int64_t)blockIdx.x >= *live) return;
   const AxpbyDenseItem it = items[blockIdx.x];
   for (int64_t e = threadIdx.x; e < (int64_t)it.m * it.n; e += 256) {
     const int i = (int)(e % it.m), j = (int)(e / it.m);
@@ -298,9 +300,9 @@ hipError_t launch_residual_finish(const double* terms, int64_t n, double rows, d
   hipLaunchKernelGGL(k_residual_finish, dim3(1), dim3(256), 0, s, terms, n, rows, out);
   return hipGetLastError();
 }
-hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s) {
+hipError_t launch_axpby_dense(const void* items, int n, hipStream_t s, const int64_t* live) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_axpby_dense, dim3(n), dim3(256), 0, s, (const AxpbyDenseItem*)items);
+  hipLaunchKernelGGL(k_axpby_dense, dim3(n), dim3(256), 0, s, (const AxpbyDenseItem*)items, live);
   return hipGetLastError();
 }
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
@@ -334,9 +336,11 @@ __device__ inline int item_cost_class(const GemmItem& it) {
 }
 
 __global__ __launch_bounds__(kOrderThreads) void k_item_order(const GemmItem* __restrict__ items,
-                                                             int n, int* __restrict__ order) {
+                                                             int n, int* __restrict__ order,
+                                                             const int64_t* __restrict__ live) {
   __shared__ int cnt[kOrderClasses];
   const int tid = threadIdx.x;
+  if (live) n = (int)min((int64_t)n, *live);
   if (tid < kOrderClasses) cnt[tid] = 0;
   __syncthreads();
   for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&cnt[item_cost_class(items[i])], 1);
@@ -353,9 +357,10 @@ __global__ __launch_bounds__(kOrderThreads) void k_item_order(const GemmItem* __
   for (int i = tid; i < n; i += kOrderThreads) order[atomicAdd(&cnt[item_cost_class(items[i])], 1)] = i;
 }
 
-hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s) {
+hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s,
+                             const int64_t* live) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_item_order, dim3(1), dim3(kOrderThreads), 0, s, items, nitems, order);
+  hipLaunchKernelGGL(k_item_order, dim3(1), dim3(kOrderThreads), 0, s, items, nitems, order, live);
   return hipGetLastError();
 }
 
@@ -432,6 +437,64 @@ hipError_t launch_kernel_matrix(const double* xr, int64_t nr, const double* xc, 
   const dim3 grid((unsigned)((nr + 255) / 256), (unsigned)((nc + kKmCols - 1) / kKmCols));
   hipLaunchKernelGGL(k_kernel_matrix, grid, dim3(256), 0, s, xr, nr, xc, nc, dim, kind, a, diag,
                      out, ld);
+  return hipGetLastError();
+}
+
+// Operand grouping without a library sort (recordable in a graph): a
+// counting sort of the items into kGroupBuckets buckets by a multiplicative
+// hash of their first term's left-operand address, in one workgroup.  Items
+// that read the same operand block share the address, hence the bucket, so
+// they run next to each other; the order inside a bucket (atomics) and of the
+// buckets changes no result.
+constexpr int kGroupBuckets = 4096;
+
+__device__ inline int operand_bucket(const GemmItem* items, const Seg* segs, int i) {
+  const uint64_t a = (uint64_t)(uintptr_t)segs[items[i].seg0].L >> 3;
+  return (int)((a * 0x9E3779B97F4A7C15ull) >> (64 - 12));
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_operand_group(const GemmItem* __restrict__ items,
+                                                                const Seg* __restrict__ segs, int n,
+                                                                int* __restrict__ order,
+                                                                const int64_t* __restrict__ live) {
+  static_assert(kGroupBuckets == 1 << 12, "the hash keeps 12 bits");
+  __shared__ int cnt[kGroupBuckets];
+  __shared__ int part[kOrderThreads];
+  const int tid = threadIdx.x;
+  if (live) n = (int)min((int64_t)n, *live);
+  for (int b = tid; b < kGroupBuckets; b += kOrderThreads) cnt[b] = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += kOrderThreads) atomicAdd(&cnt[operand_bucket(items, segs, i)], 1);
+  __syncthreads();
+  // exclusive scan of the buckets: each thread owns kGroupBuckets / kOrderThreads
+  // consecutive buckets; the per-thread totals are scanned in LDS
+  constexpr int per = kGroupBuckets / kOrderThreads;
+  int own = 0;
+  for (int t = 0; t < per; ++t) own += cnt[tid * per + t];
+  part[tid] = own;
+  __syncthreads();
+  for (int o = 1; o < kOrderThreads; o <<= 1) {
+    const int v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - own;
+  for (int t = 0; t < per; ++t) {
+    const int c = cnt[tid * per + t];
+    cnt[tid * per + t] = run;
+    run += c;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kOrderThreads)
+    order[atomicAdd(&cnt[operand_bucket(items, segs, i)], 1)] = i;
+}
+
+hipError_t launch_operand_group(const GemmItem* items, const Seg* segs, int nitems, int* order,
+                                hipStream_t s, const int64_t* live) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_operand_group, dim3(1), dim3(kOrderThreads), 0, s, items, segs, nitems,
+                     order, live);
   return hipGetLastError();
 }
 

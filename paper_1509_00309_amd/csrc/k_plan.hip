@@ -19,6 +19,13 @@ namespace clr {
 __device__ inline int64_t parts2(int rows, int cols, int maxe) {
   return (int64_t)num_parts(rows, maxe) * num_parts(cols, maxe);
 }
+// items of a thin (factor-product) output and of a dense-accumulated block
+__device__ inline int64_t thin_parts(const EdgeTable& E, int rows, int cols) {
+  return parts2(rows, cols, thin_edge(E, rows, cols));
+}
+__device__ inline int64_t dense_parts(const EdgeTable& E, int m, int n) {
+  return parts2(m, n, dense_edge(E, m, n));
+}
 
 __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __restrict__ st,
                            int* __restrict__ flags) {
@@ -51,30 +58,30 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
       ++nld;
       rcat += ra;
       pool += (int64_t)n * ra;
-      thin1 += parts2(n, ra, P.max_item_thin);
+      thin1 += thin_parts(P.edges, n, ra);
       fld += 2.0 * ra * (double)k * n;
     } else if (ka == 1 && kb == 2) {
       const int rb = P.B.rank[K * P.ncb + J];
       ++ndl;
       rcat += rb;
       pool += (int64_t)m * rb;
-      thin1 += parts2(m, rb, P.max_item_thin);
+      thin1 += thin_parts(P.edges, m, rb);
       fdl += 2.0 * m * (double)k * rb;
     } else {
       const int ra = P.A.rank[I * P.nkb + K];
       const int rb = P.B.rank[K * P.ncb + J];
       ++nll;
       pool += (int64_t)ra * rb;
-      thin1 += parts2(ra, rb, P.max_item_thin);
+      thin1 += thin_parts(P.edges, ra, rb);
       if (rb < ra) {
         rcat += rb;
         pool += (int64_t)m * rb;
-        thin2 += parts2(m, rb, P.max_item_thin);
+        thin2 += thin_parts(P.edges, m, rb);
         fll += 2.0 * k * (double)ra * rb + 2.0 * m * (double)ra * rb;
       } else {
         rcat += ra;
         pool += (int64_t)n * ra;
-        thin2 += parts2(n, ra, P.max_item_thin);
+        thin2 += thin_parts(P.edges, n, ra);
         fll += 2.0 * k * (double)ra * rb + 2.0 * n * (double)ra * rb;
       }
     }
@@ -98,7 +105,7 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
     const int path = force ? kPathForceDense : (densify ? kPathDense : kPathLowRank);
     c[kCntScratch] = rec_scratch_doubles(path, m, n, (int)rcat, P.tol);
     c[kCntComputed] = 1;
-    c[kCntGemmItems] = densify ? parts2(m, n, P.max_item) : 0;
+    c[kCntGemmItems] = densify ? dense_parts(P.edges, m, n) : 0;
     if (densify) fden = 2.0 * m * (double)n * (double)lr_rank_sum;
   }
   for (int i = 0; i < kNumCounters; ++i) cnt[(int64_t)i * npairs + pair] = c[i];
@@ -172,7 +179,8 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, i
 
 // Emit the sub-items of one thin product job (single term) into a list.
 __device__ void emit_thin(Seg* segs, GemmItem* items, int64_t& cursor, const Seg& s, double* C,
-                          int64_t ldc, int rows, int cols, int max_item) {
+                          int64_t ldc, int rows, int cols, const EdgeTable& E) {
+  const int max_item = thin_edge(E, rows, cols);
   const int pr = num_parts(rows, max_item), pc = num_parts(cols, max_item);
   for (int a = 0; a < pr; ++a) {
     int r0, rl;
@@ -220,6 +228,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   const int npairs = P.nrb * P.ncb;
   const int pair = blockIdx.x * blockDim.x + threadIdx.x;
   if (pair >= npairs) return;
+  if (F.abort && *F.abort) return;   // a list would overflow its capacity
   const int fl = F.flags[pair];
   if (!(fl & kFlagComputed)) return;
   const bool densify = fl & kFlagDensify;
@@ -263,7 +272,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
       double* T = F.pool + po;
       po += (int64_t)n * ra;
       emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(b, k, 1, Va, 1, k, k, 1.0), T, n, n, ra,
-                P.max_item_thin);
+                P.edges);
       dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
       pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
     } else if (ka == 1 && kbk == 2) {
@@ -274,7 +283,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
       double* T = F.pool + po;
       po += (int64_t)m * rb;
       emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(a, 1, m, Ub, 1, k, k, 1.0), T, m, m, rb,
-                P.max_item_thin);
+                P.edges);
       dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
       pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
     } else {
@@ -288,18 +297,18 @@ __global__ void k_fill(PlanParams P, FillParams F) {
       double* Z = F.pool + po;
       po += (int64_t)ra * rb;
       emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(Va, k, 1, Ub, 1, k, k, 1.0), Z, ra, ra,
-                rb, P.max_item_thin);
+                rb, P.edges);
       double* T = F.pool + po;
       if (rb < ra) {
         po += (int64_t)m * rb;   // T = U_A Z (m x rB)
         emit_thin(F.seg_thin2, F.items_thin2, t2, make_seg(Ua, 1, m, Z, 1, ra, ra, 1.0), T, m, m,
-                  rb, P.max_item_thin);
+                  rb, P.edges);
         dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
         pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
       } else {
         po += (int64_t)n * ra;   // T = V_B Z^T (n x rA)
         emit_thin(F.seg_thin2, F.items_thin2, t2, make_seg(Vb, 1, n, Z, ra, 1, rb, 1.0), T, n, n,
-                  ra, P.max_item_thin);
+                  ra, P.edges);
         dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
         pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
       }
@@ -316,7 +325,8 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   const double tau = P.screen ? P.eps_sp * m * (double)n : P.eps_sp;
   if (densify) {
     int64_t gi = off(kCntGemmItems);
-    const int pr = num_parts(m, P.max_item), pcn = num_parts(n, P.max_item);
+    const int de = dense_edge(P.edges, m, n);
+    const int pr = num_parts(m, de), pcn = num_parts(n, de);
     for (int a = 0; a < pr; ++a) {
       int r0, rl;
       part_range(m, pr, a, &r0, &rl);
@@ -339,7 +349,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
       }
     }
   }
-  RecItem r;
+  RecItem r{};   // every field defined (rrqr = 0: products truncate by the SVD)
   r.path = force ? kPathForceDense : (densify ? kPathDense : kPathLowRank);
   r.m = m;
   r.n = n;
@@ -395,6 +405,211 @@ hipError_t launch_add_base(int64_t* off, int64_t n, int narrays, const int64_t* 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_add_base, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, off, n,
                      narrays, base);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Capacity check of a run whose list lengths stay on the device (one thread).
+// ---------------------------------------------------------------------------
+__global__ void k_caps(const int64_t* __restrict__ totals, Caps caps, int64_t* __restrict__ live) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  bool over = live[kLiveOverflow] != 0;
+  for (int c = 0; c < kNumCounters; ++c) {
+    const int64_t t = totals[c];
+    if (t > caps.c[c]) over = true;
+    if (t > live[kLiveNeed + c]) live[kLiveNeed + c] = t;
+  }
+  for (int c = 0; c < kNumCounters; ++c) live[c] = over ? 0 : totals[c];
+  if (over) live[kLiveOverflow] = 1;
+}
+
+// acc[0] += the flop totals of one product (DD, LD, DL, LL and densify terms).
+__global__ void k_add_flops(const double* __restrict__ tot_st, double* __restrict__ acc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  acc[0] += tot_st[kStFlopsDD] + tot_st[kStFlopsLD] + tot_st[kStFlopsDL] + tot_st[kStFlopsLL] +
+            tot_st[kStFlopsDensify];
+}
+
+hipError_t launch_add_flops(const double* tot_st, double* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_flops, dim3(1), dim3(64), 0, s, tot_st, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_caps(const int64_t* totals, const Caps& caps, int64_t* live, hipStream_t s) {
+  hipLaunchKernelGGL(k_caps, dim3(1), dim3(64), 0, s, totals, caps, live);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Blockwise combination T = a X + b Y + c I.  Per block: the estimate
+// |a| ||X_IJ|| + |b| ||Y_IJ|| + |c| sqrt(m) (the identity on diagonal blocks)
+// screened against tau; the block is summed densely (and then recompressed
+// by the dense path) if it is diagonal, has a dense operand, or its
+// concatenated rank reaches half its short edge; otherwise the factors are
+// concatenated (Eq. (5)) and recompressed by the low-rank path.
+// ---------------------------------------------------------------------------
+struct CombDecision {
+  bool computed, densify, diag;
+  int m, n, kx, ky, rx, ry, R;
+  double tau;
+};
+
+__device__ inline CombDecision comb_decide(const CombParams& P, int I, int J) {
+  CombDecision d{};
+  const int b = I * P.X.ncb + J;
+  d.m = P.X.roff[I + 1] - P.X.roff[I];
+  d.n = P.X.coff[J + 1] - P.X.coff[J];
+  d.kx = P.X.kind[b];
+  d.ky = P.Y.kind ? P.Y.kind[b] : 0;
+  d.rx = d.kx == 2 ? P.X.rank[b] : 0;
+  d.ry = d.ky == 2 ? P.Y.rank[b] : 0;
+  d.diag = P.square && I == J;
+  const bool has_i = d.diag && P.c != 0.0;
+  double est = 0.0;
+  if (d.kx) est += fabs(P.a) * P.X.norm[b];
+  if (d.ky) est += fabs(P.b) * P.Y.norm[b];
+  if (has_i) est += fabs(P.c) * sqrt((double)d.m);
+  d.tau = P.screen ? P.eps_sp * d.m * (double)d.n : P.eps_sp;
+  d.computed = (d.kx || d.ky || has_i) && est >= d.tau;
+  d.R = d.rx + d.ry;
+  const bool any_dense = d.kx == 1 || d.ky == 1 || has_i;
+  d.densify = d.diag || any_dense || 2 * d.R >= min(d.m, d.n);
+  return d;
+}
+
+__global__ void k_comb_count(CombParams P, int64_t* __restrict__ cnt) {
+  const int nb = P.X.nrb * P.X.ncb;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const CombDecision d = comb_decide(P, b / P.X.ncb, b % P.X.ncb);
+  int64_t c[kNumCounters];
+  for (int i = 0; i < kNumCounters; ++i) c[i] = 0;
+  if (d.computed) {
+    const int nlr = (d.kx == 2) + (d.ky == 2);
+    c[kCntComputed] = 1;
+    if (d.densify) {
+      c[kCntCombDense] = 1;
+      c[kCntSegDense] = nlr;
+      c[kCntGemmItems] = nlr ? dense_parts(P.edges, d.m, d.n) : 0;
+      c[kCntScratch] =
+          rec_scratch_doubles(d.diag ? kPathForceDense : kPathDense, d.m, d.n, 0, P.tol);
+    } else {
+      c[kCntPieces] = nlr;
+      c[kCntScratch] = rec_scratch_doubles(kPathLowRank, d.m, d.n, d.R, P.tol);
+    }
+  }
+  for (int i = 0; i < kNumCounters; ++i) cnt[(int64_t)i * nb + b] = c[i];
+}
+
+__global__ void k_comb_fill(CombParams P, CombLists L) {
+  const int nb = P.X.nrb * P.X.ncb;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  if (L.abort && *L.abort) return;
+  const int I = b / P.X.ncb, J = b % P.X.ncb;
+  const CombDecision d = comb_decide(P, I, J);
+  if (!d.computed) return;
+  auto off = [&](int c) { return L.off[(int64_t)c * nb + b]; };
+  const int m = d.m, n = d.n;
+  const int64_t so = slot_offset(P.X.roff, P.X.coff, P.X.ncols, I, J);
+  const double* xs = P.X.arena + so;
+  const double* ys = P.Y.kind ? P.Y.arena + so : nullptr;
+  RecItem r{};
+  r.m = m;
+  r.n = n;
+  r.tau = d.tau;
+  r.out = P.t_arena + so;
+  r.kind_out = P.t_kind + b;
+  r.rank_out = P.t_rank + b;
+  r.norm_out = P.t_norm + b;
+  if (d.densify) {
+    r.path = d.diag ? kPathForceDense : kPathDense;
+    r.cert_hint = 1;
+    r.D = P.acc + so;
+    r.ldd = m;
+    AxpbyDenseItem di;
+    di.D = P.acc + so;
+    di.X = d.kx == 1 ? xs : nullptr;
+    di.Y = d.ky == 1 ? ys : nullptr;
+    di.a = P.a;
+    di.b = P.b;
+    di.c = d.diag ? P.c : 0.0;
+    di.m = m;
+    di.n = n;
+    L.dense[off(kCntCombDense)] = di;
+    // low-rank operands enter the dense sum as U V^T products (scale a or b)
+    const int64_t s0 = off(kCntSegDense);
+    int64_t sc = s0;
+    int kb = 0;
+    auto add_lr = [&](const double* f, int rk, double scale) {
+      Seg sg;
+      sg.L = f;                     // U (m x r)
+      sg.sLi = 1;
+      sg.sLk = m;
+      sg.R = f + (int64_t)m * rk;   // V (n x r) used transposed
+      sg.sRk = n;
+      sg.sRj = 1;
+      sg.k = rk;
+      sg.kbase = kb;
+      sg.scale = scale;
+      kb += rk;
+      L.segs[sc++] = sg;
+    };
+    if (d.kx == 2) add_lr(xs, d.rx, P.a);
+    if (d.ky == 2) add_lr(ys, d.ry, P.b);
+    if (kb > 0) {
+      int64_t gi = off(kCntGemmItems);
+      const int de = dense_edge(P.edges, m, n);
+      const int pr = num_parts(m, de), pc = num_parts(n, de);
+      for (int pa = 0; pa < pr; ++pa)
+        for (int pb = 0; pb < pc; ++pb) {
+          GemmItem g;
+          part_range(m, pr, pa, &g.row0, &g.m);
+          part_range(n, pc, pb, &g.col0, &g.n);
+          g.C = P.acc + so;
+          g.ldc = m;
+          g.seg0 = (int)s0;
+          g.nseg = (int)(sc - s0);
+          g.ktotal = kb;
+          g.accumulate = 1;
+          g.alpha = 1.0;
+          L.items[gi++] = g;
+        }
+    }
+  } else {
+    r.path = kPathLowRank;
+    r.piece0 = (int)off(kCntPieces);
+    r.R = d.R;
+    int64_t pi = off(kCntPieces);
+    auto add_piece = [&](const double* f, int rk, double scale) {
+      Piece p{};
+      p.U = f;
+      p.ldu = m;
+      p.V = f + (int64_t)m * rk;
+      p.ldv = n;
+      p.r = rk;
+      p.scale = scale;
+      L.pieces[pi++] = p;
+    };
+    if (d.kx == 2) add_piece(xs, d.rx, P.a);
+    if (d.ky == 2) add_piece(ys, d.ry, P.b);
+    r.npieces = (int)(pi - r.piece0);
+  }
+  r.scratch = L.cnt[(int64_t)kCntScratch * nb + b] > 0 ? L.scratch + off(kCntScratch) : nullptr;
+  L.rec[off(kCntComputed)] = r;
+}
+
+hipError_t launch_comb_count(const CombParams& P, int64_t* cnt, hipStream_t s) {
+  const int nb = P.X.nrb * P.X.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_comb_count, dim3((nb + 255) / 256), dim3(256), 0, s, P, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_comb_fill(const CombParams& P, const CombLists& L, hipStream_t s) {
+  const int nb = P.X.nrb * P.X.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_comb_fill, dim3((nb + 255) / 256), dim3(256), 0, s, P, L);
   return hipGetLastError();
 }
 

@@ -1958,9 +1958,11 @@ __device__ inline bool item_guard(const RecItem& it, double tol, int* status) {
 __global__ __launch_bounds__(kRecThreads) void k_recompress(const RecItem* __restrict__ items,
                                                             const Piece* __restrict__ pieces,
                                                             int nitems, double tol, int* status,
-                                                            const int* __restrict__ cert) {
+                                                            const int* __restrict__ cert,
+                                                            const int64_t* __restrict__ live) {
   extern __shared__ double lds[];
   __shared__ RecShared sh;
+  if (live) nitems = (int)min((int64_t)nitems, *live);
   const int per = gridDim.x / 8;
   const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (item >= nitems) return;
@@ -1992,9 +1994,11 @@ __device__ inline int rec_cost_class(const RecItem& it, double tol, bool certifi
 
 __global__ __launch_bounds__(1024) void k_rec_order(const RecItem* __restrict__ items, int n,
                                                     double tol, const int* __restrict__ cert,
-                                                    int* __restrict__ order) {
+                                                    int* __restrict__ order,
+                                                    const int64_t* __restrict__ live) {
   __shared__ int cnt[kRecOrderClasses];
   const int tid = threadIdx.x;
+  if (live) n = (int)min((int64_t)n, *live);
   if (tid < kRecOrderClasses) cnt[tid] = 0;
   __syncthreads();
   for (int i = tid; i < n; i += 1024)
@@ -2019,9 +2023,11 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* _
                                                                 Seg* gseg,
                                                                 const int* __restrict__ order,
                                                                 const int* __restrict__ cert,
-                                                                double* flops_bidiag) {
+                                                                double* flops_bidiag,
+                                                                const int64_t* __restrict__ live) {
   extern __shared__ double lds[];
   __shared__ RecShared sh;
+  if (live) nitems = (int)min((int64_t)nitems, *live);
   int item;
   if (order) {
     if ((int)blockIdx.x >= nitems) return;
@@ -2055,7 +2061,7 @@ hipError_t prepare_recompress() {
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
                              int* status, GemmItem* gout, Seg* gseg, int* order, int* cert,
                              RecCounters* ctr, hipStream_t s, hipEvent_t engine_begin,
-                             hipEvent_t engine_end) {
+                             hipEvent_t engine_end, const int64_t* live) {
   if (nitems <= 0) return hipSuccess;
   {
     hipError_t e = prepare_recompress();
@@ -2074,13 +2080,14 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
     if (e != hipSuccess) return e;
   }
   if (cert && tol > 0.0) {
-    e = launch_dense_cert(items, nitems, tol, cert, ctr ? &ctr->certified : nullptr, s);
+    e = launch_dense_cert(items, nitems, tol, cert, ctr ? &ctr->certified : nullptr, s, live);
     if (e != hipSuccess) return e;
   } else {
     cert = nullptr;
   }
   if (order) {
-    hipLaunchKernelGGL(k_rec_order, dim3(1), dim3(1024), 0, s, items, nitems, tol, cert, order);
+    hipLaunchKernelGGL(k_rec_order, dim3(1), dim3(1024), 0, s, items, nitems, tol, cert, order,
+                       live);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -2090,7 +2097,7 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
   }
   hipLaunchKernelGGL(k_recompress_reg, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items,
                      nitems, tol, status, gout, gseg, order, cert,
-                     ctr ? &ctr->flops_bidiag : nullptr);
+                     ctr ? &ctr->flops_bidiag : nullptr, live);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (engine_end) {
@@ -2098,7 +2105,7 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_recompress, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items, pieces,
-                     nitems, tol, status, cert);
+                     nitems, tol, status, cert, live);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // other factors of the truncated register-engine blocks: G_orig * basis on FP64 MFMA

@@ -514,6 +514,88 @@ def test_sqrt_inv_wide_lattice_3d(ctx, torch):
     parity.assert_parity(rep, FP64_BOUND, nblocks=len(wl.sizes) ** 2)
 
 
+def _same_clr(torch, A, B):
+    """Two CLR matrices with equal kinds, ranks, norms and dense values, bit for bit."""
+    ka, ra, na = A.meta()
+    kb, rb, nb = B.meta()
+    assert np.array_equal(ka, kb) and np.array_equal(ra, rb)
+    assert np.array_equal(na, nb)
+    assert torch.equal(A.to_dense(), B.to_dense())
+
+
+@pytest.mark.parametrize("case,precision,margin", [("line", "fp64", 0.0), ("wide", "fp64", 0.0),
+                                                    ("wide", "mixed", 0.0), ("line", "fp64", 0.01)])
+def test_sqrt_inv_graph_replay_bit_exact(ctx, torch, case, precision, margin):
+    """S^-1/2 with each iteration replayed from a recorded HIP graph (the four products, the
+    combination of Eq. (9) and the residual terms, list lengths kept on the device) equals the
+    directly run iteration bit for bit: W's kinds, ranks, norms and values, the iteration
+    count, status and both residuals.  Margin 0.01 gives the graph lists too small for the
+    second iteration, so the device flags the overflow, that iteration is redone directly and
+    the graphs are recorded again (at least four recordings), still with equal results.  The
+    iterates fill in as Z_n approaches S^-1/2, so lists can also outgrow the default margin
+    (measured: the line workload re-records twice at margin 1.5)."""
+    log(f"sqrt_inv graph replay {case} {precision} margin {margin}")
+    wl = line_n512() if case == "line" else scaled_workload("wide", 1536)
+    Sd = wl.dense()
+    S = ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    conv = wl.extra["conv_tol"]
+    kw = dict(conv_tol=conv, precision=precision, allow_not_converged=True)
+    if precision == "mixed":
+        kw["max_iter"] = 14
+    W0, s0 = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, **kw)
+    W1, s1 = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, graph=True, graph_margin=margin, **kw)
+    log(f"  direct: iters={s0.iterations} internal={s0.internal_residual:.3e} "
+        f"explicit={s0.explicit_residual:.3e}; graph: iters={s1.iterations} "
+        f"replays={s1.graph_replays} captures={s1.graph_captures}")
+    assert s1.iterations == s0.iterations and s1.converged == s0.converged
+    assert s1.internal_residual == s0.internal_residual
+    assert s1.explicit_residual == s0.explicit_residual
+    assert abs(s1.flops_products - s0.flops_products) <= 1e-12 * s0.flops_products
+    _same_clr(torch, W0, W1)
+    # every directly run iteration (the first, and each one whose lists overflowed) is followed
+    # by two recordings; every other iteration is a replay
+    assert s1.graph_captures % 2 == 0 and s1.graph_captures >= 2
+    assert s1.graph_replays + s1.graph_captures // 2 == s0.iterations
+    if margin == 0.0:
+        assert s1.graph_replays >= 1
+    else:
+        assert s1.graph_captures >= 4
+
+
+def test_sqrt_inv_graph_replay_bit_exact_n8192(ctx, torch):
+    """Graph replay against the direct iteration on the N = 8192 wide 3-D lattice (64 clusters) at
+    3 fixed iterations.  The graph's workspace is separate from the one direct calls reuse (its
+    buffers hold other data), so a kernel whose result depended on what a buffer held before (once: an
+    uninitialised flag of the product's recompression items, which sent random blocks to the
+    column-pivoted-QR truncation) shows up as a difference here."""
+    from workloads import lattice_3d_wide
+    wl = lattice_3d_wide(8192, 64)
+    S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    W0, s0 = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, fixed_iters=3)
+    W1, s1 = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, fixed_iters=3, graph=True)
+    log(f"  N=8192 graph replays={s1.graph_replays} captures={s1.graph_captures} "
+        f"internal {s0.internal_residual:.17e} / {s1.internal_residual:.17e}")
+    assert s1.graph_replays == 2 and s1.internal_residual == s0.internal_residual
+    _same_clr(torch, W0, W1)
+
+
+def test_sqrt_inv_graph_fixed_iterations_and_rejections(ctx, torch):
+    """Graph replay with a fixed iteration count equals the direct run; the precision schedule
+    and the INT8 form are rejected with graph replay."""
+    from paper_1509_00309_amd._abi import ClrError
+    wl = line_n512()
+    S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+    W0, s0 = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, fixed_iters=6)
+    W1, s1 = ctx.sqrt_inv(S, wl.tol, wl.eps_sp, fixed_iters=6, graph=True)
+    assert s1.graph_replays + s1.graph_captures // 2 == 6
+    assert s1.internal_residual == s0.internal_residual
+    _same_clr(torch, W0, W1)
+    with pytest.raises(ClrError):
+        ctx.sqrt_inv(S, wl.tol, wl.eps_sp, precision="mixed", reduced_below=0.3, graph=True)
+    with pytest.raises(ClrError):
+        ctx.sqrt_inv(S, wl.tol, wl.eps_sp, precision="ozaki", graph=True)
+
+
 @pytest.mark.parametrize("reduced_below", [0.3, 0.03])
 def test_mixed_sqrt_inv_schedule_wide_lattice_3d(ctx, torch, reduced_below):
     """Reduced-precision S^-1/2 with the precision schedule: FP64 products until
@@ -866,8 +948,9 @@ def test_plan_graph_replay(ctx, torch):
 
 
 def test_tile_edges_and_autotune(ctx, torch):
-    """Item edges change launch shapes only: results are bit-identical; the autotuner
-    returns admissible edges and leaves them set."""
+    """Item edges, one per launch class or one per shape class, change launch shapes only:
+    results are bit-identical; the autotuner returns admissible edges (launch classes, then
+    every shape class) and leaves them set."""
     log("tile edges and autotune")
     wl = scaled_workload("lattice", 1536, seed=144)
     S = ctx.compress(torch.from_numpy(wl.dense()).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10)
@@ -879,9 +962,21 @@ def test_tile_edges_and_autotune(ctx, torch):
     import paper_1509_00309_amd as clr
     with pytest.raises(clr.ClrError):
         ctx.set_tile_edges("fp64", 40, 0)
+    # per shape class: every class table gives the same result, bit for bit
+    for dense, thin in (([32, 48, 64, 96, 112, 160], [16, 32, 48, 64, 16]),
+                        ([160, 16, 32, 48, 64, 80], [64, 16, 32, 16, 48])):
+        ctx.set_tile_classes("fp64", dense, thin)
+        assert ctx.get_tile_classes("fp64") == (dense, thin)
+        got = ctx.gemm(S, S, wl.tol, wl.eps_sp).to_dense().cpu().numpy()
+        assert np.array_equal(got, ref), (dense, thin)
+    with pytest.raises(clr.ClrError):
+        ctx.set_tile_classes("fp64", [32, 48, 64, 96, 112, 176], [16, 32, 48, 64, 16])
     res = ctx.autotune(S, S, wl.tol, wl.eps_sp)
     log(f"  autotune: {res}")
     assert res["dense_edge"] in (32, 64, 96, 128, 160) and res["thin_edge"] in (32, 64)
+    assert all(e in (32, 64, 96, 128, 160) for e in res["dense_classes"])
+    assert all(e in (16, 32, 48, 64) for e in res["thin_classes"])
+    assert ctx.get_tile_classes("fp64") == (res["dense_classes"], res["thin_classes"])
     got = ctx.gemm(S, S, wl.tol, wl.eps_sp).to_dense().cpu().numpy()
     assert np.array_equal(got, ref)
     ctx.set_tile_edges("fp64", 0, 0)
