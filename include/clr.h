@@ -166,6 +166,21 @@ typedef struct {
  * hipStream_t; NULL selects the default stream).  Owns all workspace. */
 clr_status clr_context_create(clr_context** ctx, void* stream);
 clr_status clr_context_destroy(clr_context* ctx);
+
+/* The caller's device allocator for this context (for instance a framework's
+ * caching allocator): alloc(bytes, stream, user) returns device memory usable
+ * on `stream` (the context's stream, as given to clr_context_create) or NULL
+ * when out of memory; release(ptr, bytes, stream, user) gives it back, in
+ * stream order (work already queued on the stream may still read it).  Both
+ * NULL restores hipMalloc.  Matrices created afterwards and the work lists
+ * grown afterwards use it; memory is always released through the allocator
+ * that made it, so existing matrices stay valid.  The status word, the
+ * allocation-free residual's fixed array and clr_measure_peaks' buffer stay
+ * on hipMalloc.  Synchronises the context stream. */
+typedef void* (*clr_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*clr_release_fn)(void* ptr, size_t bytes, void* stream, void* user);
+clr_status clr_set_allocator(clr_context* ctx, clr_alloc_fn alloc, clr_release_fn release,
+                             void* user);
 /* Message of the last failing call on this context ("" if none).  Valid until
  * the next call on the context. */
 const char* clr_last_error(const clr_context* ctx);

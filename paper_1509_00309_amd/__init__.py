@@ -8,6 +8,8 @@ loads the shared library and fails loudly if it has not been built
 """
 from __future__ import annotations
 
+import atexit
+import sys
 import ctypes as C
 import os
 from dataclasses import dataclass
@@ -53,6 +55,12 @@ def _gemm_opts(tol, eps_sp, screen, precision, split, alpha) -> GemmOpts:
     return o
 
 
+# Set at interpreter exit, before objects are collected: callbacks into torch's allocator
+# stop then (see Context.use_torch_allocator).
+_FINALIZING = [False]
+atexit.register(lambda: _FINALIZING.__setitem__(0, True))
+
+
 class Context:
     """A library context bound to the current device and a torch stream."""
 
@@ -71,6 +79,37 @@ class Context:
         if getattr(self, "_h", None):
             lib.clr_context_destroy(self._h)
             self._h = None
+
+    def use_torch_allocator(self, enable: bool = True):
+        """Back this context's matrices and work lists with torch's caching allocator
+        (clr_set_allocator) on the context's stream; enable=False returns to hipMalloc.
+        The callbacks allocate and release through torch.cuda.caching_allocator_alloc /
+        caching_allocator_delete; they are kept alive by the context object."""
+        torch = _torch()
+        if not enable:
+            self._check(lib.clr_set_allocator(self._h, None, None, None))
+            self._alloc_cbs = None
+            return
+        device = self.device
+
+        def _alloc(nbytes, stream, user):
+            if _FINALIZING[0] or sys.is_finalizing():
+                return None
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream or 0)
+            except RuntimeError:
+                return None
+
+        def _release(ptr, nbytes, stream, user):
+            # once the interpreter is shutting down torch's allocator may already be gone:
+            # the process is ending, so the memory is left to the driver
+            if _FINALIZING[0] or sys.is_finalizing():
+                return
+            torch.cuda.caching_allocator_delete(ptr)
+
+        cbs = (_abi.ALLOC_FN(_alloc), _abi.RELEASE_FN(_release))
+        self._check(lib.clr_set_allocator(self._h, cbs[0], cbs[1], None))
+        self._alloc_cbs = cbs
 
     def __del__(self):
         try:
@@ -353,7 +392,8 @@ class Plan:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib.clr_plan_destroy(self._h)
+            if getattr(self.ctx, "_h", None):
+                lib.clr_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -377,8 +417,11 @@ class CLRMatrix:
         self.rows, self.cols = rows.value, cols.value
 
     def close(self):
+        # a matrix outliving its context (closed first) is left to it: the native
+        # handle refers to the context, which no longer exists
         if getattr(self, "_h", None):
-            lib.clr_destroy(self._h)
+            if getattr(self.ctx, "_h", None):
+                lib.clr_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -28,7 +28,8 @@ CLR_SCREEN_AREA = 1
 
 # Every function declared in include/clr.h.
 EXPORTS = [
-    "clr_context_create", "clr_context_destroy", "clr_last_error", "clr_status_string",
+    "clr_context_create", "clr_context_destroy", "clr_set_allocator", "clr_last_error",
+    "clr_status_string",
     "clr_create", "clr_compress", "clr_destroy", "clr_matrix_info", "clr_get_meta",
     "clr_get_block", "clr_to_dense", "clr_gemm", "clr_axpby", "clr_sqrt_inv",
     "clr_identity_residual", "clr_identity_residual_noalloc", "clr_gemm_backward", "clr_sqrt_inv_backward",
@@ -48,6 +49,11 @@ class SqrtInvOpts(C.Structure):
     _fields_ = [("g", GemmOpts), ("alpha", C.c_double), ("conv_tol", C.c_double),
                 ("max_iter", C.c_int), ("fixed_iters", C.c_int), ("reduced_below", C.c_double),
                 ("correction", C.c_int), ("graph", C.c_int), ("graph_margin", C.c_double)]
+
+
+# clr_set_allocator callbacks: alloc(bytes, stream, user) -> ptr, release(ptr, bytes, stream, user)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 
 
 class GemmStats(C.Structure):
@@ -120,6 +126,7 @@ def _load():
         "clr_plan_execute": [P, P, C.POINTER(GemmStats)],
         "clr_plan_destroy": [P],
         "clr_set_tile_edges": [P, C.c_int, C.c_int, C.c_int],
+        "clr_set_allocator": [P, ALLOC_FN, RELEASE_FN, P],
         "clr_set_tile_classes": [P, C.c_int, IP, IP],
         "clr_get_tile_classes": [P, C.c_int, IP, IP],
         "clr_set_dense_certificate": [P, C.c_int],

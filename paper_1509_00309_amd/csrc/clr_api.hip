@@ -31,9 +31,21 @@ using namespace clr;
 // Context and buffers
 // ---------------------------------------------------------------------------
 
+// A caller's device allocator (clr_set_allocator); alloc == null is hipMalloc.
+struct Allocator {
+  clr_alloc_fn alloc = nullptr;
+  clr_release_fn release = nullptr;
+  void* user = nullptr;
+  void* stream = nullptr;
+};
+
+// A growable device buffer.  src (optional) names the allocator to grow from;
+// owner is the allocator that made p, and the one that releases it.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  const Allocator* src = nullptr;
+  Allocator owner;
 };
 
 // Workspace of the product and combination pipelines: per-block counts and
@@ -52,6 +64,7 @@ struct Work {
 struct clr_context {
   int device = 0;
   hipStream_t stream = nullptr;
+  Allocator alloc;   // device memory of matrices and work lists (default hipMalloc)
   std::string last_error;
   Work w;
   Work gw;   // work lists of graph-replayed iterations (kept between calls, only grown)
@@ -75,6 +88,7 @@ struct clr_context {
 
 struct clr_matrix {
   clr_context* ctx = nullptr;
+  Allocator owner;   // the allocator of block (alloc == null: the context's hipMalloc cache)
   int nrb = 0, ncb = 0;
   std::vector<int> rs, cs, roff, coff;
   int64_t rows = 0, cols = 0;
@@ -155,39 +169,64 @@ clr_status fail(clr_context* ctx, clr_status s, const char* fmt, ...) {
       return fail((ctx), CLR_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
   } while (0)
 
-hipError_t ensure(DevBuf& b, size_t bytes) {
-  if (bytes == 0) bytes = 8;
-  if (b.bytes >= bytes) return hipSuccess;
-  if (b.p) {
-    hipError_t e = hipFree(b.p);
-    if (e != hipSuccess) return e;
-    b.p = nullptr;
-    b.bytes = 0;
+// Memory from an allocator (hipMalloc when it has no alloc function).
+void* dev_alloc(const Allocator& a, size_t bytes) {
+  void* p = nullptr;
+  if (a.alloc) return a.alloc(bytes, a.stream, a.user);
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+void dev_release(const Allocator& a, void* p, size_t bytes) {
+  if (!p) return;
+  if (a.alloc) {
+    if (a.release) a.release(p, bytes, a.stream, a.user);
+  } else {
+    (void)hipFree(p);
   }
-  const size_t want = std::max(bytes, b.bytes + b.bytes / 2);
-  hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) {
-    e = hipMalloc(&b.p, bytes);
-    if (e != hipSuccess) return e;
-    b.bytes = bytes;
-    return hipSuccess;
-  }
-  b.bytes = want;
-  return hipSuccess;
 }
 
 void free_buf(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+  dev_release(b.owner, b.p, b.bytes);
   b.p = nullptr;
   b.bytes = 0;
+  b.owner = Allocator{};
 }
 
-void free_work(Work& w) {
+hipError_t ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return hipSuccess;
+  const size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+  free_buf(b);
+  const Allocator a = b.src ? *b.src : Allocator{};
+  (void)hipGetLastError();
+  b.p = dev_alloc(a, want);
+  b.bytes = want;
+  if (!b.p) {
+    (void)hipGetLastError();
+    b.p = dev_alloc(a, bytes);
+    b.bytes = bytes;
+  }
+  if (!b.p) {
+    b.bytes = 0;
+    return hipErrorOutOfMemory;
+  }
+  b.owner = a;
+  return hipSuccess;
+}
+
+template <typename F>
+void each_buf(Work& w, F f) {
   for (DevBuf* b : {&w.cnt, &w.off, &w.st, &w.flags, &w.totals, &w.seg_dense, &w.items_dense,
                     &w.seg_thin1, &w.items_thin1, &w.seg_thin2, &w.items_thin2, &w.pieces, &w.rec,
                     &w.pool, &w.scratch, &w.acc, &w.terms, &w.comb_dense, &w.recg, &w.order,
                     &w.order_thin, &w.sortw, &w.live, &w.flops})
-    free_buf(*b);
+    f(*b);
+}
+void free_work(Work& w) {
+  each_buf(w, [](DevBuf& b) { free_buf(b); });
+}
+// Grow the buffers of w from allocator a from now on.
+void bind_work(Work& w, const Allocator* a) {
+  each_buf(w, [a](DevBuf& b) { b.src = a; });
 }
 
 template <typename T>
@@ -198,6 +237,11 @@ T* as(DevBuf& b) {
 constexpr size_t kCacheLimit = (size_t)96 << 30;
 
 hipError_t ctx_malloc(clr_context* ctx, size_t bytes, void** p, size_t* got) {
+  if (ctx->alloc.alloc) {   // the caller's allocator: no cache of our own
+    *p = ctx->alloc.alloc(bytes, ctx->alloc.stream, ctx->alloc.user);
+    *got = bytes;
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
   int best = -1;
   for (int i = 0; i < (int)ctx->cache.size(); ++i) {
     const size_t b = ctx->cache[i].second;
@@ -239,7 +283,10 @@ void ctx_release(clr_context* ctx, void* p, size_t bytes) {
 
 void free_matrix(clr_matrix* m) {
   if (!m) return;
-  ctx_release(m->ctx, m->block, m->block_bytes);
+  if (m->owner.alloc)
+    dev_release(m->owner, m->block, m->block_bytes);
+  else
+    ctx_release(m->ctx, m->block, m->block_bytes);
   delete m;
 }
 
@@ -282,6 +329,7 @@ clr_status alloc_matrix(clr_context* ctx, const std::vector<int>& rs, const std:
   const size_t b_roff = up(sizeof(int) * (m->nrb + 1));
   const size_t b_coff = up(sizeof(int) * (m->ncb + 1));
   const size_t total = b_arena + b_norm + 2 * b_kind + b_roff + b_coff;
+  m->owner = ctx->alloc;
   hipError_t e = ctx_malloc(ctx, total, &m->block, &m->block_bytes);
   if (e == hipSuccess) {
     char* base = static_cast<char*>(m->block);
@@ -575,6 +623,10 @@ extern "C" clr_status clr_context_create(clr_context** ctx, void* stream) {
     return CLR_ERR_HIP;
   }
   c->stream = (hipStream_t)stream;
+  c->alloc.stream = stream;
+  bind_work(c->w, &c->alloc);
+  bind_work(c->gw, &c->alloc);
+  c->ptrs.src = &c->alloc;
   for (auto& e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) {
       delete c;
@@ -586,6 +638,24 @@ extern "C" clr_status clr_context_create(clr_context** ctx, void* stream) {
     return CLR_ERR_HIP;
   }
   *ctx = c;
+  return CLR_OK;
+}
+
+// The caller's device allocator for this context's matrices and work lists.
+// Blocks of the context's own hipMalloc cache are released now; buffers keep
+// the allocator that made them until they are released or regrown.
+extern "C" clr_status clr_set_allocator(clr_context* ctx, clr_alloc_fn alloc,
+                                        clr_release_fn release, void* user) {
+  if (!ctx) return CLR_ERR_INVALID_ARG;
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(ctx, CLR_ERR_INVALID_ARG, "alloc and release must be given together");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& c : ctx->cache) (void)hipFree(c.first);
+  ctx->cache.clear();
+  ctx->cache_bytes = 0;
+  ctx->alloc.alloc = alloc;
+  ctx->alloc.release = release;
+  ctx->alloc.user = user;
   return CLR_OK;
 }
 
@@ -1564,6 +1634,11 @@ extern "C" clr_status clr_plan_create(clr_context* ctx, int nprod, const clr_mat
   if (s != CLR_OK) return s;
   clr_plan* pl = new clr_plan();
   pl->ctx = ctx;
+  for (DevBuf* b : {&pl->seg_dense, &pl->items_dense, &pl->seg_thin1, &pl->items_thin1,
+                    &pl->seg_thin2, &pl->items_thin2, &pl->pieces, &pl->rec, &pl->pool,
+                    &pl->scratch, &pl->acc, &pl->recg, &pl->status, &pl->bases, &pl->order,
+                    &pl->order_thin})
+    b->src = &ctx->alloc;
   pl->dense_cert = ctx->dense_cert;
   pl->nprod = nprod;
   pl->o = *opts;

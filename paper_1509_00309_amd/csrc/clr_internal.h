@@ -25,6 +25,18 @@ constexpr int kJacobiMaxSweeps = 60;
 constexpr int kCertEdge = 160;        // largest short edge of a block the dense certificate examines
 
 // ---------------------------------------------------------------------------
+// XCD-blocked workgroup mapping: the dispatcher deals workgroups to the 8 XCDs
+// round-robin, so workgroup b runs on XCD b % 8; unit u = (b % 8) * per + b / 8
+// gives each XCD a contiguous run of `per` units (neighbouring units share an
+// L2).  per comes from the grid, or, for a launch sized by a capacity, from the
+// live count n: workgroups past the runs get -1.
+__device__ inline int xcd_unit(int n, bool from_count) {
+  const int per = from_count ? (n + 7) / 8 : (int)gridDim.x / 8;
+  const int l = (int)blockIdx.x / 8;
+  if (l >= per) return -1;
+  return (int)(blockIdx.x % 8) * per + l;
+}
+
 // Work descriptors (device resident, built by the planning kernels)
 // ---------------------------------------------------------------------------
 

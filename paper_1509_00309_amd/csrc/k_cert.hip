@@ -311,9 +311,8 @@ __global__ __launch_bounds__(64 * WR * WC, 4) void k_dense_cert(
     unsigned long long* __restrict__ count, const int64_t* __restrict__ live) {
   __shared__ CertLds L;
   if (live) nitems = (int)min((int64_t)nitems, *live);
-  const int per = gridDim.x / 8;
-  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (item >= nitems) return;
+  const int item = xcd_unit(nitems, live != nullptr);
+  if (item < 0 || item >= nitems) return;
   const RecItem it = items[item];
   const int q = it.m < it.n ? it.m : it.n;
   if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > qlo && q <= 16 * WR * TU &&

@@ -516,9 +516,8 @@ __global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __
     if ((int)blockIdx.x >= nitems) return;
     item = order[blockIdx.x];
   } else {
-    const int per = gridDim.x / 8;
-    item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (item >= nitems) return;
+    item = xcd_unit(nitems, live != nullptr);
+    if (item < 0 || item >= nitems) return;
   }
   // Item fields are the same for every lane; readfirstlane lets the compiler
   // keep them (and all control flow derived from them) in scalar registers.
@@ -784,8 +783,8 @@ __global__ __launch_bounds__(64 * kWaveItemsPerBlock, 2) void k_wgemm(const Gemm
   // Workgroups are dealt to the 8 XCDs round-robin; blk numbers the
   // workgroups of one XCD consecutively, so neighbouring slots (items that
   // share an operand block once ordered by it) run on one XCD's L2.
-  const int per = gridDim.x / 8;
-  const int blk = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  const int blk = xcd_unit((nitems + kWaveItemsPerBlock - 1) / kWaveItemsPerBlock, live != nullptr);
+  if (blk < 0) return;
   const int slot = blk * kWaveItemsPerBlock + uni((int)threadIdx.x >> 6);
   if (slot >= nitems) return;
   const int item = order ? uni(order[slot]) : slot;

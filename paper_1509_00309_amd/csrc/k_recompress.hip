@@ -1103,6 +1103,23 @@ CLR_INLINE void reg_refine_top(int q, int r, RegLds& L, RecShared& sh) {
 #define GK_C(L, i) (((i) & 1) ? (L).e[(i) >> 1] : (L).d[(i) >> 1])
 CLR_INLINE double pivot_floor(double x) { return x != 0.0 ? x : -1e-300; }
 
+// 1 / x by the hardware reciprocal estimate and two Newton-Raphson steps
+// r <- r + r (1 - x r) (each step squares the relative error, ending within
+// about one unit in the last place): five dependent operations instead of the
+// correctly rounded division's ten, on the serial pivot chains below.  x is a
+// pivot: nonzero, finite.
+CLR_INLINE double recip_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+// Next pivot of a twisted factorisation: -lam - c^2 / d.
+CLR_INLINE double next_pivot(double lam, double c, double d) {
+  return pivot_floor(fma(-(c * c), recip_nr(d), -lam));
+}
+
 // Right singular vector of the bidiagonal for the singular value lam, as the
 // even entries of the eigenvector z of T_GK (size n = 2q) for +lam, from the
 // twisted factorisation of T_GK - lam I: top-down pivots D+ (L D+ L^T) and
@@ -1124,8 +1141,7 @@ CLR_INLINE bool twisted_vector(const RegLds& L, double* ckf, double* ckb, int q,
       for (int t = 0; t < kSeg; ++t) {
         const int i = kSeg * s + t;
         if (i > 0 && i < n) {
-          const double c = GK_C(L, i - 1);
-          dp = pivot_floor(-lam - c * c / dp);
+          dp = next_pivot(lam, GK_C(L, i - 1), dp);
         }
       }
     }
@@ -1145,8 +1161,7 @@ CLR_INLINE bool twisted_vector(const RegLds& L, double* ckf, double* ckb, int q,
           if (i == 0) {
             x = pivot_floor(-lam);
           } else {
-            const double c = GK_C(L, i - 1);
-            x = pivot_floor(-lam - c * c / x);
+            x = next_pivot(lam, GK_C(L, i - 1), x);
           }
         }
         seg[t] = x;
@@ -1156,10 +1171,7 @@ CLR_INLINE bool twisted_vector(const RegLds& L, double* ckf, double* ckb, int q,
       for (int t = kSeg - 1; t >= 0; --t) {
         const int i = kSeg * s + t;
         if (i < n) {
-          if (i < n - 1) {
-            const double c = GK_C(L, i);
-            dm = pivot_floor(-lam - c * c / dm);
-          }
+          if (i < n - 1) dm = next_pivot(lam, GK_C(L, i), dm);
           const double g = fabs(seg[t] + dm + lam);
           if (g < best) {
             best = g;
@@ -1187,8 +1199,7 @@ CLR_INLINE bool twisted_vector(const RegLds& L, double* ckf, double* ckb, int q,
           if (i == 0) {
             x = pivot_floor(-lam);
           } else {
-            const double c = GK_C(L, i - 1);
-            x = pivot_floor(-lam - c * c / x);
+            x = next_pivot(lam, GK_C(L, i - 1), x);
           }
         }
         seg[t] = x;
@@ -1197,7 +1208,7 @@ CLR_INLINE bool twisted_vector(const RegLds& L, double* ckf, double* ckb, int q,
       for (int t = kSeg - 1; t >= 0; --t) {
         const int i = kSeg * s + t;
         if (i < kst) {
-          z = -(GK_C(L, i) / seg[t]) * z;
+          z = -(GK_C(L, i) * recip_nr(seg[t])) * z;
           if ((t & 1) == 0) {
             v[i >> 1] = z;
             nrm2 += z * z;
@@ -1219,8 +1230,7 @@ CLR_INLINE bool twisted_vector(const RegLds& L, double* ckf, double* ckb, int q,
           if (i == n - 1) {
             y = pivot_floor(-lam);
           } else {
-            const double c = GK_C(L, i);
-            y = pivot_floor(-lam - c * c / y);
+            y = next_pivot(lam, GK_C(L, i), y);
           }
         }
         seg[t] = y;
@@ -1229,7 +1239,7 @@ CLR_INLINE bool twisted_vector(const RegLds& L, double* ckf, double* ckb, int q,
       for (int t = 0; t < kSeg; ++t) {
         const int i = kSeg * s + t;
         if (i > kst && i < n) {
-          z = -(GK_C(L, i - 1) / seg[t]) * z;
+          z = -(GK_C(L, i - 1) * recip_nr(seg[t])) * z;
           if ((t & 1) == 0) {
             v[i >> 1] = z;
             nrm2 += z * z;
@@ -1963,9 +1973,8 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress(const RecItem* __res
   extern __shared__ double lds[];
   __shared__ RecShared sh;
   if (live) nitems = (int)min((int64_t)nitems, *live);
-  const int per = gridDim.x / 8;
-  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (item >= nitems) return;
+  const int item = xcd_unit(nitems, live != nullptr);
+  if (item < 0 || item >= nitems) return;
   const RecItem it = items[item];
   if (it.path == kPathSkip || register_item(it, tol)) return;
   if (!item_guard(it, tol, status)) return;
@@ -2033,9 +2042,8 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* _
     if ((int)blockIdx.x >= nitems) return;
     item = order[blockIdx.x];
   } else {
-    const int per = gridDim.x / 8;
-    item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (item >= nitems) return;
+    item = xcd_unit(nitems, live != nullptr);
+    if (item < 0 || item >= nitems) return;
   }
   const RecItem it = items[item];
   if (!register_item(it, tol)) return;

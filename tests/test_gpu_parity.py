@@ -846,6 +846,54 @@ def test_autograd_entry_points(ctx, torch):
     assert torch.equal(s.grad, dS)
 
 
+def test_torch_allocator_hook(torch):
+    """A context whose matrices and work lists come from torch's caching allocator
+    (clr_set_allocator through Context.use_torch_allocator) computes the same product, combination
+    and S^-1/2 (direct and graph-replayed) bit for bit as one on hipMalloc; its matrices show up in
+    torch's allocated bytes and are returned when released."""
+    import gc
+    import paper_1509_00309_amd as clr
+    wl = line_n512()
+    Sd = torch.from_numpy(wl.dense()).cuda()
+    c1, c2 = clr.Context(), clr.Context()
+    try:
+        _torch_allocator_case(torch, clr, wl, Sd, c1, c2)
+    finally:
+        gc.collect()
+        c2.close()
+        c1.close()
+
+
+def _torch_allocator_case(torch, clr, wl, Sd, c1, c2):
+    import gc
+    c2.use_torch_allocator()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    S1 = c1.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    S2 = c2.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10)
+    torch.cuda.synchronize()
+    grown = torch.cuda.memory_allocated() - base
+    assert grown >= 8 * 512 * 512, grown   # at least S2's arena (dense-size slots)
+    _same_clr(torch, S1, S2)
+    _same_clr(torch, c1.gemm(S1, S1, wl.tol, wl.eps_sp), c2.gemm(S2, S2, wl.tol, wl.eps_sp))
+    _same_clr(torch, c1.axpby(0.5, S1, -0.25, S1, 1.0, wl.tol, wl.eps_sp),
+              c2.axpby(0.5, S2, -0.25, S2, 1.0, wl.tol, wl.eps_sp))
+    conv = wl.extra["conv_tol"]
+    for graph in (False, True):
+        W1, s1 = c1.sqrt_inv(S1, wl.tol, wl.eps_sp, conv_tol=conv, graph=graph,
+                             allow_not_converged=True)
+        W2, s2 = c2.sqrt_inv(S2, wl.tol, wl.eps_sp, conv_tol=conv, graph=graph,
+                             allow_not_converged=True)
+        assert s1.iterations == s2.iterations and s1.explicit_residual == s2.explicit_residual
+        _same_clr(torch, W1, W2)
+    del S2, W2
+    gc.collect()
+    c2.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - base < grown, "matrices not returned to torch"
+    del S1, W1
+
+
 def test_autograd_stand_in_checks(ctx, torch):
     """The dense stand-ins of gemm_dense / sqrt_inv_dense are checked against their handles:
     shape and dtype always, values on request."""
