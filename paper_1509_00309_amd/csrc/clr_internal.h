@@ -22,7 +22,8 @@ constexpr int kOzMaxSlices = 7;                    // digits per operand in that
 constexpr int kRecThreads = 512;      // recompression workgroup (32 groups of 16 lanes)
 constexpr int kRecLdsBytes = 140 * 1024;  // dynamic LDS for the working set (160 KiB minus bookkeeping)
 constexpr int kJacobiMaxSweeps = 60;
-constexpr int kCertEdge = 160;        // largest short edge of a block the dense certificate examines
+constexpr int kCertEdge = 160;        // most columns the dense certificate examines
+constexpr int kCertMaxShort = 2 * kCertEdge - 1;   // largest short edge it certifies (h + 1 <= 160)
 
 // ---------------------------------------------------------------------------
 // XCD-blocked workgroup mapping: the dispatcher deals workgroups to the 8 XCDs

@@ -24,11 +24,19 @@
 // The shift c = ||D||_F^2 (9/8 tol^2 + 4 (p + q + 2) u) covers the three
 // terms twice, so success proves s_h(D)^2 > (9/8 tol^2 + 2 (p + q + 2) u)
 // ||D||_F^2.  The margin this leaves between s_h and tol ||D||_F is at least
-// about 7e-9 ||D||_F for every tol, three orders of magnitude above the
-// worst-case error bound of a Householder-based SVD of a block of edge <= 160,
+// about 7e-9 ||D||_F for every tol, two orders of magnitude above the
+// worst-case error bound of a Householder-based SVD of a block of edge <= 319,
 // so the SVD path reaches the same decision: the certificate changes no
 // result (a certified block is copied out exactly as a block the SVD finds
 // dense), it only skips work.
+//
+// Short edges q in (160, 319]: the columns examined are a subset T of
+// qs = 160 of the q, evenly spread (column floor(a q / qs) for a < qs).
+// Deleting columns can only lower singular values (interlacing), so
+// s_h(D) >= s_h(D_T), and h + 1 <= qs pivots fit in the subset.  Every error
+// term above is bounded through ||D_T||_F <= ||D||_F and qs <= q, and the
+// shift takes the full ||D||_F^2 (summed separately, its own rounding far
+// inside the factor-two cover), so the same proof holds for the whole block.
 //
 // One workgroup per block.  The Gram matrix (q x q) is computed on FP64 MFMA
 // (v_mfma_f64_16x16x4) from 16-deep slabs of D staged in LDS, with the next
@@ -133,12 +141,31 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
   const int tid = threadIdx.x;
   const int m = it.m, n = it.n;
   const int q = m < n ? m : n, p = m < n ? n : m;
-  const int T = (q + 15) >> 4;   // 16 x 16 tiles per dimension
+  const int qs = q < kCertEdge ? q : kCertEdge;   // columns examined (all of them up to 160)
+  const int T = (qs + 15) >> 4;  // 16 x 16 tiles per dimension
   const bool trans = m < n;      // columns of D^T are the short side
   cgdbl* D = (cgdbl*)it.D;
   const int64_t ldd = it.ldd;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave % WR, wc = wave / WR;
+  // ||D||_F^2 of the whole block when only a column subset is examined: per-thread
+  // partials in a fixed assignment, lane 0's butterfly sum per wave, the wave sums
+  // added in wave order by every thread (one value in every wave)
+  double full = 0.0;
+  if (q > qs) {
+    double part = 0.0;
+    for (int j = wave; j < n; j += NT / 64)
+      for (int i = lane; i < m; i += 64) {
+        const double v = D[i + (int64_t)j * ldd];
+        part = fma(v, v, part);
+      }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (lane == 0) L.dg[wave] = part;
+    __syncthreads();
+    for (int w = 0; w < NT / 64; ++w) full += L.dg[w];
+    __syncthreads();
+  }
   static_assert(16 * (WR - 1) + 3 + 16 * WR * (TU - 1) + 12 < kCertColLd &&
                     16 * (WC - 1) + 15 + 16 * WC * (TW - 1) < kCertColLd,
                 "pivot-column reads stay inside the zero-padded column");
@@ -154,28 +181,30 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
     for (int w = 0; w < TW; ++w) acc[u][w] = d4{0.0, 0.0, 0.0, 0.0};
   for (int e = tid; e < kCertSlab * kCertLd; e += NT) {
     const int a = e % kCertLd;
-    if (a >= q) L.slab[e / kCertLd][a] = 0.0;
+    if (a >= qs) L.slab[e / kCertLd][a] = 0.0;
   }
-  // pivot-column entries beyond q stay zero: reads need no clamping, so their
+  // pivot-column entries beyond qs stay zero: reads need no clamping, so their
   // addresses are one base register plus constant offsets
   for (int e = tid; e < 2 * kCertColLd; e += NT)
-    if (e % kCertColLd >= q) L.col[e / kCertColLd][e % kCertColLd] = 0.0;
-  // staging slots of this thread (16 q <= 16 * 16 WR TU elements per slab):
-  // consecutive threads read consecutive addresses of D; slot = (kk << 8) | a
+    if (e % kCertColLd >= qs) L.col[e / kCertColLd][e % kCertColLd] = 0.0;
+  // staging slots of this thread (16 qs <= 16 * 16 WR TU elements per slab):
+  // consecutive threads read consecutive addresses of D; slot = (kk << 8) | a,
+  // src = the column of the p x q orientation that subset column a stands for
   constexpr int PRE = (kCertSlab * 16 * WR * TU + NT - 1) / NT;
-  int slot[PRE];
+  int slot[PRE], src[PRE];
 #pragma unroll
   for (int u = 0; u < PRE; ++u) {
     const int e = tid + NT * u;
-    const int kk = trans ? e / q : e % kCertSlab;
-    const int a = trans ? e % q : e / kCertSlab;
-    slot[u] = e < kCertSlab * q ? (kk << 8) | a : -1;
+    const int kk = trans ? e / qs : e % kCertSlab;
+    const int a = trans ? e % qs : e / kCertSlab;
+    slot[u] = e < kCertSlab * qs ? (kk << 8) | a : -1;
+    src[u] = (int)(((int64_t)a * q) / qs);
   }
   double pre[PRE];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < PRE; ++u) {
-      const int k = k0 + (slot[u] >> 8), a = slot[u] & 255;
+      const int k = k0 + (slot[u] >> 8), a = src[u];
       pre[u] = 0.0;
       if (slot[u] >= 0 && k < p) pre[u] = trans ? D[a + (int64_t)k * ldd] : D[k + (int64_t)a * ldd];
     }
@@ -214,7 +243,7 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int a = 16 * (wr + WR * u) + kr + 4 * v, b = 16 * (wc + WC * w) + lc;
-        if (a == b && a < q) L.dg[a] = acc[u][w][v];
+        if (a == b && a < qs) L.dg[a] = acc[u][w][v];
       }
   __syncthreads();
   double dgr[kCertDiag];
@@ -223,21 +252,26 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
 #pragma unroll
   for (int t = 0; t < kCertDiag; ++t) {
     const int a = lane + 64 * t;
-    dgr[t] = a < q ? L.dg[a] : 0.0;
-    cb[t] = a >= q;
+    dgr[t] = a < qs ? L.dg[a] : 0.0;
+    cb[t] = a >= qs;
     s += dgr[t];
   }
   // every wave sums the same values in the same order, then takes lane 0's sum
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
   s = __shfl(s, 0, 64);
-  const double c = s * (1.125 * tol * tol + 4.0 * (double)(p + q + 2) * 0x1p-53);
   // no underflow in the Gram matrix and no overflow
   if (!(s > 0x1p-600 && s < 0x1p+1000)) return false;
+  // the shift scales with ||D||_F^2 of the whole block (never below the subset's)
+  if (q > qs) {
+    if (!(full < 0x1p+1000)) return false;
+    s = fmax(s, full);
+  }
+  const double c = s * (1.125 * tol * tol + 4.0 * (double)(p + q + 2) * 0x1p-53);
 #pragma unroll
   for (int t = 0; t < kCertDiag; ++t) dgr[t] -= c;
 
-  // ---- h + 1 steps of Cholesky with diagonal pivoting
+  // ---- h + 1 steps of Cholesky with diagonal pivoting (h + 1 <= qs)
   const int h = q / 2;
   int buf = 0;
   for (int step = 0; step <= h; ++step) {
@@ -267,7 +301,7 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int a = 16 * (wr + WR * u) + kr + 4 * v;
-              if (a < q) colb[a] = acc[u][w][v];
+              if (a < qs) colb[a] = acc[u][w][v];
             }
         }
       }
@@ -303,20 +337,22 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
   return true;
 }
 
-// Size class (qlo, 16 WR TU]: WR x WC waves of TU x TW tiles of 16 x 16;
-// four waves per SIMD (two 512-thread or one 1024-thread workgroup per CU).
+// Size class (qlo, qhi] of the short edge: WR x WC waves of TU x TW tiles of
+// 16 x 16 holding the Gram matrix of min(q, 160) columns; four waves per SIMD
+// (two 512-thread or one 1024-thread workgroup per CU).
 template <int WR, int WC, int TU, int TW>
 __global__ __launch_bounds__(64 * WR * WC, 4) void k_dense_cert(
-    const RecItem* __restrict__ items, int nitems, double tol, int qlo, int* __restrict__ cert,
-    unsigned long long* __restrict__ count, const int64_t* __restrict__ live) {
+    const RecItem* __restrict__ items, int nitems, double tol, int qlo, int qhi,
+    int* __restrict__ cert, unsigned long long* __restrict__ count,
+    const int64_t* __restrict__ live) {
   __shared__ CertLds L;
   if (live) nitems = (int)min((int64_t)nitems, *live);
   const int item = xcd_unit(nitems, live != nullptr);
   if (item < 0 || item >= nitems) return;
   const RecItem it = items[item];
   const int q = it.m < it.n ? it.m : it.n;
-  if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > qlo && q <= 16 * WR * TU &&
-        it.D != nullptr))
+  if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > qlo && q <= qhi &&
+        min(q, kCertEdge) <= 16 * WR * TU && q / 2 < kCertEdge && it.D != nullptr))
     return;
   const bool ok = cert_block<WR, WC, TU, TW>(it, tol, L);
   if (ok && threadIdx.x == 0) {
@@ -335,9 +371,9 @@ hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* 
   if (e != hipSuccess) return e;
   const int grid = ((nitems + 7) / 8) * 8;
   hipLaunchKernelGGL((k_dense_cert<2, 4, 4, 2>), dim3(grid), dim3(512), 0, s, items, nitems, tol,
-                     0, cert, count, live);
+                     0, 128, cert, count, live);
   hipLaunchKernelGGL((k_dense_cert<4, 4, 3, 3>), dim3(grid), dim3(1024), 0, s, items, nitems,
-                     tol, 128, cert, count, live);
+                     tol, 128, kCertMaxShort, cert, count, live);
   return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@ import pytest
 
 import oracle as orc
 import parity
-from workloads import (line_n512, lattice_3d, kernel_matrix, points_1d, points_3d, random_blocks,
+from workloads import (batch_product, line_n512, lattice_3d, kernel_matrix, points_1d, points_3d, random_blocks,
                        rng_for, scaled_workload, sizes_weighted)
 
 pytestmark = pytest.mark.gpu
@@ -440,8 +440,21 @@ def test_dense_certificate_general_kernel(torch):
     c.set_dense_certificate(True)
     S = c.compress(torch.from_numpy(Sd3).cuda(), sizes, sizes, 1e-6, 1e-12)
     C, st = c.gemm(S, S, 1e-6, 1e-10, stats=True)
-    log(f"  product: certified {st.certified_dense} of {st.out_dense} dense")
-    assert st.certified_dense > 0
+    c.set_dense_certificate(False)
+    C_off, st_off = c.gemm(S, S, 1e-6, 1e-10, stats=True)
+    c.set_dense_certificate(True)
+    _bitwise_same(C, C_off)
+    kinds = C.meta()[0].reshape(len(sizes), len(sizes))
+    # dense off-diagonal results whose short edge is at most 160: all a certificate of the
+    # full Gram matrix could prove; the ones beyond need the 160-column subset
+    small = sum(1 for i in range(len(sizes)) for j in range(len(sizes))
+                if i != j and kinds[i, j] == 1 and min(sizes[i], sizes[j]) <= 160)
+    big = sum(1 for i in range(len(sizes)) for j in range(len(sizes))
+              if i != j and kinds[i, j] == 1 and min(sizes[i], sizes[j]) > 160)
+    log(f"  product: certified {st.certified_dense} of {st.out_dense} dense "
+        f"({small} off-diagonal with short edge <= 160, {big} beyond)")
+    assert big > 0 and st.certified_dense > small
+    assert st_off.certified_dense == 0
     O = orc.compress(Sd3, sizes, sizes, 1e-6, 1e-12)
     rep = parity.compare(C, orc.gemm(O, O, 1e-6, 1e-10), 1e-6, exact=orc.gemm(O, O, 0.0, 1e-10),
                          operands=(O, O))
@@ -954,13 +967,15 @@ def test_gemm_batch_matches_single_products(ctx, torch):
 
 
 def test_gemm_batch_against_oracle(ctx, torch):
-    """Two products of different blockings and physics in one planned batch (one launch per
-    phase for both, replayed as a HIP graph): the 3-D lattice at N = 1536 and the 1-D line at
-    N = 512, both truncated at 1e-8, each against the oracle block by block."""
+    """Three products of different blockings and physics in one planned batch (one launch per
+    phase for all, replayed as a HIP graph): the 3-D lattice at N = 1536, the 1-D line at
+    N = 512 and a product of the 256-product batch (N = 2577, clusters up to 197, so dense
+    blocks with short edges above 160), all truncated at 1e-8, each against the oracle block by
+    block."""
     log("gemm batch against the oracle")
     tol, eps = 1e-8, 1e-10
     mats, orcs, nbs = [], [], []
-    for wl in (scaled_workload("lattice", 1536, seed=147), line_n512()):
+    for wl in (scaled_workload("lattice", 1536, seed=147), line_n512(), batch_product(5)):
         Sd = wl.dense()
         mats.append(ctx.compress(torch.from_numpy(Sd).cuda(), wl.sizes, wl.sizes, wl.tol, 1e-10))
         orcs.append(orc.compress(Sd, wl.sizes, wl.sizes, wl.tol, 1e-10))
