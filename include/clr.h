@@ -191,12 +191,15 @@ const char* clr_status_string(clr_status s);
 /* Build a CLR matrix from given factors, copied into a library-owned arena.
  *   row_sizes[nrb], col_sizes[ncb] (host): the nonuniform blocking.
  *   kind[nrb*ncb] (host): 0 zero, 1 dense, 2 low rank.
- *   rank[nrb*ncb] (host): r of low-rank blocks (1 <= r <= min(m, n)); ignored otherwise.
+ *   rank[nrb*ncb] (host): r of low-rank blocks, 1 <= r and (m + n) r <= m n (a factored
+ *     block never stores more than its dense form, else CLR_ERR_CAPACITY); ignored otherwise.
  *   norms[nrb*ncb] (host, nullable): ||block||_F; when given they are checked
  *     against the recomputed values (relative 1e-10, else CLR_ERR_NORM_MISMATCH).
  *   f0[nrb*ncb], f1[nrb*ncb] (host arrays of device pointers): dense block or U;
  *     V for low-rank blocks.  Entries of zero blocks are ignored.
- * Sizes must be >= 1.  The stored norms are recomputed on the device. */
+ * Sizes must be >= 1.  The stored norms are recomputed on the device.  The
+ * arena is packed: it holds exactly the stored elements (m n per dense block,
+ * (m + n) r per low-rank block). */
 clr_status clr_create(clr_context* ctx, int nrb, const int* row_sizes, int ncb,
                       const int* col_sizes, const int8_t* kind, const int* rank,
                       const double* norms, const double* const* f0,
@@ -233,6 +236,21 @@ clr_status clr_kernel_matrix(clr_context* ctx, const double* row_points, int64_t
                              double a, double diag, double* out, int64_t ld);
 
 clr_status clr_destroy(clr_matrix* m);
+
+/* Device storage of m (host outputs, nullable): the arena's capacity in
+ * doubles and the bytes of its one allocation (arena and block metadata).
+ * Inputs from clr_create and clr_compress are packed (capacity = stored
+ * elements); a product or combination reserves per block the most its result
+ * can store (m n for a block accumulated densely, (m + n) R for a
+ * concatenation of rank R), which clr_compact gives back. */
+clr_status clr_matrix_arena(const clr_matrix* m, int64_t* capacity, size_t* bytes);
+
+/* Repack m in place so that its arena holds exactly its stored elements
+ * (Sec. 4.1: m n per dense block, (m + n) r per low-rank block).  Values,
+ * kinds, ranks and norms are unchanged; the handle stays valid.  Synchronises
+ * the context stream (the kinds and ranks are read back); returns
+ * CLR_ERR_INVALID_ARG for a matrix of another context. */
+clr_status clr_compact(clr_context* ctx, clr_matrix* m);
 
 /* Blocking and storage summary (host outputs, all nullable). */
 clr_status clr_matrix_info(const clr_matrix* m, int* nrb, int* ncb, int64_t* rows,

@@ -451,6 +451,18 @@ class CLRMatrix:
         self.ctx._check(lib.clr_matrix_info(self._h, None, None, None, None, C.byref(s)))
         return s.value
 
+    def arena(self):
+        """(capacity in doubles, bytes of the device allocation) of this matrix's storage."""
+        cap = C.c_int64()
+        nbytes = C.c_size_t()
+        self.ctx._check(lib.clr_matrix_arena(self._h, C.byref(cap), C.byref(nbytes)))
+        return cap.value, nbytes.value
+
+    def compact(self) -> "CLRMatrix":
+        """Repack the storage so that the arena holds exactly the stored elements."""
+        self.ctx._check(lib.clr_compact(self.ctx._h, self._h))
+        return self
+
     def to_dense(self):
         torch = _torch()
         buf = torch.empty((self.cols, self.rows), dtype=torch.float64, device="cuda")

@@ -30,7 +30,8 @@ CLR_SCREEN_AREA = 1
 EXPORTS = [
     "clr_context_create", "clr_context_destroy", "clr_set_allocator", "clr_last_error",
     "clr_status_string",
-    "clr_create", "clr_compress", "clr_destroy", "clr_matrix_info", "clr_get_meta",
+    "clr_create", "clr_compress", "clr_destroy", "clr_matrix_info", "clr_matrix_arena",
+    "clr_compact", "clr_get_meta",
     "clr_get_block", "clr_to_dense", "clr_gemm", "clr_axpby", "clr_sqrt_inv",
     "clr_identity_residual", "clr_identity_residual_noalloc", "clr_gemm_backward", "clr_sqrt_inv_backward",
     "clr_plan_create", "clr_plan_execute", "clr_plan_destroy", "clr_gemm_batch",
@@ -109,6 +110,8 @@ def _load():
         "clr_compress": [P, P, I64, C.c_int, IP, C.c_int, IP, D, D, C.POINTER(P)],
         "clr_destroy": [P],
         "clr_matrix_info": [P, IP, IP, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
+        "clr_matrix_arena": [P, C.POINTER(I64), C.POINTER(C.c_size_t)],
+        "clr_compact": [P, P],
         "clr_get_meta": [P, P, C.POINTER(C.c_int8), IP, DP],
         "clr_get_block": [P, P, C.c_int, C.c_int, P, P],
         "clr_to_dense": [P, P, P, I64],

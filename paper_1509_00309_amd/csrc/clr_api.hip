@@ -1,16 +1,20 @@
 // Host side of the C ABI declared in include/clr.h: contexts, CLR matrices in
-// a slot arena, and the drivers of the product, the blockwise combination and
+// blocks of an arena, and the drivers of the product, the blockwise combination and
 // the Newton-Schulz square-root inverse (Sec. 4.1 and 4.2 of Calvin, Lewis &
 // Valeev, IA^3 2015).
 //
 // Storage of a CLR matrix with blocking m_0..m_{R-1} x n_0..n_{C-1}: one FP64
-// arena of rows*cols doubles; block (I, J) owns the m_I x n_J slot at
-// roff[I]*cols + m_I*coff[J].  A dense block fills its slot (column-major,
-// ld m); a low-rank block stores U (m x r) then V (n x r) in it, which fits
-// because (m + n) r <= m n whenever r <= m n / (m + n) (in particular for
-// every r <= min(m, n)/2).  The slot layout is the dense upper bound of the
-// method's memory use, so ranks can change from product to product without
-// reallocation or compaction.
+// arena and a table of block offsets; block (I, J) starts at arena +
+// boff[I * C + J].  A dense block is m x n column-major (ld m); a factored
+// block stores U (m x r) then V (n x r).  Three layouts share that form:
+//  * packed: a block takes exactly what it stores (inputs from clr_create,
+//    compressed inputs, the identity, clr_compact), so memory follows ranks;
+//  * planned: a product or combination reserves, per block, the most its
+//    result can store (m n when accumulated densely, since a truncation keeps
+//    2 r <= min(m, n) and (m + n) r <= m n; (m + n) R for a concatenation of
+//    rank R) and writes the offsets on the device before it runs;
+//  * dense slots (m n for every block): the fixed iterates of a captured
+//    Newton-Schulz iteration, whose results change rank from replay to replay.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -97,7 +101,11 @@ struct clr_matrix {
   int* d_kind = nullptr;
   int* d_rank = nullptr;
   double* d_norm = nullptr;
+  int64_t* d_boff = nullptr;   // block offsets into the arena (doubles)
   double* arena = nullptr;
+  int64_t cap = 0;             // arena capacity (doubles)
+  std::vector<int64_t> boff;   // host copy of d_boff when host_boff
+  bool host_boff = false;      // false: offsets planned on the device
   void* block = nullptr;   // one allocation holding the arena and the metadata
   size_t block_bytes = 0;
 
@@ -109,9 +117,9 @@ struct clr_matrix {
     v.roff = d_roff;
     v.coff = d_coff;
     v.arena = arena;
+    v.boff = d_boff;
     v.nrb = nrb;
     v.ncb = ncb;
-    v.ncols = cols;
     return v;
   }
   bool square_blocked() const { return rs == cs; }
@@ -290,9 +298,19 @@ void free_matrix(clr_matrix* m) {
   delete m;
 }
 
+// Dense-slot offset of block (I, J): room for every block stored dense.
+int64_t dense_slot(const std::vector<int>& roff, const std::vector<int>& coff, int64_t cols, int I,
+                   int J) {
+  return (int64_t)roff[I] * cols + (int64_t)(roff[I + 1] - roff[I]) * coff[J];
+}
+
 // Allocate a matrix with the given blocking; metadata set to "all zero blocks".
+// Layout: offsets given on the host (with the arena capacity cap), or none and
+// cap < 0 for dense slots, or none and cap >= 0 for offsets that a kernel
+// writes before the matrix is read (zero until then).
 clr_status alloc_matrix(clr_context* ctx, const std::vector<int>& rs, const std::vector<int>& cs,
-                        clr_matrix** out) {
+                        clr_matrix** out, const std::vector<int64_t>* offsets = nullptr,
+                        int64_t cap = -1) {
   *out = nullptr;
   if (rs.empty() || cs.empty()) return fail(ctx, CLR_ERR_INVALID_ARG, "empty blocking");
   for (int v : rs)
@@ -322,23 +340,46 @@ clr_status alloc_matrix(clr_context* ctx, const std::vector<int>& rs, const std:
     free_matrix(m);
     return fail(ctx, CLR_ERR_CAPACITY, "too many blocks");
   }
+  if (offsets) {
+    if ((int64_t)offsets->size() != nb || cap < 0) {
+      delete m;
+      return fail(ctx, CLR_ERR_INTERNAL, "block offsets do not match the blocking");
+    }
+    m->boff = *offsets;
+    m->cap = cap;
+    m->host_boff = true;
+  } else if (cap < 0) {
+    m->boff.resize(nb);
+    for (int I = 0; I < m->nrb; ++I)
+      for (int J = 0; J < m->ncb; ++J)
+        m->boff[(size_t)I * m->ncb + J] = dense_slot(m->roff, m->coff, m->cols, I, J);
+    m->cap = m->rows * m->cols;
+    m->host_boff = true;
+  } else {
+    m->cap = cap;
+  }
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t b_arena = up(sizeof(double) * (size_t)m->rows * m->cols);
+  const size_t b_arena = up(sizeof(double) * (size_t)std::max<int64_t>(m->cap, 1));
   const size_t b_norm = up(sizeof(double) * nb);
+  const size_t b_boff = up(sizeof(int64_t) * nb);
   const size_t b_kind = up(sizeof(int) * nb);
   const size_t b_roff = up(sizeof(int) * (m->nrb + 1));
   const size_t b_coff = up(sizeof(int) * (m->ncb + 1));
-  const size_t total = b_arena + b_norm + 2 * b_kind + b_roff + b_coff;
+  const size_t total = b_arena + b_norm + b_boff + 2 * b_kind + b_roff + b_coff;
   m->owner = ctx->alloc;
   hipError_t e = ctx_malloc(ctx, total, &m->block, &m->block_bytes);
   if (e == hipSuccess) {
     char* base = static_cast<char*>(m->block);
     m->arena = reinterpret_cast<double*>(base);
-    m->d_norm = reinterpret_cast<double*>(base + b_arena);
-    m->d_kind = reinterpret_cast<int*>(base + b_arena + b_norm);
-    m->d_rank = reinterpret_cast<int*>(base + b_arena + b_norm + b_kind);
-    m->d_roff = reinterpret_cast<int*>(base + b_arena + b_norm + 2 * b_kind);
-    m->d_coff = reinterpret_cast<int*>(base + b_arena + b_norm + 2 * b_kind + b_roff);
+    base += b_arena;
+    m->d_norm = reinterpret_cast<double*>(base);
+    base += b_norm;
+    m->d_boff = reinterpret_cast<int64_t*>(base);
+    base += b_boff;
+    m->d_kind = reinterpret_cast<int*>(base);
+    m->d_rank = reinterpret_cast<int*>(base + b_kind);
+    m->d_roff = reinterpret_cast<int*>(base + 2 * b_kind);
+    m->d_coff = reinterpret_cast<int*>(base + 2 * b_kind + b_roff);
   }
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->d_roff, m->roff.data(), sizeof(int) * (m->nrb + 1),
@@ -346,6 +387,13 @@ clr_status alloc_matrix(clr_context* ctx, const std::vector<int>& rs, const std:
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->d_coff, m->coff.data(), sizeof(int) * (m->ncb + 1),
                        hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    if (m->host_boff)
+      e = hipMemcpyAsync(m->d_boff, m->boff.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice,
+                         ctx->stream);
+    else
+      e = launch_fill_i32(reinterpret_cast<int*>(m->d_boff), 0, 2 * nb, ctx->stream);
+  }
   if (e == hipSuccess) e = launch_fill_i32(m->d_kind, 0, nb, ctx->stream);
   if (e == hipSuccess) e = launch_fill_i32(m->d_rank, 0, nb, ctx->stream);
   if (e == hipSuccess) e = launch_fill_f64(m->d_norm, 0.0, nb, ctx->stream);
@@ -459,6 +507,77 @@ double stored_elements(const clr_matrix* m, const HostMeta& h) {
   return s;
 }
 
+// Packed offsets of the blocks described by h (each takes what it stores);
+// returns the arena capacity.
+int64_t packed_offsets(const clr_matrix* m, const HostMeta& h, std::vector<int64_t>& offs) {
+  offs.assign((size_t)m->nrb * m->ncb, 0);
+  int64_t cap = 0;
+  for (int I = 0; I < m->nrb; ++I)
+    for (int J = 0; J < m->ncb; ++J) {
+      const size_t b = (size_t)I * m->ncb + J;
+      offs[b] = cap;
+      cap += stored_size(h.kind[b], m->rs[I], m->cs[J], h.rank[b]);
+    }
+  return cap;
+}
+
+// A copy of src in another layout: offsets given on the host with the arena
+// capacity, or dense slots (offs null).  Metadata is copied; every block's
+// stored elements move to their new place.
+clr_status relayout_matrix(clr_context* ctx, const clr_matrix* src, const std::vector<int64_t>* offs,
+                           int64_t cap, clr_matrix** out) {
+  clr_matrix* m = nullptr;
+  clr_status s = offs ? alloc_matrix(ctx, src->rs, src->cs, &m, offs, cap)
+                      : alloc_matrix(ctx, src->rs, src->cs, &m);
+  if (s != CLR_OK) return s;
+  const size_t nb = (size_t)src->nrb * src->ncb;
+  hipError_t e = hipMemcpyAsync(m->d_kind, src->d_kind, nb * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->d_rank, src->d_rank, nb * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->d_norm, src->d_norm, nb * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = launch_relayout(src->view(), m->arena, m->d_boff, ctx->stream);
+  if (e != hipSuccess) {
+    free_matrix(m);
+    return fail(ctx, CLR_ERR_HIP, "relayout: %s", hipGetErrorString(e));
+  }
+  *out = m;
+  return CLR_OK;
+}
+
+// m takes t's storage and t m's old one, which is released with t.  Same
+// blocking; the release is ordered on the context stream after the work that
+// read it.
+void adopt_storage(clr_matrix* m, clr_matrix* t) {
+  std::swap(m->owner, t->owner);
+  std::swap(m->block, t->block);
+  std::swap(m->block_bytes, t->block_bytes);
+  std::swap(m->arena, t->arena);
+  std::swap(m->cap, t->cap);
+  std::swap(m->d_boff, t->d_boff);
+  std::swap(m->boff, t->boff);
+  std::swap(m->host_boff, t->host_boff);
+  std::swap(m->d_kind, t->d_kind);
+  std::swap(m->d_rank, t->d_rank);
+  std::swap(m->d_norm, t->d_norm);
+  std::swap(m->d_roff, t->d_roff);
+  std::swap(m->d_coff, t->d_coff);
+  free_matrix(t);
+}
+
+// Repack m in place so that its arena holds exactly the stored elements.
+clr_status compact_matrix(clr_context* ctx, clr_matrix* m) {
+  HostMeta h;
+  clr_status s = fetch_meta(ctx, m, h);
+  if (s != CLR_OK) return s;
+  std::vector<int64_t> offs;
+  const int64_t cap = packed_offsets(m, h, offs);
+  if (m->host_boff && cap == m->cap && offs == m->boff) return CLR_OK;   // already packed
+  clr_matrix* t = nullptr;
+  s = relayout_matrix(ctx, m, &offs, cap, &t);
+  if (s != CLR_OK) return s;
+  adopt_storage(m, t);
+  return CLR_OK;
+}
+
 // Upload a host vector into a growable device buffer (synchronous with the stream).
 template <typename T>
 clr_status upload(clr_context* ctx, DevBuf& b, const std::vector<T>& v) {
@@ -526,12 +645,17 @@ hipError_t launch_recompress_ctx(clr_context* ctx, const RecItem* items, const P
   return launch_recompress_work(ctx, ctx->w, items, pieces, nitems, tol, timed);
 }
 
-// Buffer sizes of a pipeline run over npairs result blocks of a rows x cols
-// matrix whose work lists hold at most caps.c[*] entries.
+// Buffer sizes of a pipeline run over npairs result blocks whose work lists
+// hold at most caps.c[*] entries (the output room, kCntOut, is the output
+// matrix's own arena).
+// Counters of doubles (arena room, pools), which may exceed int32.
+inline bool counts_doubles(int c) {
+  return c == kCntPool || c == kCntScratch || c == kCntOut || c == kCntAcc;
+}
 struct WorkSizes {
   std::vector<std::pair<DevBuf Work::*, size_t>> bufs;
 };
-WorkSizes work_sizes(int64_t npairs, const Caps& caps, int64_t rows, int64_t cols) {
+WorkSizes work_sizes(int64_t npairs, const Caps& caps) {
   auto n = [&](int c) { return (size_t)std::max<int64_t>(caps.c[c], 0); };
   WorkSizes w;
   w.bufs = {
@@ -553,7 +677,7 @@ WorkSizes work_sizes(int64_t npairs, const Caps& caps, int64_t rows, int64_t col
       {&Work::pool, sizeof(double) * n(kCntPool)},
       {&Work::scratch, sizeof(double) * n(kCntScratch)},
       {&Work::comb_dense, sizeof(AxpbyDenseItem) * n(kCntCombDense)},
-      {&Work::acc, sizeof(double) * (size_t)rows * (size_t)cols},
+      {&Work::acc, sizeof(double) * n(kCntAcc)},
       {&Work::recg, rec_work_bytes(caps.c[kCntComputed])},
       {&Work::terms, sizeof(double) * (size_t)npairs},
       {&Work::live, sizeof(int64_t) * kNumLive},
@@ -589,16 +713,20 @@ hipError_t reset_meta(clr_context* ctx, clr_matrix* m) {
   return e;
 }
 
+// A copy with the same layout (offsets and arena copied as they are).
 clr_status copy_matrix(clr_context* ctx, const clr_matrix* src, clr_matrix** out) {
   clr_matrix* m = nullptr;
-  clr_status s = alloc_matrix(ctx, src->rs, src->cs, &m);
+  clr_status s = src->host_boff ? alloc_matrix(ctx, src->rs, src->cs, &m, &src->boff, src->cap)
+                                : alloc_matrix(ctx, src->rs, src->cs, &m, nullptr, src->cap);
   if (s != CLR_OK) return s;
   const size_t nb = (size_t)src->nrb * src->ncb;
   hipError_t e = hipMemcpyAsync(m->d_kind, src->d_kind, nb * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(m->d_rank, src->d_rank, nb * sizeof(int), hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(m->d_norm, src->d_norm, nb * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(m->arena, src->arena, sizeof(double) * (size_t)src->rows * src->cols,
+    e = hipMemcpyAsync(m->d_boff, src->d_boff, nb * sizeof(int64_t), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess && src->cap > 0)
+    e = hipMemcpyAsync(m->arena, src->arena, sizeof(double) * (size_t)src->cap,
                        hipMemcpyDeviceToDevice, ctx->stream);
   if (e != hipSuccess) {
     free_matrix(m);
@@ -732,8 +860,17 @@ extern "C" clr_status clr_create(clr_context* ctx, int nrb, const int* row_sizes
         r[b] = std::min(rs[I], cs[J]);
       }
     }
+  // packed: every block takes what it stores
+  std::vector<int64_t> offs(nb, 0);
+  int64_t cap = 0;
+  for (int I = 0; I < nrb; ++I)
+    for (int J = 0; J < ncb; ++J) {
+      const size_t b = (size_t)I * ncb + J;
+      offs[b] = cap;
+      cap += stored_size(k[b], rs[I], cs[J], r[b]);
+    }
   clr_matrix* m = nullptr;
-  clr_status s = alloc_matrix(ctx, rs, cs, &m);
+  clr_status s = alloc_matrix(ctx, rs, cs, &m, &offs, cap);
   if (s != CLR_OK) return s;
   std::vector<const double*> tab(2 * nb);
   std::copy(p0.begin(), p0.end(), tab.begin());
@@ -807,7 +944,7 @@ extern "C" clr_status clr_compress(clr_context* ctx, const double* dense, int64_
       r.D = dense + m->roff[I] + (int64_t)m->coff[J] * ld;
       r.ldd = ld;
       r.tau = drop;
-      r.out = m->arena + slot_offset(m->roff.data(), m->coff.data(), m->cols, I, J);
+      r.out = m->arena + m->boff[(size_t)I * ncb + J];   // dense slots until compacted
       const int64_t need = rec_scratch_doubles(r.path, r.m, r.n, 0, tol);
       scratch_off.push_back(need > 0 ? scratch_total : -1);
       scratch_total += need;
@@ -835,6 +972,8 @@ extern "C" clr_status clr_compress(clr_context* ctx, const double* dense, int64_
     return fail(ctx, CLR_ERR_HIP, "recompress launch: %s", hipGetErrorString(e));
   }
   s = check_status(ctx);
+  // the result is packed: memory follows the ranks found
+  if (s == CLR_OK) s = compact_matrix(ctx, m);
   if (s != CLR_OK) {
     free_matrix(m);
     return s;
@@ -848,6 +987,19 @@ extern "C" clr_status clr_destroy(clr_matrix* m) {
   (void)hipStreamSynchronize(m->ctx->stream);
   free_matrix(m);
   return CLR_OK;
+}
+
+extern "C" clr_status clr_matrix_arena(const clr_matrix* m, int64_t* capacity, size_t* bytes) {
+  if (!m) return CLR_ERR_INVALID_ARG;
+  if (capacity) *capacity = m->cap;
+  if (bytes) *bytes = m->block_bytes;
+  return CLR_OK;
+}
+
+extern "C" clr_status clr_compact(clr_context* ctx, clr_matrix* m) {
+  if (!ctx || !m) return CLR_ERR_INVALID_ARG;
+  if (m->ctx != ctx) return fail(ctx, CLR_ERR_INVALID_ARG, "clr_compact: matrix of another context");
+  return compact_matrix(ctx, m);
 }
 
 extern "C" clr_status clr_matrix_info(const clr_matrix* m, int* nrb, int* ncb, int64_t* rows,
@@ -888,11 +1040,14 @@ extern "C" clr_status clr_get_block(clr_context* ctx, const clr_matrix* m, int I
     return fail(ctx, CLR_ERR_INVALID_ARG, "block index out of range");
   const size_t b = (size_t)I * m->ncb + J;
   int k = 0, r = 0;
+  int64_t at = m->host_boff ? m->boff[b] : 0;
   HIP_TRY(ctx, hipMemcpyAsync(&k, m->d_kind + b, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipMemcpyAsync(&r, m->d_rank + b, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  if (!m->host_boff)
+    HIP_TRY(ctx, hipMemcpyAsync(&at, m->d_boff + b, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   const int64_t rows = m->rs[I], cols = m->cs[J];
-  const double* src = m->arena + slot_offset(m->roff.data(), m->coff.data(), m->cols, I, J);
+  const double* src = m->arena + at;
   if (k == 0) return fail(ctx, CLR_ERR_INVALID_ARG, "block (%d,%d) is zero", I, J);
   if (k == 1) {
     HIP_TRY(ctx, hipMemcpyAsync(f0, src, sizeof(double) * rows * cols, hipMemcpyDeviceToDevice, ctx->stream));
@@ -933,17 +1088,15 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
     return fail(ctx, CLR_ERR_SHAPE, "column blocking of A differs from row blocking of B");
   if (dev && (st || o->precision == CLR_OZAKI || !Cinto))
     return fail(ctx, CLR_ERR_INVALID_ARG, "device-sized product: in place, FP64 or mixed, no statistics");
+  // the output: Cinto, or allocated once the symbolic phase has sized its room
   clr_matrix* C = Cinto;
   if (C) {
     if (C->rs != A->rs || C->cs != B->cs)
       return fail(ctx, CLR_ERR_SHAPE, "output blocking differs from the product's");
     HIP_TRY(ctx, reset_meta(ctx, C));
-  } else {
-    clr_status s = alloc_matrix(ctx, A->rs, B->cs, &C);
-    if (s != CLR_OK) return s;
   }
   auto bail = [&](clr_status code) {
-    if (!Cinto) free_matrix(C);
+    if (!Cinto && C) free_matrix(C);
     return code;
   };
   hipStream_t stream = ctx->stream;
@@ -963,7 +1116,7 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
   const int64_t npairs = (int64_t)P.nrb * P.ncb;
   hipError_t e = hipSuccess;
   if (dev) {
-    if (!work_fits(W, work_sizes(npairs, dev->caps, C->rows, C->cols)))
+    if (!work_fits(W, work_sizes(npairs, dev->caps)))
       return bail(fail(ctx, CLR_ERR_CAPACITY, "workspace smaller than the run's capacities"));
   } else {
     if (e == hipSuccess) e = ensure(W.cnt, sizeof(int64_t) * kNumCounters * npairs);
@@ -988,10 +1141,12 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
   int64_t* live = nullptr;
   if (dev) {
     live = as<int64_t>(W.live);
-    if (e == hipSuccess) e = launch_caps(tot_cnt, dev->caps, live, stream);
+    Caps caps = dev->caps;
+    caps.c[kCntOut] = C->cap;   // the output's arena bounds its room
+    if (e == hipSuccess) e = launch_caps(tot_cnt, caps, live, stream);
     if (e == hipSuccess) e = launch_reduce(as<double>(W.st), npairs, kNumStats, tot_st, stream);
     if (e == hipSuccess) e = launch_add_flops(tot_st, as<double>(W.flops), stream);
-    for (int i = 0; i < kNumCounters; ++i) n[i] = dev->caps.c[i];
+    for (int i = 0; i < kNumCounters; ++i) n[i] = caps.c[i];
   } else {
     if (e == hipSuccess) e = launch_reduce(as<double>(W.st), npairs, kNumStats, tot_st, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(n, tot_cnt, sizeof(n), hipMemcpyDeviceToHost, stream);
@@ -1003,19 +1158,23 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
     return bail(CLR_ERR_HIP);
   }
   for (int i = 0; i < kNumCounters; ++i)
-    if (n[i] < 0 || (i != kCntPool && i != kCntScratch && n[i] > INT32_MAX))
+    if (n[i] < 0 || (!counts_doubles(i) && n[i] > INT32_MAX))
       return bail(fail(ctx, CLR_ERR_CAPACITY, "work list %d too long (%lld)", i, (long long)n[i]));
   if (!dev) {
     for (int i = 0; i < kNumCounters; ++i) W.seen.c[i] = std::max(W.seen.c[i], n[i]);
     W.host_flops += hs[kStFlopsDD] + hs[kStFlopsLD] + hs[kStFlopsDL] + hs[kStFlopsLL] +
                     hs[kStFlopsDensify];
+    if (C) {
+      if (n[kCntOut] > C->cap)
+        return bail(fail(ctx, CLR_ERR_CAPACITY, "output arena of %lld doubles, %lld needed",
+                         (long long)C->cap, (long long)n[kCntOut]));
+    } else {
+      clr_status s = alloc_matrix(ctx, A->rs, B->cs, &C, nullptr, n[kCntOut]);
+      if (s != CLR_OK) return s;
+    }
     Caps exact;
     for (int i = 0; i < kNumCounters; ++i) exact.c[i] = n[i];
-    WorkSizes ws = work_sizes(npairs, exact, C->rows, C->cols);
-    if (n[kCntGemmItems] == 0)   // no dense accumulation: no accumulators needed
-      for (auto& b : ws.bufs)
-        if (b.first == &Work::acc) b.second = 0;
-    e = reserve_work(W, ws);
+    e = reserve_work(W, work_sizes(npairs, exact));
     if (e == hipSuccess) e = ensure(W.order_thin, sizeof(int) * n[kCntThin1]);
     if (e == hipSuccess) e = ensure(W.sortw, operand_order_bytes((int)n[kCntThin1]));
     if (e != hipSuccess) {
@@ -1040,11 +1199,13 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
   F.scratch = as<double>(W.scratch);
   F.acc = as<double>(W.acc);
   F.c_arena = C->arena;
+  F.c_boff = C->d_boff;
   F.c_kind = C->d_kind;
   F.c_rank = C->d_rank;
   F.c_norm = C->d_norm;
-  F.c_ncols = C->cols;
   F.abort = lv(kLiveOverflow);
+  // the offsets are planned on the device from here on (the host copy is stale)
+  C->host_boff = false;
   // The operand-grouped order of the factor products only improves L2 reuse
   // (each item is computed on its own).  A device-sized run groups them with
   // the hashed counting sort, which a graph can record.
@@ -1465,8 +1626,6 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     const clr_matrix* B = pl->B[p];
     if (A->cs != B->rs)
       return fail(ctx, CLR_ERR_SHAPE, "product %d: column blocking of A differs from row blocking of B", p);
-    clr_status s = alloc_matrix(ctx, A->rs, B->cs, &pl->C[p]);
-    if (s != CLR_OK) return s;
     PlanParams& q = P[p];
     q = PlanParams{};
     q.A = A->view();
@@ -1506,20 +1665,26 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   HIP_TRY(ctx, hipMemcpyAsync(hc.data(), tc, sizeof(int64_t) * hc.size(), hipMemcpyDeviceToHost, stream));
   HIP_TRY(ctx, hipMemcpyAsync(hs.data(), ts, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, stream));
   HIP_TRY(ctx, hipStreamSynchronize(stream));
-  // place of every product in the concatenated lists
+  // place of every product in the concatenated lists (the output room is
+  // per product: each output has an arena of its own)
   std::vector<int64_t> base((size_t)np * kNumCounters);
   int64_t sum[kNumCounters] = {};
   for (int p = 0; p < np; ++p)
     for (int c = 0; c < kNumCounters; ++c) {
       const int64_t v = hc[(size_t)p * kNumCounters + c];
       if (v < 0) return fail(ctx, CLR_ERR_INTERNAL, "negative work count");
-      base[(size_t)p * kNumCounters + c] = sum[c];
+      base[(size_t)p * kNumCounters + c] = c == kCntOut ? 0 : sum[c];
       sum[c] += v;
     }
   for (int c = 0; c < kNumCounters; ++c) {
-    if (c != kCntPool && c != kCntScratch && sum[c] > INT32_MAX)
+    if (!counts_doubles(c) && sum[c] > INT32_MAX)
       return fail(ctx, CLR_ERR_CAPACITY, "batch work list %d too long (%lld)", c, (long long)sum[c]);
     pl->counts[c] = sum[c];
+  }
+  for (int p = 0; p < np; ++p) {
+    clr_status s = alloc_matrix(ctx, pl->A[p]->rs, pl->B[p]->cs, &pl->C[p], nullptr,
+                                hc[(size_t)p * kNumCounters + kCntOut]);
+    if (s != CLR_OK) return s;
   }
   for (int p = 0; p < np; ++p)
     for (int k = 0; k < kNumStats; ++k) pl->flops[k] += hs[(size_t)p * kNumStats + k];
@@ -1527,12 +1692,6 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   pl->n_thin2 = sum[kCntThin2];
   pl->n_dense = sum[kCntGemmItems];
   pl->n_rec = sum[kCntComputed];
-  int64_t acc_total = 0;
-  std::vector<int64_t> acc_base(np);
-  for (int p = 0; p < np; ++p) {
-    acc_base[p] = acc_total;
-    acc_total += pl->C[p]->rows * pl->C[p]->cols;
-  }
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = ensure(pl->seg_dense, sizeof(Seg) * sum[kCntSegDense]);
   if (e == hipSuccess) e = ensure(pl->items_dense, sizeof(GemmItem) * sum[kCntGemmItems]);
@@ -1545,7 +1704,7 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   if (e == hipSuccess) e = ensure(pl->rec, sizeof(RecItem) * sum[kCntComputed]);
   if (e == hipSuccess) e = ensure(pl->pool, sizeof(double) * sum[kCntPool]);
   if (e == hipSuccess) e = ensure(pl->scratch, sizeof(double) * sum[kCntScratch]);
-  if (e == hipSuccess && sum[kCntGemmItems] > 0) e = ensure(pl->acc, sizeof(double) * (size_t)acc_total);
+  if (e == hipSuccess && sum[kCntAcc] > 0) e = ensure(pl->acc, sizeof(double) * (size_t)sum[kCntAcc]);
   if (e == hipSuccess) e = ensure(pl->recg, rec_work_bytes(sum[kCntComputed]));
   if (e == hipSuccess) e = ensure(pl->status, sizeof(int));
   if (e == hipSuccess) e = launch_fill_i32(as<int>(pl->status), 0, 1, stream);
@@ -1575,12 +1734,12 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     F.rec = as<RecItem>(pl->rec);
     F.pool = as<double>(pl->pool);
     F.scratch = as<double>(pl->scratch);
-    F.acc = pl->acc.p ? as<double>(pl->acc) + acc_base[p] : nullptr;
+    F.acc = as<double>(pl->acc);
     F.c_arena = pl->C[p]->arena;
+    F.c_boff = pl->C[p]->d_boff;
     F.c_kind = pl->C[p]->d_kind;
     F.c_rank = pl->C[p]->d_rank;
     F.c_norm = pl->C[p]->d_norm;
-    F.c_ncols = pl->C[p]->cols;
     HIP_TRY(ctx, launch_fill(P[p], F, stream));
   }
   HIP_TRY(ctx, launch_item_order(as<GemmItem>(pl->items_dense), (int)sum[kCntGemmItems],
@@ -1734,23 +1893,21 @@ clr_status axpby_impl(clr_context* ctx, Work& W, double a, const clr_matrix* X, 
   if (Y && (Y->rs != X->rs || Y->cs != X->cs))
     return fail(ctx, CLR_ERR_SHAPE, "clr_axpby: blockings differ");
   if (dev && !Tinto) return fail(ctx, CLR_ERR_INVALID_ARG, "device-sized combination: in place only");
+  // the output: Tinto, or allocated once the plan has sized its room
   clr_matrix* T = Tinto;
   if (T) {
     if (T->rs != X->rs || T->cs != X->cs) return fail(ctx, CLR_ERR_SHAPE, "clr_axpby: output blocking");
     HIP_TRY(ctx, reset_meta(ctx, T));
-  } else {
-    clr_status s = alloc_matrix(ctx, X->rs, X->cs, &T);
-    if (s != CLR_OK) return s;
   }
   auto bail = [&](clr_status code) {
-    if (!Tinto) free_matrix(T);
+    if (!Tinto && T) free_matrix(T);
     return code;
   };
   hipStream_t stream = ctx->stream;
   const int64_t nb = (int64_t)X->nrb * X->ncb;
   hipError_t e = hipSuccess;
   if (dev) {
-    if (!work_fits(W, work_sizes(nb, dev->caps, X->rows, X->cols)))
+    if (!work_fits(W, work_sizes(nb, dev->caps)))
       return bail(fail(ctx, CLR_ERR_CAPACITY, "workspace smaller than the run's capacities"));
   } else {
     if (e == hipSuccess) e = ensure(W.cnt, sizeof(int64_t) * kNumCounters * nb);
@@ -1769,10 +1926,6 @@ clr_status axpby_impl(clr_context* ctx, Work& W, double a, const clr_matrix* X, 
   P.screen = o->screen;
   P.tol = o->tol;
   P.edges = edge_table(ctx, o);
-  P.t_arena = T->arena;
-  P.t_kind = T->d_kind;
-  P.t_rank = T->d_rank;
-  P.t_norm = T->d_norm;
   int64_t* tot = as<int64_t>(W.totals);
   if (e == hipSuccess) e = launch_comb_count(P, as<int64_t>(W.cnt), stream);
   if (e == hipSuccess) e = launch_scan(as<int64_t>(W.cnt), as<int64_t>(W.off), nb, kNumCounters, tot, stream);
@@ -1780,8 +1933,10 @@ clr_status axpby_impl(clr_context* ctx, Work& W, double a, const clr_matrix* X, 
   int64_t* live = nullptr;
   if (dev) {
     live = as<int64_t>(W.live);
-    if (e == hipSuccess) e = launch_caps(tot, dev->caps, live, stream);
-    for (int i = 0; i < kNumCounters; ++i) n[i] = dev->caps.c[i];
+    Caps caps = dev->caps;
+    caps.c[kCntOut] = T->cap;   // the output's arena bounds its room
+    if (e == hipSuccess) e = launch_caps(tot, caps, live, stream);
+    for (int i = 0; i < kNumCounters; ++i) n[i] = caps.c[i];
   } else {
     if (e == hipSuccess) e = hipMemcpyAsync(n, tot, sizeof(n), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -1789,13 +1944,29 @@ clr_status axpby_impl(clr_context* ctx, Work& W, double a, const clr_matrix* X, 
       for (int i = 0; i < kNumCounters; ++i) W.seen.c[i] = std::max(W.seen.c[i], n[i]);
       Caps exact;
       for (int i = 0; i < kNumCounters; ++i) exact.c[i] = n[i];
-      e = reserve_work(W, work_sizes(nb, exact, X->rows, X->cols));
+      e = reserve_work(W, work_sizes(nb, exact));
     }
   }
   if (e != hipSuccess) return bail(fail(ctx, CLR_ERR_HIP, "combination plan: %s", hipGetErrorString(e)));
   for (int i = 0; i < kNumCounters; ++i)
-    if (n[i] < 0 || (i != kCntScratch && n[i] > INT32_MAX))
+    if (n[i] < 0 || (!counts_doubles(i) && n[i] > INT32_MAX))
       return bail(fail(ctx, CLR_ERR_CAPACITY, "work list %d too long (%lld)", i, (long long)n[i]));
+  if (!dev) {
+    if (T) {
+      if (n[kCntOut] > T->cap)
+        return bail(fail(ctx, CLR_ERR_CAPACITY, "output arena of %lld doubles, %lld needed",
+                         (long long)T->cap, (long long)n[kCntOut]));
+    } else {
+      clr_status s = alloc_matrix(ctx, X->rs, X->cs, &T, nullptr, n[kCntOut]);
+      if (s != CLR_OK) return s;
+    }
+  }
+  P.t_arena = T->arena;
+  P.t_boff = T->d_boff;
+  P.t_kind = T->d_kind;
+  P.t_rank = T->d_rank;
+  P.t_norm = T->d_norm;
+  T->host_boff = false;   // offsets planned on the device from here on
   auto lv = [&](int k) { return live ? live + k : nullptr; };
   P.acc = as<double>(W.acc);
   CombLists L{};
@@ -1886,7 +2057,15 @@ clr_status scaled_copy(clr_context* ctx, const clr_matrix* src, double sc, clr_m
 
 clr_status identity_matrix(clr_context* ctx, const std::vector<int>& sizes, clr_matrix** out) {
   clr_matrix* Z = nullptr;
-  clr_status s = alloc_matrix(ctx, sizes, sizes, &Z);
+  // packed: the diagonal blocks one after another
+  const size_t nbl = sizes.size();
+  std::vector<int64_t> offs(nbl * nbl, 0);
+  int64_t cap = 0;
+  for (size_t I = 0; I < nbl; ++I) {
+    offs[I * nbl + I] = cap;
+    cap += (int64_t)sizes[I] * sizes[I];
+  }
+  clr_status s = alloc_matrix(ctx, sizes, sizes, &Z, &offs, cap);
   if (s != CLR_OK) return s;
   // Z = 0 * (nothing) + 1 * I through the dense combination path
   const int nb = Z->nrb;
@@ -1895,7 +2074,7 @@ clr_status identity_matrix(clr_context* ctx, const std::vector<int>& sizes, clr_
   std::vector<double> norm(nb * nb, 0.0);
   for (int I = 0; I < nb; ++I) {
     AxpbyDenseItem d{};
-    d.D = Z->arena + slot_offset(Z->roff.data(), Z->coff.data(), Z->cols, I, I);
+    d.D = Z->arena + Z->boff[(size_t)I * nb + I];
     d.c = 1.0;
     d.m = d.n = sizes[I];
     items.push_back(d);
@@ -2038,7 +2217,7 @@ struct IterGraph {
       run.caps.c[c] = std::max<int64_t>(run.caps.c[c],
                                         (int64_t)std::ceil(m * (double)W.seen.c[c]) + 16);
     const int64_t nb = (int64_t)X->nrb * X->ncb;
-    HIP_TRY(ctx, reserve_work(W, work_sizes(nb, run.caps, X->rows, X->cols)));
+    HIP_TRY(ctx, reserve_work(W, work_sizes(nb, run.caps)));
     HIP_TRY(ctx, launch_fill_i32(reinterpret_cast<int*>(as<int64_t>(W.live)), 0, 2 * kNumLive,
                                  ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -2153,10 +2332,23 @@ extern "C" clr_status clr_sqrt_inv(clr_context* ctx, const clr_matrix* S, const 
   g64.split = ga64.split = 0;
   const bool scheduled = o->g.precision != CLR_FP64 && o->reduced_below > 0.0;
   clr_matrix *Z = nullptr, *Y = nullptr;
-  if ((s = identity_matrix(ctx, S->rs, &Z)) != CLR_OK) return s;
-  if ((s = copy_matrix(ctx, S, &Y)) != CLR_OK) {
-    free_matrix(Z);
-    return s;
+  if (o->graph) {
+    // the graph's fixed pairs hold results of any rank: dense slots
+    if ((s = identity_matrix(ctx, S->rs, &Y)) != CLR_OK) return s;
+    s = relayout_matrix(ctx, Y, nullptr, -1, &Z);
+    free_matrix(Y);
+    Y = nullptr;
+    if (s != CLR_OK) return s;
+    if ((s = relayout_matrix(ctx, S, nullptr, -1, &Y)) != CLR_OK) {
+      free_matrix(Z);
+      return s;
+    }
+  } else {
+    if ((s = identity_matrix(ctx, S->rs, &Z)) != CLR_OK) return s;
+    if ((s = copy_matrix(ctx, S, &Y)) != CLR_OK) {
+      free_matrix(Z);
+      return s;
+    }
   }
   // graph replay: the iterates move into the graph's fixed pairs, which it owns
   std::unique_ptr<IterGraph> G;
@@ -2343,8 +2535,20 @@ clr_status dense_to_clr(clr_context* ctx, const double* D, int64_t ld, const std
 }
 
 clr_status transpose_clr(clr_context* ctx, const clr_matrix* A, clr_matrix** out) {
+  // block (J, I) of T stores as many elements as block (I, J) of A: same offsets
+  const size_t nb = (size_t)A->nrb * A->ncb;
+  std::vector<int64_t> ab = A->boff;
+  if (!A->host_boff) {
+    ab.resize(nb);
+    HIP_TRY(ctx, hipMemcpyAsync(ab.data(), A->d_boff, sizeof(int64_t) * nb, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  std::vector<int64_t> tb(nb);
+  for (int I = 0; I < A->nrb; ++I)
+    for (int J = 0; J < A->ncb; ++J) tb[(size_t)J * A->nrb + I] = ab[(size_t)I * A->ncb + J];
   clr_matrix* T = nullptr;
-  clr_status s = alloc_matrix(ctx, A->cs, A->rs, &T);
+  clr_status s = alloc_matrix(ctx, A->cs, A->rs, &T, &tb, A->cap);
   if (s != CLR_OK) return s;
   hipError_t e = launch_transpose(A->view(), T->view(), T->arena, T->d_kind, T->d_rank, T->d_norm,
                                   ctx->stream);

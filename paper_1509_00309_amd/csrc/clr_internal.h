@@ -120,6 +120,8 @@ enum PlanCounter : int {
   kCntComputed,       // 1 if the block passed screening
   kCntGemmItems,      // output tiles of the dense accumulation GEMM
   kCntCombDense,      // dense parts of a combination a X + b Y + c I (zero in a product)
+  kCntOut,            // doubles of the output block's room (its largest possible storage)
+  kCntAcc,            // doubles of the dense accumulator of a densified block
   kNumCounters
 };
 
@@ -143,21 +145,27 @@ enum PlanStat : int {
 };
 
 // Device view of a CLR matrix's metadata and arena.
+// Block b = I * ncb + J of a matrix is stored at arena + boff[b]: a dense
+// block as m x n column-major, a factored block as U (m x r) followed by
+// V (n x r).  The offsets are free: packed (a block takes exactly what it
+// stores), dense-slot (every block has room for m x n) or upper bounds
+// planned on the device before a product runs.
 struct MatView {
   const int* kind;      // nrb*ncb
   const int* rank;
   const double* norm;
   const int* roff;      // nrb+1
   const int* coff;      // ncb+1
-  const double* arena;  // slot (I,J) at roff[I]*ncols + m_I*coff[J]
+  const double* arena;
+  const int64_t* boff;  // nrb*ncb block offsets into arena (doubles)
   int nrb, ncb;
-  int64_t ncols;
 };
 
-__host__ __device__ inline int64_t slot_offset(const int* roff, const int* coff, int64_t ncols,
-                                               int I, int J) {
-  const int64_t m = roff[I + 1] - roff[I];
-  return (int64_t)roff[I] * ncols + m * (int64_t)coff[J];
+__device__ inline const double* block_at(const MatView& M, int b) { return M.arena + M.boff[b]; }
+
+// Elements a block of the given kind stores.
+__host__ __device__ inline int64_t stored_size(int kind, int m, int n, int r) {
+  return kind == 1 ? (int64_t)m * n : kind == 2 ? (int64_t)(m + n) * r : 0;
 }
 
 // Split `extent` into at most ceil(extent/maxe) parts on 16-element boundaries.
@@ -227,12 +235,12 @@ struct FillParams {
   RecItem* rec;
   double* pool;
   double* scratch;
-  double* acc;            // dense accumulators, same slot layout as C
-  double* c_arena;
+  double* acc;            // dense accumulators (a block's at its kCntAcc offset)
+  double* c_arena;        // output room (a block's at its kCntOut offset)
+  int64_t* c_boff;        // output block offsets, written for every block
   int* c_kind;
   int* c_rank;
   double* c_norm;
-  int64_t c_ncols;
   const int64_t* abort;   // optional: nothing is written while *abort != 0
 };
 
@@ -258,8 +266,9 @@ struct CombParams {
   int screen;
   double tol;
   EdgeTable edges;        // item edges of the low-rank-term GEMM items (dense classes)
-  double* acc;            // dense accumulators, same slot layout as T
-  double* t_arena;
+  double* acc;            // dense accumulators (a block's at its kCntAcc offset)
+  double* t_arena;        // output room (a block's at its kCntOut offset)
+  int64_t* t_boff;        // output block offsets, written for every block
   int* t_kind;
   int* t_rank;
   double* t_norm;
@@ -369,6 +378,10 @@ hipError_t launch_from_dense(const MatView& M, double* arena, int* kind, int* ra
 hipError_t launch_transpose(const MatView& A, const MatView& T, double* tarena, int* tkind,
                             int* trank, double* tnorm, hipStream_t s);
 hipError_t launch_mask_dense(const MatView& M, double* out, int64_t ld, hipStream_t s);
+// Copy every block's stored elements from src to dst_arena + dst_boff[b]
+// (same blocking, kinds and ranks; the two layouts must not overlap).
+hipError_t launch_relayout(const MatView& src, double* dst_arena, const int64_t* dst_boff,
+                           hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 // Measurement kernels (k_peaks.hip): a chain of FP64 MFMAs per wave (4 waves
 // per workgroup) and a plain copy of n_doubles (even) doubles.

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_ingest(MatView M, double* arena, const 
   }
   const int m = M.roff[I + 1] - M.roff[I];
   const int n = M.coff[J + 1] - M.coff[J];
-  double* dst = arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  double* dst = arena + M.boff[blk];
   double part = 0.0;
   if (kind == 1) {
     const double* src = f0[blk];
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_to_dense(MatView M, double* out, int64_
   const int m = M.roff[I + 1] - M.roff[I];
   const int n = M.coff[J + 1] - M.coff[J];
   const int kind = M.kind[blk];
-  const double* src = M.arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  const double* src = block_at(M, blk);
   double* dst = out + M.roff[I] + (int64_t)M.coff[J] * ld;
   const int r = kind == 2 ? M.rank[blk] : 0;
   for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_scale(MatView M, double* arena, double*
   const int I = blk / M.ncb, J = blk % M.ncb;
   const int m = M.roff[I + 1] - M.roff[I];
   const int n = M.coff[J + 1] - M.coff[J];
-  double* dst = arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  double* dst = arena + M.boff[blk];
   const int64_t cnt = kind == 1 ? (int64_t)m * n : (int64_t)m * M.rank[blk];
   for (int64_t e = threadIdx.x; e < cnt; e += 256) dst[e] *= s;
   if (threadIdx.x == 0) norm[blk] = fabs(s) * norm[blk];
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_identity_terms(MatView M, double* out) 
     if (threadIdx.x == 0) out[blk] = kind == 0 ? 0.0 : M.norm[blk] * M.norm[blk];
     return;
   }
-  const double* src = M.arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  const double* src = block_at(M, blk);
   const int r = kind == 2 ? M.rank[blk] : 0;
   double part = 0.0;
   for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_from_dense(MatView M, double* arena, in
   const int m = M.roff[I + 1] - M.roff[I];
   const int n = M.coff[J + 1] - M.coff[J];
   const bool keep = mask_kind == nullptr || mask_kind[blk] != 0;
-  double* dst = arena + slot_offset(M.roff, M.coff, M.ncols, I, J);
+  double* dst = arena + M.boff[blk];
   const double* src = D + M.roff[I] + (int64_t)M.coff[J] * ld;
   double part = 0.0;
   if (keep) {
@@ -218,8 +218,8 @@ __global__ __launch_bounds__(256) void k_transpose(MatView A, MatView T, double*
     tnorm[tb] = A.norm[blk];
   }
   if (kind == 0) return;
-  const double* src = A.arena + slot_offset(A.roff, A.coff, A.ncols, I, J);
-  double* dst = tarena + slot_offset(T.roff, T.coff, T.ncols, J, I);
+  const double* src = block_at(A, blk);
+  double* dst = tarena + T.boff[tb];
   if (kind == 1) {
     for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += 256) {
       const int j = (int)(e % n), i = (int)(e / n);   // dst is n x m, ld n
@@ -263,6 +263,30 @@ hipError_t launch_transpose(const MatView& A, const MatView& T, double* tarena, 
   hipLaunchKernelGGL(k_transpose, dim3(nb), dim3(256), 0, s, A, T, tarena, tkind, trank, tnorm);
   return hipGetLastError();
 }
+// Block b's stored elements (m n dense, (m + n) r factored) from its place in
+// src to dst + dst_boff[b].
+__global__ __launch_bounds__(256) void k_relayout(MatView M, double* __restrict__ dst,
+                                                  const int64_t* __restrict__ dst_boff) {
+  const int blk = blockIdx.x;
+  const int kind = M.kind[blk];
+  if (kind == 0) return;
+  const int I = blk / M.ncb, J = blk % M.ncb;
+  const int m = M.roff[I + 1] - M.roff[I];
+  const int n = M.coff[J + 1] - M.coff[J];
+  const int64_t cnt = stored_size(kind, m, n, kind == 2 ? M.rank[blk] : 0);
+  const double* __restrict__ src = block_at(M, blk);
+  double* __restrict__ out = dst + dst_boff[blk];
+  for (int64_t e = threadIdx.x; e < cnt; e += 256) out[e] = src[e];
+}
+
+hipError_t launch_relayout(const MatView& src, double* dst_arena, const int64_t* dst_boff,
+                           hipStream_t s) {
+  const int nb = src.nrb * src.ncb;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relayout, dim3(nb), dim3(256), 0, s, src, dst_arena, dst_boff);
+  return hipGetLastError();
+}
+
 hipError_t launch_mask_dense(const MatView& M, double* out, int64_t ld, hipStream_t s) {
   const int nb = M.nrb * M.ncb;
   if (nb == 0) return hipSuccess;

@@ -106,6 +106,10 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
     c[kCntScratch] = rec_scratch_doubles(path, m, n, (int)rcat, P.tol);
     c[kCntComputed] = 1;
     c[kCntGemmItems] = densify ? dense_parts(P.edges, m, n) : 0;
+    // room of the result: dense, or truncated to rank r with 2 r <= min(m, n)
+    // ((m + n) r <= m n); a factored block keeps rank <= rcat
+    c[kCntOut] = densify ? (int64_t)m * n : (int64_t)(m + n) * rcat;
+    c[kCntAcc] = densify ? (int64_t)m * n : 0;
     if (densify) fden = 2.0 * m * (double)n * (double)lr_rank_sum;
   }
   for (int i = 0; i < kNumCounters; ++i) cnt[(int64_t)i * npairs + pair] = c[i];
@@ -229,6 +233,8 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   const int pair = blockIdx.x * blockDim.x + threadIdx.x;
   if (pair >= npairs) return;
   if (F.abort && *F.abort) return;   // a list would overflow its capacity
+  // every block's offset (a zero block's is never read)
+  F.c_boff[pair] = F.off[(int64_t)kCntOut * npairs + pair];
   const int fl = F.flags[pair];
   if (!(fl & kFlagComputed)) return;
   const bool densify = fl & kFlagDensify;
@@ -244,8 +250,8 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   const int64_t pi0 = pi;
   int64_t t1 = off(kCntThin1);
   int64_t t2 = off(kCntThin2);
-  const int64_t cslot = slot_offset(P.A.roff, P.B.coff, F.c_ncols, I, J);
-  double* accb = F.acc + cslot;
+  const int64_t cslot = off(kCntOut);
+  double* accb = F.acc + off(kCntAcc);
   int kb = 0;
   int rcat = 0;
   bool anydd = false;
@@ -255,8 +261,8 @@ __global__ void k_fill(PlanParams P, FillParams F) {
     const int kbk = P.B.kind[K * P.ncb + J];
     if (kbk == 0) continue;
     const int k = P.A.coff[K + 1] - P.A.coff[K];
-    const double* a = P.A.arena + slot_offset(P.A.roff, P.A.coff, P.A.ncols, I, K);
-    const double* b = P.B.arena + slot_offset(P.B.roff, P.B.coff, P.B.ncols, K, J);
+    const double* a = block_at(P.A, I * P.nkb + K);
+    const double* b = block_at(P.B, K * P.ncb + J);
     Seg dense_term;
     Piece pc;
     pc.pad = 0;
@@ -493,9 +499,12 @@ __global__ void k_comb_count(CombParams P, int64_t* __restrict__ cnt) {
       c[kCntGemmItems] = nlr ? dense_parts(P.edges, d.m, d.n) : 0;
       c[kCntScratch] =
           rec_scratch_doubles(d.diag ? kPathForceDense : kPathDense, d.m, d.n, 0, P.tol);
+      c[kCntOut] = (int64_t)d.m * d.n;
+      c[kCntAcc] = (int64_t)d.m * d.n;
     } else {
       c[kCntPieces] = nlr;
       c[kCntScratch] = rec_scratch_doubles(kPathLowRank, d.m, d.n, d.R, P.tol);
+      c[kCntOut] = (int64_t)(d.m + d.n) * d.R;
     }
   }
   for (int i = 0; i < kNumCounters; ++i) cnt[(int64_t)i * nb + b] = c[i];
@@ -506,29 +515,30 @@ __global__ void k_comb_fill(CombParams P, CombLists L) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   if (L.abort && *L.abort) return;
+  auto off = [&](int c) { return L.off[(int64_t)c * nb + b]; };
+  P.t_boff[b] = off(kCntOut);   // every block's (a zero block's is never read)
   const int I = b / P.X.ncb, J = b % P.X.ncb;
   const CombDecision d = comb_decide(P, I, J);
   if (!d.computed) return;
-  auto off = [&](int c) { return L.off[(int64_t)c * nb + b]; };
   const int m = d.m, n = d.n;
-  const int64_t so = slot_offset(P.X.roff, P.X.coff, P.X.ncols, I, J);
-  const double* xs = P.X.arena + so;
-  const double* ys = P.Y.kind ? P.Y.arena + so : nullptr;
+  const double* xs = block_at(P.X, b);
+  const double* ys = P.Y.kind ? block_at(P.Y, b) : nullptr;
+  double* accb = P.acc + off(kCntAcc);
   RecItem r{};
   r.m = m;
   r.n = n;
   r.tau = d.tau;
-  r.out = P.t_arena + so;
+  r.out = P.t_arena + off(kCntOut);
   r.kind_out = P.t_kind + b;
   r.rank_out = P.t_rank + b;
   r.norm_out = P.t_norm + b;
   if (d.densify) {
     r.path = d.diag ? kPathForceDense : kPathDense;
     r.cert_hint = 1;
-    r.D = P.acc + so;
+    r.D = accb;
     r.ldd = m;
     AxpbyDenseItem di;
-    di.D = P.acc + so;
+    di.D = accb;
     di.X = d.kx == 1 ? xs : nullptr;
     di.Y = d.ky == 1 ? ys : nullptr;
     di.a = P.a;
@@ -566,7 +576,7 @@ __global__ void k_comb_fill(CombParams P, CombLists L) {
           GemmItem g;
           part_range(m, pr, pa, &g.row0, &g.m);
           part_range(n, pc, pb, &g.col0, &g.n);
-          g.C = P.acc + so;
+          g.C = accb;
           g.ldc = m;
           g.seg0 = (int)s0;
           g.nseg = (int)(sc - s0);
