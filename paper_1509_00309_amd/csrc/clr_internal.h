@@ -23,7 +23,8 @@ constexpr int kRecThreads = 512;      // recompression workgroup (32 groups of 1
 constexpr int kRecLdsBytes = 140 * 1024;  // dynamic LDS for the working set (160 KiB minus bookkeeping)
 constexpr int kJacobiMaxSweeps = 60;
 constexpr int kCertEdge = 160;        // most columns the dense certificate examines
-constexpr int kCertMaxShort = 2 * kCertEdge - 1;   // largest short edge it certifies (h + 1 <= 160)
+constexpr int kCertMaxShort = 2 * kCertEdge - 1;   // largest short edge of the column-subset form
+constexpr int kCertMaxEdge = 512;    // largest block edge of the left-looking form beyond that
 
 // ---------------------------------------------------------------------------
 // XCD-blocked workgroup mapping: the dispatcher deals workgroups to the 8 XCDs

@@ -25,10 +25,21 @@
 // terms twice, so success proves s_h(D)^2 > (9/8 tol^2 + 2 (p + q + 2) u)
 // ||D||_F^2.  The margin this leaves between s_h and tol ||D||_F is at least
 // about 7e-9 ||D||_F for every tol, two orders of magnitude above the
-// worst-case error bound of a Householder-based SVD of a block of edge <= 319,
+// worst-case error bound of a Householder-based SVD of a block of edge <= 512,
 // so the SVD path reaches the same decision: the certificate changes no
 // result (a certified block is copied out exactly as a block the SVD finds
 // dense), it only skips work.
+//
+// Short edges q in (319, 512], and those in (160, 319] whose column subset
+// fails (h + 1 pivots out of 160 columns leave little choice near 319): every
+// column takes part and the Gram matrix is not held at all.  A left-looking pivoted Cholesky
+// forms, at step k, the pivot's Gram column g_j = <d_j, d_piv> (a dot product
+// of length p, each entry computed once: the symmetric matrix with those
+// entries differs from D^T D by at most gamma_p |D|^T |D|, so by at most
+// gamma_p ||D||_F^2 in the 2-norm, as above), subtracts L(j, 0:k) L(piv, 0:k)^T
+// and keeps column k of L in the block's recompression scratch (q x (h + 1)
+// doubles, which the block's SVD working set m n exceeds).  The Cholesky error
+// bound holds for any order of the inner products, so the proof is unchanged.
 //
 // Short edges q in (160, 319]: the columns examined are a subset T of
 // qs = 160 of the q, evenly spread (column floor(a q / qs) for a < qs).
@@ -56,6 +67,7 @@ namespace clr {
 namespace {
 
 typedef const double __attribute__((address_space(1))) cgdbl;
+typedef double __attribute__((address_space(1))) gdbl;
 
 constexpr int kCertSlab = 16;               // inner indices staged per slab
 constexpr int kCertLd = kCertEdge + 1;
@@ -361,6 +373,148 @@ __global__ __launch_bounds__(64 * WR * WC, 4) void k_dense_cert(
   }
 }
 
+// All 16 lanes of a DPP row end with the row's sum: each step adds the
+// lane's value and its partner's (the same two numbers in both lanes).
+__device__ __attribute__((always_inline)) inline double row_sum16(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  v += dpp_d<0x140>(v);   // row_mirror
+  return v;
+}
+
+constexpr int kBigThreads = 512;
+struct BigCertLds {
+  double dg[kCertMaxEdge];     // residual diagonal of D^T D - c I
+  double colp[kCertMaxEdge];   // the pivot column of G (p entries)
+  double gcol[kCertMaxEdge];   // its Gram column
+  double lrow[kCertMaxEdge / 2 + 1];   // the pivot's row of L
+  int taken[kCertMaxEdge];
+  double wv[kBigThreads / 64];
+  int wi[kBigThreads / 64];
+};
+
+// Short edges in (kCertEdge, kCertMaxEdge] not proved by the column subset:
+// G (p x q) is D or D^T, thread t owns column t of G (q <= 512 = the
+// workgroup).
+__device__ bool cert_big(const RecItem& it, double tol, BigCertLds& L) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int m = it.m, n = it.n;
+  const bool trans = m < n;
+  const int q = trans ? m : n, p = trans ? n : m;
+  cgdbl* D = (cgdbl*)it.D;
+  const int64_t ldd = it.ldd;
+  gdbl* __restrict__ Lf = (gdbl*)it.scratch;   // column k of L at Lf + k q
+  // G(i, j) = D(i, j), or D(j, i) when the columns of D^T are the short side
+  auto g_at = [&](int i, int j) -> double { return trans ? D[j + (int64_t)i * ldd] : D[i + (int64_t)j * ldd]; };
+  // squared column norms (thread t sums column t in index order)
+  double own = 0.0;
+  if (tid < q)
+    for (int i = 0; i < p; ++i) {
+      const double v = g_at(i, tid);
+      own = fma(v, v, own);
+    }
+  // ||D||_F^2: lane 0's butterfly sum per wave, the wave sums in wave order
+  double part = own;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+  if (lane == 0) L.wv[wave] = part;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kBigThreads / 64; ++w) s += L.wv[w];
+  if (!(s > 0x1p-600 && s < 0x1p+1000)) return false;   // uniform
+  const double c = s * (1.125 * tol * tol + 4.0 * (double)(p + q + 2) * 0x1p-53);
+  if (tid < q) {
+    L.dg[tid] = own - c;
+    L.taken[tid] = 0;
+  }
+  __syncthreads();
+  const int h = q / 2;
+  for (int k = 0; k <= h; ++k) {
+    // pivot: the largest residual diagonal entry, the smallest index among ties
+    double bv = -__builtin_huge_val();
+    int bi = 0x7fffffff;
+    if (tid < q && !L.taken[tid]) {
+      bv = L.dg[tid];
+      bi = tid;
+    }
+    wave_argmax(bv, bi, lane);
+    if (lane == 0) {
+      L.wv[wave] = bv;
+      L.wi[wave] = bi;
+    }
+    __syncthreads();
+    bv = L.wv[0];
+    bi = L.wi[0];
+    for (int w = 1; w < kBigThreads / 64; ++w)
+      if (L.wv[w] > bv || (L.wv[w] == bv && L.wi[w] < bi)) {
+        bv = L.wv[w];
+        bi = L.wi[w];
+      }
+    if (!(bv > 0.0)) return false;   // the same decision in every thread
+    const int piv = bi;
+    const double inv = 1.0 / sqrt(bv);
+    for (int i = tid; i < p; i += kBigThreads) L.colp[i] = g_at(i, piv);
+    for (int j = tid; j < k; j += kBigThreads) L.lrow[j] = Lf[piv + (int64_t)j * q];
+    __syncthreads();
+    // Gram column of the pivot over the columns not yet taken
+    if (trans) {
+      // G(i, j) = D(j, i): consecutive threads read consecutive addresses
+      if (tid < q && !L.taken[tid] && tid != piv) {
+        double g = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < p; ++i) g = fma(D[tid + (int64_t)i * ldd], L.colp[i], g);
+        L.gcol[tid] = g;
+      }
+    } else {
+      // 32 groups of 16 lanes, one column per group at a time
+      const int grp = tid >> 4, gl = tid & 15;
+      for (int j = grp; j < q; j += kBigThreads / 16) {
+        if (L.taken[j] || j == piv) continue;   // uniform in the group
+        cgdbl* __restrict__ col = D + (int64_t)j * ldd;
+        double g = 0.0;
+        for (int i = gl; i < p; i += 16) g = fma(col[i], L.colp[i], g);
+        g = row_sum16(g);
+        if (gl == 0) L.gcol[j] = g;
+      }
+    }
+    __syncthreads();
+    if (tid < q && !L.taken[tid] && tid != piv) {
+      double v = L.gcol[tid];
+      for (int j = 0; j < k; ++j) v = fma(-Lf[tid + (int64_t)j * q], L.lrow[j], v);
+      const double l = v * inv;
+      Lf[tid + (int64_t)k * q] = l;
+      L.dg[tid] = fma(-l, l, L.dg[tid]);
+    }
+    if (tid == piv) L.taken[tid] = 1;
+    __syncthreads();
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(kBigThreads) void k_dense_cert_big(
+    const RecItem* __restrict__ items, int nitems, double tol, int* __restrict__ cert,
+    unsigned long long* __restrict__ count, const int64_t* __restrict__ live) {
+  __shared__ BigCertLds L;
+  if (live) nitems = (int)min((int64_t)nitems, *live);
+  const int item = xcd_unit(nitems, live != nullptr);
+  if (item < 0 || item >= nitems) return;
+  const RecItem it = items[item];
+  const int q = it.m < it.n ? it.m : it.n, p = it.m < it.n ? it.n : it.m;
+  // short edges beyond 319, and those in (160, 319] that the column subset
+  // did not prove (its h + 1 pivots use up to all 160 columns); the factor L
+  // (q x (h + 1)) lives in the block's scratch, which holds m n
+  if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > kCertEdge &&
+        p <= kCertMaxEdge && cert[item] == 0 && it.D != nullptr && it.scratch != nullptr))
+    return;
+  const bool ok = cert_big(it, tol, L);
+  if (ok && threadIdx.x == 0) {
+    cert[item] = 1;
+    if (count) atomicAdd(count, 1ull);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* cert,
@@ -374,6 +528,8 @@ hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* 
                      0, 128, cert, count, live);
   hipLaunchKernelGGL((k_dense_cert<4, 4, 3, 3>), dim3(grid), dim3(1024), 0, s, items, nitems,
                      tol, 128, kCertMaxShort, cert, count, live);
+  hipLaunchKernelGGL(k_dense_cert_big, dim3(grid), dim3(kBigThreads), 0, s, items, nitems, tol,
+                     cert, count, live);
   return hipGetLastError();
 }
 
