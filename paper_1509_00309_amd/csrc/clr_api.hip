@@ -60,7 +60,7 @@ struct DevBuf {
 struct Work {
   DevBuf cnt, off, st, flags, totals, seg_dense, items_dense, seg_thin1, items_thin1, seg_thin2,
       items_thin2, pieces, rec, pool, scratch, acc, terms, comb_dense, recg, order, order_thin,
-      sortw, live, flops;
+      sortw, live, flops, lists;
   clr::Caps seen{};   // largest list lengths of the runs sized on the host
   double host_flops = 0.0;   // product flops of those runs (their symbolic statistics)
 };
@@ -226,7 +226,7 @@ void each_buf(Work& w, F f) {
   for (DevBuf* b : {&w.cnt, &w.off, &w.st, &w.flags, &w.totals, &w.seg_dense, &w.items_dense,
                     &w.seg_thin1, &w.items_thin1, &w.seg_thin2, &w.items_thin2, &w.pieces, &w.rec,
                     &w.pool, &w.scratch, &w.acc, &w.terms, &w.comb_dense, &w.recg, &w.order,
-                    &w.order_thin, &w.sortw, &w.live, &w.flops})
+                    &w.order_thin, &w.sortw, &w.live, &w.flops, &w.lists})
     f(*b);
 }
 void free_work(Work& w) {
@@ -655,7 +655,7 @@ inline bool counts_doubles(int c) {
 struct WorkSizes {
   std::vector<std::pair<DevBuf Work::*, size_t>> bufs;
 };
-WorkSizes work_sizes(int64_t npairs, const Caps& caps) {
+WorkSizes work_sizes(int64_t npairs, const Caps& caps, int64_t list_ints = 0) {
   auto n = [&](int c) { return (size_t)std::max<int64_t>(caps.c[c], 0); };
   WorkSizes w;
   w.bufs = {
@@ -682,6 +682,7 @@ WorkSizes work_sizes(int64_t npairs, const Caps& caps) {
       {&Work::terms, sizeof(double) * (size_t)npairs},
       {&Work::live, sizeof(int64_t) * kNumLive},
       {&Work::flops, sizeof(double)},
+      {&Work::lists, sizeof(int) * (size_t)list_ints},
   };
   return w;
 }
@@ -1114,11 +1115,13 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
   P.edges = edge_table(ctx, o);
   P.mask_kind = mask ? mask->d_kind : nullptr;
   const int64_t npairs = (int64_t)P.nrb * P.ncb;
+  const int64_t list_ints = block_list_ints(P.nrb, P.ncb, P.nkb);
   hipError_t e = hipSuccess;
   if (dev) {
-    if (!work_fits(W, work_sizes(npairs, dev->caps)))
+    if (!work_fits(W, work_sizes(npairs, dev->caps, list_ints)))
       return bail(fail(ctx, CLR_ERR_CAPACITY, "workspace smaller than the run's capacities"));
   } else {
+    if (e == hipSuccess) e = ensure(W.lists, sizeof(int) * list_ints);
     if (e == hipSuccess) e = ensure(W.cnt, sizeof(int64_t) * kNumCounters * npairs);
     if (e == hipSuccess) e = ensure(W.off, sizeof(int64_t) * kNumCounters * npairs);
     if (e == hipSuccess) e = ensure(W.st, sizeof(double) * kNumStats * npairs);
@@ -1132,6 +1135,8 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
   int64_t* tot_cnt = as<int64_t>(W.totals);
   double* tot_st = reinterpret_cast<double*>(tot_cnt + kNumCounters);
   if (!dev && e == hipSuccess) e = hipEventRecord(ctx->ev[0], stream);
+  bind_block_lists(P, as<int>(W.lists));
+  if (e == hipSuccess) e = launch_block_lists(P, stream);
   if (e == hipSuccess) e = launch_symbolic(P, as<int64_t>(W.cnt), as<double>(W.st), as<int>(W.flags), stream);
   if (e == hipSuccess) e = launch_scan(as<int64_t>(W.cnt), as<int64_t>(W.off), npairs, kNumCounters, tot_cnt, stream);
   // n[c]: length (eager) or capacity (device-sized) of list c; live: the
@@ -1643,6 +1648,11 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     pb[p + 1] = pb[p] + (int64_t)q.nrb * q.ncb;
   }
   const int64_t tp = pb[np];
+  // every product's block lists (read by its symbolic and fill kernels)
+  std::vector<int64_t> lb(np + 1, 0);
+  for (int p = 0; p < np; ++p) lb[p + 1] = lb[p] + block_list_ints(P[p].nrb, P[p].ncb, P[p].nkb);
+  HIP_TRY(ctx, ensure(ctx->w.lists, sizeof(int) * lb[np]));
+  for (int p = 0; p < np; ++p) bind_block_lists(P[p], as<int>(ctx->w.lists) + lb[p]);
   const size_t tot_bytes = (size_t)np * (sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats);
   HIP_TRY(ctx, ensure(ctx->w.cnt, sizeof(int64_t) * kNumCounters * tp));
   HIP_TRY(ctx, ensure(ctx->w.off, sizeof(int64_t) * kNumCounters * tp));
@@ -1656,6 +1666,7 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     int64_t* cnt = as<int64_t>(ctx->w.cnt) + kNumCounters * pb[p];
     int64_t* off = as<int64_t>(ctx->w.off) + kNumCounters * pb[p];
     double* st = as<double>(ctx->w.st) + kNumStats * pb[p];
+    HIP_TRY(ctx, launch_block_lists(P[p], stream));
     HIP_TRY(ctx, launch_symbolic(P[p], cnt, st, as<int>(ctx->w.flags) + pb[p], stream));
     HIP_TRY(ctx, launch_scan(cnt, off, npairs, kNumCounters, tc + (size_t)p * kNumCounters, stream));
     HIP_TRY(ctx, launch_reduce(st, npairs, kNumStats, ts + (size_t)p * kNumStats, stream));
@@ -2217,7 +2228,7 @@ struct IterGraph {
       run.caps.c[c] = std::max<int64_t>(run.caps.c[c],
                                         (int64_t)std::ceil(m * (double)W.seen.c[c]) + 16);
     const int64_t nb = (int64_t)X->nrb * X->ncb;
-    HIP_TRY(ctx, reserve_work(W, work_sizes(nb, run.caps)));
+    HIP_TRY(ctx, reserve_work(W, work_sizes(nb, run.caps, block_list_ints(X->nrb, X->ncb, X->ncb))));
     HIP_TRY(ctx, launch_fill_i32(reinterpret_cast<int*>(as<int64_t>(W.live)), 0, 2 * kNumLive,
                                  ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -220,7 +220,30 @@ struct PlanParams {
   int square;     // C's row and column blockings are identical
   EdgeTable edges;    // item edges of the dense-accumulation and factor-product launches
   const int* mask_kind;   // optional: only blocks stored in this kind table are computed
+  // nonzero blocks of A's block rows and B's block columns, inner index K
+  // ascending: row I's at a_idx + I * nkb (a_cnt[I] of them), column J's at
+  // b_idx + J * nkb (b_cnt[J]); built by launch_block_lists
+  const int* a_cnt;
+  const int* a_idx;
+  const int* b_cnt;
+  const int* b_idx;
 };
+
+// Ints of the block lists of a product with nrb x nkb and nkb x ncb blockings.
+inline int64_t block_list_ints(int nrb, int ncb, int nkb) {
+  return (int64_t)(nrb + ncb) * (1 + (int64_t)nkb);
+}
+// The lists inside a buffer of block_list_ints ints.
+inline void bind_block_lists(PlanParams& P, int* base) {
+  int* a_cnt = base;
+  int* b_cnt = a_cnt + P.nrb;
+  int* a_idx = b_cnt + P.ncb;
+  int* b_idx = a_idx + (int64_t)P.nrb * P.nkb;
+  P.a_cnt = a_cnt;
+  P.b_cnt = b_cnt;
+  P.a_idx = a_idx;
+  P.b_idx = b_idx;
+}
 
 struct FillParams {
   const int64_t* off;     // [kNumCounters][npairs]
@@ -347,6 +370,9 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
                              int* status, GemmItem* gout, Seg* gseg, int* order, int* cert,
                              RecCounters* ctr, hipStream_t s, hipEvent_t engine_begin = nullptr,
                              hipEvent_t engine_end = nullptr, const int64_t* live = nullptr);
+// Sparse block lists of A's rows and B's columns (the buffers P's list
+// pointers name, bound by bind_block_lists).
+hipError_t launch_block_lists(const PlanParams& P, hipStream_t s);
 hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
                            hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,

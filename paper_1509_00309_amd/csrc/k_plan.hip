@@ -1,8 +1,12 @@
 // Symbolic phase of the CLR product C = alpha A B on the device.
 //
-// k_symbolic: one thread per candidate result block (I, J).  It walks the
-//   inner block index K in ascending order over the pairs where both A_IK
-//   and B_KJ are nonzero, accumulates the norm estimate
+// k_block_lists: the nonzero blocks of every block row of A and block column
+//   of B as lists of inner indices K, ascending (one wave per row or column,
+//   compacted with ballots).
+// k_symbolic: one thread per candidate result block (I, J).  It merges row
+//   I's list with column J's, visiting in ascending K the pairs where both
+//   A_IK and B_KJ are nonzero (work proportional to the two lists, not to the
+//   number of inner blocks), accumulates the norm estimate
 //   est_IJ = |alpha| sum_K ||A_IK||_F ||B_KJ||_F (triangle inequality and
 //   submultiplicativity, Sec. 4.1), applies the screening test est >= tau,
 //   decides dense or factored accumulation, and counts the work and memory
@@ -27,6 +31,65 @@ __device__ inline int64_t dense_parts(const EdgeTable& E, int m, int n) {
   return parts2(m, n, dense_edge(E, m, n));
 }
 
+// Wave w < nrb lists row w of A, wave nrb + J column J of B.
+__global__ __launch_bounds__(256) void k_block_lists(PlanParams P) {
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= P.nrb + P.ncb) return;
+  const bool row = wave < P.nrb;
+  const int r = row ? wave : wave - P.nrb;
+  int* out = row ? (int*)P.a_idx + (int64_t)r * P.nkb : (int*)P.b_idx + (int64_t)r * P.nkb;
+  int n = 0;
+  for (int k0 = 0; k0 < P.nkb; k0 += 64) {
+    const int K = k0 + lane;
+    bool nz = false;
+    if (K < P.nkb) nz = (row ? P.A.kind[(int64_t)r * P.nkb + K] : P.B.kind[(int64_t)K * P.ncb + r]) != 0;
+    const unsigned long long m = __ballot(nz);
+    if (nz) out[n + __popcll(m & ((1ull << lane) - 1ull))] = K;
+    n += __popcll(m);
+  }
+  if (lane == 0) {
+    if (row)
+      ((int*)P.a_cnt)[r] = n;
+    else
+      ((int*)P.b_cnt)[r] = n;
+  }
+}
+
+hipError_t launch_block_lists(const PlanParams& P, hipStream_t s) {
+  const int waves = P.nrb + P.ncb;
+  if (waves == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_lists, dim3((waves + 3) / 4), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+// The inner indices K, ascending, where A_IK and B_KJ are both nonzero:
+// a merge of row I's list with column J's.
+struct PairWalk {
+  const int* a;
+  const int* b;
+  int na, nb, ia = 0, ib = 0;
+  __device__ PairWalk(const PlanParams& P, int I, int J)
+      : a(P.a_idx + (int64_t)I * P.nkb), b(P.b_idx + (int64_t)J * P.nkb), na(P.a_cnt[I]),
+        nb(P.b_cnt[J]) {}
+  // next common K, or -1 when either list is exhausted
+  __device__ int next() {
+    while (ia < na && ib < nb) {
+      const int ka = a[ia], kb = b[ib];
+      if (ka < kb) {
+        ++ia;
+      } else if (kb < ka) {
+        ++ib;
+      } else {
+        ++ia;
+        ++ib;
+        return ka;
+      }
+    }
+    return -1;
+  }
+};
+
 __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __restrict__ st,
                            int* __restrict__ flags) {
   const int npairs = P.nrb * P.ncb;
@@ -41,11 +104,10 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
   bool anydd = false;
   // low-rank contributions that a densified block adds with rank r cost 2 m n r
   int64_t lr_rank_sum = 0;
-  for (int K = 0; K < P.nkb; ++K) {
+  PairWalk walk(P, I, J);
+  for (int K = walk.next(); K >= 0; K = walk.next()) {
     const int ka = P.A.kind[I * P.nkb + K];
-    if (ka == 0) continue;
     const int kb = P.B.kind[K * P.ncb + J];
-    if (kb == 0) continue;
     const int k = P.A.coff[K + 1] - P.A.coff[K];
     est += P.A.norm[I * P.nkb + K] * P.B.norm[K * P.ncb + J];
     ++nseg;
@@ -255,11 +317,10 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   int kb = 0;
   int rcat = 0;
   bool anydd = false;
-  for (int K = 0; K < P.nkb; ++K) {
+  PairWalk walk(P, I, J);
+  for (int K = walk.next(); K >= 0; K = walk.next()) {
     const int ka = P.A.kind[I * P.nkb + K];
-    if (ka == 0) continue;
     const int kbk = P.B.kind[K * P.ncb + J];
-    if (kbk == 0) continue;
     const int k = P.A.coff[K + 1] - P.A.coff[K];
     const double* a = block_at(P.A, I * P.nkb + K);
     const double* b = block_at(P.B, K * P.ncb + J);
