@@ -232,6 +232,20 @@ def run_sqrtinv(ctx, n, forms, log_fn):
             "forms": out}
 
 
+def storage_summary(S, C, n):
+    """Device storage of the input S and of a product C against the dense N^2 doubles: S is
+    packed, C holds the room its blocks were planned with (the most each result can store), and
+    compaction would shrink it to the stored elements."""
+    cap_s, _ = S.arena()
+    cap_c, _ = C.arena()
+    stored_c = C.stored_elements()
+    dense = float(n) * n
+    return {"dense_doubles": int(dense), "input_doubles": int(cap_s),
+            "input_fraction_of_dense": cap_s / dense, "product_room_doubles": int(cap_c),
+            "product_room_fraction_of_dense": cap_c / dense,
+            "product_stored_fraction_of_dense": stored_c / dense}
+
+
 def run_low_rank(ctx, forms, steps, warmup, log_fn, with_oracle=True):
     """The rank-sparse regime: C = S*S at N = 8192 on Morton-ordered compact clusters of the
     3D Gaussian lattice and on a Coulomb-like 1/sqrt(r^2 + 1) kernel (tol 1e-6)."""
@@ -251,6 +265,8 @@ def run_low_rank(ctx, forms, steps, warmup, log_fn, with_oracle=True):
         for form in forms:
             _C, wall, stats = run_form(ctx, S, wl, form, steps, warmup)
             err = sampled_error(sample, _C.to_dense().cpu().numpy(), wl.offsets()) if sample else None
+            if "storage" not in res:
+                res["storage"] = storage_summary(S, _C, wl.n)
             del _C
             sm = summarize(stats, wall, form)
             res["forms"][form] = {k: sm[k] for k in ("tflops", "ms_per_step", "phase_ms",
@@ -466,8 +482,11 @@ def run_sqrtinv_scale(ctx, n, nclusters, forms, log_fn):
            f"{int(np.sum(kind != 0))} nonzero blocks of {kind.size}, {int(np.sum(kind == 2))} low rank")
     conv = wl.extra["conv_tol"]
     # a warm-up product of the same size per form (kernel code objects, workspace)
+    storage = None
     for prec in ("fp64", "mixed"):
         C = ctx.gemm(S, S, wl.tol, wl.eps_sp, precision=prec)
+        if storage is None:
+            storage = storage_summary(S, C, wl.n)
         del C
     torch.cuda.synchronize()
     out = {}
@@ -506,7 +525,7 @@ def run_sqrtinv_scale(ctx, n, nclusters, forms, log_fn):
     return {"workload": f"S^-1/2, N={n} 3D lattice (spacing 1.2, jitter 0.3) overlap-like "
                         f"exp(-0.2 r^2)+0.05 delta, {nclusters} clusters 128+-U{{-32..32}}, "
                         f"tol {wl.tol:g}, screen 1e-10, conv 1e-8; input generated on the device",
-            "forms": out}
+            "storage": storage, "forms": out}
 
 
 def run_adjoint(ctx, forms, log_fn):
@@ -725,6 +744,8 @@ def main():
 
     base = "fp64" if "fp64" in forms else next(iter(forms))
     fb = forms[base]
+    storage = storage_summary(S, results[base], wl.n)
+    log(f"storage: {storage}")
     dense_equiv = 2.0 * wl.n ** 3 / (fb["ms_per_step"] * 1e-3) / 1e12
 
     cpu = None
@@ -828,6 +849,7 @@ def main():
         },
         "dense_equivalent_tflops": dense_equiv,
         "forms": forms,
+        "storage": storage,
         "error_vs_oracle_sampled": err_oracle,
         "measured_peaks": peaks,
         "sqrt_inv_scale": scale,

@@ -290,13 +290,32 @@ __device__ inline Seg make_seg(const double* L, int64_t sLi, int64_t sLk, const 
   return s;
 }
 
-__global__ void k_fill(PlanParams P, FillParams F) {
+// Inclusive sum over the lanes 0..lane of the wave.
+template <typename T>
+__device__ inline T wave_incl_scan(T v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// One wave per result block.  The lanes take the candidate terms of a chunk
+// of 64 entries of A's row list (a term where B_KJ is nonzero too), so the
+// terms of a chunk are the set bits of a ballot in ascending K; every list
+// offset (terms, factor-product items, pool doubles, inner ranges) is an
+// exclusive prefix sum over the terms before, plus the running totals of the
+// earlier chunks: the lists are the ones a walk term by term would write.
+constexpr int kFillThreads = 256;
+__global__ __launch_bounds__(kFillThreads) void k_fill(PlanParams P, FillParams F) {
   const int npairs = P.nrb * P.ncb;
-  const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int pair = (int)((blockIdx.x * (unsigned)kFillThreads + threadIdx.x) >> 6);
   if (pair >= npairs) return;
   if (F.abort && *F.abort) return;   // a list would overflow its capacity
   // every block's offset (a zero block's is never read)
-  F.c_boff[pair] = F.off[(int64_t)kCntOut * npairs + pair];
+  if (lane == 0) F.c_boff[pair] = F.off[(int64_t)kCntOut * npairs + pair];
   const int fl = F.flags[pair];
   if (!(fl & kFlagComputed)) return;
   const bool densify = fl & kFlagDensify;
@@ -305,6 +324,7 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   const int m = P.A.roff[I + 1] - P.A.roff[I];
   const int n = P.B.coff[J + 1] - P.B.coff[J];
   auto off = [&](int c) { return F.off[(int64_t)c * npairs + pair]; };
+  // running totals of the earlier chunks (uniform in the wave)
   int64_t po = off(kCntPool);
   int64_t so = off(kCntSegDense);
   const int64_t so0 = so;
@@ -317,78 +337,130 @@ __global__ void k_fill(PlanParams P, FillParams F) {
   int kb = 0;
   int rcat = 0;
   bool anydd = false;
-  PairWalk walk(P, I, J);
-  for (int K = walk.next(); K >= 0; K = walk.next()) {
-    const int ka = P.A.kind[I * P.nkb + K];
-    const int kbk = P.B.kind[K * P.ncb + J];
-    const int k = P.A.coff[K + 1] - P.A.coff[K];
-    const double* a = block_at(P.A, I * P.nkb + K);
-    const double* b = block_at(P.B, K * P.ncb + J);
-    Seg dense_term;
-    Piece pc;
-    pc.pad = 0;
-    pc.scale = P.alpha;
-    if (ka == 1 && kbk == 1) {
-      anydd = true;
-      dense_term = make_seg(a, 1, m, b, 1, k, k, 1.0);
-    } else if (ka == 2 && kbk == 1) {
-      // LD: U_A (B^T V_A)^T; T = B^T V_A is n x rA
-      const int ra = P.A.rank[I * P.nkb + K];
-      const double* Ua = a;
-      const double* Va = a + (int64_t)m * ra;
-      double* T = F.pool + po;
-      po += (int64_t)n * ra;
-      emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(b, k, 1, Va, 1, k, k, 1.0), T, n, n, ra,
-                P.edges);
-      dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
-      pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
-    } else if (ka == 1 && kbk == 2) {
-      // DL: (A U_B) V_B^T; T = A U_B is m x rB
-      const int rb = P.B.rank[K * P.ncb + J];
-      const double* Ub = b;
-      const double* Vb = b + (int64_t)k * rb;
-      double* T = F.pool + po;
-      po += (int64_t)m * rb;
-      emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(a, 1, m, Ub, 1, k, k, 1.0), T, m, m, rb,
-                P.edges);
-      dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
-      pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
-    } else {
-      // LL: core Z = V_A^T U_B (rA x rB), absorbed on the side giving the smaller rank (Eq. (4))
-      const int ra = P.A.rank[I * P.nkb + K];
-      const int rb = P.B.rank[K * P.ncb + J];
-      const double* Ua = a;
-      const double* Va = a + (int64_t)m * ra;
-      const double* Ub = b;
-      const double* Vb = b + (int64_t)k * rb;
-      double* Z = F.pool + po;
-      po += (int64_t)ra * rb;
-      emit_thin(F.seg_thin1, F.items_thin1, t1, make_seg(Va, k, 1, Ub, 1, k, k, 1.0), Z, ra, ra,
-                rb, P.edges);
-      double* T = F.pool + po;
-      if (rb < ra) {
-        po += (int64_t)m * rb;   // T = U_A Z (m x rB)
-        emit_thin(F.seg_thin2, F.items_thin2, t2, make_seg(Ua, 1, m, Z, 1, ra, ra, 1.0), T, m, m,
+  const int* arow = P.a_idx + (int64_t)I * P.nkb;
+  const int na = P.a_cnt[I];
+  for (int c0 = 0; c0 < na; c0 += 64) {
+    const int K = c0 + lane < na ? arow[c0 + lane] : -1;
+    const int ka = K >= 0 ? P.A.kind[I * P.nkb + K] : 0;
+    const int kbk = K >= 0 ? P.B.kind[K * P.ncb + J] : 0;
+    const bool term = ka != 0 && kbk != 0;
+    // this lane's term: its counts
+    int k = 0, ra = 0, rb = 0, rk = 0;   // rk: rank (inner extent) of the term's dense form
+    int64_t npool = 0, nt1 = 0, nt2 = 0;
+    if (term) {
+      k = P.A.coff[K + 1] - P.A.coff[K];
+      ra = ka == 2 ? P.A.rank[I * P.nkb + K] : 0;
+      rb = kbk == 2 ? P.B.rank[K * P.ncb + J] : 0;
+      if (ka == 1 && kbk == 1) {
+        rk = k;
+      } else if (ka == 2 && kbk == 1) {
+        rk = ra;
+        npool = (int64_t)n * ra;
+        nt1 = thin_parts(P.edges, n, ra);
+      } else if (ka == 1 && kbk == 2) {
+        rk = rb;
+        npool = (int64_t)m * rb;
+        nt1 = thin_parts(P.edges, m, rb);
+      } else {
+        nt1 = thin_parts(P.edges, ra, rb);
+        if (rb < ra) {
+          rk = rb;
+          npool = (int64_t)ra * rb + (int64_t)m * rb;
+          nt2 = thin_parts(P.edges, m, rb);
+        } else {
+          rk = ra;
+          npool = (int64_t)ra * rb + (int64_t)n * ra;
+          nt2 = thin_parts(P.edges, n, ra);
+        }
+      }
+    }
+    const int one = term ? 1 : 0;
+    // exclusive prefixes over the chunk's terms
+    const int64_t xpool = wave_incl_scan<long long>(npool, lane) - npool;
+    const int64_t xt1 = wave_incl_scan<long long>(nt1, lane) - nt1;
+    const int64_t xt2 = wave_incl_scan<long long>(nt2, lane) - nt2;
+    const int xone = wave_incl_scan<int>(one, lane) - one;
+    const int xrk = wave_incl_scan<int>(term ? rk : 0, lane) - (term ? rk : 0);
+    if (term) {
+      const double* a = block_at(P.A, I * P.nkb + K);
+      const double* b = block_at(P.B, K * P.ncb + J);
+      int64_t my_po = po + xpool;
+      int64_t my_t1 = t1 + xt1;
+      int64_t my_t2 = t2 + xt2;
+      Seg dense_term;
+      Piece pc;
+      pc.pad = 0;
+      pc.scale = P.alpha;
+      if (ka == 1 && kbk == 1) {
+        dense_term = make_seg(a, 1, m, b, 1, k, k, 1.0);
+      } else if (ka == 2 && kbk == 1) {
+        // LD: U_A (B^T V_A)^T; T = B^T V_A is n x rA
+        const double* Ua = a;
+        const double* Va = a + (int64_t)m * ra;
+        double* T = F.pool + my_po;
+        emit_thin(F.seg_thin1, F.items_thin1, my_t1, make_seg(b, k, 1, Va, 1, k, k, 1.0), T, n, n,
+                  ra, P.edges);
+        dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
+        pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
+      } else if (ka == 1 && kbk == 2) {
+        // DL: (A U_B) V_B^T; T = A U_B is m x rB
+        const double* Ub = b;
+        const double* Vb = b + (int64_t)k * rb;
+        double* T = F.pool + my_po;
+        emit_thin(F.seg_thin1, F.items_thin1, my_t1, make_seg(a, 1, m, Ub, 1, k, k, 1.0), T, m, m,
                   rb, P.edges);
         dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
         pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
       } else {
-        po += (int64_t)n * ra;   // T = V_B Z^T (n x rA)
-        emit_thin(F.seg_thin2, F.items_thin2, t2, make_seg(Vb, 1, n, Z, ra, 1, rb, 1.0), T, n, n,
-                  ra, P.edges);
-        dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
-        pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
+        // LL: core Z = V_A^T U_B (rA x rB), absorbed on the side giving the smaller rank (Eq. (4))
+        const double* Ua = a;
+        const double* Va = a + (int64_t)m * ra;
+        const double* Ub = b;
+        const double* Vb = b + (int64_t)k * rb;
+        double* Z = F.pool + my_po;
+        emit_thin(F.seg_thin1, F.items_thin1, my_t1, make_seg(Va, k, 1, Ub, 1, k, k, 1.0), Z, ra,
+                  ra, rb, P.edges);
+        double* T = Z + (int64_t)ra * rb;
+        if (rb < ra) {
+          // T = U_A Z (m x rB)
+          emit_thin(F.seg_thin2, F.items_thin2, my_t2, make_seg(Ua, 1, m, Z, 1, ra, ra, 1.0), T, m,
+                    m, rb, P.edges);
+          dense_term = make_seg(T, 1, m, Vb, n, 1, rb, 1.0);
+          pc.U = T; pc.ldu = m; pc.V = Vb; pc.ldv = n; pc.r = rb;
+        } else {
+          // T = V_B Z^T (n x rA)
+          emit_thin(F.seg_thin2, F.items_thin2, my_t2, make_seg(Vb, 1, n, Z, ra, 1, rb, 1.0), T, n,
+                    n, ra, P.edges);
+          dense_term = make_seg(Ua, 1, m, T, n, 1, ra, 1.0);
+          pc.U = Ua; pc.ldu = m; pc.V = T; pc.ldv = n; pc.r = ra;
+        }
+      }
+      if (densify) {
+        dense_term.kbase = kb + xrk;
+        F.seg_dense[so + xone] = dense_term;
+      } else {
+        F.pieces[pi + xone] = pc;
       }
     }
+    // advance the running totals by the chunk's sums (read from the last lane)
+    const int64_t spool = __shfl(xpool + npool, 63, 64);
+    const int64_t st1 = __shfl(xt1 + nt1, 63, 64);
+    const int64_t st2 = __shfl(xt2 + nt2, 63, 64);
+    const int sone = __shfl(xone + one, 63, 64);
+    const int srk = __shfl(xrk + (term ? rk : 0), 63, 64);
+    po += spool;
+    t1 += st1;
+    t2 += st2;
     if (densify) {
-      dense_term.kbase = kb;
-      kb += dense_term.k;
-      F.seg_dense[so++] = dense_term;
+      so += sone;
+      kb += srk;
     } else {
-      rcat += pc.r;
-      F.pieces[pi++] = pc;
+      pi += sone;
+      rcat += srk;
     }
+    anydd = anydd || __ballot(term && ka == 1 && kbk == 1) != 0ull;
   }
+  if (lane != 0) return;
   const double tau = P.screen ? P.eps_sp * m * (double)n : P.eps_sp;
   if (densify) {
     int64_t gi = off(kCntGemmItems);
@@ -687,7 +759,8 @@ hipError_t launch_comb_fill(const CombParams& P, const CombLists& L, hipStream_t
 hipError_t launch_fill(const PlanParams& P, const FillParams& F, hipStream_t s) {
   const int npairs = P.nrb * P.ncb;
   if (npairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill, dim3((npairs + 255) / 256), dim3(256), 0, s, P, F);
+  constexpr int per = kFillThreads / 64;   // result blocks (waves) per workgroup
+  hipLaunchKernelGGL(k_fill, dim3((npairs + per - 1) / per), dim3(kFillThreads), 0, s, P, F);
   return hipGetLastError();
 }
 
