@@ -434,6 +434,21 @@ hipError_t run_ggemm(const clr_gemm_opts* o, const GemmItem* items, const Seg* s
   return launch_ggemm_f64(items, segs, n, s, dense, order, live);
 }
 
+// The dense accumulation of a product: the longest-first list `order` (n
+// slots, followed by one int of room for the counter) on a persistent launch
+// of the LDS kernel (the INT8 form keeps its own launch).
+hipError_t run_dense(const clr_gemm_opts* o, const GemmItem* items, const Seg* segs, int n,
+                     int* order, hipStream_t s, const int64_t* live) {
+  if (n <= 0) return hipSuccess;
+  if (o->precision == CLR_OZAKI) return run_ggemm(o, items, segs, n, s, true, order, live);
+  int* next = order + n;
+  hipError_t e = launch_fill_i32(next, 0, 1, s);
+  if (e != hipSuccess) return e;
+  if (o->precision == CLR_MIXED)
+    return launch_ggemm_f32(items, segs, n, o->split, s, true, order, live, next);
+  return launch_ggemm_f64(items, segs, n, s, true, order, live, next);
+}
+
 int max_item(const clr_gemm_opts* o) {
   if (o->precision == CLR_OZAKI) return kMaxItemOzaki;
   if (o->precision == CLR_MIXED) return o->split ? kMaxItemF32Split : kMaxItemF32;
@@ -666,7 +681,7 @@ WorkSizes work_sizes(int64_t npairs, const Caps& caps, int64_t list_ints = 0) {
       {&Work::totals, sizeof(int64_t) * kNumCounters + sizeof(double) * kNumStats},
       {&Work::seg_dense, sizeof(Seg) * n(kCntSegDense)},
       {&Work::items_dense, sizeof(GemmItem) * n(kCntGemmItems)},
-      {&Work::order, sizeof(int) * n(kCntGemmItems)},
+      {&Work::order, sizeof(int) * (n(kCntGemmItems) + 1)},   // list and the persistent counter
       {&Work::order_thin, sizeof(int) * n(kCntThin1)},
       {&Work::seg_thin1, sizeof(Seg) * n(kCntThin1)},
       {&Work::items_thin1, sizeof(GemmItem) * n(kCntThin1)},
@@ -1233,8 +1248,8 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
     e = run_wgemm(o, F.items_thin2, F.seg_thin2, (int)n[kCntThin2], stream, nullptr, lv(kCntThin2));
   if (e == hipSuccess && !dev) e = hipEventRecord(ctx->ev[6], stream);
   if (e == hipSuccess)
-    e = run_ggemm(o, F.items_dense, F.seg_dense, (int)n[kCntGemmItems], stream, true,
-                  as<int>(W.order), lv(kCntGemmItems));
+    e = run_dense(o, F.items_dense, F.seg_dense, (int)n[kCntGemmItems], as<int>(W.order), stream,
+                  lv(kCntGemmItems));
   if (e == hipSuccess && !dev) e = hipEventRecord(ctx->ev[2], stream);
   if (e == hipSuccess)
     e = launch_recompress_work(ctx, W, F.rec, F.pieces, (int)n[kCntComputed], o->tol,
@@ -1596,8 +1611,8 @@ hipError_t plan_launch(clr_plan* pl, hipStream_t s) {
   if (e == hipSuccess)
     e = run_wgemm(o, as<GemmItem>(pl->items_thin2), as<Seg>(pl->seg_thin2), (int)pl->n_thin2, s);
   if (e == hipSuccess)
-    e = run_ggemm(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense, s, true,
-                  as<int>(pl->order));
+    e = run_dense(o, as<GemmItem>(pl->items_dense), as<Seg>(pl->seg_dense), (int)pl->n_dense,
+                  as<int>(pl->order), s, nullptr);
   if (e == hipSuccess && pl->n_rec > 0) {
     const RecWork w = rec_work(pl->recg.p, pl->n_rec);
     e = launch_recompress(as<RecItem>(pl->rec), as<Piece>(pl->pieces), (int)pl->n_rec, o->tol,
@@ -1706,7 +1721,7 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = ensure(pl->seg_dense, sizeof(Seg) * sum[kCntSegDense]);
   if (e == hipSuccess) e = ensure(pl->items_dense, sizeof(GemmItem) * sum[kCntGemmItems]);
-  if (e == hipSuccess) e = ensure(pl->order, sizeof(int) * sum[kCntGemmItems]);
+  if (e == hipSuccess) e = ensure(pl->order, sizeof(int) * (sum[kCntGemmItems] + 1));
   if (e == hipSuccess) e = ensure(pl->seg_thin1, sizeof(Seg) * sum[kCntThin1]);
   if (e == hipSuccess) e = ensure(pl->items_thin1, sizeof(GemmItem) * sum[kCntThin1]);
   if (e == hipSuccess) e = ensure(pl->seg_thin2, sizeof(Seg) * sum[kCntThin2]);

@@ -316,9 +316,11 @@ struct CombLists {
 // from launch_item_order; null keeps the XCD-blocked order.
 // live: optional device-resident item count; the launch covers nitems
 // items (its capacity) and the kernels stop at min(nitems, *live).
+// next: optional device counter, zero at launch: the LDS kernel runs
+// persistent (one workgroup per CU taking list slots from it).
 hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
                             bool dense = false, const int* order = nullptr,
-                            const int64_t* live = nullptr);
+                            const int64_t* live = nullptr, int* next = nullptr);
 hipError_t launch_wgemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
                             const int* order = nullptr, const int64_t* live = nullptr);
 hipError_t launch_wgemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
@@ -327,7 +329,9 @@ hipError_t launch_wgemm_f32(const GemmItem* items, const Seg* segs, int nitems, 
 constexpr int kMaxItemThin = 64;   // largest edge of a wave-per-item (thin) GEMM item
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
                             hipStream_t s, bool dense = false, const int* order = nullptr,
-                            const int64_t* live = nullptr);
+                            const int64_t* live = nullptr, int* next = nullptr);
+// Workgroups of a persistent LDS-kernel launch over nitems items: one per CU.
+int persistent_grid(int nitems);
 // Items of the LDS grouped GEMM by decreasing estimated cost (slabs times the
 // busiest wave's tiles, in quarter-octave classes) into order[0 .. nitems).
 hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s,

@@ -492,33 +492,13 @@ __device__ __attribute__((always_inline)) inline void run_nb(GemmLds<F32, SPLIT>
   }
 }
 
-// DENSE only names the instantiation: the dense-accumulation launch of a
-// product gets its own kernel symbol, so profiles separate it from the other
-// launches that share the code.
-template <bool F32, bool SPLIT, bool DENSE>
-__global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
-                                                              const Seg* __restrict__ segs,
-                                                              int nitems,
-                                                              const int* __restrict__ order,
-                                                              const int64_t* __restrict__ live) {
+// One item of the LDS kernel, start to finish (every thread of the workgroup).
+template <bool F32, bool SPLIT>
+__device__ __attribute__((always_inline)) inline void ggemm_item(GemmLds<F32, SPLIT>& sh,
+                                                                  const GemmItem* __restrict__ items,
+                                                                  const Seg* __restrict__ segs,
+                                                                  int item) {
   using CF = GemmCfg<F32, SPLIT>;
-  __shared__ GemmLds<F32, SPLIT> sh;
-  // a device-resident count (captured launches) caps the grid's capacity
-  if (live) nitems = uni((int)min((int64_t)nitems, *live));
-
-  // With an order (items by decreasing cost), workgroup b runs item order[b]:
-  // the dispatcher deals workgroups to the 8 XCDs round-robin, so the long
-  // items start first on every XCD and the short ones fill the tail.
-  // Without one, the XCD-aware order: consecutive items (tiles of one block
-  // row) share an XCD's L2.
-  int item;
-  if (order) {
-    if ((int)blockIdx.x >= nitems) return;
-    item = order[blockIdx.x];
-  } else {
-    item = xcd_unit(nitems, live != nullptr);
-    if (item < 0 || item >= nitems) return;
-  }
   // Item fields are the same for every lane; readfirstlane lets the compiler
   // keep them (and all control flow derived from them) in scalar registers.
   GemmItem it = items[item];
@@ -556,6 +536,53 @@ __global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __
     case 4: run_nb<F32, SPLIT, 4>(sh, it, segs, wr, wc, nb); break;
     default: run_nb<F32, SPLIT, CF::TA>(sh, it, segs, wr, wc, nb); break;
   }
+}
+
+// DENSE only names the instantiation: the dense-accumulation launch of a
+// product gets its own kernel symbol, so profiles separate it from the other
+// launches that share the code.
+//
+// With `next` (a device counter, zero at launch), the launch is persistent:
+// one workgroup per CU takes list slots from the counter until the list is
+// exhausted, so the items of the longest-first order go to whichever CU of
+// whichever XCD frees up first (list scheduling, no static XCD deal).
+template <bool F32, bool SPLIT, bool DENSE>
+__global__ __launch_bounds__(kLdsGemmThreads, 1) void k_ggemm(const GemmItem* __restrict__ items,
+                                                              const Seg* __restrict__ segs,
+                                                              int nitems,
+                                                              const int* __restrict__ order,
+                                                              const int64_t* __restrict__ live,
+                                                              int* __restrict__ next) {
+  __shared__ GemmLds<F32, SPLIT> sh;
+  __shared__ int slot_sh;
+  // a device-resident count (captured launches) caps the grid's capacity
+  if (live) nitems = uni((int)min((int64_t)nitems, *live));
+
+  if (next) {
+    for (;;) {
+      if (threadIdx.x == 0) slot_sh = atomicAdd(next, 1);
+      __syncthreads();
+      const int slot = uni(slot_sh);
+      if (slot >= nitems) return;   // the same value in every thread
+      ggemm_item<F32, SPLIT>(sh, items, segs, order ? order[slot] : slot);
+      __syncthreads();   // LDS and slot_sh free for the next item
+    }
+  }
+
+  // With an order (items by decreasing cost), workgroup b runs item order[b]:
+  // the dispatcher deals workgroups to the 8 XCDs round-robin, so the long
+  // items start first on every XCD and the short ones fill the tail.
+  // Without one, the XCD-aware order: consecutive items (tiles of one block
+  // row) share an XCD's L2.
+  int item;
+  if (order) {
+    if ((int)blockIdx.x >= nitems) return;
+    item = order[blockIdx.x];
+  } else {
+    item = xcd_unit(nitems, live != nullptr);
+    if (item < 0 || item >= nitems) return;
+  }
+  ggemm_item<F32, SPLIT>(sh, items, segs, item);
 }
 
 static inline int xcd_grid(int n) { return ((n + 7) / 8) * 8; }

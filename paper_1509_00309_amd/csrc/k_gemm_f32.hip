@@ -5,17 +5,22 @@
 namespace clr {
 
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
-                            hipStream_t s, bool dense, const int* order, const int64_t* live) {
+                            hipStream_t s, bool dense, const int* order, const int64_t* live,
+                            int* next) {
   if (nitems <= 0) return hipSuccess;
-  const dim3 grid(xcd_grid(nitems)), block(kLdsGemmThreads);
+  const dim3 grid(next ? persistent_grid(nitems) : xcd_grid(nitems)), block(kLdsGemmThreads);
   if (split && dense)
-    hipLaunchKernelGGL((k_ggemm<true, true, true>), grid, block, 0, s, items, segs, nitems, order, live);
+    hipLaunchKernelGGL((k_ggemm<true, true, true>), grid, block, 0, s, items, segs, nitems, order,
+                       live, next);
   else if (split)
-    hipLaunchKernelGGL((k_ggemm<true, true, false>), grid, block, 0, s, items, segs, nitems, order, live);
+    hipLaunchKernelGGL((k_ggemm<true, true, false>), grid, block, 0, s, items, segs, nitems, order,
+                       live, next);
   else if (dense)
-    hipLaunchKernelGGL((k_ggemm<true, false, true>), grid, block, 0, s, items, segs, nitems, order, live);
+    hipLaunchKernelGGL((k_ggemm<true, false, true>), grid, block, 0, s, items, segs, nitems, order,
+                       live, next);
   else
-    hipLaunchKernelGGL((k_ggemm<true, false, false>), grid, block, 0, s, items, segs, nitems, order, live);
+    hipLaunchKernelGGL((k_ggemm<true, false, false>), grid, block, 0, s, items, segs, nitems, order,
+                       live, next);
   return hipGetLastError();
 }
 

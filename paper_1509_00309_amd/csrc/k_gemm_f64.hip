@@ -3,15 +3,29 @@
 
 namespace clr {
 
+int persistent_grid(int nitems) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return nitems < cus ? nitems : cus;
+}
+
 hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
-                            bool dense, const int* order, const int64_t* live) {
+                            bool dense, const int* order, const int64_t* live, int* next) {
   if (nitems <= 0) return hipSuccess;
+  const dim3 grid(next ? persistent_grid(nitems) : xcd_grid(nitems));
   if (dense)
-    hipLaunchKernelGGL((k_ggemm<false, false, true>), dim3(xcd_grid(nitems)),
-                       dim3(kLdsGemmThreads), 0, s, items, segs, nitems, order, live);
+    hipLaunchKernelGGL((k_ggemm<false, false, true>), grid, dim3(kLdsGemmThreads), 0, s, items,
+                       segs, nitems, order, live, next);
   else
-    hipLaunchKernelGGL((k_ggemm<false, false, false>), dim3(xcd_grid(nitems)),
-                       dim3(kLdsGemmThreads), 0, s, items, segs, nitems, order, live);
+    hipLaunchKernelGGL((k_ggemm<false, false, false>), grid, dim3(kLdsGemmThreads), 0, s, items,
+                       segs, nitems, order, live, next);
   return hipGetLastError();
 }
 
