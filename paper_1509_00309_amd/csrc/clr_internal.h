@@ -365,8 +365,10 @@ struct RecCounters {
   double flops_bidiag;              // 4 p q^2 - 4 q^3 / 3 per block the register engine reduces
   unsigned long long certified;     // blocks proved dense without an SVD
 };
-// order: workspace of nitems ints; when given, the register engine runs its
-// blocks in decreasing order of estimated cost (null: XCD-blocked order).
+// order: workspace of nitems + 1 ints; when given, the register engine runs
+// its blocks in decreasing order of estimated cost, persistent (one workgroup
+// per CU taking list slots from the counter in the last int); null: one
+// workgroup per block in the XCD-blocked order.
 // cert: workspace of nitems ints; when given, dense-path blocks are first
 // tested by the dense certificate and the proved ones are copied out without
 // an SVD.  ctr (optional) receives the launch's counters.

@@ -2026,6 +2026,9 @@ __global__ __launch_bounds__(1024) void k_rec_order(const RecItem* __restrict__ 
     order[atomicAdd(&cnt[rec_cost_class(items[i], tol, cert != nullptr && cert[i] != 0)], 1)] = i;
 }
 
+// With `next` (a counter, zero at launch) the launch is persistent: one
+// workgroup per CU takes the slots of the longest-first order from it, so a
+// long block goes to whichever CU frees first.
 __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* __restrict__ items,
                                                                 int nitems, double tol,
                                                                 int* status, GemmItem* gout,
@@ -2033,23 +2036,42 @@ __global__ __launch_bounds__(kRecThreads) void k_recompress_reg(const RecItem* _
                                                                 const int* __restrict__ order,
                                                                 const int* __restrict__ cert,
                                                                 double* flops_bidiag,
-                                                                const int64_t* __restrict__ live) {
+                                                                const int64_t* __restrict__ live,
+                                                                int* __restrict__ next) {
   extern __shared__ double lds[];
   __shared__ RecShared sh;
+  __shared__ int slot_sh;
   if (live) nitems = (int)min((int64_t)nitems, *live);
-  int item;
-  if (order) {
-    if ((int)blockIdx.x >= nitems) return;
-    item = order[blockIdx.x];
-  } else {
-    item = xcd_unit(nitems, live != nullptr);
-    if (item < 0 || item >= nitems) return;
+  auto run = [&](int item) {
+    const RecItem it = items[item];
+    if (!register_item(it, tol)) return;
+    if (!item_guard(it, tol, status)) return;
+    dense_path<true>(it, tol, lds, status, sh, cert != nullptr && cert[item] != 0, gout, gseg, item,
+                     flops_bidiag);
+  };
+  // one call site of the block body (it is inlined): persistent slots, or the
+  // workgroup's own block once
+  for (bool first = true;; first = false) {
+    int item;
+    if (next) {
+      if (!first) __syncthreads();   // LDS and slot_sh free for the next block
+      if (threadIdx.x == 0) slot_sh = atomicAdd(next, 1);
+      __syncthreads();
+      const int slot = __builtin_amdgcn_readfirstlane(slot_sh);
+      if (slot >= nitems) return;   // the same value in every thread
+      item = order[slot];
+    } else {
+      if (!first) return;
+      if (order) {
+        if ((int)blockIdx.x >= nitems) return;
+        item = order[blockIdx.x];
+      } else {
+        item = xcd_unit(nitems, live != nullptr);
+        if (item < 0 || item >= nitems) return;
+      }
+    }
+    run(item);
   }
-  const RecItem it = items[item];
-  if (!register_item(it, tol)) return;
-  if (!item_guard(it, tol, status)) return;
-  dense_path<true>(it, tol, lds, status, sh, cert != nullptr && cert[item] != 0, gout, gseg, item,
-                   flops_bidiag);
 }
 
 // Dynamic-LDS limits of the recompression kernels; done once, before any
@@ -2103,9 +2125,15 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
     e = hipEventRecord(engine_begin, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_recompress_reg, dim3(grid), dim3(kRecThreads), kRecLdsBytes, s, items,
-                     nitems, tol, status, gout, gseg, order, cert,
-                     ctr ? &ctr->flops_bidiag : nullptr, live);
+  // with an order, persistent: one workgroup per CU over the list (counter after it)
+  int* next = order ? order + nitems : nullptr;
+  if (next) {
+    e = launch_fill_i32(next, 0, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_recompress_reg, dim3(next ? persistent_grid(nitems) : grid), dim3(kRecThreads),
+                     kRecLdsBytes, s, items, nitems, tol, status, gout, gseg, order, cert,
+                     ctr ? &ctr->flops_bidiag : nullptr, live, next);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (engine_end) {
