@@ -619,7 +619,7 @@ inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 size_t rec_work_bytes(int64_t nitems) {
   const size_t n = (size_t)std::max<int64_t>(nitems, 1);
   return align256(sizeof(GemmItem) * n) + align256(sizeof(Seg) * n) +
-         align256(sizeof(int) * (n + 1)) + align256(sizeof(int) * n) + sizeof(RecCounters);
+         align256(sizeof(int) * (n + 1)) + align256(sizeof(int) * (n + 3)) + sizeof(RecCounters);
 }
 RecWork rec_work(void* base, int64_t nitems) {
   const size_t n = (size_t)std::max<int64_t>(nitems, 1);
@@ -631,8 +631,8 @@ RecWork rec_work(void* base, int64_t nitems) {
   p += align256(sizeof(Seg) * n);
   w.order = reinterpret_cast<int*>(p);   // the launch order and the persistent counter
   p += align256(sizeof(int) * (n + 1));
-  w.cert = reinterpret_cast<int*>(p);
-  p += align256(sizeof(int) * n);
+  w.cert = reinterpret_cast<int*>(p);   // the proofs and three persistent counters
+  p += align256(sizeof(int) * (n + 3));
   w.ctr = reinterpret_cast<RecCounters*>(p);
   return w;
 }

@@ -330,8 +330,8 @@ constexpr int kMaxItemThin = 64;   // largest edge of a wave-per-item (thin) GEM
 hipError_t launch_ggemm_f32(const GemmItem* items, const Seg* segs, int nitems, int split,
                             hipStream_t s, bool dense = false, const int* order = nullptr,
                             const int64_t* live = nullptr, int* next = nullptr);
-// Workgroups of a persistent LDS-kernel launch over nitems items: one per CU.
-int persistent_grid(int nitems);
+// Workgroups of a persistent launch over nitems items: per_cu per CU.
+int persistent_grid(int nitems, int per_cu = 1);
 // Items of the LDS grouped GEMM by decreasing estimated cost (slabs times the
 // busiest wave's tiles, in quarter-octave classes) into order[0 .. nitems).
 hipError_t launch_item_order(const GemmItem* items, int nitems, int* order, hipStream_t s,
@@ -369,9 +369,9 @@ struct RecCounters {
 // its blocks in decreasing order of estimated cost, persistent (one workgroup
 // per CU taking list slots from the counter in the last int); null: one
 // workgroup per block in the XCD-blocked order.
-// cert: workspace of nitems ints; when given, dense-path blocks are first
-// tested by the dense certificate and the proved ones are copied out without
-// an SVD.  ctr (optional) receives the launch's counters.
+// cert: workspace of nitems + 3 ints; when given, dense-path blocks are
+// first tested by the dense certificate (persistent launches, their counters
+// in the last three ints) and the proved ones are copied out without an SVD.  ctr (optional) receives the launch's counters.
 hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nitems, double tol,
                              int* status, GemmItem* gout, Seg* gseg, int* order, int* cert,
                              RecCounters* ctr, hipStream_t s, hipEvent_t engine_begin = nullptr,

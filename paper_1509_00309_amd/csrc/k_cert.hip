@@ -352,24 +352,44 @@ __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& 
 // Size class (qlo, qhi] of the short edge: WR x WC waves of TU x TW tiles of
 // 16 x 16 holding the Gram matrix of min(q, 160) columns; four waves per SIMD
 // (two 512-thread or one 1024-thread workgroup per CU).
+// Item of the next iteration of a certificate kernel: with `next` (a counter,
+// zero at launch) the launch is persistent and its workgroups take the items
+// in index order from it; otherwise every workgroup takes its own item once.
+// -1: nothing left.  Uniform in the workgroup.
+__device__ inline int cert_next(int* next, int* slot_sh, bool first, int nitems, bool live) {
+  if (next) {
+    if (!first) __syncthreads();   // slot_sh and the LDS of the last item free
+    if (threadIdx.x == 0) *slot_sh = atomicAdd(next, 1);
+    __syncthreads();
+    const int slot = __builtin_amdgcn_readfirstlane(*slot_sh);
+    return slot < nitems ? slot : -1;
+  }
+  if (!first) return -1;
+  const int item = xcd_unit(nitems, live);
+  return item >= 0 && item < nitems ? item : -1;
+}
+
 template <int WR, int WC, int TU, int TW>
 __global__ __launch_bounds__(64 * WR * WC, 4) void k_dense_cert(
     const RecItem* __restrict__ items, int nitems, double tol, int qlo, int qhi,
     int* __restrict__ cert, unsigned long long* __restrict__ count,
-    const int64_t* __restrict__ live) {
+    const int64_t* __restrict__ live, int* __restrict__ next) {
   __shared__ CertLds L;
+  __shared__ int slot_sh;
   if (live) nitems = (int)min((int64_t)nitems, *live);
-  const int item = xcd_unit(nitems, live != nullptr);
-  if (item < 0 || item >= nitems) return;
-  const RecItem it = items[item];
-  const int q = it.m < it.n ? it.m : it.n;
-  if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > qlo && q <= qhi &&
-        min(q, kCertEdge) <= 16 * WR * TU && q / 2 < kCertEdge && it.D != nullptr))
-    return;
-  const bool ok = cert_block<WR, WC, TU, TW>(it, tol, L);
-  if (ok && threadIdx.x == 0) {
-    cert[item] = 1;
-    if (count) atomicAdd(count, 1ull);
+  for (bool first = true;; first = false) {
+    const int item = cert_next(next, &slot_sh, first, nitems, live != nullptr);
+    if (item < 0) return;
+    const RecItem it = items[item];
+    const int q = it.m < it.n ? it.m : it.n;
+    if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > qlo && q <= qhi &&
+          min(q, kCertEdge) <= 16 * WR * TU && q / 2 < kCertEdge && it.D != nullptr))
+      continue;
+    const bool ok = cert_block<WR, WC, TU, TW>(it, tol, L);
+    if (ok && threadIdx.x == 0) {
+      cert[item] = 1;
+      if (count) atomicAdd(count, 1ull);
+    }
   }
 }
 
@@ -495,23 +515,27 @@ __device__ bool cert_big(const RecItem& it, double tol, BigCertLds& L) {
 
 __global__ __launch_bounds__(kBigThreads) void k_dense_cert_big(
     const RecItem* __restrict__ items, int nitems, double tol, int* __restrict__ cert,
-    unsigned long long* __restrict__ count, const int64_t* __restrict__ live) {
+    unsigned long long* __restrict__ count, const int64_t* __restrict__ live,
+    int* __restrict__ next) {
   __shared__ BigCertLds L;
+  __shared__ int slot_sh;
   if (live) nitems = (int)min((int64_t)nitems, *live);
-  const int item = xcd_unit(nitems, live != nullptr);
-  if (item < 0 || item >= nitems) return;
-  const RecItem it = items[item];
-  const int q = it.m < it.n ? it.m : it.n, p = it.m < it.n ? it.n : it.m;
-  // short edges beyond 319, and those in (160, 319] that the column subset
-  // did not prove (its h + 1 pivots use up to all 160 columns); the factor L
-  // (q x (h + 1)) lives in the block's scratch, which holds m n
-  if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > kCertEdge &&
-        p <= kCertMaxEdge && cert[item] == 0 && it.D != nullptr && it.scratch != nullptr))
-    return;
-  const bool ok = cert_big(it, tol, L);
-  if (ok && threadIdx.x == 0) {
-    cert[item] = 1;
-    if (count) atomicAdd(count, 1ull);
+  for (bool first = true;; first = false) {
+    const int item = cert_next(next, &slot_sh, first, nitems, live != nullptr);
+    if (item < 0) return;
+    const RecItem it = items[item];
+    const int q = it.m < it.n ? it.m : it.n, p = it.m < it.n ? it.n : it.m;
+    // short edges beyond 319, and those in (160, 319] that the column subset
+    // did not prove (its h + 1 pivots use up to all 160 columns); the factor L
+    // (q x (h + 1)) lives in the block's scratch, which holds m n
+    if (!(it.path == kPathDense && it.cert_hint && tol > 0.0 && q > kCertEdge &&
+          p <= kCertMaxEdge && cert[item] == 0 && it.D != nullptr && it.scratch != nullptr))
+      continue;
+    const bool ok = cert_big(it, tol, L);
+    if (ok && threadIdx.x == 0) {
+      cert[item] = 1;
+      if (count) atomicAdd(count, 1ull);
+    }
   }
 }
 
@@ -521,15 +545,17 @@ hipError_t launch_dense_cert(const RecItem* items, int nitems, double tol, int* 
                              unsigned long long* count, hipStream_t s, const int64_t* live) {
   static_assert(16 * 4 * 3 >= kCertEdge, "the largest size class covers kCertEdge");
   if (nitems <= 0) return hipSuccess;
-  hipError_t e = launch_fill_i32(cert, 0, nitems, s);
+  // the proofs and the three launches' counters start at zero
+  hipError_t e = launch_fill_i32(cert, 0, nitems + 3, s);
   if (e != hipSuccess) return e;
-  const int grid = ((nitems + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_dense_cert<2, 4, 4, 2>), dim3(grid), dim3(512), 0, s, items, nitems, tol,
-                     0, 128, cert, count, live);
-  hipLaunchKernelGGL((k_dense_cert<4, 4, 3, 3>), dim3(grid), dim3(1024), 0, s, items, nitems,
-                     tol, 128, kCertMaxShort, cert, count, live);
-  hipLaunchKernelGGL(k_dense_cert_big, dim3(grid), dim3(kBigThreads), 0, s, items, nitems, tol,
-                     cert, count, live);
+  int* next = cert + nitems;
+  // persistent: two 512-thread, one 1024-thread or two big-form workgroups per CU
+  hipLaunchKernelGGL((k_dense_cert<2, 4, 4, 2>), dim3(persistent_grid(nitems, 2)), dim3(512), 0, s,
+                     items, nitems, tol, 0, 128, cert, count, live, next);
+  hipLaunchKernelGGL((k_dense_cert<4, 4, 3, 3>), dim3(persistent_grid(nitems, 1)), dim3(1024), 0,
+                     s, items, nitems, tol, 128, kCertMaxShort, cert, count, live, next + 1);
+  hipLaunchKernelGGL(k_dense_cert_big, dim3(persistent_grid(nitems, 2)), dim3(kBigThreads), 0, s,
+                     items, nitems, tol, cert, count, live, next + 2);
   return hipGetLastError();
 }
 

@@ -3,7 +3,7 @@
 
 namespace clr {
 
-int persistent_grid(int nitems) {
+int persistent_grid(int nitems, int per_cu) {
   static int cus = 0;
   if (cus == 0) {
     int dev = 0, n = 0;
@@ -13,7 +13,8 @@ int persistent_grid(int nitems) {
     else
       cus = 256;
   }
-  return nitems < cus ? nitems : cus;
+  const int64_t g = (int64_t)cus * per_cu;
+  return nitems < g ? nitems : (int)g;
 }
 
 hipError_t launch_ggemm_f64(const GemmItem* items, const Seg* segs, int nitems, hipStream_t s,
