@@ -1151,7 +1151,7 @@ clr_status gemm_impl(clr_context* ctx, Work& W, const clr_matrix* A, const clr_m
   double* tot_st = reinterpret_cast<double*>(tot_cnt + kNumCounters);
   if (!dev && e == hipSuccess) e = hipEventRecord(ctx->ev[0], stream);
   bind_block_lists(P, as<int>(W.lists));
-  if (e == hipSuccess) e = launch_block_lists(P, stream);
+  if (e == hipSuccess) e = launch_block_lists(P, as<int>(W.lists), stream);
   if (e == hipSuccess) e = launch_symbolic(P, as<int64_t>(W.cnt), as<double>(W.st), as<int>(W.flags), stream);
   if (e == hipSuccess) e = launch_scan(as<int64_t>(W.cnt), as<int64_t>(W.off), npairs, kNumCounters, tot_cnt, stream);
   // n[c]: length (eager) or capacity (device-sized) of list c; live: the
@@ -1681,7 +1681,7 @@ clr_status plan_build(clr_context* ctx, clr_plan* pl) {
     int64_t* cnt = as<int64_t>(ctx->w.cnt) + kNumCounters * pb[p];
     int64_t* off = as<int64_t>(ctx->w.off) + kNumCounters * pb[p];
     double* st = as<double>(ctx->w.st) + kNumStats * pb[p];
-    HIP_TRY(ctx, launch_block_lists(P[p], stream));
+    HIP_TRY(ctx, launch_block_lists(P[p], as<int>(ctx->w.lists) + lb[p], stream));
     HIP_TRY(ctx, launch_symbolic(P[p], cnt, st, as<int>(ctx->w.flags) + pb[p], stream));
     HIP_TRY(ctx, launch_scan(cnt, off, npairs, kNumCounters, tc + (size_t)p * kNumCounters, stream));
     HIP_TRY(ctx, launch_reduce(st, npairs, kNumStats, ts + (size_t)p * kNumStats, stream));

@@ -376,9 +376,9 @@ hipError_t launch_recompress(const RecItem* items, const Piece* pieces, int nite
                              int* status, GemmItem* gout, Seg* gseg, int* order, int* cert,
                              RecCounters* ctr, hipStream_t s, hipEvent_t engine_begin = nullptr,
                              hipEvent_t engine_end = nullptr, const int64_t* live = nullptr);
-// Sparse block lists of A's rows and B's columns (the buffers P's list
-// pointers name, bound by bind_block_lists).
-hipError_t launch_block_lists(const PlanParams& P, hipStream_t s);
+// Sparse block lists of A's rows and B's columns into `base`, the buffer
+// bind_block_lists bound P's list pointers to.
+hipError_t launch_block_lists(const PlanParams& P, int* base, hipStream_t s);
 hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* flags,
                            hipStream_t s);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,

@@ -31,14 +31,20 @@ __device__ inline int64_t dense_parts(const EdgeTable& E, int m, int n) {
   return parts2(m, n, dense_edge(E, m, n));
 }
 
-// Wave w < nrb lists row w of A, wave nrb + J column J of B.
-__global__ __launch_bounds__(256) void k_block_lists(PlanParams P) {
+// Wave w < nrb lists row w of A, wave nrb + J column J of B, into the
+// buffer `base` that bind_block_lists laid out (counts of the rows, counts of
+// the columns, then the row lists and the column lists, nkb ints each).
+__global__ __launch_bounds__(256) void k_block_lists(PlanParams P, int* __restrict__ base) {
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (wave >= P.nrb + P.ncb) return;
   const bool row = wave < P.nrb;
   const int r = row ? wave : wave - P.nrb;
-  int* out = row ? (int*)P.a_idx + (int64_t)r * P.nkb : (int*)P.b_idx + (int64_t)r * P.nkb;
+  int* const a_cnt = base;
+  int* const b_cnt = a_cnt + P.nrb;
+  int* const a_idx = b_cnt + P.ncb;
+  int* const b_idx = a_idx + (int64_t)P.nrb * P.nkb;
+  int* out = (row ? a_idx : b_idx) + (int64_t)r * P.nkb;
   int n = 0;
   for (int k0 = 0; k0 < P.nkb; k0 += 64) {
     const int K = k0 + lane;
@@ -48,18 +54,13 @@ __global__ __launch_bounds__(256) void k_block_lists(PlanParams P) {
     if (nz) out[n + __popcll(m & ((1ull << lane) - 1ull))] = K;
     n += __popcll(m);
   }
-  if (lane == 0) {
-    if (row)
-      ((int*)P.a_cnt)[r] = n;
-    else
-      ((int*)P.b_cnt)[r] = n;
-  }
+  if (lane == 0) (row ? a_cnt : b_cnt)[r] = n;
 }
 
-hipError_t launch_block_lists(const PlanParams& P, hipStream_t s) {
+hipError_t launch_block_lists(const PlanParams& P, int* base, hipStream_t s) {
   const int waves = P.nrb + P.ncb;
   if (waves == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_block_lists, dim3((waves + 3) / 4), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_block_lists, dim3((waves + 3) / 4), dim3(256), 0, s, P, base);
   return hipGetLastError();
 }
 
