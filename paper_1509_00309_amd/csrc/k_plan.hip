@@ -3,16 +3,17 @@
 // k_block_lists: the nonzero blocks of every block row of A and block column
 //   of B as lists of inner indices K, ascending (one wave per row or column,
 //   compacted with ballots).
-// k_symbolic: one thread per candidate result block (I, J).  It merges row
-//   I's list with column J's, visiting in ascending K the pairs where both
-//   A_IK and B_KJ are nonzero (work proportional to the two lists, not to the
-//   number of inner blocks), accumulates the norm estimate
+// k_symbolic: one wave per candidate result block (I, J).  It walks the
+//   shorter of row I's list and column J's list and keeps, in ascending K,
+//   the pairs where both A_IK and B_KJ are nonzero (work proportional to the
+//   shorter list, not to the number of inner blocks), accumulates the norm
+//   estimate
 //   est_IJ = |alpha| sum_K ||A_IK||_F ||B_KJ||_F (triangle inequality and
 //   submultiplicativity, Sec. 4.1), applies the screening test est >= tau,
 //   decides dense or factored accumulation, and counts the work and memory
 //   every later phase needs.
-// k_scan:     exclusive prefix sums of those counts (one workgroup).
-// k_reduce:   deterministic totals of the per-block statistics.
+// k_scan:     exclusive prefix sums of those counts (a workgroup per array).
+// k_reduce:   deterministic totals of the per-block statistics (one per array).
 // k_fill:     writes the work lists at the scanned offsets: thin factor
 //   products (Eq. (4)), terms of the dense accumulation GEMM, low-rank pieces
 //   of factored blocks (Eq. (5)) and one recompression item per block.
@@ -64,37 +65,42 @@ hipError_t launch_block_lists(const PlanParams& P, int* base, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The inner indices K, ascending, where A_IK and B_KJ are both nonzero:
-// a merge of row I's list with column J's.
-struct PairWalk {
-  const int* a;
-  const int* b;
-  int na, nb, ia = 0, ib = 0;
-  __device__ PairWalk(const PlanParams& P, int I, int J)
-      : a(P.a_idx + (int64_t)I * P.nkb), b(P.b_idx + (int64_t)J * P.nkb), na(P.a_cnt[I]),
-        nb(P.b_cnt[J]) {}
-  // next common K, or -1 when either list is exhausted
-  __device__ int next() {
-    while (ia < na && ib < nb) {
-      const int ka = a[ia], kb = b[ib];
-      if (ka < kb) {
-        ++ia;
-      } else if (kb < ka) {
-        ++ib;
-      } else {
-        ++ia;
-        ++ib;
-        return ka;
-      }
-    }
-    return -1;
-  }
-};
 
-__global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __restrict__ st,
-                           int* __restrict__ flags) {
+// The candidate inner indices of result block (I, J): the shorter of A's
+// row-I list and B's column-J list (K ascending); the other side's kind table
+// then says whether K is a term.
+struct TermList {
+  const int* k;
+  int n;
+};
+__device__ inline TermList term_list(const PlanParams& P, int I, int J) {
+  const int na = P.a_cnt[I], nb = P.b_cnt[J];
+  if (nb < na) return TermList{P.b_idx + (int64_t)J * P.nkb, nb};
+  return TermList{P.a_idx + (int64_t)I * P.nkb, na};
+}
+
+// Sum over the wave of a per-lane value (exact for the integer-valued
+// quantities it is used on: counts and flop counts below 2^53).
+template <typename T>
+__device__ inline T wave_sum_all(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One wave per candidate result block.  The lanes take the candidate terms of
+// 64-entry chunks of the block's term list (a term where both A_IK and B_KJ
+// are nonzero); the
+// norm estimate is summed in ascending K as a term-by-term walk would (lane
+// by lane, a lane without a term adding +0), every other per-block quantity
+// is a count or an integer-valued flop count and is summed over the wave.
+constexpr int kSymThreads = 256;
+__global__ __launch_bounds__(kSymThreads) void k_symbolic(PlanParams P, int64_t* __restrict__ cnt,
+                                                          double* __restrict__ st,
+                                                          int* __restrict__ flags) {
   const int npairs = P.nrb * P.ncb;
-  const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int pair = (int)((blockIdx.x * (unsigned)kSymThreads + threadIdx.x) >> 6);
   if (pair >= npairs) return;
   const int I = pair / P.ncb, J = pair % P.ncb;
   const int m = P.A.roff[I + 1] - P.A.roff[I];
@@ -105,50 +111,75 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
   bool anydd = false;
   // low-rank contributions that a densified block adds with rank r cost 2 m n r
   int64_t lr_rank_sum = 0;
-  PairWalk walk(P, I, J);
-  for (int K = walk.next(); K >= 0; K = walk.next()) {
-    const int ka = P.A.kind[I * P.nkb + K];
-    const int kb = P.B.kind[K * P.ncb + J];
-    const int k = P.A.coff[K + 1] - P.A.coff[K];
-    est += P.A.norm[I * P.nkb + K] * P.B.norm[K * P.ncb + J];
-    ++nseg;
-    if (ka == 1 && kb == 1) {
-      anydd = true;
-      ++ndd;
-      fdd += 2.0 * m * (double)k * n;
-    } else if (ka == 2 && kb == 1) {
-      const int ra = P.A.rank[I * P.nkb + K];
-      ++nld;
-      rcat += ra;
-      pool += (int64_t)n * ra;
-      thin1 += thin_parts(P.edges, n, ra);
-      fld += 2.0 * ra * (double)k * n;
-    } else if (ka == 1 && kb == 2) {
-      const int rb = P.B.rank[K * P.ncb + J];
-      ++ndl;
-      rcat += rb;
-      pool += (int64_t)m * rb;
-      thin1 += thin_parts(P.edges, m, rb);
-      fdl += 2.0 * m * (double)k * rb;
-    } else {
-      const int ra = P.A.rank[I * P.nkb + K];
-      const int rb = P.B.rank[K * P.ncb + J];
-      ++nll;
-      pool += (int64_t)ra * rb;
-      thin1 += thin_parts(P.edges, ra, rb);
-      if (rb < ra) {
-        rcat += rb;
-        pool += (int64_t)m * rb;
-        thin2 += thin_parts(P.edges, m, rb);
-        fll += 2.0 * k * (double)ra * rb + 2.0 * m * (double)ra * rb;
+  const TermList tl = term_list(P, I, J);
+  for (int c0 = 0; c0 < tl.n; c0 += 64) {
+    const int K = c0 + lane < tl.n ? tl.k[c0 + lane] : -1;
+    const int ka = K >= 0 ? P.A.kind[I * P.nkb + K] : 0;
+    const int kb = K >= 0 ? P.B.kind[K * P.ncb + J] : 0;
+    const bool term = ka != 0 && kb != 0;
+    double prod = 0.0, ldd = 0.0, lld = 0.0, ldl = 0.0, lll = 0.0;
+    int64_t lrc = 0, lpool = 0, lt1 = 0, lt2 = 0;
+    if (term) {
+      const int k = P.A.coff[K + 1] - P.A.coff[K];
+      prod = P.A.norm[I * P.nkb + K] * P.B.norm[K * P.ncb + J];
+      if (ka == 1 && kb == 1) {
+        ldd = 2.0 * m * (double)k * n;
+      } else if (ka == 2 && kb == 1) {
+        const int ra = P.A.rank[I * P.nkb + K];
+        lrc = ra;
+        lpool = (int64_t)n * ra;
+        lt1 = thin_parts(P.edges, n, ra);
+        lld = 2.0 * ra * (double)k * n;
+      } else if (ka == 1 && kb == 2) {
+        const int rb = P.B.rank[K * P.ncb + J];
+        lrc = rb;
+        lpool = (int64_t)m * rb;
+        lt1 = thin_parts(P.edges, m, rb);
+        ldl = 2.0 * m * (double)k * rb;
       } else {
-        rcat += ra;
-        pool += (int64_t)n * ra;
-        thin2 += thin_parts(P.edges, n, ra);
-        fll += 2.0 * k * (double)ra * rb + 2.0 * n * (double)ra * rb;
+        const int ra = P.A.rank[I * P.nkb + K];
+        const int rb = P.B.rank[K * P.ncb + J];
+        lpool = (int64_t)ra * rb;
+        lt1 = thin_parts(P.edges, ra, rb);
+        if (rb < ra) {
+          lrc = rb;
+          lpool += (int64_t)m * rb;
+          lt2 = thin_parts(P.edges, m, rb);
+          lll = 2.0 * k * (double)ra * rb + 2.0 * m * (double)ra * rb;
+        } else {
+          lrc = ra;
+          lpool += (int64_t)n * ra;
+          lt2 = thin_parts(P.edges, n, ra);
+          lll = 2.0 * k * (double)ra * rb + 2.0 * n * (double)ra * rb;
+        }
       }
     }
+    // the estimate in K order: the chunk's lanes one after another
+    {
+      const long long bits = __double_as_longlong(prod);
+      const int lo = (int)(bits & 0xffffffffLL), hi = (int)(bits >> 32);
+      for (int l = 0; l < 64; ++l) {
+        const unsigned blo = (unsigned)__builtin_amdgcn_readlane(lo, l);
+        const unsigned bhi = (unsigned)__builtin_amdgcn_readlane(hi, l);
+        est += __longlong_as_double((long long)(((unsigned long long)bhi << 32) | blo));
+      }
+    }
+    nseg += wave_sum_all<int>(term ? 1 : 0);
+    ndd += wave_sum_all<int>(term && ka == 1 && kb == 1 ? 1 : 0);
+    nld += wave_sum_all<int>(term && ka == 2 && kb == 1 ? 1 : 0);
+    ndl += wave_sum_all<int>(term && ka == 1 && kb == 2 ? 1 : 0);
+    nll += wave_sum_all<int>(term && ka == 2 && kb == 2 ? 1 : 0);
+    fdd += wave_sum_all<double>(ldd);
+    fld += wave_sum_all<double>(lld);
+    fdl += wave_sum_all<double>(ldl);
+    fll += wave_sum_all<double>(lll);
+    rcat += wave_sum_all<long long>(lrc);
+    pool += wave_sum_all<long long>(lpool);
+    thin1 += wave_sum_all<long long>(lt1);
+    thin2 += wave_sum_all<long long>(lt2);
   }
+  anydd = ndd > 0;
+  if (lane != 0) return;
   lr_rank_sum = rcat;
   est *= fabs(P.alpha);
   const double tau = P.screen ? P.eps_sp * m * (double)n : P.eps_sp;
@@ -192,14 +223,15 @@ __global__ void k_symbolic(PlanParams P, int64_t* __restrict__ cnt, double* __re
                 (force ? kFlagForce : 0);
 }
 
-// Exclusive prefix sums of `narrays` arrays of length n (one workgroup of 1024).
+// Exclusive prefix sums of `narrays` arrays of length n (a workgroup of 1024 per array).
 __global__ __launch_bounds__(1024) void k_scan(const int64_t* __restrict__ in,
                                                int64_t* __restrict__ out, int64_t n,
                                                int narrays, int64_t* __restrict__ totals) {
   __shared__ int64_t part[1024];
   const int tid = threadIdx.x;
   const int64_t chunk = (n + 1023) / 1024;
-  for (int a = 0; a < narrays; ++a) {
+  // workgroup a scans array a (the grid covers the arrays)
+  for (int a = blockIdx.x; a < narrays; a += gridDim.x) {
     const int64_t* x = in + (int64_t)a * n;
     int64_t* y = out + (int64_t)a * n;
     const int64_t b0 = tid * chunk;
@@ -225,12 +257,13 @@ __global__ __launch_bounds__(1024) void k_scan(const int64_t* __restrict__ in,
   }
 }
 
-// Totals of `narrays` double arrays of length n in a fixed order (one workgroup of 256).
+// Totals of `narrays` double arrays of length n in a fixed order (a workgroup of 256 per array).
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ in, int64_t n,
                                                 int narrays, double* __restrict__ totals) {
   __shared__ double part[256];
   const int tid = threadIdx.x;
-  for (int a = 0; a < narrays; ++a) {
+  // workgroup a sums array a (the grid covers the arrays)
+  for (int a = blockIdx.x; a < narrays; a += gridDim.x) {
     double s = 0.0;
     for (int64_t i = tid; i < n; i += 256) s += in[(int64_t)a * n + i];
     part[tid] = s;
@@ -303,8 +336,9 @@ __device__ inline T wave_incl_scan(T v, int lane) {
 }
 
 // One wave per result block.  The lanes take the candidate terms of a chunk
-// of 64 entries of A's row list (a term where B_KJ is nonzero too), so the
-// terms of a chunk are the set bits of a ballot in ascending K; every list
+// of 64 entries of the block's term list (the shorter of A's row list and B's
+// column list), so the terms of a chunk are the lanes with both blocks nonzero,
+// in ascending K; every list
 // offset (terms, factor-product items, pool doubles, inner ranges) is an
 // exclusive prefix sum over the terms before, plus the running totals of the
 // earlier chunks: the lists are the ones a walk term by term would write.
@@ -338,10 +372,9 @@ __global__ __launch_bounds__(kFillThreads) void k_fill(PlanParams P, FillParams 
   int kb = 0;
   int rcat = 0;
   bool anydd = false;
-  const int* arow = P.a_idx + (int64_t)I * P.nkb;
-  const int na = P.a_cnt[I];
-  for (int c0 = 0; c0 < na; c0 += 64) {
-    const int K = c0 + lane < na ? arow[c0 + lane] : -1;
+  const TermList tl = term_list(P, I, J);
+  for (int c0 = 0; c0 < tl.n; c0 += 64) {
+    const int K = c0 + lane < tl.n ? tl.k[c0 + lane] : -1;
     const int ka = K >= 0 ? P.A.kind[I * P.nkb + K] : 0;
     const int kbk = K >= 0 ? P.B.kind[K * P.ncb + J] : 0;
     const bool term = ka != 0 && kbk != 0;
@@ -515,19 +548,23 @@ hipError_t launch_symbolic(const PlanParams& P, int64_t* cnt, double* st, int* f
                            hipStream_t s) {
   const int npairs = P.nrb * P.ncb;
   if (npairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_symbolic, dim3((npairs + 255) / 256), dim3(256), 0, s, P, cnt, st, flags);
+  constexpr int per = kSymThreads / 64;   // result blocks (waves) per workgroup
+  hipLaunchKernelGGL(k_symbolic, dim3((npairs + per - 1) / per), dim3(kSymThreads), 0, s, P, cnt,
+                     st, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int narrays, int64_t* totals,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, in, out, n, narrays, totals);
+  if (narrays <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan, dim3(narrays), dim3(1024), 0, s, in, out, n, narrays, totals);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* in, int64_t n, int narrays, double* totals,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, in, n, narrays, totals);
+  if (narrays <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(narrays), dim3(256), 0, s, in, n, narrays, totals);
   return hipGetLastError();
 }
 
