@@ -70,6 +70,9 @@ struct GemmCfg<true, true> {
   static constexpr int WR = 2, WC = 4, TA = 4, TB = 2, TILES = 8;    // 128 x 128
 };
 constexpr int kLdsGemmThreads = 512;
+// s_waitcnt operand (gfx9 encoding) that waits for vmcnt 0 and leaves the
+// expcnt and lgkmcnt limits at their maxima.
+constexpr int kWaitVmAll = 0x0F70;
 // FP32 partials of the mixed form are added into the FP64 accumulators every
 // kF32FlushSlabs slabs (32 inner indices).
 constexpr int kF32FlushSlabs = 2;
@@ -299,9 +302,15 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32, SPLI
       if (it.nseg <= kSegCacheLds)
         resolve_row<lseg*, true>(it, segs, (lseg*)sh.segs, slab, tid, cursor, lp, rp, sli, srj, sc,
                                  bok);
-      else
+      else {
         resolve_row<gseg*, true>(it, segs, (gseg*)(segs + it.seg0), slab, tid, cursor, lp, rp, sli,
                                  srj, sc, bok);
+        // Nothing of this path stays in flight: otherwise the compiler, which
+        // cannot tell the paths apart where they join, waits for every global
+        // load at the top of each slab (the operand prefetch included) before
+        // it reuses the registers these descriptor loads wrote.
+        __builtin_amdgcn_s_waitcnt(kWaitVmAll);
+      }
       sh.lp[d][tid] = lp;
       sh.rp[d][tid] = rp;
       sh.sli[d][tid] = sli;
@@ -427,17 +436,22 @@ __device__ __attribute__((always_inline)) inline void run_item(GemmLds<F32, SPLI
     for (int s = 0; s < nslab; ++s) {
       const int cur = s & 1, nxt = cur ^ 1;
       // descriptors of slab s + 2 sit in buffer s & 1, those of s + 1 were consumed
-      const bool st_next = s + 1 < nslab, ld_next = s + 2 < nslab;
-      if (ld_next) prep(cur);
+      // The staging stores and loads run in every slab, also where there is
+      // no next slab to stage (they then store into the idle buffer and
+      // reload the last prepared descriptors, whose addresses are valid).
+      // With one path through the loop, the compiler's wait before each
+      // store counts only the loads that precede it; a skipped load on one
+      // path would make it wait for the newest prefetch on every path.
+      if (s + 2 < nslab) prep(cur);
       if (s + 3 < nslab) resolve(s + 3, nxt);
       auto mid = [&](int q) {
-        if (q == 0 && st_next) {
+        if (q == 0) {
           store_a(nxt);
-          if (ld_next) load_a();
+          load_a();
         }
-        if (q == 1 && st_next) {
+        if (q == 1) {
           store_b(nxt);
-          if (ld_next) load_b();
+          load_b();
         }
       };
       if constexpr (NA > 0 && NB > 0) {
