@@ -26,6 +26,17 @@ constexpr int kCertEdge = 160;        // most columns the dense certificate exam
 constexpr int kCertMaxShort = 2 * kCertEdge - 1;   // largest short edge of the column-subset form
 constexpr int kCertMaxEdge = 512;    // largest block edge of the left-looking form beyond that
 
+// The thread index, opaque to loop-invariant code motion.  Kernels that run
+// one work unit after another in a persistent loop would otherwise have the
+// values derived from threadIdx.x hoisted out of that loop, live across every
+// phase of every unit, and spilled.  Reading the index through an empty asm
+// statement makes each read a new value, so its uses stay where they are.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // XCD-blocked workgroup mapping: the dispatcher deals workgroups to the 8 XCDs
 // round-robin, so workgroup b runs on XCD b % 8; unit u = (b % 8) * per + b / 8

@@ -150,7 +150,7 @@ template <int WR, int WC, int TU, int TW>
 __device__ __attribute__((always_inline)) inline bool cert_block(const RecItem& it, double tol,
                                                                  CertLds& L) {
   constexpr int NT = 64 * WR * WC;
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int m = it.m, n = it.n;
   const int q = m < n ? m : n, p = m < n ? n : m;
   const int qs = q < kCertEdge ? q : kCertEdge;   // columns examined (all of them up to 160)
@@ -418,7 +418,7 @@ struct BigCertLds {
 // G (p x q) is D or D^T, thread t owns column t of G (q <= 512 = the
 // workgroup).
 __device__ bool cert_big(const RecItem& it, double tol, BigCertLds& L) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int lane = tid & 63, wave = tid >> 6;
   const int m = it.m, n = it.n;
   const bool trans = m < n;

@@ -136,7 +136,7 @@ __device__ inline double wave_sum(double v) { return xor32_sum(hw_sum(v)); }
 
 // Deterministic workgroup sum: per-thread partials, tree over LDS.
 CLR_INLINE double block_sum(double v, RecShared& sh) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   sh.red[tid] = v;
   __syncthreads();
   for (int s = kRecThreads / 2; s > 0; s >>= 1) {
@@ -171,7 +171,7 @@ __device__ inline void tournament(int round, int k, int P, int& a, int& b) {
 template <typename PT>
 CLR_INLINE int pivoted_qr(PT* G, int p, int q, int64_t ld, RecShared& sh,
                           double stop2 = kRankFloor2, bool keep_tau = false) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int lane = tid & 63, wave = tid >> 6;
   const int g = tid >> 4, gl = tid & 15;
   for (int j = g; j < q; j += kGroups) {
@@ -293,7 +293,7 @@ template <typename PT>
 CLR_INLINE void transpose_r(PT* G, int q, int k, int64_t ld) {
   // pairs (i, j), i < j < q, i < k: X(j, i) = R(i, j); X(i, j) = R(j, i) = 0 when j < k
   const int64_t total = (int64_t)k * q;
-  for (int64_t e = threadIdx.x; e < total; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < total; e += kRecThreads) {
     const int i = (int)(e / q), j = (int)(e % q);
     if (j <= i) continue;
     const double v = G[i + (int64_t)j * ld];
@@ -312,7 +312,7 @@ CLR_INLINE void transpose_r(PT* G, int q, int k, int64_t ld) {
 // Returns false if it did not converge.
 template <int NR, typename PT>
 CLR_INLINE bool jacobi_columns_t(PT* X, int rows, int kc, int64_t ld, RecShared& sh) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int g = tid >> 4, gl = tid & 15;
   const int P = kc + (kc & 1);
   const double tolj = (double)rows * DBL_EPSILON;
@@ -368,7 +368,7 @@ CLR_INLINE bool jacobi_columns_t(PT* X, int rows, int kc, int64_t ld, RecShared&
 // Two-pass variant for columns longer than 160 (blocks beyond the register engine).
 template <typename PT>
 CLR_INLINE bool jacobi_columns_long(PT* X, int rows, int kc, int64_t ld, RecShared& sh) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int g = tid >> 4, gl = tid & 15;
   const int P = kc + (kc & 1);
   const double tolj = (double)rows * DBL_EPSILON;
@@ -426,7 +426,7 @@ CLR_INLINE bool jacobi_columns(PT* X, int rows, int kc, int64_t ld, RecShared& s
 template <typename PT>
 CLR_INLINE int rank_from_columns(const PT* X, int rows, int kc, int64_t ld, double tol,
                                  RecShared& sh) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int g = tid >> 4, gl = tid & 15;
   for (int j = g; j < kc; j += kGroups) {
     const PT* w = X + (int64_t)j * ld;
@@ -470,7 +470,7 @@ CLR_INLINE int rank_from_columns(const PT* X, int rows, int kc, int64_t ld, doub
 template <typename PT, typename BT>
 CLR_INLINE void write_basis(const PT* X, int64_t ld, int q, int r, BT* basis, int64_t ldb,
                             RecShared& sh) {
-  for (int64_t e = threadIdx.x; e < (int64_t)q * r; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < (int64_t)q * r; e += kRecThreads) {
     const int j = (int)(e % q), c = (int)(e / q);
     const int src = sh.order[c];
     basis[sh.perm[j] + (int64_t)c * ldb] = X[j + (int64_t)src * ld] / sh.sigma[src];
@@ -486,7 +486,7 @@ CLR_INLINE int svd_rank(PT* G, int p, int q, int64_t ld, double tol, int* status
   const int kc = pivoted_qr(G, p, q, ld, sh);
   transpose_r(G, q, kc, ld);
   if (!jacobi_columns(G, q, kc, ld, sh)) {
-    if (threadIdx.x == 0) atomicOr(status, 1);
+    if (opaque_tid() == 0) atomicOr(status, 1);
   }
   return rank_from_columns(G, q, kc, ld, tol, sh);
 }
@@ -569,7 +569,7 @@ static_assert(sizeof(RegLds) <= (size_t)kRecLdsBytes, "register engine bookkeepi
 typedef double RegTile[kRR][kRC];
 
 CLR_INLINE void write_meta(const RecItem& it, int kind, int rank, double norm) {
-  if (threadIdx.x == 0) {
+  if (opaque_tid() == 0) {
     *it.kind_out = kind;
     *it.rank_out = rank;
     *it.norm_out = norm;
@@ -580,7 +580,7 @@ CLR_INLINE int vs_off(int k, int q) { return k * (2 * q - k - 1) / 2; }
 
 CLR_INLINE void reg_load(RegTile& a, const double* D, int64_t ldd, bool trans, double scale,
                          int p, int q) {
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  const int tr = opaque_tid() & 15, tc = opaque_tid() >> 4;
 #pragma unroll
   for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
@@ -684,7 +684,7 @@ __device__ inline void row_sum16_from(double (&v)[N]) {
 template <int P>
 CLR_INLINE bool bd_step(RegTile& a, int k, int p, int q, RegLds& L, BdCarry& S) {
   constexpr int JB = P >> 1;   // first column block with unfinished columns
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int tr = tid & 15, tc = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
   const int kk = k - 16 * P;   // the diagonal row within block P
@@ -850,7 +850,7 @@ CLR_INLINE void reg_bidiag(RegTile& a, int p_in, int q_in, RegLds& L) {
   static_assert(kRR == 10 && kRC == 5, "phase dispatch below assumes a 160 x 160 frame");
   // uniform in the workgroup; made explicit so loop bounds are scalar
   const int p = __builtin_amdgcn_readfirstlane(p_in), q = __builtin_amdgcn_readfirstlane(q_in);
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int tr = tid & 15, tc = tid >> 4;
   if (tc == 0) {
 #pragma unroll
@@ -937,7 +937,7 @@ CLR_INLINE int wave_isum(int v) {
 // the kept rank is #{r < q : T(r) > tol^2}; evaluated with the lower ends,
 // the upper ends and the midpoints of the brackets.
 CLR_INLINE void rank_counts(const RegLds& L, int q, double bound, int& rlo, int& rhi, int& rmid) {
-  const int lane = threadIdx.x & 63;
+  const int lane = opaque_tid() & 63;
   double sl[3], shh[3], sm[3];
   double cl = 0.0, ch = 0.0, cm = 0.0;
 #pragma unroll
@@ -983,7 +983,7 @@ CLR_INLINE void rank_counts(const RegLds& L, int q, double bound, int& rlo, int&
 // One multisection round over the active brackets (S.act[0 .. nact)).
 CLR_INLINE void multisect_round(int q, int nact, RegLds& L) {
   auto& S = L.u.st;
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int ts = kRecThreads / nact;
   const int a = tid / ts, sub = tid % ts;
   // probe points lo + (s + 1) w, w = (hi - lo) / (ts + 1), computed the same
@@ -1017,7 +1017,7 @@ CLR_INLINE void multisect_round(int q, int nact, RegLds& L) {
 // Wave 0: active list of the unsettled brackets with index in [from, to).
 CLR_INLINE int collect_active(RegLds& L, int from, int to) {
   auto& S = L.u.st;
-  const int lane = threadIdx.x & 63;
+  const int lane = opaque_tid() & 63;
   int base = 0;
   for (int c0 = 0; c0 < to; c0 += 64) {
     const int i = c0 + lane;
@@ -1033,7 +1033,7 @@ CLR_INLINE int collect_active(RegLds& L, int from, int to) {
 // Brackets end in L.u.st.lo / hi; sh.sigma receives the midpoints.
 CLR_INLINE int reg_decide(int q, double tol, RegLds& L, RecShared& sh) {
   auto& S = L.u.st;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = opaque_tid(), wave = tid >> 6, lane = tid & 63;
   if (tid < 2 * q - 1) {
     const double b = (tid & 1) ? L.e[tid >> 1] : L.d[tid >> 1];
     S.b2[tid] = fmax(b * b, 0x1p-600);   // positive: see sturm_greater
@@ -1085,7 +1085,7 @@ CLR_INLINE int reg_decide(int q, double tol, RegLds& L, RecShared& sh) {
 // Full-precision brackets for values 0 .. r-1; midpoints into sh.sigma.
 CLR_INLINE void reg_refine_top(int q, int r, RegLds& L, RecShared& sh) {
   auto& S = L.u.st;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = opaque_tid(), wave = tid >> 6, lane = tid & 63;
   for (int round = 0; round < 256; ++round) {
     if (wave == 0) {
       const int nact = collect_active(L, 0, r);
@@ -1262,7 +1262,7 @@ CLR_INLINE bool close_values(const RecShared& sh, int c) {
 // (nothing final written) when a vector cannot be resolved this way.
 CLR_INLINE bool reg_vectors(const RecItem& it, int p, int q, bool trans, int r, double normc,
                             RegLds& L, RecShared& sh, GemmItem* gout, Seg* gseg, int gidx) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int g = tid >> 4, gl = tid & 15;
   const int m = it.m;
   gdbl* Uo = (gdbl*)it.out;
@@ -1400,7 +1400,7 @@ CLR_INLINE bool reg_vectors(const RecItem& it, int p, int q, bool trans, int r, 
 
 // Left reflector of the pivoted QR on column k of the tile (vector in colk).
 CLR_INLINE void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  const int tr = opaque_tid() & 15, tc = opaque_tid() >> 4;
   const int kj = k >> 5;
   if (tc == (k & 31)) {
     double s2 = 0.0, x0p = 0.0;
@@ -1462,7 +1462,7 @@ CLR_INLINE void reg_left(RegTile& a, int k, int p, int q, RegLds& L) {
 // rank (trailing squared norm <= kRankFloor2).  Returns the number of steps k;
 // R(0:k, :) stays in the registers, sh.perm holds the permutation.
 CLR_INLINE int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int tr = tid & 15, tc = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
   auto column_norms = [&](int from_row, int from_col) {
@@ -1559,7 +1559,7 @@ CLR_INLINE int reg_pivoted_qr(RegTile& a, int p, int q, RegLds& L, RecShared& sh
 // X (q x kq, leading dimension ldx) = R(0:kq, 0:q)^T from the registers.
 template <typename PT>
 CLR_INLINE void reg_store_rt(const RegTile& a, int q, int kq, PT* X, int64_t ldx) {
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  const int tr = opaque_tid() & 15, tc = opaque_tid() >> 4;
 #pragma unroll
   for (int ir = 0; ir < kRR; ++ir)
 #pragma unroll
@@ -1574,7 +1574,7 @@ CLR_INLINE void copy_dense_out(const RecItem& it) {
   const int64_t total = (int64_t)it.m * it.n;
   const cgdbl* D = (const cgdbl*)it.D;
   gdbl* out = (gdbl*)it.out;
-  for (int64_t e = threadIdx.x; e < total; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < total; e += kRecThreads) {
     const int i = (int)(e % it.m), j = (int)(e / it.m);
     out[e] = D[i + (int64_t)j * it.ldd];
   }
@@ -1585,7 +1585,7 @@ CLR_INLINE void copy_dense_out(const RecItem& it) {
 // (H_k = I - tau_k v_k v_k^T, v_k = (1, W[k+1:, k])).
 template <typename PT>
 CLR_INLINE void householder_qr(PT* W, int rows, int cols, PT* tau) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int lane = tid & 63, wave = tid >> 6;
   const int g = tid >> 4, gl = tid & 15;
   for (int k = 0; k < cols && k < rows; ++k) {
@@ -1626,7 +1626,7 @@ CLR_INLINE void householder_qr(PT* W, int rows, int cols, PT* tau) {
 template <typename PT, typename TT = PT>
 CLR_INLINE void apply_q(const PT* W, int rows, int kk, const TT* tau, gdbl* X, int64_t ldx,
                         int ncol) {
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int g = tid >> 4, gl = tid & 15;
   for (int c = g; c < ncol; c += kGroups) {
     gdbl* x = X + (int64_t)c * ldx;
@@ -1664,7 +1664,7 @@ CLR_INLINE void dense_truncated_out(const RecItem& it, const PT* X, int64_t ldx,
   gdbl* other = trans ? Vo : Uo;
   write_basis(X, ldx, q, r, basis, q, sh);
   const cgdbl* D = (const cgdbl*)it.D;
-  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
+  const int g = opaque_tid() >> 4, gl = opaque_tid() & 15;
   for (int o = g; o < p * r; o += kGroups) {
     const int i = o % p, c = o / p;
     const gdbl* b = basis + (int64_t)c * q;
@@ -1688,7 +1688,7 @@ CLR_INLINE void reg_truncated(const RecItem& it, const RegTile& a, PT* X, int64_
                               int* status, RecShared& sh) {
   reg_store_rt(a, q, kc, X, ldx);
   if (!jacobi_columns(X, q, kc, ldx, sh)) {
-    if (threadIdx.x == 0) atomicOr(status, 1);
+    if (opaque_tid() == 0) atomicOr(status, 1);
   }
   // sorted Jacobi columns give the vectors; the rank decided from the bidiagonal stands
   (void)rank_from_columns(X, q, kc, ldx, tol, sh);
@@ -1703,7 +1703,7 @@ CLR_INLINE void dense_general(const RecItem& it, PT* G, int p, int q, bool trans
   const int m = it.m, n = it.n;
   const double inv_norm = 1.0 / normc;
   const cgdbl* D = (const cgdbl*)it.D;
-  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < (int64_t)m * n; e += kRecThreads) {
     const int i = (int)(e % m), j = (int)(e / m);
     const double v = D[i + (int64_t)j * it.ldd] * inv_norm;
     if (!trans)
@@ -1736,7 +1736,7 @@ CLR_INLINE void dense_rrqr(const RecItem& it, PT* G, double tol, double normc, R
   const int m = it.m, n = it.n, q = m < n ? m : n;
   const double inv_norm = 1.0 / normc;
   const cgdbl* D = (const cgdbl*)it.D;
-  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < (int64_t)m * n; e += kRecThreads) {
     const int i = (int)(e % m), j = (int)(e / m);
     G[i + (int64_t)j * m] = D[i + (int64_t)j * it.ldd] * inv_norm;
   }
@@ -1753,14 +1753,14 @@ CLR_INLINE void dense_rrqr(const RecItem& it, PT* G, double tol, double normc, R
   }
   gdbl* Uo = (gdbl*)it.out;
   gdbl* Vo = Uo + (int64_t)m * r;
-  for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < (int64_t)m * r; e += kRecThreads) {
     const int i = (int)(e % m), c = (int)(e / m);
     Uo[e] = i == c ? 1.0 : 0.0;
   }
   __syncthreads();
   apply_q(G, m, r, sh.sigma, Uo, m, r);
   double part = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < (int64_t)n * r; e += kRecThreads) {
     const int j = (int)(e % n), i = (int)(e / n);
     const double v = j >= i ? G[i + (int64_t)j * m] : 0.0;
     part += v * v;
@@ -1779,13 +1779,13 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
   const int m = it.m, n = it.n;
   const cgdbl* D = (const cgdbl*)it.D;
   double part = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < (int64_t)m * n; e += kRecThreads) {
     const double v = D[(e % m) + (e / m) * it.ldd];
     part += v * v;
   }
   const double normc = sqrt(block_sum(part, sh));
   if (!(normc == normc) || normc > DBL_MAX) {
-    if (threadIdx.x == 0) atomicOr(status, 2);
+    if (opaque_tid() == 0) atomicOr(status, 2);
   }
   if (normc < it.tau || (normc == 0.0 && it.tau == 0.0)) {
     write_meta(it, 0, 0, 0.0);
@@ -1805,7 +1805,7 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
     RegTile a;
     reg_load(a, it.D, it.ldd, trans, 1.0 / normc, p, q);
     reg_bidiag(a, p, q, L);
-    if (flops_bidiag && threadIdx.x == 0)
+    if (flops_bidiag && opaque_tid() == 0)
       atomicAdd(flops_bidiag, 4.0 * p * (double)q * q - 4.0 * (double)q * q * q / 3.0);
     const int r = reg_decide(q, tol, L, sh);
     if (r == 0) {
@@ -1827,7 +1827,7 @@ CLR_INLINE void dense_path(const RecItem& it, double tol, double* lds, int* stat
       reg_truncated(it, a, (ldbl*)lds, ldx, p, q, kc, trans, r, tol, normc, status, sh);
     } else if (it.scratch != nullptr) {
       reg_truncated(it, a, (gdbl*)it.scratch, ldx, p, q, kc, trans, r, tol, normc, status, sh);
-    } else if (threadIdx.x == 0) {
+    } else if (opaque_tid() == 0) {
       atomicOr(status, 4);   // cannot happen with the planner's scratch rule
     }
   } else if (it.rrqr) {
@@ -1860,11 +1860,11 @@ CLR_INLINE void lowrank_body(const RecItem& it, const Piece* __restrict__ pieces
     const Piece pz = pieces[it.piece0 + pc];
     const cgdbl* pu = (const cgdbl*)pz.U;
     const cgdbl* pv = (const cgdbl*)pz.V;
-    for (int64_t e = threadIdx.x; e < (int64_t)m * pz.r; e += kRecThreads) {
+    for (int64_t e = opaque_tid(); e < (int64_t)m * pz.r; e += kRecThreads) {
       const int i = (int)(e % m), c = (int)(e / m);
       Uc[i + (int64_t)(off + c) * m] = pz.scale * pu[i + (int64_t)c * pz.ldu];
     }
-    for (int64_t e = threadIdx.x; e < (int64_t)n * pz.r; e += kRecThreads) {
+    for (int64_t e = opaque_tid(); e < (int64_t)n * pz.r; e += kRecThreads) {
       const int i = (int)(e % n), c = (int)(e / n);
       Vc[i + (int64_t)(off + c) * n] = pv[i + (int64_t)c * pz.ldv];
     }
@@ -1874,7 +1874,7 @@ CLR_INLINE void lowrank_body(const RecItem& it, const Piece* __restrict__ pieces
   if (tol == 0.0) {
     // no truncation: the concatenation itself is the result; keep a copy in the
     // output slot before the QR below overwrites the working factors
-    for (int64_t e = threadIdx.x; e < (int64_t)(m + n) * R; e += kRecThreads) out[e] = W[e];
+    for (int64_t e = opaque_tid(); e < (int64_t)(m + n) * R; e += kRecThreads) out[e] = W[e];
     __syncthreads();
   }
   householder_qr(Uc, m, R, tauU);
@@ -1882,7 +1882,7 @@ CLR_INLINE void lowrank_body(const RecItem& it, const Piece* __restrict__ pieces
   // core M = R_U R_V^T (Eq. (6)), both factors upper triangular;
   // ||U V^T||_F = ||M||_F keeps its accuracy when the concatenated terms cancel
   double part = 0.0;
-  for (int e = threadIdx.x; e < R * R; e += kRecThreads) {
+  for (int e = opaque_tid(); e < R * R; e += kRecThreads) {
     const int i = e % R, j = e / R;
     double s = 0.0;
     for (int k = (i > j ? i : j); k < R; ++k) s += Uc[i + (int64_t)k * m] * Vc[j + (int64_t)k * n];
@@ -1891,7 +1891,7 @@ CLR_INLINE void lowrank_body(const RecItem& it, const Piece* __restrict__ pieces
   }
   const double normc = sqrt(block_sum(part, sh));
   if (!(normc == normc) || normc > DBL_MAX) {
-    if (threadIdx.x == 0) atomicOr(status, 2);
+    if (opaque_tid() == 0) atomicOr(status, 2);
   }
   if (normc < it.tau || (normc == 0.0 && it.tau == 0.0)) {
     write_meta(it, 0, 0, 0.0);
@@ -1902,7 +1902,7 @@ CLR_INLINE void lowrank_body(const RecItem& it, const Piece* __restrict__ pieces
     return;
   }
   const double inv_norm = 1.0 / normc;
-  for (int e = threadIdx.x; e < R * R; e += kRecThreads) {
+  for (int e = opaque_tid(); e < R * R; e += kRecThreads) {
     const int i = e % R, j = e / R;
     G[j + (int64_t)i * R] = Mc[e] * inv_norm;   // G = M^T / ||M||
   }
@@ -1921,11 +1921,11 @@ CLR_INLINE void lowrank_body(const RecItem& it, const Piece* __restrict__ pieces
   gdbl* Uo = out;
   gdbl* Vo = out + (int64_t)m * r;
   // left singular vectors of M (right ones of M^T) into the top of U'
-  for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += kRecThreads) Uo[e] = 0.0;
+  for (int64_t e = opaque_tid(); e < (int64_t)m * r; e += kRecThreads) Uo[e] = 0.0;
   __syncthreads();
   write_basis(G, R, R, r, Uo, m, sh);
   // V' top rows = M^T u_M (= V_M Sigma)
-  for (int64_t e = threadIdx.x; e < (int64_t)n * r; e += kRecThreads) {
+  for (int64_t e = opaque_tid(); e < (int64_t)n * r; e += kRecThreads) {
     const int i = (int)(e % n), c = (int)(e / n);
     double s = 0.0;
     if (i < R)
@@ -1955,11 +1955,11 @@ __device__ inline bool register_item(const RecItem& it, double tol) {
 __device__ inline bool item_guard(const RecItem& it, double tol, int* status) {
   // the planner gives scratch to every block whose working set exceeds the LDS budget
   if (it.scratch == nullptr && rec_scratch_doubles(it.path, it.m, it.n, it.R, tol) > 0) {
-    if (threadIdx.x == 0) atomicOr(status, 4);
+    if (opaque_tid() == 0) atomicOr(status, 4);
     return false;
   }
   if (it.m > kMaxDim || it.n > kMaxDim) {
-    if (threadIdx.x == 0) atomicOr(status, 8);
+    if (opaque_tid() == 0) atomicOr(status, 8);
     return false;
   }
   return true;
