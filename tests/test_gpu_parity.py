@@ -1175,6 +1175,35 @@ def test_gemm_largest_block_edge(ctx, torch):
         parity.assert_parity(rep, FP64_BOUND, nblocks=9)
 
 
+
+def test_gemm_many_terms_per_block(ctx, torch):
+    """Result blocks with more inner terms than the grouped GEMM caches in LDS (256): their
+    term descriptors are read from global memory on every slab.  FP64 to the oracle's bar;
+    the mixed forms on the same path within FP32 rounding of the FP64 product (random
+    N(0,1) operands over ~1500 inner indices, so not the 10 x tol bar of the decaying
+    workloads)."""
+    log("gemm with 300 inner blocks")
+    rs, cs = [40, 24], [32, 17]
+    ks = [3 + (7 * i) % 5 for i in range(300)]
+    ra = random_blocks(611, rs, ks, p_zero=0.02, p_dense=0.5, max_rank=2)
+    rb = random_blocks(612, ks, cs, p_zero=0.02, p_dense=0.5, max_rank=2)
+    terms = ((ra.kind != 0).astype(int) @ (rb.kind != 0).astype(int))
+    assert terms.max() > 256, terms
+    A, B = gpu_from_random(ctx, torch, ra), gpu_from_random(ctx, torch, rb)
+    OA, OB = orc_from_random(ra), orc_from_random(rb)
+    for tol in (1e-8, 0.0):
+        C = ctx.gemm(A, B, tol, 1e-10)
+        Oc = orc.gemm(OA, OB, tol, 1e-10)
+        rep = parity.compare(C, Oc, tol, operands=(OA, OB))
+        log(f"  tol={tol:g} " + parity.summary(rep))
+        parity.assert_parity(rep, FP64_BOUND, nblocks=4)
+    ref = ctx.gemm(A, B, 0.0, 1e-10).to_dense()
+    for split in (0, 1):
+        Cm = ctx.gemm(A, B, 0.0, 1e-10, precision="mixed", split=split).to_dense()
+        err = float(torch.linalg.norm(Cm - ref) / torch.linalg.norm(ref))
+        log(f"  mixed split={split} rel err vs FP64 {err:.2e}")
+        assert err < 1e-5
+
 def _alpha_of(S):
     _k, _r, norm = S.meta()
     return 1.0 / float(np.max(np.sum(norm, axis=1)))
