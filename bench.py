@@ -528,7 +528,7 @@ def run_sqrtinv_scale(ctx, n, nclusters, forms, log_fn):
             "storage": storage, "forms": out}
 
 
-def run_adjoint(ctx, forms, log_fn):
+def run_adjoint(ctx, forms, log_fn, cpu=False):
     """dS of L = sum(Wbar o W), W after 20 unrolled iterations, checkpoint every 5, at N = 4096
     (32 clusters, tol 1e-8); Wbar seeded N(0, 1) masked to S's stored blocks.  The error is
     against the Daleckii-Krein gradient Q (Gamma o (Q^T Wbar Q)) Q^T of the dense S^-1/2 of the
@@ -580,6 +580,27 @@ def run_adjoint(ctx, forms, log_fn):
         }
         log_fn(f"  adjoint {form}: {out['forms'][form]}")
         del W, Wb, dS, Wd
+    if cpu:
+        # the oracle on a bounded sample: one of the 20 iterations, forward alone and
+        # forward + backward, on the oracle's own compression of the same matrix
+        import oracle as orc
+        O = orc.compress(wl.dense(), wl.sizes, wl.sizes, wl.tol, 1e-10)
+        wbar = wl.extra["weights"] * orc.structure_mask(O)
+        t0 = time.perf_counter()
+        orc.sqrt_inv(O, wl.tol, wl.eps_sp, fixed_iters=1)
+        t_f = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        orc.sqrt_inv_vjp(O, wbar, 1, wl.tol, wl.eps_sp)
+        t_fb = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": t_f * 1e3, "unit": "ms per forward iteration", "cores": int(blas_threads()),
+            "cpu": cpu_model(), "kind": "oracle",
+            "forward_backward_ms_per_iteration": t_fb * 1e3,
+            "sample": "the first of the 20 iterations (its four products and combination), forward "
+                      "by oracle.sqrt_inv(fixed_iters=1) and forward + backward by "
+                      "oracle.sqrt_inv_vjp(iters=1), on the oracle's compression of the same matrix; "
+                      "the 20 iterations take at least 20 times as long (later iterates are denser)"}
+        log_fn(f"  adjoint cpu baseline: {out['cpu_baseline']}")
     return out
 
 
@@ -779,7 +800,8 @@ def main():
     adjoint = None
     if not args.no_adjoint:
         log("adjoint N=4096")
-        adjoint = run_adjoint(ctx, [f for f in args.forms.split(",") if f in ("fp64", "mixed")], log)
+        adjoint = run_adjoint(ctx, [f for f in args.forms.split(",") if f in ("fp64", "mixed")], log,
+                              not args.no_cpu_baseline)
 
     # The two largest kernels by device time: the register-resident
     # recompression (FP64 vector ALU / latency bound; peak = 256 CUs x 4 SIMD x
